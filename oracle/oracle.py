@@ -1,0 +1,258 @@
+"""ctypes wrapper of the C oracle -- TEST INFRASTRUCTURE ONLY.
+
+The oracle is the plain serial loop over individuals (Supplementary Fig.
+S5(A)) of one replicate; batches of replicates are lists of ``OraclePop``.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("SPEGG_ORACLE_LIB") or os.path.join(HERE, "libspegg_oracle.so")
+
+ALWAYS = 1 << 32
+MODE_NAMES = {0: "raw", 1: "zero", 2: "skip", 3: "lazy"}
+
+
+class OracleParams(C.Structure):
+    _fields_ = [
+        ("seed", C.c_uint64),
+        ("replicate_id", C.c_uint32),
+        ("regime", C.c_uint32),
+        ("n0", C.c_uint32),
+        ("capacity", C.c_uint32),
+        ("n_loci", C.c_uint32),
+        ("reserved", C.c_uint32),
+        ("mu", C.c_double),
+        ("r", C.c_double),
+        ("theta", C.c_double),
+        ("omega", C.c_double),
+        ("K", C.c_double),
+        ("fecundity", C.c_double),
+        ("effects", C.POINTER(C.c_int8)),
+    ]
+
+
+class OracleStats(C.Structure):
+    _fields_ = [
+        ("generation", C.c_uint32),
+        ("n", C.c_uint32),
+        ("n_parents", C.c_uint32),
+        ("n_survivors", C.c_uint32),
+        ("extinct", C.c_uint32),
+        ("reserved", C.c_uint32),
+        ("sum_z", C.c_int64),
+        ("sum_z2", C.c_int64),
+        ("near_ties", C.c_uint64),
+        ("truncated", C.c_uint64),
+        ("sum_threshold", C.c_uint64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_lib = None
+
+
+def load():
+    """Load (building first if needed) the oracle library."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from .build import build
+        build()
+    lib = C.CDLL(LIB_PATH)
+    u32, u64, i32, vp = C.c_uint32, C.c_uint64, C.c_int32, C.c_void_p
+    P64 = C.POINTER(C.c_uint64)
+    P32 = C.POINTER(C.c_uint32)
+    lib.oracle_philox4x32_10.argtypes = [P32, P32, P32]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_prob_threshold.argtypes = [C.c_double]
+    lib.oracle_prob_threshold.restype = u64
+    lib.oracle_poisson_thresholds.argtypes = [C.c_double, P64, C.c_int]
+    lib.oracle_poisson_thresholds.restype = C.c_int
+    lib.oracle_binomial_thresholds.argtypes = [u32, C.c_double, P64, C.c_int]
+    lib.oracle_binomial_thresholds.restype = C.c_int
+    lib.oracle_geometric_thresholds.argtypes = [C.c_double, u32, P64]
+    lib.oracle_geometric_thresholds.restype = None
+    lib.oracle_recomb_mode.argtypes = [C.c_double]
+    lib.oracle_recomb_mode.restype = C.c_int
+    lib.oracle_create.argtypes = [C.POINTER(OracleParams)]
+    lib.oracle_create.restype = vp
+    lib.oracle_destroy.argtypes = [vp]
+    lib.oracle_destroy.restype = None
+    lib.oracle_step.argtypes = [vp, u32]
+    lib.oracle_step.restype = C.c_int
+    lib.oracle_get_stats.argtypes = [vp, C.POINTER(OracleStats)]
+    lib.oracle_get_stats.restype = None
+    lib.oracle_get_n.argtypes = [vp]
+    lib.oracle_get_n.restype = u32
+    lib.oracle_get_generation.argtypes = [vp]
+    lib.oracle_get_generation.restype = u32
+    lib.oracle_get_mode.argtypes = [vp]
+    lib.oracle_get_mode.restype = C.c_int
+    lib.oracle_get_genomes.argtypes = [vp, P32, C.c_size_t]
+    lib.oracle_get_genomes.restype = C.c_int
+    lib.oracle_set_genomes.argtypes = [vp, P32, u32, u32]
+    lib.oracle_set_genomes.restype = C.c_int
+    lib.oracle_get_phenotypes.argtypes = [vp, C.POINTER(i32), C.c_size_t]
+    lib.oracle_get_phenotypes.restype = C.c_int
+    lib.oracle_get_survivors.argtypes = [vp, P32, C.c_size_t]
+    lib.oracle_get_survivors.restype = u32
+    lib.oracle_get_parents.argtypes = [vp, P32, P32, C.c_size_t]
+    lib.oracle_get_parents.restype = C.c_int
+    lib.oracle_sample_gametes.argtypes = [vp, C.POINTER(C.c_uint8), u32, u32, u32, C.c_int, C.POINTER(C.c_uint8)]
+    lib.oracle_sample_gametes.restype = C.c_int
+    lib.oracle_phenotype.argtypes = [vp, C.POINTER(C.c_uint8), C.POINTER(C.c_uint8)]
+    lib.oracle_phenotype.restype = i32
+    _lib = lib
+    return lib
+
+
+def _p(arr, ctype):
+    return arr.ctypes.data_as(C.POINTER(ctype))
+
+
+def philox4x32_10(ctr, key):
+    lib = load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib.oracle_philox4x32_10(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(out, C.c_uint32))
+    return out
+
+
+def prob_threshold(p):
+    return int(load().oracle_prob_threshold(float(p)))
+
+
+def poisson_thresholds(lam, cap=1024):
+    out = np.zeros(cap, dtype=np.uint64)
+    n = load().oracle_poisson_thresholds(float(lam), _p(out, C.c_uint64), cap)
+    return out[:n].copy()
+
+
+def binomial_thresholds(L, mu, cap=1024):
+    out = np.zeros(cap, dtype=np.uint64)
+    n = load().oracle_binomial_thresholds(int(L), float(mu), _p(out, C.c_uint64), cap)
+    return out[:n].copy()
+
+
+def geometric_thresholds(r, n):
+    out = np.zeros(max(int(n), 1), dtype=np.uint64)
+    load().oracle_geometric_thresholds(float(r), int(n), _p(out, C.c_uint64))
+    return out[: int(n)].copy()
+
+
+def recomb_mode(r):
+    return MODE_NAMES[load().oracle_recomb_mode(float(r))]
+
+
+class OraclePop:
+    """One replicate in the oracle.  ``params`` is a dict with the keys of
+    ``OracleParams`` (effects as a sequence of ints or None)."""
+
+    def __init__(self, seed=1, replicate_id=0, regime=0, n0=100, capacity=None, n_loci=64,
+                 mu=0.0, r=0.5, theta=0.0, omega=0.0, K=0.0, fecundity=0.0, effects=None):
+        lib = load()
+        self.L = int(n_loci)
+        self.W = (self.L + 31) // 32
+        self._effects = None
+        eff_ptr = None
+        if effects is not None:
+            self._effects = np.ascontiguousarray(effects, dtype=np.int8)
+            assert self._effects.shape == (self.L,)
+            eff_ptr = _p(self._effects, C.c_int8)
+        prm = OracleParams(seed=seed, replicate_id=replicate_id, regime=regime, n0=n0,
+                           capacity=n0 if capacity is None else capacity, n_loci=n_loci, reserved=0,
+                           mu=mu, r=r, theta=theta, omega=omega, K=K, fecundity=fecundity,
+                           effects=eff_ptr)
+        self.capacity = prm.capacity
+        self._h = lib.oracle_create(C.byref(prm))
+        if not self._h:
+            raise ValueError("oracle_create rejected the parameters")
+        self._lib = lib
+
+    def close(self):
+        if self._h:
+            self._lib.oracle_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        self._lib.oracle_step(self._h, int(n))
+
+    @property
+    def n(self):
+        return int(self._lib.oracle_get_n(self._h))
+
+    @property
+    def generation(self):
+        return int(self._lib.oracle_get_generation(self._h))
+
+    @property
+    def mode(self):
+        return MODE_NAMES[self._lib.oracle_get_mode(self._h)]
+
+    def stats(self):
+        s = OracleStats()
+        self._lib.oracle_get_stats(self._h, C.byref(s))
+        return s.as_dict()
+
+    def genomes(self):
+        """Packed genomes, shape (n, 2, W) uint32."""
+        n = self.n
+        out = np.zeros(max(n, 1) * 2 * self.W, dtype=np.uint32)
+        assert self._lib.oracle_get_genomes(self._h, _p(out, C.c_uint32), out.size) == 0
+        return out[: n * 2 * self.W].reshape(n, 2, self.W)
+
+    def alleles(self):
+        """Unpacked alleles, shape (n, 2, L) uint8."""
+        g = self.genomes()
+        bits = np.unpackbits(g.view(np.uint8).reshape(g.shape[0], 2, -1), axis=-1, bitorder="little")
+        return bits[..., : self.L]
+
+    def set_genomes(self, words, generation):
+        w = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1)
+        n = w.size // (2 * self.W)
+        assert self._lib.oracle_set_genomes(self._h, _p(w, C.c_uint32), n, int(generation)) == 0
+
+    def phenotypes(self):
+        n = self.n
+        out = np.zeros(max(n, 1), dtype=np.int32)
+        assert self._lib.oracle_get_phenotypes(self._h, _p(out, C.c_int32), out.size) == 0
+        return out[:n]
+
+    def survivors(self):
+        m = self._lib.oracle_get_survivors(self._h, None, 0)
+        out = np.zeros(max(m, 1), dtype=np.uint32)
+        self._lib.oracle_get_survivors(self._h, _p(out, C.c_uint32), out.size)
+        return out[:m]
+
+    def parents(self):
+        n = self.n
+        mom = np.zeros(max(n, 1), dtype=np.uint32)
+        dad = np.zeros(max(n, 1), dtype=np.uint32)
+        assert self._lib.oracle_get_parents(self._h, _p(mom, C.c_uint32), _p(dad, C.c_uint32), mom.size) == 0
+        return mom[:n], dad[:n]
+
+    def sample_gametes(self, parent_alleles, j0, count, gen=0, paternal=False):
+        """Gametes (count, L) uint8 of a parent given as (2, L) alleles."""
+        par = np.ascontiguousarray(parent_alleles, dtype=np.uint8).reshape(2 * self.L)
+        out = np.zeros((count, self.L), dtype=np.uint8)
+        self._lib.oracle_sample_gametes(self._h, _p(par, C.c_uint8), int(j0), int(count), int(gen),
+                                        1 if paternal else 0, _p(out, C.c_uint8))
+        return out
+
+    def phenotype_of(self, h0, h1):
+        a = np.ascontiguousarray(h0, dtype=np.uint8)
+        b = np.ascontiguousarray(h1, dtype=np.uint8)
+        return int(self._lib.oracle_phenotype(self._h, _p(a, C.c_uint8), _p(b, C.c_uint8)))

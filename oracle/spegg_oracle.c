@@ -1,0 +1,682 @@
+/*
+ * spegg_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU oracle for the per-generation update
+ * of sPEGG's individual-based model (Okamoto & Amarasekare, "sPEGG: high
+ * throughput eco-evolutionary simulations on commodity graphics
+ * processors"): main text, Fig. 1 steps A-F; Supplementary Information S2,
+ * "Genetics"; Supplementary Fig. S5(A), the serial loop over replicates and
+ * individuals.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this file's library.  It shares no source with the GPU
+ * library: its own Philox, its own threshold tables, its own genome
+ * representation (one byte per allele, not packed words).  Conversions to
+ * the packed layout exist only so that results can be compared.
+ *
+ * The genetics follow the biallelic reading of the paper's additive model:
+ * allele value A = e_l * (2b - 1) at locus l with b in {0,1}, so the paper's
+ * midpoint sum over loci of (A_f + A_m)/2 (eqn. S2 phenotype value, noise
+ * variance zero) is exactly the integer z = sum_l e_l (b_f + b_m - 1).
+ *
+ * Every random decision is an integer comparison of a Philox4x32-10 word
+ * (Salmon, Moraes, Dror & Shaw, SC'11) against a threshold; probabilities
+ * are computed in IEEE double (basic operations plus glibc exp) and
+ * distribution tables in x87 extended precision, each from its definition.
+ *
+ * Pins: see tests/test_oracle_*.py.  Every function below is pinned there
+ * against a published value, a closed form, an exact enumeration or a
+ * population-genetic law; none is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_ALWAYS 4294967296ULL /* threshold that every 32-bit word is below */
+#define TWO32 4294967296.0
+#define TWO32L 4294967296.0L
+
+/* Philox counter field c1 = stream << 24 | sub.  One stream per kind of
+ * random decision, so that no decision reuses another's words. */
+enum {
+    ST_INIT = 1,
+    ST_SURVIVE = 3,
+    ST_FECUND = 4,
+    ST_PARENT = 5,
+    ST_RECOMB_MAT = 6,
+    ST_RECOMB_PAT = 7,
+    ST_MUTATE_MAT = 8,
+    ST_MUTATE_PAT = 9
+};
+
+enum { REGIME_WF = 0, REGIME_POISSON_BH = 1 };
+enum { MODE_RAW = 0, MODE_ZERO = 1, MODE_SKIP = 2, MODE_LAZY = 3 };
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10, written from its published definition (Salmon et al. */
+/* 2011, section 3): ten rounds of two 32x32->64 multiplications with  */
+/* the Weyl key schedule.                                               */
+/* ------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    int round;
+    for (round = 0; round < 10; ++round) {
+        uint64_t prod_a = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t prod_b = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(prod_b >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)prod_b;
+        uint32_t y2 = (uint32_t)(prod_a >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)prod_a;
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        x3 = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+/* Counter-based stream: the word for (individual index, stream, sub,
+ * component) in generation gen of the replicate identified by c3.  The
+ * last block is memoised; that changes no result. */
+typedef struct {
+    uint32_t key[2];
+    uint32_t c3;
+    uint32_t memo_ctr[4];
+    uint32_t memo_out[4];
+    int memo_valid;
+} rng_ctx;
+
+static uint32_t rng_word(rng_ctx *g, uint32_t index, uint32_t stream, uint32_t gen, uint32_t sub, uint32_t comp)
+{
+    uint32_t ctr[4];
+    ctr[0] = index;
+    ctr[1] = (stream << 24) | sub;
+    ctr[2] = gen;
+    ctr[3] = g->c3;
+    if (!(g->memo_valid && memcmp(ctr, g->memo_ctr, sizeof ctr) == 0)) {
+        oracle_philox4x32_10(ctr, g->key, g->memo_out);
+        memcpy(g->memo_ctr, ctr, sizeof ctr);
+        g->memo_valid = 1;
+    }
+    return g->memo_out[comp];
+}
+
+/* Word q of a stream read as one sequence: block q/4, component q%4. */
+static uint32_t seq_word(rng_ctx *g, uint32_t index, uint32_t stream, uint32_t gen, uint32_t q)
+{
+    return rng_word(g, index, stream, gen, q >> 2, q & 3u);
+}
+
+/* Uniform index in [0, n): floor(x * n / 2^64) with x the 64-bit word
+ * lo | hi << 32, so every index has probability 1/n up to 2^-64. */
+static uint32_t uniform_index(uint32_t lo, uint32_t hi, uint32_t n)
+{
+    unsigned __int128 x = ((unsigned __int128)hi << 32) | lo;
+    return (uint32_t)((x * n) >> 64);
+}
+
+/* ------------------------------------------------------------------ */
+/* Thresholds.  A Bernoulli(p) decision is "x < T" with T = floor(p 2^32)*/
+/* (p >= 1: always, p <= 0: never).  A discrete draw by inversion is    */
+/* k = min{k : x < T_k} with T_k = floor(F(k) 2^32); the last entry is  */
+/* "always".  A table ends at the first k whose T_k reaches 2^32 - 1.   */
+/* ------------------------------------------------------------------ */
+uint64_t oracle_prob_threshold(double p)
+{
+    if (p >= 1.0)
+        return ORACLE_ALWAYS;
+    if (!(p > 0.0))
+        return 0;
+    return (uint64_t)floor(p * TWO32);
+}
+
+static int close_table(long double cdf, int k, int cap, uint64_t *T)
+{
+    long double scaled = floorl(cdf * TWO32L);
+    if (scaled >= 4294967295.0L || k == cap - 1) {
+        T[k] = ORACLE_ALWAYS;
+        return 1;
+    }
+    T[k] = (uint64_t)scaled;
+    return 0;
+}
+
+/* Poisson(lambda) inverse-CDF thresholds: p_0 = e^-lambda,
+ * p_k = p_{k-1} lambda / k, F(k) = F(k-1) + p_k.  Returns the length. */
+int oracle_poisson_thresholds(double lambda, uint64_t *T, int cap)
+{
+    long double pk = expl(-(long double)lambda), cdf = 0.0L;
+    int k;
+    for (k = 0; k < cap; ++k) {
+        if (k > 0)
+            pk = pk * (long double)lambda / (long double)k;
+        cdf += pk;
+        if (close_table(cdf, k, cap, T))
+            return k + 1;
+    }
+    return cap;
+}
+
+/* Binomial(L, mu) inverse-CDF thresholds: p_0 = (1-mu)^L,
+ * p_k = p_{k-1} (L-k+1)/k mu/(1-mu).  Valid for 0 <= mu < 1. */
+int oracle_binomial_thresholds(uint32_t L, double mu, uint64_t *T, int cap)
+{
+    long double m = (long double)mu;
+    long double pk = powl(1.0L - m, (long double)L), cdf = 0.0L;
+    int k;
+    for (k = 0; k < cap; ++k) {
+        if (k > 0) {
+            if ((uint32_t)k > L)
+                pk = 0.0L;
+            else
+                pk = pk * (long double)(L - (uint32_t)k + 1u) / (long double)k * m / (1.0L - m);
+        }
+        cdf += pk;
+        if ((uint32_t)k == L) { /* all mass is in 0..L */
+            T[k] = ORACLE_ALWAYS;
+            return k + 1;
+        }
+        if (close_table(cdf, k, cap, T))
+            return k + 1;
+    }
+    return cap;
+}
+
+/* Geometric skip thresholds: the number of non-crossover boundaries
+ * before the next crossover, g, has P(g <= k) = 1 - (1-r)^(k+1).
+ * T_k = floor((1 - (1-r)^(k+1)) 2^32) for k = 0 .. n-1. */
+void oracle_geometric_thresholds(double r, uint32_t n, uint64_t *T)
+{
+    uint32_t k;
+    for (k = 0; k < n; ++k)
+        T[k] = (uint64_t)floorl((1.0L - powl(1.0L - (long double)r, (long double)(k + 1u))) * TWO32L);
+}
+
+/* Inversion: smallest k with x < T_k. */
+static uint32_t draw_by_table(uint32_t x, const uint64_t *T, int len)
+{
+    int k = 0;
+    while (k < len - 1 && (uint64_t)x >= T[k])
+        ++k;
+    return (uint32_t)k;
+}
+
+/* ------------------------------------------------------------------ */
+/* Parameters, state, statistics.                                      */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    uint64_t seed;
+    uint32_t replicate_id;
+    uint32_t regime; /* 0: Wright-Fisher, constant N; 1: Poisson fecundity, Beverton-Holt survival */
+    uint32_t n0, capacity, n_loci, reserved;
+    double mu, r, theta, omega, K, fecundity;
+    const int8_t *effects; /* n_loci values, NULL: all +1 */
+} oracle_params;
+
+typedef struct {
+    uint32_t generation, n, n_parents, n_survivors, extinct, reserved;
+    int64_t sum_z, sum_z2;
+    uint64_t near_ties, truncated, sum_threshold;
+} oracle_stats;
+
+typedef struct {
+    oracle_params prm;
+    int8_t *effects;
+    rng_ctx rng;
+    int mode;
+    uint32_t L;
+    uint64_t *geo;   /* L-1 entries */
+    uint64_t *binom; /* mutation-count table */
+    int binom_len;
+    uint64_t *pois;
+    int pois_len;
+    /* state: genome[i][h][l] one byte per allele, z[i] */
+    uint32_t generation, n;
+    uint8_t *genome;
+    int32_t *z;
+    /* the last generation's survivors and parents, for comparison */
+    uint32_t *survivors, n_survivors;
+    uint32_t *mom, *dad;
+    oracle_stats stats;
+} oracle_pop;
+
+#define TABLE_CAP 1024
+
+/* The crossover-sampling mode is a function of r alone. */
+int oracle_recomb_mode(double r)
+{
+    if (r == 0.5)
+        return MODE_RAW;
+    if (r == 0.0)
+        return MODE_ZERO;
+    if (r < 0.17)
+        return MODE_SKIP;
+    return MODE_LAZY;
+}
+
+/* Viability under Gaussian stabilising selection, v(z) = exp(-(z-theta)^2
+ * / (2 omega^2)); omega <= 0 switches selection off. */
+static double viability(const oracle_pop *P, int32_t z)
+{
+    double d;
+    if (!(P->prm.omega > 0.0))
+        return 1.0;
+    d = (double)z - P->prm.theta;
+    return exp(-(d * d) / (2.0 * P->prm.omega * P->prm.omega));
+}
+
+/* Beverton-Holt density factor s(N) = 1 / (1 + (lambda - 1) N / K): with
+ * Poisson(lambda) offspring per survivor the expected next census is
+ * lambda N s(N), whose fixed point is K when selection is off. */
+static double density_factor(const oracle_pop *P, uint32_t n)
+{
+    if (P->prm.regime != REGIME_POISSON_BH || !(P->prm.K > 0.0))
+        return 1.0;
+    return 1.0 / (1.0 + (P->prm.fecundity - 1.0) * (double)n / P->prm.K);
+}
+
+/* Additive genotype-phenotype map, z = sum_l e_l (b0_l + b1_l - 1). */
+static int32_t phenotype(const oracle_pop *P, const uint8_t *h0, const uint8_t *h1)
+{
+    int64_t z = 0;
+    uint32_t l;
+    for (l = 0; l < P->L; ++l)
+        z += (int64_t)P->effects[l] * ((int64_t)h0[l] + (int64_t)h1[l] - 1);
+    return (int32_t)z;
+}
+
+static uint8_t *allele_row(const oracle_pop *P, uint8_t *g, uint32_t i, uint32_t h)
+{
+    return g + ((size_t)i * 2u + h) * P->L;
+}
+
+static void free_pop_state(oracle_pop *P)
+{
+    free(P->genome);
+    free(P->z);
+    free(P->survivors);
+    free(P->mom);
+    free(P->dad);
+    P->genome = NULL;
+    P->z = NULL;
+    P->survivors = P->mom = P->dad = NULL;
+}
+
+void oracle_destroy(oracle_pop *P)
+{
+    if (!P)
+        return;
+    free_pop_state(P);
+    free(P->effects);
+    free(P->geo);
+    free(P->binom);
+    free(P->pois);
+    free(P);
+}
+
+static void census(oracle_pop *P)
+{
+    uint32_t i;
+    P->stats.generation = P->generation;
+    P->stats.n = P->n;
+    P->stats.sum_z = 0;
+    P->stats.sum_z2 = 0;
+    for (i = 0; i < P->n; ++i) {
+        P->stats.sum_z += P->z[i];
+        P->stats.sum_z2 += (int64_t)P->z[i] * (int64_t)P->z[i];
+    }
+}
+
+oracle_pop *oracle_create(const oracle_params *prm)
+{
+    oracle_pop *P;
+    uint32_t L = prm->n_loci, l, i, h;
+    if (L == 0 || prm->n0 > prm->capacity || !(prm->mu >= 0.0 && prm->mu < 1.0) || !(prm->r >= 0.0 && prm->r <= 0.5))
+        return NULL;
+    P = (oracle_pop *)calloc(1, sizeof *P);
+    if (!P)
+        return NULL;
+    P->prm = *prm;
+    P->L = L;
+    P->effects = (int8_t *)malloc(L);
+    for (l = 0; l < L; ++l)
+        P->effects[l] = prm->effects ? prm->effects[l] : 1;
+    P->prm.effects = P->effects;
+    P->rng.key[0] = (uint32_t)prm->seed;
+    P->rng.key[1] = (uint32_t)(prm->seed >> 32);
+    P->rng.c3 = prm->replicate_id << 12; /* species 0, patch 0 */
+    P->mode = oracle_recomb_mode(prm->r);
+    P->geo = (uint64_t *)malloc(sizeof(uint64_t) * (L > 1 ? L - 1 : 1));
+    oracle_geometric_thresholds(prm->r, L - 1, P->geo);
+    P->binom = (uint64_t *)malloc(sizeof(uint64_t) * TABLE_CAP);
+    P->binom_len = oracle_binomial_thresholds(L, prm->mu, P->binom, TABLE_CAP);
+    P->pois = (uint64_t *)malloc(sizeof(uint64_t) * TABLE_CAP);
+    P->pois_len = oracle_poisson_thresholds(prm->fecundity, P->pois, TABLE_CAP);
+
+    /* Initial state: every allele an independent fair bit (Hardy-Weinberg,
+     * allele frequency one half), drawn from stream INIT in generation 0. */
+    P->generation = 0;
+    P->n = prm->n0;
+    P->genome = (uint8_t *)malloc((size_t)(prm->n0 ? prm->n0 : 1) * 2u * L);
+    P->z = (int32_t *)malloc(sizeof(int32_t) * (prm->n0 ? prm->n0 : 1));
+    {
+        uint32_t W = (L + 31u) / 32u;
+        for (i = 0; i < prm->n0; ++i) {
+            for (h = 0; h < 2; ++h) {
+                uint8_t *row = allele_row(P, P->genome, i, h);
+                for (l = 0; l < L; ++l) {
+                    uint32_t w = seq_word(&P->rng, i, ST_INIT, 0, h * W + l / 32u);
+                    row[l] = (uint8_t)((w >> (l % 32u)) & 1u);
+                }
+            }
+            P->z[i] = phenotype(P, allele_row(P, P->genome, i, 0), allele_row(P, P->genome, i, 1));
+        }
+    }
+    census(P);
+    P->stats.n_parents = 0;
+    return P;
+}
+
+/* ------------------------------------------------------------------ */
+/* Gamete formation (Fig. 1B; S2 "Genetics": a gamete carries half of  */
+/* the parent's alleles, then each locus mutates with probability mu). */
+/* mask[l] = 1 takes the allele of haplotype 1 at locus l.              */
+/* ------------------------------------------------------------------ */
+
+/* One boundary's crossover under the exact bit-serial comparison of a
+ * uniform 32-bit U against R = floor(r 2^32): bit i of U (from the top)
+ * is bit `bit` of word 31-i of the boundary's block. */
+static int lazy_crossover(rng_ctx *g, uint32_t j, uint32_t stream, uint32_t gen, uint32_t block, uint32_t bit, uint32_t R)
+{
+    int i;
+    for (i = 31; i >= 0; --i) {
+        uint32_t rest = (i == 31) ? R : (R & ((1u << (i + 1)) - 1u));
+        uint32_t q, x, u, ri;
+        if (rest == 0)
+            return 0; /* U >= R: the remaining bits of R are zero */
+        q = 31u - (uint32_t)i;
+        x = rng_word(g, j, stream, gen, 1u + block * 8u + (q >> 2), q & 3u);
+        u = (x >> bit) & 1u;
+        ri = (R >> i) & 1u;
+        if (u != ri)
+            return u < ri;
+    }
+    return 0; /* U == R */
+}
+
+static void recombination_mask(oracle_pop *P, uint32_t j, uint32_t stream, uint32_t gen, uint8_t *mask, uint8_t *toggles)
+{
+    uint32_t L = P->L, l;
+    uint32_t phase;
+    if (P->mode == MODE_RAW) {
+        /* r = 1/2: every locus independently takes either haplotype. */
+        for (l = 0; l < L; ++l)
+            mask[l] = (uint8_t)((seq_word(&P->rng, j, stream, gen, l / 32u) >> (l % 32u)) & 1u);
+        return;
+    }
+    phase = seq_word(&P->rng, j, stream, gen, 0) & 1u;
+    memset(toggles, 0, L);
+    toggles[0] = (uint8_t)phase;
+    if (P->mode == MODE_SKIP) {
+        /* Crossover boundaries b (between loci b-1 and b) with independent
+         * probability r: successive gaps are 1 + geometric. */
+        uint64_t b = 0;
+        uint32_t q = 1;
+        for (;;) {
+            uint32_t x = seq_word(&P->rng, j, stream, gen, q++);
+            uint32_t gap = 0; /* smallest k with x < T_k, else L - 1 */
+            while (gap + 1u < L && (uint64_t)x >= P->geo[gap])
+                ++gap;
+            b += 1u + gap;
+            if (b > L - 1u)
+                break;
+            toggles[b] = 1;
+        }
+    } else if (P->mode == MODE_LAZY) {
+        uint32_t R = (uint32_t)floor(P->prm.r * TWO32);
+        uint32_t bnd;
+        for (bnd = 1; bnd < L; ++bnd)
+            toggles[bnd] = (uint8_t)lazy_crossover(&P->rng, j, stream, gen, bnd / 32u, bnd % 32u, R);
+    }
+    /* MODE_ZERO: no crossover, the phase alone. */
+    {
+        uint8_t m = 0;
+        for (l = 0; l < L; ++l) {
+            m ^= toggles[l];
+            mask[l] = m;
+        }
+    }
+}
+
+static void make_gamete(oracle_pop *P, const uint8_t *h0, const uint8_t *h1, uint32_t j, uint32_t gen, int paternal, uint8_t *out, uint8_t *scratch)
+{
+    uint32_t L = P->L, l;
+    uint8_t *mask = scratch, *toggles = scratch + L, *chosen = scratch + 2u * L;
+    uint32_t rstream = paternal ? ST_RECOMB_PAT : ST_RECOMB_MAT;
+    uint32_t mstream = paternal ? ST_MUTATE_PAT : ST_MUTATE_MAT;
+    uint32_t K, accepted = 0, cand = 0;
+    recombination_mask(P, j, rstream, gen, mask, toggles);
+    for (l = 0; l < L; ++l)
+        out[l] = mask[l] ? h1[l] : h0[l];
+    /* Mutation: K ~ Binomial(L, mu) loci, chosen uniformly without
+     * replacement, each flipped -- the same law as an independent flip at
+     * each locus with probability mu. */
+    K = draw_by_table(seq_word(&P->rng, j, mstream, gen, 0), P->binom, P->binom_len);
+    if (K == 0)
+        return;
+    memset(chosen, 0, L);
+    while (accepted < K) {
+        uint32_t lo = seq_word(&P->rng, j, mstream, gen, 1u + 2u * cand);
+        uint32_t hi = seq_word(&P->rng, j, mstream, gen, 2u + 2u * cand);
+        uint32_t pos = uniform_index(lo, hi, L);
+        ++cand;
+        if (chosen[pos])
+            continue;
+        chosen[pos] = 1;
+        out[pos] ^= 1u;
+        ++accepted;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* One generation (Fig. 1): survival under the selective environment   */
+/* (D), removal of the dead (E), parents and neonate count (A),        */
+/* transmission (B), phenotypes of the newborns (C).                   */
+/* ------------------------------------------------------------------ */
+int oracle_step(oracle_pop *P, uint32_t n_generations)
+{
+    uint32_t it;
+    for (it = 0; it < n_generations; ++it) {
+        uint32_t t = P->generation, n = P->n, L = P->L, i, j;
+        uint32_t ns = 0, nn;
+        uint64_t ktot = 0, sumT = 0;
+        double s = density_factor(P, n);
+        uint8_t *alive = (uint8_t *)calloc(n ? n : 1, 1);
+        uint32_t *kids = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+        uint32_t *owner = NULL;
+        uint8_t *next;
+        int32_t *znext;
+        uint8_t *scratch = (uint8_t *)malloc(3u * L);
+
+        /* Survival: Bernoulli(v(z) s(N)) per adult. */
+        for (i = 0; i < n; ++i) {
+            double p = viability(P, P->z[i]) * s;
+            uint64_t T = oracle_prob_threshold(p);
+            uint32_t x = seq_word(&P->rng, i, ST_SURVIVE, t, 0);
+            alive[i] = (uint8_t)((uint64_t)x < T);
+            sumT += T;
+            if (p > 0.0 && p < 1.0 && fabs((double)x * (1.0 / TWO32) - p) < 1e-6)
+                P->stats.near_ties++;
+        }
+        /* Removal of the dead: survivors in ascending index order. */
+        free(P->survivors);
+        P->survivors = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+        for (i = 0; i < n; ++i)
+            if (alive[i])
+                P->survivors[ns++] = i;
+        P->n_survivors = ns;
+
+        /* Neonate count. */
+        if (ns == 0) {
+            nn = 0;
+        } else if (P->prm.regime == REGIME_WF) {
+            nn = n;
+        } else {
+            uint32_t slot = 0;
+            for (i = 0; i < ns; ++i) {
+                kids[i] = draw_by_table(seq_word(&P->rng, P->survivors[i], ST_FECUND, t, 0), P->pois, P->pois_len);
+                ktot += kids[i];
+            }
+            nn = ktot > P->prm.capacity ? P->prm.capacity : (uint32_t)ktot;
+            P->stats.truncated += ktot - nn;
+            owner = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
+            for (i = 0; i < ns; ++i) {
+                uint32_t m;
+                for (m = 0; m < kids[i]; ++m, ++slot)
+                    if (slot < nn)
+                        owner[slot] = P->survivors[i];
+            }
+        }
+
+        /* Parents and transmission. */
+        free(P->mom);
+        free(P->dad);
+        P->mom = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
+        P->dad = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
+        next = (uint8_t *)malloc((size_t)(nn ? nn : 1) * 2u * L);
+        znext = (int32_t *)malloc(sizeof(int32_t) * (nn ? nn : 1));
+        for (j = 0; j < nn; ++j) {
+            uint32_t w0 = seq_word(&P->rng, j, ST_PARENT, t, 0);
+            uint32_t w1 = seq_word(&P->rng, j, ST_PARENT, t, 1);
+            uint32_t w2 = seq_word(&P->rng, j, ST_PARENT, t, 2);
+            uint32_t w3 = seq_word(&P->rng, j, ST_PARENT, t, 3);
+            uint32_t mom, dad;
+            if (P->prm.regime == REGIME_WF)
+                mom = P->survivors[uniform_index(w0, w1, ns)];
+            else
+                mom = owner[j];
+            dad = P->survivors[uniform_index(w2, w3, ns)];
+            P->mom[j] = mom;
+            P->dad[j] = dad;
+            make_gamete(P, allele_row(P, P->genome, mom, 0), allele_row(P, P->genome, mom, 1), j, t, 0, allele_row(P, next, j, 0), scratch);
+            make_gamete(P, allele_row(P, P->genome, dad, 0), allele_row(P, P->genome, dad, 1), j, t, 1, allele_row(P, next, j, 1), scratch);
+            znext[j] = phenotype(P, allele_row(P, next, j, 0), allele_row(P, next, j, 1));
+        }
+        free(P->genome);
+        free(P->z);
+        P->genome = next;
+        P->z = znext;
+        P->n = nn;
+        P->generation = t + 1;
+        P->stats.n_parents = n;
+        P->stats.n_survivors = ns;
+        P->stats.sum_threshold = sumT;
+        if (nn == 0)
+            P->stats.extinct = 1;
+        census(P);
+        free(alive);
+        free(kids);
+        free(owner);
+        free(scratch);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Accessors.  Packed layout: individual i, haplotype h, word w holds  */
+/* loci 32w .. 32w+31, locus l at bit l % 32; tail bits are zero.       */
+/* ------------------------------------------------------------------ */
+void oracle_get_stats(const oracle_pop *P, oracle_stats *out) { *out = P->stats; }
+uint32_t oracle_get_n(const oracle_pop *P) { return P->n; }
+uint32_t oracle_get_generation(const oracle_pop *P) { return P->generation; }
+int oracle_get_mode(const oracle_pop *P) { return P->mode; }
+
+int oracle_get_genomes(const oracle_pop *P, uint32_t *words, size_t n_words)
+{
+    uint32_t W = (P->L + 31u) / 32u, i, h, l;
+    if (n_words < (size_t)P->n * 2u * W)
+        return -1;
+    memset(words, 0, sizeof(uint32_t) * (size_t)P->n * 2u * W);
+    for (i = 0; i < P->n; ++i)
+        for (h = 0; h < 2; ++h) {
+            const uint8_t *row = P->genome + ((size_t)i * 2u + h) * P->L;
+            uint32_t *dst = words + ((size_t)i * 2u + h) * W;
+            for (l = 0; l < P->L; ++l)
+                dst[l / 32u] |= (uint32_t)row[l] << (l % 32u);
+        }
+    return 0;
+}
+
+int oracle_set_genomes(oracle_pop *P, const uint32_t *words, uint32_t n, uint32_t generation)
+{
+    uint32_t W = (P->L + 31u) / 32u, i, h, l;
+    if (n > P->prm.capacity)
+        return -1;
+    free_pop_state(P);
+    P->genome = (uint8_t *)malloc((size_t)(n ? n : 1) * 2u * P->L);
+    P->z = (int32_t *)malloc(sizeof(int32_t) * (n ? n : 1));
+    for (i = 0; i < n; ++i) {
+        for (h = 0; h < 2; ++h) {
+            uint8_t *row = P->genome + ((size_t)i * 2u + h) * P->L;
+            const uint32_t *src = words + ((size_t)i * 2u + h) * W;
+            for (l = 0; l < P->L; ++l)
+                row[l] = (uint8_t)((src[l / 32u] >> (l % 32u)) & 1u);
+        }
+        P->z[i] = phenotype(P, P->genome + (size_t)i * 2u * P->L, P->genome + ((size_t)i * 2u + 1u) * P->L);
+    }
+    P->n = n;
+    P->generation = generation;
+    P->n_survivors = 0;
+    memset(&P->stats, 0, sizeof P->stats);
+    P->stats.extinct = n == 0;
+    census(P);
+    return 0;
+}
+
+int oracle_get_phenotypes(const oracle_pop *P, int32_t *z, size_t n)
+{
+    if (n < P->n)
+        return -1;
+    memcpy(z, P->z, sizeof(int32_t) * P->n);
+    return 0;
+}
+
+uint32_t oracle_get_survivors(const oracle_pop *P, uint32_t *S, size_t n)
+{
+    if (S && n >= P->n_survivors)
+        memcpy(S, P->survivors, sizeof(uint32_t) * P->n_survivors);
+    return P->n_survivors;
+}
+
+int oracle_get_parents(const oracle_pop *P, uint32_t *mom, uint32_t *dad, size_t n)
+{
+    if (n < P->n)
+        return -1;
+    memcpy(mom, P->mom, sizeof(uint32_t) * P->n);
+    memcpy(dad, P->dad, sizeof(uint32_t) * P->n);
+    return 0;
+}
+
+/* Gametes of one parent for offspring slots j0 .. j0+count-1 in
+ * generation gen (the statistical pins sample this directly).  parent is
+ * 2L bytes (haplotype 0 then 1); out is count x L bytes. */
+int oracle_sample_gametes(oracle_pop *P, const uint8_t *parent, uint32_t j0, uint32_t count, uint32_t gen, int paternal, uint8_t *out)
+{
+    uint32_t c;
+    uint8_t *scratch = (uint8_t *)malloc(3u * P->L);
+    for (c = 0; c < count; ++c)
+        make_gamete(P, parent, parent + P->L, j0 + c, gen, paternal, out + (size_t)c * P->L, scratch);
+    free(scratch);
+    return 0;
+}
+
+/* The phenotype of given allele rows (for pins of the map). */
+int32_t oracle_phenotype(const oracle_pop *P, const uint8_t *h0, const uint8_t *h1) { return phenotype(P, h0, h1); }
