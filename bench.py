@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Throughput of the per-generation update on one MI355X.
+
+Workload: the plain method at scale -- one replicate, N0 = 100000 diploids
+(capacity 250000), L = 1024 loci packed in uint32 words, allelic effects on
+the integer grid [-4, 4], adjacent-locus crossover probability 0.01,
+mutation 1e-6 per locus, Poisson(2.2) fecundity with Beverton-Holt
+density-dependent survival (K = 100000) and Gaussian stabilising selection
+of width 64.  A step is one generation (survival, compaction, fecundity,
+parents, gametes, phenotypes, census) of that population; the data are
+synthetic (seeded Philox initial genomes).
+
+Prints one JSON line: genotype-locus updates/s (sum over timed generations
+of N_t x L, divided by wall time with inputs resident on the device), the
+roofline of the offspring kernel measured with HIP events in the timed
+region, and the CPU oracle timed on a bounded sample on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "genotype-locus updates/s on 1 GPU (% HBM roofline); p50/p99 sweep-job latency"
+UNIT = "genotype-locus updates/s"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_update(L):
+    # compulsory traffic of a generation per genotype-locus update: read the
+    # parents' genomes once and write the newborns' once (2 x L/4 bytes per
+    # individual over L updates), plus about 20 bytes of per-individual
+    # metadata (phenotype read and write, survivor index, two parent indices)
+    return 0.5 + 20.0 / L
+
+
+def cpu_baseline(desc, budget_s):
+    """The oracle (plain serial loop) on the host, single thread, on as many
+    generations of the same workload as fit in about budget_s seconds."""
+    import oracle
+
+    keys = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
+            "fecundity", "effects")
+    orc = oracle.OraclePop(**{k: desc[k] for k in keys})
+    start_updates = orc.stats()["updates"]
+    gens = 0
+    t0 = time.perf_counter()
+    while True:
+        orc.step(1)
+        gens += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or gens >= 200:
+            break
+    upd = orc.stats()["updates"] - start_updates
+    orc.close()
+    return {"value": upd / el, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"{gens} generations of the same workload from its initial population "
+                      f"({upd} updates, {el:.1f} s, initialisation excluded), one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000, help="timed generations")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed generations first")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the workload is one replicate "
+              "resident on one device)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1603_09255_amd import spegg, workloads
+
+    desc, _ = workloads.plain_scale(seed=1)
+    L = desc["n_loci"]
+    torch.cuda.set_device(0)
+    log(f"bench: creating population N0={desc['n0']} L={L}")
+    pop = spegg.Population([desc])
+    torch.cuda.synchronize()
+    log(f"bench: warmup {args.warmup} generations")
+    pop.step(args.warmup)
+    torch.cuda.synchronize()
+
+    # Timed region: K generations; the offspring kernel is bracketed by HIP
+    # events on the population's stream.
+    pop.set_timing(["offspring"])
+    pop.kernel_times()
+    s0 = pop.stats()[0]
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} generations")
+    t0 = time.perf_counter()
+    pop.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1 = pop.stats()[0]
+    kt = pop.kernel_times()
+    pop.set_timing([])
+    elapsed = t1 - t0
+    updates = s1["updates"] - s0["updates"]
+    value = updates / elapsed
+    off_ms, off_n = kt["offspring"]
+    per_launch_bytes = updates / max(off_n, 1) * bytes_per_update(L)
+    avg_launch_s = off_ms / 1e3 / max(off_n, 1)
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    log(f"bench: {updates} updates in {elapsed * 1e3:.2f} ms; offspring kernel avg {avg_launch_s * 1e6:.2f} us "
+        f"x {off_n}; N now {s1['n']}")
+
+    # The same K generations without events, for the event overhead.
+    s0b = pop.stats()[0]
+    torch.cuda.synchronize()
+    t0b = time.perf_counter()
+    pop.step(args.steps)
+    torch.cuda.synchronize()
+    t1b = time.perf_counter()
+    s1b = pop.stats()[0]
+    value_plain = (s1b["updates"] - s0b["updates"]) / (t1b - t0b)
+    log(f"bench: without events {value_plain:.4g} updates/s ({(t1b - t0b) * 1e3:.2f} ms)")
+    pop.close()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain method at scale: 1 replicate, N0=100000 (capacity 250000), L=1024 loci in uint32 "
+                        "words, effects on [-4,4], r=0.01, mu=1e-6, Poisson(2.2) fecundity, Beverton-Holt "
+                        "survival K=100000, stabilising selection width 64",
+            "replicates": 1,
+            "n_loci": L,
+            "generations_timed": args.steps,
+            "mean_census": updates / args.steps / L,
+            "updates_per_s_without_events": value_plain,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "offspring",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_update": bytes_per_update(L),
+            "avg_launch_us": avg_launch_s * 1e6,
+            "launches": off_n,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log(f"bench: CPU oracle sample, about {args.cpu_seconds:.0f} s")
+        out["cpu_baseline"] = cpu_baseline(desc, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * spegg.h -- C ABI of the MI355X implementation of sPEGG's per-generation
+ * update (Okamoto & Amarasekare, "sPEGG: high throughput eco-evolutionary
+ * simulations on commodity graphics processors").
+ *
+ * What one generation computes (main text, Fig. 1, steps A-F):
+ *   D  survival under the selective environment: adult i survives with
+ *      probability v(z_i) s(N_t), v Gaussian stabilising viability, s the
+ *      Beverton-Holt density factor (regime SPEGG_POISSON_BH only);
+ *   E  the dead are removed: survivors listed in ascending index order;
+ *   A  parents and neonate count: Wright-Fisher keeps N constant and draws
+ *      mother and father uniformly from the survivors; the Poisson regime
+ *      gives each survivor Poisson(lambda) offspring as mother, capped at the
+ *      capacity, with a uniformly drawn father;
+ *   B  transmission: each parent makes a gamete by crossing over between its
+ *      two haplotypes (independent crossovers with probability r at each
+ *      boundary between adjacent loci) and flipping each locus with
+ *      probability mu (Supplementary Information S2, "Genetics");
+ *   C  the newborn's phenotype by the additive map
+ *      z = sum_l e_l (b0_l + b1_l - 1), the biallelic form of the paper's
+ *      midpoint sum of allelic values (eqn. S2, phenotype value).
+ * Replicates advance together as one flattened loop over individuals
+ * (Supplementary Fig. S5(B)); each replicate keeps its own parameters.
+ *
+ * Genome layout (device and host copies alike): individual i of a replicate
+ * owns 2W consecutive uint32 words, W = ceil(L/32): haplotype 0 (maternal)
+ * words 0..W-1, then haplotype 1 (paternal).  Locus l is bit l%32 of word
+ * l/32; bits at loci >= L are zero.  Seen as uint64 on a little-endian
+ * machine this is the same bit order.
+ *
+ * Randomness: Philox4x32-10 keyed by the replicate's 64-bit seed, with
+ * counter (index, stream << 24 | block, generation, replicate_id << 12).
+ * No counter field encodes a batch position, a thread or a tile, so a
+ * replicate's trajectory is the same alone or in any batch.
+ *
+ * Memory: the caller owns the device memory (one block of
+ * spegg_footprint() bytes, 256-byte aligned) and the HIP stream; the library
+ * never allocates device memory.  Every call below that takes a spegg_pop
+ * is enqueued on that stream.  One handle is used by one thread at a time.
+ *
+ * Errors: every call returns a status and never throws.  A failed HIP call
+ * returns SPEGG_E_DEVICE and makes the handle sticky-errored: later calls
+ * return SPEGG_E_STATE.  spegg_last_error() gives the calling thread's
+ * message for the last non-OK status.  Extinction and capacity truncation
+ * are not errors: they are reported in spegg_rep_stats.
+ */
+#ifndef SPEGG_H
+#define SPEGG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPEGG_ABI_VERSION 1
+#define SPEGG_MAX_LOCI 16384u
+#define SPEGG_MAX_REPLICATE_ID ((1u << 20) - 1u)
+
+typedef enum {
+    SPEGG_OK = 0,
+    SPEGG_E_INVALID = -1,     /* an argument or descriptor is out of range */
+    SPEGG_E_NOMEM = -2,       /* the caller's workspace is too small or misaligned */
+    SPEGG_E_DEVICE = -3,      /* a HIP call failed; the handle is now sticky-errored */
+    SPEGG_E_STATE = -4,       /* the handle is errored, or the call needs a mode that is off */
+    SPEGG_E_UNSUPPORTED = -5  /* valid model, but outside what this build implements */
+} spegg_status;
+
+typedef enum {
+    SPEGG_WF = 0,         /* Wright-Fisher: N constant, viability selection, parents uniform over survivors */
+    SPEGG_POISSON_BH = 1  /* Poisson(fecundity) offspring per surviving mother, survival x Beverton-Holt s(N) */
+} spegg_regime;
+
+typedef struct spegg_pop spegg_pop; /* opaque; owns no device memory */
+
+/* One replicate.  The per-deme parameter table of Supplementary Fig. S5(B):
+ * every individual looks up its replicate's entry. */
+typedef struct spegg_rep_desc {
+    uint64_t seed;         /* Philox key */
+    uint32_t replicate_id; /* logical replicate id, 0..SPEGG_MAX_REPLICATE_ID; never a batch slot */
+    uint32_t regime;       /* spegg_regime */
+    uint32_t n0;           /* initial census, <= capacity */
+    uint32_t capacity;     /* most individuals the replicate may hold, >= 1 */
+    uint32_t n_loci;       /* L, 1..SPEGG_MAX_LOCI */
+    uint32_t reserved;     /* must be 0 */
+    double mu;             /* per-locus, per-gamete flip probability, 0 <= mu < 1 */
+    double r;              /* crossover probability at each adjacent-locus boundary, 0 <= r <= 1/2 */
+    double theta;          /* optimum of Gaussian stabilising selection */
+    double omega;          /* its width, v(z) = exp(-(z-theta)^2 / (2 omega^2)); omega <= 0: no selection */
+    double K;              /* Beverton-Holt carrying capacity (POISSON_BH); K <= 0: no density dependence */
+    double fecundity;      /* Poisson mean lambda (POISSON_BH) */
+    const int8_t *effects; /* n_loci allelic effects in [-4, 4], copied at create; NULL: all +1 */
+} spegg_rep_desc;
+
+/* Census of one replicate after its latest generation. */
+typedef struct spegg_rep_stats {
+    uint32_t generation;    /* t: generations completed since creation (or since the last write) */
+    uint32_t n;             /* N_t */
+    uint32_t n_parents;     /* N_{t-1}, the adults the last generation started from */
+    uint32_t n_survivors;   /* survivors among them */
+    uint32_t extinct;       /* 1 once N reached 0 */
+    uint32_t reserved;
+    int64_t sum_z;          /* sum of z over the N_t individuals (exact) */
+    int64_t sum_z2;         /* sum of z^2 (exact) */
+    uint64_t near_ties;     /* cumulative survival draws with |x 2^-32 - p| < 1e-6, 0 < p < 1 */
+    uint64_t truncated;     /* cumulative offspring dropped at the capacity */
+    uint64_t sum_threshold; /* sum over the last adults of floor(p 2^32): mean viability x 2^32 x n_parents */
+    uint64_t updates;       /* cumulative genotype-locus updates: sum over generations of N_t x L */
+} spegg_rep_stats;
+
+/* ABI version of the loaded library; equals SPEGG_ABI_VERSION. */
+int spegg_abi_version(void);
+
+/* Message for the calling thread's last non-OK status ("" if none).  The
+ * pointer stays valid until the thread's next spegg call. */
+const char *spegg_last_error(void);
+
+/* Device bytes a population of these replicates needs; 0 if a descriptor
+ * is invalid (spegg_last_error says which).  Host-only; no device access. */
+size_t spegg_footprint(const spegg_rep_desc *reps, uint32_t n_reps);
+
+/* Validate the descriptors, carve the caller's workspace (device_mem,
+ * device_bytes >= spegg_footprint, 256-byte aligned), upload the parameter
+ * tables, and enqueue the initial population on hip_stream (a hipStream_t;
+ * NULL is the null stream): every allele an independent fair bit, drawn
+ * from the INIT stream in generation 0.  Returns without waiting.  The
+ * handle borrows device_mem and the stream; both must outlive it. */
+spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void *device_mem, size_t device_bytes,
+                              void *hip_stream, spegg_pop **out);
+
+/* Enqueue n_generations full generations (Fig. 1 steps D, E, A, B, C) for
+ * every replicate.  Returns without waiting; no device-to-host traffic. */
+spegg_status spegg_step_generations(spegg_pop *pop, uint32_t n_generations);
+
+/* Wait for the stream, then copy the census of replicates 0..n-1 (n <=
+ * n_reps) into host_out. */
+spegg_status spegg_stats(spegg_pop *pop, spegg_rep_stats *host_out, uint32_t n);
+
+/* Wait, then copy replicate rep's current genomes (N x 2W words, layout
+ * above) into host_words (room for n_words words); *n_out = N.
+ * SPEGG_E_INVALID if the room is short.  patch and species must be 0. */
+spegg_status spegg_read_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *host_words,
+                                size_t n_words, uint32_t *n_out);
+
+/* Replace replicate rep's population by n individuals given as n x 2W
+ * words (tail bits must be zero, n <= capacity) at generation `generation`;
+ * phenotypes are recomputed and the census and cumulative counters reset.
+ * Waits for the stream before returning (host_words may be reused). */
+spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species,
+                                 const uint32_t *host_words, uint32_t n, uint32_t generation);
+
+/* Wait, then copy replicate rep's phenotypes z (N int32) into host_z. */
+spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, int32_t *host_z, size_t n, uint32_t *n_out);
+
+/* Wait, then copy the ascending survivor list of replicate rep's last
+ * generation (indices into the previous adults) into host_idx. */
+spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t *host_idx, size_t n, uint32_t *n_out);
+
+/* Record each newborn's mother and father (indices into the previous
+ * adults) from the next generation on.  Off by default. */
+spegg_status spegg_set_trace(spegg_pop *pop, int enable);
+
+/* Wait, then copy the parents recorded for replicate rep's current
+ * newborns.  SPEGG_E_STATE if tracing was off for the last generation. */
+spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t *host_mom, uint32_t *host_dad, size_t n,
+                                uint32_t *n_out);
+
+/* Kernel kinds timed by spegg_set_timing. */
+enum {
+    SPEGG_KERNEL_SURVIVE = 0,   /* steps D and the fecundity draw of A */
+    SPEGG_KERNEL_SCAN = 1,      /* per-replicate prefix sums, neonate count */
+    SPEGG_KERNEL_COMPACT = 2,   /* step E, the survivor list and slot owners */
+    SPEGG_KERNEL_OFFSPRING = 3, /* steps A (parents), B and C */
+    SPEGG_KERNEL_FINALIZE = 4,  /* census */
+    SPEGG_KERNEL_KINDS = 5
+};
+
+#define SPEGG_TIME_ALL 0x1Fu
+
+/* Bracket the kernels of the kinds in kinds_mask (bit k: kind k; 0 stops)
+ * launched by later spegg_step_generations calls with HIP events on the
+ * population's stream. */
+spegg_status spegg_set_timing(spegg_pop *pop, uint32_t kinds_mask);
+
+/* Wait, then report per kernel kind the summed event time in milliseconds
+ * and the number of launches timed since the last call, and reset them.
+ * Arrays hold n_kinds (<= SPEGG_KERNEL_KINDS) entries. */
+spegg_status spegg_kernel_times(spegg_pop *pop, double *ms, uint64_t *launches, uint32_t n_kinds);
+
+/* Release the handle (not the caller's memory or stream).  NULL is a no-op. */
+void spegg_pop_destroy(spegg_pop *pop);
+
+/* Host-only: the library's inverse-CDF threshold table (x < T_k decides k;
+ * the last entry is 2^32, "always").  kind 0: Poisson(a); 1: Binomial(b, a);
+ * 2: geometric crossover gaps for r = a over b entries.  Returns the length,
+ * or -1 if cap is too small or the arguments are invalid. */
+int spegg_threshold_table(int kind, double a, uint32_t b, uint64_t *out, int cap);
+
+/* Host-only: crossover-sampling mode for r (0 raw bits, r = 1/2; 1 none,
+ * r = 0; 2 geometric skips, 0 < r < 0.17; 3 bit-serial comparison). */
+int spegg_recomb_mode(double r);
+
+/* Device Philox4x32-10 for testing: for i < n, out[4i..4i+3] =
+ * Philox(counter ctr[4i..4i+3], key = seed), both arrays in device memory,
+ * enqueued on hip_stream; waits for completion. */
+spegg_status spegg_philox_fill(uint64_t seed, const uint32_t *ctr_dev, uint32_t *out_dev, uint32_t n,
+                               void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPEGG_H */

@@ -47,6 +47,7 @@ class OracleStats(C.Structure):
         ("near_ties", C.c_uint64),
         ("truncated", C.c_uint64),
         ("sum_threshold", C.c_uint64),
+        ("updates", C.c_uint64),
     ]
 
     def as_dict(self):

@@ -225,6 +225,7 @@ typedef struct {
     uint32_t generation, n, n_parents, n_survivors, extinct, reserved;
     int64_t sum_z, sum_z2;
     uint64_t near_ties, truncated, sum_threshold;
+    uint64_t updates; /* cumulative genotype-locus updates, sum of N_t L */
 } oracle_stats;
 
 typedef struct {
@@ -356,8 +357,8 @@ oracle_pop *oracle_create(const oracle_params *prm)
     P->mode = oracle_recomb_mode(prm->r);
     P->geo = (uint64_t *)malloc(sizeof(uint64_t) * (L > 1 ? L - 1 : 1));
     oracle_geometric_thresholds(prm->r, L - 1, P->geo);
-    P->binom = (uint64_t *)malloc(sizeof(uint64_t) * TABLE_CAP);
-    P->binom_len = oracle_binomial_thresholds(L, prm->mu, P->binom, TABLE_CAP);
+    P->binom = (uint64_t *)malloc(sizeof(uint64_t) * (L + 1u));
+    P->binom_len = oracle_binomial_thresholds(L, prm->mu, P->binom, (int)L + 1);
     P->pois = (uint64_t *)malloc(sizeof(uint64_t) * TABLE_CAP);
     P->pois_len = oracle_poisson_thresholds(prm->fecundity, P->pois, TABLE_CAP);
 
@@ -382,6 +383,7 @@ oracle_pop *oracle_create(const oracle_params *prm)
     }
     census(P);
     P->stats.n_parents = 0;
+    P->stats.extinct = prm->n0 == 0;
     return P;
 }
 
@@ -473,7 +475,9 @@ static void make_gamete(oracle_pop *P, const uint8_t *h0, const uint8_t *h1, uin
     if (K == 0)
         return;
     memset(chosen, 0, L);
-    while (accepted < K) {
+    /* at most 2^23 candidate pairs per gamete, a bound no run with mu < 1
+     * comes near; it keeps every loop finite */
+    while (accepted < K && cand < (1u << 23)) {
         uint32_t lo = seq_word(&P->rng, j, mstream, gen, 1u + 2u * cand);
         uint32_t hi = seq_word(&P->rng, j, mstream, gen, 2u + 2u * cand);
         uint32_t pos = uniform_index(lo, hi, L);
@@ -581,6 +585,7 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
         P->stats.sum_threshold = sumT;
         if (nn == 0)
             P->stats.extinct = 1;
+        P->stats.updates += (uint64_t)nn * L;
         census(P);
         free(alive);
         free(kids);

@@ -1,0 +1,696 @@
+// C ABI of libspegg (include/spegg.h): validation, workspace carving,
+// table upload, and the per-generation launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "spegg.h"
+#include "spegg_internal.h"
+#include "tables.h"
+
+using namespace spegg;
+
+namespace {
+
+thread_local std::string g_error;
+
+spegg_status fail(spegg_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kPoissonCap = 1024;
+constexpr uint32_t kMaxOffspringGrid = 4096;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    }
+};
+
+// Everything the host derives from one descriptor.
+struct RepPlan {
+    uint32_t W = 0, mode = 0, R = 0, tpo = 0, opt = 0;
+    int32_t zmin = 0, sum_e = 0;
+    uint32_t zlen = 0;
+    bool unit = true;
+    std::vector<uint64_t> pois, binom, geo;
+    std::vector<double> vtab;
+    std::vector<uint32_t> planes;
+    uint32_t surv_tile0 = 0, surv_ntiles = 0, off_tile0 = 0, off_ntiles = 0;
+    size_t genome[2] = {0, 0}, z[2] = {0, 0}, fate = 0, S = 0, owner = 0, mom = 0, dad = 0;
+    size_t vtab_at = 0, pois_at = 0, binom_at = 0, geo_at = 0, planes_at = 0;
+};
+
+struct OffClass {
+    int tpo;
+    uint32_t tile0, ntiles, grid;
+    size_t lds;
+};
+
+struct Plan {
+    std::vector<RepPlan> reps;
+    std::vector<OffClass> classes;
+    std::vector<SurvTile> surv_tiles;
+    std::vector<OffTile> off_tiles;
+    size_t descs = 0, states = 0, surv_tiles_at = 0, off_tiles_at = 0;
+    size_t static_end = 0;  // [0, static_end) is uploaded at create
+    size_t surv_counts = 0, partials = 0, total = 0;
+};
+
+spegg_status validate(const spegg_rep_desc &d, uint32_t i) {
+    if (d.n_loci < 1 || d.n_loci > SPEGG_MAX_LOCI)
+        return fail(SPEGG_E_INVALID, "replicate %u: n_loci %u outside 1..%u", i, d.n_loci, SPEGG_MAX_LOCI);
+    if (d.capacity < 1 || d.capacity > (1u << 30))
+        return fail(SPEGG_E_INVALID, "replicate %u: capacity %u outside 1..2^30", i, d.capacity);
+    if (d.n0 > d.capacity) return fail(SPEGG_E_INVALID, "replicate %u: n0 %u exceeds capacity %u", i, d.n0, d.capacity);
+    if (d.replicate_id > SPEGG_MAX_REPLICATE_ID)
+        return fail(SPEGG_E_INVALID, "replicate %u: replicate_id %u exceeds %u", i, d.replicate_id,
+                    SPEGG_MAX_REPLICATE_ID);
+    if (d.regime != SPEGG_WF && d.regime != SPEGG_POISSON_BH)
+        return fail(SPEGG_E_INVALID, "replicate %u: unknown regime %u", i, d.regime);
+    if (d.reserved != 0) return fail(SPEGG_E_INVALID, "replicate %u: reserved field must be 0", i);
+    if (!(d.mu >= 0.0 && d.mu < 1.0)) return fail(SPEGG_E_INVALID, "replicate %u: mu %g outside [0, 1)", i, d.mu);
+    if (!(d.r >= 0.0 && d.r <= 0.5)) return fail(SPEGG_E_INVALID, "replicate %u: r %g outside [0, 1/2]", i, d.r);
+    if (!std::isfinite(d.theta) || std::isnan(d.omega))
+        return fail(SPEGG_E_INVALID, "replicate %u: theta and omega must be numbers", i);
+    if (d.regime == SPEGG_POISSON_BH) {
+        if (!(d.fecundity >= 0.0) || !std::isfinite(d.fecundity))
+            return fail(SPEGG_E_INVALID, "replicate %u: fecundity %g must be >= 0", i, d.fecundity);
+        if (std::isnan(d.K) || std::isinf(d.K)) return fail(SPEGG_E_INVALID, "replicate %u: K must be finite", i);
+    }
+    if (d.effects)
+        for (uint32_t l = 0; l < d.n_loci; ++l)
+            if (d.effects[l] < -4 || d.effects[l] > 4)
+                return fail(SPEGG_E_INVALID, "replicate %u: effect %d at locus %u outside [-4, 4]", i, d.effects[l], l);
+    return SPEGG_OK;
+}
+
+spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p) {
+    spegg_status st = validate(d, i);
+    if (st != SPEGG_OK) return st;
+    const uint32_t L = d.n_loci;
+    p.W = (L + 31u) / 32u;
+    p.mode = recomb_mode(d.r);
+    p.R = (uint32_t)std::floor(d.r * 4294967296.0);
+    int32_t abs_sum = 0;
+    p.sum_e = 0;
+    p.unit = true;
+    for (uint32_t l = 0; l < L; ++l) {
+        const int e = d.effects ? d.effects[l] : 1;
+        abs_sum += e < 0 ? -e : e;
+        p.sum_e += e;
+        if (e != 1) p.unit = false;
+    }
+    p.zmin = -abs_sum;
+    p.zlen = 2u * (uint32_t)abs_sum + 1u;
+    if (d.omega > 0.0) viability_table(d.theta, d.omega, p.zmin, p.zlen, p.vtab);
+    if (!p.unit) {
+        p.planes.assign(6u * p.W, 0u);
+        for (uint32_t l = 0; l < L; ++l) {
+            const int e = d.effects[l];
+            const uint32_t mag = (uint32_t)(e < 0 ? -e : e), bit = 1u << (l % 32u), w = l / 32u;
+            for (uint32_t k = 0; k < 3; ++k)
+                if (mag & (1u << k)) p.planes[((e < 0 ? 3u : 0u) + k) * p.W + w] |= bit;
+        }
+    }
+    if (!binomial_table(L, d.mu, (int)L + 1, p.binom))
+        return fail(SPEGG_E_UNSUPPORTED, "replicate %u: mutation-count table does not close", i);
+    if (d.regime == SPEGG_POISSON_BH && !poisson_table(d.fecundity, kPoissonCap, p.pois))
+        return fail(SPEGG_E_UNSUPPORTED, "replicate %u: fecundity %g needs more than %d table entries", i,
+                    d.fecundity, kPoissonCap);
+    if (p.mode == kModeSkip && L > 1) geometric_table(d.r, L - 1u, p.geo);
+    p.tpo = (uint32_t)lanes_per_offspring(p.W);
+    p.opt = (uint32_t)offspring_per_tile((int)p.tpo);
+    p.surv_ntiles = (d.capacity + kSurvTile - 1) / kSurvTile;
+    p.off_ntiles = (d.capacity + p.opt - 1) / p.opt;
+    return SPEGG_OK;
+}
+
+spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
+    if (!reps || n == 0) return fail(SPEGG_E_INVALID, "no replicates");
+    P.reps.resize(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const spegg_status st = build_rep(reps[i], i, P.reps[i]);
+        if (st != SPEGG_OK) return st;
+    }
+    // survival tiles, replicate by replicate
+    for (uint32_t i = 0; i < n; ++i) {
+        RepPlan &p = P.reps[i];
+        p.surv_tile0 = (uint32_t)P.surv_tiles.size();
+        for (uint32_t k = 0; k < p.surv_ntiles; ++k) P.surv_tiles.push_back({i, k * (uint32_t)kSurvTile});
+    }
+    // offspring tiles grouped by kernel shape (lanes per offspring)
+    for (int tpo = 4; tpo <= 64; tpo <<= 1) {
+        OffClass c{tpo, (uint32_t)P.off_tiles.size(), 0, 0, 0};
+        uint32_t maxW = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            RepPlan &p = P.reps[i];
+            if ((int)p.tpo != tpo) continue;
+            p.off_tile0 = (uint32_t)P.off_tiles.size();
+            for (uint32_t k = 0; k < p.off_ntiles; ++k) P.off_tiles.push_back({i, k * p.opt});
+            if (p.W > maxW) maxW = p.W;
+        }
+        c.ntiles = (uint32_t)P.off_tiles.size() - c.tile0;
+        if (c.ntiles == 0) continue;
+        c.grid = c.ntiles < kMaxOffspringGrid ? c.ntiles : kMaxOffspringGrid;
+        c.lds = offspring_lds_bytes(tpo, maxW);
+        P.classes.push_back(c);
+    }
+    Carver cv;
+    P.descs = cv.take(sizeof(RepDesc) * n);
+    P.states = cv.take(sizeof(RepState) * n);
+    P.surv_tiles_at = cv.take(sizeof(SurvTile) * P.surv_tiles.size());
+    P.off_tiles_at = cv.take(sizeof(OffTile) * P.off_tiles.size());
+    for (uint32_t i = 0; i < n; ++i) {
+        RepPlan &p = P.reps[i];
+        if (!p.vtab.empty()) p.vtab_at = cv.take(sizeof(double) * p.vtab.size());
+        if (!p.pois.empty()) p.pois_at = cv.take(sizeof(uint64_t) * p.pois.size());
+        p.binom_at = cv.take(sizeof(uint64_t) * p.binom.size());
+        if (!p.geo.empty()) p.geo_at = cv.take(sizeof(uint64_t) * p.geo.size());
+        if (!p.planes.empty()) p.planes_at = cv.take(sizeof(uint32_t) * p.planes.size());
+    }
+    P.static_end = cv.off;
+    P.surv_counts = cv.take(sizeof(SurvCount) * P.surv_tiles.size());
+    P.partials = cv.take(sizeof(Partial) * P.off_tiles.size());
+    for (uint32_t i = 0; i < n; ++i) {
+        RepPlan &p = P.reps[i];
+        const size_t cap = reps[i].capacity;
+        const size_t gbytes = cap * 2u * p.W * sizeof(uint32_t);
+        p.genome[0] = cv.take(gbytes);
+        p.genome[1] = cv.take(gbytes);
+        p.z[0] = cv.take(cap * sizeof(int32_t));
+        p.z[1] = cv.take(cap * sizeof(int32_t));
+        p.fate = cv.take(cap * sizeof(uint16_t));
+        p.S = cv.take(cap * sizeof(uint32_t));
+        if (reps[i].regime == SPEGG_POISSON_BH) p.owner = cv.take(cap * sizeof(uint32_t));
+        p.mom = cv.take(cap * sizeof(uint32_t));
+        p.dad = cv.take(cap * sizeof(uint32_t));
+    }
+    P.total = cv.off;
+    return SPEGG_OK;
+}
+
+template <typename T>
+T *at(uint8_t *base, size_t off) {
+    return reinterpret_cast<T *>(base + off);
+}
+
+struct Timed {
+    int kind;
+    hipEvent_t a, b;
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            changed = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct spegg_pop {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    uint8_t *base = nullptr;
+    uint32_t n_reps = 0;
+    Plan plan;
+    std::vector<spegg_rep_desc> descs;
+    std::vector<RepDesc> dev_descs;  // host images of the device descriptors
+    std::vector<uint8_t> image;      // host image of [0, static_end)
+    bool errored = false;
+    bool trace = false;
+    uint32_t timing = 0;  // mask of kernel kinds bracketed by events
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> event_pool;
+    double ms[SPEGG_KERNEL_KINDS] = {0};
+    uint64_t launches[SPEGG_KERNEL_KINDS] = {0};
+
+    RepDesc *d_descs() { return at<RepDesc>(base, plan.descs); }
+    RepState *d_states() { return at<RepState>(base, plan.states); }
+    SurvTile *d_surv_tiles() { return at<SurvTile>(base, plan.surv_tiles_at); }
+    OffTile *d_off_tiles() { return at<OffTile>(base, plan.off_tiles_at); }
+    SurvCount *d_surv_counts() { return at<SurvCount>(base, plan.surv_counts); }
+    Partial *d_partials() { return at<Partial>(base, plan.partials); }
+};
+
+namespace {
+
+spegg_status device_fail(spegg_pop *pop, hipError_t e, const char *what) {
+    if (pop) pop->errored = true;
+    return fail(SPEGG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+spegg_status check_pop(spegg_pop *pop) {
+    if (!pop) return fail(SPEGG_E_INVALID, "null population handle");
+    if (pop->errored) return fail(SPEGG_E_STATE, "population handle is errored by an earlier device failure");
+    return SPEGG_OK;
+}
+
+hipEvent_t take_event(spegg_pop *pop) {
+    if (!pop->event_pool.empty()) {
+        hipEvent_t e = pop->event_pool.back();
+        pop->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch through f, bracketed by events when timing is on.
+template <typename F>
+hipError_t timed(spegg_pop *pop, int kind, F &&f) {
+    if (!(pop->timing & (1u << kind))) return f();
+    hipEvent_t a = take_event(pop), b = take_event(pop);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, pop->stream);
+    if (e != hipSuccess) return e;
+    e = f();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, pop->stream);
+    if (e != hipSuccess) return e;
+    pop->pending.push_back({kind, a, b});
+    return hipSuccess;
+}
+
+RepState initial_state(uint32_t t, uint32_t n) {
+    RepState s;
+    std::memset(&s, 0, sizeof s);
+    s.t = t;
+    s.n = n;
+    s.extinct = n == 0;
+    s.stats.generation = t;
+    s.stats.n = n;
+    s.stats.extinct = s.extinct;
+    return s;
+}
+
+spegg_status sync_stream(spegg_pop *pop) {
+    const hipError_t e = hipStreamSynchronize(pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipStreamSynchronize");
+    return SPEGG_OK;
+}
+
+spegg_status read_state(spegg_pop *pop, uint32_t rep, RepState &s) {
+    hipError_t e = hipMemcpyAsync(&s, pop->d_states() + rep, sizeof s, hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(state)");
+    return sync_stream(pop);
+}
+
+spegg_status check_rep(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species) {
+    if (rep >= pop->n_reps) return fail(SPEGG_E_INVALID, "replicate %u out of range (%u)", rep, pop->n_reps);
+    if (patch != 0 || species != 0)
+        return fail(SPEGG_E_UNSUPPORTED, "one patch and one species per replicate in this build");
+    return SPEGG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spegg_abi_version(void) { return SPEGG_ABI_VERSION; }
+
+const char *spegg_last_error(void) { return g_error.c_str(); }
+
+size_t spegg_footprint(const spegg_rep_desc *reps, uint32_t n_reps) {
+    Plan P;
+    if (make_plan(reps, n_reps, P) != SPEGG_OK) return 0;
+    g_error.clear();
+    return P.total;
+}
+
+spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void *device_mem, size_t device_bytes,
+                              void *hip_stream, spegg_pop **out) {
+    if (!out) return fail(SPEGG_E_INVALID, "null output handle pointer");
+    *out = nullptr;
+    spegg_pop *pop = new spegg_pop();
+    spegg_status st = make_plan(reps, n_reps, pop->plan);
+    if (st != SPEGG_OK) {
+        delete pop;
+        return st;
+    }
+    if (!device_mem || ((uintptr_t)device_mem & (kAlign - 1)) != 0) {
+        delete pop;
+        return fail(SPEGG_E_NOMEM, "workspace must be a non-null, %zu-byte aligned device pointer", kAlign);
+    }
+    if (device_bytes < pop->plan.total) {
+        const size_t need = pop->plan.total;
+        delete pop;
+        return fail(SPEGG_E_NOMEM, "workspace holds %zu bytes, the population needs %zu", device_bytes, need);
+    }
+    pop->stream = (hipStream_t)hip_stream;
+    pop->base = (uint8_t *)device_mem;
+    pop->n_reps = n_reps;
+    pop->descs.assign(reps, reps + n_reps);
+    hipError_t e = hipGetDevice(&pop->device);
+    if (e != hipSuccess) {
+        delete pop;
+        return fail(SPEGG_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+
+    Plan &P = pop->plan;
+    pop->image.assign(P.static_end, 0);
+    uint8_t *img = pop->image.data();
+    pop->dev_descs.resize(n_reps);
+    for (uint32_t i = 0; i < n_reps; ++i) {
+        const spegg_rep_desc &d = reps[i];
+        RepPlan &p = P.reps[i];
+        RepDesc h;
+        std::memset(&h, 0, sizeof h);
+        h.L = d.n_loci;
+        h.W = p.W;
+        h.cap = d.capacity;
+        h.regime = d.regime;
+        h.key0 = (uint32_t)d.seed;
+        h.key1 = (uint32_t)(d.seed >> 32);
+        h.c3 = d.replicate_id << 12;  // species 0, patch 0
+        h.mode = p.mode;
+        h.R = p.R;
+        h.geo_len = (uint32_t)p.geo.size();
+        h.binom_len = (uint32_t)p.binom.size();
+        h.pois_len = (uint32_t)p.pois.size();
+        h.zmin = p.zmin;
+        h.zlen = p.zlen;
+        h.sum_e = p.sum_e;
+        h.unit_effects = p.unit ? 1u : 0u;
+        h.tail_mask = (d.n_loci % 32u) ? ((1u << (d.n_loci % 32u)) - 1u) : ~0u;
+        h.surv_tile0 = p.surv_tile0;
+        h.surv_ntiles = p.surv_ntiles;
+        h.off_tile0 = p.off_tile0;
+        h.off_ntiles = p.off_ntiles;
+        h.off_per_tile = p.opt;
+        h.K = d.K;
+        h.lambda = d.fecundity;
+        h.genome[0] = at<uint32_t>(pop->base, p.genome[0]);
+        h.genome[1] = at<uint32_t>(pop->base, p.genome[1]);
+        h.z[0] = at<int32_t>(pop->base, p.z[0]);
+        h.z[1] = at<int32_t>(pop->base, p.z[1]);
+        h.fate = at<uint16_t>(pop->base, p.fate);
+        h.S = at<uint32_t>(pop->base, p.S);
+        h.owner = p.owner ? at<uint32_t>(pop->base, p.owner) : nullptr;
+        h.mom = at<uint32_t>(pop->base, p.mom);
+        h.dad = at<uint32_t>(pop->base, p.dad);
+        h.vtab = p.vtab.empty() ? nullptr : at<double>(pop->base, p.vtab_at);
+        h.pois = p.pois.empty() ? nullptr : at<uint64_t>(pop->base, p.pois_at);
+        h.binom = at<uint64_t>(pop->base, p.binom_at);
+        h.geo = p.geo.empty() ? nullptr : at<uint64_t>(pop->base, p.geo_at);
+        h.planes = p.planes.empty() ? nullptr : at<uint32_t>(pop->base, p.planes_at);
+        pop->dev_descs[i] = h;
+        std::memcpy(img + P.descs + i * sizeof(RepDesc), &h, sizeof h);
+        const RepState s0 = initial_state(0, d.n0);
+        std::memcpy(img + P.states + i * sizeof(RepState), &s0, sizeof s0);
+        if (!p.vtab.empty()) std::memcpy(img + p.vtab_at, p.vtab.data(), sizeof(double) * p.vtab.size());
+        if (!p.pois.empty()) std::memcpy(img + p.pois_at, p.pois.data(), sizeof(uint64_t) * p.pois.size());
+        std::memcpy(img + p.binom_at, p.binom.data(), sizeof(uint64_t) * p.binom.size());
+        if (!p.geo.empty()) std::memcpy(img + p.geo_at, p.geo.data(), sizeof(uint64_t) * p.geo.size());
+        if (!p.planes.empty()) std::memcpy(img + p.planes_at, p.planes.data(), sizeof(uint32_t) * p.planes.size());
+    }
+    if (!P.surv_tiles.empty())
+        std::memcpy(img + P.surv_tiles_at, P.surv_tiles.data(), sizeof(SurvTile) * P.surv_tiles.size());
+    if (!P.off_tiles.empty())
+        std::memcpy(img + P.off_tiles_at, P.off_tiles.data(), sizeof(OffTile) * P.off_tiles.size());
+
+    e = hipMemcpyAsync(pop->base, img, P.static_end, hipMemcpyHostToDevice, pop->stream);
+    if (e != hipSuccess) {
+        delete pop;
+        return fail(SPEGG_E_DEVICE, "hipMemcpyAsync(tables): %s", hipGetErrorString(e));
+    }
+    for (uint32_t i = 0; i < n_reps; ++i) {
+        e = launch_init(pop->d_descs() + i, pop->dev_descs[i], reps[i].n0, pop->stream);
+        if (e == hipSuccess)
+            e = launch_phenotypes(pop->d_descs() + i, pop->d_states() + i, pop->dev_descs[i], reps[i].n0, 0,
+                                  pop->stream);
+        if (e != hipSuccess) {
+            delete pop;
+            return fail(SPEGG_E_DEVICE, "initial population: %s", hipGetErrorString(e));
+        }
+    }
+    // The effects pointer is the caller's; keep only the copy in the tables.
+    for (auto &d : pop->descs) d.effects = nullptr;
+    *out = pop;
+    g_error.clear();
+    return SPEGG_OK;
+}
+
+spegg_status spegg_step_generations(spegg_pop *pop, uint32_t n_generations) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    DeviceGuard guard(pop->device);
+    Plan &P = pop->plan;
+    const uint32_t ns_tiles = (uint32_t)P.surv_tiles.size();
+    const int trace = pop->trace ? 1 : 0;
+    for (uint32_t g = 0; g < n_generations; ++g) {
+        hipError_t e = timed(pop, SPEGG_KERNEL_SURVIVE, [&] {
+            return launch_survive(pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), pop->d_surv_counts(),
+                                  ns_tiles, pop->stream);
+        });
+        if (e == hipSuccess)
+            e = timed(pop, SPEGG_KERNEL_SCAN, [&] {
+                return launch_scan(pop->d_descs(), pop->d_states(), pop->d_surv_counts(), pop->n_reps, pop->stream);
+            });
+        if (e == hipSuccess)
+            e = timed(pop, SPEGG_KERNEL_COMPACT, [&] {
+                return launch_compact(pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), pop->d_surv_counts(),
+                                      ns_tiles, pop->stream);
+            });
+        for (const OffClass &c : P.classes) {
+            if (e != hipSuccess) break;
+            e = timed(pop, SPEGG_KERNEL_OFFSPRING, [&] {
+                return launch_offspring(c.tpo, pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0,
+                                        c.ntiles, pop->d_partials(), c.grid, c.lds, trace, pop->stream);
+            });
+        }
+        if (e == hipSuccess)
+            e = timed(pop, SPEGG_KERNEL_FINALIZE, [&] {
+                return launch_finalize(pop->d_descs(), pop->d_states(), pop->d_partials(), pop->n_reps, trace,
+                                       pop->stream);
+            });
+        if (e != hipSuccess) return device_fail(pop, e, "generation launch");
+    }
+    return SPEGG_OK;
+}
+
+spegg_status spegg_stats(spegg_pop *pop, spegg_rep_stats *host_out, uint32_t n) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if (!host_out || n > pop->n_reps) return fail(SPEGG_E_INVALID, "stats: need 0 < n <= %u and a buffer", pop->n_reps);
+    DeviceGuard guard(pop->device);
+    std::vector<RepState> s(n);
+    hipError_t e = hipMemcpyAsync(s.data(), pop->d_states(), sizeof(RepState) * n, hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(stats)");
+    st = sync_stream(pop);
+    if (st != SPEGG_OK) return st;
+    for (uint32_t i = 0; i < n; ++i) host_out[i] = s[i].stats;
+    return SPEGG_OK;
+}
+
+spegg_status spegg_read_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *host_words,
+                                size_t n_words, uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if ((st = check_rep(pop, rep, patch, species)) != SPEGG_OK) return st;
+    DeviceGuard guard(pop->device);
+    RepState s;
+    if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
+    const RepDesc &h = pop->dev_descs[rep];
+    const size_t words = (size_t)s.n * 2u * h.W;
+    if (n_out) *n_out = s.n;
+    if (words == 0) return SPEGG_OK;
+    if (!host_words || n_words < words)
+        return fail(SPEGG_E_INVALID, "read_genomes: need room for %zu words, have %zu", words, n_words);
+    hipError_t e = hipMemcpyAsync(host_words, h.genome[s.t & 1u], words * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                  pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(genomes)");
+    return sync_stream(pop);
+}
+
+spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species,
+                                 const uint32_t *host_words, uint32_t n, uint32_t generation) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if ((st = check_rep(pop, rep, patch, species)) != SPEGG_OK) return st;
+    const RepDesc &h = pop->dev_descs[rep];
+    if (n > h.cap) return fail(SPEGG_E_INVALID, "write_genomes: %u individuals exceed capacity %u", n, h.cap);
+    if (n > 0 && !host_words) return fail(SPEGG_E_INVALID, "write_genomes: null words");
+    for (uint32_t i = 0; i < n; ++i)
+        for (uint32_t hh = 0; hh < 2; ++hh)
+            if (host_words[((size_t)i * 2u + hh) * h.W + h.W - 1u] & ~h.tail_mask)
+                return fail(SPEGG_E_INVALID, "write_genomes: individual %u has bits set beyond locus L-1", i);
+    DeviceGuard guard(pop->device);
+    if ((st = sync_stream(pop)) != SPEGG_OK) return st;
+    const uint32_t buf = generation & 1u;
+    const RepState s0 = initial_state(generation, n);
+    hipError_t e = hipSuccess;
+    if (n > 0)
+        e = hipMemcpyAsync(h.genome[buf], host_words, (size_t)n * 2u * h.W * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           pop->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pop->d_states() + rep, &s0, sizeof s0, hipMemcpyHostToDevice, pop->stream);
+    if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + rep, pop->d_states() + rep, h, n, buf, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "write_genomes");
+    return sync_stream(pop);
+}
+
+spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, int32_t *host_z, size_t n, uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if ((st = check_rep(pop, rep, 0, 0)) != SPEGG_OK) return st;
+    DeviceGuard guard(pop->device);
+    RepState s;
+    if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
+    if (n_out) *n_out = s.n;
+    if (s.n == 0) return SPEGG_OK;
+    if (!host_z || n < s.n) return fail(SPEGG_E_INVALID, "read_phenotypes: need room for %u values", s.n);
+    hipError_t e = hipMemcpyAsync(host_z, pop->dev_descs[rep].z[s.t & 1u], (size_t)s.n * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(phenotypes)");
+    return sync_stream(pop);
+}
+
+spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t *host_idx, size_t n, uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if ((st = check_rep(pop, rep, 0, 0)) != SPEGG_OK) return st;
+    DeviceGuard guard(pop->device);
+    RepState s;
+    if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
+    const uint32_t m = s.stats.n_survivors;
+    if (n_out) *n_out = m;
+    if (m == 0) return SPEGG_OK;
+    if (!host_idx || n < m) return fail(SPEGG_E_INVALID, "read_survivors: need room for %u indices", m);
+    hipError_t e = hipMemcpyAsync(host_idx, pop->dev_descs[rep].S, (size_t)m * sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(survivors)");
+    return sync_stream(pop);
+}
+
+spegg_status spegg_set_trace(spegg_pop *pop, int enable) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    pop->trace = enable != 0;
+    return SPEGG_OK;
+}
+
+spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t *host_mom, uint32_t *host_dad, size_t n,
+                                uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if ((st = check_rep(pop, rep, 0, 0)) != SPEGG_OK) return st;
+    DeviceGuard guard(pop->device);
+    RepState s;
+    if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
+    if (!s.traced) return fail(SPEGG_E_STATE, "read_parents: tracing was off for the last generation");
+    if (n_out) *n_out = s.n;
+    if (s.n == 0) return SPEGG_OK;
+    if (!host_mom || !host_dad || n < s.n) return fail(SPEGG_E_INVALID, "read_parents: need room for %u entries", s.n);
+    const RepDesc &h = pop->dev_descs[rep];
+    hipError_t e = hipMemcpyAsync(host_mom, h.mom, (size_t)s.n * sizeof(uint32_t), hipMemcpyDeviceToHost, pop->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_dad, h.dad, (size_t)s.n * sizeof(uint32_t), hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(parents)");
+    return sync_stream(pop);
+}
+
+spegg_status spegg_set_timing(spegg_pop *pop, uint32_t kinds_mask) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if (kinds_mask & ~SPEGG_TIME_ALL) return fail(SPEGG_E_INVALID, "set_timing: unknown kernel kinds in mask");
+    pop->timing = kinds_mask;
+    return SPEGG_OK;
+}
+
+spegg_status spegg_kernel_times(spegg_pop *pop, double *ms, uint64_t *launches, uint32_t n_kinds) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if (n_kinds > SPEGG_KERNEL_KINDS || (n_kinds && (!ms || !launches)))
+        return fail(SPEGG_E_INVALID, "kernel_times: n_kinds <= %d and two arrays", SPEGG_KERNEL_KINDS);
+    DeviceGuard guard(pop->device);
+    if ((st = sync_stream(pop)) != SPEGG_OK) return st;
+    for (const Timed &t : pop->pending) {
+        float x = 0.f;
+        const hipError_t e = hipEventElapsedTime(&x, t.a, t.b);
+        if (e != hipSuccess) return device_fail(pop, e, "hipEventElapsedTime");
+        pop->ms[t.kind] += x;
+        pop->launches[t.kind] += 1;
+        pop->event_pool.push_back(t.a);
+        pop->event_pool.push_back(t.b);
+    }
+    pop->pending.clear();
+    for (uint32_t k = 0; k < n_kinds; ++k) {
+        ms[k] = pop->ms[k];
+        launches[k] = pop->launches[k];
+    }
+    for (int k = 0; k < SPEGG_KERNEL_KINDS; ++k) {
+        pop->ms[k] = 0;
+        pop->launches[k] = 0;
+    }
+    return SPEGG_OK;
+}
+
+void spegg_pop_destroy(spegg_pop *pop) {
+    if (!pop) return;
+    {
+        DeviceGuard guard(pop->device);
+        (void)hipStreamSynchronize(pop->stream);
+        for (const Timed &t : pop->pending) {
+            (void)hipEventDestroy(t.a);
+            (void)hipEventDestroy(t.b);
+        }
+        for (hipEvent_t e : pop->event_pool) (void)hipEventDestroy(e);
+    }
+    delete pop;
+}
+
+int spegg_threshold_table(int kind, double a, uint32_t b, uint64_t *out, int cap) {
+    std::vector<uint64_t> T;
+    bool ok = false;
+    if (kind == 0) ok = poisson_table(a, cap, T);
+    else if (kind == 1) ok = binomial_table(b, a, cap, T);
+    else if (kind == 2) {
+        if (a >= 0.0 && a <= 0.5 && (int64_t)b <= cap) {
+            geometric_table(a, b, T);
+            ok = true;
+        }
+    }
+    if (!ok || !out || (int)T.size() > cap) return -1;
+    std::memcpy(out, T.data(), sizeof(uint64_t) * T.size());
+    return (int)T.size();
+}
+
+int spegg_recomb_mode(double r) { return (int)recomb_mode(r); }
+
+spegg_status spegg_philox_fill(uint64_t seed, const uint32_t *ctr_dev, uint32_t *out_dev, uint32_t n,
+                               void *hip_stream) {
+    if (n && (!ctr_dev || !out_dev)) return fail(SPEGG_E_INVALID, "philox_fill: null arrays");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = launch_philox_fill((uint32_t)seed, (uint32_t)(seed >> 32), ctr_dev, out_dev, n, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(SPEGG_E_DEVICE, "philox_fill: %s", hipGetErrorString(e));
+    return SPEGG_OK;
+}
+
+}  // extern "C"

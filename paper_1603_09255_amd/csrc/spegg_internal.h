@@ -1,0 +1,129 @@
+// Internal types shared by the host side and the kernels of libspegg.
+//
+// Device memory of a population is one caller-owned block, carved into:
+//   [RepDesc x n_reps][RepState x n_reps][SurvTile...][OffTile...][tables]   uploaded once at create
+//   [SurvCount...][Partial...][per-replicate buffers]                         written by kernels
+// Per replicate: two genome buffers (ping-pong by generation parity), two
+// phenotype buffers, the fate byte-pairs, the survivor list, the slot-owner
+// list (Poisson regime) and the parent trace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "spegg.h"
+
+namespace spegg {
+
+constexpr uint64_t kAlways = 1ull << 32;  // threshold every 32-bit word is below
+
+// Philox counter field c1 = stream << 24 | block.  One stream per kind of
+// random decision.
+enum Stream : uint32_t {
+    kStInit = 1,
+    kStSurvive = 3,
+    kStFecund = 4,
+    kStParent = 5,
+    kStRecomb = 6,  // + 0 maternal gamete, + 1 paternal
+    kStMutate = 8   // + 0 maternal gamete, + 1 paternal
+};
+
+// Crossover sampling, a function of r alone.
+enum Mode : uint32_t { kModeRaw = 0, kModeZero = 1, kModeSkip = 2, kModeLazy = 3 };
+
+constexpr double kSkipBelow = 0.17;  // r < 0.17: geometric gaps; above: bit-serial Bernoulli
+
+constexpr int kBlock = 256;          // threads per block in every kernel
+constexpr int kSurvTile = 256;       // adults per survival / compaction tile
+
+struct RepDesc {
+    uint32_t L, W, cap, regime;
+    uint32_t key0, key1, c3, mode;
+    uint32_t R;          // floor(r 2^32), bit-serial mode
+    uint32_t geo_len;    // L - 1 (skip mode)
+    uint32_t binom_len, pois_len;
+    int32_t zmin;        // vtab[z - zmin]
+    uint32_t zlen;
+    int32_t sum_e;       // sum of the effects
+    uint32_t unit_effects;
+    uint32_t tail_mask;  // valid bits of word W-1
+    uint32_t surv_tile0, surv_ntiles;
+    uint32_t off_tile0, off_ntiles, off_per_tile;
+    uint32_t pad0;
+    double K, lambda;    // Beverton-Holt density factor; 0 < K enables it
+    uint32_t *genome[2];
+    int32_t *z[2];
+    uint16_t *fate;      // bit 15 alive, bits 0..14 offspring count
+    uint32_t *S;         // survivors, ascending
+    uint32_t *owner;     // mother of each offspring slot (Poisson regime)
+    uint32_t *mom, *dad; // parent trace
+    const double *vtab;  // viability by phenotype, NULL: selection off
+    const uint64_t *pois, *binom, *geo;
+    const uint32_t *planes;  // 6 x W effect bit-planes: +1,+2,+4 then -1,-2,-4
+};
+
+struct RepState {
+    uint32_t t;       // generation of the current adults
+    uint32_t n;       // N_t
+    uint32_t n_surv;  // survivors of the generation in progress
+    uint32_t n_next;  // N_{t+1}
+    uint32_t extinct;
+    uint32_t traced;  // parents of the current newborns were recorded
+    uint64_t near_ties, truncated;
+    spegg_rep_stats stats;
+};
+
+struct SurvTile {
+    uint32_t rep, start;
+};
+
+struct SurvCount {
+    uint32_t alive, kids, near, pad;
+    uint64_t sum_t;
+    uint32_t alive_off, kid_off;
+};
+
+struct OffTile {
+    uint32_t rep, start;
+};
+
+struct Partial {
+    int64_t sum_z;
+    uint64_t sum_z2;
+};
+
+// Offspring-kernel shape for a genome of W words: lanes per offspring
+// (both gametes), a power of two between 4 and 64.
+inline int lanes_per_offspring(uint32_t W) {
+    int g = 2;
+    while (g < (int)W && g < 32) g <<= 1;
+    return 2 * g;
+}
+inline int offspring_per_tile(int tpo) {
+    int teams = kBlock / tpo;
+    int iters = teams >= 16 ? 1 : 16 / teams;
+    return teams * iters;
+}
+inline size_t offspring_lds_bytes(int tpo, uint32_t W) {
+    // per team and gamete: crossover bitmap and flip bitmap, W words each
+    return (size_t)(kBlock / tpo) * 2u * 2u * W * sizeof(uint32_t);
+}
+
+// Host-side launchers (kernels.hip).
+hipError_t launch_init(const RepDesc *d_desc, const RepDesc &h, uint32_t n0, hipStream_t s);
+hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, const RepDesc &h, uint32_t n, uint32_t buf,
+                             hipStream_t s);
+hipError_t launch_survive(const RepDesc *descs, RepState *states, const SurvTile *tiles, SurvCount *counts,
+                          uint32_t ntiles, hipStream_t s);
+hipError_t launch_scan(const RepDesc *descs, RepState *states, SurvCount *counts, uint32_t n_reps, hipStream_t s);
+hipError_t launch_compact(const RepDesc *descs, const RepState *states, const SurvTile *tiles,
+                          const SurvCount *counts, uint32_t ntiles, hipStream_t s);
+hipError_t launch_offspring(int tpo, const RepDesc *descs, RepState *states, const OffTile *tiles, uint32_t tile0,
+                            uint32_t ntiles, Partial *partials, uint32_t grid, size_t lds, int trace, hipStream_t s);
+hipError_t launch_finalize(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,
+                           int trace, hipStream_t s);
+hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out, uint32_t n,
+                              hipStream_t s);
+
+}  // namespace spegg

@@ -1,0 +1,19 @@
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "spegg_internal.h"
+
+namespace spegg {
+
+// Each returns false if the table would need more than cap entries to
+// reach probability one within 2^-32, or if an argument is out of range.
+bool poisson_table(double lambda, int cap, std::vector<uint64_t> &T);
+bool binomial_table(uint32_t L, double mu, int cap, std::vector<uint64_t> &T);
+void geometric_table(double r, uint32_t n, std::vector<uint64_t> &T);
+uint32_t recomb_mode(double r);
+void viability_table(double theta, double omega, int32_t zmin, uint32_t n, std::vector<double> &v);
+
+}  // namespace spegg

@@ -1,0 +1,296 @@
+"""Python binding of libspegg (include/spegg.h): argument marshalling only.
+
+PyTorch supplies the device memory (one ``uint8`` tensor of
+``spegg_footprint`` bytes) and the stream; every step of the generation runs
+in the library's HIP kernels.  Loading fails loudly when the library is not
+built: there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libspegg.so")
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+WF, POISSON_BH = 0, 1
+KERNEL_NAMES = ["survive", "scan", "compact", "offspring", "finalize"]
+
+
+class SpeggError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"spegg status {status}: {message}")
+        self.status = status
+
+
+class RepDesc(C.Structure):
+    _fields_ = [
+        ("seed", C.c_uint64),
+        ("replicate_id", C.c_uint32),
+        ("regime", C.c_uint32),
+        ("n0", C.c_uint32),
+        ("capacity", C.c_uint32),
+        ("n_loci", C.c_uint32),
+        ("reserved", C.c_uint32),
+        ("mu", C.c_double),
+        ("r", C.c_double),
+        ("theta", C.c_double),
+        ("omega", C.c_double),
+        ("K", C.c_double),
+        ("fecundity", C.c_double),
+        ("effects", C.POINTER(C.c_int8)),
+    ]
+
+
+class RepStats(C.Structure):
+    _fields_ = [
+        ("generation", C.c_uint32),
+        ("n", C.c_uint32),
+        ("n_parents", C.c_uint32),
+        ("n_survivors", C.c_uint32),
+        ("extinct", C.c_uint32),
+        ("reserved", C.c_uint32),
+        ("sum_z", C.c_int64),
+        ("sum_z2", C.c_int64),
+        ("near_ties", C.c_uint64),
+        ("truncated", C.c_uint64),
+        ("sum_threshold", C.c_uint64),
+        ("updates", C.c_uint64),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_lib = None
+
+
+def load():
+    """Load the built library; raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(or python paper_1603_09255_amd/build.py) first")
+    lib = C.CDLL(LIB_PATH)
+    vp, u32, st = C.c_void_p, C.c_uint32, C.c_int
+    P32 = C.POINTER(C.c_uint32)
+    lib.spegg_abi_version.restype = C.c_int
+    lib.spegg_abi_version.argtypes = []
+    lib.spegg_last_error.restype = C.c_char_p
+    lib.spegg_last_error.argtypes = []
+    lib.spegg_footprint.restype = C.c_size_t
+    lib.spegg_footprint.argtypes = [C.POINTER(RepDesc), u32]
+    lib.spegg_pop_create.restype = st
+    lib.spegg_pop_create.argtypes = [C.POINTER(RepDesc), u32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.spegg_step_generations.restype = st
+    lib.spegg_step_generations.argtypes = [vp, u32]
+    lib.spegg_stats.restype = st
+    lib.spegg_stats.argtypes = [vp, C.POINTER(RepStats), u32]
+    lib.spegg_read_genomes.restype = st
+    lib.spegg_read_genomes.argtypes = [vp, u32, u32, u32, P32, C.c_size_t, P32]
+    lib.spegg_write_genomes.restype = st
+    lib.spegg_write_genomes.argtypes = [vp, u32, u32, u32, P32, u32, u32]
+    lib.spegg_read_phenotypes.restype = st
+    lib.spegg_read_phenotypes.argtypes = [vp, u32, C.POINTER(C.c_int32), C.c_size_t, P32]
+    lib.spegg_read_survivors.restype = st
+    lib.spegg_read_survivors.argtypes = [vp, u32, P32, C.c_size_t, P32]
+    lib.spegg_set_trace.restype = st
+    lib.spegg_set_trace.argtypes = [vp, C.c_int]
+    lib.spegg_read_parents.restype = st
+    lib.spegg_read_parents.argtypes = [vp, u32, P32, P32, C.c_size_t, P32]
+    lib.spegg_set_timing.restype = st
+    lib.spegg_set_timing.argtypes = [vp, u32]
+    lib.spegg_kernel_times.restype = st
+    lib.spegg_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64), u32]
+    lib.spegg_pop_destroy.restype = None
+    lib.spegg_pop_destroy.argtypes = [vp]
+    lib.spegg_threshold_table.restype = C.c_int
+    lib.spegg_threshold_table.argtypes = [C.c_int, C.c_double, u32, C.POINTER(C.c_uint64), C.c_int]
+    lib.spegg_recomb_mode.restype = C.c_int
+    lib.spegg_recomb_mode.argtypes = [C.c_double]
+    lib.spegg_philox_fill.restype = st
+    lib.spegg_philox_fill.argtypes = [C.c_uint64, vp, vp, u32, vp]
+    _lib = lib
+    return lib
+
+
+def last_error():
+    return load().spegg_last_error().decode()
+
+
+def check(status):
+    if status != OK:
+        raise SpeggError(status, last_error())
+
+
+def _p(arr, ctype):
+    return arr.ctypes.data_as(C.POINTER(ctype))
+
+
+DESC_KEYS = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
+             "fecundity", "effects")
+
+
+def make_descs(reps):
+    """ctypes array of descriptors from dicts; returns (array, keepalive)."""
+    arr = (RepDesc * len(reps))()
+    keep = []
+    for k, d in enumerate(reps):
+        unknown = set(d) - set(DESC_KEYS)
+        if unknown:
+            raise ValueError(f"unknown descriptor keys {sorted(unknown)}")
+        n0 = int(d.get("n0", 0))
+        arr[k].seed = int(d.get("seed", 1))
+        arr[k].replicate_id = int(d.get("replicate_id", 0))
+        arr[k].regime = int(d.get("regime", WF))
+        arr[k].n0 = n0
+        arr[k].capacity = int(d.get("capacity", n0))
+        arr[k].n_loci = int(d.get("n_loci", 64))
+        arr[k].reserved = 0
+        for f in ("mu", "r", "theta", "omega", "K", "fecundity"):
+            setattr(arr[k], f, float(d.get(f, 0.5 if f == "r" else 0.0)))
+        eff = d.get("effects")
+        if eff is not None:
+            e = np.ascontiguousarray(eff, dtype=np.int8)
+            keep.append(e)
+            arr[k].effects = _p(e, C.c_int8)
+    return arr, keep
+
+
+def footprint(reps):
+    arr, _keep = make_descs(reps)
+    n = load().spegg_footprint(arr, len(reps))
+    if n == 0:
+        raise SpeggError(E_INVALID, last_error())
+    return int(n)
+
+
+def threshold_table(kind, a, b=0, cap=None):
+    cap = cap or max(1024, int(b) + 1)
+    out = np.zeros(cap, dtype=np.uint64)
+    n = load().spegg_threshold_table(int(kind), float(a), int(b), _p(out, C.c_uint64), cap)
+    if n < 0:
+        raise SpeggError(E_INVALID, "threshold_table rejected its arguments")
+    return out[:n].copy()
+
+
+def recomb_mode(r):
+    return {0: "raw", 1: "zero", 2: "skip", 3: "lazy"}[load().spegg_recomb_mode(float(r))]
+
+
+def philox_fill(seed, ctr):
+    """Device Philox4x32-10 of counters ctr (n x 4 uint32) -> n x 4 uint32."""
+    import torch
+    c = torch.as_tensor(np.ascontiguousarray(ctr, dtype=np.uint32).view(np.int32)).reshape(-1, 4).to("cuda")
+    out = torch.empty_like(c)
+    stream = torch.cuda.current_stream().cuda_stream
+    check(load().spegg_philox_fill(int(seed), c.data_ptr(), out.data_ptr(), c.shape[0], stream))
+    return out.cpu().numpy().view(np.uint32)
+
+
+class Population:
+    """Replicates resident in device memory, advanced by the HIP kernels."""
+
+    def __init__(self, reps, device="cuda", stream=None):
+        import torch
+        self.lib = load()
+        self.reps = [dict(d) for d in reps]
+        self.n_reps = len(reps)
+        arr, keep = make_descs(self.reps)
+        self.footprint = int(self.lib.spegg_footprint(arr, self.n_reps))
+        if self.footprint == 0:
+            raise SpeggError(E_INVALID, last_error())
+        self.workspace = torch.empty(self.footprint, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        h = C.c_void_p()
+        check(self.lib.spegg_pop_create(arr, self.n_reps, C.c_void_p(self.workspace.data_ptr()), self.footprint,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.L = [int(d.get("n_loci", 64)) for d in self.reps]
+        self.W = [(L + 31) // 32 for L in self.L]
+        del keep
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.spegg_pop_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, n=1):
+        check(self.lib.spegg_step_generations(self._h, int(n)))
+
+    def stats(self):
+        out = (RepStats * self.n_reps)()
+        check(self.lib.spegg_stats(self._h, out, self.n_reps))
+        return [s.as_dict() for s in out]
+
+    def _n_of(self, rep):
+        return self.stats()[rep]["n"]
+
+    def genomes(self, rep=0):
+        n = self._n_of(rep)
+        W = self.W[rep]
+        out = np.zeros(max(n, 1) * 2 * W, dtype=np.uint32)
+        got = C.c_uint32()
+        check(self.lib.spegg_read_genomes(self._h, rep, 0, 0, _p(out, C.c_uint32), out.size, C.byref(got)))
+        return out[: got.value * 2 * W].reshape(got.value, 2, W)
+
+    def write_genomes(self, rep, words, generation):
+        w = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1)
+        n = w.size // (2 * self.W[rep])
+        check(self.lib.spegg_write_genomes(self._h, rep, 0, 0, _p(w, C.c_uint32), n, int(generation)))
+
+    def phenotypes(self, rep=0):
+        n = self._n_of(rep)
+        out = np.zeros(max(n, 1), dtype=np.int32)
+        got = C.c_uint32()
+        check(self.lib.spegg_read_phenotypes(self._h, rep, _p(out, C.c_int32), out.size, C.byref(got)))
+        return out[: got.value]
+
+    def survivors(self, rep=0):
+        n = self.stats()[rep]["n_survivors"]
+        out = np.zeros(max(n, 1), dtype=np.uint32)
+        got = C.c_uint32()
+        check(self.lib.spegg_read_survivors(self._h, rep, _p(out, C.c_uint32), out.size, C.byref(got)))
+        return out[: got.value]
+
+    def set_trace(self, enable=True):
+        check(self.lib.spegg_set_trace(self._h, 1 if enable else 0))
+
+    def parents(self, rep=0):
+        n = self._n_of(rep)
+        mom = np.zeros(max(n, 1), dtype=np.uint32)
+        dad = np.zeros(max(n, 1), dtype=np.uint32)
+        got = C.c_uint32()
+        check(self.lib.spegg_read_parents(self._h, rep, _p(mom, C.c_uint32), _p(dad, C.c_uint32), mom.size,
+                                          C.byref(got)))
+        return mom[: got.value], dad[: got.value]
+
+    def set_timing(self, kernels=("survive", "scan", "compact", "offspring", "finalize")):
+        """Bracket the named kernels with HIP events (empty: stop)."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << KERNEL_NAMES.index(k)
+        check(self.lib.spegg_set_timing(self._h, mask))
+
+    def kernel_times(self):
+        """{kernel: (ms summed, launches)} since the last call."""
+        k = len(KERNEL_NAMES)
+        ms = (C.c_double * k)()
+        n = (C.c_uint64 * k)()
+        check(self.lib.spegg_kernel_times(self._h, ms, n, k))
+        return {KERNEL_NAMES[i]: (ms[i], n[i]) for i in range(k)}

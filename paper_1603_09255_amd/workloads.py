@@ -1,0 +1,64 @@
+"""Seeded synthetic workloads shaped like the paper's case studies.
+
+This module only generates inputs (parameter sets, allelic effects, random
+genomes) from fixed seeds; it holds none of the model's arithmetic.  The
+same dicts feed the HIP library's descriptors and the oracle's parameters
+(identical key names).
+
+The paper's own runs use about 50,000 individuals per patch, up to 100
+patches and 250 iterations (main text, Fig. 2 caption); their parameter
+values are not part of the paper.  The configurations below are synthetic
+stand-ins of that shape.
+"""
+import numpy as np
+
+WF, POISSON_BH = 0, 1
+
+
+def plain_small(seed=1):
+    """Wright-Fisher, N = 1000 diploids, L = 64 loci (two 32-bit words),
+    unit additive effects, Gaussian stabilising selection (optimum 0,
+    width 8), free recombination, mu = 1e-5 per locus; 100 generations."""
+    return dict(seed=seed, replicate_id=0, regime=WF, n0=1000, capacity=1000, n_loci=64, mu=1e-5, r=0.5,
+                theta=0.0, omega=8.0, K=0.0, fecundity=0.0, effects=None), 100
+
+
+def plain_scale_effects(L=1024, seed=20260102):
+    """Allelic effects on the integer grid [-4, 4], drawn once."""
+    return np.random.default_rng(seed).integers(-4, 5, size=L).astype(np.int8)
+
+
+def plain_scale(seed=1):
+    """One replicate at scale: N0 = 100000 (capacity 250000), L = 1024 loci,
+    effects on the integer grid [-4, 4], adjacent-locus crossover r = 0.01,
+    mu = 1e-6, Poisson(2.2) fecundity with Beverton-Holt density-dependent
+    survival (K = 100000), stabilising selection of width 64; 1000
+    generations."""
+    return dict(seed=seed, replicate_id=0, regime=POISSON_BH, n0=100_000, capacity=250_000, n_loci=1024,
+                mu=1e-6, r=0.01, theta=0.0, omega=64.0, K=100_000.0, fecundity=2.2,
+                effects=plain_scale_effects()), 1000
+
+
+def batched_table(n_reps=4096, seed=20260101, philox_seed=1):
+    """Per-replicate parameters of the batched form: N ~ U{500..50000},
+    L from {64, 256, 1024}, mu log-uniform in [1e-7, 1e-4], r ~ U[0.001, 0.5],
+    selection width ~ U[2, 16]; Wright-Fisher, unit effects."""
+    g = np.random.default_rng(seed)
+    N = g.integers(500, 50_001, n_reps)
+    L = g.choice([64, 256, 1024], n_reps)
+    mu = 10.0 ** g.uniform(-7.0, -4.0, n_reps)
+    r = g.uniform(0.001, 0.5, n_reps)
+    omega = g.uniform(2.0, 16.0, n_reps)
+    return [dict(seed=philox_seed, replicate_id=i, regime=WF, n0=int(N[i]), capacity=int(N[i]), n_loci=int(L[i]),
+                 mu=float(mu[i]), r=float(r[i]), theta=0.0, omega=float(omega[i]), K=0.0, fecundity=0.0,
+                 effects=None) for i in range(n_reps)]
+
+
+def random_genomes(n, L, seed, p_one=0.5):
+    """n packed diploid genomes (n, 2, ceil(L/32)) uint32 with locus l at
+    bit l % 32 of word l // 32, allele 1 with probability p_one, tail zero."""
+    g = np.random.default_rng(seed)
+    W = (L + 31) // 32
+    bits = (g.random((n, 2, W * 32)) < p_one).astype(np.uint8)
+    bits[:, :, L:] = 0
+    return np.packbits(bits, axis=-1, bitorder="little").view(np.uint32).reshape(n, 2, W).copy()

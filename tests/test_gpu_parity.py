@@ -1,0 +1,165 @@
+"""GPU parity: the HIP library against the oracle, bit for bit.
+
+Every case starts both sides from the same seeded input (the INIT stream or
+genomes from the shared input generator), advances them independently and
+compares genomes, phenotypes, survivor lists, parents and the census after
+every generation.  Tolerance: none (all decisions are integer comparisons).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import read_kat
+from gpu_helpers import assert_same_state, lockstep, oracle_pop, say
+from paper_1603_09255_amd import spegg, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def test_device_philox_known_answers():
+    for ctr, key, expect in read_kat():
+        say("philox KAT", ctr, key)
+        out = spegg.philox_fill(key[0] | (key[1] << 32), np.array([ctr], np.uint32))
+        assert [int(x) for x in out[0]] == expect
+
+
+def test_device_philox_matches_oracle_on_counter_grid():
+    g = np.random.default_rng(3)
+    ctr = g.integers(0, 1 << 32, (4096, 4), dtype=np.uint64).astype(np.uint32)
+    seed = 0x1234_5678_9ABC_DEF0
+    say("philox grid", ctr.shape)
+    dev = spegg.philox_fill(seed, ctr)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for i in range(0, 4096, 37):
+        assert np.array_equal(dev[i], oracle.philox4x32_10(ctr[i], key))
+
+
+@pytest.mark.parametrize("L,n0", [(1, 7), (31, 50), (32, 64), (33, 65), (64, 1000), (100, 257), (1024, 300),
+                                  (4000, 40)])
+def test_initial_population_matches_oracle(L, n0):
+    say("init", L, n0)
+    d = dict(seed=5, replicate_id=3, regime=0, n0=n0, capacity=n0 + 5, n_loci=L, mu=0.0, r=0.5, omega=0.0)
+    pop = spegg.Population([d])
+    orc = oracle_pop(d)
+    assert_same_state(pop, 0, orc, "init")
+
+
+def test_plain_small_100_generations_bit_exact():
+    desc, gens = workloads.plain_small(seed=1)
+    say("plain small", desc, gens)
+    st = lockstep(desc, gens, trace=True, check_every=10)
+    assert st["generation"] == 100 and st["n"] == 1000
+
+
+CASES = [
+    # id, descriptor overrides, generations
+    ("wf-raw-L64", dict(regime=0, n_loci=64, r=0.5, mu=1e-3, omega=4.0), 3),
+    ("wf-zero-L100", dict(regime=0, n_loci=100, r=0.0, mu=0.01, omega=6.0), 3),
+    ("wf-skip-L1024", dict(regime=0, n_loci=1024, r=0.01, mu=1e-3, omega=20.0), 3),
+    ("wf-skip-L257", dict(regime=0, n_loci=257, r=0.1, mu=0.02, omega=9.0), 3),
+    ("wf-lazy-L200", dict(regime=0, n_loci=200, r=0.3, mu=1e-2, omega=8.0), 3),
+    ("wf-lazy-boundary-r", dict(regime=0, n_loci=96, r=0.17, mu=0.0, omega=0.0), 2),
+    ("wf-lazy-L2048", dict(regime=0, n_loci=2048, r=0.45, mu=1e-4, omega=30.0), 2),
+    ("wf-L1", dict(regime=0, n_loci=1, r=0.01, mu=0.1, omega=0.5), 3),
+    ("wf-L31-high-mu", dict(regime=0, n_loci=31, r=0.5, mu=0.4, omega=3.0), 3),
+    ("wf-effects", dict(regime=0, n_loci=300, r=0.05, mu=1e-3, omega=15.0, effects="grid"), 3),
+    ("pois-bh-L1024", dict(regime=1, n_loci=1024, r=0.01, mu=1e-4, omega=64.0, K=800.0, fecundity=2.2,
+                           capacity=3000, effects="grid"), 3),
+    ("pois-trunc", dict(regime=1, n_loci=64, r=0.25, mu=1e-3, omega=0.0, K=0.0, fecundity=4.0, capacity=700), 3),
+    ("pois-no-K", dict(regime=1, n_loci=40, r=0.5, mu=0.0, omega=5.0, K=0.0, fecundity=1.5, capacity=5000), 4),
+    ("extinction", dict(regime=0, n_loci=64, r=0.5, mu=0.0, omega=0.3, theta=500.0), 3),
+    ("n-one", dict(regime=0, n_loci=70, r=0.2, mu=0.05, omega=0.0, n0=1, capacity=1), 3),
+]
+
+
+@pytest.mark.parametrize("name,over,gens", CASES, ids=[c[0] for c in CASES])
+def test_lockstep_from_generator_genomes(name, over, gens):
+    over = dict(over)
+    L = over["n_loci"]
+    n0 = over.pop("n0", 600)
+    cap = over.pop("capacity", n0)
+    if over.get("effects") == "grid":
+        over["effects"] = np.random.default_rng(L).integers(-4, 5, L).astype(np.int8)
+    desc = dict(seed=77, replicate_id=5, n0=n0, capacity=cap, theta=0.0, K=0.0, fecundity=0.0)
+    desc.update(over)
+    words = workloads.random_genomes(n0, L, seed=L + n0, p_one=0.4)
+    say("lockstep", name, "L", L, "n0", n0, "cap", cap)
+    lockstep(desc, gens, start_words=words, start_gen=37, trace=True)
+
+
+def test_batch_equals_each_replicate_alone_and_oracle():
+    g = np.random.default_rng(11)
+    reps = []
+    for i, (L, regime, r) in enumerate([(64, 0, 0.5), (1024, 0, 0.01), (256, 1, 0.3), (33, 0, 0.0),
+                                        (700, 1, 0.12), (64, 0, 0.2)]):
+        n0 = int(g.integers(50, 400))
+        reps.append(dict(seed=9, replicate_id=100 + i, regime=regime, n0=n0, capacity=3 * n0, n_loci=L, r=r,
+                         mu=1e-3, theta=0.0, omega=float(g.uniform(3, 20)), K=float(n0), fecundity=2.0))
+    say("batch of", len(reps))
+    batch = spegg.Population(reps)
+    batch.set_trace(True)
+    batch.step(4)
+    for i, d in enumerate(reps):
+        alone = spegg.Population([d])
+        alone.set_trace(True)
+        alone.step(4)
+        assert batch.stats()[i] == alone.stats()[0]
+        assert np.array_equal(batch.genomes(i), alone.genomes(0))
+        orc = oracle_pop(d)
+        orc.step(4)
+        assert_same_state(batch, i, orc, f"batch replicate {i}", parents=True)
+        alone.close()
+
+
+def test_plain_scale_first_generations_full_size():
+    desc, _ = workloads.plain_scale(seed=1)
+    say("plain scale full size, 2 generations")
+    gpu = spegg.Population([desc])
+    gpu.set_trace(True)
+    orc = oracle_pop(desc)
+    assert_same_state(gpu, 0, orc, "init")
+    for _ in range(2):
+        gpu.step(1)
+        orc.step(1)
+        assert_same_state(gpu, 0, orc, f"generation {orc.generation}", parents=True)
+
+
+def test_write_read_errors_and_roundtrip():
+    d = dict(seed=1, n0=10, capacity=20, n_loci=40, r=0.5, omega=0.0)
+    pop = spegg.Population([d])
+    w = workloads.random_genomes(15, 40, seed=2)
+    pop.write_genomes(0, w, 9)
+    assert np.array_equal(pop.genomes(0), w)
+    assert pop.stats()[0]["generation"] == 9
+    bad = w.copy()
+    bad[3, 1, 1] |= 1 << 20  # locus 52 >= L
+    with pytest.raises(spegg.SpeggError) as ei:
+        pop.write_genomes(0, bad, 9)
+    assert ei.value.status == spegg.E_INVALID
+    with pytest.raises(spegg.SpeggError):
+        pop.write_genomes(0, workloads.random_genomes(21, 40, seed=3), 0)
+    with pytest.raises(spegg.SpeggError) as ei:
+        pop.parents(0)
+    assert ei.value.status == spegg.E_STATE
+    import ctypes as C
+    got = C.c_uint32()
+    small = np.zeros(4, np.uint32)
+    st = pop.lib.spegg_read_genomes(pop._h, 0, 0, 0, small.ctypes.data_as(C.POINTER(C.c_uint32)), 4, C.byref(got))
+    assert st == spegg.E_INVALID and got.value == 15
+
+
+def test_kernel_timing_counts_launches():
+    desc, _ = workloads.plain_small(seed=2)
+    pop = spegg.Population([desc])
+    pop.set_timing()
+    pop.step(5)
+    t = pop.kernel_times()
+    assert all(t[k][1] == 5 for k in t)
+    assert all(t[k][0] > 0 for k in t)
+    pop.set_timing(["offspring"])
+    pop.step(3)
+    t = pop.kernel_times()
+    assert t["offspring"][1] == 3 and t["survive"][1] == 0
+    pop.set_timing([])
+    pop.step(2)
+    assert all(v[1] == 0 for v in pop.kernel_times().values())
