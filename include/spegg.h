@@ -168,15 +168,14 @@ spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t *host_mom
 
 /* Kernel kinds timed by spegg_set_timing. */
 enum {
-    SPEGG_KERNEL_SURVIVE = 0,   /* steps D and the fecundity draw of A */
-    SPEGG_KERNEL_SCAN = 1,      /* per-replicate prefix sums, neonate count */
-    SPEGG_KERNEL_COMPACT = 2,   /* step E, the survivor list and slot owners */
-    SPEGG_KERNEL_OFFSPRING = 3, /* steps A (parents), B and C */
-    SPEGG_KERNEL_FINALIZE = 4,  /* census */
-    SPEGG_KERNEL_KINDS = 5
+    SPEGG_KERNEL_SURVIVE = 0,   /* step D and the fecundity draw of A */
+    SPEGG_KERNEL_SCAN = 1,      /* per-replicate prefix sums, neonate count, generation advance */
+    SPEGG_KERNEL_COMPACT = 2,   /* step E: the survivor list and slot owners */
+    SPEGG_KERNEL_OFFSPRING = 3, /* steps A (parents), B and C, census sums */
+    SPEGG_KERNEL_KINDS = 4
 };
 
-#define SPEGG_TIME_ALL 0x1Fu
+#define SPEGG_TIME_ALL 0xFu
 
 /* Bracket the kernels of the kinds in kinds_mask (bit k: kind k; 0 stops)
  * launched by later spegg_step_generations calls with HIP events on the

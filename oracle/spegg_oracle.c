@@ -429,9 +429,10 @@ static void recombination_mask(oracle_pop *P, uint32_t j, uint32_t stream, uint3
     toggles[0] = (uint8_t)phase;
     if (P->mode == MODE_SKIP) {
         /* Crossover boundaries b (between loci b-1 and b) with independent
-         * probability r: successive gaps are 1 + geometric. */
+         * probability r: successive gaps are 1 + geometric, one word each,
+         * from word 4 of the stream on (block 0 carries only the phase). */
         uint64_t b = 0;
-        uint32_t q = 1;
+        uint32_t q = 4;
         for (;;) {
             uint32_t x = seq_word(&P->rng, j, stream, gen, q++);
             uint32_t gap = 0; /* smallest k with x < T_k, else L - 1 */

@@ -1,15 +1,15 @@
 // Kernels of one generation (main text, Fig. 1) for gfx950.
 //
 //   survive   D + the fecundity draw of A: per adult, p = v(z) s(N), one
-//             Philox word against floor(p 2^32); per tile counts
+//             Philox word against floor(p 2^32); per-tile counts
 //   scan      per replicate: exclusive prefix sums of the tile counts,
-//             survivor count, neonate count N_{t+1}
+//             survivor count, neonate count N_{t+1}; advances the
+//             generation and clears the census sums
 //   compact   E: ballot/mbcnt ranks -> ascending survivor list; Poisson
 //             regime: each mother writes her offspring slots
 //   offspring A (parents) + B (gametes: crossover mask, mutation flips)
-//             + C (additive phenotype by popcounts), one team of lanes per
-//             newborn, one lane per genome word
-//   finalize  census of the newborns, generation counter
+//             + C (additive phenotype by popcounts) + census sums; one
+//             team of 2G lanes per newborn, V consecutive words per lane
 //
 // All of it is integer work except p = v s (IEEE double, no contraction),
 // so every result is reproducible bit for bit.
@@ -60,12 +60,12 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, ui
     return off + incl - v;
 }
 
-// LDS visibility among the lanes of one wave: no reordering across it and
-// the wave's LDS operations complete first.
+// LDS visibility among the lanes of one wave: the wave's LDS operations
+// complete and are not reordered across it; global loads stay in flight.
 __device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Inclusive prefix XOR over the bits of a word: bit i = XOR of bits 0..i.
@@ -91,6 +91,84 @@ __device__ __forceinline__ int32_t word_effect(const RepDesc &d, uint32_t w, uin
     return (int32_t)__popc(g & P[w]) + 2 * (int32_t)__popc(g & P[W + w]) + 4 * (int32_t)__popc(g & P[2 * W + w]) -
            (int32_t)__popc(g & P[3 * W + w]) - 2 * (int32_t)__popc(g & P[4 * W + w]) -
            4 * (int32_t)__popc(g & P[5 * W + w]);
+}
+
+template <int V>
+struct Words {
+    uint32_t v[V];
+};
+
+template <int V>
+__device__ __forceinline__ Words<V> load_words(const uint32_t *p) {
+    Words<V> w;
+    if constexpr (V == 4) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(p);
+        w.v[0] = q.x;
+        w.v[1] = q.y;
+        w.v[2] = q.z;
+        w.v[3] = q.w;
+    } else if constexpr (V == 2) {
+        const uint2 q = *reinterpret_cast<const uint2 *>(p);
+        w.v[0] = q.x;
+        w.v[1] = q.y;
+    } else {
+        w.v[0] = *p;
+    }
+    return w;
+}
+
+template <int V>
+__device__ __forceinline__ void store_words(uint32_t *p, const Words<V> &w) {
+    if constexpr (V == 4) {
+        *reinterpret_cast<uint4 *>(p) = make_uint4(w.v[0], w.v[1], w.v[2], w.v[3]);
+    } else if constexpr (V == 2) {
+        *reinterpret_cast<uint2 *>(p) = make_uint2(w.v[0], w.v[1]);
+    } else {
+        *p = w.v[0];
+    }
+}
+
+// Number of geometric-gap thresholds T[0..len) that are <= x: the gap of
+// the inverse-CDF draw.  A float guess floor(log2(1 - x/2^32) / log2(1 - r))
+// is corrected against the table, so the table alone decides.
+__device__ __forceinline__ uint32_t geometric_gap(const RepDesc &d, uint32_t x) {
+    const uint32_t len = d.geo_len;
+    const float lg = __log2f((float)(4294967296.0 - (double)x)) - 32.0f;
+    const float guess = lg * d.geo_scale;
+    uint32_t g = guess >= (float)len ? len : (guess > 0.0f ? (uint32_t)guess : 0u);
+    const uint64_t *T = d.geo;
+    const uint64_t below = g > 0 ? T[g - 1] : 0ull;   // both checks load at once
+    const uint64_t above = g < len ? T[g] : kAlways;
+    if (below > (uint64_t)x || above <= (uint64_t)x) {
+        while (g > 0 && T[g - 1] > (uint64_t)x) --g;
+        while (g < len && T[g] <= (uint64_t)x) ++g;
+    }
+    return g;
+}
+
+// Crossovers of one 32-boundary block under the bit-serial comparison
+// U < R: U's bits, from the top, are successive words of the block's
+// stream; a boundary is decided at its first bit differing from R.
+__device__ __forceinline__ uint32_t lazy_block(const Rng &rng, uint32_t j, uint32_t rs, uint32_t tp, uint32_t w,
+                                               uint32_t R) {
+    uint32_t und = ~0u, hit = 0;
+    for (int i = 31; i >= 0; i -= 4) {
+        const Words4 blk = rng.block(j, rs, 1u + w * 8u + (uint32_t)((31 - i) >> 2), tp);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int b = i - c;
+            const uint32_t rest = b == 31 ? R : (R & ((1u << (b + 1)) - 1u));
+            if (rest == 0 || und == 0) return hit;
+            const uint32_t x = blk.v[c];
+            if ((R >> b) & 1u) {
+                hit |= und & ~x;
+                und &= x;
+            } else {
+                und &= ~x;
+            }
+        }
+    }
+    return hit;
 }
 
 // ---------------------------------------------------------------- init
@@ -123,15 +201,16 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
     const int64_t sz = wave_sum<int64_t>(z);
     const uint64_t sz2 = wave_sum<uint64_t>((uint64_t)(z * z));
     if (lane_id() == 0 && (sz != 0 || sz2 != 0)) {
-        atomicAdd((unsigned long long *)&state->stats.sum_z, (unsigned long long)sz);
-        atomicAdd((unsigned long long *)&state->stats.sum_z2, (unsigned long long)sz2);
+        const uint32_t slot = blockIdx.x % kCensusSlots;
+        atomicAdd((unsigned long long *)&state->sum_z[slot], (unsigned long long)sz);
+        atomicAdd((unsigned long long *)&state->sum_z2[slot], (unsigned long long)sz2);
     }
 }
 
 // ---------------------------------------------------------------- survive
 
 __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restrict__ descs,
-                                                         RepState *__restrict__ states,
+                                                         const RepState *__restrict__ states,
                                                          const SurvTile *__restrict__ tiles,
                                                          SurvCount *__restrict__ counts) {
     __shared__ uint32_t sh_u[3][kBlock / 64];
@@ -183,10 +262,12 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
 
 // ---------------------------------------------------------------- scan
 
-// One block per replicate: offsets of every survival tile, neonate count.
+// One block per replicate: offsets of every survival tile, neonate count,
+// and the advance of the replicate to the next generation.
 __global__ void __launch_bounds__(kBlock) scan_kernel(const RepDesc *__restrict__ descs,
                                                       RepState *__restrict__ states,
-                                                      SurvCount *__restrict__ counts) {
+                                                      SurvCount *__restrict__ counts, int trace) {
+    constexpr int PER = 4;  // tiles per thread per pass, loaded together
     __shared__ uint32_t sh[2][kBlock / 64];
     __shared__ uint64_t sh64[2][kBlock / 64];
     const uint32_t rep = blockIdx.x;
@@ -196,22 +277,39 @@ __global__ void __launch_bounds__(kBlock) scan_kernel(const RepDesc *__restrict_
     SurvCount *c = counts + d.surv_tile0;
     uint32_t alive_carry = 0;
     uint64_t kid_carry = 0, near_sum = 0, t_sum = 0;
-    for (uint32_t base = 0; base < ntiles; base += kBlock) {
-        const uint32_t k = base + threadIdx.x;
-        const bool ok = k < ntiles;
-        const uint32_t a = ok ? c[k].alive : 0u, kk = ok ? c[k].kids : 0u;
-        uint32_t ta, tk;
-        const uint32_t ea = block_excl_scan(a, sh[0], &ta);
-        const uint32_t ek = block_excl_scan(kk, sh[1], &tk);
-        if (ok) {
-            c[k].alive_off = alive_carry + ea;
-            const uint64_t ko = kid_carry + ek;
-            c[k].kid_off = ko > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)ko;
+    for (uint32_t base = 0; base < ntiles; base += kBlock * PER) {
+        const uint32_t k0 = base + threadIdx.x * PER;
+        uint32_t a[PER], kk[PER], ta = 0, tk = 0;
+        uint64_t nr = 0, ts = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const bool ok = k0 + q < ntiles;
+            const SurvCount v = ok ? c[k0 + q] : SurvCount{};
+            a[q] = v.alive;
+            kk[q] = v.kids;
+            ta += v.alive;
+            tk += v.kids;
+            nr += v.near;
+            ts += v.sum_t;
         }
-        alive_carry += ta;
-        kid_carry += tk;
-        const uint64_t nr = wave_sum<uint64_t>(ok ? c[k].near : 0u);
-        const uint64_t ts = wave_sum<uint64_t>(ok ? c[k].sum_t : 0ull);
+        uint32_t tot_a, tot_k;
+        const uint32_t ea = block_excl_scan(ta, sh[0], &tot_a);
+        const uint32_t ek = block_excl_scan(tk, sh[1], &tot_k);
+        uint32_t ra = alive_carry + ea;
+        uint64_t rk = kid_carry + ek;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (k0 + q < ntiles) {
+                c[k0 + q].alive_off = ra;
+                c[k0 + q].kid_off = rk > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)rk;
+            }
+            ra += a[q];
+            rk += kk[q];
+        }
+        alive_carry += tot_a;
+        kid_carry += tot_k;
+        nr = wave_sum<uint64_t>(nr);
+        ts = wave_sum<uint64_t>(ts);
         if (lane_id() == 0) {
             sh64[0][threadIdx.x >> 6] = nr;
             sh64[1][threadIdx.x >> 6] = ts;
@@ -222,6 +320,10 @@ __global__ void __launch_bounds__(kBlock) scan_kernel(const RepDesc *__restrict_
             t_sum += sh64[1][w];
         }
         __syncthreads();
+    }
+    if (threadIdx.x < kCensusSlots) {
+        st.sum_z[threadIdx.x] = 0;
+        st.sum_z2[threadIdx.x] = 0;
     }
     if (threadIdx.x == 0) {
         const uint32_t n = st.n, ns = alive_carry;
@@ -234,12 +336,16 @@ __global__ void __launch_bounds__(kBlock) scan_kernel(const RepDesc *__restrict_
             nn = kid_carry > d.cap ? d.cap : (uint32_t)kid_carry;
             st.truncated += kid_carry - nn;
         }
+        st.n_prev = n;
         st.n_surv = ns;
-        st.n_next = nn;
+        st.n = nn;
+        st.t += 1;
+        if (nn == 0) st.extinct = 1;
+        st.traced = trace ? 1u : 0u;
+        st.census_pending = 1;
         st.near_ties += near_sum;
-        st.stats.n_parents = n;
-        st.stats.n_survivors = ns;
-        st.stats.sum_threshold = t_sum;
+        st.sum_threshold = t_sum;
+        st.updates += (uint64_t)nn * d.L;
     }
 }
 
@@ -254,8 +360,8 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     const SurvTile tile = tiles[blockIdx.x];
     const RepDesc &d = descs[tile.rep];
     const RepState &st = states[tile.rep];
-    const uint32_t n = st.n;
-    if (tile.start >= n) return;  // uniform over the block
+    const uint32_t n = st.n_prev;  // the adults this generation started from
+    if (tile.start >= n) return;   // uniform over the block
     const uint32_t i = tile.start + threadIdx.x;
     const uint32_t f = i < n ? d.fate[i] : 0u;
     const uint32_t alive = f >> 15, kids = f & 0x7FFFu;
@@ -272,7 +378,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     const SurvCount c = counts[blockIdx.x];
     if (alive) d.S[c.alive_off + wave_off + rank_in_wave] = i;
     if (d.regime == SPEGG_POISSON_BH && kids) {
-        const uint32_t nn = st.n_next;
+        const uint32_t nn = st.n;
         const uint64_t slot0 = (uint64_t)c.kid_off + kid_rank;
         for (uint32_t m = 0; m < kids; ++m) {
             const uint64_t slot = slot0 + m;
@@ -283,19 +389,20 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
 
 // ---------------------------------------------------------------- offspring
 
-// One team of TPO lanes makes one newborn: lanes [0, G) build the maternal
-// gamete (haplotype 0), lanes [G, 2G) the paternal one; lane g handles
-// genome words g, g + G, ...  Each tile holds offspring_per_tile(TPO)
-// consecutive newborn slots of one replicate.
-template <int TPO>
+// One team of 2G lanes makes one newborn: lanes [0, G) build the maternal
+// gamete (haplotype 0), lanes [G, 2G) the paternal one; in each chunk of
+// G x V words, lane g handles V consecutive words from g x V.
+template <int G, int V>
 __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__restrict__ descs,
                                                            RepState *__restrict__ states,
                                                            const OffTile *__restrict__ tiles, uint32_t tile0,
-                                                           uint32_t ntiles, Partial *__restrict__ partials,
-                                                           int trace) {
-    constexpr int G = TPO / 2;
-    constexpr int TEAMS = kBlock / TPO;
-    constexpr int ITERS = TEAMS >= 16 ? 1 : 16 / TEAMS;
+                                                           uint32_t ntiles, int single_rep,
+                                                           Partial *__restrict__ partials, int trace) {
+    constexpr uint32_t TPO = 2 * G;
+    constexpr uint32_t TEAMS = kBlock / TPO;
+    constexpr uint32_t ITERS = TEAMS >= 16 ? 1 : 16 / TEAMS;
+    constexpr uint32_t OPT = TEAMS * ITERS;
+    constexpr uint32_t CH = G * V;  // words of one gamete per chunk
     extern __shared__ uint32_t lds[];
     __shared__ int64_t red_z[kBlock / 64];
     __shared__ uint64_t red_z2[kBlock / 64];
@@ -303,74 +410,114 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
     const uint32_t team = threadIdx.x / TPO, lane = threadIdx.x % TPO;
     const uint32_t half = lane / G, gl = lane % G;
     const uint32_t seg0 = lane_id() - gl;  // first wave lane of this gamete's lanes
-    const uint64_t segmask = G >= 64 ? ~0ull : ((1ull << G) - 1ull);
+    const uint32_t segmask = G >= 32 ? 0xFFFFFFFFu : ((1u << G) - 1u);
 
-    for (uint32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
-        const OffTile tile = tiles[tile0 + ti];
-        const RepDesc &d = descs[tile.rep];
-        RepState &st = states[tile.rep];
-        const uint32_t nn = st.n_next;
-        if (tile.start >= nn) continue;  // uniform over the block
-        const uint32_t t = st.t, ns = st.n_surv, cur = t & 1u;
+    uint32_t limit = ntiles;
+    if (single_rep >= 0) {
+        const uint32_t nn = states[single_rep].n;
+        const uint32_t active = (nn + OPT - 1) / OPT;
+        limit = active < ntiles ? active : ntiles;
+    }
+    for (uint32_t ti = blockIdx.x; ti < limit; ti += gridDim.x) {
+        uint32_t rep, start;
+        if (single_rep >= 0) {
+            rep = (uint32_t)single_rep;
+            start = ti * OPT;
+        } else {
+            const OffTile tile = tiles[tile0 + ti];
+            rep = tile.rep;
+            start = tile.start;
+        }
+        const RepDesc &d = descs[rep];
+        RepState &st = states[rep];
+        const uint32_t nn = st.n;
+        if (start >= nn) continue;  // uniform over the block
+        const uint32_t tp = st.t - 1u, ns = st.n_surv, cur = tp & 1u;
         const uint32_t W = d.W, L = d.L, mode = d.mode;
+        const uint64_t binom0 = d.binom[0];  // most gametes carry no mutation
         const Rng rng{d.key0, d.key1, d.c3};
-        const uint32_t *__restrict__ src_base = d.genome[cur];
-        uint32_t *__restrict__ dst_base = d.genome[cur ^ 1u];
         uint32_t *X = lds + (size_t)(team * 2u + half) * 2u * W;  // crossover toggles
         uint32_t *F = X + W;                                        // mutation flips
         int64_t my_z = 0;
         uint64_t my_z2 = 0;
 
-        for (int it = 0; it < ITERS; ++it) {
-            const uint32_t j = tile.start + (uint32_t)it * TEAMS + team;
+        for (uint32_t it = 0; it < ITERS; ++it) {
+            const uint32_t j = start + it * TEAMS + team;
             if (j >= nn) continue;  // uniform over the team
 
             // A: parents, uniform over the survivors (Poisson: the slot's mother)
-            const Words4 pw = rng.block(j, kStParent, 0, t);
+            const Words4 pw = rng.block(j, kStParent, 0, tp);
             const uint32_t mom = d.regime == SPEGG_WF ? d.S[uniform_index(pw.v[0], pw.v[1], ns)] : d.owner[j];
             const uint32_t dad = d.S[uniform_index(pw.v[2], pw.v[3], ns)];
-            const uint32_t *__restrict__ src = src_base + (size_t)(half ? dad : mom) * 2u * W;
-            uint32_t *__restrict__ dst = dst_base + (size_t)j * 2u * W + (size_t)half * W;
+            const uint32_t *__restrict__ src = d.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
+            uint32_t *__restrict__ dst = d.genome[cur ^ 1u] + (size_t)j * 2u * W + (size_t)half * W;
             const uint32_t rs = kStRecomb + half, ms = kStMutate + half;
+
+            // first chunk of the parent's haplotypes, in flight while the
+            // crossover mask is drawn
+            uint32_t w0 = gl * V;
+            Words<V> h0{}, h1{};
+            if (w0 < W) {
+                h0 = load_words<V>(src + w0);
+                h1 = load_words<V>(src + W + w0);
+            }
 
             // B1: crossover toggles.  Boundary b (between loci b-1 and b)
             // toggles the source haplotype from locus b on; bit 0 of word 0
             // holds the phase (which haplotype locus 0 copies).
             uint32_t phase = 0;
-            if (mode != kModeRaw) phase = rng.block(j, rs, 0, t).v[0] & 1u;
+            if (mode != kModeRaw) phase = rng.block(j, rs, 0, tp).v[0] & 1u;
             if (mode == kModeSkip) {
-                for (uint32_t w = gl; w < W; w += G) X[w] = 0;
+                for (uint32_t w = gl * V; w < W; w += CH)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) X[w + v] = 0;
                 wave_lds_sync();
-                uint32_t b = 0, q0 = 1;
+                // gaps come four to a Philox block from block 1 on; lane g
+                // takes block blk + g, so a pass places up to 4G crossovers
+                uint32_t b = 0, blk = 1;
                 for (;;) {
-                    const uint32_t x = rng.seq(j, rs, q0 + gl, t);
-                    uint32_t pos = 1u + table_count_le(d.geo, d.geo_len, x);
+                    const Words4 xw = rng.block(j, rs, blk + gl, tp);
+                    uint32_t cum[4];
+                    uint32_t acc = 0;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        acc += 1u + geometric_gap(d, xw.v[c]);
+                        cum[c] = acc;
+                    }
+                    uint32_t incl = acc;
 #pragma unroll
                     for (int o = 1; o < G; o <<= 1) {
-                        const uint32_t v = __shfl_up(pos, o, G);
-                        if (gl >= (uint32_t)o) pos += v;
+                        const uint32_t y = __shfl_up(incl, o, G);
+                        if (gl >= (uint32_t)o) incl += y;
                     }
-                    pos += b;
-                    if (pos <= L - 1u) atomicOr(&X[pos >> 5], 1u << (pos & 31u));
-                    const uint32_t last = __shfl(pos, G - 1, G);
+                    const uint32_t base = b + incl - acc;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const uint32_t pos = base + cum[c];
+                        if (pos <= L - 1u) atomicOr(&X[pos >> 5], 1u << (pos & 31u));
+                    }
+                    const uint32_t last = __shfl(b + incl, G - 1, G);
                     if (last > L - 1u) break;
                     b = last;
-                    q0 += G;
+                    blk += G;
                 }
                 wave_lds_sync();
             }
 
             // B2: mutation, K ~ Binomial(L, mu) distinct loci flipped
-            const uint32_t K = table_draw(d.binom, d.binom_len, rng.block(j, ms, 0, t).v[0]);
+            const uint32_t xk = rng.block(j, ms, 0, tp).v[0];
+            const uint32_t K = (uint64_t)xk < binom0 ? 0u : table_draw(d.binom, d.binom_len, xk);
             if (K > 0) {
-                for (uint32_t w = gl; w < W; w += G) F[w] = 0;
+                for (uint32_t w = gl * V; w < W; w += CH)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) F[w + v] = 0;
                 wave_lds_sync();
                 if (gl == 0) {
                     uint32_t accepted = 0;
                     // at most 2^23 candidates per gamete: every loop ends
                     for (uint32_t m = 0; accepted < K && m < (1u << 23); ++m) {
-                        const uint32_t lo = rng.seq(j, ms, 1u + 2u * m, t);
-                        const uint32_t hi = rng.seq(j, ms, 2u + 2u * m, t);
+                        const uint32_t lo = rng.seq(j, ms, 1u + 2u * m, tp);
+                        const uint32_t hi = rng.seq(j, ms, 2u + 2u * m, tp);
                         const uint32_t pos = uniform_index(lo, hi, L);
                         const uint32_t bit = 1u << (pos & 31u);
                         if (!(F[pos >> 5] & bit)) {
@@ -385,58 +532,60 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             // B3 + C: gamete words, written out; additive phenotype
             int32_t zc = 0;
             uint32_t carry = 0;  // parity of the toggles in earlier chunks
-            for (uint32_t base = 0; base < W; base += G) {
-                const uint32_t w = base + gl;
-                const bool valid = w < W;
-                const uint32_t h0 = valid ? src[w] : 0u, h1 = valid ? src[W + w] : 0u;
-                uint32_t M;
+            for (uint32_t base = 0; base < W; base += CH) {
+                w0 = base + gl * V;
+                const bool valid = w0 < W;
+                if (base > 0 && valid) {
+                    h0 = load_words<V>(src + w0);
+                    h1 = load_words<V>(src + W + w0);
+                }
+                Words<V> M;
                 if (mode == kModeRaw) {
-                    M = rng.seq(j, rs, w, t);
-                } else {
-                    uint32_t tog = 0;
-                    if (valid) {
-                        if (mode == kModeSkip) {
-                            tog = X[w];
-                        } else if (mode == kModeLazy) {
-                            // boundary 32w + i crosses iff U < R, U's bits from
-                            // the top taken from successive words of block w
-                            const uint32_t R = d.R;
-                            uint32_t und = ~0u, hit = 0;
-                            for (int i = 31; i >= 0; --i) {
-                                const uint32_t rest = i == 31 ? R : (R & ((1u << (i + 1)) - 1u));
-                                if (rest == 0 || und == 0) break;
-                                const uint32_t q = 31u - (uint32_t)i;
-                                const Words4 blk = rng.block(j, rs, 1u + w * 8u + (q >> 2), t);
-                                const uint32_t c = q & 3u;
-                                const uint32_t x = c == 0 ? blk.v[0] : c == 1 ? blk.v[1] : c == 2 ? blk.v[2] : blk.v[3];
-                                if ((R >> i) & 1u) {
-                                    hit |= und & ~x;
-                                    und &= x;
-                                } else {
-                                    und &= ~x;
-                                }
-                            }
-                            tog = hit;
-                        }
-                        if (w == 0) tog = (tog & ~1u) | phase;
+                    const Words4 blk = rng.block(j, rs, w0 >> 2, tp);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const uint32_t c = (w0 + v) & 3u;
+                        M.v[v] = c == 0 ? blk.v[0] : c == 1 ? blk.v[1] : c == 2 ? blk.v[2] : blk.v[3];
                     }
-                    const uint32_t pre = prefix_xor32(tog);
-                    const uint64_t bal = __ballot(pre >> 31);
-                    const uint32_t seg = (uint32_t)((bal >> seg0) & segmask);
+                } else {
+                    uint32_t lane_par = 0;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const uint32_t w = w0 + v;
+                        uint32_t tog = 0;
+                        if (valid) {
+                            if (mode == kModeSkip) tog = X[w];
+                            else if (mode == kModeLazy) tog = lazy_block(rng, j, rs, tp, w, d.R);
+                            if (w == 0) tog = (tog & ~1u) | phase;
+                        }
+                        const uint32_t pre = prefix_xor32(tog);
+                        M.v[v] = pre ^ (lane_par ? ~0u : 0u);
+                        lane_par ^= pre >> 31;
+                    }
+                    // parity of the toggles in the gamete's lanes below this one
+                    const uint64_t bal = __ballot(lane_par);
+                    const uint32_t seg = (uint32_t)(bal >> seg0) & segmask;
                     const uint32_t below = __popc(seg & ((1u << gl) - 1u));
-                    M = pre ^ (((below + carry) & 1u) ? ~0u : 0u);
+                    const uint32_t flip = ((below + carry) & 1u) ? ~0u : 0u;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) M.v[v] ^= flip;
                     carry = (carry + __popc(seg)) & 1u;
                 }
-                uint32_t g = (h0 & ~M) | (h1 & M);
                 if (valid) {
-                    if (K > 0) g ^= F[w];
-                    if (w == W - 1u) g &= d.tail_mask;
-                    dst[w] = g;
-                    zc += word_effect(d, w, g);
+                    Words<V> g;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        uint32_t x = (h0.v[v] & ~M.v[v]) | (h1.v[v] & M.v[v]);
+                        if (K > 0) x ^= F[w0 + v];
+                        if (w0 + v == W - 1u) x &= d.tail_mask;
+                        g.v[v] = x;
+                        zc += word_effect(d, w0 + v, x);
+                    }
+                    store_words<V>(dst + w0, g);
                 }
             }
 #pragma unroll
-            for (int o = 1; o < TPO; o <<= 1) zc += __shfl_xor(zc, o, TPO);
+            for (int o = 1; o < (int)TPO; o <<= 1) zc += __shfl_xor(zc, o, TPO);
             if (lane == 0) {
                 const int32_t z = zc - d.sum_e;
                 d.z[cur ^ 1u][j] = z;
@@ -448,7 +597,7 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
                 }
             }
         }
-        // per-tile census partials (no atomics)
+        // census sums of the tile, folded later by the census kernel
         const int64_t wz = wave_sum<int64_t>(my_z);
         const uint64_t wz2 = wave_sum<uint64_t>(my_z2);
         if (lane_id() == 0) {
@@ -457,29 +606,29 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            Partial p{0, 0};
+            int64_t a = 0;
+            uint64_t b = 0;
             for (int w = 0; w < kBlock / 64; ++w) {
-                p.sum_z += red_z[w];
-                p.sum_z2 += red_z2[w];
+                a += red_z[w];
+                b += red_z2[w];
             }
-            partials[tile0 + ti] = p;
+            partials[tile0 + ti] = Partial{a, b};
         }
         __syncthreads();
     }
 }
 
-// ---------------------------------------------------------------- finalize
-
-__global__ void __launch_bounds__(kBlock) finalize_kernel(const RepDesc *__restrict__ descs,
-                                                          RepState *__restrict__ states,
-                                                          const Partial *__restrict__ partials, int trace) {
+// One block per replicate: sums of the tile partials of the newest census.
+__global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restrict__ descs,
+                                                        RepState *__restrict__ states,
+                                                        const Partial *__restrict__ partials) {
     __shared__ int64_t sz[kBlock / 64];
     __shared__ uint64_t sz2[kBlock / 64];
     const uint32_t rep = blockIdx.x;
-    const RepDesc &d = descs[rep];
     RepState &st = states[rep];
-    const uint32_t nn = st.n_next;
-    const uint32_t used = (nn + d.off_per_tile - 1u) / d.off_per_tile;
+    if (!st.census_pending) return;  // uniform over the block
+    const RepDesc &d = descs[rep];
+    const uint32_t used = (st.n + d.off_per_tile - 1u) / d.off_per_tile;
     int64_t a = 0;
     uint64_t b = 0;
     for (uint32_t k = threadIdx.x; k < used; k += kBlock) {
@@ -494,26 +643,18 @@ __global__ void __launch_bounds__(kBlock) finalize_kernel(const RepDesc *__restr
         sz2[threadIdx.x >> 6] = b;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kCensusSlots) {
         int64_t sa = 0;
         uint64_t sb = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
-            sa += sz[w];
-            sb += sz2[w];
-        }
-        st.t += 1;
-        st.n = nn;
-        if (nn == 0) st.extinct = 1;
-        st.traced = trace ? 1u : 0u;
-        st.stats.generation = st.t;
-        st.stats.n = nn;
-        st.stats.extinct = st.extinct;
-        st.stats.sum_z = sa;
-        st.stats.sum_z2 = (int64_t)sb;
-        st.stats.near_ties = st.near_ties;
-        st.stats.truncated = st.truncated;
-        st.stats.updates += (uint64_t)nn * d.L;
+        if (threadIdx.x == 0)
+            for (int w = 0; w < kBlock / 64; ++w) {
+                sa += sz[w];
+                sb += sz2[w];
+            }
+        st.sum_z[threadIdx.x] = sa;
+        st.sum_z2[threadIdx.x] = sb;
     }
+    if (threadIdx.x == 0) st.census_pending = 0;
 }
 
 __global__ void philox_fill_kernel(uint32_t k0, uint32_t k1, const uint32_t *__restrict__ ctr,
@@ -526,6 +667,39 @@ __global__ void philox_fill_kernel(uint32_t k0, uint32_t k1, const uint32_t *__r
 
 inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
 
+struct OffArgs {
+    const RepDesc *descs;
+    RepState *states;
+    const OffTile *tiles;
+    uint32_t tile0, ntiles;
+    int single_rep;
+    Partial *partials;
+    uint32_t grid;
+    size_t lds;
+    int trace;
+    hipStream_t s;
+};
+
+template <int G, int V>
+hipError_t launch_offspring_gv(const OffArgs &a) {
+    hipLaunchKernelGGL((offspring_kernel<G, V>), dim3(a.grid), dim3(kBlock), a.lds, a.s, a.descs, a.states, a.tiles,
+                       a.tile0, a.ntiles, a.single_rep, a.partials, a.trace);
+    return hipGetLastError();
+}
+
+template <int V>
+hipError_t launch_offspring_v(int g, const OffArgs &a) {
+    switch (g) {
+    case 1: return launch_offspring_gv<1, V>(a);
+    case 2: return launch_offspring_gv<2, V>(a);
+    case 4: return launch_offspring_gv<4, V>(a);
+    case 8: return launch_offspring_gv<8, V>(a);
+    case 16: return launch_offspring_gv<16, V>(a);
+    case 32: return launch_offspring_gv<32, V>(a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -537,22 +711,21 @@ hipError_t launch_init(const RepDesc *d_desc, const RepDesc &h, uint32_t n0, hip
     return hipGetLastError();
 }
 
-hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, const RepDesc &h, uint32_t n, uint32_t buf,
-                             hipStream_t s) {
-    (void)h;
+hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t n, uint32_t buf, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(phenotype_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, d_desc, d_state, n, buf);
     return hipGetLastError();
 }
 
-hipError_t launch_survive(const RepDesc *descs, RepState *states, const SurvTile *tiles, SurvCount *counts,
+hipError_t launch_survive(const RepDesc *descs, const RepState *states, const SurvTile *tiles, SurvCount *counts,
                           uint32_t ntiles, hipStream_t s) {
     hipLaunchKernelGGL(survive_kernel, dim3(ntiles), dim3(kBlock), 0, s, descs, states, tiles, counts);
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const RepDesc *descs, RepState *states, SurvCount *counts, uint32_t n_reps, hipStream_t s) {
-    hipLaunchKernelGGL(scan_kernel, dim3(n_reps), dim3(kBlock), 0, s, descs, states, counts);
+hipError_t launch_scan(const RepDesc *descs, RepState *states, SurvCount *counts, uint32_t n_reps, int trace,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(scan_kernel, dim3(n_reps), dim3(kBlock), 0, s, descs, states, counts, trace);
     return hipGetLastError();
 }
 
@@ -562,38 +735,21 @@ hipError_t launch_compact(const RepDesc *descs, const RepState *states, const Su
     return hipGetLastError();
 }
 
-hipError_t launch_offspring(int tpo, const RepDesc *descs, RepState *states, const OffTile *tiles, uint32_t tile0,
-                            uint32_t ntiles, Partial *partials, uint32_t grid, size_t lds, int trace, hipStream_t s) {
-    switch (tpo) {
-    case 4:
-        hipLaunchKernelGGL(offspring_kernel<4>, dim3(grid), dim3(kBlock), lds, s, descs, states, tiles, tile0, ntiles,
-                           partials, trace);
-        break;
-    case 8:
-        hipLaunchKernelGGL(offspring_kernel<8>, dim3(grid), dim3(kBlock), lds, s, descs, states, tiles, tile0, ntiles,
-                           partials, trace);
-        break;
-    case 16:
-        hipLaunchKernelGGL(offspring_kernel<16>, dim3(grid), dim3(kBlock), lds, s, descs, states, tiles, tile0, ntiles,
-                           partials, trace);
-        break;
-    case 32:
-        hipLaunchKernelGGL(offspring_kernel<32>, dim3(grid), dim3(kBlock), lds, s, descs, states, tiles, tile0, ntiles,
-                           partials, trace);
-        break;
-    case 64:
-        hipLaunchKernelGGL(offspring_kernel<64>, dim3(grid), dim3(kBlock), lds, s, descs, states, tiles, tile0, ntiles,
-                           partials, trace);
-        break;
-    default:
-        return hipErrorInvalidValue;
+hipError_t launch_offspring(OffShape shape, const RepDesc *descs, RepState *states, const OffTile *tiles,
+                            uint32_t tile0, uint32_t ntiles, int single_rep, Partial *partials, uint32_t grid,
+                            size_t lds, int trace, hipStream_t s) {
+    const OffArgs a{descs, states, tiles, tile0, ntiles, single_rep, partials, grid, lds, trace, s};
+    switch (shape.vpl) {
+    case 1: return launch_offspring_v<1>(shape.g, a);
+    case 2: return launch_offspring_v<2>(shape.g, a);
+    case 4: return launch_offspring_v<4>(shape.g, a);
+    default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
-hipError_t launch_finalize(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,
-                           int trace, hipStream_t s) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(n_reps), dim3(kBlock), 0, s, descs, states, partials, trace);
+hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(census_kernel, dim3(n_reps), dim3(kBlock), 0, s, descs, states, partials);
     return hipGetLastError();
 }
 

@@ -46,7 +46,8 @@ struct Carver {
 
 // Everything the host derives from one descriptor.
 struct RepPlan {
-    uint32_t W = 0, mode = 0, R = 0, tpo = 0, opt = 0;
+    uint32_t W = 0, mode = 0, R = 0, opt = 0;
+    OffShape shape{1, 1};
     int32_t zmin = 0, sum_e = 0;
     uint32_t zlen = 0;
     bool unit = true;
@@ -58,9 +59,11 @@ struct RepPlan {
     size_t vtab_at = 0, pois_at = 0, binom_at = 0, geo_at = 0, planes_at = 0;
 };
 
+// Replicates sharing one offspring-kernel shape.
 struct OffClass {
-    int tpo;
+    OffShape shape;
     uint32_t tile0, ntiles, grid;
+    int single_rep;  // the class's only replicate, or -1
     size_t lds;
 };
 
@@ -136,8 +139,8 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p) {
         return fail(SPEGG_E_UNSUPPORTED, "replicate %u: fecundity %g needs more than %d table entries", i,
                     d.fecundity, kPoissonCap);
     if (p.mode == kModeSkip && L > 1) geometric_table(d.r, L - 1u, p.geo);
-    p.tpo = (uint32_t)lanes_per_offspring(p.W);
-    p.opt = (uint32_t)offspring_per_tile((int)p.tpo);
+    p.shape = offspring_shape(p.W);
+    p.opt = (uint32_t)offspring_per_tile(p.shape.g);
     p.surv_ntiles = (d.capacity + kSurvTile - 1) / kSurvTile;
     p.off_ntiles = (d.capacity + p.opt - 1) / p.opt;
     return SPEGG_OK;
@@ -156,23 +159,27 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
         p.surv_tile0 = (uint32_t)P.surv_tiles.size();
         for (uint32_t k = 0; k < p.surv_ntiles; ++k) P.surv_tiles.push_back({i, k * (uint32_t)kSurvTile});
     }
-    // offspring tiles grouped by kernel shape (lanes per offspring)
-    for (int tpo = 4; tpo <= 64; tpo <<= 1) {
-        OffClass c{tpo, (uint32_t)P.off_tiles.size(), 0, 0, 0};
-        uint32_t maxW = 0;
-        for (uint32_t i = 0; i < n; ++i) {
-            RepPlan &p = P.reps[i];
-            if ((int)p.tpo != tpo) continue;
-            p.off_tile0 = (uint32_t)P.off_tiles.size();
-            for (uint32_t k = 0; k < p.off_ntiles; ++k) P.off_tiles.push_back({i, k * p.opt});
-            if (p.W > maxW) maxW = p.W;
+    // offspring tiles grouped by kernel shape
+    for (int vpl = 1; vpl <= 4; vpl <<= 1)
+        for (int g = 1; g <= 32; g <<= 1) {
+            OffClass c{{g, vpl}, (uint32_t)P.off_tiles.size(), 0, 0, -1, 0};
+            uint32_t maxW = 0, members = 0, last = 0;
+            for (uint32_t i = 0; i < n; ++i) {
+                RepPlan &p = P.reps[i];
+                if (p.shape.g != g || p.shape.vpl != vpl) continue;
+                p.off_tile0 = (uint32_t)P.off_tiles.size();
+                for (uint32_t k = 0; k < p.off_ntiles; ++k) P.off_tiles.push_back({i, k * p.opt});
+                if (p.W > maxW) maxW = p.W;
+                ++members;
+                last = i;
+            }
+            c.ntiles = (uint32_t)P.off_tiles.size() - c.tile0;
+            if (c.ntiles == 0) continue;
+            c.single_rep = members == 1 ? (int)last : -1;
+            c.grid = c.ntiles < kMaxOffspringGrid ? c.ntiles : kMaxOffspringGrid;
+            c.lds = offspring_lds_bytes(g, maxW);
+            P.classes.push_back(c);
         }
-        c.ntiles = (uint32_t)P.off_tiles.size() - c.tile0;
-        if (c.ntiles == 0) continue;
-        c.grid = c.ntiles < kMaxOffspringGrid ? c.ntiles : kMaxOffspringGrid;
-        c.lds = offspring_lds_bytes(tpo, maxW);
-        P.classes.push_back(c);
-    }
     Carver cv;
     P.descs = cv.take(sizeof(RepDesc) * n);
     P.states = cv.take(sizeof(RepState) * n);
@@ -303,10 +310,26 @@ RepState initial_state(uint32_t t, uint32_t n) {
     s.t = t;
     s.n = n;
     s.extinct = n == 0;
-    s.stats.generation = t;
-    s.stats.n = n;
-    s.stats.extinct = s.extinct;
     return s;
+}
+
+spegg_rep_stats census_of(const RepState &s) {
+    spegg_rep_stats c;
+    std::memset(&c, 0, sizeof c);
+    c.generation = s.t;
+    c.n = s.n;
+    c.n_parents = s.n_prev;
+    c.n_survivors = s.n_surv;
+    c.extinct = s.extinct;
+    for (int k = 0; k < kCensusSlots; ++k) {
+        c.sum_z += s.sum_z[k];
+        c.sum_z2 += (int64_t)s.sum_z2[k];
+    }
+    c.near_ties = s.near_ties;
+    c.truncated = s.truncated;
+    c.sum_threshold = s.sum_threshold;
+    c.updates = s.updates;
+    return c;
 }
 
 spegg_status sync_stream(spegg_pop *pop) {
@@ -403,6 +426,7 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.off_tile0 = p.off_tile0;
         h.off_ntiles = p.off_ntiles;
         h.off_per_tile = p.opt;
+        h.geo_scale = p.mode == kModeSkip ? (float)(1.0 / std::log2(1.0 - d.r)) : 0.0f;
         h.K = d.K;
         h.lambda = d.fecundity;
         h.genome[0] = at<uint32_t>(pop->base, p.genome[0]);
@@ -442,8 +466,7 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
     for (uint32_t i = 0; i < n_reps; ++i) {
         e = launch_init(pop->d_descs() + i, pop->dev_descs[i], reps[i].n0, pop->stream);
         if (e == hipSuccess)
-            e = launch_phenotypes(pop->d_descs() + i, pop->d_states() + i, pop->dev_descs[i], reps[i].n0, 0,
-                                  pop->stream);
+            e = launch_phenotypes(pop->d_descs() + i, pop->d_states() + i, reps[i].n0, 0, pop->stream);
         if (e != hipSuccess) {
             delete pop;
             return fail(SPEGG_E_DEVICE, "initial population: %s", hipGetErrorString(e));
@@ -470,7 +493,8 @@ spegg_status spegg_step_generations(spegg_pop *pop, uint32_t n_generations) {
         });
         if (e == hipSuccess)
             e = timed(pop, SPEGG_KERNEL_SCAN, [&] {
-                return launch_scan(pop->d_descs(), pop->d_states(), pop->d_surv_counts(), pop->n_reps, pop->stream);
+                return launch_scan(pop->d_descs(), pop->d_states(), pop->d_surv_counts(), pop->n_reps, trace,
+                                   pop->stream);
             });
         if (e == hipSuccess)
             e = timed(pop, SPEGG_KERNEL_COMPACT, [&] {
@@ -480,15 +504,11 @@ spegg_status spegg_step_generations(spegg_pop *pop, uint32_t n_generations) {
         for (const OffClass &c : P.classes) {
             if (e != hipSuccess) break;
             e = timed(pop, SPEGG_KERNEL_OFFSPRING, [&] {
-                return launch_offspring(c.tpo, pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0,
-                                        c.ntiles, pop->d_partials(), c.grid, c.lds, trace, pop->stream);
+                return launch_offspring(c.shape, pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0,
+                                        c.ntiles, c.single_rep, pop->d_partials(), c.grid, c.lds, trace,
+                                        pop->stream);
             });
         }
-        if (e == hipSuccess)
-            e = timed(pop, SPEGG_KERNEL_FINALIZE, [&] {
-                return launch_finalize(pop->d_descs(), pop->d_states(), pop->d_partials(), pop->n_reps, trace,
-                                       pop->stream);
-            });
         if (e != hipSuccess) return device_fail(pop, e, "generation launch");
     }
     return SPEGG_OK;
@@ -500,11 +520,13 @@ spegg_status spegg_stats(spegg_pop *pop, spegg_rep_stats *host_out, uint32_t n) 
     if (!host_out || n > pop->n_reps) return fail(SPEGG_E_INVALID, "stats: need 0 < n <= %u and a buffer", pop->n_reps);
     DeviceGuard guard(pop->device);
     std::vector<RepState> s(n);
-    hipError_t e = hipMemcpyAsync(s.data(), pop->d_states(), sizeof(RepState) * n, hipMemcpyDeviceToHost, pop->stream);
+    hipError_t e = launch_census(pop->d_descs(), pop->d_states(), pop->d_partials(), n, pop->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s.data(), pop->d_states(), sizeof(RepState) * n, hipMemcpyDeviceToHost, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(stats)");
     st = sync_stream(pop);
     if (st != SPEGG_OK) return st;
-    for (uint32_t i = 0; i < n; ++i) host_out[i] = s[i].stats;
+    for (uint32_t i = 0; i < n; ++i) host_out[i] = census_of(s[i]);
     return SPEGG_OK;
 }
 
@@ -550,7 +572,7 @@ spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, u
                            pop->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(pop->d_states() + rep, &s0, sizeof s0, hipMemcpyHostToDevice, pop->stream);
-    if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + rep, pop->d_states() + rep, h, n, buf, pop->stream);
+    if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + rep, pop->d_states() + rep, n, buf, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "write_genomes");
     return sync_stream(pop);
 }
@@ -578,7 +600,7 @@ spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t *host_i
     DeviceGuard guard(pop->device);
     RepState s;
     if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
-    const uint32_t m = s.stats.n_survivors;
+    const uint32_t m = s.n_surv;
     if (n_out) *n_out = m;
     if (m == 0) return SPEGG_OK;
     if (!host_idx || n < m) return fail(SPEGG_E_INVALID, "read_survivors: need room for %u indices", m);

@@ -36,6 +36,7 @@ constexpr double kSkipBelow = 0.17;  // r < 0.17: geometric gaps; above: bit-ser
 
 constexpr int kBlock = 256;          // threads per block in every kernel
 constexpr int kSurvTile = 256;       // adults per survival / compaction tile
+constexpr int kCensusSlots = 16;     // census sums are spread over this many atomic slots
 
 struct RepDesc {
     uint32_t L, W, cap, regime;
@@ -49,8 +50,8 @@ struct RepDesc {
     uint32_t unit_effects;
     uint32_t tail_mask;  // valid bits of word W-1
     uint32_t surv_tile0, surv_ntiles;
-    uint32_t off_tile0, off_ntiles, off_per_tile;
-    uint32_t pad0;
+    uint32_t off_tile0, off_ntiles, off_per_tile;  // offspring tiles: global index of the first
+    float geo_scale;     // 1 / log2(1 - r): first guess of a geometric gap (checked against geo)
     double K, lambda;    // Beverton-Holt density factor; 0 < K enables it
     uint32_t *genome[2];
     int32_t *z[2];
@@ -63,15 +64,20 @@ struct RepDesc {
     const uint32_t *planes;  // 6 x W effect bit-planes: +1,+2,+4 then -1,-2,-4
 };
 
+// Per-replicate state.  A generation reads (t, n), and its scan kernel
+// advances them: t + 1, n = newborns, n_prev = the adults it started from.
 struct RepState {
-    uint32_t t;       // generation of the current adults
-    uint32_t n;       // N_t
-    uint32_t n_surv;  // survivors of the generation in progress
-    uint32_t n_next;  // N_{t+1}
+    uint32_t t;       // generation of the newest census
+    uint32_t n;       // its size
+    uint32_t n_prev;  // adults of the last generation
+    uint32_t n_surv;  // their survivors
     uint32_t extinct;
     uint32_t traced;  // parents of the current newborns were recorded
-    uint64_t near_ties, truncated;
-    spegg_rep_stats stats;
+    uint32_t census_pending;  // census sums still sit in the offspring tiles' partials
+    uint32_t pad0;
+    uint64_t near_ties, truncated, updates, sum_threshold;
+    int64_t sum_z[kCensusSlots];
+    uint64_t sum_z2[kCensusSlots];
 };
 
 struct SurvTile {
@@ -88,41 +94,53 @@ struct OffTile {
     uint32_t rep, start;
 };
 
+// Census sums of one offspring tile.
 struct Partial {
     int64_t sum_z;
     uint64_t sum_z2;
 };
 
-// Offspring-kernel shape for a genome of W words: lanes per offspring
-// (both gametes), a power of two between 4 and 64.
-inline int lanes_per_offspring(uint32_t W) {
-    int g = 2;
-    while (g < (int)W && g < 32) g <<= 1;
-    return 2 * g;
+// Offspring-kernel shape for a genome of W words per haplotype: VPL
+// consecutive words per lane (16- or 8-byte accesses when W allows), G
+// lanes per gamete (a power of two, at most 32; larger genomes loop over
+// chunks of G x VPL words), 2G lanes per newborn.
+struct OffShape {
+    int g, vpl;
+};
+inline OffShape offspring_shape(uint32_t W) {
+    OffShape s;
+    s.vpl = (W % 4 == 0 && W >= 16) ? 4 : (W % 2 == 0) ? 2 : 1;
+    const uint32_t per = W / s.vpl;
+    s.g = 1;
+    while ((uint32_t)s.g < per && s.g < 32) s.g <<= 1;
+    return s;
 }
-inline int offspring_per_tile(int tpo) {
-    int teams = kBlock / tpo;
-    int iters = teams >= 16 ? 1 : 16 / teams;
-    return teams * iters;
+inline int offspring_per_tile(int g) {
+    const int teams = kBlock / (2 * g);
+    return teams >= 16 ? teams : 16;
 }
-inline size_t offspring_lds_bytes(int tpo, uint32_t W) {
+inline size_t offspring_lds_bytes(int g, uint32_t W) {
     // per team and gamete: crossover bitmap and flip bitmap, W words each
-    return (size_t)(kBlock / tpo) * 2u * 2u * W * sizeof(uint32_t);
+    return (size_t)(kBlock / (2 * g)) * 2u * 2u * W * sizeof(uint32_t);
 }
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_init(const RepDesc *d_desc, const RepDesc &h, uint32_t n0, hipStream_t s);
-hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, const RepDesc &h, uint32_t n, uint32_t buf,
-                             hipStream_t s);
-hipError_t launch_survive(const RepDesc *descs, RepState *states, const SurvTile *tiles, SurvCount *counts,
+hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t n, uint32_t buf, hipStream_t s);
+hipError_t launch_survive(const RepDesc *descs, const RepState *states, const SurvTile *tiles, SurvCount *counts,
                           uint32_t ntiles, hipStream_t s);
-hipError_t launch_scan(const RepDesc *descs, RepState *states, SurvCount *counts, uint32_t n_reps, hipStream_t s);
+hipError_t launch_scan(const RepDesc *descs, RepState *states, SurvCount *counts, uint32_t n_reps, int trace,
+                       hipStream_t s);
 hipError_t launch_compact(const RepDesc *descs, const RepState *states, const SurvTile *tiles,
                           const SurvCount *counts, uint32_t ntiles, hipStream_t s);
-hipError_t launch_offspring(int tpo, const RepDesc *descs, RepState *states, const OffTile *tiles, uint32_t tile0,
-                            uint32_t ntiles, Partial *partials, uint32_t grid, size_t lds, int trace, hipStream_t s);
-hipError_t launch_finalize(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,
-                           int trace, hipStream_t s);
+// single_rep >= 0: the class holds only that replicate and its tiles are
+// implicit; otherwise tiles[tile0 .. tile0 + ntiles) lists them.
+hipError_t launch_offspring(OffShape shape, const RepDesc *descs, RepState *states, const OffTile *tiles,
+                            uint32_t tile0, uint32_t ntiles, int single_rep, Partial *partials, uint32_t grid,
+                            size_t lds, int trace, hipStream_t s);
+// Fold pending per-tile census sums into each replicate's state.
+hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,
+                         hipStream_t s);
 hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out, uint32_t n,
                               hipStream_t s);
 

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(PKG, "libspegg.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 WF, POISSON_BH = 0, 1
-KERNEL_NAMES = ["survive", "scan", "compact", "offspring", "finalize"]
+KERNEL_NAMES = ["survive", "scan", "compact", "offspring"]
 
 
 class SpeggError(RuntimeError):
@@ -280,7 +280,7 @@ class Population:
                                           C.byref(got)))
         return mom[: got.value], dad[: got.value]
 
-    def set_timing(self, kernels=("survive", "scan", "compact", "offspring", "finalize")):
+    def set_timing(self, kernels=("survive", "scan", "compact", "offspring")):
         """Bracket the named kernels with HIP events (empty: stop)."""
         mask = 0
         for k in kernels:

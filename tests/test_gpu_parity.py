@@ -69,6 +69,12 @@ CASES = [
     ("pois-no-K", dict(regime=1, n_loci=40, r=0.5, mu=0.0, omega=5.0, K=0.0, fecundity=1.5, capacity=5000), 4),
     ("extinction", dict(regime=0, n_loci=64, r=0.5, mu=0.0, omega=0.3, theta=500.0), 3),
     ("n-one", dict(regime=0, n_loci=70, r=0.2, mu=0.05, omega=0.0, n0=1, capacity=1), 3),
+    # kernel shapes: 8-byte lanes (L=256), chunked genomes (L=8192, 16384), odd word count (L=4000)
+    ("wf-lazy-L256", dict(regime=0, n_loci=256, r=0.2, mu=1e-3, omega=10.0), 3),
+    ("wf-skip-L8192-chunks", dict(regime=0, n_loci=8192, r=0.002, mu=1e-4, omega=60.0, n0=120), 2),
+    ("wf-raw-L4000-odd-words", dict(regime=0, n_loci=4000, r=0.5, mu=1e-4, omega=50.0, n0=80), 2),
+    ("pois-lazy-L16384", dict(regime=1, n_loci=16384, r=0.3, mu=1e-5, omega=0.0, K=60.0, fecundity=2.0,
+                              n0=40, capacity=120), 2),
 ]
 
 
