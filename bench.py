@@ -72,6 +72,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20, help="untimed generations first")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["scale", "batched"], default="scale",
+                    help="scale: one replicate at scale (default); batched: the 4096-replicate batch")
+    ap.add_argument("--reps", type=int, default=4096, help="replicates of the batched workload")
+    ap.add_argument("--plain-sample", type=int, default=64,
+                    help="batched: replicates timed one at a time for the plain per-replicate loop")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the workload is one replicate "
@@ -81,6 +86,9 @@ def main():
     import torch
 
     from paper_1603_09255_amd import spegg, workloads
+
+    if args.workload == "batched":
+        return bench_batched(args)
 
     desc, _ = workloads.plain_scale(seed=1)
     L = desc["n_loci"]
@@ -92,10 +100,7 @@ def main():
     pop.step(args.warmup)
     torch.cuda.synchronize()
 
-    # Timed region: K generations; the offspring kernel is bracketed by HIP
-    # events on the population's stream.
-    pop.set_timing(["offspring"])
-    pop.kernel_times()
+    # Timed region: K generations, nothing but the generation launches.
     s0 = pop.stats()[0]
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} generations")
@@ -104,19 +109,15 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     s1 = pop.stats()[0]
-    kt = pop.kernel_times()
-    pop.set_timing([])
     elapsed = t1 - t0
     updates = s1["updates"] - s0["updates"]
     value = updates / elapsed
-    off_ms, off_n = kt["offspring"]
-    per_launch_bytes = updates / max(off_n, 1) * bytes_per_update(L)
-    avg_launch_s = off_ms / 1e3 / max(off_n, 1)
-    achieved = per_launch_bytes / avg_launch_s / 1e9
-    log(f"bench: {updates} updates in {elapsed * 1e3:.2f} ms; offspring kernel avg {avg_launch_s * 1e6:.2f} us "
-        f"x {off_n}; N now {s1['n']}")
+    log(f"bench: {updates} updates in {elapsed * 1e3:.2f} ms ({value:.4g}/s); N now {s1['n']}")
 
-    # The same K generations without events, for the event overhead.
+    # Roofline pass: the same number of generations with the offspring
+    # kernel bracketed by HIP events on the population's stream.
+    pop.set_timing(["offspring"])
+    pop.kernel_times()
     s0b = pop.stats()[0]
     torch.cuda.synchronize()
     t0b = time.perf_counter()
@@ -124,8 +125,14 @@ def main():
     torch.cuda.synchronize()
     t1b = time.perf_counter()
     s1b = pop.stats()[0]
-    value_plain = (s1b["updates"] - s0b["updates"]) / (t1b - t0b)
-    log(f"bench: without events {value_plain:.4g} updates/s ({(t1b - t0b) * 1e3:.2f} ms)")
+    kt = pop.kernel_times()
+    pop.set_timing([])
+    updates_b = s1b["updates"] - s0b["updates"]
+    off_ms, off_n = kt["offspring"]
+    per_launch_bytes = updates_b / max(off_n, 1) * bytes_per_update(L)
+    avg_launch_s = off_ms / 1e3 / max(off_n, 1)
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    log(f"bench: event pass {(t1b - t0b) * 1e3:.2f} ms; offspring kernel avg {avg_launch_s * 1e6:.2f} us x {off_n}")
     pop.close()
 
     out = {
@@ -149,7 +156,6 @@ def main():
             "n_loci": L,
             "generations_timed": args.steps,
             "mean_census": updates / args.steps / L,
-            "updates_per_s_without_events": value_plain,
         },
         "roofline": {
             "bound": "hbm",
@@ -162,12 +168,91 @@ def main():
             "bytes_per_update": bytes_per_update(L),
             "avg_launch_us": avg_launch_s * 1e6,
             "launches": off_n,
+            "timing": "HIP events around each offspring launch, in a second pass of the same length",
         },
     }
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle sample, about {args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(desc, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """Replicates of uneven N and L advanced together, against the plain
+    per-replicate loop (the same kernels, one replicate at a time, eager
+    launches) on a sample of the same replicates."""
+    import torch
+
+    from paper_1603_09255_amd import spegg, workloads
+
+    reps = workloads.batched_table(n_reps=args.reps)
+    torch.cuda.set_device(0)
+    log(f"bench: creating batch of {len(reps)} replicates")
+    pop = spegg.Population(reps)
+    torch.cuda.synchronize()
+    pop.step(args.warmup)
+    torch.cuda.synchronize()
+    s0 = sum(r["updates"] for r in pop.stats())
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} generations of the batch")
+    t0 = time.perf_counter()
+    pop.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1 = sum(r["updates"] for r in pop.stats())
+    elapsed = t1 - t0
+    updates = s1 - s0
+    value = updates / elapsed
+    log(f"bench: batch {updates} updates in {elapsed:.3f} s ({value:.4g}/s)")
+    pop.set_timing(["offspring"])
+    pop.kernel_times()
+    sb0 = sum(r["updates"] for r in pop.stats())
+    pop.step(min(args.steps, 20))
+    kt = pop.kernel_times()
+    sb1 = sum(r["updates"] for r in pop.stats())
+    pop.set_timing([])
+    pop.close()
+    bpu = sum(workloads_bytes(r) for r in reps) / sum(r["n0"] * r["n_loci"] for r in reps)
+    off_ms, off_n = kt["offspring"]
+    gens_b = min(args.steps, 20)
+    achieved = (sb1 - sb0) * bpu / (off_ms / 1e3) / 1e9
+    # plain per-replicate loop on a sample
+    sample = reps[: args.plain_sample]
+    plain_updates, plain_time = 0, 0.0
+    for d in sample:
+        p = spegg.Population([d])
+        p.set_graph(False)
+        p.step(args.warmup)
+        torch.cuda.synchronize()
+        a0 = p.stats()[0]["updates"]
+        ta = time.perf_counter()
+        p.step(args.steps)
+        torch.cuda.synchronize()
+        plain_time += time.perf_counter() - ta
+        plain_updates += p.stats()[0]["updates"] - a0
+        p.close()
+    plain_rate = plain_updates / plain_time
+    log(f"bench: plain loop over {len(sample)} replicates: {plain_rate:.4g} updates/s")
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"batched form: {len(reps)} Wright-Fisher replicates, N ~ U{{500..50000}}, "
+                               "L from {64,256,1024}, mu log-uniform [1e-7,1e-4], r ~ U[0.001,0.5], "
+                               "selection width ~ U[2,16], all advanced together",
+                   "replicates": len(reps), "generations_timed": args.steps,
+                   "plain_loop_updates_per_s": plain_rate, "plain_loop_sample": len(sample),
+                   "speedup_vs_plain_loop": value / plain_rate},
+        "roofline": {"bound": "hbm", "kernel": "offspring", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_update": bpu, "launches": off_n, "generations": gens_b},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def workloads_bytes(d):
+    """Compulsory bytes of one generation of replicate d at its initial census."""
+    return d["n0"] * d["n_loci"] * bytes_per_update(d["n_loci"])
 
 
 if __name__ == "__main__":

@@ -157,6 +157,14 @@ spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, int32_t *host_z
  * generation (indices into the previous adults) into host_idx. */
 spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t *host_idx, size_t n, uint32_t *n_out);
 
+/* Per-locus copies of allele 1 over replicate rep's current census (2N
+ * genes per locus): the genetic distribution behind the phenotypes (Fig. 1F;
+ * Supplementary S2, "Genetics").  counts_dev is caller-owned device scratch
+ * of n_loci uint32 (n_loci must equal the replicate's L); host_counts gets
+ * the result; *n_out = N.  Reads every genome once; waits for the stream. */
+spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t *counts_dev, uint32_t *host_counts,
+                                 uint32_t n_loci, uint32_t *n_out);
+
 /* Record each newborn's mother and father (indices into the previous
  * adults) from the next generation on.  Off by default. */
 spegg_status spegg_set_trace(spegg_pop *pop, int enable);
@@ -166,16 +174,20 @@ spegg_status spegg_set_trace(spegg_pop *pop, int enable);
 spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t *host_mom, uint32_t *host_dad, size_t n,
                                 uint32_t *n_out);
 
+/* Replay generations as captured HIP graphs (enable = 1, the default) or
+ * launch every kernel (0).  Graphs are used only on a non-null stream and
+ * while no kernel timing is on; results are the same either way. */
+spegg_status spegg_set_graph(spegg_pop *pop, int enable);
+
 /* Kernel kinds timed by spegg_set_timing. */
 enum {
-    SPEGG_KERNEL_SURVIVE = 0,   /* step D and the fecundity draw of A */
-    SPEGG_KERNEL_SCAN = 1,      /* per-replicate prefix sums, neonate count, generation advance */
-    SPEGG_KERNEL_COMPACT = 2,   /* step E: the survivor list and slot owners */
-    SPEGG_KERNEL_OFFSPRING = 3, /* steps A (parents), B and C, census sums */
-    SPEGG_KERNEL_KINDS = 4
+    SPEGG_KERNEL_SURVIVE = 0,   /* step D and the offspring count of A */
+    SPEGG_KERNEL_COMPACT = 1,   /* step E: survivor list, offspring slots, census advance */
+    SPEGG_KERNEL_OFFSPRING = 2, /* steps A (parents), B and C, census partials */
+    SPEGG_KERNEL_KINDS = 3
 };
 
-#define SPEGG_TIME_ALL 0xFu
+#define SPEGG_TIME_ALL 0x7u
 
 /* Bracket the kernels of the kinds in kinds_mask (bit k: kind k; 0 stops)
  * launched by later spegg_step_generations calls with HIP events on the

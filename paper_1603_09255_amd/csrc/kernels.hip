@@ -1,18 +1,26 @@
 // Kernels of one generation (main text, Fig. 1) for gfx950.
 //
-//   survive   D + the fecundity draw of A: per adult, p = v(z) s(N), one
-//             Philox word against floor(p 2^32); per-tile counts
-//   scan      per replicate: exclusive prefix sums of the tile counts,
-//             survivor count, neonate count N_{t+1}; advances the
-//             generation and clears the census sums
-//   compact   E: ballot/mbcnt ranks -> ascending survivor list; Poisson
-//             regime: each mother writes her offspring slots
-//   offspring A (parents) + B (gametes: crossover mask, mutation flips)
-//             + C (additive phenotype by popcounts) + census sums; one
-//             team of 2G lanes per newborn, V consecutive words per lane
+//   survive    D + the offspring count of A: per adult p = v(z) s(N), one
+//              Philox word against floor(p 2^32), the Poisson offspring
+//              count of a surviving mother; a fate per adult, counts per tile
+//   compact    E: each tile's prefix is the sum of the counts of the
+//              replicate's earlier tiles; survivor ranks give the ascending
+//              survivor list, kid ranks each mother's offspring slots; tile 0
+//              of each replicate advances the census
+//   offspring  A (parents) + B (gametes: crossover mask, mutation flips)
+//              + C (additive phenotype by popcounts) + census partials; one
+//              team of 2G lanes per newborn, V consecutive words per lane
+//   census     (on demand) folds the partials into the census sums
 //
 // All of it is integer work except p = v s (IEEE double, no contraction),
-// so every result is reproducible bit for bit.
+// so every result is reproducible bit for bit.  No kernel waits on another
+// block of its own launch: blocks communicate only across launches.
+//
+// The census (generation t, size N) is double-buffered per replicate: the
+// current census is the pair with the larger t; compact writes (t + 1,
+// newborns) into the other pair, which no other block of its launch reads.
+// So no kernel argument changes from one generation to the next and
+// generations can be replayed as graphs.
 #include <hip/hip_runtime.h>
 
 #include "philox.h"
@@ -24,6 +32,13 @@ namespace {
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     const uint32_t lane = lane_id();
 #pragma unroll
@@ -31,13 +46,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
         const uint32_t t = __shfl_up(v, o, 64);
         if (lane >= (uint32_t)o) v += t;
     }
-    return v;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
@@ -83,11 +91,10 @@ __device__ __forceinline__ double density_factor(const RepDesc &d, uint32_t n) {
     return 1.0 / (1.0 + (d.lambda - 1.0) * (double)n / d.K);
 }
 
-// Additive contribution sum_l e_l b_l of one haplotype word.
-__device__ __forceinline__ int32_t word_effect(const RepDesc &d, uint32_t w, uint32_t g) {
-    if (d.unit_effects) return (int32_t)__popc(g);
-    const uint32_t *P = d.planes;
-    const uint32_t W = d.W;
+// Additive contribution sum_l e_l b_l of one haplotype word; P holds the six
+// effect bit-planes (+1, +2, +4, -1, -2, -4), W words each.
+__device__ __forceinline__ int32_t word_effect(bool unit, const uint32_t *P, uint32_t W, uint32_t w, uint32_t g) {
+    if (unit) return (int32_t)__popc(g);
     return (int32_t)__popc(g & P[w]) + 2 * (int32_t)__popc(g & P[W + w]) + 4 * (int32_t)__popc(g & P[2 * W + w]) -
            (int32_t)__popc(g & P[3 * W + w]) - 2 * (int32_t)__popc(g & P[4 * W + w]) -
            4 * (int32_t)__popc(g & P[5 * W + w]);
@@ -137,7 +144,7 @@ __device__ __forceinline__ uint32_t geometric_gap(const RepDesc &d, uint32_t x) 
     const float guess = lg * d.geo_scale;
     uint32_t g = guess >= (float)len ? len : (guess > 0.0f ? (uint32_t)guess : 0u);
     const uint64_t *T = d.geo;
-    const uint64_t below = g > 0 ? T[g - 1] : 0ull;   // both checks load at once
+    const uint64_t below = g > 0 ? T[g - 1] : 0ull;  // both checks load at once
     const uint64_t above = g < len ? T[g] : kAlways;
     if (below > (uint64_t)x || above <= (uint64_t)x) {
         while (g > 0 && T[g - 1] > (uint64_t)x) --g;
@@ -171,6 +178,11 @@ __device__ __forceinline__ uint32_t lazy_block(const Rng &rng, uint32_t j, uint3
     return hit;
 }
 
+// Index of the current census pair: the one with the larger generation.
+__device__ __forceinline__ uint32_t current_pair(const RepState &st) {
+    return (int32_t)(st.t[1] - st.t[0]) > 0 ? 1u : 0u;
+}
+
 // ---------------------------------------------------------------- init
 
 __global__ void __launch_bounds__(kBlock) init_kernel(const RepDesc *__restrict__ desc, uint32_t n0) {
@@ -194,7 +206,9 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
     if (i < n) {
         const uint32_t *g = d.genome[buf] + (size_t)i * 2u * d.W;
         int32_t acc = 0;
-        for (uint32_t w = 0; w < d.W; ++w) acc += word_effect(d, w, g[w]) + word_effect(d, w, g[d.W + w]);
+        for (uint32_t w = 0; w < d.W; ++w)
+            acc += word_effect(d.unit_effects, d.planes, d.W, w, g[w]) +
+                   word_effect(d.unit_effects, d.planes, d.W, w, g[d.W + w]);
         z = (int64_t)acc - d.sum_e;
         d.z[buf][i] = (int32_t)z;
     }
@@ -209,180 +223,195 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
 
 // ---------------------------------------------------------------- survive
 
+// One block per tile of kSurvTile adults; thread x holds the kSurvItems
+// consecutive adults from tile start + x kSurvItems (z and fate buffers are
+// padded to whole tiles, so the vector accesses stay inside).
 __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restrict__ descs,
                                                          const RepState *__restrict__ states,
                                                          const SurvTile *__restrict__ tiles,
                                                          SurvCount *__restrict__ counts) {
-    __shared__ uint32_t sh_u[3][kBlock / 64];
+    constexpr uint32_t IT = kSurvItems;
+    __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_n[kBlock / 64];
     __shared__ uint64_t sh_t[kBlock / 64];
+    __shared__ uint64_t sh_pois[kPoissonTableCap];
     const SurvTile tile = tiles[blockIdx.x];
     const RepDesc &d = descs[tile.rep];
     const RepState &st = states[tile.rep];
-    const uint32_t n = st.n, t = st.t;
-    const uint32_t i = tile.start + threadIdx.x;
-    uint32_t alive = 0, kids = 0, near = 0;
-    uint64_t thr = 0;
-    if (i < n) {
-        const int32_t z = d.z[t & 1u][i];
-        const double v = d.vtab ? d.vtab[z - d.zmin] : 1.0;
-        const double p = v * density_factor(d, n);
-        thr = p >= 1.0 ? kAlways : (p > 0.0 ? (uint64_t)floor(p * 4294967296.0) : 0ull);
-        const Rng rng{d.key0, d.key1, d.c3};
-        const uint32_t x = rng.block(i, kStSurvive, 0, t).v[0];
-        alive = (uint64_t)x < thr;
-        near = (p > 0.0 && p < 1.0 && fabs((double)x * (1.0 / 4294967296.0) - p) < 1e-6) ? 1u : 0u;
-        if (alive && d.regime == SPEGG_POISSON_BH) {
-            const uint32_t xf = rng.block(i, kStFecund, 0, t).v[0];
-            kids = table_draw(d.pois, d.pois_len, xf);
-        }
-        d.fate[i] = (uint16_t)(alive ? (0x8000u | kids) : 0u);
+    const uint32_t par = current_pair(st);
+    const uint32_t t = st.t[par], n = st.n[par];
+    // beyond the census: uniform over the block; tile 0 always records the census
+    if (tile.start >= n && tile.start != 0) return;
+    const bool poisson = d.regime == SPEGG_POISSON_BH;
+    if (poisson) {
+        for (uint32_t q = threadIdx.x; q < d.pois_len; q += kBlock) sh_pois[q] = d.pois[q];
+        __syncthreads();
     }
+    const uint32_t i0 = tile.start + threadIdx.x * IT;
+    const double s = density_factor(d, n);
+    const Rng rng{d.key0, d.key1, d.c3};
+    const Words<IT> zw = load_words<IT>(reinterpret_cast<const uint32_t *>(d.z[t & 1u]) + i0);
+    double v[IT];
+#pragma unroll
+    for (uint32_t q = 0; q < IT; ++q) v[q] = (d.vtab && i0 + q < n) ? d.vtab[(int32_t)zw.v[q] - d.zmin] : 1.0;
+    uint32_t fate[IT], a_loc = 0, k_loc = 0, near = 0;
+    uint64_t thr_sum = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < IT; ++q) {
+        const uint32_t i = i0 + q;
+        fate[q] = 0;
+        if (i < n) {
+            const double p = v[q] * s;
+            const uint64_t thr = p >= 1.0 ? kAlways : (p > 0.0 ? (uint64_t)floor(p * 4294967296.0) : 0ull);
+            const uint32_t x = rng.block(i, kStSurvive, 0, t).v[0];
+            thr_sum += thr;
+            near += (p > 0.0 && p < 1.0 && fabs((double)x * (1.0 / 4294967296.0) - p) < 1e-6) ? 1u : 0u;
+            if ((uint64_t)x < thr) {
+                uint32_t kids = 0;
+                if (poisson) kids = table_draw(sh_pois, d.pois_len, rng.block(i, kStFecund, 0, t).v[0]);
+                fate[q] = 0x8000u | kids;
+                ++a_loc;
+                k_loc += kids;
+            }
+        }
+    }
+    // fates of the thread's adults, one 8-byte store
+    uint16_t *fp = d.fate + i0;
+    *reinterpret_cast<uint2 *>(fp) = make_uint2(fate[0] | (fate[1] << 16), fate[2] | (fate[3] << 16));
     const uint32_t wave = threadIdx.x >> 6;
-    const uint64_t ballot = __ballot(alive);
-    const uint32_t k = wave_sum<uint32_t>(kids), nr = wave_sum<uint32_t>(near);
-    const uint64_t ts = wave_sum<uint64_t>(thr);
+    const uint32_t wa = wave_sum<uint32_t>(a_loc), wk = wave_sum<uint32_t>(k_loc), wn = wave_sum<uint32_t>(near);
+    const uint64_t wt = wave_sum<uint64_t>(thr_sum);
     if (lane_id() == 0) {
-        sh_u[0][wave] = (uint32_t)__popcll(ballot);
-        sh_u[1][wave] = k;
-        sh_u[2][wave] = nr;
-        sh_t[wave] = ts;
+        sh_a[wave] = wa;
+        sh_k[wave] = wk;
+        sh_n[wave] = wn;
+        sh_t[wave] = wt;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         SurvCount c{};
         for (int w = 0; w < kBlock / 64; ++w) {
-            c.alive += sh_u[0][w];
-            c.kids += sh_u[1][w];
-            c.near += sh_u[2][w];
+            c.alive += sh_a[w];
+            c.kids += sh_k[w];
+            c.near += sh_n[w];
             c.sum_t += sh_t[w];
         }
+        c.par = par;
+        c.t = t;
+        c.n = n;
         counts[blockIdx.x] = c;
     }
 }
 
-// ---------------------------------------------------------------- scan
+// ---------------------------------------------------------------- compact
 
-// One block per replicate: offsets of every survival tile, neonate count,
-// and the advance of the replicate to the next generation.
-__global__ void __launch_bounds__(kBlock) scan_kernel(const RepDesc *__restrict__ descs,
-                                                      RepState *__restrict__ states,
-                                                      SurvCount *__restrict__ counts, int trace) {
-    constexpr int PER = 4;  // tiles per thread per pass, loaded together
-    __shared__ uint32_t sh[2][kBlock / 64];
-    __shared__ uint64_t sh64[2][kBlock / 64];
-    const uint32_t rep = blockIdx.x;
-    const RepDesc &d = descs[rep];
-    RepState &st = states[rep];
-    const uint32_t ntiles = d.surv_ntiles;
-    SurvCount *c = counts + d.surv_tile0;
-    uint32_t alive_carry = 0;
-    uint64_t kid_carry = 0, near_sum = 0, t_sum = 0;
-    for (uint32_t base = 0; base < ntiles; base += kBlock * PER) {
-        const uint32_t k0 = base + threadIdx.x * PER;
-        uint32_t a[PER], kk[PER], ta = 0, tk = 0;
-        uint64_t nr = 0, ts = 0;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const bool ok = k0 + q < ntiles;
-            const SurvCount v = ok ? c[k0 + q] : SurvCount{};
-            a[q] = v.alive;
-            kk[q] = v.kids;
-            ta += v.alive;
-            tk += v.kids;
-            nr += v.near;
-            ts += v.sum_t;
-        }
-        uint32_t tot_a, tot_k;
-        const uint32_t ea = block_excl_scan(ta, sh[0], &tot_a);
-        const uint32_t ek = block_excl_scan(tk, sh[1], &tot_k);
-        uint32_t ra = alive_carry + ea;
-        uint64_t rk = kid_carry + ek;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            if (k0 + q < ntiles) {
-                c[k0 + q].alive_off = ra;
-                c[k0 + q].kid_off = rk > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)rk;
-            }
-            ra += a[q];
-            rk += kk[q];
-        }
-        alive_carry += tot_a;
-        kid_carry += tot_k;
-        nr = wave_sum<uint64_t>(nr);
-        ts = wave_sum<uint64_t>(ts);
-        if (lane_id() == 0) {
-            sh64[0][threadIdx.x >> 6] = nr;
-            sh64[1][threadIdx.x >> 6] = ts;
-        }
-        __syncthreads();
-        for (int w = 0; w < kBlock / 64; ++w) {
-            near_sum += sh64[0][w];
-            t_sum += sh64[1][w];
-        }
-        __syncthreads();
+// One block per tile: its prefix is summed from the counts of the
+// replicate's earlier tiles (written by survive, a launch earlier), then
+// block ranks place its survivors and its mothers' offspring slots.  Tile 0
+// of each replicate sums all the tiles and advances the census.
+__global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restrict__ descs,
+                                                         RepState *__restrict__ states,
+                                                         const SurvTile *__restrict__ tiles,
+                                                         const SurvCount *__restrict__ counts, int trace) {
+    constexpr uint32_t IT = kSurvItems;
+    __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64];
+    __shared__ uint64_t sh_kk[kBlock / 64], sh_n[kBlock / 64], sh_t[kBlock / 64];
+    const SurvTile tile = tiles[blockIdx.x];
+    const RepDesc &d = descs[tile.rep];
+    RepState &st = states[tile.rep];
+    const SurvCount *C = counts + d.surv_tile0;
+    // the census this generation started from, as survive recorded it: tile 0
+    // of this launch rewrites the state's other pair
+    const SurvCount c0 = C[0];
+    const uint32_t par = c0.par, t = c0.t, n = c0.n;
+    const uint32_t k = blockIdx.x - d.surv_tile0;  // tile index within the replicate
+    const uint32_t active = (n + kSurvTile - 1) / kSurvTile;
+    if (k >= active && k != 0) return;  // beyond the census: uniform over the block
+    const uint32_t wave = threadIdx.x >> 6;
+
+    // exclusive prefix of this tile (tile 0: the totals as well)
+    const uint32_t span = k == 0 ? active : k;
+    uint32_t pa = 0;
+    uint64_t pk = 0, pn = 0, pt = 0;
+    for (uint32_t q = threadIdx.x; q < span; q += kBlock) {
+        const SurvCount c = C[q];
+        pa += c.alive;
+        pk += c.kids;
+        pn += c.near;
+        pt += c.sum_t;
     }
-    if (threadIdx.x < kCensusSlots) {
-        st.sum_z[threadIdx.x] = 0;
-        st.sum_z2[threadIdx.x] = 0;
+    pa = wave_sum<uint32_t>(pa);
+    pk = wave_sum<uint64_t>(pk);
+    pn = wave_sum<uint64_t>(pn);
+    pt = wave_sum<uint64_t>(pt);
+    if (lane_id() == 0) {
+        sh_a[wave] = pa;
+        sh_kk[wave] = pk;
+        sh_n[wave] = pn;
+        sh_t[wave] = pt;
     }
-    if (threadIdx.x == 0) {
-        const uint32_t n = st.n, ns = alive_carry;
+    __syncthreads();
+    uint32_t sum_a = 0;
+    uint64_t sum_k = 0, sum_n = 0, sum_t = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        sum_a += sh_a[w];
+        sum_k += sh_kk[w];
+        sum_n += sh_n[w];
+        sum_t += sh_t[w];
+    }
+    __syncthreads();
+
+    if (k == 0 && threadIdx.x == 0) {
+        // census of the newborns, into the pair the other blocks do not read
+        const uint32_t ns = sum_a;
         uint32_t nn;
         if (ns == 0) {
             nn = 0;
         } else if (d.regime == SPEGG_WF) {
             nn = n;
         } else {
-            nn = kid_carry > d.cap ? d.cap : (uint32_t)kid_carry;
-            st.truncated += kid_carry - nn;
+            nn = sum_k > d.cap ? d.cap : (uint32_t)sum_k;
+            st.truncated += sum_k - nn;
         }
         st.n_prev = n;
         st.n_surv = ns;
-        st.n = nn;
-        st.t += 1;
+        st.t[par ^ 1u] = t + 1;
+        st.n[par ^ 1u] = nn;
         if (nn == 0) st.extinct = 1;
         st.traced = trace ? 1u : 0u;
         st.census_pending = 1;
-        st.near_ties += near_sum;
-        st.sum_threshold = t_sum;
+        st.near_ties += sum_n;
+        st.sum_threshold = sum_t;
         st.updates += (uint64_t)nn * d.L;
     }
-}
+    if (k >= active) return;  // tile 0 of an empty census: uniform over the block
+    const uint32_t aoff = k == 0 ? 0u : sum_a;
+    const uint64_t koff = k == 0 ? 0ull : sum_k;
 
-// ---------------------------------------------------------------- compact
-
-__global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restrict__ descs,
-                                                         const RepState *__restrict__ states,
-                                                         const SurvTile *__restrict__ tiles,
-                                                         const SurvCount *__restrict__ counts) {
-    __shared__ uint32_t sh_a[kBlock / 64];
-    __shared__ uint32_t sh_k[kBlock / 64];
-    const SurvTile tile = tiles[blockIdx.x];
-    const RepDesc &d = descs[tile.rep];
-    const RepState &st = states[tile.rep];
-    const uint32_t n = st.n_prev;  // the adults this generation started from
-    if (tile.start >= n) return;   // uniform over the block
-    const uint32_t i = tile.start + threadIdx.x;
-    const uint32_t f = i < n ? d.fate[i] : 0u;
-    const uint32_t alive = f >> 15, kids = f & 0x7FFFu;
-    // survivor rank: ballot within the wave, wave totals through LDS
-    const uint32_t wave = threadIdx.x >> 6;
-    const uint64_t ballot = __ballot(alive);
-    const uint32_t rank_in_wave = __builtin_amdgcn_mbcnt_hi((uint32_t)(ballot >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
-    if (lane_id() == 0) sh_a[wave] = (uint32_t)__popcll(ballot);
-    uint32_t ktot;
-    const uint32_t kid_rank = block_excl_scan(kids, sh_k, &ktot);  // contains __syncthreads
-    uint32_t wave_off = 0;
-    for (uint32_t w = 0; w < wave; ++w) wave_off += sh_a[w];
-    const SurvCount c = counts[blockIdx.x];
-    if (alive) d.S[c.alive_off + wave_off + rank_in_wave] = i;
-    if (d.regime == SPEGG_POISSON_BH && kids) {
-        const uint32_t nn = st.n;
-        const uint64_t slot0 = (uint64_t)c.kid_off + kid_rank;
-        for (uint32_t m = 0; m < kids; ++m) {
-            const uint64_t slot = slot0 + m;
-            if (slot < nn) d.owner[slot] = i;
+    // survivor and slot ranks of the thread's adults, ascending order
+    const uint32_t i0 = tile.start + threadIdx.x * IT;
+    const uint2 fw = *reinterpret_cast<const uint2 *>(d.fate + i0);
+    uint32_t fate[IT] = {fw.x & 0xFFFFu, fw.x >> 16, fw.y & 0xFFFFu, fw.y >> 16};
+    uint32_t a_loc = 0, k_loc = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < IT; ++q) {
+        if (i0 + q >= n) fate[q] = 0;
+        a_loc += fate[q] >> 15;
+        k_loc += fate[q] & 0x7FFFu;
+    }
+    uint32_t atot, ktot;
+    uint32_t spos = aoff + block_excl_scan(a_loc, sh_a, &atot);
+    uint64_t slot = koff + block_excl_scan(k_loc, sh_k, &ktot);
+#pragma unroll
+    for (uint32_t q = 0; q < IT; ++q) {
+        if (fate[q] >> 15) {
+            if (spos < d.cap) d.S[spos] = i0 + q;
+            ++spos;
+        }
+        if (d.regime == SPEGG_POISSON_BH) {
+            const uint32_t kids = fate[q] & 0x7FFFu;
+            for (uint32_t m = 0; m < kids; ++m, ++slot)
+                if (slot < d.cap) d.owner[slot] = i0 + q;
         }
     }
 }
@@ -390,19 +419,30 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
 // ---------------------------------------------------------------- offspring
 
 // One team of 2G lanes makes one newborn: lanes [0, G) build the maternal
-// gamete (haplotype 0), lanes [G, 2G) the paternal one; in each chunk of
-// G x V words, lane g handles V consecutive words from g x V.
-template <int G, int V>
+// gamete (haplotype 0), lanes [G, 2G) the paternal one.  A gamete's W words
+// are cut into chunks of G x V; in each chunk lane g handles V consecutive
+// words from g x V.  NCH > 0: the gamete is exactly NCH chunks or fewer and
+// all of them are gathered into registers before the crossover mask is
+// drawn; NCH == 0: any number of chunks, gathered one at a time.
+// Dynamic LDS: the effect planes (plane_words) then, per team and gamete,
+// a crossover bitmap and a flip bitmap of W words each.
+template <int G, int V, int NCH>
 __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__restrict__ descs,
-                                                           RepState *__restrict__ states,
+                                                           const RepState *__restrict__ states,
                                                            const OffTile *__restrict__ tiles, uint32_t tile0,
                                                            uint32_t ntiles, int single_rep,
-                                                           Partial *__restrict__ partials, int trace) {
+                                                           Partial *__restrict__ partials, uint32_t plane_words,
+                                                           int trace) {
     constexpr uint32_t TPO = 2 * G;
     constexpr uint32_t TEAMS = kBlock / TPO;
     constexpr uint32_t ITERS = TEAMS >= 16 ? 1 : 16 / TEAMS;
     constexpr uint32_t OPT = TEAMS * ITERS;
     constexpr uint32_t CH = G * V;  // words of one gamete per chunk
+    constexpr int NREG = NCH > 0 ? NCH : 1;
+    // per-newborn draws, one Philox block each, spread over the team:
+    // 0 parents, 1/2 crossover phase (maternal/paternal), 3/4 mutation count
+    constexpr uint32_t NSD = 5;
+    constexpr uint32_t SR = (NSD + TPO - 1) / TPO;
     extern __shared__ uint32_t lds[];
     __shared__ int64_t red_z[kBlock / 64];
     __shared__ uint64_t red_z2[kBlock / 64];
@@ -411,10 +451,12 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
     const uint32_t half = lane / G, gl = lane % G;
     const uint32_t seg0 = lane_id() - gl;  // first wave lane of this gamete's lanes
     const uint32_t segmask = G >= 32 ? 0xFFFFFFFFu : ((1u << G) - 1u);
+    uint32_t *planes = lds;
 
     uint32_t limit = ntiles;
     if (single_rep >= 0) {
-        const uint32_t nn = states[single_rep].n;
+        const RepState &s1 = states[single_rep];
+        const uint32_t nn = s1.n[current_pair(s1)];
         const uint32_t active = (nn + OPT - 1) / OPT;
         limit = active < ntiles ? active : ntiles;
     }
@@ -429,15 +471,22 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             start = tile.start;
         }
         const RepDesc &d = descs[rep];
-        RepState &st = states[rep];
-        const uint32_t nn = st.n;
-        if (start >= nn) continue;  // uniform over the block
-        const uint32_t tp = st.t - 1u, ns = st.n_surv, cur = tp & 1u;
+        const RepState &st = states[rep];
+        const uint32_t newest = current_pair(st);  // the newborns' census, written by this generation's select
+        const uint32_t nn = st.n[newest];
+        if (start >= nn || st.error) continue;  // uniform over the block
+        const uint32_t tp = st.t[newest] - 1u, ns = st.n_surv, cur = tp & 1u;
+        const uint32_t nprev = st.n_prev;
         const uint32_t W = d.W, L = d.L, mode = d.mode;
-        const uint64_t binom0 = d.binom[0];  // most gametes carry no mutation
+        const bool unit = d.unit_effects != 0;
+        const uint64_t binom0 = d.binom0;  // most gametes carry no mutation
         const Rng rng{d.key0, d.key1, d.c3};
-        uint32_t *X = lds + (size_t)(team * 2u + half) * 2u * W;  // crossover toggles
-        uint32_t *F = X + W;                                        // mutation flips
+        if (!unit) {
+            for (uint32_t q = threadIdx.x; q < 6u * W; q += kBlock) planes[q] = d.planes[q];
+            __syncthreads();
+        }
+        uint32_t *X = lds + plane_words + (size_t)(team * 2u + half) * 2u * W;  // crossover toggles
+        uint32_t *F = X + W;                                                     // mutation flips
         int64_t my_z = 0;
         uint64_t my_z2 = 0;
 
@@ -445,28 +494,52 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             const uint32_t j = start + it * TEAMS + team;
             if (j >= nn) continue;  // uniform over the team
 
+            Words4 sd[SR];
+#pragma unroll
+            for (uint32_t r = 0; r < SR; ++r) {
+                const uint32_t kd = lane + r * TPO;
+                const uint32_t stream = kd == 0 ? kStParent : kd <= 2 ? kStRecomb + kd - 1u : kStMutate + kd - 3u;
+                if (kd < NSD) {
+                    sd[r] = rng.block(j, stream, 0, tp);
+                } else {
+                    sd[r].v[0] = sd[r].v[1] = sd[r].v[2] = sd[r].v[3] = 0;
+                }
+            }
+            // word c of draw kd, from the lane of the team that made it
+            auto draw = [&](uint32_t kd, int c) -> uint32_t {
+                return (uint32_t)__shfl((int)sd[kd / TPO].v[c], (int)(kd % TPO), (int)TPO);
+            };
+
             // A: parents, uniform over the survivors (Poisson: the slot's mother)
-            const Words4 pw = rng.block(j, kStParent, 0, tp);
-            const uint32_t mom = d.regime == SPEGG_WF ? d.S[uniform_index(pw.v[0], pw.v[1], ns)] : d.owner[j];
-            const uint32_t dad = d.S[uniform_index(pw.v[2], pw.v[3], ns)];
+            const uint32_t p0 = draw(0, 0), p1 = draw(0, 1), p2 = draw(0, 2), p3 = draw(0, 3);
+            uint32_t mom = d.regime == SPEGG_WF ? d.S[uniform_index(p0, p1, ns)] : d.owner[j];
+            uint32_t dad = d.S[uniform_index(p2, p3, ns)];
+            // parents are adults of the last census; the clamp never changes a
+            // correct index and keeps every gather inside the buffer
+            mom = mom < nprev ? mom : nprev - 1u;
+            dad = dad < nprev ? dad : nprev - 1u;
             const uint32_t *__restrict__ src = d.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
             uint32_t *__restrict__ dst = d.genome[cur ^ 1u] + (size_t)j * 2u * W + (size_t)half * W;
             const uint32_t rs = kStRecomb + half, ms = kStMutate + half;
+            const uint32_t phase_m = draw(1, 0), phase_p = draw(2, 0);
+            const uint32_t xk_m = draw(3, 0), xk_p = draw(4, 0);
 
-            // first chunk of the parent's haplotypes, in flight while the
-            // crossover mask is drawn
-            uint32_t w0 = gl * V;
-            Words<V> h0{}, h1{};
-            if (w0 < W) {
-                h0 = load_words<V>(src + w0);
-                h1 = load_words<V>(src + W + w0);
+            // the parent's haplotypes (all chunks, or the first), in flight
+            // while the crossover mask is drawn
+            Words<V> h0[NREG], h1[NREG];
+#pragma unroll
+            for (int c = 0; c < NREG; ++c) {
+                const uint32_t w0 = (uint32_t)c * CH + gl * V;
+                if (w0 < W) {
+                    h0[c] = load_words<V>(src + w0);
+                    h1[c] = load_words<V>(src + W + w0);
+                }
             }
 
             // B1: crossover toggles.  Boundary b (between loci b-1 and b)
             // toggles the source haplotype from locus b on; bit 0 of word 0
             // holds the phase (which haplotype locus 0 copies).
-            uint32_t phase = 0;
-            if (mode != kModeRaw) phase = rng.block(j, rs, 0, tp).v[0] & 1u;
+            const uint32_t phase = (half ? phase_p : phase_m) & 1u;
             if (mode == kModeSkip) {
                 for (uint32_t w = gl * V; w < W; w += CH)
 #pragma unroll
@@ -505,7 +578,7 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             }
 
             // B2: mutation, K ~ Binomial(L, mu) distinct loci flipped
-            const uint32_t xk = rng.block(j, ms, 0, tp).v[0];
+            const uint32_t xk = half ? xk_p : xk_m;
             const uint32_t K = (uint64_t)xk < binom0 ? 0u : table_draw(d.binom, d.binom_len, xk);
             if (K > 0) {
                 for (uint32_t w = gl * V; w < W; w += CH)
@@ -532,20 +605,16 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             // B3 + C: gamete words, written out; additive phenotype
             int32_t zc = 0;
             uint32_t carry = 0;  // parity of the toggles in earlier chunks
-            for (uint32_t base = 0; base < W; base += CH) {
-                w0 = base + gl * V;
+            auto chunk = [&](uint32_t c, const Words<V> &a, const Words<V> &b) {
+                const uint32_t w0 = c * CH + gl * V;
                 const bool valid = w0 < W;
-                if (base > 0 && valid) {
-                    h0 = load_words<V>(src + w0);
-                    h1 = load_words<V>(src + W + w0);
-                }
                 Words<V> M;
                 if (mode == kModeRaw) {
                     const Words4 blk = rng.block(j, rs, w0 >> 2, tp);
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
-                        const uint32_t c = (w0 + v) & 3u;
-                        M.v[v] = c == 0 ? blk.v[0] : c == 1 ? blk.v[1] : c == 2 ? blk.v[2] : blk.v[3];
+                        const uint32_t q = (w0 + v) & 3u;
+                        M.v[v] = q == 0 ? blk.v[0] : q == 1 ? blk.v[1] : q == 2 ? blk.v[2] : blk.v[3];
                     }
                 } else {
                     uint32_t lane_par = 0;
@@ -575,13 +644,29 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
                     Words<V> g;
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
-                        uint32_t x = (h0.v[v] & ~M.v[v]) | (h1.v[v] & M.v[v]);
+                        uint32_t x = (a.v[v] & ~M.v[v]) | (b.v[v] & M.v[v]);
                         if (K > 0) x ^= F[w0 + v];
                         if (w0 + v == W - 1u) x &= d.tail_mask;
                         g.v[v] = x;
-                        zc += word_effect(d, w0 + v, x);
+                        zc += word_effect(unit, planes, W, w0 + v, x);
                     }
                     store_words<V>(dst + w0, g);
+                }
+            };
+            if constexpr (NCH > 0) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) chunk((uint32_t)c, h0[c], h1[c]);
+            } else {
+                const uint32_t nch = (W + CH - 1) / CH;
+                chunk(0, h0[0], h1[0]);
+                for (uint32_t c = 1; c < nch; ++c) {
+                    const uint32_t w0 = c * CH + gl * V;
+                    Words<V> a{}, b{};
+                    if (w0 < W) {
+                        a = load_words<V>(src + w0);
+                        b = load_words<V>(src + W + w0);
+                    }
+                    chunk(c, a, b);
                 }
             }
 #pragma unroll
@@ -618,6 +703,8 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
     }
 }
 
+// ---------------------------------------------------------------- census
+
 // One block per replicate: sums of the tile partials of the newest census.
 __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restrict__ descs,
                                                         RepState *__restrict__ states,
@@ -628,7 +715,7 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
     RepState &st = states[rep];
     if (!st.census_pending) return;  // uniform over the block
     const RepDesc &d = descs[rep];
-    const uint32_t used = (st.n + d.off_per_tile - 1u) / d.off_per_tile;
+    const uint32_t used = (st.n[current_pair(st)] + d.off_per_tile - 1u) / d.off_per_tile;
     int64_t a = 0;
     uint64_t b = 0;
     for (uint32_t k = threadIdx.x; k < used; k += kBlock) {
@@ -657,6 +744,39 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
     if (threadIdx.x == 0) st.census_pending = 0;
 }
 
+// ---------------------------------------------------------------- allele counts
+
+// Copies of allele 1 at each locus over the current census (2N genes per
+// locus; Fig. 1F, the genetic distribution the environment responds to).
+// Thread (word w, slice of individuals) keeps 32 per-locus counters and adds
+// them once; counts must be zero on entry.
+__global__ void __launch_bounds__(kBlock) allele_count_kernel(const RepDesc *__restrict__ desc,
+                                                              const RepState *__restrict__ state,
+                                                              uint32_t *__restrict__ counts, uint32_t slice) {
+    const RepDesc &d = *desc;
+    const RepState &st = *state;
+    const uint32_t par = current_pair(st);
+    const uint32_t n = st.n[par], buf = st.t[par] & 1u;
+    const uint32_t W = d.W;
+    const uint64_t gid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t w = (uint32_t)(gid % W), sl = (uint32_t)(gid / W);
+    const uint32_t i_begin = sl * slice;
+    if (i_begin >= n) return;
+    const uint32_t i_end = i_begin + slice < n ? i_begin + slice : n;
+    uint32_t c[32];
+#pragma unroll
+    for (int b = 0; b < 32; ++b) c[b] = 0;
+    const uint32_t *g = d.genome[buf];
+    for (uint32_t i = i_begin; i < i_end; ++i) {
+        const uint32_t a = g[(size_t)i * 2u * W + w], b2 = g[(size_t)i * 2u * W + W + w];
+#pragma unroll
+        for (int b = 0; b < 32; ++b) c[b] += ((a >> b) & 1u) + ((b2 >> b) & 1u);
+    }
+    const uint32_t nb = w == W - 1u ? (d.L - 32u * w) : 32u;
+    for (uint32_t b = 0; b < nb; ++b)
+        if (c[b]) atomicAdd(&counts[32u * w + b], c[b]);
+}
+
 __global__ void philox_fill_kernel(uint32_t k0, uint32_t k1, const uint32_t *__restrict__ ctr,
                                    uint32_t *__restrict__ out, uint32_t n) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
@@ -667,35 +787,33 @@ __global__ void philox_fill_kernel(uint32_t k0, uint32_t k1, const uint32_t *__r
 
 inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
 
-struct OffArgs {
-    const RepDesc *descs;
-    RepState *states;
-    const OffTile *tiles;
-    uint32_t tile0, ntiles;
-    int single_rep;
-    Partial *partials;
-    uint32_t grid;
-    size_t lds;
-    int trace;
-    hipStream_t s;
-};
-
-template <int G, int V>
-hipError_t launch_offspring_gv(const OffArgs &a) {
-    hipLaunchKernelGGL((offspring_kernel<G, V>), dim3(a.grid), dim3(kBlock), a.lds, a.s, a.descs, a.states, a.tiles,
-                       a.tile0, a.ntiles, a.single_rep, a.partials, a.trace);
+template <int G, int V, int NCH>
+hipError_t launch_offspring_gvn(const OffArgs &a) {
+    hipLaunchKernelGGL((offspring_kernel<G, V, NCH>), dim3(a.grid), dim3(kBlock), a.lds, a.s, a.descs, a.states,
+                       a.tiles, a.tile0, a.ntiles, a.single_rep, a.partials, a.plane_words, a.trace);
     return hipGetLastError();
 }
 
+template <int G, int V>
+hipError_t launch_offspring_gv(int nch, const OffArgs &a) {
+    switch (nch) {
+    case 0: return launch_offspring_gvn<G, V, 0>(a);
+    case 1: return launch_offspring_gvn<G, V, 1>(a);
+    case 2: return launch_offspring_gvn<G, V, 2>(a);
+    case 4: return launch_offspring_gvn<G, V, 4>(a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int V>
-hipError_t launch_offspring_v(int g, const OffArgs &a) {
+hipError_t launch_offspring_v(int g, int nch, const OffArgs &a) {
     switch (g) {
-    case 1: return launch_offspring_gv<1, V>(a);
-    case 2: return launch_offspring_gv<2, V>(a);
-    case 4: return launch_offspring_gv<4, V>(a);
-    case 8: return launch_offspring_gv<8, V>(a);
-    case 16: return launch_offspring_gv<16, V>(a);
-    case 32: return launch_offspring_gv<32, V>(a);
+    case 1: return launch_offspring_gv<1, V>(nch, a);
+    case 2: return launch_offspring_gv<2, V>(nch, a);
+    case 4: return launch_offspring_gv<4, V>(nch, a);
+    case 8: return launch_offspring_gv<8, V>(nch, a);
+    case 16: return launch_offspring_gv<16, V>(nch, a);
+    case 32: return launch_offspring_gv<32, V>(nch, a);
     default: return hipErrorInvalidValue;
     }
 }
@@ -717,32 +835,22 @@ hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t 
     return hipGetLastError();
 }
 
-hipError_t launch_survive(const RepDesc *descs, const RepState *states, const SurvTile *tiles, SurvCount *counts,
-                          uint32_t ntiles, hipStream_t s) {
-    hipLaunchKernelGGL(survive_kernel, dim3(ntiles), dim3(kBlock), 0, s, descs, states, tiles, counts);
+hipError_t launch_survive(const SelArgs &a) {
+    hipLaunchKernelGGL(survive_kernel, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles, a.counts);
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const RepDesc *descs, RepState *states, SurvCount *counts, uint32_t n_reps, int trace,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(scan_kernel, dim3(n_reps), dim3(kBlock), 0, s, descs, states, counts, trace);
+hipError_t launch_compact(const SelArgs &a) {
+    hipLaunchKernelGGL(compact_kernel, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles, a.counts,
+                       a.trace);
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const RepDesc *descs, const RepState *states, const SurvTile *tiles,
-                          const SurvCount *counts, uint32_t ntiles, hipStream_t s) {
-    hipLaunchKernelGGL(compact_kernel, dim3(ntiles), dim3(kBlock), 0, s, descs, states, tiles, counts);
-    return hipGetLastError();
-}
-
-hipError_t launch_offspring(OffShape shape, const RepDesc *descs, RepState *states, const OffTile *tiles,
-                            uint32_t tile0, uint32_t ntiles, int single_rep, Partial *partials, uint32_t grid,
-                            size_t lds, int trace, hipStream_t s) {
-    const OffArgs a{descs, states, tiles, tile0, ntiles, single_rep, partials, grid, lds, trace, s};
+hipError_t launch_offspring(OffShape shape, const OffArgs &a) {
     switch (shape.vpl) {
-    case 1: return launch_offspring_v<1>(shape.g, a);
-    case 2: return launch_offspring_v<2>(shape.g, a);
-    case 4: return launch_offspring_v<4>(shape.g, a);
+    case 1: return launch_offspring_v<1>(shape.g, shape.nch, a);
+    case 2: return launch_offspring_v<2>(shape.g, shape.nch, a);
+    case 4: return launch_offspring_v<4>(shape.g, shape.nch, a);
     default: return hipErrorInvalidValue;
     }
 }
@@ -750,6 +858,16 @@ hipError_t launch_offspring(OffShape shape, const RepDesc *descs, RepState *stat
 hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,
                          hipStream_t s) {
     hipLaunchKernelGGL(census_kernel, dim3(n_reps), dim3(kBlock), 0, s, descs, states, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_allele_counts(const RepDesc *d_desc, const RepState *d_state, const RepDesc &h, uint32_t n,
+                                uint32_t *counts, hipStream_t s) {
+    constexpr uint32_t kSlice = 256;  // individuals per thread
+    const uint64_t threads = (uint64_t)h.W * ((n + kSlice - 1) / kSlice);
+    if (threads == 0) return hipSuccess;
+    hipLaunchKernelGGL(allele_count_kernel, dim3(blocks_for(threads)), dim3(kBlock), 0, s, d_desc, d_state, counts,
+                       kSlice);
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -30,7 +31,6 @@ spegg_status fail(spegg_status st, const char *fmt, ...) {
 }
 
 constexpr size_t kAlign = 256;
-constexpr int kPoissonCap = 1024;
 constexpr uint32_t kMaxOffspringGrid = 4096;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -63,7 +63,8 @@ struct RepPlan {
 struct OffClass {
     OffShape shape;
     uint32_t tile0, ntiles, grid;
-    int single_rep;  // the class's only replicate, or -1
+    int single_rep;        // the class's only replicate, or -1
+    uint32_t plane_words;  // LDS words for the effect planes (0: unit effects only)
     size_t lds;
 };
 
@@ -76,6 +77,17 @@ struct Plan {
     size_t static_end = 0;  // [0, static_end) is uploaded at create
     size_t surv_counts = 0, partials = 0, total = 0;
 };
+
+// Lanes-per-gamete cap of the offspring kernel.  A tuning knob only:
+// results do not depend on it.  SPEGG_OFFSPRING_GCAP overrides the default.
+int offspring_gcap() {
+    const char *e = std::getenv("SPEGG_OFFSPRING_GCAP");
+    if (e) {
+        const int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32) return v;
+    }
+    return kDefaultGCap;
+}
 
 spegg_status validate(const spegg_rep_desc &d, uint32_t i) {
     if (d.n_loci < 1 || d.n_loci > SPEGG_MAX_LOCI)
@@ -135,11 +147,11 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p) {
     }
     if (!binomial_table(L, d.mu, (int)L + 1, p.binom))
         return fail(SPEGG_E_UNSUPPORTED, "replicate %u: mutation-count table does not close", i);
-    if (d.regime == SPEGG_POISSON_BH && !poisson_table(d.fecundity, kPoissonCap, p.pois))
+    if (d.regime == SPEGG_POISSON_BH && !poisson_table(d.fecundity, kPoissonTableCap, p.pois))
         return fail(SPEGG_E_UNSUPPORTED, "replicate %u: fecundity %g needs more than %d table entries", i,
-                    d.fecundity, kPoissonCap);
+                    d.fecundity, kPoissonTableCap);
     if (p.mode == kModeSkip && L > 1) geometric_table(d.r, L - 1u, p.geo);
-    p.shape = offspring_shape(p.W);
+    p.shape = offspring_shape(p.W, offspring_gcap());
     p.opt = (uint32_t)offspring_per_tile(p.shape.g);
     p.surv_ntiles = (d.capacity + kSurvTile - 1) / kSurvTile;
     p.off_ntiles = (d.capacity + p.opt - 1) / p.opt;
@@ -160,26 +172,34 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
         for (uint32_t k = 0; k < p.surv_ntiles; ++k) P.surv_tiles.push_back({i, k * (uint32_t)kSurvTile});
     }
     // offspring tiles grouped by kernel shape
-    for (int vpl = 1; vpl <= 4; vpl <<= 1)
-        for (int g = 1; g <= 32; g <<= 1) {
-            OffClass c{{g, vpl}, (uint32_t)P.off_tiles.size(), 0, 0, -1, 0};
-            uint32_t maxW = 0, members = 0, last = 0;
-            for (uint32_t i = 0; i < n; ++i) {
-                RepPlan &p = P.reps[i];
-                if (p.shape.g != g || p.shape.vpl != vpl) continue;
-                p.off_tile0 = (uint32_t)P.off_tiles.size();
-                for (uint32_t k = 0; k < p.off_ntiles; ++k) P.off_tiles.push_back({i, k * p.opt});
-                if (p.W > maxW) maxW = p.W;
-                ++members;
-                last = i;
-            }
-            c.ntiles = (uint32_t)P.off_tiles.size() - c.tile0;
-            if (c.ntiles == 0) continue;
-            c.single_rep = members == 1 ? (int)last : -1;
-            c.grid = c.ntiles < kMaxOffspringGrid ? c.ntiles : kMaxOffspringGrid;
-            c.lds = offspring_lds_bytes(g, maxW);
-            P.classes.push_back(c);
+    std::vector<OffShape> shapes;
+    for (uint32_t i = 0; i < n; ++i) {
+        const OffShape sh = P.reps[i].shape;
+        bool seen = false;
+        for (const OffShape &x : shapes) seen |= x.g == sh.g && x.vpl == sh.vpl && x.nch == sh.nch;
+        if (!seen) shapes.push_back(sh);
+    }
+    for (const OffShape &sh : shapes) {
+        OffClass c{sh, (uint32_t)P.off_tiles.size(), 0, 0, -1, 0, 0};
+        uint32_t maxW = 0, members = 0, last = 0;
+        bool planes = false;
+        for (uint32_t i = 0; i < n; ++i) {
+            RepPlan &p = P.reps[i];
+            if (p.shape.g != sh.g || p.shape.vpl != sh.vpl || p.shape.nch != sh.nch) continue;
+            p.off_tile0 = (uint32_t)P.off_tiles.size();
+            for (uint32_t k = 0; k < p.off_ntiles; ++k) P.off_tiles.push_back({i, k * p.opt});
+            if (p.W > maxW) maxW = p.W;
+            planes |= !p.unit;
+            ++members;
+            last = i;
         }
+        c.ntiles = (uint32_t)P.off_tiles.size() - c.tile0;
+        c.single_rep = members == 1 ? (int)last : -1;
+        c.grid = c.ntiles < kMaxOffspringGrid ? c.ntiles : kMaxOffspringGrid;
+        c.plane_words = planes ? 6u * maxW : 0u;
+        c.lds = c.plane_words * sizeof(uint32_t) + offspring_lds_bytes(sh.g, maxW);
+        P.classes.push_back(c);
+    }
     Carver cv;
     P.descs = cv.take(sizeof(RepDesc) * n);
     P.states = cv.take(sizeof(RepState) * n);
@@ -202,9 +222,11 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
         const size_t gbytes = cap * 2u * p.W * sizeof(uint32_t);
         p.genome[0] = cv.take(gbytes);
         p.genome[1] = cv.take(gbytes);
-        p.z[0] = cv.take(cap * sizeof(int32_t));
-        p.z[1] = cv.take(cap * sizeof(int32_t));
-        p.fate = cv.take(cap * sizeof(uint16_t));
+        // phenotypes padded to whole select tiles (read as vectors)
+        const size_t zcap = ((cap + kSurvTile - 1) / kSurvTile) * kSurvTile;
+        p.z[0] = cv.take(zcap * sizeof(int32_t));
+        p.z[1] = cv.take(zcap * sizeof(int32_t));
+        p.fate = cv.take(zcap * sizeof(uint16_t));
         p.S = cv.take(cap * sizeof(uint32_t));
         if (reps[i].regime == SPEGG_POISSON_BH) p.owner = cv.take(cap * sizeof(uint32_t));
         p.mom = cv.take(cap * sizeof(uint32_t));
@@ -223,6 +245,20 @@ struct Timed {
     int kind;
     hipEvent_t a, b;
 };
+
+// An instantiated graph of a fixed number of generations.
+struct GenGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+};
+
+constexpr uint32_t kGraphGenerations = 16;  // generations per replay of the long graph
 
 struct DeviceGuard {
     int prev = -1;
@@ -251,6 +287,12 @@ struct spegg_pop {
     bool errored = false;
     bool trace = false;
     uint32_t timing = 0;  // mask of kernel kinds bracketed by events
+    bool use_graph = true;        // replay captured generations when the stream allows
+    GenGraph graph_one, graph_many;  // captured with the trace setting below
+    void drop_graphs() {
+        graph_one.release();
+        graph_many.release();
+    }
     std::vector<Timed> pending;
     std::vector<hipEvent_t> event_pool;
     double ms[SPEGG_KERNEL_KINDS] = {0};
@@ -304,20 +346,24 @@ hipError_t timed(spegg_pop *pop, int kind, F &&f) {
     return hipSuccess;
 }
 
+// A census (t, n) in pair 0; pair 1 one generation older and empty.
 RepState initial_state(uint32_t t, uint32_t n) {
     RepState s;
     std::memset(&s, 0, sizeof s);
-    s.t = t;
-    s.n = n;
+    s.t[0] = t;
+    s.n[0] = n;
+    s.t[1] = t - 1u;
+    s.n[1] = 0;
     s.extinct = n == 0;
     return s;
 }
 
 spegg_rep_stats census_of(const RepState &s) {
+    const uint32_t par = current_pair_host(s);
     spegg_rep_stats c;
     std::memset(&c, 0, sizeof c);
-    c.generation = s.t;
-    c.n = s.n;
+    c.generation = s.t[par];
+    c.n = s.n[par];
     c.n_parents = s.n_prev;
     c.n_survivors = s.n_surv;
     c.extinct = s.extinct;
@@ -349,6 +395,46 @@ spegg_status check_rep(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t sp
     if (patch != 0 || species != 0)
         return fail(SPEGG_E_UNSUPPORTED, "one patch and one species per replicate in this build");
     return SPEGG_OK;
+}
+
+// The launches of n generations on the population's stream.
+hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
+    Plan &P = pop->plan;
+    const uint32_t ns_tiles = (uint32_t)P.surv_tiles.size();
+    const int trace = pop->trace ? 1 : 0;
+    for (uint32_t g = 0; g < n; ++g) {
+        const SelArgs sa{pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), pop->d_surv_counts(), ns_tiles, trace,
+                         pop->stream};
+        hipError_t e = timed(pop, SPEGG_KERNEL_SURVIVE, [&] { return launch_survive(sa); });
+        if (e == hipSuccess) e = timed(pop, SPEGG_KERNEL_COMPACT, [&] { return launch_compact(sa); });
+        for (const OffClass &c : P.classes) {
+            if (e != hipSuccess) return e;
+            const OffArgs oa{pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0, c.ntiles, c.single_rep,
+                             pop->d_partials(), c.plane_words, c.grid, c.lds, trace, pop->stream};
+            e = timed(pop, SPEGG_KERNEL_OFFSPRING, [&] { return launch_offspring(c.shape, oa); });
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Capture n generations (with the current trace setting) as a graph.
+hipError_t capture(spegg_pop *pop, uint32_t n, GenGraph &g) {
+    g.release();
+    hipError_t e = hipStreamBeginCapture(pop->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t le = enqueue_generations(pop, n);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(pop->stream, &graph);
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return le;
+    }
+    if (e != hipSuccess) return e;
+    g.graph = graph;
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) g.release();
+    return e;
 }
 
 }  // namespace
@@ -415,6 +501,7 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.R = p.R;
         h.geo_len = (uint32_t)p.geo.size();
         h.binom_len = (uint32_t)p.binom.size();
+        h.binom0 = p.binom[0];
         h.pois_len = (uint32_t)p.pois.size();
         h.zmin = p.zmin;
         h.zlen = p.zlen;
@@ -483,34 +570,33 @@ spegg_status spegg_step_generations(spegg_pop *pop, uint32_t n_generations) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
     DeviceGuard guard(pop->device);
-    Plan &P = pop->plan;
-    const uint32_t ns_tiles = (uint32_t)P.surv_tiles.size();
-    const int trace = pop->trace ? 1 : 0;
-    for (uint32_t g = 0; g < n_generations; ++g) {
-        hipError_t e = timed(pop, SPEGG_KERNEL_SURVIVE, [&] {
-            return launch_survive(pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), pop->d_surv_counts(),
-                                  ns_tiles, pop->stream);
-        });
-        if (e == hipSuccess)
-            e = timed(pop, SPEGG_KERNEL_SCAN, [&] {
-                return launch_scan(pop->d_descs(), pop->d_states(), pop->d_surv_counts(), pop->n_reps, trace,
-                                   pop->stream);
-            });
-        if (e == hipSuccess)
-            e = timed(pop, SPEGG_KERNEL_COMPACT, [&] {
-                return launch_compact(pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), pop->d_surv_counts(),
-                                      ns_tiles, pop->stream);
-            });
-        for (const OffClass &c : P.classes) {
-            if (e != hipSuccess) break;
-            e = timed(pop, SPEGG_KERNEL_OFFSPRING, [&] {
-                return launch_offspring(c.shape, pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0,
-                                        c.ntiles, c.single_rep, pop->d_partials(), c.grid, c.lds, trace,
-                                        pop->stream);
-            });
+    // Graph replay needs a capturable stream and no per-launch events.
+    const bool graphs = pop->use_graph && pop->stream != nullptr && pop->timing == 0;
+    uint32_t done = 0;
+    if (graphs) {
+        hipError_t e = hipSuccess;
+        while (e == hipSuccess && n_generations - done >= kGraphGenerations) {
+            if (!pop->graph_many.exec) e = capture(pop, kGraphGenerations, pop->graph_many);
+            if (e == hipSuccess) e = hipGraphLaunch(pop->graph_many.exec, pop->stream);
+            done += kGraphGenerations;
         }
-        if (e != hipSuccess) return device_fail(pop, e, "generation launch");
+        while (e == hipSuccess && done < n_generations) {
+            if (!pop->graph_one.exec) e = capture(pop, 1, pop->graph_one);
+            if (e == hipSuccess) e = hipGraphLaunch(pop->graph_one.exec, pop->stream);
+            ++done;
+        }
+        if (e != hipSuccess) return device_fail(pop, e, "generation graph");
+        return SPEGG_OK;
     }
+    const hipError_t e = enqueue_generations(pop, n_generations);
+    if (e != hipSuccess) return device_fail(pop, e, "generation launch");
+    return SPEGG_OK;
+}
+
+spegg_status spegg_set_graph(spegg_pop *pop, int enable) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    pop->use_graph = enable != 0;
     return SPEGG_OK;
 }
 
@@ -526,7 +612,13 @@ spegg_status spegg_stats(spegg_pop *pop, spegg_rep_stats *host_out, uint32_t n) 
     if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(stats)");
     st = sync_stream(pop);
     if (st != SPEGG_OK) return st;
-    for (uint32_t i = 0; i < n; ++i) host_out[i] = census_of(s[i]);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (s[i].error) {
+            pop->errored = true;
+            return fail(SPEGG_E_DEVICE, "replicate %u: a kernel reported an impossible state", i);
+        }
+        host_out[i] = census_of(s[i]);
+    }
     return SPEGG_OK;
 }
 
@@ -539,12 +631,13 @@ spegg_status spegg_read_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, ui
     RepState s;
     if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
     const RepDesc &h = pop->dev_descs[rep];
-    const size_t words = (size_t)s.n * 2u * h.W;
-    if (n_out) *n_out = s.n;
+    const uint32_t n = s.n[current_pair_host(s)], t = s.t[current_pair_host(s)];
+    const size_t words = (size_t)n * 2u * h.W;
+    if (n_out) *n_out = n;
     if (words == 0) return SPEGG_OK;
     if (!host_words || n_words < words)
         return fail(SPEGG_E_INVALID, "read_genomes: need room for %zu words, have %zu", words, n_words);
-    hipError_t e = hipMemcpyAsync(host_words, h.genome[s.t & 1u], words * sizeof(uint32_t), hipMemcpyDeviceToHost,
+    hipError_t e = hipMemcpyAsync(host_words, h.genome[t & 1u], words * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                   pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(genomes)");
     return sync_stream(pop);
@@ -584,10 +677,11 @@ spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, int32_t *host_z
     DeviceGuard guard(pop->device);
     RepState s;
     if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
-    if (n_out) *n_out = s.n;
-    if (s.n == 0) return SPEGG_OK;
-    if (!host_z || n < s.n) return fail(SPEGG_E_INVALID, "read_phenotypes: need room for %u values", s.n);
-    hipError_t e = hipMemcpyAsync(host_z, pop->dev_descs[rep].z[s.t & 1u], (size_t)s.n * sizeof(int32_t),
+    const uint32_t cn = s.n[current_pair_host(s)], ct = s.t[current_pair_host(s)];
+    if (n_out) *n_out = cn;
+    if (cn == 0) return SPEGG_OK;
+    if (!host_z || n < cn) return fail(SPEGG_E_INVALID, "read_phenotypes: need room for %u values", cn);
+    hipError_t e = hipMemcpyAsync(host_z, pop->dev_descs[rep].z[ct & 1u], (size_t)cn * sizeof(int32_t),
                                   hipMemcpyDeviceToHost, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(phenotypes)");
     return sync_stream(pop);
@@ -610,9 +704,32 @@ spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t *host_i
     return sync_stream(pop);
 }
 
+spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t *counts_dev, uint32_t *host_counts,
+                                 uint32_t n_loci, uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if ((st = check_rep(pop, rep, 0, 0)) != SPEGG_OK) return st;
+    const RepDesc &h = pop->dev_descs[rep];
+    if (n_loci != h.L || !counts_dev || !host_counts)
+        return fail(SPEGG_E_INVALID, "allele_counts: need n_loci == %u and both arrays", h.L);
+    DeviceGuard guard(pop->device);
+    RepState s;
+    if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
+    const uint32_t n = s.n[current_pair_host(s)];
+    if (n_out) *n_out = n;
+    hipError_t e = hipMemsetAsync(counts_dev, 0, sizeof(uint32_t) * h.L, pop->stream);
+    if (e == hipSuccess) e = launch_allele_counts(pop->d_descs() + rep, pop->d_states() + rep, h, n, counts_dev,
+                                                  pop->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_counts, counts_dev, sizeof(uint32_t) * h.L, hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "allele_counts");
+    return sync_stream(pop);
+}
+
 spegg_status spegg_set_trace(spegg_pop *pop, int enable) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
+    if (pop->trace != (enable != 0)) pop->drop_graphs();
     pop->trace = enable != 0;
     return SPEGG_OK;
 }
@@ -626,13 +743,14 @@ spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t *host_mom
     RepState s;
     if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
     if (!s.traced) return fail(SPEGG_E_STATE, "read_parents: tracing was off for the last generation");
-    if (n_out) *n_out = s.n;
-    if (s.n == 0) return SPEGG_OK;
-    if (!host_mom || !host_dad || n < s.n) return fail(SPEGG_E_INVALID, "read_parents: need room for %u entries", s.n);
+    const uint32_t cn = s.n[current_pair_host(s)];
+    if (n_out) *n_out = cn;
+    if (cn == 0) return SPEGG_OK;
+    if (!host_mom || !host_dad || n < cn) return fail(SPEGG_E_INVALID, "read_parents: need room for %u entries", cn);
     const RepDesc &h = pop->dev_descs[rep];
-    hipError_t e = hipMemcpyAsync(host_mom, h.mom, (size_t)s.n * sizeof(uint32_t), hipMemcpyDeviceToHost, pop->stream);
+    hipError_t e = hipMemcpyAsync(host_mom, h.mom, (size_t)cn * sizeof(uint32_t), hipMemcpyDeviceToHost, pop->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(host_dad, h.dad, (size_t)s.n * sizeof(uint32_t), hipMemcpyDeviceToHost, pop->stream);
+        e = hipMemcpyAsync(host_dad, h.dad, (size_t)cn * sizeof(uint32_t), hipMemcpyDeviceToHost, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(parents)");
     return sync_stream(pop);
 }
@@ -683,6 +801,7 @@ void spegg_pop_destroy(spegg_pop *pop) {
             (void)hipEventDestroy(t.b);
         }
         for (hipEvent_t e : pop->event_pool) (void)hipEventDestroy(e);
+        pop->drop_graphs();
     }
     delete pop;
 }

@@ -1,11 +1,11 @@
 // Internal types shared by the host side and the kernels of libspegg.
 //
 // Device memory of a population is one caller-owned block, carved into:
-//   [RepDesc x n_reps][RepState x n_reps][SurvTile...][OffTile...][tables]   uploaded once at create
-//   [SurvCount...][Partial...][per-replicate buffers]                         written by kernels
+//   [RepDesc x n_reps][RepState x n_reps][SurvTile...][OffTile...][tables]  uploaded once at create
+//   [SurvCount...][Partial...][per-replicate buffers]                       written by kernels
 // Per replicate: two genome buffers (ping-pong by generation parity), two
-// phenotype buffers, the fate byte-pairs, the survivor list, the slot-owner
-// list (Poisson regime) and the parent trace.
+// phenotype buffers, the fates, the survivor list, the slot-owner list
+// (Poisson regime) and the parent trace.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,8 +35,10 @@ enum Mode : uint32_t { kModeRaw = 0, kModeZero = 1, kModeSkip = 2, kModeLazy = 3
 constexpr double kSkipBelow = 0.17;  // r < 0.17: geometric gaps; above: bit-serial Bernoulli
 
 constexpr int kBlock = 256;          // threads per block in every kernel
-constexpr int kSurvTile = 256;       // adults per survival / compaction tile
-constexpr int kCensusSlots = 16;     // census sums are spread over this many atomic slots
+constexpr int kSurvItems = 4;        // consecutive adults per thread in survive and compact
+constexpr int kSurvTile = kBlock * kSurvItems;  // adults per survival tile
+constexpr int kPoissonTableCap = 1024;  // longest Poisson threshold table
+constexpr int kCensusSlots = 16;     // slots of the census sums (init and write_genomes spread atomics)
 
 struct RepDesc {
     uint32_t L, W, cap, regime;
@@ -44,6 +46,7 @@ struct RepDesc {
     uint32_t R;          // floor(r 2^32), bit-serial mode
     uint32_t geo_len;    // L - 1 (skip mode)
     uint32_t binom_len, pois_len;
+    uint64_t binom0;     // binom[0]: a gamete draws no mutation when x < binom0
     int32_t zmin;        // vtab[z - zmin]
     uint32_t zlen;
     int32_t sum_e;       // sum of the effects
@@ -55,7 +58,7 @@ struct RepDesc {
     double K, lambda;    // Beverton-Holt density factor; 0 < K enables it
     uint32_t *genome[2];
     int32_t *z[2];
-    uint16_t *fate;      // bit 15 alive, bits 0..14 offspring count
+    uint16_t *fate;      // per adult: bit 15 survived, bits 0..14 offspring as mother
     uint32_t *S;         // survivors, ascending
     uint32_t *owner;     // mother of each offspring slot (Poisson regime)
     uint32_t *mom, *dad; // parent trace
@@ -64,16 +67,18 @@ struct RepDesc {
     const uint32_t *planes;  // 6 x W effect bit-planes: +1,+2,+4 then -1,-2,-4
 };
 
-// Per-replicate state.  A generation reads (t, n), and its scan kernel
-// advances them: t + 1, n = newborns, n_prev = the adults it started from.
+// Per-replicate state.  The census (generation t, size n) is double-buffered:
+// the current census is the pair with the larger t (compared modulo 2^32);
+// a generation reads it and writes (t + 1, newborns) into the other pair.
 struct RepState {
-    uint32_t t;       // generation of the newest census
-    uint32_t n;       // its size
+    uint32_t t[2];    // generation of the census
+    uint32_t n[2];    // its size
     uint32_t n_prev;  // adults of the last generation
     uint32_t n_surv;  // their survivors
     uint32_t extinct;
-    uint32_t traced;  // parents of the current newborns were recorded
+    uint32_t traced;          // parents of the current newborns were recorded
     uint32_t census_pending;  // census sums still sit in the offspring tiles' partials
+    uint32_t error;           // set by a kernel that found an impossible state (never expected)
     uint32_t pad0;
     uint64_t near_ties, truncated, updates, sum_threshold;
     int64_t sum_z[kCensusSlots];
@@ -84,10 +89,13 @@ struct SurvTile {
     uint32_t rep, start;
 };
 
+// Counts of one survival tile; tile 0 of a replicate also records the
+// census the generation started from (pair index, t, n), which compact
+// reads instead of the state it advances.
 struct SurvCount {
-    uint32_t alive, kids, near, pad;
+    uint32_t alive, kids, near, par;
     uint64_t sum_t;
-    uint32_t alive_off, kid_off;
+    uint32_t t, n;
 };
 
 struct OffTile {
@@ -102,17 +110,32 @@ struct Partial {
 
 // Offspring-kernel shape for a genome of W words per haplotype: VPL
 // consecutive words per lane (16- or 8-byte accesses when W allows), G
-// lanes per gamete (a power of two, at most 32; larger genomes loop over
-// chunks of G x VPL words), 2G lanes per newborn.
+// lanes per gamete (a power of two, at most gcap), 2G lanes per newborn; a
+// gamete spans nch chunks of G x VPL words, all gathered into registers up
+// front when nch <= 4 (nch = 0: more chunks, gathered one at a time).  Any
+// shape gives the same results: the random words a newborn consumes do not
+// depend on it.
 struct OffShape {
-    int g, vpl;
+    int g, vpl, nch;
 };
-inline OffShape offspring_shape(uint32_t W) {
+constexpr int kDefaultGCap = 8;
+inline OffShape offspring_shape(uint32_t W, int gcap = kDefaultGCap) {
     OffShape s;
-    s.vpl = (W % 4 == 0 && W >= 16) ? 4 : (W % 2 == 0) ? 2 : 1;
-    const uint32_t per = W / s.vpl;
+    s.vpl = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
+    const uint32_t per = W / s.vpl;  // lanes of one gamete without chunking
     s.g = 1;
-    while ((uint32_t)s.g < per && s.g < 32) s.g <<= 1;
+    while ((uint32_t)s.g < per && s.g < gcap) s.g <<= 1;
+    const uint32_t chunks = (per + s.g - 1) / s.g;
+    if (chunks <= 2) {
+        s.nch = chunks <= 1 ? 1 : 2;
+    } else if (chunks <= 4) {
+        s.nch = 4;
+    } else {
+        // long genomes: widest team, chunks gathered one at a time
+        s.g = 1;
+        while ((uint32_t)s.g < per && s.g < 32) s.g <<= 1;
+        s.nch = (per + s.g - 1) / s.g <= 1 ? 1 : 0;
+    }
     return s;
 }
 inline int offspring_per_tile(int g) {
@@ -124,23 +147,46 @@ inline size_t offspring_lds_bytes(int g, uint32_t W) {
     return (size_t)(kBlock / (2 * g)) * 2u * 2u * W * sizeof(uint32_t);
 }
 
+struct SelArgs {
+    const RepDesc *descs;
+    RepState *states;
+    const SurvTile *tiles;
+    SurvCount *counts;
+    uint32_t ntiles;
+    int trace;
+    hipStream_t s;
+};
+
+struct OffArgs {
+    const RepDesc *descs;
+    const RepState *states;
+    const OffTile *tiles;
+    uint32_t tile0, ntiles;
+    int single_rep;  // >= 0: the class's only replicate, tiles implicit
+    Partial *partials;
+    uint32_t plane_words;  // LDS words reserved for the effect planes
+    uint32_t grid;
+    size_t lds;
+    int trace;
+    hipStream_t s;
+};
+
 // Host-side launchers (kernels.hip).
 hipError_t launch_init(const RepDesc *d_desc, const RepDesc &h, uint32_t n0, hipStream_t s);
 hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t n, uint32_t buf, hipStream_t s);
-hipError_t launch_survive(const RepDesc *descs, const RepState *states, const SurvTile *tiles, SurvCount *counts,
-                          uint32_t ntiles, hipStream_t s);
-hipError_t launch_scan(const RepDesc *descs, RepState *states, SurvCount *counts, uint32_t n_reps, int trace,
-                       hipStream_t s);
-hipError_t launch_compact(const RepDesc *descs, const RepState *states, const SurvTile *tiles,
-                          const SurvCount *counts, uint32_t ntiles, hipStream_t s);
-// single_rep >= 0: the class holds only that replicate and its tiles are
-// implicit; otherwise tiles[tile0 .. tile0 + ntiles) lists them.
-hipError_t launch_offspring(OffShape shape, const RepDesc *descs, RepState *states, const OffTile *tiles,
-                            uint32_t tile0, uint32_t ntiles, int single_rep, Partial *partials, uint32_t grid,
-                            size_t lds, int trace, hipStream_t s);
+hipError_t launch_survive(const SelArgs &a);
+hipError_t launch_compact(const SelArgs &a);
+hipError_t launch_offspring(OffShape shape, const OffArgs &a);
 // Fold pending per-tile census sums into each replicate's state.
 hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,
                          hipStream_t s);
+
+// Host twin of the kernels' choice of the current census pair.
+inline uint32_t current_pair_host(const RepState &st) { return (int32_t)(st.t[1] - st.t[0]) > 0 ? 1u : 0u; }
+// Per-locus copies of allele 1 over the current census of n individuals
+// into counts (L words, zeroed by the caller).
+hipError_t launch_allele_counts(const RepDesc *d_desc, const RepState *d_state, const RepDesc &h, uint32_t n,
+                                uint32_t *counts, hipStream_t s);
 hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out, uint32_t n,
                               hipStream_t s);
 

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(PKG, "libspegg.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 WF, POISSON_BH = 0, 1
-KERNEL_NAMES = ["survive", "scan", "compact", "offspring"]
+KERNEL_NAMES = ["survive", "compact", "offspring"]
 
 
 class SpeggError(RuntimeError):
@@ -97,10 +97,14 @@ def load():
     lib.spegg_read_phenotypes.argtypes = [vp, u32, C.POINTER(C.c_int32), C.c_size_t, P32]
     lib.spegg_read_survivors.restype = st
     lib.spegg_read_survivors.argtypes = [vp, u32, P32, C.c_size_t, P32]
+    lib.spegg_allele_counts.restype = st
+    lib.spegg_allele_counts.argtypes = [vp, u32, vp, P32, u32, P32]
     lib.spegg_set_trace.restype = st
     lib.spegg_set_trace.argtypes = [vp, C.c_int]
     lib.spegg_read_parents.restype = st
     lib.spegg_read_parents.argtypes = [vp, u32, P32, P32, C.c_size_t, P32]
+    lib.spegg_set_graph.restype = st
+    lib.spegg_set_graph.argtypes = [vp, C.c_int]
     lib.spegg_set_timing.restype = st
     lib.spegg_set_timing.argtypes = [vp, u32]
     lib.spegg_kernel_times.restype = st
@@ -204,7 +208,12 @@ class Population:
         if self.footprint == 0:
             raise SpeggError(E_INVALID, last_error())
         self.workspace = torch.empty(self.footprint, dtype=torch.uint8, device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        if stream is None:
+            # a stream of its own (default priority), so generations can be
+            # replayed as graphs; it waits for the workspace allocation
+            stream = torch.cuda.Stream(device=self.workspace.device)
+            stream.wait_stream(torch.cuda.current_stream(self.workspace.device))
+        self.stream = stream
         h = C.c_void_p()
         check(self.lib.spegg_pop_create(arr, self.n_reps, C.c_void_p(self.workspace.data_ptr()), self.footprint,
                                         C.c_void_p(self.stream.cuda_stream), C.byref(h)))
@@ -268,6 +277,21 @@ class Population:
         check(self.lib.spegg_read_survivors(self._h, rep, _p(out, C.c_uint32), out.size, C.byref(got)))
         return out[: got.value]
 
+    def allele_counts(self, rep=0):
+        """Copies of allele 1 per locus over the current census (uint32, L)."""
+        import torch
+        L = self.L[rep]
+        scratch = torch.empty(L, dtype=torch.int32, device=self.workspace.device)
+        out = np.zeros(L, dtype=np.uint32)
+        got = C.c_uint32()
+        check(self.lib.spegg_allele_counts(self._h, rep, C.c_void_p(scratch.data_ptr()), _p(out, C.c_uint32), L,
+                                           C.byref(got)))
+        return out
+
+    def set_graph(self, enable=True):
+        """Replay generations as captured HIP graphs (default) or launch eagerly."""
+        check(self.lib.spegg_set_graph(self._h, 1 if enable else 0))
+
     def set_trace(self, enable=True):
         check(self.lib.spegg_set_trace(self._h, 1 if enable else 0))
 
@@ -280,7 +304,7 @@ class Population:
                                           C.byref(got)))
         return mom[: got.value], dad[: got.value]
 
-    def set_timing(self, kernels=("survive", "scan", "compact", "offspring")):
+    def set_timing(self, kernels=("survive", "compact", "offspring")):
         """Bracket the named kernels with HIP events (empty: stop)."""
         mask = 0
         for k in kernels:

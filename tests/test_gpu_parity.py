@@ -169,3 +169,50 @@ def test_kernel_timing_counts_launches():
     pop.set_timing([])
     pop.step(2)
     assert all(v[1] == 0 for v in pop.kernel_times().values())
+
+
+@pytest.mark.parametrize("desc_name", ["small", "poisson"])
+def test_graph_replay_equals_eager_and_oracle(desc_name):
+    """Generations replayed as captured graphs (16- and 1-generation graphs,
+    many replays, with host reads and synchronisations in between) give the
+    same state as eager launches and as the oracle, after every chunk."""
+    if desc_name == "small":
+        desc, _ = workloads.plain_small(seed=3)
+    else:
+        desc = dict(seed=4, replicate_id=2, regime=1, n0=800, capacity=2500, n_loci=300, mu=1e-3, r=0.05,
+                    theta=0.0, omega=12.0, K=900.0, fecundity=2.2,
+                    effects=np.random.default_rng(9).integers(-4, 5, 300).astype(np.int8))
+    say("graph vs eager", desc_name)
+    g = spegg.Population([desc])
+    e = spegg.Population([desc])
+    e.set_graph(False)
+    orc = oracle_pop(desc)
+    for chunk in (1, 16, 3, 17, 1, 33):
+        g.step(chunk)
+        e.step(chunk)
+        orc.step(chunk)
+        assert g.stats() == e.stats()
+        assert np.array_equal(g.genomes(0), e.genomes(0))
+        assert_same_state(g, 0, orc, f"after chunk {chunk}")
+    g.set_trace(True)  # a new trace setting recaptures the graphs
+    e.set_trace(True)
+    g.step(2)
+    e.step(2)
+    orc.step(2)
+    assert_same_state(g, 0, orc, "traced", parents=True)
+    assert np.array_equal(g.parents(0)[0], e.parents(0)[0])
+
+
+@pytest.mark.parametrize("L,n0", [(1, 10), (70, 300), (1024, 2000)])
+def test_allele_counts_match_oracle(L, n0):
+    desc = dict(seed=12, replicate_id=1, regime=0, n0=n0, capacity=n0, n_loci=L, mu=1e-3, r=0.2, theta=0.0,
+                omega=0.0)
+    say("allele counts", L, n0)
+    pop = spegg.Population([desc])
+    orc = oracle_pop(desc)
+    pop.step(3)
+    orc.step(3)
+    got = pop.allele_counts(0)
+    expect = orc.alleles().astype(np.int64).sum(axis=(0, 1))
+    assert np.array_equal(got.astype(np.int64), expect)
+    assert got.max() <= 2 * n0
