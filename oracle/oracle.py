@@ -23,13 +23,14 @@ class OracleParams(C.Structure):
         ("n0", C.c_uint32),
         ("capacity", C.c_uint32),
         ("n_loci", C.c_uint32),
-        ("reserved", C.c_uint32),
+        ("n_patches", C.c_uint32),
         ("mu", C.c_double),
         ("r", C.c_double),
         ("theta", C.c_double),
         ("omega", C.c_double),
         ("K", C.c_double),
         ("fecundity", C.c_double),
+        ("migration", C.c_double),
         ("effects", C.POINTER(C.c_int8)),
     ]
 
@@ -87,23 +88,25 @@ def load():
     lib.oracle_destroy.restype = None
     lib.oracle_step.argtypes = [vp, u32]
     lib.oracle_step.restype = C.c_int
-    lib.oracle_get_stats.argtypes = [vp, C.POINTER(OracleStats)]
-    lib.oracle_get_stats.restype = None
-    lib.oracle_get_n.argtypes = [vp]
+    lib.oracle_get_stats.argtypes = [vp, u32, C.POINTER(OracleStats)]
+    lib.oracle_get_stats.restype = C.c_int
+    lib.oracle_get_n.argtypes = [vp, u32]
     lib.oracle_get_n.restype = u32
     lib.oracle_get_generation.argtypes = [vp]
     lib.oracle_get_generation.restype = u32
+    lib.oracle_get_patches.argtypes = [vp]
+    lib.oracle_get_patches.restype = u32
     lib.oracle_get_mode.argtypes = [vp]
     lib.oracle_get_mode.restype = C.c_int
-    lib.oracle_get_genomes.argtypes = [vp, P32, C.c_size_t]
+    lib.oracle_get_genomes.argtypes = [vp, u32, P32, C.c_size_t]
     lib.oracle_get_genomes.restype = C.c_int
-    lib.oracle_set_genomes.argtypes = [vp, P32, u32, u32]
+    lib.oracle_set_genomes.argtypes = [vp, u32, P32, u32, u32]
     lib.oracle_set_genomes.restype = C.c_int
-    lib.oracle_get_phenotypes.argtypes = [vp, C.POINTER(i32), C.c_size_t]
+    lib.oracle_get_phenotypes.argtypes = [vp, u32, C.POINTER(i32), C.c_size_t]
     lib.oracle_get_phenotypes.restype = C.c_int
-    lib.oracle_get_survivors.argtypes = [vp, P32, C.c_size_t]
+    lib.oracle_get_survivors.argtypes = [vp, u32, P32, C.c_size_t]
     lib.oracle_get_survivors.restype = u32
-    lib.oracle_get_parents.argtypes = [vp, P32, P32, C.c_size_t]
+    lib.oracle_get_parents.argtypes = [vp, u32, P32, P32, P32, C.c_size_t]
     lib.oracle_get_parents.restype = C.c_int
     lib.oracle_sample_gametes.argtypes = [vp, C.POINTER(C.c_uint8), u32, u32, u32, C.c_int, C.POINTER(C.c_uint8)]
     lib.oracle_sample_gametes.restype = C.c_int
@@ -153,14 +156,17 @@ def recomb_mode(r):
 
 
 class OraclePop:
-    """One replicate in the oracle.  ``params`` is a dict with the keys of
-    ``OracleParams`` (effects as a sequence of ints or None)."""
+    """One replicate in the oracle: a ring of ``n_patches`` patches (one by
+    default).  Per-patch accessors take ``patch``; ``total_stats`` sums the
+    census over the patches."""
 
     def __init__(self, seed=1, replicate_id=0, regime=0, n0=100, capacity=None, n_loci=64,
-                 mu=0.0, r=0.5, theta=0.0, omega=0.0, K=0.0, fecundity=0.0, effects=None):
+                 mu=0.0, r=0.5, theta=0.0, omega=0.0, K=0.0, fecundity=0.0, effects=None,
+                 n_patches=1, migration=0.0):
         lib = load()
         self.L = int(n_loci)
         self.W = (self.L + 31) // 32
+        self.n_patches = int(n_patches)
         self._effects = None
         eff_ptr = None
         if effects is not None:
@@ -168,8 +174,8 @@ class OraclePop:
             assert self._effects.shape == (self.L,)
             eff_ptr = _p(self._effects, C.c_int8)
         prm = OracleParams(seed=seed, replicate_id=replicate_id, regime=regime, n0=n0,
-                           capacity=n0 if capacity is None else capacity, n_loci=n_loci, reserved=0,
-                           mu=mu, r=r, theta=theta, omega=omega, K=K, fecundity=fecundity,
+                           capacity=n0 if capacity is None else capacity, n_loci=n_loci, n_patches=n_patches,
+                           mu=mu, r=r, theta=theta, omega=omega, K=K, fecundity=fecundity, migration=migration,
                            effects=eff_ptr)
         self.capacity = prm.capacity
         self._h = lib.oracle_create(C.byref(prm))
@@ -193,7 +199,10 @@ class OraclePop:
 
     @property
     def n(self):
-        return int(self._lib.oracle_get_n(self._h))
+        return int(self._lib.oracle_get_n(self._h, 0))
+
+    def n_of(self, patch):
+        return int(self._lib.oracle_get_n(self._h, int(patch)))
 
     @property
     def generation(self):
@@ -203,46 +212,60 @@ class OraclePop:
     def mode(self):
         return MODE_NAMES[self._lib.oracle_get_mode(self._h)]
 
-    def stats(self):
+    def stats(self, patch=0):
         s = OracleStats()
-        self._lib.oracle_get_stats(self._h, C.byref(s))
+        assert self._lib.oracle_get_stats(self._h, int(patch), C.byref(s)) == 0
         return s.as_dict()
 
-    def genomes(self):
+    def total_stats(self):
+        """The census summed over patches (generation and extinct: shared)."""
+        per = [self.stats(k) for k in range(self.n_patches)]
+        out = {k: sum(p[k] for p in per) for k in per[0]}
+        out["generation"] = per[0]["generation"]
+        out["extinct"] = int(all(p["extinct"] for p in per))
+        return out
+
+    def genomes(self, patch=0):
         """Packed genomes, shape (n, 2, W) uint32."""
-        n = self.n
+        n = self.n_of(patch)
         out = np.zeros(max(n, 1) * 2 * self.W, dtype=np.uint32)
-        assert self._lib.oracle_get_genomes(self._h, _p(out, C.c_uint32), out.size) == 0
+        assert self._lib.oracle_get_genomes(self._h, int(patch), _p(out, C.c_uint32), out.size) == 0
         return out[: n * 2 * self.W].reshape(n, 2, self.W)
 
-    def alleles(self):
+    def alleles(self, patch=0):
         """Unpacked alleles, shape (n, 2, L) uint8."""
-        g = self.genomes()
+        g = self.genomes(patch)
         bits = np.unpackbits(g.view(np.uint8).reshape(g.shape[0], 2, -1), axis=-1, bitorder="little")
         return bits[..., : self.L]
 
-    def set_genomes(self, words, generation):
+    def set_genomes(self, words, generation, patch=0):
         w = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1)
         n = w.size // (2 * self.W)
-        assert self._lib.oracle_set_genomes(self._h, _p(w, C.c_uint32), n, int(generation)) == 0
+        assert self._lib.oracle_set_genomes(self._h, int(patch), _p(w, C.c_uint32), n, int(generation)) == 0
 
-    def phenotypes(self):
-        n = self.n
+    def phenotypes(self, patch=0):
+        n = self.n_of(patch)
         out = np.zeros(max(n, 1), dtype=np.int32)
-        assert self._lib.oracle_get_phenotypes(self._h, _p(out, C.c_int32), out.size) == 0
+        assert self._lib.oracle_get_phenotypes(self._h, int(patch), _p(out, C.c_int32), out.size) == 0
         return out[:n]
 
-    def survivors(self):
-        m = self._lib.oracle_get_survivors(self._h, None, 0)
+    def survivors(self, patch=0):
+        m = self._lib.oracle_get_survivors(self._h, int(patch), None, 0)
         out = np.zeros(max(m, 1), dtype=np.uint32)
-        self._lib.oracle_get_survivors(self._h, _p(out, C.c_uint32), out.size)
+        self._lib.oracle_get_survivors(self._h, int(patch), _p(out, C.c_uint32), out.size)
         return out[:m]
 
-    def parents(self):
-        n = self.n
+    def parents(self, patch=0, with_source=False):
+        """Mother and father of each current newborn (indices into the adults
+        of its source patch) and, with_source, that patch."""
+        n = self.n_of(patch)
         mom = np.zeros(max(n, 1), dtype=np.uint32)
         dad = np.zeros(max(n, 1), dtype=np.uint32)
-        assert self._lib.oracle_get_parents(self._h, _p(mom, C.c_uint32), _p(dad, C.c_uint32), mom.size) == 0
+        src = np.zeros(max(n, 1), dtype=np.uint32)
+        assert self._lib.oracle_get_parents(self._h, int(patch), _p(mom, C.c_uint32), _p(dad, C.c_uint32),
+                                            _p(src, C.c_uint32), mom.size) == 0
+        if with_source:
+            return mom[:n], dad[:n], src[:n]
         return mom[:n], dad[:n]
 
     def sample_gametes(self, parent_alleles, j0, count, gen=0, paternal=False):

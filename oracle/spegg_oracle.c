@@ -47,7 +47,8 @@ enum {
     ST_RECOMB_MAT = 6,
     ST_RECOMB_PAT = 7,
     ST_MUTATE_MAT = 8,
-    ST_MUTATE_PAT = 9
+    ST_MUTATE_PAT = 9,
+    ST_MIGRATE = 10
 };
 
 enum { REGIME_WF = 0, REGIME_POISSON_BH = 1 };
@@ -216,8 +217,11 @@ typedef struct {
     uint64_t seed;
     uint32_t replicate_id;
     uint32_t regime; /* 0: Wright-Fisher, constant N; 1: Poisson fecundity, Beverton-Holt survival */
-    uint32_t n0, capacity, n_loci, reserved;
+    uint32_t n0, capacity; /* per patch */
+    uint32_t n_loci;
+    uint32_t n_patches; /* patches on a ring, >= 1 */
     double mu, r, theta, omega, K, fecundity;
+    double migration; /* backward migration rate to the two ring neighbours */
     const int8_t *effects; /* n_loci values, NULL: all +1 */
 } oracle_params;
 
@@ -228,10 +232,23 @@ typedef struct {
     uint64_t updates; /* cumulative genotype-locus updates, sum of N_t L */
 } oracle_stats;
 
+/* One patch of a replicate: its own individuals and its own Philox
+ * counter field c3 = replicate << 12 | patch (species 0). */
+typedef struct {
+    rng_ctx rng;
+    uint32_t n;
+    uint8_t *genome; /* genome[i][h][l], one byte per allele */
+    int32_t *z;
+    /* the last generation's survivors, fecundities and parents */
+    uint32_t *survivors, n_survivors;
+    uint32_t *kids, *owner, n_next;
+    uint32_t *mom, *dad, *src;
+    oracle_stats stats;
+} oracle_deme;
+
 typedef struct {
     oracle_params prm;
     int8_t *effects;
-    rng_ctx rng;
     int mode;
     uint32_t L;
     uint64_t *geo;   /* L-1 entries */
@@ -239,14 +256,9 @@ typedef struct {
     int binom_len;
     uint64_t *pois;
     int pois_len;
-    /* state: genome[i][h][l] one byte per allele, z[i] */
-    uint32_t generation, n;
-    uint8_t *genome;
-    int32_t *z;
-    /* the last generation's survivors and parents, for comparison */
-    uint32_t *survivors, n_survivors;
-    uint32_t *mom, *dad;
-    oracle_stats stats;
+    uint64_t mig_T; /* migration threshold, 0: no migration */
+    uint32_t generation, n_patches;
+    oracle_deme *deme;
 } oracle_pop;
 
 #define TABLE_CAP 1024
@@ -299,23 +311,30 @@ static uint8_t *allele_row(const oracle_pop *P, uint8_t *g, uint32_t i, uint32_t
     return g + ((size_t)i * 2u + h) * P->L;
 }
 
-static void free_pop_state(oracle_pop *P)
+static void free_deme(oracle_deme *D)
 {
-    free(P->genome);
-    free(P->z);
-    free(P->survivors);
-    free(P->mom);
-    free(P->dad);
-    P->genome = NULL;
-    P->z = NULL;
-    P->survivors = P->mom = P->dad = NULL;
+    free(D->genome);
+    free(D->z);
+    free(D->survivors);
+    free(D->kids);
+    free(D->owner);
+    free(D->mom);
+    free(D->dad);
+    free(D->src);
+    D->genome = NULL;
+    D->z = NULL;
+    D->survivors = D->kids = D->owner = D->mom = D->dad = D->src = NULL;
 }
 
 void oracle_destroy(oracle_pop *P)
 {
+    uint32_t k;
     if (!P)
         return;
-    free_pop_state(P);
+    if (P->deme)
+        for (k = 0; k < P->n_patches; ++k)
+            free_deme(&P->deme[k]);
+    free(P->deme);
     free(P->effects);
     free(P->geo);
     free(P->binom);
@@ -323,24 +342,26 @@ void oracle_destroy(oracle_pop *P)
     free(P);
 }
 
-static void census(oracle_pop *P)
+static void census(oracle_pop *P, oracle_deme *D)
 {
     uint32_t i;
-    P->stats.generation = P->generation;
-    P->stats.n = P->n;
-    P->stats.sum_z = 0;
-    P->stats.sum_z2 = 0;
-    for (i = 0; i < P->n; ++i) {
-        P->stats.sum_z += P->z[i];
-        P->stats.sum_z2 += (int64_t)P->z[i] * (int64_t)P->z[i];
+    D->stats.generation = P->generation;
+    D->stats.n = D->n;
+    D->stats.sum_z = 0;
+    D->stats.sum_z2 = 0;
+    for (i = 0; i < D->n; ++i) {
+        D->stats.sum_z += D->z[i];
+        D->stats.sum_z2 += (int64_t)D->z[i] * (int64_t)D->z[i];
     }
 }
 
 oracle_pop *oracle_create(const oracle_params *prm)
 {
     oracle_pop *P;
-    uint32_t L = prm->n_loci, l, i, h;
-    if (L == 0 || prm->n0 > prm->capacity || !(prm->mu >= 0.0 && prm->mu < 1.0) || !(prm->r >= 0.0 && prm->r <= 0.5))
+    uint32_t L = prm->n_loci, l, i, h, k;
+    if (L == 0 || prm->n0 > prm->capacity || !(prm->mu >= 0.0 && prm->mu < 1.0) || !(prm->r >= 0.0 && prm->r <= 0.5) ||
+        prm->n_patches < 1 || prm->n_patches > 1024 || !(prm->migration >= 0.0 && prm->migration <= 1.0) ||
+        (prm->n_patches > 1 && prm->regime != REGIME_WF))
         return NULL;
     P = (oracle_pop *)calloc(1, sizeof *P);
     if (!P)
@@ -351,9 +372,6 @@ oracle_pop *oracle_create(const oracle_params *prm)
     for (l = 0; l < L; ++l)
         P->effects[l] = prm->effects ? prm->effects[l] : 1;
     P->prm.effects = P->effects;
-    P->rng.key[0] = (uint32_t)prm->seed;
-    P->rng.key[1] = (uint32_t)(prm->seed >> 32);
-    P->rng.c3 = prm->replicate_id << 12; /* species 0, patch 0 */
     P->mode = oracle_recomb_mode(prm->r);
     P->geo = (uint64_t *)malloc(sizeof(uint64_t) * (L > 1 ? L - 1 : 1));
     oracle_geometric_thresholds(prm->r, L - 1, P->geo);
@@ -361,29 +379,37 @@ oracle_pop *oracle_create(const oracle_params *prm)
     P->binom_len = oracle_binomial_thresholds(L, prm->mu, P->binom, (int)L + 1);
     P->pois = (uint64_t *)malloc(sizeof(uint64_t) * TABLE_CAP);
     P->pois_len = oracle_poisson_thresholds(prm->fecundity, P->pois, TABLE_CAP);
+    P->n_patches = prm->n_patches;
+    P->mig_T = prm->n_patches > 1 ? oracle_prob_threshold(prm->migration) : 0;
+    P->deme = (oracle_deme *)calloc(P->n_patches, sizeof(oracle_deme));
+    P->generation = 0;
 
     /* Initial state: every allele an independent fair bit (Hardy-Weinberg,
-     * allele frequency one half), drawn from stream INIT in generation 0. */
-    P->generation = 0;
-    P->n = prm->n0;
-    P->genome = (uint8_t *)malloc((size_t)(prm->n0 ? prm->n0 : 1) * 2u * L);
-    P->z = (int32_t *)malloc(sizeof(int32_t) * (prm->n0 ? prm->n0 : 1));
-    {
+     * allele frequency one half), drawn from stream INIT in generation 0,
+     * patch by patch. */
+    for (k = 0; k < P->n_patches; ++k) {
+        oracle_deme *D = &P->deme[k];
         uint32_t W = (L + 31u) / 32u;
+        D->rng.key[0] = (uint32_t)prm->seed;
+        D->rng.key[1] = (uint32_t)(prm->seed >> 32);
+        D->rng.c3 = (prm->replicate_id << 12) | k; /* species 0 */
+        D->n = prm->n0;
+        D->genome = (uint8_t *)malloc((size_t)(prm->n0 ? prm->n0 : 1) * 2u * L);
+        D->z = (int32_t *)malloc(sizeof(int32_t) * (prm->n0 ? prm->n0 : 1));
         for (i = 0; i < prm->n0; ++i) {
             for (h = 0; h < 2; ++h) {
-                uint8_t *row = allele_row(P, P->genome, i, h);
+                uint8_t *row = allele_row(P, D->genome, i, h);
                 for (l = 0; l < L; ++l) {
-                    uint32_t w = seq_word(&P->rng, i, ST_INIT, 0, h * W + l / 32u);
+                    uint32_t w = seq_word(&D->rng, i, ST_INIT, 0, h * W + l / 32u);
                     row[l] = (uint8_t)((w >> (l % 32u)) & 1u);
                 }
             }
-            P->z[i] = phenotype(P, allele_row(P, P->genome, i, 0), allele_row(P, P->genome, i, 1));
+            D->z[i] = phenotype(P, allele_row(P, D->genome, i, 0), allele_row(P, D->genome, i, 1));
         }
+        census(P, D);
+        D->stats.n_parents = 0;
+        D->stats.extinct = prm->n0 == 0;
     }
-    census(P);
-    P->stats.n_parents = 0;
-    P->stats.extinct = prm->n0 == 0;
     return P;
 }
 
@@ -414,17 +440,18 @@ static int lazy_crossover(rng_ctx *g, uint32_t j, uint32_t stream, uint32_t gen,
     return 0; /* U == R */
 }
 
-static void recombination_mask(oracle_pop *P, uint32_t j, uint32_t stream, uint32_t gen, uint8_t *mask, uint8_t *toggles)
+static void recombination_mask(const oracle_pop *P, rng_ctx *g, uint32_t j, uint32_t stream, uint32_t gen, uint8_t *mask,
+                               uint8_t *toggles)
 {
     uint32_t L = P->L, l;
     uint32_t phase;
     if (P->mode == MODE_RAW) {
         /* r = 1/2: every locus independently takes either haplotype. */
         for (l = 0; l < L; ++l)
-            mask[l] = (uint8_t)((seq_word(&P->rng, j, stream, gen, l / 32u) >> (l % 32u)) & 1u);
+            mask[l] = (uint8_t)((seq_word(g, j, stream, gen, l / 32u) >> (l % 32u)) & 1u);
         return;
     }
-    phase = seq_word(&P->rng, j, stream, gen, 0) & 1u;
+    phase = seq_word(g, j, stream, gen, 0) & 1u;
     memset(toggles, 0, L);
     toggles[0] = (uint8_t)phase;
     if (P->mode == MODE_SKIP) {
@@ -434,7 +461,7 @@ static void recombination_mask(oracle_pop *P, uint32_t j, uint32_t stream, uint3
         uint64_t b = 0;
         uint32_t q = 4;
         for (;;) {
-            uint32_t x = seq_word(&P->rng, j, stream, gen, q++);
+            uint32_t x = seq_word(g, j, stream, gen, q++);
             uint32_t gap = 0; /* smallest k with x < T_k, else L - 1 */
             while (gap + 1u < L && (uint64_t)x >= P->geo[gap])
                 ++gap;
@@ -447,7 +474,7 @@ static void recombination_mask(oracle_pop *P, uint32_t j, uint32_t stream, uint3
         uint32_t R = (uint32_t)floor(P->prm.r * TWO32);
         uint32_t bnd;
         for (bnd = 1; bnd < L; ++bnd)
-            toggles[bnd] = (uint8_t)lazy_crossover(&P->rng, j, stream, gen, bnd / 32u, bnd % 32u, R);
+            toggles[bnd] = (uint8_t)lazy_crossover(g, j, stream, gen, bnd / 32u, bnd % 32u, R);
     }
     /* MODE_ZERO: no crossover, the phase alone. */
     {
@@ -459,28 +486,29 @@ static void recombination_mask(oracle_pop *P, uint32_t j, uint32_t stream, uint3
     }
 }
 
-static void make_gamete(oracle_pop *P, const uint8_t *h0, const uint8_t *h1, uint32_t j, uint32_t gen, int paternal, uint8_t *out, uint8_t *scratch)
+static void make_gamete(const oracle_pop *P, rng_ctx *g, const uint8_t *h0, const uint8_t *h1, uint32_t j, uint32_t gen,
+                        int paternal, uint8_t *out, uint8_t *scratch)
 {
     uint32_t L = P->L, l;
     uint8_t *mask = scratch, *toggles = scratch + L, *chosen = scratch + 2u * L;
     uint32_t rstream = paternal ? ST_RECOMB_PAT : ST_RECOMB_MAT;
     uint32_t mstream = paternal ? ST_MUTATE_PAT : ST_MUTATE_MAT;
     uint32_t K, accepted = 0, cand = 0;
-    recombination_mask(P, j, rstream, gen, mask, toggles);
+    recombination_mask(P, g, j, rstream, gen, mask, toggles);
     for (l = 0; l < L; ++l)
         out[l] = mask[l] ? h1[l] : h0[l];
     /* Mutation: K ~ Binomial(L, mu) loci, chosen uniformly without
      * replacement, each flipped -- the same law as an independent flip at
      * each locus with probability mu. */
-    K = draw_by_table(seq_word(&P->rng, j, mstream, gen, 0), P->binom, P->binom_len);
+    K = draw_by_table(seq_word(g, j, mstream, gen, 0), P->binom, P->binom_len);
     if (K == 0)
         return;
     memset(chosen, 0, L);
     /* at most 2^23 candidate pairs per gamete, a bound no run with mu < 1
      * comes near; it keeps every loop finite */
     while (accepted < K && cand < (1u << 23)) {
-        uint32_t lo = seq_word(&P->rng, j, mstream, gen, 1u + 2u * cand);
-        uint32_t hi = seq_word(&P->rng, j, mstream, gen, 2u + 2u * cand);
+        uint32_t lo = seq_word(g, j, mstream, gen, 1u + 2u * cand);
+        uint32_t hi = seq_word(g, j, mstream, gen, 2u + 2u * cand);
         uint32_t pos = uniform_index(lo, hi, L);
         ++cand;
         if (chosen[pos])
@@ -494,126 +522,210 @@ static void make_gamete(oracle_pop *P, const uint8_t *h0, const uint8_t *h1, uin
 /* ------------------------------------------------------------------ */
 /* One generation (Fig. 1): survival under the selective environment   */
 /* (D), removal of the dead (E), parents and neonate count (A),        */
-/* transmission (B), phenotypes of the newborns (C).                   */
+/* transmission (B), phenotypes of the newborns (C).  Patches on a     */
+/* ring exchange offspring by backward migration (Supplementary S3:    */
+/* each patch linked by migration to its neighbouring patches).        */
 /* ------------------------------------------------------------------ */
+
+/* D, E and the offspring counts of A in one patch. */
+static void select_and_count(oracle_pop *P, oracle_deme *D, uint32_t t)
+{
+    uint32_t n = D->n, i, ns = 0;
+    uint64_t sumT = 0;
+    double s = density_factor(P, n);
+    uint8_t *alive = (uint8_t *)calloc(n ? n : 1, 1);
+    /* Survival: Bernoulli(v(z) s(N)) per adult. */
+    for (i = 0; i < n; ++i) {
+        double p = viability(P, D->z[i]) * s;
+        uint64_t T = oracle_prob_threshold(p);
+        uint32_t x = seq_word(&D->rng, i, ST_SURVIVE, t, 0);
+        alive[i] = (uint8_t)((uint64_t)x < T);
+        sumT += T;
+        if (p > 0.0 && p < 1.0 && fabs((double)x * (1.0 / TWO32) - p) < 1e-6)
+            D->stats.near_ties++;
+    }
+    /* Removal of the dead: survivors in ascending index order. */
+    free(D->survivors);
+    D->survivors = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    for (i = 0; i < n; ++i)
+        if (alive[i])
+            D->survivors[ns++] = i;
+    D->n_survivors = ns;
+    D->stats.sum_threshold = sumT;
+    free(alive);
+    /* Poisson regime: each survivor's offspring count as mother. */
+    free(D->kids);
+    D->kids = NULL;
+    if (P->prm.regime == REGIME_POISSON_BH) {
+        D->kids = (uint32_t *)malloc(sizeof(uint32_t) * (ns ? ns : 1));
+        for (i = 0; i < ns; ++i)
+            D->kids[i] = draw_by_table(seq_word(&D->rng, D->survivors[i], ST_FECUND, t, 0), P->pois, P->pois_len);
+    }
+}
+
+/* Neonate count of patch k and, in the Poisson regime, each offspring
+ * slot's mother.  Wright-Fisher keeps the patch's census while any patch
+ * its offspring may descend from (itself and its ring neighbours) has a
+ * survivor. */
+static void neonates(oracle_pop *P, uint32_t k)
+{
+    oracle_deme *D = &P->deme[k];
+    uint32_t nn, i;
+    free(D->owner);
+    D->owner = NULL;
+    if (P->prm.regime == REGIME_WF) {
+        uint32_t left = (k + P->n_patches - 1u) % P->n_patches, right = (k + 1u) % P->n_patches;
+        uint32_t sources = D->n_survivors;
+        if (P->mig_T > 0)
+            sources += P->deme[left].n_survivors + P->deme[right].n_survivors;
+        nn = sources > 0 ? D->n : 0;
+    } else {
+        uint64_t ktot = 0;
+        uint32_t slot = 0;
+        for (i = 0; i < D->n_survivors; ++i)
+            ktot += D->kids[i];
+        nn = ktot > P->prm.capacity ? P->prm.capacity : (uint32_t)ktot;
+        D->stats.truncated += ktot - nn;
+        D->owner = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
+        for (i = 0; i < D->n_survivors; ++i) {
+            uint32_t m;
+            for (m = 0; m < D->kids[i]; ++m, ++slot)
+                if (slot < nn)
+                    D->owner[slot] = D->survivors[i];
+        }
+    }
+    D->n_next = nn;
+}
+
+/* The patch offspring j of patch k descends from.  With probability m it
+ * is a migrant whose parents live in a ring neighbour (bit 0 of MIGRATE
+ * word 1 picks the side); a source without survivors passes the draw on,
+ * in the order: drawn patch, home, the picked side, the other side. */
+static uint32_t source_patch(oracle_pop *P, uint32_t k, uint32_t j, uint32_t t)
+{
+    oracle_deme *D = &P->deme[k];
+    uint32_t left, right, side, other, drawn, order[4], q;
+    if (P->mig_T == 0)
+        return k;
+    left = (k + P->n_patches - 1u) % P->n_patches;
+    right = (k + 1u) % P->n_patches;
+    side = (seq_word(&D->rng, j, ST_MIGRATE, t, 1) & 1u) ? right : left;
+    other = side == right ? left : right;
+    drawn = (uint64_t)seq_word(&D->rng, j, ST_MIGRATE, t, 0) < P->mig_T ? side : k;
+    order[0] = drawn;
+    order[1] = k;
+    order[2] = side;
+    order[3] = other;
+    for (q = 0; q < 4; ++q)
+        if (P->deme[order[q]].n_survivors > 0)
+            return order[q];
+    return k; /* unreachable: a patch with no source has no offspring */
+}
+
+/* A (parents) + B + C for the offspring of patch k; the new genomes go to
+ * *next and *znext. */
+static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int32_t **znext)
+{
+    oracle_deme *D = &P->deme[k];
+    uint32_t nn = D->n_next, j, L = P->L;
+    uint8_t *scratch = (uint8_t *)malloc(3u * L);
+    free(D->mom);
+    free(D->dad);
+    free(D->src);
+    D->mom = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
+    D->dad = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
+    D->src = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
+    *next = (uint8_t *)malloc((size_t)(nn ? nn : 1) * 2u * L);
+    *znext = (int32_t *)malloc(sizeof(int32_t) * (nn ? nn : 1));
+    for (j = 0; j < nn; ++j) {
+        uint32_t w0 = seq_word(&D->rng, j, ST_PARENT, t, 0);
+        uint32_t w1 = seq_word(&D->rng, j, ST_PARENT, t, 1);
+        uint32_t w2 = seq_word(&D->rng, j, ST_PARENT, t, 2);
+        uint32_t w3 = seq_word(&D->rng, j, ST_PARENT, t, 3);
+        uint32_t sp = source_patch(P, k, j, t);
+        oracle_deme *S = &P->deme[sp];
+        uint32_t mom, dad;
+        if (P->prm.regime == REGIME_WF)
+            mom = S->survivors[uniform_index(w0, w1, S->n_survivors)];
+        else
+            mom = D->owner[j];
+        dad = S->survivors[uniform_index(w2, w3, S->n_survivors)];
+        D->mom[j] = mom;
+        D->dad[j] = dad;
+        D->src[j] = sp;
+        make_gamete(P, &D->rng, allele_row(P, S->genome, mom, 0), allele_row(P, S->genome, mom, 1), j, t, 0,
+                    allele_row(P, *next, j, 0), scratch);
+        make_gamete(P, &D->rng, allele_row(P, S->genome, dad, 0), allele_row(P, S->genome, dad, 1), j, t, 1,
+                    allele_row(P, *next, j, 1), scratch);
+        (*znext)[j] = phenotype(P, allele_row(P, *next, j, 0), allele_row(P, *next, j, 1));
+    }
+    free(scratch);
+}
+
 int oracle_step(oracle_pop *P, uint32_t n_generations)
 {
-    uint32_t it;
+    uint32_t it, k, np = P->n_patches;
+    uint8_t **next = (uint8_t **)calloc(np, sizeof(uint8_t *));
+    int32_t **znext = (int32_t **)calloc(np, sizeof(int32_t *));
     for (it = 0; it < n_generations; ++it) {
-        uint32_t t = P->generation, n = P->n, L = P->L, i, j;
-        uint32_t ns = 0, nn;
-        uint64_t ktot = 0, sumT = 0;
-        double s = density_factor(P, n);
-        uint8_t *alive = (uint8_t *)calloc(n ? n : 1, 1);
-        uint32_t *kids = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
-        uint32_t *owner = NULL;
-        uint8_t *next;
-        int32_t *znext;
-        uint8_t *scratch = (uint8_t *)malloc(3u * L);
-
-        /* Survival: Bernoulli(v(z) s(N)) per adult. */
-        for (i = 0; i < n; ++i) {
-            double p = viability(P, P->z[i]) * s;
-            uint64_t T = oracle_prob_threshold(p);
-            uint32_t x = seq_word(&P->rng, i, ST_SURVIVE, t, 0);
-            alive[i] = (uint8_t)((uint64_t)x < T);
-            sumT += T;
-            if (p > 0.0 && p < 1.0 && fabs((double)x * (1.0 / TWO32) - p) < 1e-6)
-                P->stats.near_ties++;
-        }
-        /* Removal of the dead: survivors in ascending index order. */
-        free(P->survivors);
-        P->survivors = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
-        for (i = 0; i < n; ++i)
-            if (alive[i])
-                P->survivors[ns++] = i;
-        P->n_survivors = ns;
-
-        /* Neonate count. */
-        if (ns == 0) {
-            nn = 0;
-        } else if (P->prm.regime == REGIME_WF) {
-            nn = n;
-        } else {
-            uint32_t slot = 0;
-            for (i = 0; i < ns; ++i) {
-                kids[i] = draw_by_table(seq_word(&P->rng, P->survivors[i], ST_FECUND, t, 0), P->pois, P->pois_len);
-                ktot += kids[i];
-            }
-            nn = ktot > P->prm.capacity ? P->prm.capacity : (uint32_t)ktot;
-            P->stats.truncated += ktot - nn;
-            owner = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
-            for (i = 0; i < ns; ++i) {
-                uint32_t m;
-                for (m = 0; m < kids[i]; ++m, ++slot)
-                    if (slot < nn)
-                        owner[slot] = P->survivors[i];
-            }
-        }
-
-        /* Parents and transmission. */
-        free(P->mom);
-        free(P->dad);
-        P->mom = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
-        P->dad = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
-        next = (uint8_t *)malloc((size_t)(nn ? nn : 1) * 2u * L);
-        znext = (int32_t *)malloc(sizeof(int32_t) * (nn ? nn : 1));
-        for (j = 0; j < nn; ++j) {
-            uint32_t w0 = seq_word(&P->rng, j, ST_PARENT, t, 0);
-            uint32_t w1 = seq_word(&P->rng, j, ST_PARENT, t, 1);
-            uint32_t w2 = seq_word(&P->rng, j, ST_PARENT, t, 2);
-            uint32_t w3 = seq_word(&P->rng, j, ST_PARENT, t, 3);
-            uint32_t mom, dad;
-            if (P->prm.regime == REGIME_WF)
-                mom = P->survivors[uniform_index(w0, w1, ns)];
-            else
-                mom = owner[j];
-            dad = P->survivors[uniform_index(w2, w3, ns)];
-            P->mom[j] = mom;
-            P->dad[j] = dad;
-            make_gamete(P, allele_row(P, P->genome, mom, 0), allele_row(P, P->genome, mom, 1), j, t, 0, allele_row(P, next, j, 0), scratch);
-            make_gamete(P, allele_row(P, P->genome, dad, 0), allele_row(P, P->genome, dad, 1), j, t, 1, allele_row(P, next, j, 1), scratch);
-            znext[j] = phenotype(P, allele_row(P, next, j, 0), allele_row(P, next, j, 1));
-        }
-        free(P->genome);
-        free(P->z);
-        P->genome = next;
-        P->z = znext;
-        P->n = nn;
+        uint32_t t = P->generation;
+        for (k = 0; k < np; ++k)
+            select_and_count(P, &P->deme[k], t);
+        for (k = 0; k < np; ++k)
+            neonates(P, k);
+        for (k = 0; k < np; ++k)
+            offspring(P, k, t, &next[k], &znext[k]);
         P->generation = t + 1;
-        P->stats.n_parents = n;
-        P->stats.n_survivors = ns;
-        P->stats.sum_threshold = sumT;
-        if (nn == 0)
-            P->stats.extinct = 1;
-        P->stats.updates += (uint64_t)nn * L;
-        census(P);
-        free(alive);
-        free(kids);
-        free(owner);
-        free(scratch);
+        for (k = 0; k < np; ++k) {
+            oracle_deme *D = &P->deme[k];
+            free(D->genome);
+            free(D->z);
+            D->genome = next[k];
+            D->z = znext[k];
+            D->stats.n_parents = D->n;
+            D->stats.n_survivors = D->n_survivors;
+            D->n = D->n_next;
+            if (D->n == 0)
+                D->stats.extinct = 1;
+            D->stats.updates += (uint64_t)D->n * P->L;
+            census(P, D);
+        }
     }
+    free(next);
+    free(znext);
     return 0;
 }
 
 /* ------------------------------------------------------------------ */
-/* Accessors.  Packed layout: individual i, haplotype h, word w holds  */
-/* loci 32w .. 32w+31, locus l at bit l % 32; tail bits are zero.       */
+/* Accessors, per patch.  Packed layout: individual i, haplotype h,    */
+/* word w holds loci 32w .. 32w+31, locus l at bit l % 32; tail bits   */
+/* are zero.                                                            */
 /* ------------------------------------------------------------------ */
-void oracle_get_stats(const oracle_pop *P, oracle_stats *out) { *out = P->stats; }
-uint32_t oracle_get_n(const oracle_pop *P) { return P->n; }
+static oracle_deme *deme_of(const oracle_pop *P, uint32_t patch) { return patch < P->n_patches ? &P->deme[patch] : NULL; }
+
+int oracle_get_stats(const oracle_pop *P, uint32_t patch, oracle_stats *out)
+{
+    oracle_deme *D = deme_of(P, patch);
+    if (!D)
+        return -1;
+    *out = D->stats;
+    return 0;
+}
+uint32_t oracle_get_n(const oracle_pop *P, uint32_t patch) { return deme_of(P, patch) ? P->deme[patch].n : 0; }
 uint32_t oracle_get_generation(const oracle_pop *P) { return P->generation; }
+uint32_t oracle_get_patches(const oracle_pop *P) { return P->n_patches; }
 int oracle_get_mode(const oracle_pop *P) { return P->mode; }
 
-int oracle_get_genomes(const oracle_pop *P, uint32_t *words, size_t n_words)
+int oracle_get_genomes(const oracle_pop *P, uint32_t patch, uint32_t *words, size_t n_words)
 {
     uint32_t W = (P->L + 31u) / 32u, i, h, l;
-    if (n_words < (size_t)P->n * 2u * W)
+    oracle_deme *D = deme_of(P, patch);
+    if (!D || n_words < (size_t)D->n * 2u * W)
         return -1;
-    memset(words, 0, sizeof(uint32_t) * (size_t)P->n * 2u * W);
-    for (i = 0; i < P->n; ++i)
+    memset(words, 0, sizeof(uint32_t) * (size_t)D->n * 2u * W);
+    for (i = 0; i < D->n; ++i)
         for (h = 0; h < 2; ++h) {
-            const uint8_t *row = P->genome + ((size_t)i * 2u + h) * P->L;
+            const uint8_t *row = D->genome + ((size_t)i * 2u + h) * P->L;
             uint32_t *dst = words + ((size_t)i * 2u + h) * W;
             for (l = 0; l < P->L; ++l)
                 dst[l / 32u] |= (uint32_t)row[l] << (l % 32u);
@@ -621,65 +733,77 @@ int oracle_get_genomes(const oracle_pop *P, uint32_t *words, size_t n_words)
     return 0;
 }
 
-int oracle_set_genomes(oracle_pop *P, const uint32_t *words, uint32_t n, uint32_t generation)
+/* Replace patch `patch`'s population at generation `generation` (which
+ * becomes the replicate's generation) and reset its counters. */
+int oracle_set_genomes(oracle_pop *P, uint32_t patch, const uint32_t *words, uint32_t n, uint32_t generation)
 {
     uint32_t W = (P->L + 31u) / 32u, i, h, l;
-    if (n > P->prm.capacity)
+    oracle_deme *D = deme_of(P, patch);
+    if (!D || n > P->prm.capacity)
         return -1;
-    free_pop_state(P);
-    P->genome = (uint8_t *)malloc((size_t)(n ? n : 1) * 2u * P->L);
-    P->z = (int32_t *)malloc(sizeof(int32_t) * (n ? n : 1));
+    free_deme(D);
+    D->genome = (uint8_t *)malloc((size_t)(n ? n : 1) * 2u * P->L);
+    D->z = (int32_t *)malloc(sizeof(int32_t) * (n ? n : 1));
     for (i = 0; i < n; ++i) {
         for (h = 0; h < 2; ++h) {
-            uint8_t *row = P->genome + ((size_t)i * 2u + h) * P->L;
+            uint8_t *row = D->genome + ((size_t)i * 2u + h) * P->L;
             const uint32_t *src = words + ((size_t)i * 2u + h) * W;
             for (l = 0; l < P->L; ++l)
                 row[l] = (uint8_t)((src[l / 32u] >> (l % 32u)) & 1u);
         }
-        P->z[i] = phenotype(P, P->genome + (size_t)i * 2u * P->L, P->genome + ((size_t)i * 2u + 1u) * P->L);
+        D->z[i] = phenotype(P, D->genome + (size_t)i * 2u * P->L, D->genome + ((size_t)i * 2u + 1u) * P->L);
     }
-    P->n = n;
+    D->n = n;
     P->generation = generation;
-    P->n_survivors = 0;
-    memset(&P->stats, 0, sizeof P->stats);
-    P->stats.extinct = n == 0;
-    census(P);
+    D->n_survivors = 0;
+    memset(&D->stats, 0, sizeof D->stats);
+    D->stats.extinct = n == 0;
+    census(P, D);
     return 0;
 }
 
-int oracle_get_phenotypes(const oracle_pop *P, int32_t *z, size_t n)
+int oracle_get_phenotypes(const oracle_pop *P, uint32_t patch, int32_t *z, size_t n)
 {
-    if (n < P->n)
+    oracle_deme *D = deme_of(P, patch);
+    if (!D || n < D->n)
         return -1;
-    memcpy(z, P->z, sizeof(int32_t) * P->n);
+    memcpy(z, D->z, sizeof(int32_t) * D->n);
     return 0;
 }
 
-uint32_t oracle_get_survivors(const oracle_pop *P, uint32_t *S, size_t n)
+uint32_t oracle_get_survivors(const oracle_pop *P, uint32_t patch, uint32_t *S, size_t n)
 {
-    if (S && n >= P->n_survivors)
-        memcpy(S, P->survivors, sizeof(uint32_t) * P->n_survivors);
-    return P->n_survivors;
+    oracle_deme *D = deme_of(P, patch);
+    if (!D)
+        return 0;
+    if (S && n >= D->n_survivors)
+        memcpy(S, D->survivors, sizeof(uint32_t) * D->n_survivors);
+    return D->n_survivors;
 }
 
-int oracle_get_parents(const oracle_pop *P, uint32_t *mom, uint32_t *dad, size_t n)
+/* Parents of the current newborns of a patch: indices into the adults of
+ * their source patch, and that patch. */
+int oracle_get_parents(const oracle_pop *P, uint32_t patch, uint32_t *mom, uint32_t *dad, uint32_t *src, size_t n)
 {
-    if (n < P->n)
+    oracle_deme *D = deme_of(P, patch);
+    if (!D || n < D->n || (D->n > 0 && !D->mom))
         return -1;
-    memcpy(mom, P->mom, sizeof(uint32_t) * P->n);
-    memcpy(dad, P->dad, sizeof(uint32_t) * P->n);
+    memcpy(mom, D->mom, sizeof(uint32_t) * D->n);
+    memcpy(dad, D->dad, sizeof(uint32_t) * D->n);
+    if (src)
+        memcpy(src, D->src, sizeof(uint32_t) * D->n);
     return 0;
 }
 
-/* Gametes of one parent for offspring slots j0 .. j0+count-1 in
- * generation gen (the statistical pins sample this directly).  parent is
- * 2L bytes (haplotype 0 then 1); out is count x L bytes. */
+/* Gametes of one parent for offspring slots j0 .. j0+count-1 of patch 0
+ * in generation gen (the statistical pins sample this directly).  parent
+ * is 2L bytes (haplotype 0 then 1); out is count x L bytes. */
 int oracle_sample_gametes(oracle_pop *P, const uint8_t *parent, uint32_t j0, uint32_t count, uint32_t gen, int paternal, uint8_t *out)
 {
     uint32_t c;
     uint8_t *scratch = (uint8_t *)malloc(3u * P->L);
     for (c = 0; c < count; ++c)
-        make_gamete(P, parent, parent + P->L, j0 + c, gen, paternal, out + (size_t)c * P->L, scratch);
+        make_gamete(P, &P->deme[0].rng, parent, parent + P->L, j0 + c, gen, paternal, out + (size_t)c * P->L, scratch);
     free(scratch);
     return 0;
 }
