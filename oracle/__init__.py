@@ -5,6 +5,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 its binding) never does, and this package imports nothing from it.
 """
 from .oracle import (  # noqa: F401
+    OracleEcology,
     OracleParams,
     OraclePop,
     OracleStats,
@@ -15,4 +16,5 @@ from .oracle import (  # noqa: F401
     poisson_thresholds,
     prob_threshold,
     recomb_mode,
+    small_binomial_thresholds,
 )

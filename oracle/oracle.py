@@ -15,6 +15,35 @@ ALWAYS = 1 << 32
 MODE_NAMES = {0: "raw", 1: "zero", 2: "skip", 3: "lazy"}
 
 
+class OracleEcology(C.Structure):
+    _fields_ = [
+        ("n0_consumer", C.c_uint32),
+        ("capacity_consumer", C.c_uint32),
+        ("resource_trials", C.c_uint32),
+        ("habitat", C.c_uint32),
+        ("attack", C.c_double),
+        ("match_width", C.c_double),
+        ("encounters", C.c_double),
+        ("conversion", C.c_double),
+        ("resource_q0", C.c_double),
+        ("resource_K", C.c_double),
+        ("surv_resource", C.c_double * 4),
+        ("surv_consumer", C.c_double * 4),
+    ]
+
+
+def make_ecology(eco):
+    e = OracleEcology()
+    for k, v in eco.items():
+        if k in ("surv_resource", "surv_consumer"):
+            arr = getattr(e, k)
+            for a in range(4):
+                arr[a] = float(v[a])
+        else:
+            setattr(e, k, v)
+    return e
+
+
 class OracleParams(C.Structure):
     _fields_ = [
         ("seed", C.c_uint64),
@@ -32,6 +61,7 @@ class OracleParams(C.Structure):
         ("fecundity", C.c_double),
         ("migration", C.c_double),
         ("effects", C.POINTER(C.c_int8)),
+        ("ecology", C.POINTER(OracleEcology)),
     ]
 
 
@@ -42,7 +72,7 @@ class OracleStats(C.Structure):
         ("n_parents", C.c_uint32),
         ("n_survivors", C.c_uint32),
         ("extinct", C.c_uint32),
-        ("reserved", C.c_uint32),
+        ("captures", C.c_uint32),
         ("sum_z", C.c_int64),
         ("sum_z2", C.c_int64),
         ("near_ties", C.c_uint64),
@@ -52,7 +82,7 @@ class OracleStats(C.Structure):
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None
@@ -80,6 +110,8 @@ def load():
     lib.oracle_binomial_thresholds.restype = C.c_int
     lib.oracle_geometric_thresholds.argtypes = [C.c_double, u32, P64]
     lib.oracle_geometric_thresholds.restype = None
+    lib.oracle_small_binomial_thresholds.argtypes = [u32, C.c_double, P64]
+    lib.oracle_small_binomial_thresholds.restype = C.c_int
     lib.oracle_recomb_mode.argtypes = [C.c_double]
     lib.oracle_recomb_mode.restype = C.c_int
     lib.oracle_create.argtypes = [C.POINTER(OracleParams)]
@@ -94,8 +126,14 @@ def load():
     lib.oracle_get_n.restype = u32
     lib.oracle_get_generation.argtypes = [vp]
     lib.oracle_get_generation.restype = u32
-    lib.oracle_get_patches.argtypes = [vp]
-    lib.oracle_get_patches.restype = u32
+    lib.oracle_get_demes.argtypes = [vp]
+    lib.oracle_get_demes.restype = u32
+    lib.oracle_get_newborns.argtypes = [vp, u32]
+    lib.oracle_get_newborns.restype = u32
+    lib.oracle_get_ages.argtypes = [vp, u32, C.POINTER(C.c_uint8), C.c_size_t]
+    lib.oracle_get_ages.restype = C.c_int
+    lib.oracle_get_intake.argtypes = [vp, P32, C.c_size_t]
+    lib.oracle_get_intake.restype = C.c_int
     lib.oracle_get_mode.argtypes = [vp]
     lib.oracle_get_mode.restype = C.c_int
     lib.oracle_get_genomes.argtypes = [vp, u32, P32, C.c_size_t]
@@ -151,18 +189,26 @@ def geometric_thresholds(r, n):
     return out[: int(n)].copy()
 
 
+def small_binomial_thresholds(n, q):
+    out = np.zeros(int(n) + 1, dtype=np.uint64)
+    k = load().oracle_small_binomial_thresholds(int(n), float(q), _p(out, C.c_uint64))
+    return out[:k].copy()
+
+
 def recomb_mode(r):
     return MODE_NAMES[load().oracle_recomb_mode(float(r))]
 
 
 class OraclePop:
     """One replicate in the oracle: a ring of ``n_patches`` patches (one by
-    default).  Per-patch accessors take ``patch``; ``total_stats`` sums the
-    census over the patches."""
+    default), or the two species of the consumer-resource regime
+    (``ecology`` given; species 0 resource, 1 consumer).  Per-deme
+    accessors take ``patch`` or ``species``; ``total_stats`` sums the census
+    over the demes."""
 
     def __init__(self, seed=1, replicate_id=0, regime=0, n0=100, capacity=None, n_loci=64,
                  mu=0.0, r=0.5, theta=0.0, omega=0.0, K=0.0, fecundity=0.0, effects=None,
-                 n_patches=1, migration=0.0):
+                 n_patches=1, migration=0.0, ecology=None):
         lib = load()
         self.L = int(n_loci)
         self.W = (self.L + 31) // 32
@@ -173,15 +219,17 @@ class OraclePop:
             self._effects = np.ascontiguousarray(effects, dtype=np.int8)
             assert self._effects.shape == (self.L,)
             eff_ptr = _p(self._effects, C.c_int8)
+        self._eco = make_ecology(ecology) if ecology is not None else None
         prm = OracleParams(seed=seed, replicate_id=replicate_id, regime=regime, n0=n0,
                            capacity=n0 if capacity is None else capacity, n_loci=n_loci, n_patches=n_patches,
                            mu=mu, r=r, theta=theta, omega=omega, K=K, fecundity=fecundity, migration=migration,
-                           effects=eff_ptr)
+                           effects=eff_ptr, ecology=C.pointer(self._eco) if self._eco is not None else None)
         self.capacity = prm.capacity
         self._h = lib.oracle_create(C.byref(prm))
         if not self._h:
             raise ValueError("oracle_create rejected the parameters")
         self._lib = lib
+        self.n_demes = int(lib.oracle_get_demes(self._h))
 
     def close(self):
         if self._h:
@@ -197,12 +245,16 @@ class OraclePop:
     def step(self, n=1):
         self._lib.oracle_step(self._h, int(n))
 
+    @staticmethod
+    def _deme(patch, species):
+        return int(patch) + int(species)  # one of them is 0: rings have one species, two species one patch
+
     @property
     def n(self):
         return int(self._lib.oracle_get_n(self._h, 0))
 
-    def n_of(self, patch):
-        return int(self._lib.oracle_get_n(self._h, int(patch)))
+    def n_of(self, patch=0, species=0):
+        return int(self._lib.oracle_get_n(self._h, self._deme(patch, species)))
 
     @property
     def generation(self):
@@ -212,57 +264,79 @@ class OraclePop:
     def mode(self):
         return MODE_NAMES[self._lib.oracle_get_mode(self._h)]
 
-    def stats(self, patch=0):
+    def stats(self, patch=0, species=0):
         s = OracleStats()
-        assert self._lib.oracle_get_stats(self._h, int(patch), C.byref(s)) == 0
+        assert self._lib.oracle_get_stats(self._h, self._deme(patch, species), C.byref(s)) == 0
         return s.as_dict()
 
     def total_stats(self):
-        """The census summed over patches (generation and extinct: shared)."""
-        per = [self.stats(k) for k in range(self.n_patches)]
+        """The census summed over demes (generation: shared; extinct: all)."""
+        per = [self.stats(k) for k in range(self.n_demes)]
         out = {k: sum(p[k] for p in per) for k in per[0]}
         out["generation"] = per[0]["generation"]
         out["extinct"] = int(all(p["extinct"] for p in per))
         return out
 
-    def genomes(self, patch=0):
+    def genomes(self, patch=0, species=0):
         """Packed genomes, shape (n, 2, W) uint32."""
-        n = self.n_of(patch)
+        d = self._deme(patch, species)
+        n = self.n_of(d)
         out = np.zeros(max(n, 1) * 2 * self.W, dtype=np.uint32)
-        assert self._lib.oracle_get_genomes(self._h, int(patch), _p(out, C.c_uint32), out.size) == 0
+        assert self._lib.oracle_get_genomes(self._h, d, _p(out, C.c_uint32), out.size) == 0
         return out[: n * 2 * self.W].reshape(n, 2, self.W)
 
-    def alleles(self, patch=0):
+    def alleles(self, patch=0, species=0):
         """Unpacked alleles, shape (n, 2, L) uint8."""
-        g = self.genomes(patch)
+        g = self.genomes(patch, species)
         bits = np.unpackbits(g.view(np.uint8).reshape(g.shape[0], 2, -1), axis=-1, bitorder="little")
         return bits[..., : self.L]
 
-    def set_genomes(self, words, generation, patch=0):
+    def set_genomes(self, words, generation, patch=0, species=0):
         w = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1)
         n = w.size // (2 * self.W)
-        assert self._lib.oracle_set_genomes(self._h, int(patch), _p(w, C.c_uint32), n, int(generation)) == 0
+        assert self._lib.oracle_set_genomes(self._h, self._deme(patch, species), _p(w, C.c_uint32), n,
+                                            int(generation)) == 0
 
-    def phenotypes(self, patch=0):
-        n = self.n_of(patch)
+    def phenotypes(self, patch=0, species=0):
+        d = self._deme(patch, species)
+        n = self.n_of(d)
         out = np.zeros(max(n, 1), dtype=np.int32)
-        assert self._lib.oracle_get_phenotypes(self._h, int(patch), _p(out, C.c_int32), out.size) == 0
+        assert self._lib.oracle_get_phenotypes(self._h, d, _p(out, C.c_int32), out.size) == 0
         return out[:n]
 
-    def survivors(self, patch=0):
-        m = self._lib.oracle_get_survivors(self._h, int(patch), None, 0)
+    def ages(self, patch=0, species=0):
+        d = self._deme(patch, species)
+        n = self.n_of(d)
+        out = np.zeros(max(n, 1), dtype=np.uint8)
+        assert self._lib.oracle_get_ages(self._h, d, _p(out, C.c_uint8), out.size) == 0
+        return out[:n]
+
+    def intake(self):
+        """Consumers' credited captures in the last generation, by adult index."""
+        n = self.stats(species=1)["n_parents"]
+        out = np.zeros(max(n, 1), dtype=np.uint32)
+        assert self._lib.oracle_get_intake(self._h, _p(out, C.c_uint32), out.size) == 0
+        return out[:n]
+
+    def survivors(self, patch=0, species=0):
+        d = self._deme(patch, species)
+        m = self._lib.oracle_get_survivors(self._h, d, None, 0)
         out = np.zeros(max(m, 1), dtype=np.uint32)
-        self._lib.oracle_get_survivors(self._h, int(patch), _p(out, C.c_uint32), out.size)
+        self._lib.oracle_get_survivors(self._h, d, _p(out, C.c_uint32), out.size)
         return out[:m]
 
-    def parents(self, patch=0, with_source=False):
-        """Mother and father of each current newborn (indices into the adults
-        of its source patch) and, with_source, that patch."""
-        n = self.n_of(patch)
+    def newborns(self, patch=0, species=0):
+        return int(self._lib.oracle_get_newborns(self._h, self._deme(patch, species)))
+
+    def parents(self, patch=0, with_source=False, species=0):
+        """Mother and father of each newborn of the last generation (indices
+        into the adults of its source patch) and, with_source, that patch."""
+        d = self._deme(patch, species)
+        n = self.newborns(d)
         mom = np.zeros(max(n, 1), dtype=np.uint32)
         dad = np.zeros(max(n, 1), dtype=np.uint32)
         src = np.zeros(max(n, 1), dtype=np.uint32)
-        assert self._lib.oracle_get_parents(self._h, int(patch), _p(mom, C.c_uint32), _p(dad, C.c_uint32),
+        assert self._lib.oracle_get_parents(self._h, d, _p(mom, C.c_uint32), _p(dad, C.c_uint32),
                                             _p(src, C.c_uint32), mom.size) == 0
         if with_source:
             return mom[:n], dad[:n], src[:n]

@@ -48,10 +48,12 @@ enum {
     ST_RECOMB_PAT = 7,
     ST_MUTATE_MAT = 8,
     ST_MUTATE_PAT = 9,
-    ST_MIGRATE = 10
+    ST_MIGRATE = 10,
+    ST_ENCOUNTER = 11,
+    ST_CAPTURE = 12
 };
 
-enum { REGIME_WF = 0, REGIME_POISSON_BH = 1 };
+enum { REGIME_WF = 0, REGIME_POISSON_BH = 1, REGIME_CONSUMER_RESOURCE = 2 };
 enum { MODE_RAW = 0, MODE_ZERO = 1, MODE_SKIP = 2, MODE_LAZY = 3 };
 
 /* ------------------------------------------------------------------ */
@@ -213,6 +215,21 @@ static uint32_t draw_by_table(uint32_t x, const uint64_t *T, int len)
 /* ------------------------------------------------------------------ */
 /* Parameters, state, statistics.                                      */
 /* ------------------------------------------------------------------ */
+/* The consumer-resource regime's extra parameters: the resource is species
+ * 0 (census n0 / capacity of the parameters), the consumer species 1. */
+typedef struct {
+    uint32_t n0_consumer, capacity_consumer;
+    uint32_t resource_trials; /* offspring trials per surviving resource */
+    uint32_t habitat;         /* slots an encounter lands on uniformly; 0: the resource census */
+    double attack;      /* capture probability at a perfect phenotype match */
+    double match_width; /* width of the Gaussian matching of phenotypes */
+    double encounters;  /* mean encounters per consumer and generation */
+    double conversion;  /* consumer offspring mean per credited capture */
+    double resource_q0; /* per-trial success of a resource at low density */
+    double resource_K;  /* resource density scale of the logistic factor */
+    double surv_resource[4], surv_consumer[4]; /* survival by age 0..3 */
+} oracle_ecology;
+
 typedef struct {
     uint64_t seed;
     uint32_t replicate_id;
@@ -223,26 +240,33 @@ typedef struct {
     double mu, r, theta, omega, K, fecundity;
     double migration; /* backward migration rate to the two ring neighbours */
     const int8_t *effects; /* n_loci values, NULL: all +1 */
+    const oracle_ecology *ecology; /* consumer-resource regime only */
 } oracle_params;
 
 typedef struct {
-    uint32_t generation, n, n_parents, n_survivors, extinct, reserved;
+    uint32_t generation, n, n_parents, n_survivors, extinct;
+    uint32_t captures; /* consumers: credited captures of the last generation */
     int64_t sum_z, sum_z2;
     uint64_t near_ties, truncated, sum_threshold;
     uint64_t updates; /* cumulative genotype-locus updates, sum of N_t L */
 } oracle_stats;
 
-/* One patch of a replicate: its own individuals and its own Philox
- * counter field c3 = replicate << 12 | patch (species 0). */
+/* One patch of one species of a replicate (a deme): its own individuals
+ * and its own Philox counter field c3 = replicate << 12 | species << 10 |
+ * patch. */
 typedef struct {
     rng_ctx rng;
+    uint32_t species, cap;
     uint32_t n;
     uint8_t *genome; /* genome[i][h][l], one byte per allele */
     int32_t *z;
+    uint8_t *age;    /* consumer-resource regime: age of each individual */
     /* the last generation's survivors, fecundities and parents */
     uint32_t *survivors, n_survivors;
-    uint32_t *kids, *owner, n_next;
+    uint32_t *kids, *owner, n_next, n_carry;
     uint32_t *mom, *dad, *src;
+    uint64_t *won;     /* resources: lowest key of a capture this generation */
+    uint32_t *intake;  /* consumers: credited captures this generation */
     oracle_stats stats;
 } oracle_deme;
 
@@ -257,8 +281,16 @@ typedef struct {
     uint64_t *pois;
     int pois_len;
     uint64_t mig_T; /* migration threshold, 0: no migration */
-    uint32_t generation, n_patches;
+    uint32_t generation, n_patches, n_demes;
     oracle_deme *deme;
+    /* consumer-resource regime */
+    oracle_ecology eco;
+    uint64_t *enc;  /* encounters per consumer, Poisson(encounters) */
+    int enc_len;
+    uint64_t *capT; /* capture threshold by |z_c - z_r| */
+    uint32_t capT_len;
+    uint64_t *cpois; /* consumer offspring: Poisson(conversion m) for intake m, TABLE_CAP each */
+    int *cpois_len;
 } oracle_pop;
 
 #define TABLE_CAP 1024
@@ -315,6 +347,12 @@ static void free_deme(oracle_deme *D)
 {
     free(D->genome);
     free(D->z);
+    free(D->age);
+    free(D->won);
+    free(D->intake);
+    D->age = NULL;
+    D->won = NULL;
+    D->intake = NULL;
     free(D->survivors);
     free(D->kids);
     free(D->owner);
@@ -332,9 +370,13 @@ void oracle_destroy(oracle_pop *P)
     if (!P)
         return;
     if (P->deme)
-        for (k = 0; k < P->n_patches; ++k)
+        for (k = 0; k < P->n_demes; ++k)
             free_deme(&P->deme[k]);
     free(P->deme);
+    free(P->enc);
+    free(P->capT);
+    free(P->cpois);
+    free(P->cpois_len);
     free(P->effects);
     free(P->geo);
     free(P->binom);
@@ -342,7 +384,7 @@ void oracle_destroy(oracle_pop *P)
     free(P);
 }
 
-static void census(oracle_pop *P, oracle_deme *D)
+static void census(const oracle_pop *P, oracle_deme *D)
 {
     uint32_t i;
     D->stats.generation = P->generation;
@@ -355,13 +397,56 @@ static void census(oracle_pop *P, oracle_deme *D)
     }
 }
 
+/* Consumer-resource tables: encounters per consumer, capture threshold by
+ * phenotype distance, consumer offspring by intake. */
+static void build_ecology(oracle_pop *P)
+{
+    const oracle_ecology *E = &P->eco;
+    uint32_t d, m;
+    int32_t abs_sum = 0;
+    uint32_t l;
+    for (l = 0; l < P->L; ++l)
+        abs_sum += P->effects[l] < 0 ? -P->effects[l] : P->effects[l];
+    P->enc = (uint64_t *)malloc(sizeof(uint64_t) * TABLE_CAP);
+    P->enc_len = oracle_poisson_thresholds(E->encounters, P->enc, TABLE_CAP);
+    /* |z_c - z_r| <= 2 sum |e_l| */
+    P->capT_len = 2u * (uint32_t)abs_sum + 1u;
+    P->capT = (uint64_t *)malloc(sizeof(uint64_t) * P->capT_len);
+    for (d = 0; d < P->capT_len; ++d) {
+        double dd = (double)d;
+        P->capT[d] = oracle_prob_threshold(E->attack * exp(-(dd * dd) / (2.0 * E->match_width * E->match_width)));
+    }
+    /* intake never exceeds the encounters, at most enc_len - 1 */
+    P->cpois = (uint64_t *)malloc(sizeof(uint64_t) * TABLE_CAP * (size_t)P->enc_len);
+    P->cpois_len = (int *)malloc(sizeof(int) * (size_t)P->enc_len);
+    for (m = 0; m < (uint32_t)P->enc_len; ++m)
+        P->cpois_len[m] = oracle_poisson_thresholds(E->conversion * (double)m, P->cpois + (size_t)m * TABLE_CAP, TABLE_CAP);
+}
+
+static int ecology_ok(const oracle_ecology *E)
+{
+    int a;
+    if (!E || E->n0_consumer > E->capacity_consumer || E->capacity_consumer < 1 || E->resource_trials < 1 ||
+        E->resource_trials > 64 || !(E->attack >= 0.0 && E->attack <= 1.0) || !(E->match_width > 0.0) ||
+        !(E->encounters >= 0.0) || !(E->conversion >= 0.0) || !(E->resource_q0 >= 0.0 && E->resource_q0 <= 1.0) ||
+        !(E->resource_K > 0.0))
+        return 0;
+    for (a = 0; a < 4; ++a)
+        if (!(E->surv_resource[a] >= 0.0 && E->surv_resource[a] <= 1.0) ||
+            !(E->surv_consumer[a] >= 0.0 && E->surv_consumer[a] <= 1.0))
+            return 0;
+    return 1;
+}
+
 oracle_pop *oracle_create(const oracle_params *prm)
 {
     oracle_pop *P;
     uint32_t L = prm->n_loci, l, i, h, k;
+    int cr = prm->regime == REGIME_CONSUMER_RESOURCE;
     if (L == 0 || prm->n0 > prm->capacity || !(prm->mu >= 0.0 && prm->mu < 1.0) || !(prm->r >= 0.0 && prm->r <= 0.5) ||
         prm->n_patches < 1 || prm->n_patches > 1024 || !(prm->migration >= 0.0 && prm->migration <= 1.0) ||
-        (prm->n_patches > 1 && prm->regime != REGIME_WF))
+        (prm->n_patches > 1 && prm->regime != REGIME_WF) || prm->regime > REGIME_CONSUMER_RESOURCE ||
+        (cr && !ecology_ok(prm->ecology)))
         return NULL;
     P = (oracle_pop *)calloc(1, sizeof *P);
     if (!P)
@@ -372,6 +457,7 @@ oracle_pop *oracle_create(const oracle_params *prm)
     for (l = 0; l < L; ++l)
         P->effects[l] = prm->effects ? prm->effects[l] : 1;
     P->prm.effects = P->effects;
+    P->prm.ecology = NULL;
     P->mode = oracle_recomb_mode(prm->r);
     P->geo = (uint64_t *)malloc(sizeof(uint64_t) * (L > 1 ? L - 1 : 1));
     oracle_geometric_thresholds(prm->r, L - 1, P->geo);
@@ -380,23 +466,32 @@ oracle_pop *oracle_create(const oracle_params *prm)
     P->pois = (uint64_t *)malloc(sizeof(uint64_t) * TABLE_CAP);
     P->pois_len = oracle_poisson_thresholds(prm->fecundity, P->pois, TABLE_CAP);
     P->n_patches = prm->n_patches;
+    P->n_demes = cr ? 2u : prm->n_patches;
     P->mig_T = prm->n_patches > 1 ? oracle_prob_threshold(prm->migration) : 0;
-    P->deme = (oracle_deme *)calloc(P->n_patches, sizeof(oracle_deme));
+    if (cr) {
+        P->eco = *prm->ecology;
+        build_ecology(P);
+    }
+    P->deme = (oracle_deme *)calloc(P->n_demes, sizeof(oracle_deme));
     P->generation = 0;
 
     /* Initial state: every allele an independent fair bit (Hardy-Weinberg,
      * allele frequency one half), drawn from stream INIT in generation 0,
-     * patch by patch. */
-    for (k = 0; k < P->n_patches; ++k) {
+     * deme by deme; every individual of age 0. */
+    for (k = 0; k < P->n_demes; ++k) {
         oracle_deme *D = &P->deme[k];
         uint32_t W = (L + 31u) / 32u;
+        uint32_t n0 = cr && k == 1 ? P->eco.n0_consumer : prm->n0;
+        D->species = cr ? k : 0u;
+        D->cap = cr && k == 1 ? P->eco.capacity_consumer : prm->capacity;
         D->rng.key[0] = (uint32_t)prm->seed;
         D->rng.key[1] = (uint32_t)(prm->seed >> 32);
-        D->rng.c3 = (prm->replicate_id << 12) | k; /* species 0 */
-        D->n = prm->n0;
-        D->genome = (uint8_t *)malloc((size_t)(prm->n0 ? prm->n0 : 1) * 2u * L);
-        D->z = (int32_t *)malloc(sizeof(int32_t) * (prm->n0 ? prm->n0 : 1));
-        for (i = 0; i < prm->n0; ++i) {
+        D->rng.c3 = (prm->replicate_id << 12) | (D->species << 10) | (cr ? 0u : k);
+        D->n = n0;
+        D->genome = (uint8_t *)malloc((size_t)(n0 ? n0 : 1) * 2u * L);
+        D->z = (int32_t *)malloc(sizeof(int32_t) * (n0 ? n0 : 1));
+        D->age = (uint8_t *)calloc(n0 ? n0 : 1, 1);
+        for (i = 0; i < n0; ++i) {
             for (h = 0; h < 2; ++h) {
                 uint8_t *row = allele_row(P, D->genome, i, h);
                 for (l = 0; l < L; ++l) {
@@ -408,7 +503,7 @@ oracle_pop *oracle_create(const oracle_params *prm)
         }
         census(P, D);
         D->stats.n_parents = 0;
-        D->stats.extinct = prm->n0 == 0;
+        D->stats.extinct = n0 == 0;
     }
     return P;
 }
@@ -527,18 +622,131 @@ static void make_gamete(const oracle_pop *P, rng_ctx *g, const uint8_t *h0, cons
 /* each patch linked by migration to its neighbouring patches).        */
 /* ------------------------------------------------------------------ */
 
-/* D, E and the offspring counts of A in one patch. */
+/* Consumer-resource regime, before survival (step 1 of the generation):
+ * every consumer meets Poisson(encounters) resources drawn uniformly, with
+ * replacement, from the resource census, and captures one when its
+ * CAPTURE word falls below the threshold of a exp(-(z_c - z_r)^2 /
+ * (2 sigma^2)).  A resource captured more than once is credited to the
+ * capture with the lowest (consumer, encounter) pair; captured resources
+ * die.  A consumer's intake is its number of credited captures. */
+static uint32_t encounter_count(oracle_pop *P, oracle_deme *C, uint32_t i, uint32_t t, uint32_t NR)
+{
+    if (NR == 0)
+        return 0;
+    return draw_by_table(seq_word(&C->rng, i, ST_ENCOUNTER, t, 0), P->enc, P->enc_len);
+}
+
+/* Target resource of encounter e of consumer i, or NR when nothing is
+ * captured.  The encounter lands on a uniform slot of the habitat (at
+ * least the resource census): a slot below N_R holds that resource, the
+ * others are empty, so encounters fall in proportion to N_R / habitat. */
+static uint32_t capture_of(oracle_pop *P, uint32_t i, uint32_t e, uint32_t t)
+{
+    oracle_deme *R = &P->deme[0], *C = &P->deme[1];
+    uint32_t NR = R->n, span = P->eco.habitat > NR ? P->eco.habitat : NR;
+    uint32_t tgt = uniform_index(seq_word(&C->rng, i, ST_ENCOUNTER, t, 1u + 2u * e),
+                                 seq_word(&C->rng, i, ST_ENCOUNTER, t, 2u + 2u * e), span);
+    int32_t dz;
+    if (tgt >= NR)
+        return NR;
+    dz = C->z[i] - R->z[tgt];
+    uint32_t d = (uint32_t)(dz < 0 ? -dz : dz);
+    return (uint64_t)seq_word(&C->rng, i, ST_CAPTURE, t, e) < P->capT[d] ? tgt : NR;
+}
+
+static void encounters(oracle_pop *P, uint32_t t)
+{
+    oracle_deme *R = &P->deme[0], *C = &P->deme[1];
+    uint32_t NR = R->n, NC = C->n, i, e;
+    free(R->won);
+    free(C->intake);
+    R->won = (uint64_t *)malloc(sizeof(uint64_t) * (NR ? NR : 1));
+    C->intake = (uint32_t *)calloc(NC ? NC : 1, sizeof(uint32_t));
+    for (i = 0; i < NR; ++i)
+        R->won[i] = UINT64_MAX;
+    /* captures, each resource keeping its lowest (consumer, encounter) */
+    for (i = 0; i < NC; ++i) {
+        uint32_t ne = encounter_count(P, C, i, t, NR);
+        for (e = 0; e < ne; ++e) {
+            uint32_t tgt = capture_of(P, i, e, t);
+            uint64_t key = ((uint64_t)i << 32) | e;
+            if (tgt < NR && key < R->won[tgt])
+                R->won[tgt] = key;
+        }
+    }
+    /* credit */
+    C->stats.captures = 0;
+    for (i = 0; i < NC; ++i) {
+        uint32_t ne = encounter_count(P, C, i, t, NR);
+        for (e = 0; e < ne; ++e) {
+            uint32_t tgt = capture_of(P, i, e, t);
+            if (tgt < NR && R->won[tgt] == (((uint64_t)i << 32) | e))
+                C->intake[i]++;
+        }
+        C->stats.captures += C->intake[i];
+    }
+}
+
+/* Binomial(n, q) inverse-CDF thresholds from IEEE double basic operations
+ * (the resource's density-dependent fecundity, recomputed every
+ * generation): P(k) = C(n, k) q^k (1-q)^(n-k), the coefficient by the
+ * recurrence C(n, k) = C(n, k-1) (n-k+1) / k, the powers by repeated
+ * multiplication, F accumulated in order. */
+int oracle_small_binomial_thresholds(uint32_t n, double q, uint64_t *T)
+{
+    double u = 1.0 - q, c = 1.0, F = 0.0;
+    uint32_t k, m;
+    for (k = 0; k <= n; ++k) {
+        double pk;
+        uint64_t thr;
+        if (k > 0)
+            c = c * (double)(n - k + 1u) / (double)k;
+        pk = c;
+        for (m = 0; m < k; ++m)
+            pk = pk * q;
+        for (m = 0; m < n - k; ++m)
+            pk = pk * u;
+        F = F + pk;
+        thr = oracle_prob_threshold(F);
+        if (thr >= 4294967295ULL || k == n) {
+            T[k] = ORACLE_ALWAYS;
+            return (int)k + 1;
+        }
+        T[k] = thr;
+    }
+    return (int)n + 1;
+}
+
+/* Survival probability of individual i of deme D: v(z) times the
+ * Beverton-Holt factor (Poisson regime) or the survival of its age class
+ * (consumer-resource regime). */
+static double survival_probability(const oracle_pop *P, const oracle_deme *D, uint32_t i, double s)
+{
+    if (P->prm.regime == REGIME_CONSUMER_RESOURCE) {
+        const double *sa = D->species == 0 ? P->eco.surv_resource : P->eco.surv_consumer;
+        return viability(P, D->z[i]) * sa[D->age[i]];
+    }
+    return viability(P, D->z[i]) * s;
+}
+
+/* D, E and the offspring counts of A in one deme. */
 static void select_and_count(oracle_pop *P, oracle_deme *D, uint32_t t)
 {
     uint32_t n = D->n, i, ns = 0;
     uint64_t sumT = 0;
     double s = density_factor(P, n);
+    int cr = P->prm.regime == REGIME_CONSUMER_RESOURCE;
     uint8_t *alive = (uint8_t *)calloc(n ? n : 1, 1);
-    /* Survival: Bernoulli(v(z) s(N)) per adult. */
+    /* Survival: Bernoulli(p) per adult; a captured resource dies. */
     for (i = 0; i < n; ++i) {
-        double p = viability(P, D->z[i]) * s;
-        uint64_t T = oracle_prob_threshold(p);
-        uint32_t x = seq_word(&D->rng, i, ST_SURVIVE, t, 0);
+        double p;
+        uint64_t T;
+        uint32_t x;
+        if (cr && D->species == 0 && D->won[i] != UINT64_MAX)
+            continue;
+        p = survival_probability(P, D, i, s);
+        T = oracle_prob_threshold(p);
+        x = seq_word(&D->rng, i, ST_SURVIVE, t, 0);
         alive[i] = (uint8_t)((uint64_t)x < T);
         sumT += T;
         if (p > 0.0 && p < 1.0 && fabs((double)x * (1.0 / TWO32) - p) < 1e-6)
@@ -553,26 +761,46 @@ static void select_and_count(oracle_pop *P, oracle_deme *D, uint32_t t)
     D->n_survivors = ns;
     D->stats.sum_threshold = sumT;
     free(alive);
-    /* Poisson regime: each survivor's offspring count as mother. */
+    /* Offspring counts as mother: Poisson(fecundity) in the Poisson regime;
+     * resources Binomial(trials, q0 max(0, 1 - N_R/K_R)), consumers
+     * Poisson(conversion x intake) in the consumer-resource regime. */
     free(D->kids);
     D->kids = NULL;
     if (P->prm.regime == REGIME_POISSON_BH) {
         D->kids = (uint32_t *)malloc(sizeof(uint32_t) * (ns ? ns : 1));
         for (i = 0; i < ns; ++i)
             D->kids[i] = draw_by_table(seq_word(&D->rng, D->survivors[i], ST_FECUND, t, 0), P->pois, P->pois_len);
+    } else if (cr) {
+        D->kids = (uint32_t *)malloc(sizeof(uint32_t) * (ns ? ns : 1));
+        if (D->species == 0) {
+            uint64_t T[65];
+            double x = 1.0 - (double)n / P->eco.resource_K;
+            int len = oracle_small_binomial_thresholds(P->eco.resource_trials, P->eco.resource_q0 * (x > 0.0 ? x : 0.0), T);
+            for (i = 0; i < ns; ++i)
+                D->kids[i] = draw_by_table(seq_word(&D->rng, D->survivors[i], ST_FECUND, t, 0), T, len);
+        } else {
+            for (i = 0; i < ns; ++i) {
+                uint32_t m = D->intake[D->survivors[i]];
+                D->kids[i] = draw_by_table(seq_word(&D->rng, D->survivors[i], ST_FECUND, t, 0),
+                                           P->cpois + (size_t)m * TABLE_CAP, P->cpois_len[m]);
+            }
+        }
     }
 }
 
-/* Neonate count of patch k and, in the Poisson regime, each offspring
- * slot's mother.  Wright-Fisher keeps the patch's census while any patch
- * its offspring may descend from (itself and its ring neighbours) has a
- * survivor. */
+/* Neonate count of deme k and, where mothers have offspring counts, each
+ * offspring slot's mother.  Wright-Fisher keeps the patch's census while
+ * any patch its offspring may descend from (itself and its ring
+ * neighbours) has a survivor.  The consumer-resource regime carries its
+ * survivors into the next census and fills the room left up to the
+ * capacity with newborns. */
 static void neonates(oracle_pop *P, uint32_t k)
 {
     oracle_deme *D = &P->deme[k];
     uint32_t nn, i;
     free(D->owner);
     D->owner = NULL;
+    D->n_carry = 0;
     if (P->prm.regime == REGIME_WF) {
         uint32_t left = (k + P->n_patches - 1u) % P->n_patches, right = (k + 1u) % P->n_patches;
         uint32_t sources = D->n_survivors;
@@ -581,10 +809,13 @@ static void neonates(oracle_pop *P, uint32_t k)
         nn = sources > 0 ? D->n : 0;
     } else {
         uint64_t ktot = 0;
-        uint32_t slot = 0;
+        uint32_t slot = 0, room;
+        if (P->prm.regime == REGIME_CONSUMER_RESOURCE)
+            D->n_carry = D->n_survivors;
+        room = D->cap - D->n_carry;
         for (i = 0; i < D->n_survivors; ++i)
             ktot += D->kids[i];
-        nn = ktot > P->prm.capacity ? P->prm.capacity : (uint32_t)ktot;
+        nn = ktot > room ? room : (uint32_t)ktot;
         D->stats.truncated += ktot - nn;
         D->owner = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
         for (i = 0; i < D->n_survivors; ++i) {
@@ -594,7 +825,7 @@ static void neonates(oracle_pop *P, uint32_t k)
                     D->owner[slot] = D->survivors[i];
         }
     }
-    D->n_next = nn;
+    D->n_next = nn; /* newborns; the next census is n_carry + n_next */
 }
 
 /* The patch offspring j of patch k descends from.  With probability m it
@@ -622,12 +853,14 @@ static uint32_t source_patch(oracle_pop *P, uint32_t k, uint32_t j, uint32_t t)
     return k; /* unreachable: a patch with no source has no offspring */
 }
 
-/* A (parents) + B + C for the offspring of patch k; the new genomes go to
- * *next and *znext. */
-static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int32_t **znext)
+/* The next census of deme k into *next, *znext, *anext: carried survivors
+ * first (consumer-resource regime: genomes and phenotypes copied, one age
+ * class older), then the newborns -- A (parents) + B + C. */
+static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int32_t **znext, uint8_t **anext)
 {
     oracle_deme *D = &P->deme[k];
-    uint32_t nn = D->n_next, j, L = P->L;
+    uint32_t nc = D->n_carry, nn = D->n_next, j, L = P->L;
+    uint32_t total = nc + nn;
     uint8_t *scratch = (uint8_t *)malloc(3u * L);
     free(D->mom);
     free(D->dad);
@@ -635,16 +868,23 @@ static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int
     D->mom = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
     D->dad = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
     D->src = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
-    *next = (uint8_t *)malloc((size_t)(nn ? nn : 1) * 2u * L);
-    *znext = (int32_t *)malloc(sizeof(int32_t) * (nn ? nn : 1));
+    *next = (uint8_t *)malloc((size_t)(total ? total : 1) * 2u * L);
+    *znext = (int32_t *)malloc(sizeof(int32_t) * (total ? total : 1));
+    *anext = (uint8_t *)calloc(total ? total : 1, 1);
+    for (j = 0; j < nc; ++j) {
+        uint32_t i = D->survivors[j];
+        memcpy(allele_row(P, *next, j, 0), allele_row(P, D->genome, i, 0), 2u * L);
+        (*znext)[j] = D->z[i];
+        (*anext)[j] = (uint8_t)(D->age[i] + 1u);
+    }
     for (j = 0; j < nn; ++j) {
         uint32_t w0 = seq_word(&D->rng, j, ST_PARENT, t, 0);
         uint32_t w1 = seq_word(&D->rng, j, ST_PARENT, t, 1);
         uint32_t w2 = seq_word(&D->rng, j, ST_PARENT, t, 2);
         uint32_t w3 = seq_word(&D->rng, j, ST_PARENT, t, 3);
-        uint32_t sp = source_patch(P, k, j, t);
+        uint32_t sp = P->prm.regime == REGIME_WF ? source_patch(P, k, j, t) : k;
         oracle_deme *S = &P->deme[sp];
-        uint32_t mom, dad;
+        uint32_t mom, dad, pos = nc + j;
         if (P->prm.regime == REGIME_WF)
             mom = S->survivors[uniform_index(w0, w1, S->n_survivors)];
         else
@@ -654,37 +894,42 @@ static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int
         D->dad[j] = dad;
         D->src[j] = sp;
         make_gamete(P, &D->rng, allele_row(P, S->genome, mom, 0), allele_row(P, S->genome, mom, 1), j, t, 0,
-                    allele_row(P, *next, j, 0), scratch);
+                    allele_row(P, *next, pos, 0), scratch);
         make_gamete(P, &D->rng, allele_row(P, S->genome, dad, 0), allele_row(P, S->genome, dad, 1), j, t, 1,
-                    allele_row(P, *next, j, 1), scratch);
-        (*znext)[j] = phenotype(P, allele_row(P, *next, j, 0), allele_row(P, *next, j, 1));
+                    allele_row(P, *next, pos, 1), scratch);
+        (*znext)[pos] = phenotype(P, allele_row(P, *next, pos, 0), allele_row(P, *next, pos, 1));
     }
     free(scratch);
 }
 
 int oracle_step(oracle_pop *P, uint32_t n_generations)
 {
-    uint32_t it, k, np = P->n_patches;
-    uint8_t **next = (uint8_t **)calloc(np, sizeof(uint8_t *));
-    int32_t **znext = (int32_t **)calloc(np, sizeof(int32_t *));
+    uint32_t it, k, nd = P->n_demes;
+    uint8_t **next = (uint8_t **)calloc(nd, sizeof(uint8_t *));
+    int32_t **znext = (int32_t **)calloc(nd, sizeof(int32_t *));
+    uint8_t **anext = (uint8_t **)calloc(nd, sizeof(uint8_t *));
     for (it = 0; it < n_generations; ++it) {
         uint32_t t = P->generation;
-        for (k = 0; k < np; ++k)
+        if (P->prm.regime == REGIME_CONSUMER_RESOURCE)
+            encounters(P, t);
+        for (k = 0; k < nd; ++k)
             select_and_count(P, &P->deme[k], t);
-        for (k = 0; k < np; ++k)
+        for (k = 0; k < nd; ++k)
             neonates(P, k);
-        for (k = 0; k < np; ++k)
-            offspring(P, k, t, &next[k], &znext[k]);
+        for (k = 0; k < nd; ++k)
+            offspring(P, k, t, &next[k], &znext[k], &anext[k]);
         P->generation = t + 1;
-        for (k = 0; k < np; ++k) {
+        for (k = 0; k < nd; ++k) {
             oracle_deme *D = &P->deme[k];
             free(D->genome);
             free(D->z);
+            free(D->age);
             D->genome = next[k];
             D->z = znext[k];
+            D->age = anext[k];
             D->stats.n_parents = D->n;
             D->stats.n_survivors = D->n_survivors;
-            D->n = D->n_next;
+            D->n = D->n_carry + D->n_next;
             if (D->n == 0)
                 D->stats.extinct = 1;
             D->stats.updates += (uint64_t)D->n * P->L;
@@ -693,33 +938,37 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
     }
     free(next);
     free(znext);
+    free(anext);
     return 0;
 }
 
 /* ------------------------------------------------------------------ */
-/* Accessors, per patch.  Packed layout: individual i, haplotype h,    */
-/* word w holds loci 32w .. 32w+31, locus l at bit l % 32; tail bits   */
-/* are zero.                                                            */
+/* Accessors, per deme (the patch of a ring, or the species of the      */
+/* consumer-resource regime: 0 resource, 1 consumer).  Packed layout:   */
+/* individual i, haplotype h, word w holds loci 32w .. 32w+31, locus l  */
+/* at bit l % 32; tail bits are zero.                                    */
 /* ------------------------------------------------------------------ */
-static oracle_deme *deme_of(const oracle_pop *P, uint32_t patch) { return patch < P->n_patches ? &P->deme[patch] : NULL; }
+static oracle_deme *deme_of(const oracle_pop *P, uint32_t deme) { return deme < P->n_demes ? &P->deme[deme] : NULL; }
 
-int oracle_get_stats(const oracle_pop *P, uint32_t patch, oracle_stats *out)
+int oracle_get_stats(const oracle_pop *P, uint32_t deme, oracle_stats *out)
 {
-    oracle_deme *D = deme_of(P, patch);
+    oracle_deme *D = deme_of(P, deme);
     if (!D)
         return -1;
     *out = D->stats;
     return 0;
 }
-uint32_t oracle_get_n(const oracle_pop *P, uint32_t patch) { return deme_of(P, patch) ? P->deme[patch].n : 0; }
+uint32_t oracle_get_n(const oracle_pop *P, uint32_t deme) { return deme_of(P, deme) ? P->deme[deme].n : 0; }
 uint32_t oracle_get_generation(const oracle_pop *P) { return P->generation; }
-uint32_t oracle_get_patches(const oracle_pop *P) { return P->n_patches; }
+uint32_t oracle_get_demes(const oracle_pop *P) { return P->n_demes; }
 int oracle_get_mode(const oracle_pop *P) { return P->mode; }
+/* Newborns of the last generation (the census minus carried survivors). */
+uint32_t oracle_get_newborns(const oracle_pop *P, uint32_t deme) { return deme_of(P, deme) ? P->deme[deme].n_next : 0; }
 
-int oracle_get_genomes(const oracle_pop *P, uint32_t patch, uint32_t *words, size_t n_words)
+int oracle_get_genomes(const oracle_pop *P, uint32_t deme, uint32_t *words, size_t n_words)
 {
     uint32_t W = (P->L + 31u) / 32u, i, h, l;
-    oracle_deme *D = deme_of(P, patch);
+    oracle_deme *D = deme_of(P, deme);
     if (!D || n_words < (size_t)D->n * 2u * W)
         return -1;
     memset(words, 0, sizeof(uint32_t) * (size_t)D->n * 2u * W);
@@ -733,17 +982,18 @@ int oracle_get_genomes(const oracle_pop *P, uint32_t patch, uint32_t *words, siz
     return 0;
 }
 
-/* Replace patch `patch`'s population at generation `generation` (which
- * becomes the replicate's generation) and reset its counters. */
-int oracle_set_genomes(oracle_pop *P, uint32_t patch, const uint32_t *words, uint32_t n, uint32_t generation)
+/* Replace a deme's population (all of age 0) at generation `generation`
+ * (which becomes the replicate's generation) and reset its counters. */
+int oracle_set_genomes(oracle_pop *P, uint32_t deme, const uint32_t *words, uint32_t n, uint32_t generation)
 {
     uint32_t W = (P->L + 31u) / 32u, i, h, l;
-    oracle_deme *D = deme_of(P, patch);
-    if (!D || n > P->prm.capacity)
+    oracle_deme *D = deme_of(P, deme);
+    if (!D || n > D->cap)
         return -1;
     free_deme(D);
     D->genome = (uint8_t *)malloc((size_t)(n ? n : 1) * 2u * P->L);
     D->z = (int32_t *)malloc(sizeof(int32_t) * (n ? n : 1));
+    D->age = (uint8_t *)calloc(n ? n : 1, 1);
     for (i = 0; i < n; ++i) {
         for (h = 0; h < 2; ++h) {
             uint8_t *row = D->genome + ((size_t)i * 2u + h) * P->L;
@@ -756,24 +1006,45 @@ int oracle_set_genomes(oracle_pop *P, uint32_t patch, const uint32_t *words, uin
     D->n = n;
     P->generation = generation;
     D->n_survivors = 0;
+    D->n_next = 0;
+    D->n_carry = 0;
     memset(&D->stats, 0, sizeof D->stats);
     D->stats.extinct = n == 0;
     census(P, D);
     return 0;
 }
 
-int oracle_get_phenotypes(const oracle_pop *P, uint32_t patch, int32_t *z, size_t n)
+int oracle_get_phenotypes(const oracle_pop *P, uint32_t deme, int32_t *z, size_t n)
 {
-    oracle_deme *D = deme_of(P, patch);
+    oracle_deme *D = deme_of(P, deme);
     if (!D || n < D->n)
         return -1;
     memcpy(z, D->z, sizeof(int32_t) * D->n);
     return 0;
 }
 
-uint32_t oracle_get_survivors(const oracle_pop *P, uint32_t patch, uint32_t *S, size_t n)
+int oracle_get_ages(const oracle_pop *P, uint32_t deme, uint8_t *age, size_t n)
 {
-    oracle_deme *D = deme_of(P, patch);
+    oracle_deme *D = deme_of(P, deme);
+    if (!D || n < D->n)
+        return -1;
+    memcpy(age, D->age, D->n);
+    return 0;
+}
+
+/* Consumers: credited captures of each adult in the last generation. */
+int oracle_get_intake(const oracle_pop *P, uint32_t *intake, size_t n)
+{
+    oracle_deme *D = deme_of(P, 1);
+    if (P->prm.regime != REGIME_CONSUMER_RESOURCE || !D || !D->intake || n < D->stats.n_parents)
+        return -1;
+    memcpy(intake, D->intake, sizeof(uint32_t) * D->stats.n_parents);
+    return 0;
+}
+
+uint32_t oracle_get_survivors(const oracle_pop *P, uint32_t deme, uint32_t *S, size_t n)
+{
+    oracle_deme *D = deme_of(P, deme);
     if (!D)
         return 0;
     if (S && n >= D->n_survivors)
@@ -781,17 +1052,17 @@ uint32_t oracle_get_survivors(const oracle_pop *P, uint32_t patch, uint32_t *S, 
     return D->n_survivors;
 }
 
-/* Parents of the current newborns of a patch: indices into the adults of
- * their source patch, and that patch. */
-int oracle_get_parents(const oracle_pop *P, uint32_t patch, uint32_t *mom, uint32_t *dad, uint32_t *src, size_t n)
+/* Parents of the last generation's newborns of a deme: indices into the
+ * adults of their source patch, and that patch. */
+int oracle_get_parents(const oracle_pop *P, uint32_t deme, uint32_t *mom, uint32_t *dad, uint32_t *src, size_t n)
 {
-    oracle_deme *D = deme_of(P, patch);
-    if (!D || n < D->n || (D->n > 0 && !D->mom))
+    oracle_deme *D = deme_of(P, deme);
+    if (!D || n < D->n_next || (D->n_next > 0 && !D->mom))
         return -1;
-    memcpy(mom, D->mom, sizeof(uint32_t) * D->n);
-    memcpy(dad, D->dad, sizeof(uint32_t) * D->n);
+    memcpy(mom, D->mom, sizeof(uint32_t) * D->n_next);
+    memcpy(dad, D->dad, sizeof(uint32_t) * D->n_next);
     if (src)
-        memcpy(src, D->src, sizeof(uint32_t) * D->n);
+        memcpy(src, D->src, sizeof(uint32_t) * D->n_next);
     return 0;
 }
 
