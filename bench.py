@@ -29,6 +29,21 @@ UNIT = "genotype-locus updates/s"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
+# HBM bytes per genotype-locus update of the offspring kernel, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE counters scaled by a device copy of known size
+# (profiles/offspring_plain_scale_hbm_traffic.md), valid for the kernel
+# source with this SHA-256 prefix only.
+MEASURED_TRAFFIC = {"kernels_sha256_16": "a91e02b96d000174", "bytes_per_update": 0.5877}
+
+
+def measured_traffic_per_update():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1603_09255_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return MEASURED_TRAFFIC["bytes_per_update"] if sha == MEASURED_TRAFFIC["kernels_sha256_16"] else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -47,8 +62,8 @@ def cpu_baseline(desc, budget_s):
     import oracle
 
     keys = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
-            "fecundity", "effects")
-    orc = oracle.OraclePop(**{k: desc[k] for k in keys})
+            "fecundity", "effects", "n_patches", "migration")
+    orc = oracle.OraclePop(**{k: desc[k] for k in keys if k in desc})
     start_updates = orc.stats()["updates"]
     gens = 0
     t0 = time.perf_counter()
@@ -72,12 +87,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=20, help="untimed generations first")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["scale", "batched"], default="scale",
-                    help="scale: one replicate at scale (default); batched: the 4096-replicate batch")
+    ap.add_argument("--workload", choices=["scale", "batched", "serve"], default="scale",
+                    help="scale: one replicate at scale (default); batched: the 4096-replicate batch; "
+                         "serve: sweep jobs arriving at random, served with continuous batching")
     ap.add_argument("--reps", type=int, default=4096, help="replicates of the batched workload")
     ap.add_argument("--plain-sample", type=int, default=64,
                     help="batched: replicates timed one at a time for the plain per-replicate loop")
+    ap.add_argument("--jobs", type=int, default=200, help="serve: jobs in the trace")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
+    ap.add_argument("--sweep", type=str, default="",
+                    help="serve: comma-separated arrival rates for a rate sweep after the main trace")
+    ap.add_argument("--quantum", type=int, default=8, help="serve: generations per scheduling step")
+    ap.add_argument("--full-jobs", action="store_true",
+                    help="serve: jobs at their full size (reps U{8..256}, gens U{100..2000}); hours of GPU time")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only copy a device buffer of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        return calibrate_copy(args.calibrate_copy_mib)
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the workload is one replicate "
               "resident on one device)", file=sys.stderr)
@@ -89,6 +116,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     desc, _ = workloads.plain_scale(seed=1)
     L = desc["n_loci"]
@@ -164,7 +193,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": (None if measured_traffic_per_update() is None else
+                        measured_traffic_per_update() * updates_b / max(off_n, 1)),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 counters, scaled)",
             "bytes_per_update": bytes_per_update(L),
             "avg_launch_us": avg_launch_s * 1e6,
             "launches": off_n,
@@ -248,6 +279,68 @@ def bench_batched(args):
                      "bytes_per_update": bpu, "launches": off_n, "generations": gens_b},
     }
     print(json.dumps(out), flush=True)
+
+
+SERVE_SCALED = dict(reps=(1, 8), gens=(20, 200))  # the served jobs, cut to fit a bench run
+
+
+def bench_serve(args):
+    """Sweep jobs of 100-patch rings (L = 256, m = 0.01) arriving as a
+    Poisson process, admitted by footprint and served with continuous
+    batching; latency = completion - arrival on the loop's clock."""
+    import torch
+
+    from paper_1603_09255_amd import serve, spegg, workloads
+
+    torch.cuda.set_device(0)
+    shape = {} if args.full_jobs else SERVE_SCALED
+    free, _total = torch.cuda.mem_get_info()
+    arena = int(free * 0.8) & ~255
+    srv = spegg.Server(arena)
+
+    def one(rate, n_jobs):
+        jobs = workloads.serve_trace(n_jobs=n_jobs, rate=rate, **shape)
+        log(f"bench: serving {n_jobs} jobs at {rate}/s")
+        out = serve.run_trace(jobs, arena, quantum=args.quantum, server=srv)
+        return {"rate_per_s": rate, "jobs": n_jobs, "p50_s": out["p50_s"], "p99_s": out["p99_s"],
+                "makespan_s": out["makespan_s"], "updates_per_s": out["updates"] / out["makespan_s"],
+                "max_resident": out["max_resident"], "steps": out["steps"]}
+
+    # warm-up: a few jobs to load code and allocator paths
+    serve.run_trace(workloads.serve_trace(n_jobs=3, rate=1000.0, seed=99, **shape), arena, quantum=args.quantum,
+                    server=srv)
+    main_run = one(args.rate, args.jobs)
+    sweep = [one(float(r), max(20, args.jobs // 4)) for r in args.sweep.split(",") if r]
+    srv.close()
+    out = {
+        "metric": METRIC, "value": main_run["updates_per_s"], "unit": UNIT, "n_gpus": 1, "steps": main_run["steps"],
+        "warmup": 3, "ms_per_step": main_run["makespan_s"] * 1e3 / max(main_run["steps"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "served sweep jobs: Poisson arrivals; per job one parameter point (per-patch N "
+                               "~U{200..5000}, mu log-uniform [1e-7,1e-4], r ~U[0.001,0.5], width ~U[2,16]) run as "
+                               "replicates of a 100-patch ring, L=256, m=0.01; "
+                               + ("full-size jobs (reps U{8..256}, gens U{100..2000})" if args.full_jobs else
+                                  "jobs cut to reps U{1..8}, gens U{20..200}"),
+                   "jobs": args.jobs, "arrival_rate_per_s": args.rate, "quantum_generations": args.quantum,
+                   "p50_latency_s": main_run["p50_s"], "p99_latency_s": main_run["p99_s"],
+                   "makespan_s": main_run["makespan_s"], "max_resident_jobs": main_run["max_resident"],
+                   "arena_bytes": arena, "rate_sweep": sweep},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def calibrate_copy(mib):
+    """A plain device copy of known size: each launch reads and writes
+    mib MiB, the reference for scaling the HBM byte counters."""
+    import torch
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"bench: copied {mib} MiB 5 times")
 
 
 def workloads_bytes(d):

@@ -28,10 +28,20 @@
  * l/32; bits at loci >= L are zero.  Seen as uint64 on a little-endian
  * machine this is the same bit order.
  *
+ * Patches: a replicate may be a ring of n_patches patches (Supplementary
+ * Information S3: patches linked by migration to their neighbours), each a
+ * Wright-Fisher deme of its own census.  With probability `migration` a
+ * newborn of patch k descends from parents in patch k-1 or k+1 (backward
+ * migration; one fair bit picks the side); a source patch without
+ * survivors passes the draw on (drawn patch, home, picked side, other
+ * side), so a patch keeps its census while it or a neighbour has a
+ * survivor.  Patches advance together; all per-individual indices below are
+ * within a patch.
+ *
  * Randomness: Philox4x32-10 keyed by the replicate's 64-bit seed, with
- * counter (index, stream << 24 | block, generation, replicate_id << 12).
- * No counter field encodes a batch position, a thread or a tile, so a
- * replicate's trajectory is the same alone or in any batch.
+ * counter (index, stream << 24 | block, generation, replicate_id << 12 |
+ * patch).  No counter field encodes a batch position, a thread or a tile,
+ * so a replicate's trajectory is the same alone or in any batch.
  *
  * Memory: the caller owns the device memory (one block of
  * spegg_footprint() bytes, 256-byte aligned) and the HIP stream; the library
@@ -54,9 +64,10 @@
 extern "C" {
 #endif
 
-#define SPEGG_ABI_VERSION 1
+#define SPEGG_ABI_VERSION 2
 #define SPEGG_MAX_LOCI 16384u
 #define SPEGG_MAX_REPLICATE_ID ((1u << 20) - 1u)
+#define SPEGG_MAX_PATCHES 1024u
 
 typedef enum {
     SPEGG_OK = 0,
@@ -80,27 +91,29 @@ typedef struct spegg_rep_desc {
     uint64_t seed;         /* Philox key */
     uint32_t replicate_id; /* logical replicate id, 0..SPEGG_MAX_REPLICATE_ID; never a batch slot */
     uint32_t regime;       /* spegg_regime */
-    uint32_t n0;           /* initial census, <= capacity */
-    uint32_t capacity;     /* most individuals the replicate may hold, >= 1 */
+    uint32_t n0;           /* initial census of each patch, <= capacity */
+    uint32_t capacity;     /* most individuals a patch may hold, >= 1 */
     uint32_t n_loci;       /* L, 1..SPEGG_MAX_LOCI */
-    uint32_t reserved;     /* must be 0 */
+    uint32_t n_patches;    /* patches on the ring, 1..SPEGG_MAX_PATCHES; more than 1 needs SPEGG_WF */
     double mu;             /* per-locus, per-gamete flip probability, 0 <= mu < 1 */
     double r;              /* crossover probability at each adjacent-locus boundary, 0 <= r <= 1/2 */
     double theta;          /* optimum of Gaussian stabilising selection */
     double omega;          /* its width, v(z) = exp(-(z-theta)^2 / (2 omega^2)); omega <= 0: no selection */
     double K;              /* Beverton-Holt carrying capacity (POISSON_BH); K <= 0: no density dependence */
     double fecundity;      /* Poisson mean lambda (POISSON_BH) */
+    double migration;      /* backward migration rate to the ring neighbours, 0..1; unused with one patch */
     const int8_t *effects; /* n_loci allelic effects in [-4, 4], copied at create; NULL: all +1 */
 } spegg_rep_desc;
 
-/* Census of one replicate after its latest generation. */
+/* Census of one patch, or of a replicate summed over its patches, after
+ * the latest generation. */
 typedef struct spegg_rep_stats {
     uint32_t generation;    /* t: generations completed since creation (or since the last write) */
     uint32_t n;             /* N_t */
     uint32_t n_parents;     /* N_{t-1}, the adults the last generation started from */
     uint32_t n_survivors;   /* survivors among them */
-    uint32_t extinct;       /* 1 once N reached 0 */
-    uint32_t reserved;
+    uint32_t extinct;       /* 1 once N reached 0 (replicate: every patch) */
+    uint32_t captures;      /* consumers: resources captured and credited in the last generation; else 0 */
     int64_t sum_z;          /* sum of z over the N_t individuals (exact) */
     int64_t sum_z2;         /* sum of z^2 (exact) */
     uint64_t near_ties;     /* cumulative survival draws with |x 2^-32 - p| < 1e-6, 0 < p < 1 */
@@ -134,45 +147,55 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
 spegg_status spegg_step_generations(spegg_pop *pop, uint32_t n_generations);
 
 /* Wait for the stream, then copy the census of replicates 0..n-1 (n <=
- * n_reps) into host_out. */
+ * n_reps), each summed over its patches, into host_out. */
 spegg_status spegg_stats(spegg_pop *pop, spegg_rep_stats *host_out, uint32_t n);
 
-/* Wait, then copy replicate rep's current genomes (N x 2W words, layout
- * above) into host_words (room for n_words words); *n_out = N.
- * SPEGG_E_INVALID if the room is short.  patch and species must be 0. */
+/* Wait, then copy the census of each of replicate rep's patches (n must
+ * equal its n_patches) into host_out. */
+spegg_status spegg_patch_stats(spegg_pop *pop, uint32_t rep, spegg_rep_stats *host_out, uint32_t n);
+
+/* Wait, then copy the current genomes of patch `patch` of replicate rep
+ * (N x 2W words, layout above) into host_words (room for n_words words);
+ * *n_out = N.  SPEGG_E_INVALID if the room is short; species must be 0. */
 spegg_status spegg_read_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *host_words,
                                 size_t n_words, uint32_t *n_out);
 
-/* Replace replicate rep's population by n individuals given as n x 2W
- * words (tail bits must be zero, n <= capacity) at generation `generation`;
- * phenotypes are recomputed and the census and cumulative counters reset.
+/* Replace the population of patch `patch` of replicate rep by n
+ * individuals given as n x 2W words (tail bits must be zero, n <= capacity)
+ * at generation `generation`; phenotypes are recomputed and the patch's
+ * census and cumulative counters reset.  Patches of one replicate must all
+ * be at one generation when it next steps (SPEGG_E_STATE otherwise).
  * Waits for the stream before returning (host_words may be reused). */
 spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species,
                                  const uint32_t *host_words, uint32_t n, uint32_t generation);
 
-/* Wait, then copy replicate rep's phenotypes z (N int32) into host_z. */
-spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, int32_t *host_z, size_t n, uint32_t *n_out);
+/* Wait, then copy the phenotypes z (N int32) of a patch into host_z. */
+spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, uint32_t patch, int32_t *host_z, size_t n,
+                                   uint32_t *n_out);
 
-/* Wait, then copy the ascending survivor list of replicate rep's last
- * generation (indices into the previous adults) into host_idx. */
-spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t *host_idx, size_t n, uint32_t *n_out);
+/* Wait, then copy the ascending survivor list of a patch's last
+ * generation (indices into its previous adults) into host_idx. */
+spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *host_idx, size_t n,
+                                  uint32_t *n_out);
 
-/* Per-locus copies of allele 1 over replicate rep's current census (2N
- * genes per locus): the genetic distribution behind the phenotypes (Fig. 1F;
+/* Per-locus copies of allele 1 over a patch's current census (2N genes
+ * per locus): the genetic distribution behind the phenotypes (Fig. 1F;
  * Supplementary S2, "Genetics").  counts_dev is caller-owned device scratch
  * of n_loci uint32 (n_loci must equal the replicate's L); host_counts gets
  * the result; *n_out = N.  Reads every genome once; waits for the stream. */
-spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t *counts_dev, uint32_t *host_counts,
-                                 uint32_t n_loci, uint32_t *n_out);
+spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *counts_dev,
+                                 uint32_t *host_counts, uint32_t n_loci, uint32_t *n_out);
 
 /* Record each newborn's mother and father (indices into the previous
  * adults) from the next generation on.  Off by default. */
 spegg_status spegg_set_trace(spegg_pop *pop, int enable);
 
-/* Wait, then copy the parents recorded for replicate rep's current
- * newborns.  SPEGG_E_STATE if tracing was off for the last generation. */
-spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t *host_mom, uint32_t *host_dad, size_t n,
-                                uint32_t *n_out);
+/* Wait, then copy the parents recorded for a patch's current newborns:
+ * mother and father as indices into the adults of the patch they came
+ * from, and that patch (host_src may be NULL).  SPEGG_E_STATE if tracing
+ * was off for the last generation. */
+spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *host_mom, uint32_t *host_dad,
+                                uint32_t *host_src, size_t n, uint32_t *n_out);
 
 /* Replay generations as captured HIP graphs (enable = 1, the default) or
  * launch every kernel (0).  Graphs are used only on a non-null stream and
@@ -201,6 +224,55 @@ spegg_status spegg_kernel_times(spegg_pop *pop, double *ms, uint64_t *launches, 
 
 /* Release the handle (not the caller's memory or stream).  NULL is a no-op. */
 void spegg_pop_destroy(spegg_pop *pop);
+
+/* ------------------------------------------------------------- serving
+ * Sweep jobs served from one device arena with continuous batching.  A job
+ * is the replicates of one parameter sweep point (Supplementary Fig. S5(B):
+ * replicates and parameter combinations run side by side), advanced for a
+ * fixed number of generations.  Jobs are admitted in submission order
+ * while the oldest waiting job's footprint fits in the free arena; between
+ * steps resident jobs keep their state, finished jobs leave at once and
+ * free their memory, and newly admitted jobs join.  A job's results are
+ * those of its replicates run alone: the counters never see the batch.
+ * The server borrows the arena (256-byte aligned) and the stream; it
+ * allocates no device memory. */
+typedef struct spegg_server spegg_server;
+
+/* n_streams (1..8): resident jobs are spread over hip_stream and
+ * n_streams - 1 streams the server creates (default priority), so the
+ * kernels of different jobs overlap on the device; 1 keeps all work on
+ * hip_stream.  Waits for hip_stream once (the arena must be ready). */
+spegg_status spegg_server_create(void *device_mem, size_t device_bytes, void *hip_stream, uint32_t n_streams,
+                                 spegg_server **out);
+
+/* Queue a job of n_reps replicates for n_generations (>= 1) generations.
+ * SPEGG_E_INVALID for a bad descriptor or a job_id already queued,
+ * resident or holding an unread result; SPEGG_E_NOMEM if the job's
+ * footprint exceeds the whole arena (it could never be admitted).
+ * Descriptors and effects are copied. */
+spegg_status spegg_server_submit(spegg_server *srv, uint64_t job_id, const spegg_rep_desc *reps, uint32_t n_reps,
+                                 uint32_t n_generations);
+
+/* Admit waiting jobs that fit (oldest first, stopping at the first that
+ * does not) onto the least loaded stream, advance every resident job by
+ * min(n_generations, its remaining generations), wait for all streams, and
+ * retire the jobs that finished.  Reports the jobs resident after admission and those still
+ * waiting (either pointer may be NULL). */
+spegg_status spegg_server_step(spegg_server *srv, uint32_t n_generations, uint32_t *n_resident, uint32_t *n_waiting);
+
+/* Ids of the jobs finished since the last poll, in completion order (at
+ * most cap; *n_out = how many were written). */
+spegg_status spegg_server_poll(spegg_server *srv, uint64_t *job_ids, uint32_t cap, uint32_t *n_out);
+
+/* Final census of each replicate (summed over patches) of a finished job;
+ * n must equal its n_reps.  The result is released once read. */
+spegg_status spegg_server_result(spegg_server *srv, uint64_t job_id, spegg_rep_stats *host_out, uint32_t n);
+
+/* Arena bytes held by resident jobs and the largest free block. */
+spegg_status spegg_server_usage(spegg_server *srv, size_t *used, size_t *largest_free);
+
+/* Release the server and every resident job (not the arena or stream). */
+void spegg_server_destroy(spegg_server *srv);
 
 /* Host-only: the library's inverse-CDF threshold table (x < T_k decides k;
  * the last entry is 2^32, "always").  kind 0: Poisson(a); 1: Binomial(b, a);

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libspegg.so")
-SOURCES = ["kernels.hip", "tables.cpp", "spegg_capi.cpp"]
+SOURCES = ["kernels.hip", "tables.cpp", "spegg_capi.cpp", "spegg_server.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

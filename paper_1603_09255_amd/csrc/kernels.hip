@@ -361,11 +361,30 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     }
     __syncthreads();
 
+    // A patch whose adults all died keeps its census when a ring neighbour
+    // has survivors to supply its newborns: count the neighbours' survivors
+    // (uniform over the block: only tile 0 of such a deme enters).
+    uint32_t nb_alive = 0;
+    if (k == 0 && sum_a == 0 && n > 0 && d.mig_T != 0) {
+        uint32_t x = 0;
+        for (int side = 0; side < 2; ++side) {
+            const SurvCount *CE = counts + descs[side ? d.right : d.left].surv_tile0;
+            const uint32_t act = (CE[0].n + kSurvTile - 1) / kSurvTile;
+            for (uint32_t q = threadIdx.x; q < act; q += kBlock) x += CE[q].alive;
+        }
+        x = wave_sum<uint32_t>(x);
+        if (lane_id() == 0) sh_a[wave] = x;
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) nb_alive += sh_a[w];
+        __syncthreads();
+    }
+
     if (k == 0 && threadIdx.x == 0) {
         // census of the newborns, into the pair the other blocks do not read
         const uint32_t ns = sum_a;
         uint32_t nn;
-        if (ns == 0) {
+        if (ns + nb_alive == 0) {
             nn = 0;
         } else if (d.regime == SPEGG_WF) {
             nn = n;
@@ -430,7 +449,7 @@ template <int G, int V, int NCH>
 __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__restrict__ descs,
                                                            const RepState *__restrict__ states,
                                                            const OffTile *__restrict__ tiles, uint32_t tile0,
-                                                           uint32_t ntiles, int single_rep,
+                                                           uint32_t ntiles, int single_deme,
                                                            Partial *__restrict__ partials, uint32_t plane_words,
                                                            int trace) {
     constexpr uint32_t TPO = 2 * G;
@@ -440,8 +459,9 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
     constexpr uint32_t CH = G * V;  // words of one gamete per chunk
     constexpr int NREG = NCH > 0 ? NCH : 1;
     // per-newborn draws, one Philox block each, spread over the team:
-    // 0 parents, 1/2 crossover phase (maternal/paternal), 3/4 mutation count
-    constexpr uint32_t NSD = 5;
+    // 0 parents, 1/2 crossover phase (maternal/paternal), 3/4 mutation
+    // count, 5 migration (only where the deme has migration)
+    constexpr uint32_t NSD = 6;
     constexpr uint32_t SR = (NSD + TPO - 1) / TPO;
     extern __shared__ uint32_t lds[];
     __shared__ int64_t red_z[kBlock / 64];
@@ -454,16 +474,16 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
     uint32_t *planes = lds;
 
     uint32_t limit = ntiles;
-    if (single_rep >= 0) {
-        const RepState &s1 = states[single_rep];
+    if (single_deme >= 0) {
+        const RepState &s1 = states[single_deme];
         const uint32_t nn = s1.n[current_pair(s1)];
         const uint32_t active = (nn + OPT - 1) / OPT;
         limit = active < ntiles ? active : ntiles;
     }
     for (uint32_t ti = blockIdx.x; ti < limit; ti += gridDim.x) {
         uint32_t rep, start;
-        if (single_rep >= 0) {
-            rep = (uint32_t)single_rep;
+        if (single_deme >= 0) {
+            rep = (uint32_t)single_deme;
             start = ti * OPT;
         } else {
             const OffTile tile = tiles[tile0 + ti];
@@ -475,9 +495,9 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
         const uint32_t newest = current_pair(st);  // the newborns' census, written by this generation's select
         const uint32_t nn = st.n[newest];
         if (start >= nn || st.error) continue;  // uniform over the block
-        const uint32_t tp = st.t[newest] - 1u, ns = st.n_surv, cur = tp & 1u;
-        const uint32_t nprev = st.n_prev;
+        const uint32_t tp = st.t[newest] - 1u, cur = tp & 1u;
         const uint32_t W = d.W, L = d.L, mode = d.mode;
+        const uint32_t nsd = d.mig_T != 0 ? NSD : NSD - 1u;
         const bool unit = d.unit_effects != 0;
         const uint64_t binom0 = d.binom0;  // most gametes carry no mutation
         const Rng rng{d.key0, d.key1, d.c3};
@@ -498,8 +518,11 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
 #pragma unroll
             for (uint32_t r = 0; r < SR; ++r) {
                 const uint32_t kd = lane + r * TPO;
-                const uint32_t stream = kd == 0 ? kStParent : kd <= 2 ? kStRecomb + kd - 1u : kStMutate + kd - 3u;
-                if (kd < NSD) {
+                const uint32_t stream = kd == 0   ? kStParent
+                                        : kd <= 2 ? kStRecomb + kd - 1u
+                                        : kd <= 4 ? kStMutate + kd - 3u
+                                                  : kStMigrate;
+                if (kd < nsd) {
                     sd[r] = rng.block(j, stream, 0, tp);
                 } else {
                     sd[r].v[0] = sd[r].v[1] = sd[r].v[2] = sd[r].v[3] = 0;
@@ -510,15 +533,27 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
                 return (uint32_t)__shfl((int)sd[kd / TPO].v[c], (int)(kd % TPO), (int)TPO);
             };
 
-            // A: parents, uniform over the survivors (Poisson: the slot's mother)
+            // A: the patch the parents live in (a migrant's comes from a ring
+            // neighbour; a patch without survivors passes the draw on: drawn,
+            // home, picked side, other side), then parents uniform over its
+            // survivors (Poisson: the slot's mother)
+            uint32_t su = rep;
+            if (d.mig_T != 0) {
+                const uint32_t m0 = draw(5, 0), m1 = draw(5, 1);
+                const uint32_t side = (m1 & 1u) ? d.right : d.left, other = (m1 & 1u) ? d.left : d.right;
+                const uint32_t drawn = (uint64_t)m0 < d.mig_T ? side : rep;
+                su = states[drawn].n_surv ? drawn : st.n_surv ? rep : states[side].n_surv ? side : other;
+            }
+            const RepDesc &sd_src = descs[su];
+            const uint32_t ns = states[su].n_surv, nprev = states[su].n_prev;
             const uint32_t p0 = draw(0, 0), p1 = draw(0, 1), p2 = draw(0, 2), p3 = draw(0, 3);
-            uint32_t mom = d.regime == SPEGG_WF ? d.S[uniform_index(p0, p1, ns)] : d.owner[j];
-            uint32_t dad = d.S[uniform_index(p2, p3, ns)];
+            uint32_t mom = d.regime == SPEGG_WF ? sd_src.S[uniform_index(p0, p1, ns)] : d.owner[j];
+            uint32_t dad = sd_src.S[uniform_index(p2, p3, ns)];
             // parents are adults of the last census; the clamp never changes a
             // correct index and keeps every gather inside the buffer
             mom = mom < nprev ? mom : nprev - 1u;
             dad = dad < nprev ? dad : nprev - 1u;
-            const uint32_t *__restrict__ src = d.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
+            const uint32_t *__restrict__ src = sd_src.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
             uint32_t *__restrict__ dst = d.genome[cur ^ 1u] + (size_t)j * 2u * W + (size_t)half * W;
             const uint32_t rs = kStRecomb + half, ms = kStMutate + half;
             const uint32_t phase_m = draw(1, 0), phase_p = draw(2, 0);
@@ -679,6 +714,7 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
                 if (trace) {
                     d.mom[j] = mom;
                     d.dad[j] = dad;
+                    if (d.mig_T != 0) d.src[j] = sd_src.patch;  // the buffer exists with migration only
                 }
             }
         }
@@ -790,7 +826,7 @@ inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kB
 template <int G, int V, int NCH>
 hipError_t launch_offspring_gvn(const OffArgs &a) {
     hipLaunchKernelGGL((offspring_kernel<G, V, NCH>), dim3(a.grid), dim3(kBlock), a.lds, a.s, a.descs, a.states,
-                       a.tiles, a.tile0, a.ntiles, a.single_rep, a.partials, a.plane_words, a.trace);
+                       a.tiles, a.tile0, a.ntiles, a.single_deme, a.partials, a.plane_words, a.trace);
     return hipGetLastError();
 }
 

@@ -20,6 +20,12 @@ namespace {
 
 thread_local std::string g_error;
 
+}  // namespace
+
+void spegg::set_last_error(const char *msg) { g_error = msg; }
+
+namespace {
+
 spegg_status fail(spegg_status st, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -44,32 +50,40 @@ struct Carver {
     }
 };
 
-// Everything the host derives from one descriptor.
+// Everything the host derives from one descriptor, and its shared tables.
 struct RepPlan {
     uint32_t W = 0, mode = 0, R = 0, opt = 0;
-    OffShape shape{1, 1};
+    OffShape shape{1, 1, 1};
     int32_t zmin = 0, sum_e = 0;
     uint32_t zlen = 0;
     bool unit = true;
+    uint64_t mig_T = 0;
     std::vector<uint64_t> pois, binom, geo;
     std::vector<double> vtab;
     std::vector<uint32_t> planes;
-    uint32_t surv_tile0 = 0, surv_ntiles = 0, off_tile0 = 0, off_ntiles = 0;
-    size_t genome[2] = {0, 0}, z[2] = {0, 0}, fate = 0, S = 0, owner = 0, mom = 0, dad = 0;
     size_t vtab_at = 0, pois_at = 0, binom_at = 0, geo_at = 0, planes_at = 0;
+    uint32_t deme0 = 0, n_demes = 0;  // the replicate's patches are demes deme0 .. deme0 + n_demes - 1
 };
 
-// Replicates sharing one offspring-kernel shape.
+// One patch of one replicate: its tiles and buffers.
+struct DemePlan {
+    uint32_t rep = 0, patch = 0;
+    uint32_t surv_tile0 = 0, surv_ntiles = 0, off_tile0 = 0, off_ntiles = 0;
+    size_t genome[2] = {0, 0}, z[2] = {0, 0}, fate = 0, S = 0, owner = 0, mom = 0, dad = 0, src = 0;
+};
+
+// Demes sharing one offspring-kernel shape.
 struct OffClass {
     OffShape shape;
     uint32_t tile0, ntiles, grid;
-    int single_rep;        // the class's only replicate, or -1
+    int single_deme;       // the class's only deme, or -1
     uint32_t plane_words;  // LDS words for the effect planes (0: unit effects only)
     size_t lds;
 };
 
 struct Plan {
     std::vector<RepPlan> reps;
+    std::vector<DemePlan> demes;
     std::vector<OffClass> classes;
     std::vector<SurvTile> surv_tiles;
     std::vector<OffTile> off_tiles;
@@ -100,7 +114,12 @@ spegg_status validate(const spegg_rep_desc &d, uint32_t i) {
                     SPEGG_MAX_REPLICATE_ID);
     if (d.regime != SPEGG_WF && d.regime != SPEGG_POISSON_BH)
         return fail(SPEGG_E_INVALID, "replicate %u: unknown regime %u", i, d.regime);
-    if (d.reserved != 0) return fail(SPEGG_E_INVALID, "replicate %u: reserved field must be 0", i);
+    if (d.n_patches < 1 || d.n_patches > SPEGG_MAX_PATCHES)
+        return fail(SPEGG_E_INVALID, "replicate %u: n_patches %u outside 1..%u", i, d.n_patches, SPEGG_MAX_PATCHES);
+    if (d.n_patches > 1 && d.regime != SPEGG_WF)
+        return fail(SPEGG_E_UNSUPPORTED, "replicate %u: patches need the Wright-Fisher regime", i);
+    if (!(d.migration >= 0.0 && d.migration <= 1.0))
+        return fail(SPEGG_E_INVALID, "replicate %u: migration %g outside [0, 1]", i, d.migration);
     if (!(d.mu >= 0.0 && d.mu < 1.0)) return fail(SPEGG_E_INVALID, "replicate %u: mu %g outside [0, 1)", i, d.mu);
     if (!(d.r >= 0.0 && d.r <= 0.5)) return fail(SPEGG_E_INVALID, "replicate %u: r %g outside [0, 1/2]", i, d.r);
     if (!std::isfinite(d.theta) || std::isnan(d.omega))
@@ -124,6 +143,7 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p) {
     p.W = (L + 31u) / 32u;
     p.mode = recomb_mode(d.r);
     p.R = (uint32_t)std::floor(d.r * 4294967296.0);
+    p.mig_T = d.n_patches > 1 ? prob_threshold(d.migration) : 0;
     int32_t abs_sum = 0;
     p.sum_e = 0;
     p.unit = true;
@@ -153,23 +173,35 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p) {
     if (p.mode == kModeSkip && L > 1) geometric_table(d.r, L - 1u, p.geo);
     p.shape = offspring_shape(p.W, offspring_gcap());
     p.opt = (uint32_t)offspring_per_tile(p.shape.g);
-    p.surv_ntiles = (d.capacity + kSurvTile - 1) / kSurvTile;
-    p.off_ntiles = (d.capacity + p.opt - 1) / p.opt;
+    p.n_demes = d.n_patches;
     return SPEGG_OK;
 }
 
 spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
     if (!reps || n == 0) return fail(SPEGG_E_INVALID, "no replicates");
     P.reps.resize(n);
+    uint64_t n_demes = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const spegg_status st = build_rep(reps[i], i, P.reps[i]);
         if (st != SPEGG_OK) return st;
+        P.reps[i].deme0 = (uint32_t)n_demes;
+        n_demes += P.reps[i].n_demes;
     }
-    // survival tiles, replicate by replicate
-    for (uint32_t i = 0; i < n; ++i) {
-        RepPlan &p = P.reps[i];
-        p.surv_tile0 = (uint32_t)P.surv_tiles.size();
-        for (uint32_t k = 0; k < p.surv_ntiles; ++k) P.surv_tiles.push_back({i, k * (uint32_t)kSurvTile});
+    if (n_demes > (1u << 24)) return fail(SPEGG_E_INVALID, "%llu patches in total exceed 2^24",
+                                          (unsigned long long)n_demes);
+    P.demes.resize(n_demes);
+    for (uint32_t i = 0; i < n; ++i)
+        for (uint32_t k = 0; k < P.reps[i].n_demes; ++k) {
+            DemePlan &q = P.demes[P.reps[i].deme0 + k];
+            q.rep = i;
+            q.patch = k;
+        }
+    // survival tiles, deme by deme
+    for (uint32_t u = 0; u < P.demes.size(); ++u) {
+        DemePlan &q = P.demes[u];
+        q.surv_tile0 = (uint32_t)P.surv_tiles.size();
+        q.surv_ntiles = (reps[q.rep].capacity + kSurvTile - 1) / kSurvTile;
+        for (uint32_t k = 0; k < q.surv_ntiles; ++k) P.surv_tiles.push_back({u, k * (uint32_t)kSurvTile});
     }
     // offspring tiles grouped by kernel shape
     std::vector<OffShape> shapes;
@@ -183,26 +215,28 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
         OffClass c{sh, (uint32_t)P.off_tiles.size(), 0, 0, -1, 0, 0};
         uint32_t maxW = 0, members = 0, last = 0;
         bool planes = false;
-        for (uint32_t i = 0; i < n; ++i) {
-            RepPlan &p = P.reps[i];
+        for (uint32_t u = 0; u < P.demes.size(); ++u) {
+            DemePlan &q = P.demes[u];
+            const RepPlan &p = P.reps[q.rep];
             if (p.shape.g != sh.g || p.shape.vpl != sh.vpl || p.shape.nch != sh.nch) continue;
-            p.off_tile0 = (uint32_t)P.off_tiles.size();
-            for (uint32_t k = 0; k < p.off_ntiles; ++k) P.off_tiles.push_back({i, k * p.opt});
+            q.off_tile0 = (uint32_t)P.off_tiles.size();
+            q.off_ntiles = (reps[q.rep].capacity + p.opt - 1) / p.opt;
+            for (uint32_t k = 0; k < q.off_ntiles; ++k) P.off_tiles.push_back({u, k * p.opt});
             if (p.W > maxW) maxW = p.W;
             planes |= !p.unit;
             ++members;
-            last = i;
+            last = u;
         }
         c.ntiles = (uint32_t)P.off_tiles.size() - c.tile0;
-        c.single_rep = members == 1 ? (int)last : -1;
+        c.single_deme = members == 1 ? (int)last : -1;
         c.grid = c.ntiles < kMaxOffspringGrid ? c.ntiles : kMaxOffspringGrid;
         c.plane_words = planes ? 6u * maxW : 0u;
         c.lds = c.plane_words * sizeof(uint32_t) + offspring_lds_bytes(sh.g, maxW);
         P.classes.push_back(c);
     }
     Carver cv;
-    P.descs = cv.take(sizeof(RepDesc) * n);
-    P.states = cv.take(sizeof(RepState) * n);
+    P.descs = cv.take(sizeof(RepDesc) * P.demes.size());
+    P.states = cv.take(sizeof(RepState) * P.demes.size());
     P.surv_tiles_at = cv.take(sizeof(SurvTile) * P.surv_tiles.size());
     P.off_tiles_at = cv.take(sizeof(OffTile) * P.off_tiles.size());
     for (uint32_t i = 0; i < n; ++i) {
@@ -216,21 +250,22 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
     P.static_end = cv.off;
     P.surv_counts = cv.take(sizeof(SurvCount) * P.surv_tiles.size());
     P.partials = cv.take(sizeof(Partial) * P.off_tiles.size());
-    for (uint32_t i = 0; i < n; ++i) {
-        RepPlan &p = P.reps[i];
-        const size_t cap = reps[i].capacity;
+    for (DemePlan &q : P.demes) {
+        const RepPlan &p = P.reps[q.rep];
+        const size_t cap = reps[q.rep].capacity;
         const size_t gbytes = cap * 2u * p.W * sizeof(uint32_t);
-        p.genome[0] = cv.take(gbytes);
-        p.genome[1] = cv.take(gbytes);
+        q.genome[0] = cv.take(gbytes);
+        q.genome[1] = cv.take(gbytes);
         // phenotypes padded to whole select tiles (read as vectors)
         const size_t zcap = ((cap + kSurvTile - 1) / kSurvTile) * kSurvTile;
-        p.z[0] = cv.take(zcap * sizeof(int32_t));
-        p.z[1] = cv.take(zcap * sizeof(int32_t));
-        p.fate = cv.take(zcap * sizeof(uint16_t));
-        p.S = cv.take(cap * sizeof(uint32_t));
-        if (reps[i].regime == SPEGG_POISSON_BH) p.owner = cv.take(cap * sizeof(uint32_t));
-        p.mom = cv.take(cap * sizeof(uint32_t));
-        p.dad = cv.take(cap * sizeof(uint32_t));
+        q.z[0] = cv.take(zcap * sizeof(int32_t));
+        q.z[1] = cv.take(zcap * sizeof(int32_t));
+        q.fate = cv.take(zcap * sizeof(uint16_t));
+        q.S = cv.take(cap * sizeof(uint32_t));
+        if (reps[q.rep].regime == SPEGG_POISSON_BH) q.owner = cv.take(cap * sizeof(uint32_t));
+        q.mom = cv.take(cap * sizeof(uint32_t));
+        q.dad = cv.take(cap * sizeof(uint32_t));
+        if (p.mig_T) q.src = cv.take(cap * sizeof(uint32_t));
     }
     P.total = cv.off;
     return SPEGG_OK;
@@ -279,10 +314,11 @@ struct spegg_pop {
     hipStream_t stream = nullptr;
     int device = 0;
     uint8_t *base = nullptr;
-    uint32_t n_reps = 0;
+    uint32_t n_reps = 0, n_demes = 0;
     Plan plan;
     std::vector<spegg_rep_desc> descs;
-    std::vector<RepDesc> dev_descs;  // host images of the device descriptors
+    std::vector<RepDesc> dev_descs;  // host images of the device descriptors, one per deme
+    std::vector<uint32_t> deme_gen;  // each deme's generation, tracked on the host
     std::vector<uint8_t> image;      // host image of [0, static_end)
     bool errored = false;
     bool trace = false;
@@ -367,6 +403,7 @@ spegg_rep_stats census_of(const RepState &s) {
     c.n_parents = s.n_prev;
     c.n_survivors = s.n_surv;
     c.extinct = s.extinct;
+    c.captures = s.captures;
     for (int k = 0; k < kCensusSlots; ++k) {
         c.sum_z += s.sum_z[k];
         c.sum_z2 += (int64_t)s.sum_z2[k];
@@ -378,22 +415,66 @@ spegg_rep_stats census_of(const RepState &s) {
     return c;
 }
 
+// A replicate's census: its patches' summed (extinct when all are).
+spegg_rep_stats sum_of(const spegg_rep_stats *p, uint32_t n) {
+    spegg_rep_stats c = p[0];
+    for (uint32_t k = 1; k < n; ++k) {
+        c.n += p[k].n;
+        c.n_parents += p[k].n_parents;
+        c.n_survivors += p[k].n_survivors;
+        c.extinct &= p[k].extinct;
+        c.captures += p[k].captures;
+        c.sum_z += p[k].sum_z;
+        c.sum_z2 += p[k].sum_z2;
+        c.near_ties += p[k].near_ties;
+        c.truncated += p[k].truncated;
+        c.sum_threshold += p[k].sum_threshold;
+        c.updates += p[k].updates;
+    }
+    return c;
+}
+
 spegg_status sync_stream(spegg_pop *pop) {
     const hipError_t e = hipStreamSynchronize(pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "hipStreamSynchronize");
     return SPEGG_OK;
 }
 
-spegg_status read_state(spegg_pop *pop, uint32_t rep, RepState &s) {
-    hipError_t e = hipMemcpyAsync(&s, pop->d_states() + rep, sizeof s, hipMemcpyDeviceToHost, pop->stream);
+spegg_status read_state(spegg_pop *pop, uint32_t deme, RepState &s) {
+    hipError_t e = hipMemcpyAsync(&s, pop->d_states() + deme, sizeof s, hipMemcpyDeviceToHost, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(state)");
     return sync_stream(pop);
 }
 
-spegg_status check_rep(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species) {
+// The deme of (replicate, patch, species).
+spegg_status find_deme(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *deme) {
     if (rep >= pop->n_reps) return fail(SPEGG_E_INVALID, "replicate %u out of range (%u)", rep, pop->n_reps);
-    if (patch != 0 || species != 0)
-        return fail(SPEGG_E_UNSUPPORTED, "one patch and one species per replicate in this build");
+    const RepPlan &p = pop->plan.reps[rep];
+    if (patch >= p.n_demes)
+        return fail(SPEGG_E_INVALID, "patch %u out of range (replicate %u has %u)", patch, rep, p.n_demes);
+    if (species != 0) return fail(SPEGG_E_UNSUPPORTED, "one species per patch in this build");
+    *deme = p.deme0 + patch;
+    return SPEGG_OK;
+}
+
+// Census of demes [0, n_demes) after folding pending sums.
+spegg_status deme_stats(spegg_pop *pop, uint32_t n_demes, std::vector<spegg_rep_stats> &out) {
+    std::vector<RepState> s(n_demes);
+    hipError_t e = launch_census(pop->d_descs(), pop->d_states(), pop->d_partials(), n_demes, pop->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s.data(), pop->d_states(), sizeof(RepState) * n_demes, hipMemcpyDeviceToHost,
+                           pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "stats");
+    spegg_status st = sync_stream(pop);
+    if (st != SPEGG_OK) return st;
+    out.resize(n_demes);
+    for (uint32_t u = 0; u < n_demes; ++u) {
+        if (s[u].error) {
+            pop->errored = true;
+            return fail(SPEGG_E_DEVICE, "deme %u: a kernel reported an impossible state", u);
+        }
+        out[u] = census_of(s[u]);
+    }
     return SPEGG_OK;
 }
 
@@ -409,7 +490,7 @@ hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
         if (e == hipSuccess) e = timed(pop, SPEGG_KERNEL_COMPACT, [&] { return launch_compact(sa); });
         for (const OffClass &c : P.classes) {
             if (e != hipSuccess) return e;
-            const OffArgs oa{pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0, c.ntiles, c.single_rep,
+            const OffArgs oa{pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0, c.ntiles, c.single_deme,
                              pop->d_partials(), c.plane_words, c.grid, c.lds, trace, pop->stream};
             e = timed(pop, SPEGG_KERNEL_OFFSPRING, [&] { return launch_offspring(c.shape, oa); });
         }
@@ -482,12 +563,15 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
     }
 
     Plan &P = pop->plan;
+    pop->n_demes = (uint32_t)P.demes.size();
     pop->image.assign(P.static_end, 0);
     uint8_t *img = pop->image.data();
-    pop->dev_descs.resize(n_reps);
-    for (uint32_t i = 0; i < n_reps; ++i) {
-        const spegg_rep_desc &d = reps[i];
-        RepPlan &p = P.reps[i];
+    pop->dev_descs.resize(pop->n_demes);
+    pop->deme_gen.assign(pop->n_demes, 0u);
+    for (uint32_t u = 0; u < pop->n_demes; ++u) {
+        const DemePlan &q = P.demes[u];
+        const spegg_rep_desc &d = reps[q.rep];
+        const RepPlan &p = P.reps[q.rep];
         RepDesc h;
         std::memset(&h, 0, sizeof h);
         h.L = d.n_loci;
@@ -496,7 +580,7 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.regime = d.regime;
         h.key0 = (uint32_t)d.seed;
         h.key1 = (uint32_t)(d.seed >> 32);
-        h.c3 = d.replicate_id << 12;  // species 0, patch 0
+        h.c3 = d.replicate_id << 12 | q.patch;  // species 0
         h.mode = p.mode;
         h.R = p.R;
         h.geo_len = (uint32_t)p.geo.size();
@@ -508,32 +592,40 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.sum_e = p.sum_e;
         h.unit_effects = p.unit ? 1u : 0u;
         h.tail_mask = (d.n_loci % 32u) ? ((1u << (d.n_loci % 32u)) - 1u) : ~0u;
-        h.surv_tile0 = p.surv_tile0;
-        h.surv_ntiles = p.surv_ntiles;
-        h.off_tile0 = p.off_tile0;
-        h.off_ntiles = p.off_ntiles;
+        h.surv_tile0 = q.surv_tile0;
+        h.surv_ntiles = q.surv_ntiles;
+        h.off_tile0 = q.off_tile0;
+        h.off_ntiles = q.off_ntiles;
         h.off_per_tile = p.opt;
         h.geo_scale = p.mode == kModeSkip ? (float)(1.0 / std::log2(1.0 - d.r)) : 0.0f;
         h.K = d.K;
         h.lambda = d.fecundity;
-        h.genome[0] = at<uint32_t>(pop->base, p.genome[0]);
-        h.genome[1] = at<uint32_t>(pop->base, p.genome[1]);
-        h.z[0] = at<int32_t>(pop->base, p.z[0]);
-        h.z[1] = at<int32_t>(pop->base, p.z[1]);
-        h.fate = at<uint16_t>(pop->base, p.fate);
-        h.S = at<uint32_t>(pop->base, p.S);
-        h.owner = p.owner ? at<uint32_t>(pop->base, p.owner) : nullptr;
-        h.mom = at<uint32_t>(pop->base, p.mom);
-        h.dad = at<uint32_t>(pop->base, p.dad);
+        h.mig_T = p.mig_T;
+        h.patch = q.patch;
+        h.left = p.mig_T ? p.deme0 + (q.patch + p.n_demes - 1u) % p.n_demes : u;
+        h.right = p.mig_T ? p.deme0 + (q.patch + 1u) % p.n_demes : u;
+        h.genome[0] = at<uint32_t>(pop->base, q.genome[0]);
+        h.genome[1] = at<uint32_t>(pop->base, q.genome[1]);
+        h.z[0] = at<int32_t>(pop->base, q.z[0]);
+        h.z[1] = at<int32_t>(pop->base, q.z[1]);
+        h.fate = at<uint16_t>(pop->base, q.fate);
+        h.S = at<uint32_t>(pop->base, q.S);
+        h.owner = q.owner ? at<uint32_t>(pop->base, q.owner) : nullptr;
+        h.mom = at<uint32_t>(pop->base, q.mom);
+        h.dad = at<uint32_t>(pop->base, q.dad);
+        h.src = q.src ? at<uint32_t>(pop->base, q.src) : nullptr;
         h.vtab = p.vtab.empty() ? nullptr : at<double>(pop->base, p.vtab_at);
         h.pois = p.pois.empty() ? nullptr : at<uint64_t>(pop->base, p.pois_at);
         h.binom = at<uint64_t>(pop->base, p.binom_at);
         h.geo = p.geo.empty() ? nullptr : at<uint64_t>(pop->base, p.geo_at);
         h.planes = p.planes.empty() ? nullptr : at<uint32_t>(pop->base, p.planes_at);
-        pop->dev_descs[i] = h;
-        std::memcpy(img + P.descs + i * sizeof(RepDesc), &h, sizeof h);
+        pop->dev_descs[u] = h;
+        std::memcpy(img + P.descs + u * sizeof(RepDesc), &h, sizeof h);
         const RepState s0 = initial_state(0, d.n0);
-        std::memcpy(img + P.states + i * sizeof(RepState), &s0, sizeof s0);
+        std::memcpy(img + P.states + u * sizeof(RepState), &s0, sizeof s0);
+    }
+    for (uint32_t i = 0; i < n_reps; ++i) {
+        const RepPlan &p = P.reps[i];
         if (!p.vtab.empty()) std::memcpy(img + p.vtab_at, p.vtab.data(), sizeof(double) * p.vtab.size());
         if (!p.pois.empty()) std::memcpy(img + p.pois_at, p.pois.data(), sizeof(uint64_t) * p.pois.size());
         std::memcpy(img + p.binom_at, p.binom.data(), sizeof(uint64_t) * p.binom.size());
@@ -550,10 +642,10 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         delete pop;
         return fail(SPEGG_E_DEVICE, "hipMemcpyAsync(tables): %s", hipGetErrorString(e));
     }
-    for (uint32_t i = 0; i < n_reps; ++i) {
-        e = launch_init(pop->d_descs() + i, pop->dev_descs[i], reps[i].n0, pop->stream);
-        if (e == hipSuccess)
-            e = launch_phenotypes(pop->d_descs() + i, pop->d_states() + i, reps[i].n0, 0, pop->stream);
+    for (uint32_t u = 0; u < pop->n_demes; ++u) {
+        const uint32_t n0 = reps[P.demes[u].rep].n0;
+        e = launch_init(pop->d_descs() + u, pop->dev_descs[u], n0, pop->stream);
+        if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + u, pop->d_states() + u, n0, 0, pop->stream);
         if (e != hipSuccess) {
             delete pop;
             return fail(SPEGG_E_DEVICE, "initial population: %s", hipGetErrorString(e));
@@ -569,6 +661,15 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
 spegg_status spegg_step_generations(spegg_pop *pop, uint32_t n_generations) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
+    // the patches of a replicate read each other's generation buffers
+    for (uint32_t i = 0; i < pop->n_reps; ++i) {
+        const RepPlan &p = pop->plan.reps[i];
+        for (uint32_t k = 1; k < p.n_demes; ++k)
+            if (pop->deme_gen[p.deme0 + k] != pop->deme_gen[p.deme0])
+                return fail(SPEGG_E_STATE, "replicate %u: patch %u is at generation %u, patch 0 at %u", i, k,
+                            pop->deme_gen[p.deme0 + k], pop->deme_gen[p.deme0]);
+    }
+    for (uint32_t &g : pop->deme_gen) g += n_generations;
     DeviceGuard guard(pop->device);
     // Graph replay needs a capturable stream and no per-launch events.
     const bool graphs = pop->use_graph && pop->stream != nullptr && pop->timing == 0;
@@ -603,22 +704,30 @@ spegg_status spegg_set_graph(spegg_pop *pop, int enable) {
 spegg_status spegg_stats(spegg_pop *pop, spegg_rep_stats *host_out, uint32_t n) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
-    if (!host_out || n > pop->n_reps) return fail(SPEGG_E_INVALID, "stats: need 0 < n <= %u and a buffer", pop->n_reps);
+    if (!host_out || n == 0 || n > pop->n_reps)
+        return fail(SPEGG_E_INVALID, "stats: need 0 < n <= %u and a buffer", pop->n_reps);
     DeviceGuard guard(pop->device);
-    std::vector<RepState> s(n);
-    hipError_t e = launch_census(pop->d_descs(), pop->d_states(), pop->d_partials(), n, pop->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(s.data(), pop->d_states(), sizeof(RepState) * n, hipMemcpyDeviceToHost, pop->stream);
-    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(stats)");
-    st = sync_stream(pop);
-    if (st != SPEGG_OK) return st;
+    const RepPlan &last = pop->plan.reps[n - 1];
+    std::vector<spegg_rep_stats> per;
+    if ((st = deme_stats(pop, last.deme0 + last.n_demes, per)) != SPEGG_OK) return st;
     for (uint32_t i = 0; i < n; ++i) {
-        if (s[i].error) {
-            pop->errored = true;
-            return fail(SPEGG_E_DEVICE, "replicate %u: a kernel reported an impossible state", i);
-        }
-        host_out[i] = census_of(s[i]);
+        const RepPlan &p = pop->plan.reps[i];
+        host_out[i] = sum_of(per.data() + p.deme0, p.n_demes);
     }
+    return SPEGG_OK;
+}
+
+spegg_status spegg_patch_stats(spegg_pop *pop, uint32_t rep, spegg_rep_stats *host_out, uint32_t n) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if (rep >= pop->n_reps) return fail(SPEGG_E_INVALID, "replicate %u out of range (%u)", rep, pop->n_reps);
+    const RepPlan &p = pop->plan.reps[rep];
+    if (!host_out || n != p.n_demes)
+        return fail(SPEGG_E_INVALID, "patch_stats: replicate %u has %u patches", rep, p.n_demes);
+    DeviceGuard guard(pop->device);
+    std::vector<spegg_rep_stats> per;
+    if ((st = deme_stats(pop, p.deme0 + p.n_demes, per)) != SPEGG_OK) return st;
+    for (uint32_t k = 0; k < n; ++k) host_out[k] = per[p.deme0 + k];
     return SPEGG_OK;
 }
 
@@ -626,11 +735,12 @@ spegg_status spegg_read_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, ui
                                 size_t n_words, uint32_t *n_out) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
-    if ((st = check_rep(pop, rep, patch, species)) != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, species, &u)) != SPEGG_OK) return st;
     DeviceGuard guard(pop->device);
     RepState s;
-    if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
-    const RepDesc &h = pop->dev_descs[rep];
+    if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
+    const RepDesc &h = pop->dev_descs[u];
     const uint32_t n = s.n[current_pair_host(s)], t = s.t[current_pair_host(s)];
     const size_t words = (size_t)n * 2u * h.W;
     if (n_out) *n_out = n;
@@ -647,8 +757,9 @@ spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, u
                                  const uint32_t *host_words, uint32_t n, uint32_t generation) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
-    if ((st = check_rep(pop, rep, patch, species)) != SPEGG_OK) return st;
-    const RepDesc &h = pop->dev_descs[rep];
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, species, &u)) != SPEGG_OK) return st;
+    const RepDesc &h = pop->dev_descs[u];
     if (n > h.cap) return fail(SPEGG_E_INVALID, "write_genomes: %u individuals exceed capacity %u", n, h.cap);
     if (n > 0 && !host_words) return fail(SPEGG_E_INVALID, "write_genomes: null words");
     for (uint32_t i = 0; i < n; ++i)
@@ -663,63 +774,69 @@ spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, u
     if (n > 0)
         e = hipMemcpyAsync(h.genome[buf], host_words, (size_t)n * 2u * h.W * sizeof(uint32_t), hipMemcpyHostToDevice,
                            pop->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(pop->d_states() + rep, &s0, sizeof s0, hipMemcpyHostToDevice, pop->stream);
-    if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + rep, pop->d_states() + rep, n, buf, pop->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(pop->d_states() + u, &s0, sizeof s0, hipMemcpyHostToDevice, pop->stream);
+    if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + u, pop->d_states() + u, n, buf, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "write_genomes");
-    return sync_stream(pop);
+    st = sync_stream(pop);
+    if (st == SPEGG_OK) pop->deme_gen[u] = generation;
+    return st;
 }
 
-spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, int32_t *host_z, size_t n, uint32_t *n_out) {
+spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, uint32_t patch, int32_t *host_z, size_t n,
+                                   uint32_t *n_out) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
-    if ((st = check_rep(pop, rep, 0, 0)) != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
     DeviceGuard guard(pop->device);
     RepState s;
-    if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
+    if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
     const uint32_t cn = s.n[current_pair_host(s)], ct = s.t[current_pair_host(s)];
     if (n_out) *n_out = cn;
     if (cn == 0) return SPEGG_OK;
     if (!host_z || n < cn) return fail(SPEGG_E_INVALID, "read_phenotypes: need room for %u values", cn);
-    hipError_t e = hipMemcpyAsync(host_z, pop->dev_descs[rep].z[ct & 1u], (size_t)cn * sizeof(int32_t),
+    hipError_t e = hipMemcpyAsync(host_z, pop->dev_descs[u].z[ct & 1u], (size_t)cn * sizeof(int32_t),
                                   hipMemcpyDeviceToHost, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(phenotypes)");
     return sync_stream(pop);
 }
 
-spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t *host_idx, size_t n, uint32_t *n_out) {
+spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *host_idx, size_t n,
+                                  uint32_t *n_out) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
-    if ((st = check_rep(pop, rep, 0, 0)) != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
     DeviceGuard guard(pop->device);
     RepState s;
-    if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
+    if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
     const uint32_t m = s.n_surv;
     if (n_out) *n_out = m;
     if (m == 0) return SPEGG_OK;
     if (!host_idx || n < m) return fail(SPEGG_E_INVALID, "read_survivors: need room for %u indices", m);
-    hipError_t e = hipMemcpyAsync(host_idx, pop->dev_descs[rep].S, (size_t)m * sizeof(uint32_t),
+    hipError_t e = hipMemcpyAsync(host_idx, pop->dev_descs[u].S, (size_t)m * sizeof(uint32_t),
                                   hipMemcpyDeviceToHost, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(survivors)");
     return sync_stream(pop);
 }
 
-spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t *counts_dev, uint32_t *host_counts,
-                                 uint32_t n_loci, uint32_t *n_out) {
+spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *counts_dev,
+                                 uint32_t *host_counts, uint32_t n_loci, uint32_t *n_out) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
-    if ((st = check_rep(pop, rep, 0, 0)) != SPEGG_OK) return st;
-    const RepDesc &h = pop->dev_descs[rep];
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
+    const RepDesc &h = pop->dev_descs[u];
     if (n_loci != h.L || !counts_dev || !host_counts)
         return fail(SPEGG_E_INVALID, "allele_counts: need n_loci == %u and both arrays", h.L);
     DeviceGuard guard(pop->device);
     RepState s;
-    if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
+    if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
     const uint32_t n = s.n[current_pair_host(s)];
     if (n_out) *n_out = n;
     hipError_t e = hipMemsetAsync(counts_dev, 0, sizeof(uint32_t) * h.L, pop->stream);
-    if (e == hipSuccess) e = launch_allele_counts(pop->d_descs() + rep, pop->d_states() + rep, h, n, counts_dev,
-                                                  pop->stream);
+    if (e == hipSuccess)
+        e = launch_allele_counts(pop->d_descs() + u, pop->d_states() + u, h, n, counts_dev, pop->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(host_counts, counts_dev, sizeof(uint32_t) * h.L, hipMemcpyDeviceToHost, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "allele_counts");
@@ -734,24 +851,33 @@ spegg_status spegg_set_trace(spegg_pop *pop, int enable) {
     return SPEGG_OK;
 }
 
-spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t *host_mom, uint32_t *host_dad, size_t n,
-                                uint32_t *n_out) {
+spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *host_mom, uint32_t *host_dad,
+                                uint32_t *host_src, size_t n, uint32_t *n_out) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
-    if ((st = check_rep(pop, rep, 0, 0)) != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
     DeviceGuard guard(pop->device);
     RepState s;
-    if ((st = read_state(pop, rep, s)) != SPEGG_OK) return st;
+    if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
     if (!s.traced) return fail(SPEGG_E_STATE, "read_parents: tracing was off for the last generation");
     const uint32_t cn = s.n[current_pair_host(s)];
     if (n_out) *n_out = cn;
     if (cn == 0) return SPEGG_OK;
     if (!host_mom || !host_dad || n < cn) return fail(SPEGG_E_INVALID, "read_parents: need room for %u entries", cn);
-    const RepDesc &h = pop->dev_descs[rep];
+    const RepDesc &h = pop->dev_descs[u];
     hipError_t e = hipMemcpyAsync(host_mom, h.mom, (size_t)cn * sizeof(uint32_t), hipMemcpyDeviceToHost, pop->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(host_dad, h.dad, (size_t)cn * sizeof(uint32_t), hipMemcpyDeviceToHost, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(parents)");
+    if (host_src) {
+        if (h.src) {
+            e = hipMemcpyAsync(host_src, h.src, (size_t)cn * sizeof(uint32_t), hipMemcpyDeviceToHost, pop->stream);
+            if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(parents)");
+        } else {
+            for (uint32_t j = 0; j < cn; ++j) host_src[j] = patch;  // no migration: the home patch
+        }
+    }
     return sync_stream(pop);
 }
 

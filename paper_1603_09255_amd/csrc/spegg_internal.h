@@ -1,9 +1,12 @@
 // Internal types shared by the host side and the kernels of libspegg.
 //
+// The kernels work on demes: one patch of one replicate.  A replicate of P
+// patches is P consecutive demes sharing its tables.
+//
 // Device memory of a population is one caller-owned block, carved into:
-//   [RepDesc x n_reps][RepState x n_reps][SurvTile...][OffTile...][tables]  uploaded once at create
-//   [SurvCount...][Partial...][per-replicate buffers]                       written by kernels
-// Per replicate: two genome buffers (ping-pong by generation parity), two
+//   [RepDesc x n_demes][RepState x n_demes][SurvTile...][OffTile...][tables]  uploaded once at create
+//   [SurvCount...][Partial...][per-deme buffers]                              written by kernels
+// Per deme: two genome buffers (ping-pong by generation parity), two
 // phenotype buffers, the fates, the survivor list, the slot-owner list
 // (Poisson regime) and the parent trace.
 #pragma once
@@ -26,7 +29,8 @@ enum Stream : uint32_t {
     kStFecund = 4,
     kStParent = 5,
     kStRecomb = 6,  // + 0 maternal gamete, + 1 paternal
-    kStMutate = 8   // + 0 maternal gamete, + 1 paternal
+    kStMutate = 8,  // + 0 maternal gamete, + 1 paternal
+    kStMigrate = 10
 };
 
 // Crossover sampling, a function of r alone.
@@ -56,18 +60,23 @@ struct RepDesc {
     uint32_t off_tile0, off_ntiles, off_per_tile;  // offspring tiles: global index of the first
     float geo_scale;     // 1 / log2(1 - r): first guess of a geometric gap (checked against geo)
     double K, lambda;    // Beverton-Holt density factor; 0 < K enables it
+    uint64_t mig_T;      // a newborn is a migrant when MIGRATE word 0 < mig_T; 0: no migration
+    uint32_t patch;      // patch of the deme within its replicate
+    uint32_t left, right;  // demes of the ring neighbours (the deme itself without migration)
+    uint32_t pad1;
     uint32_t *genome[2];
     int32_t *z[2];
     uint16_t *fate;      // per adult: bit 15 survived, bits 0..14 offspring as mother
     uint32_t *S;         // survivors, ascending
     uint32_t *owner;     // mother of each offspring slot (Poisson regime)
     uint32_t *mom, *dad; // parent trace
+    uint32_t *src;       // parent trace: patch of the parents
     const double *vtab;  // viability by phenotype, NULL: selection off
     const uint64_t *pois, *binom, *geo;
     const uint32_t *planes;  // 6 x W effect bit-planes: +1,+2,+4 then -1,-2,-4
 };
 
-// Per-replicate state.  The census (generation t, size n) is double-buffered:
+// Per-deme state.  The census (generation t, size n) is double-buffered:
 // the current census is the pair with the larger t (compared modulo 2^32);
 // a generation reads it and writes (t + 1, newborns) into the other pair.
 struct RepState {
@@ -79,7 +88,7 @@ struct RepState {
     uint32_t traced;          // parents of the current newborns were recorded
     uint32_t census_pending;  // census sums still sit in the offspring tiles' partials
     uint32_t error;           // set by a kernel that found an impossible state (never expected)
-    uint32_t pad0;
+    uint32_t captures;        // consumers: credited captures of the last generation
     uint64_t near_ties, truncated, updates, sum_threshold;
     int64_t sum_z[kCensusSlots];
     uint64_t sum_z2[kCensusSlots];
@@ -162,7 +171,7 @@ struct OffArgs {
     const RepState *states;
     const OffTile *tiles;
     uint32_t tile0, ntiles;
-    int single_rep;  // >= 0: the class's only replicate, tiles implicit
+    int single_deme;  // >= 0: the class's only replicate, tiles implicit
     Partial *partials;
     uint32_t plane_words;  // LDS words reserved for the effect planes
     uint32_t grid;
@@ -180,6 +189,9 @@ hipError_t launch_offspring(OffShape shape, const OffArgs &a);
 // Fold pending per-tile census sums into each replicate's state.
 hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,
                          hipStream_t s);
+
+// Set the calling thread's message returned by spegg_last_error.
+void set_last_error(const char *msg);
 
 // Host twin of the kernels' choice of the current census pair.
 inline uint32_t current_pair_host(const RepState &st) { return (int32_t)(st.t[1] - st.t[0]) > 0 ? 1u : 0u; }

@@ -27,6 +27,12 @@ bool put(std::vector<uint64_t> &T, long double cdf, int k, int cap) {
 }
 }  // namespace
 
+uint64_t prob_threshold(double p) {
+    if (p >= 1.0) return kAlways;
+    if (!(p > 0.0)) return 0;
+    return (uint64_t)std::floor(p * 4294967296.0);
+}
+
 // Poisson(lambda): p_0 = e^-lambda, p_k = p_{k-1} lambda / k.
 bool poisson_table(double lambda, int cap, std::vector<uint64_t> &T) {
     T.clear();

@@ -14,6 +14,8 @@ bool poisson_table(double lambda, int cap, std::vector<uint64_t> &T);
 bool binomial_table(uint32_t L, double mu, int cap, std::vector<uint64_t> &T);
 void geometric_table(double r, uint32_t n, std::vector<uint64_t> &T);
 uint32_t recomb_mode(double r);
+// Bernoulli(p) threshold floor(p 2^32); p >= 1: 2^32 (always), p <= 0: 0.
+uint64_t prob_threshold(double p);
 void viability_table(double theta, double omega, int32_t zmin, uint32_t n, std::vector<double> &v);
 
 }  // namespace spegg

@@ -32,13 +32,14 @@ class RepDesc(C.Structure):
         ("n0", C.c_uint32),
         ("capacity", C.c_uint32),
         ("n_loci", C.c_uint32),
-        ("reserved", C.c_uint32),
+        ("n_patches", C.c_uint32),
         ("mu", C.c_double),
         ("r", C.c_double),
         ("theta", C.c_double),
         ("omega", C.c_double),
         ("K", C.c_double),
         ("fecundity", C.c_double),
+        ("migration", C.c_double),
         ("effects", C.POINTER(C.c_int8)),
     ]
 
@@ -50,7 +51,7 @@ class RepStats(C.Structure):
         ("n_parents", C.c_uint32),
         ("n_survivors", C.c_uint32),
         ("extinct", C.c_uint32),
-        ("reserved", C.c_uint32),
+        ("captures", C.c_uint32),
         ("sum_z", C.c_int64),
         ("sum_z2", C.c_int64),
         ("near_ties", C.c_uint64),
@@ -60,7 +61,7 @@ class RepStats(C.Structure):
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None
@@ -89,20 +90,22 @@ def load():
     lib.spegg_step_generations.argtypes = [vp, u32]
     lib.spegg_stats.restype = st
     lib.spegg_stats.argtypes = [vp, C.POINTER(RepStats), u32]
+    lib.spegg_patch_stats.restype = st
+    lib.spegg_patch_stats.argtypes = [vp, u32, C.POINTER(RepStats), u32]
     lib.spegg_read_genomes.restype = st
     lib.spegg_read_genomes.argtypes = [vp, u32, u32, u32, P32, C.c_size_t, P32]
     lib.spegg_write_genomes.restype = st
     lib.spegg_write_genomes.argtypes = [vp, u32, u32, u32, P32, u32, u32]
     lib.spegg_read_phenotypes.restype = st
-    lib.spegg_read_phenotypes.argtypes = [vp, u32, C.POINTER(C.c_int32), C.c_size_t, P32]
+    lib.spegg_read_phenotypes.argtypes = [vp, u32, u32, C.POINTER(C.c_int32), C.c_size_t, P32]
     lib.spegg_read_survivors.restype = st
-    lib.spegg_read_survivors.argtypes = [vp, u32, P32, C.c_size_t, P32]
+    lib.spegg_read_survivors.argtypes = [vp, u32, u32, P32, C.c_size_t, P32]
     lib.spegg_allele_counts.restype = st
-    lib.spegg_allele_counts.argtypes = [vp, u32, vp, P32, u32, P32]
+    lib.spegg_allele_counts.argtypes = [vp, u32, u32, vp, P32, u32, P32]
     lib.spegg_set_trace.restype = st
     lib.spegg_set_trace.argtypes = [vp, C.c_int]
     lib.spegg_read_parents.restype = st
-    lib.spegg_read_parents.argtypes = [vp, u32, P32, P32, C.c_size_t, P32]
+    lib.spegg_read_parents.argtypes = [vp, u32, u32, P32, P32, P32, C.c_size_t, P32]
     lib.spegg_set_graph.restype = st
     lib.spegg_set_graph.argtypes = [vp, C.c_int]
     lib.spegg_set_timing.restype = st
@@ -117,6 +120,20 @@ def load():
     lib.spegg_recomb_mode.argtypes = [C.c_double]
     lib.spegg_philox_fill.restype = st
     lib.spegg_philox_fill.argtypes = [C.c_uint64, vp, vp, u32, vp]
+    lib.spegg_server_create.restype = st
+    lib.spegg_server_create.argtypes = [vp, C.c_size_t, vp, u32, C.POINTER(vp)]
+    lib.spegg_server_submit.restype = st
+    lib.spegg_server_submit.argtypes = [vp, C.c_uint64, C.POINTER(RepDesc), u32, u32]
+    lib.spegg_server_step.restype = st
+    lib.spegg_server_step.argtypes = [vp, u32, P32, P32]
+    lib.spegg_server_poll.restype = st
+    lib.spegg_server_poll.argtypes = [vp, C.POINTER(C.c_uint64), u32, P32]
+    lib.spegg_server_result.restype = st
+    lib.spegg_server_result.argtypes = [vp, C.c_uint64, C.POINTER(RepStats), u32]
+    lib.spegg_server_usage.restype = st
+    lib.spegg_server_usage.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    lib.spegg_server_destroy.restype = None
+    lib.spegg_server_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -135,7 +152,7 @@ def _p(arr, ctype):
 
 
 DESC_KEYS = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
-             "fecundity", "effects")
+             "fecundity", "effects", "n_patches", "migration")
 
 
 def make_descs(reps):
@@ -153,8 +170,8 @@ def make_descs(reps):
         arr[k].n0 = n0
         arr[k].capacity = int(d.get("capacity", n0))
         arr[k].n_loci = int(d.get("n_loci", 64))
-        arr[k].reserved = 0
-        for f in ("mu", "r", "theta", "omega", "K", "fecundity"):
+        arr[k].n_patches = int(d.get("n_patches", 1))
+        for f in ("mu", "r", "theta", "omega", "K", "fecundity", "migration"):
             setattr(arr[k], f, float(d.get(f, 0.5 if f == "r" else 0.0)))
         eff = d.get("effects")
         if eff is not None:
@@ -196,7 +213,8 @@ def philox_fill(seed, ctr):
 
 
 class Population:
-    """Replicates resident in device memory, advanced by the HIP kernels."""
+    """Replicates resident in device memory, advanced by the HIP kernels.
+    Per-patch accessors take ``patch`` (0 for single-patch replicates)."""
 
     def __init__(self, reps, device="cuda", stream=None):
         import torch
@@ -220,6 +238,7 @@ class Population:
         self._h = h
         self.L = [int(d.get("n_loci", 64)) for d in self.reps]
         self.W = [(L + 31) // 32 for L in self.L]
+        self.P = [int(d.get("n_patches", 1)) for d in self.reps]
         del keep
 
     def close(self):
@@ -247,45 +266,54 @@ class Population:
         check(self.lib.spegg_stats(self._h, out, self.n_reps))
         return [s.as_dict() for s in out]
 
-    def _n_of(self, rep):
-        return self.stats()[rep]["n"]
+    def patch_stats(self, rep=0):
+        """The census of each of replicate rep's patches."""
+        out = (RepStats * self.P[rep])()
+        check(self.lib.spegg_patch_stats(self._h, rep, out, self.P[rep]))
+        return [s.as_dict() for s in out]
 
-    def genomes(self, rep=0):
-        n = self._n_of(rep)
+    def _n_of(self, rep, patch=0):
+        per = self.patch_stats(rep)
+        if not 0 <= patch < len(per):
+            raise SpeggError(E_INVALID, f"patch {patch} out of range (replicate {rep} has {len(per)})")
+        return per[patch]["n"]
+
+    def genomes(self, rep=0, patch=0):
+        n = self._n_of(rep, patch)
         W = self.W[rep]
         out = np.zeros(max(n, 1) * 2 * W, dtype=np.uint32)
         got = C.c_uint32()
-        check(self.lib.spegg_read_genomes(self._h, rep, 0, 0, _p(out, C.c_uint32), out.size, C.byref(got)))
+        check(self.lib.spegg_read_genomes(self._h, rep, patch, 0, _p(out, C.c_uint32), out.size, C.byref(got)))
         return out[: got.value * 2 * W].reshape(got.value, 2, W)
 
-    def write_genomes(self, rep, words, generation):
+    def write_genomes(self, rep, words, generation, patch=0):
         w = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1)
         n = w.size // (2 * self.W[rep])
-        check(self.lib.spegg_write_genomes(self._h, rep, 0, 0, _p(w, C.c_uint32), n, int(generation)))
+        check(self.lib.spegg_write_genomes(self._h, rep, patch, 0, _p(w, C.c_uint32), n, int(generation)))
 
-    def phenotypes(self, rep=0):
-        n = self._n_of(rep)
+    def phenotypes(self, rep=0, patch=0):
+        n = self._n_of(rep, patch)
         out = np.zeros(max(n, 1), dtype=np.int32)
         got = C.c_uint32()
-        check(self.lib.spegg_read_phenotypes(self._h, rep, _p(out, C.c_int32), out.size, C.byref(got)))
+        check(self.lib.spegg_read_phenotypes(self._h, rep, patch, _p(out, C.c_int32), out.size, C.byref(got)))
         return out[: got.value]
 
-    def survivors(self, rep=0):
-        n = self.stats()[rep]["n_survivors"]
+    def survivors(self, rep=0, patch=0):
+        n = self.patch_stats(rep)[patch]["n_survivors"]
         out = np.zeros(max(n, 1), dtype=np.uint32)
         got = C.c_uint32()
-        check(self.lib.spegg_read_survivors(self._h, rep, _p(out, C.c_uint32), out.size, C.byref(got)))
+        check(self.lib.spegg_read_survivors(self._h, rep, patch, _p(out, C.c_uint32), out.size, C.byref(got)))
         return out[: got.value]
 
-    def allele_counts(self, rep=0):
-        """Copies of allele 1 per locus over the current census (uint32, L)."""
+    def allele_counts(self, rep=0, patch=0):
+        """Copies of allele 1 per locus over a patch's current census (uint32, L)."""
         import torch
         L = self.L[rep]
         scratch = torch.empty(L, dtype=torch.int32, device=self.workspace.device)
         out = np.zeros(L, dtype=np.uint32)
         got = C.c_uint32()
-        check(self.lib.spegg_allele_counts(self._h, rep, C.c_void_p(scratch.data_ptr()), _p(out, C.c_uint32), L,
-                                           C.byref(got)))
+        check(self.lib.spegg_allele_counts(self._h, rep, patch, C.c_void_p(scratch.data_ptr()), _p(out, C.c_uint32),
+                                           L, C.byref(got)))
         return out
 
     def set_graph(self, enable=True):
@@ -295,13 +323,18 @@ class Population:
     def set_trace(self, enable=True):
         check(self.lib.spegg_set_trace(self._h, 1 if enable else 0))
 
-    def parents(self, rep=0):
-        n = self._n_of(rep)
+    def parents(self, rep=0, patch=0, with_source=False):
+        """Mother and father of each current newborn (indices into the adults
+        of the patch they came from) and, with_source, that patch."""
+        n = self._n_of(rep, patch)
         mom = np.zeros(max(n, 1), dtype=np.uint32)
         dad = np.zeros(max(n, 1), dtype=np.uint32)
+        src = np.zeros(max(n, 1), dtype=np.uint32)
         got = C.c_uint32()
-        check(self.lib.spegg_read_parents(self._h, rep, _p(mom, C.c_uint32), _p(dad, C.c_uint32), mom.size,
-                                          C.byref(got)))
+        check(self.lib.spegg_read_parents(self._h, rep, patch, _p(mom, C.c_uint32), _p(dad, C.c_uint32),
+                                          _p(src, C.c_uint32), mom.size, C.byref(got)))
+        if with_source:
+            return mom[: got.value], dad[: got.value], src[: got.value]
         return mom[: got.value], dad[: got.value]
 
     def set_timing(self, kernels=("survive", "compact", "offspring")):
@@ -318,3 +351,71 @@ class Population:
         n = (C.c_uint64 * k)()
         check(self.lib.spegg_kernel_times(self._h, ms, n, k))
         return {KERNEL_NAMES[i]: (ms[i], n[i]) for i in range(k)}
+
+
+class Server:
+    """Sweep jobs served from one device arena with continuous batching
+    (the library's native scheduler; this class only marshals arguments).
+
+    ``arena`` is a device pointer (int) and its size, or None to allocate
+    ``arena_bytes`` with torch.  Without a device (``arena`` given as a
+    plain aligned integer) only submission checks can run."""
+
+    def __init__(self, arena_bytes, arena=None, stream=None, device="cuda", n_streams=4):
+        self.lib = load()
+        self.workspace = None
+        if arena is None:
+            import torch
+            self.workspace = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+            arena = self.workspace.data_ptr()
+            if stream is None:
+                stream = torch.cuda.Stream(device=self.workspace.device)
+                stream.wait_stream(torch.cuda.current_stream(self.workspace.device))
+        self.stream = stream
+        sptr = stream.cuda_stream if stream is not None and hasattr(stream, "cuda_stream") else stream
+        h = C.c_void_p()
+        check(self.lib.spegg_server_create(C.c_void_p(int(arena)), int(arena_bytes), C.c_void_p(sptr),
+                                           int(n_streams), C.byref(h)))
+        self._h = h
+        self.n_reps = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.spegg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, job_id, reps, generations):
+        arr, keep = make_descs(reps)
+        check(self.lib.spegg_server_submit(self._h, int(job_id), arr, len(reps), int(generations)))
+        self.n_reps[int(job_id)] = len(reps)
+        del keep
+
+    def step(self, generations=1):
+        """One scheduling step; returns (resident, waiting)."""
+        res, wait = C.c_uint32(), C.c_uint32()
+        check(self.lib.spegg_server_step(self._h, int(generations), C.byref(res), C.byref(wait)))
+        return res.value, wait.value
+
+    def poll(self, cap=1024):
+        ids = (C.c_uint64 * cap)()
+        n = C.c_uint32()
+        check(self.lib.spegg_server_poll(self._h, ids, cap, C.byref(n)))
+        return [int(ids[i]) for i in range(n.value)]
+
+    def result(self, job_id):
+        n = self.n_reps[int(job_id)]
+        out = (RepStats * n)()
+        check(self.lib.spegg_server_result(self._h, int(job_id), out, n))
+        del self.n_reps[int(job_id)]
+        return [x.as_dict() for x in out]
+
+    def usage(self):
+        used, free = C.c_size_t(), C.c_size_t()
+        check(self.lib.spegg_server_usage(self._h, C.byref(used), C.byref(free)))
+        return used.value, free.value

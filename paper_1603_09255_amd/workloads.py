@@ -62,3 +62,33 @@ def random_genomes(n, L, seed, p_one=0.5):
     bits = (g.random((n, 2, W * 32)) < p_one).astype(np.uint8)
     bits[:, :, L:] = 0
     return np.packbits(bits, axis=-1, bitorder="little").view(np.uint32).reshape(n, 2, W).copy()
+
+
+def serve_trace(n_jobs=200, rate=20.0, seed=7, philox_seed=1, reps=(8, 256), gens=(100, 2000),
+                patch_n=(200, 5000), n_patches=100, n_loci=256, migration=0.01):
+    """Sweep jobs of the served form, arriving as a Poisson process of the
+    given rate (jobs/s): each job is one parameter combination -- its own
+    per-patch census N ~ U{patch_n}, mu log-uniform in [1e-7, 1e-4],
+    r ~ U[0.001, 0.5], selection width ~ U[2, 16] -- run as U{reps}
+    replicates of a ring of n_patches Wright-Fisher patches (L loci, unit
+    effects, backward migration rate m) for U{gens} generations.
+
+    Returns [(arrival_s, job_id, [descs], generations)] in arrival order.
+    Replicate ids are unique over the trace, so no two replicates share a
+    random stream."""
+    g = np.random.default_rng(seed)
+    arrivals = np.cumsum(g.exponential(1.0 / rate, n_jobs))
+    jobs, rid = [], 0
+    for k in range(n_jobs):
+        R = int(g.integers(reps[0], reps[1] + 1))
+        G = int(g.integers(gens[0], gens[1] + 1))
+        N = int(g.integers(patch_n[0], patch_n[1] + 1))
+        mu = float(10.0 ** g.uniform(-7.0, -4.0))
+        r = float(g.uniform(0.001, 0.5))
+        omega = float(g.uniform(2.0, 16.0))
+        descs = [dict(seed=philox_seed, replicate_id=rid + i, regime=WF, n0=N, capacity=N, n_loci=n_loci, mu=mu,
+                      r=r, theta=0.0, omega=omega, K=0.0, fecundity=0.0, effects=None, n_patches=n_patches,
+                      migration=migration) for i in range(R)]
+        rid += R
+        jobs.append((float(arrivals[k]), k, descs, G))
+    return jobs

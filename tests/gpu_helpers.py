@@ -8,7 +8,7 @@ import oracle
 from paper_1603_09255_amd import spegg
 
 ORACLE_KEYS = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
-               "fecundity", "effects")
+               "fecundity", "effects", "n_patches", "migration")
 
 
 def say(*args):
@@ -21,22 +21,31 @@ def oracle_pop(desc):
 
 
 def assert_same_state(gpu, rep, orc, what, parents=False):
+    """Every output of replicate rep equal to the oracle's: the replicate's
+    census, and per patch the census, genomes, phenotypes, survivors and
+    (parents=True) the traced parents with their source patch."""
     sg = gpu.stats()[rep]
-    so = orc.stats()
+    so = orc.total_stats()
     assert sg == so, f"{what}: stats differ\n gpu    {sg}\n oracle {so}"
-    g = gpu.genomes(rep)
-    o = orc.genomes()
-    assert g.shape == o.shape, f"{what}: genome shapes {g.shape} vs {o.shape}"
-    if not np.array_equal(g, o):
-        bad = np.argwhere(g != o)
-        raise AssertionError(f"{what}: {len(bad)} genome words differ, first at {bad[:5].tolist()}")
-    assert np.array_equal(gpu.phenotypes(rep), orc.phenotypes()), f"{what}: phenotypes differ"
-    if so["generation"] > 0 and so["n_parents"] > 0:
-        assert np.array_equal(gpu.survivors(rep), orc.survivors()), f"{what}: survivor lists differ"
-    if parents and so["n"] > 0:
-        gm, gd = gpu.parents(rep)
-        om, od = orc.parents()
-        assert np.array_equal(gm, om) and np.array_equal(gd, od), f"{what}: parents differ"
+    per = gpu.patch_stats(rep)
+    for k in range(orc.n_patches):
+        wk = f"{what}, patch {k}"
+        sok = orc.stats(k)
+        assert per[k] == sok, f"{wk}: stats differ\n gpu    {per[k]}\n oracle {sok}"
+        g = gpu.genomes(rep, k)
+        o = orc.genomes(k)
+        assert g.shape == o.shape, f"{wk}: genome shapes {g.shape} vs {o.shape}"
+        if not np.array_equal(g, o):
+            bad = np.argwhere(g != o)
+            raise AssertionError(f"{wk}: {len(bad)} genome words differ, first at {bad[:5].tolist()}")
+        assert np.array_equal(gpu.phenotypes(rep, k), orc.phenotypes(k)), f"{wk}: phenotypes differ"
+        if sok["generation"] > 0 and sok["n_parents"] > 0:
+            assert np.array_equal(gpu.survivors(rep, k), orc.survivors(k)), f"{wk}: survivor lists differ"
+        if parents and sok["n"] > 0:
+            gm, gd, gs = gpu.parents(rep, k, with_source=True)
+            om, od, os_ = orc.parents(k, with_source=True)
+            assert np.array_equal(gs, os_), f"{wk}: source patches differ"
+            assert np.array_equal(gm, om) and np.array_equal(gd, od), f"{wk}: parents differ"
 
 
 def lockstep(desc, generations, start_words=None, start_gen=0, trace=True, check_every=1):

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_function(lib):
     assert len(names) >= 15
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.spegg_abi_version() == 1
+    assert lib.spegg_abi_version() == 2
 
 
 @pytest.mark.parametrize("lam", [0.0, 0.5, 2.2, 10.0, 30.0, 200.0])
@@ -82,12 +82,23 @@ def base_desc(**kw):
     (dict(regime=1, fecundity=-1.0), "fecundity"),
     (dict(regime=1, fecundity=5000.0), "fecundity"),
     (dict(theta=float("nan")), "theta"),
+    (dict(n_patches=0), "n_patches"),
+    (dict(n_patches=1025), "n_patches"),
+    (dict(n_patches=2, migration=1.5), "migration"),
+    (dict(n_patches=2, regime=1, fecundity=2.0, capacity=200), "Wright-Fisher"),
 ])
 def test_invalid_descriptors_are_rejected(bad, needle):
     with pytest.raises(spegg.SpeggError) as ei:
         spegg.footprint([base_desc(), base_desc(**bad)])
     assert needle in str(ei.value)
     assert "replicate 1" in str(ei.value)
+
+
+def test_footprint_counts_every_patch():
+    one = spegg.footprint([base_desc(capacity=1000, n0=10)])
+    ring = spegg.footprint([base_desc(capacity=1000, n0=10, n_patches=5, migration=0.1)])
+    # five patches of buffers (plus the parent-source trace), one set of tables
+    assert 4.5 * one < ring < 6 * one
 
 
 def test_footprint_scales_with_capacity_and_loci():

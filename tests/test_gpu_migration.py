@@ -1,0 +1,130 @@
+"""GPU parity of patches on a ring with backward migration (Supplementary
+Information S3): the HIP library against the oracle, bit for bit, per patch
+-- genomes, phenotypes, survivors, parents with their source patch and the
+census -- after every generation."""
+import numpy as np
+import pytest
+
+from gpu_helpers import assert_same_state, oracle_pop, say
+from paper_1603_09255_amd import spegg, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def ring(**kw):
+    d = dict(seed=5, replicate_id=3, regime=0, n0=200, capacity=200, n_loci=64, mu=1e-3, r=0.5, theta=0.0,
+             omega=6.0, n_patches=3, migration=0.1)
+    d.update(kw)
+    return d
+
+
+RING_CASES = [
+    ("p3_raw", ring(), 10),
+    ("p2_skip", ring(n_patches=2, n0=300, capacity=300, n_loci=100, r=0.05, migration=0.3), 8),
+    ("p8_lazy_l256", ring(n_patches=8, n0=150, capacity=150, n_loci=256, r=0.3, omega=4.0, migration=0.01), 8),
+    ("p4_all_migrants", ring(n_patches=4, migration=1.0, r=0.0), 6),
+    ("p5_strong_selection", ring(n_patches=5, n0=120, capacity=120, omega=1.5, migration=0.2, r=0.2), 8),
+    ("p1_rate_ignored", ring(n_patches=1, migration=0.5), 6),
+    ("p3_no_migration", ring(migration=0.0), 6),
+]
+
+
+@pytest.mark.parametrize("name,desc,gens", RING_CASES, ids=[c[0] for c in RING_CASES])
+def test_ring_lockstep(name, desc, gens):
+    say("ring lockstep", name)
+    gpu = spegg.Population([desc])
+    gpu.set_trace(True)
+    orc = oracle_pop(desc)
+    assert_same_state(gpu, 0, orc, f"{name} start")
+    for _ in range(gens):
+        gpu.step(1)
+        orc.step(1)
+        assert_same_state(gpu, 0, orc, f"{name} generation {orc.generation}", parents=True)
+    gpu.close()
+    orc.close()
+
+
+def pack(alleles):
+    n, _, L = alleles.shape
+    words = np.zeros((n, 2, (L + 31) // 32), np.uint32)
+    for l in range(L):
+        words[:, :, l // 32] |= alleles[:, :, l].astype(np.uint32) << np.uint32(l % 32)
+    return words
+
+
+def test_dead_patch_is_refilled_and_dead_rings_go_extinct():
+    P, N, L = 5, 300, 64
+    d = ring(seed=30, n_patches=P, n0=N, capacity=N, n_loci=L, omega=0.5, migration=0.05, mu=0.0)
+    ones = pack(np.ones((N, 2, L), np.uint8))  # z = L: dies surely
+    het = np.zeros((N, 2, L), np.uint8)
+    het[:, 1, :] = 1
+    het = pack(het)  # z = 0: survives surely
+    gpu = spegg.Population([d])
+    gpu.set_trace(True)
+    orc = oracle_pop(d)
+    for k in range(P):
+        w = ones if k in (0, 3) else het
+        gpu.write_genomes(0, w, 2, patch=k)
+        orc.set_genomes(w, 2, patch=k)
+    for _ in range(3):
+        gpu.step(1)
+        orc.step(1)
+        assert_same_state(gpu, 0, orc, f"refill generation {orc.generation}", parents=True)
+    # every patch dead at once: the ring dies out and stays out
+    d3 = ring(seed=31, n_patches=3, n0=100, capacity=100, n_loci=32, omega=0.5)
+    ones3 = pack(np.ones((100, 2, 32), np.uint8))
+    gpu3 = spegg.Population([d3])
+    orc3 = oracle_pop(d3)
+    for k in range(3):
+        gpu3.write_genomes(0, ones3, 4, patch=k)
+        orc3.set_genomes(ones3, 4, patch=k)
+    gpu3.step(2)
+    orc3.step(2)
+    assert_same_state(gpu3, 0, orc3, "dead ring")
+    assert gpu3.stats()[0]["extinct"] == 1 and gpu3.stats()[0]["n"] == 0
+
+
+def test_rings_in_a_batch_equal_each_alone():
+    reps = [ring(replicate_id=10), dict(seed=9, replicate_id=11, n0=400, capacity=400, n_loci=1024, r=0.01,
+                                        mu=1e-4, omega=20.0),
+            ring(replicate_id=12, n_patches=6, n0=90, capacity=90, n_loci=256, r=0.4, migration=0.05),
+            ring(replicate_id=13, n_patches=2, n_loci=33, r=0.0, migration=0.5)]
+    batch = spegg.Population(reps)
+    batch.set_trace(True)
+    batch.step(5)
+    for i, d in enumerate(reps):
+        orc = oracle_pop(d)
+        orc.step(5)
+        assert_same_state(batch, i, orc, f"batch replicate {i}", parents=True)
+        orc.close()
+
+
+def test_patches_must_share_a_generation():
+    d = ring(n_patches=2)
+    pop = spegg.Population([d])
+    w = workloads.random_genomes(200, 64, seed=4)
+    pop.write_genomes(0, w, 7, patch=1)
+    with pytest.raises(spegg.SpeggError) as ei:
+        pop.step(1)
+    assert ei.value.status == spegg.E_STATE
+    pop.write_genomes(0, w, 7, patch=0)
+    pop.step(1)
+    assert [s["generation"] for s in pop.patch_stats(0)] == [8, 8]
+    with pytest.raises(spegg.SpeggError) as ei:
+        pop.genomes(0, patch=2)
+    assert ei.value.status == spegg.E_INVALID
+
+
+def test_ring_at_serving_shape_two_generations():
+    # one replicate of the serving workload's shape: 100 patches on a ring,
+    # L = 256, m = 0.01
+    d = ring(seed=7, replicate_id=1, n_patches=100, n0=1500, capacity=1500, n_loci=256, r=0.25, mu=1e-4,
+             omega=8.0, migration=0.01)
+    say("ring of 100 patches x 1500, L = 256")
+    gpu = spegg.Population([d])
+    gpu.set_trace(True)
+    orc = oracle_pop(d)
+    for _ in range(2):
+        gpu.step(1)
+        orc.step(1)
+        assert_same_state(gpu, 0, orc, f"serving shape generation {orc.generation}", parents=True)
