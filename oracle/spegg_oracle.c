@@ -227,7 +227,7 @@ typedef struct {
     double conversion;  /* consumer offspring mean per credited capture */
     double resource_q0; /* per-trial success of a resource at low density */
     double resource_K;  /* resource density scale of the logistic factor */
-    double surv_resource[4], surv_consumer[4]; /* survival by age 0..3 */
+    double surv_resource[4], surv_consumer[4]; /* survival by age class 0, 1, 2, 3 and older */
 } oracle_ecology;
 
 typedef struct {
@@ -875,7 +875,7 @@ static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int
         uint32_t i = D->survivors[j];
         memcpy(allele_row(P, *next, j, 0), allele_row(P, D->genome, i, 0), 2u * L);
         (*znext)[j] = D->z[i];
-        (*anext)[j] = (uint8_t)(D->age[i] + 1u);
+        (*anext)[j] = (uint8_t)(D->age[i] < 3u ? D->age[i] + 1u : 3u); /* class 3: three and older */
     }
     for (j = 0; j < nn; ++j) {
         uint32_t w0 = seq_word(&D->rng, j, ST_PARENT, t, 0);
@@ -892,7 +892,7 @@ static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int
         dad = S->survivors[uniform_index(w2, w3, S->n_survivors)];
         D->mom[j] = mom;
         D->dad[j] = dad;
-        D->src[j] = sp;
+        D->src[j] = P->prm.regime == REGIME_CONSUMER_RESOURCE ? 0u : sp; /* the source's patch */
         make_gamete(P, &D->rng, allele_row(P, S->genome, mom, 0), allele_row(P, S->genome, mom, 1), j, t, 0,
                     allele_row(P, *next, pos, 0), scratch);
         make_gamete(P, &D->rng, allele_row(P, S->genome, dad, 0), allele_row(P, S->genome, dad, 1), j, t, 1,

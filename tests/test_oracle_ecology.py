@@ -101,6 +101,15 @@ def test_age_classes_survive_by_their_rates_and_age():
         assert np.all(after[ns:] == 0) and after.max() <= 3
 
 
+def test_oldest_class_holds_three_and_older():
+    e = eco(n0_consumer=0, capacity_consumer=1, attack=0.0, resource_q0=0.0, surv_resource=(1, 1, 1, 1))
+    pop = oracle.OraclePop(seed=3, regime=CR, n0=500, capacity=500, n_loci=32, ecology=e)
+    for gen in range(1, 7):
+        pop.step(1)
+        assert np.all(pop.ages(species=0) == min(gen, 3))
+        assert pop.n_of(species=0) == 500
+
+
 def test_carried_survivors_keep_their_genomes():
     L = 96
     e = eco(n0_consumer=50, capacity_consumer=500, encounters=5.0)
