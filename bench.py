@@ -87,9 +87,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20, help="untimed generations first")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["scale", "batched", "serve"], default="scale",
+    ap.add_argument("--workload", choices=["scale", "batched", "serve", "ecology"], default="scale",
                     help="scale: one replicate at scale (default); batched: the 4096-replicate batch; "
-                         "serve: sweep jobs arriving at random, served with continuous batching")
+                         "serve: sweep jobs arriving at random, served with continuous batching; "
+                         "ecology: 64 replicates of the two-species consumer-resource form")
     ap.add_argument("--reps", type=int, default=4096, help="replicates of the batched workload")
     ap.add_argument("--plain-sample", type=int, default=64,
                     help="batched: replicates timed one at a time for the plain per-replicate loop")
@@ -118,6 +119,8 @@ def main():
         return bench_batched(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "ecology":
+        return bench_ecology(args)
 
     desc, _ = workloads.plain_scale(seed=1)
     L = desc["n_loci"]
@@ -277,6 +280,61 @@ def bench_batched(args):
         "roofline": {"bound": "hbm", "kernel": "offspring", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_update": bpu, "launches": off_n, "generations": gens_b},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_ecology(args):
+    """64 replicates of the consumer-resource form (resource 1e5, consumer
+    1e4, L = 256, ages 0-3), all advanced together; updates count carried
+    survivors and newborns of both species."""
+    import torch
+
+    from paper_1603_09255_amd import spegg, workloads
+
+    reps, _ = workloads.consumer_resource(n_reps=64)
+    torch.cuda.set_device(0)
+    log(f"bench: creating {len(reps)} consumer-resource replicates")
+    pop = spegg.Population(reps)
+    pop.step(args.warmup)
+    torch.cuda.synchronize()
+    s0 = sum(r["updates"] for r in pop.stats())
+    t0 = time.perf_counter()
+    pop.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = pop.stats()
+    updates = sum(r["updates"] for r in st) - s0
+    value = updates / elapsed
+    log(f"bench: {updates} updates in {elapsed:.3f} s ({value:.4g}/s)")
+    # roofline pass: offspring launches bracketed by events
+    pop.set_timing(["offspring"])
+    pop.kernel_times()
+    sb0 = sum(r["updates"] for r in pop.stats())
+    gens_b = min(args.steps, 50)
+    pop.step(gens_b)
+    kt = pop.kernel_times()
+    sb1 = sum(r["updates"] for r in pop.stats())
+    pop.set_timing([])
+    per = pop.deme_stats(0)
+    pop.close()
+    off_ms, off_n = kt["offspring"]
+    bpu = bytes_per_update(256)
+    achieved = (sb1 - sb0) * bpu / (off_ms / 1e3) / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "two-species consumer-resource form: 64 replicates, resource N0=1e5 (capacity 2.5e5), "
+                               "consumer N0=1e4 (capacity 5e4), L=256 each, capture by Gaussian phenotype matching "
+                               "(width 4), ages 0-3, resource logistic binomial fecundity, consumer fecundity "
+                               "Poisson in intake",
+                   "replicates": len(reps), "generations_timed": args.steps,
+                   "replicate0_resource_n": per[0]["n"], "replicate0_consumer_n": per[1]["n"],
+                   "replicate0_captures": per[1]["captures"]},
+        "roofline": {"bound": "hbm", "kernel": "offspring", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_update": bpu,
+                     "launches": off_n, "generations": gens_b},
     }
     print(json.dumps(out), flush=True)
 

@@ -79,9 +79,45 @@ typedef enum {
 } spegg_status;
 
 typedef enum {
-    SPEGG_WF = 0,         /* Wright-Fisher: N constant, viability selection, parents uniform over survivors */
-    SPEGG_POISSON_BH = 1  /* Poisson(fecundity) offspring per surviving mother, survival x Beverton-Holt s(N) */
+    SPEGG_WF = 0,                /* Wright-Fisher: N constant, viability selection, parents uniform over survivors */
+    SPEGG_POISSON_BH = 1,        /* Poisson(fecundity) offspring per surviving mother, survival x Beverton-Holt s(N) */
+    SPEGG_CONSUMER_RESOURCE = 2  /* two coevolving species with age classes (spegg_ecology) */
 } spegg_regime;
+
+/* The consumer-resource regime (Supplementary Information S3: a consumer
+ * exploits a resource by phenotype matching), as an individual-based model
+ * with overlapping generations and age classes 0..3.  Species 0 is the
+ * resource (census n0, capacity of the descriptor), species 1 the consumer.
+ * One generation:
+ *   1. every consumer draws Poisson(encounters) encounters; each lands on a
+ *      uniform slot of the habitat (at least the resource census) and meets
+ *      the resource of that index if there is one (mass action); it
+ *      captures it when a CAPTURE word falls below
+ *      floor(attack exp(-(z_c - z_r)^2 / (2 match_width^2)) 2^32);
+ *   2. a resource captured more than once is credited to the capture with
+ *      the lowest (consumer index, encounter ordinal); captured resources
+ *      die; a consumer's intake is its number of credited captures;
+ *   3. the others survive with v(z) times the survival of their age class;
+ *   4. surviving resources have Binomial(resource_trials, resource_q0 max(0,
+ *      1 - N_R / resource_K)) offspring as mothers, surviving consumers
+ *      Poisson(conversion x intake); fathers are uniform survivors of the
+ *      same species;
+ *   5. the next census is the survivors (one age class older, genomes
+ *      carried; class 3 holds three and older) followed by the newborns
+ *      (age 0), up to the capacity.
+ * Philox counters carry the species in c3 (bits 10..11). */
+typedef struct spegg_ecology {
+    uint32_t n0_consumer, capacity_consumer;
+    uint32_t resource_trials; /* 1..64 */
+    uint32_t habitat;         /* encounter slots; 0: the resource census (every encounter meets a resource) */
+    double attack;            /* capture probability at a perfect match, 0..1 */
+    double match_width;       /* > 0 */
+    double encounters;        /* mean encounters per consumer and generation, >= 0 */
+    double conversion;        /* consumer offspring mean per credited capture, >= 0 */
+    double resource_q0;       /* per-trial offspring probability of a resource at low density, 0..1 */
+    double resource_K;        /* > 0 */
+    double surv_resource[4], surv_consumer[4]; /* survival by age class 0, 1, 2, 3 and older; each 0..1 */
+} spegg_ecology;
 
 typedef struct spegg_pop spegg_pop; /* opaque; owns no device memory */
 
@@ -103,10 +139,12 @@ typedef struct spegg_rep_desc {
     double fecundity;      /* Poisson mean lambda (POISSON_BH) */
     double migration;      /* backward migration rate to the ring neighbours, 0..1; unused with one patch */
     const int8_t *effects; /* n_loci allelic effects in [-4, 4], copied at create; NULL: all +1 */
+    const spegg_ecology *ecology; /* SPEGG_CONSUMER_RESOURCE only (copied at create); else NULL */
 } spegg_rep_desc;
 
-/* Census of one patch, or of a replicate summed over its patches, after
- * the latest generation. */
+/* Census of one deme (a patch, or a species of the consumer-resource
+ * regime), or of a replicate summed over its demes, after the latest
+ * generation. */
 typedef struct spegg_rep_stats {
     uint32_t generation;    /* t: generations completed since creation (or since the last write) */
     uint32_t n;             /* N_t */
@@ -150,52 +188,65 @@ spegg_status spegg_step_generations(spegg_pop *pop, uint32_t n_generations);
  * n_reps), each summed over its patches, into host_out. */
 spegg_status spegg_stats(spegg_pop *pop, spegg_rep_stats *host_out, uint32_t n);
 
-/* Wait, then copy the census of each of replicate rep's patches (n must
- * equal its n_patches) into host_out. */
-spegg_status spegg_patch_stats(spegg_pop *pop, uint32_t rep, spegg_rep_stats *host_out, uint32_t n);
+/* Wait, then copy the census of each of replicate rep's demes into
+ * host_out: its patches in order, or for the consumer-resource regime its
+ * two species (0 resource, 1 consumer).  n must equal the number of demes. */
+spegg_status spegg_deme_stats(spegg_pop *pop, uint32_t rep, spegg_rep_stats *host_out, uint32_t n);
 
-/* Wait, then copy the current genomes of patch `patch` of replicate rep
- * (N x 2W words, layout above) into host_words (room for n_words words);
- * *n_out = N.  SPEGG_E_INVALID if the room is short; species must be 0. */
+/* Wait, then copy the current genomes of one deme of replicate rep (patch
+ * `patch` of a ring, or species `species` of the consumer-resource regime;
+ * the other index is 0) as N x 2W words (layout above) into host_words
+ * (room for n_words words); *n_out = N.  SPEGG_E_INVALID if the room is
+ * short or the deme does not exist. */
 spegg_status spegg_read_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *host_words,
                                 size_t n_words, uint32_t *n_out);
 
-/* Replace the population of patch `patch` of replicate rep by n
- * individuals given as n x 2W words (tail bits must be zero, n <= capacity)
- * at generation `generation`; phenotypes are recomputed and the patch's
- * census and cumulative counters reset.  Patches of one replicate must all
- * be at one generation when it next steps (SPEGG_E_STATE otherwise).
- * Waits for the stream before returning (host_words may be reused). */
+/* Replace the population of one deme by n individuals (all of age 0)
+ * given as n x 2W words (tail bits must be zero, n <= capacity) at
+ * generation `generation`; phenotypes are recomputed and the deme's census
+ * and cumulative counters reset.  The demes of one replicate must all be at
+ * one generation when it next steps (SPEGG_E_STATE otherwise).  Waits for
+ * the stream before returning (host_words may be reused). */
 spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species,
                                  const uint32_t *host_words, uint32_t n, uint32_t generation);
 
-/* Wait, then copy the phenotypes z (N int32) of a patch into host_z. */
-spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, uint32_t patch, int32_t *host_z, size_t n,
-                                   uint32_t *n_out);
+/* Wait, then copy the phenotypes z (N int32) of a deme into host_z. */
+spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, int32_t *host_z,
+                                   size_t n, uint32_t *n_out);
 
-/* Wait, then copy the ascending survivor list of a patch's last
- * generation (indices into its previous adults) into host_idx. */
-spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *host_idx, size_t n,
-                                  uint32_t *n_out);
+/* Wait, then copy the age classes (N uint8, 0..3) of a deme of the
+ * consumer-resource regime into host_age. */
+spegg_status spegg_read_ages(spegg_pop *pop, uint32_t rep, uint32_t species, uint8_t *host_age, size_t n,
+                             uint32_t *n_out);
 
-/* Per-locus copies of allele 1 over a patch's current census (2N genes
- * per locus): the genetic distribution behind the phenotypes (Fig. 1F;
+/* Wait, then copy each consumer's credited captures in the last
+ * generation, by its index among that generation's adults. */
+spegg_status spegg_read_intake(spegg_pop *pop, uint32_t rep, uint32_t *host_intake, size_t n, uint32_t *n_out);
+
+/* Wait, then copy the ascending survivor list of a deme's last generation
+ * (indices into its previous adults) into host_idx. */
+spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *host_idx,
+                                  size_t n, uint32_t *n_out);
+
+/* Per-locus copies of allele 1 over a deme's current census (2N genes per
+ * locus): the genetic distribution behind the phenotypes (Fig. 1F;
  * Supplementary S2, "Genetics").  counts_dev is caller-owned device scratch
  * of n_loci uint32 (n_loci must equal the replicate's L); host_counts gets
  * the result; *n_out = N.  Reads every genome once; waits for the stream. */
-spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *counts_dev,
+spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *counts_dev,
                                  uint32_t *host_counts, uint32_t n_loci, uint32_t *n_out);
 
 /* Record each newborn's mother and father (indices into the previous
  * adults) from the next generation on.  Off by default. */
 spegg_status spegg_set_trace(spegg_pop *pop, int enable);
 
-/* Wait, then copy the parents recorded for a patch's current newborns:
- * mother and father as indices into the adults of the patch they came
- * from, and that patch (host_src may be NULL).  SPEGG_E_STATE if tracing
- * was off for the last generation. */
-spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *host_mom, uint32_t *host_dad,
-                                uint32_t *host_src, size_t n, uint32_t *n_out);
+/* Wait, then copy the parents recorded for a deme's newborns of the last
+ * generation (the census minus carried survivors): mother and father as
+ * indices into the adults of the patch they came from, and that patch
+ * (host_src may be NULL).  SPEGG_E_STATE if tracing was off for the last
+ * generation. */
+spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *host_mom,
+                                uint32_t *host_dad, uint32_t *host_src, size_t n, uint32_t *n_out);
 
 /* Replay generations as captured HIP graphs (enable = 1, the default) or
  * launch every kernel (0).  Graphs are used only on a non-null stream and
@@ -207,10 +258,12 @@ enum {
     SPEGG_KERNEL_SURVIVE = 0,   /* step D and the offspring count of A */
     SPEGG_KERNEL_COMPACT = 1,   /* step E: survivor list, offspring slots, census advance */
     SPEGG_KERNEL_OFFSPRING = 2, /* steps A (parents), B and C, census partials */
-    SPEGG_KERNEL_KINDS = 3
+    SPEGG_KERNEL_ENCOUNTER = 3, /* consumer-resource: encounters and captures */
+    SPEGG_KERNEL_CARRY = 4,     /* consumer-resource: survivors carried into the next census */
+    SPEGG_KERNEL_KINDS = 5
 };
 
-#define SPEGG_TIME_ALL 0x7u
+#define SPEGG_TIME_ALL 0x1Fu
 
 /* Bracket the kernels of the kinds in kinds_mask (bit k: kind k; 0 stops)
  * launched by later spegg_step_generations calls with HIP events on the
@@ -221,6 +274,18 @@ spegg_status spegg_set_timing(spegg_pop *pop, uint32_t kinds_mask);
  * and the number of launches timed since the last call, and reset them.
  * Arrays hold n_kinds (<= SPEGG_KERNEL_KINDS) entries. */
 spegg_status spegg_kernel_times(spegg_pop *pop, double *ms, uint64_t *launches, uint32_t n_kinds);
+
+/* Pick the offspring kernel's shape (lanes per gamete, words per lane,
+ * chunks held in registers) for each genome length W in the population by
+ * timing: for each W in turn, every distinct shape runs
+ * generations_per_trial real generations with its offspring launches timed
+ * by HIP events, and the one with the least time per genotype-locus update
+ * stays.  Shapes change no result, so the trial generations are ordinary
+ * generations of the simulation (the population advances by their total).
+ * Reports the distinct W (ascending) and each one's chosen cap on lanes per
+ * gamete (arrays of cap entries; *n_out = number of W).  Waits. */
+spegg_status spegg_autotune(spegg_pop *pop, uint32_t generations_per_trial, uint32_t *w_out, uint32_t *gcap_out,
+                            uint32_t cap, uint32_t *n_out);
 
 /* Release the handle (not the caller's memory or stream).  NULL is a no-op. */
 void spegg_pop_destroy(spegg_pop *pop);

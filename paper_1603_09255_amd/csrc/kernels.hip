@@ -11,6 +11,11 @@
 //              + C (additive phenotype by popcounts) + census partials; one
 //              team of 2G lanes per newborn, V consecutive words per lane
 //   census     (on demand) folds the partials into the census sums
+//   encounter  (consumer-resource regime, before survive) consumers meet
+//              and capture resources; each captured resource keeps the
+//              lowest (consumer, encounter) key by a 64-bit atomic minimum
+//   carry      (consumer-resource regime, after compact) survivors move to
+//              the front of the next census, one age class older
 //
 // All of it is integer work except p = v s (IEEE double, no contraction),
 // so every result is reproducible bit for bit.  No kernel waits on another
@@ -183,6 +188,73 @@ __device__ __forceinline__ uint32_t current_pair(const RepState &st) {
     return (int32_t)(st.t[1] - st.t[0]) > 0 ? 1u : 0u;
 }
 
+// Words of one stream of one individual read in order, one Philox block
+// per four words.
+struct SeqWords {
+    Rng rng;
+    uint32_t index, stream, gen;
+    uint32_t blk;
+    Words4 w;
+    __device__ __forceinline__ SeqWords(const Rng &r, uint32_t i, uint32_t st, uint32_t g)
+        : rng(r), index(i), stream(st), gen(g), blk(~0u) {}
+    __device__ __forceinline__ uint32_t operator()(uint32_t q) {
+        if ((q >> 2) != blk) {
+            blk = q >> 2;
+            w = rng.block(index, stream, blk, gen);
+        }
+        const uint32_t c = q & 3u;
+        return c == 0 ? w.v[0] : c == 1 ? w.v[1] : c == 2 ? w.v[2] : w.v[3];
+    }
+};
+
+// Consumer-resource regime: the encounters of consumer i.  Each lands on a
+// uniform slot of the habitat (at least the resource census NR) and meets
+// the resource of that index if there is one; it captures it when its
+// CAPTURE word is below the matching threshold.  f(e, target) is called
+// for every capture.
+template <typename F>
+__device__ __forceinline__ void consumer_captures(const RepDesc &c, uint32_t i, uint32_t t, int32_t zc,
+                                                  const int32_t *__restrict__ zr, uint32_t NR, F &&f) {
+    if (NR == 0) return;
+    const Rng rng{c.key0, c.key1, c.c3};
+    SeqWords enc(rng, i, kStEncounter, t), cap(rng, i, kStCapture, t);
+    const uint32_t ne = table_draw(c.enc, c.enc_len, enc(0));
+    const uint32_t span = c.habitat > NR ? c.habitat : NR;
+    for (uint32_t e = 0; e < ne; ++e) {
+        const uint32_t lo = enc(1u + 2u * e), hi = enc(2u + 2u * e);
+        const uint32_t tgt = uniform_index(lo, hi, span);
+        if (tgt >= NR) continue;
+        const int32_t dz = zc - zr[tgt];
+        const uint32_t d = (uint32_t)(dz < 0 ? -dz : dz);
+        if ((uint64_t)cap(e) < c.capT[d]) f(e, tgt);
+    }
+}
+
+__device__ __forceinline__ uint64_t capture_key(uint32_t i, uint32_t e) { return ((uint64_t)i << 32) | e; }
+
+// Binomial(n, q) thresholds from IEEE double basic operations: P(k) =
+// C(n, k) q^k (1-q)^(n-k), the coefficient by C(n, k) = C(n, k-1)(n-k+1)/k,
+// the powers by repeated multiplication, F accumulated in order; the table
+// closes at the first threshold reaching 2^32 - 1, or at k = n.
+__device__ uint32_t small_binomial_table(uint32_t n, double q, uint64_t *T) {
+    const double u = 1.0 - q;
+    double c = 1.0, F = 0.0;
+    for (uint32_t k = 0; k <= n; ++k) {
+        if (k > 0) c = c * (double)(n - k + 1u) / (double)k;
+        double pk = c;
+        for (uint32_t m = 0; m < k; ++m) pk = pk * q;
+        for (uint32_t m = 0; m < n - k; ++m) pk = pk * u;
+        F = F + pk;
+        const uint64_t thr = F >= 1.0 ? kAlways : (F > 0.0 ? (uint64_t)floor(F * 4294967296.0) : 0ull);
+        if (thr >= 4294967295ull || k == n) {
+            T[k] = kAlways;
+            return k + 1;
+        }
+        T[k] = thr;
+    }
+    return n + 1;
+}
+
 // ---------------------------------------------------------------- init
 
 __global__ void __launch_bounds__(kBlock) init_kernel(const RepDesc *__restrict__ desc, uint32_t n0) {
@@ -231,7 +303,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
                                                          const SurvTile *__restrict__ tiles,
                                                          SurvCount *__restrict__ counts) {
     constexpr uint32_t IT = kSurvItems;
-    __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_n[kBlock / 64];
+    __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_n[kBlock / 64], sh_i[kBlock / 64];
     __shared__ uint64_t sh_t[kBlock / 64];
     __shared__ uint64_t sh_pois[kPoissonTableCap];
     const SurvTile tile = tiles[blockIdx.x];
@@ -242,9 +314,20 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     // beyond the census: uniform over the block; tile 0 always records the census
     if (tile.start >= n && tile.start != 0) return;
     const bool poisson = d.regime == SPEGG_POISSON_BH;
+    const bool cr = d.regime == SPEGG_CONSUMER_RESOURCE;
+    __shared__ uint32_t sh_tlen;
+    uint32_t tlen = d.pois_len;  // length of the table in sh_pois
     if (poisson) {
         for (uint32_t q = threadIdx.x; q < d.pois_len; q += kBlock) sh_pois[q] = d.pois[q];
         __syncthreads();
+    } else if (cr && d.species == 0) {
+        // the resource's offspring table of this generation's density
+        if (threadIdx.x == 0) {
+            const double x = 1.0 - (double)n / d.KR;
+            sh_tlen = small_binomial_table(d.trials, d.q0 * (x > 0.0 ? x : 0.0), sh_pois);
+        }
+        __syncthreads();
+        tlen = sh_tlen;
     }
     const uint32_t i0 = tile.start + threadIdx.x * IT;
     const double s = density_factor(d, n);
@@ -253,24 +336,51 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     double v[IT];
 #pragma unroll
     for (uint32_t q = 0; q < IT; ++q) v[q] = (d.vtab && i0 + q < n) ? d.vtab[(int32_t)zw.v[q] - d.zmin] : 1.0;
-    uint32_t fate[IT], a_loc = 0, k_loc = 0, near = 0;
+    uint32_t age4 = 0;
+    if (cr) age4 = *reinterpret_cast<const uint32_t *>(d.age[t & 1u] + i0);
+    uint32_t fate[IT], a_loc = 0, k_loc = 0, near = 0, in_loc = 0;
     uint64_t thr_sum = 0;
 #pragma unroll
     for (uint32_t q = 0; q < IT; ++q) {
         const uint32_t i = i0 + q;
         fate[q] = 0;
         if (i < n) {
-            const double p = v[q] * s;
-            const uint64_t thr = p >= 1.0 ? kAlways : (p > 0.0 ? (uint64_t)floor(p * 4294967296.0) : 0ull);
-            const uint32_t x = rng.block(i, kStSurvive, 0, t).v[0];
-            thr_sum += thr;
-            near += (p > 0.0 && p < 1.0 && fabs((double)x * (1.0 / 4294967296.0) - p) < 1e-6) ? 1u : 0u;
-            if ((uint64_t)x < thr) {
-                uint32_t kids = 0;
-                if (poisson) kids = table_draw(sh_pois, d.pois_len, rng.block(i, kStFecund, 0, t).v[0]);
-                fate[q] = 0x8000u | kids;
-                ++a_loc;
-                k_loc += kids;
+            uint32_t intake = 0;
+            bool captured = false;
+            double p = v[q] * s;
+            if (cr) {
+                p = v[q] * d.surv_age[(age4 >> (8u * q)) & 3u];
+                if (d.species == 0) {
+                    captured = d.won[i] != ~0ull;
+                } else {
+                    // credited captures: those whose resource kept this key
+                    const RepDesc &r = descs[d.partner];
+                    const RepState &rs = states[d.partner];
+                    const uint32_t NR = rs.n[current_pair(rs)];
+                    consumer_captures(d, i, t, (int32_t)zw.v[q], r.z[t & 1u], NR, [&](uint32_t e, uint32_t tgt) {
+                        if (r.won[tgt] == capture_key(i, e)) ++intake;
+                    });
+                    d.intake[i] = intake;
+                    in_loc += intake;
+                }
+            }
+            if (!captured) {
+                const uint64_t thr = p >= 1.0 ? kAlways : (p > 0.0 ? (uint64_t)floor(p * 4294967296.0) : 0ull);
+                const uint32_t x = rng.block(i, kStSurvive, 0, t).v[0];
+                thr_sum += thr;
+                near += (p > 0.0 && p < 1.0 && fabs((double)x * (1.0 / 4294967296.0) - p) < 1e-6) ? 1u : 0u;
+                if ((uint64_t)x < thr) {
+                    uint32_t kids = 0;
+                    if (poisson || (cr && d.species == 0)) {
+                        kids = table_draw(sh_pois, tlen, rng.block(i, kStFecund, 0, t).v[0]);
+                    } else if (cr) {
+                        const uint32_t off = d.cpois_off[2u * intake], len = d.cpois_off[2u * intake + 1u];
+                        kids = table_draw(d.cpois + off, len, rng.block(i, kStFecund, 0, t).v[0]);
+                    }
+                    fate[q] = 0x8000u | kids;
+                    ++a_loc;
+                    k_loc += kids;
+                }
             }
         }
     }
@@ -279,11 +389,13 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     *reinterpret_cast<uint2 *>(fp) = make_uint2(fate[0] | (fate[1] << 16), fate[2] | (fate[3] << 16));
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t wa = wave_sum<uint32_t>(a_loc), wk = wave_sum<uint32_t>(k_loc), wn = wave_sum<uint32_t>(near);
+    const uint32_t wi = wave_sum<uint32_t>(in_loc);
     const uint64_t wt = wave_sum<uint64_t>(thr_sum);
     if (lane_id() == 0) {
         sh_a[wave] = wa;
         sh_k[wave] = wk;
         sh_n[wave] = wn;
+        sh_i[wave] = wi;
         sh_t[wave] = wt;
     }
     __syncthreads();
@@ -293,6 +405,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
             c.alive += sh_a[w];
             c.kids += sh_k[w];
             c.near += sh_n[w];
+            c.intake += sh_i[w];
             c.sum_t += sh_t[w];
         }
         c.par = par;
@@ -313,7 +426,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
                                                          const SurvTile *__restrict__ tiles,
                                                          const SurvCount *__restrict__ counts, int trace) {
     constexpr uint32_t IT = kSurvItems;
-    __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64];
+    __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_in[kBlock / 64];
     __shared__ uint64_t sh_kk[kBlock / 64], sh_n[kBlock / 64], sh_t[kBlock / 64];
     const SurvTile tile = tiles[blockIdx.x];
     const RepDesc &d = descs[tile.rep];
@@ -330,7 +443,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
 
     // exclusive prefix of this tile (tile 0: the totals as well)
     const uint32_t span = k == 0 ? active : k;
-    uint32_t pa = 0;
+    uint32_t pa = 0, pi = 0;
     uint64_t pk = 0, pn = 0, pt = 0;
     for (uint32_t q = threadIdx.x; q < span; q += kBlock) {
         const SurvCount c = C[q];
@@ -338,23 +451,27 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
         pk += c.kids;
         pn += c.near;
         pt += c.sum_t;
+        pi += c.intake;
     }
     pa = wave_sum<uint32_t>(pa);
+    pi = wave_sum<uint32_t>(pi);
     pk = wave_sum<uint64_t>(pk);
     pn = wave_sum<uint64_t>(pn);
     pt = wave_sum<uint64_t>(pt);
     if (lane_id() == 0) {
         sh_a[wave] = pa;
+        sh_in[wave] = pi;
         sh_kk[wave] = pk;
         sh_n[wave] = pn;
         sh_t[wave] = pt;
     }
     __syncthreads();
-    uint32_t sum_a = 0;
+    uint32_t sum_a = 0, sum_i = 0;
     uint64_t sum_k = 0, sum_n = 0, sum_t = 0;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) {
         sum_a += sh_a[w];
+        sum_i += sh_in[w];
         sum_k += sh_kk[w];
         sum_n += sh_n[w];
         sum_t += sh_t[w];
@@ -383,15 +500,21 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     if (k == 0 && threadIdx.x == 0) {
         // census of the newborns, into the pair the other blocks do not read
         const uint32_t ns = sum_a;
+        const bool cr = d.regime == SPEGG_CONSUMER_RESOURCE;
         uint32_t nn;
         if (ns + nb_alive == 0) {
             nn = 0;
         } else if (d.regime == SPEGG_WF) {
             nn = n;
         } else {
-            nn = sum_k > d.cap ? d.cap : (uint32_t)sum_k;
-            st.truncated += sum_k - nn;
+            // newborns fill the room the carried survivors leave
+            const uint32_t room = cr ? d.cap - ns : d.cap;
+            const uint32_t nb = sum_k > room ? room : (uint32_t)sum_k;
+            st.truncated += sum_k - nb;
+            nn = (cr ? ns : 0u) + nb;
         }
+        st.n_carry = cr ? ns : 0u;
+        st.captures = sum_i;
         st.n_prev = n;
         st.n_surv = ns;
         st.t[par ^ 1u] = t + 1;
@@ -427,7 +550,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
             if (spos < d.cap) d.S[spos] = i0 + q;
             ++spos;
         }
-        if (d.regime == SPEGG_POISSON_BH) {
+        if (d.regime != SPEGG_WF) {  // mothers with offspring counts own their slots
             const uint32_t kids = fate[q] & 0x7FFFu;
             for (uint32_t m = 0; m < kids; ++m, ++slot)
                 if (slot < d.cap) d.owner[slot] = i0 + q;
@@ -476,8 +599,8 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
     uint32_t limit = ntiles;
     if (single_deme >= 0) {
         const RepState &s1 = states[single_deme];
-        const uint32_t nn = s1.n[current_pair(s1)];
-        const uint32_t active = (nn + OPT - 1) / OPT;
+        const uint32_t nb1 = s1.n[current_pair(s1)] - s1.n_carry;
+        const uint32_t active = (nb1 + OPT - 1) / OPT;
         limit = active < ntiles ? active : ntiles;
     }
     for (uint32_t ti = blockIdx.x; ti < limit; ti += gridDim.x) {
@@ -493,7 +616,8 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
         const RepDesc &d = descs[rep];
         const RepState &st = states[rep];
         const uint32_t newest = current_pair(st);  // the newborns' census, written by this generation's select
-        const uint32_t nn = st.n[newest];
+        const uint32_t base = st.n_carry;          // carried survivors come first in the census
+        const uint32_t nn = st.n[newest] - base;   // newborns
         if (start >= nn || st.error) continue;  // uniform over the block
         const uint32_t tp = st.t[newest] - 1u, cur = tp & 1u;
         const uint32_t W = d.W, L = d.L, mode = d.mode;
@@ -554,7 +678,7 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             mom = mom < nprev ? mom : nprev - 1u;
             dad = dad < nprev ? dad : nprev - 1u;
             const uint32_t *__restrict__ src = sd_src.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
-            uint32_t *__restrict__ dst = d.genome[cur ^ 1u] + (size_t)j * 2u * W + (size_t)half * W;
+            uint32_t *__restrict__ dst = d.genome[cur ^ 1u] + (size_t)(base + j) * 2u * W + (size_t)half * W;
             const uint32_t rs = kStRecomb + half, ms = kStMutate + half;
             const uint32_t phase_m = draw(1, 0), phase_p = draw(2, 0);
             const uint32_t xk_m = draw(3, 0), xk_p = draw(4, 0);
@@ -708,7 +832,11 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             for (int o = 1; o < (int)TPO; o <<= 1) zc += __shfl_xor(zc, o, TPO);
             if (lane == 0) {
                 const int32_t z = zc - d.sum_e;
-                d.z[cur ^ 1u][j] = z;
+                d.z[cur ^ 1u][base + j] = z;
+                if (d.regime == SPEGG_CONSUMER_RESOURCE) {
+                    d.age[cur ^ 1u][base + j] = 0;
+                    if (d.species == 0) d.won[base + j] = ~0ull;  // not captured in the next generation yet
+                }
                 my_z += z;
                 my_z2 += (uint64_t)((int64_t)z * (int64_t)z);
                 if (trace) {
@@ -751,13 +879,23 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
     RepState &st = states[rep];
     if (!st.census_pending) return;  // uniform over the block
     const RepDesc &d = descs[rep];
-    const uint32_t used = (st.n[current_pair(st)] + d.off_per_tile - 1u) / d.off_per_tile;
     int64_t a = 0;
     uint64_t b = 0;
-    for (uint32_t k = threadIdx.x; k < used; k += kBlock) {
-        const Partial p = partials[d.off_tile0 + k];
-        a += p.sum_z;
-        b += p.sum_z2;
+    if (d.regime == SPEGG_CONSUMER_RESOURCE) {
+        // carried survivors are not in the offspring partials: sum the census
+        const uint32_t par = current_pair(st), n = st.n[par];
+        const int32_t *z = d.z[st.t[par] & 1u];
+        for (uint32_t k = threadIdx.x; k < n; k += kBlock) {
+            a += z[k];
+            b += (uint64_t)((int64_t)z[k] * (int64_t)z[k]);
+        }
+    } else {
+        const uint32_t used = (st.n[current_pair(st)] + d.off_per_tile - 1u) / d.off_per_tile;
+        for (uint32_t k = threadIdx.x; k < used; k += kBlock) {
+            const Partial p = partials[d.off_tile0 + k];
+            a += p.sum_z;
+            b += p.sum_z2;
+        }
     }
     a = wave_sum<int64_t>(a);
     b = wave_sum<uint64_t>(b);
@@ -778,6 +916,76 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
         st.sum_z2[threadIdx.x] = sb;
     }
     if (threadIdx.x == 0) st.census_pending = 0;
+}
+
+// ---------------------------------------------------------------- consumer-resource
+
+// One block per tile of kSurvTile consumers, 4 per thread: every capture
+// offers its key (consumer, encounter) to the captured resource, which
+// keeps the lowest.  The keys were reset to ~0 when the resource census was
+// written.
+__global__ void __launch_bounds__(kBlock) encounter_kernel(const RepDesc *__restrict__ descs,
+                                                           const RepState *__restrict__ states,
+                                                           const SurvTile *__restrict__ tiles) {
+    const SurvTile tile = tiles[blockIdx.x];
+    const RepDesc &c = descs[tile.rep];
+    const RepState &cs = states[tile.rep];
+    const uint32_t par = current_pair(cs);
+    const uint32_t t = cs.t[par], n = cs.n[par];
+    if (tile.start >= n) return;
+    const RepDesc &r = descs[c.partner];
+    const RepState &rs = states[c.partner];
+    const uint32_t NR = rs.n[current_pair(rs)];
+    const int32_t *zr = r.z[t & 1u];
+    const int32_t *zc = c.z[t & 1u];
+    unsigned long long *won = reinterpret_cast<unsigned long long *>(r.won);
+    for (uint32_t q = 0; q < kSurvItems; ++q) {
+        const uint32_t i = tile.start + threadIdx.x * kSurvItems + q;
+        if (i >= n) break;
+        consumer_captures(c, i, t, zc[i], zr, NR,
+                          [&](uint32_t e, uint32_t tgt) { atomicMin(won + tgt, (unsigned long long)capture_key(i, e)); });
+    }
+}
+
+// One block per survival tile of a consumer-resource deme: survivors
+// S[k], k in the tile, move to position k of the next census with their
+// genome, phenotype and age class plus one (compact advanced the census and
+// recorded how many are carried).
+__global__ void __launch_bounds__(kBlock) carry_kernel(const RepDesc *__restrict__ descs,
+                                                       const RepState *__restrict__ states,
+                                                       const SurvTile *__restrict__ tiles) {
+    const SurvTile tile = tiles[blockIdx.x];
+    const RepDesc &d = descs[tile.rep];
+    const RepState &st = states[tile.rep];
+    const uint32_t newest = current_pair(st);
+    const uint32_t nc = st.n_carry;
+    if (tile.start >= nc) return;
+    const uint32_t cur = (st.t[newest] - 1u) & 1u;
+    const uint32_t cnt = nc - tile.start < (uint32_t)kSurvTile ? nc - tile.start : (uint32_t)kSurvTile;
+    const uint32_t per = 2u * d.W;
+    const uint32_t *__restrict__ src = d.genome[cur];
+    uint32_t *__restrict__ dst = d.genome[cur ^ 1u];
+    for (uint32_t idx = threadIdx.x; idx < cnt * per; idx += kBlock) {
+        const uint32_t k = tile.start + idx / per, w = idx % per;
+        dst[(size_t)k * per + w] = src[(size_t)d.S[k] * per + w];
+    }
+    for (uint32_t idx = threadIdx.x; idx < cnt; idx += kBlock) {
+        const uint32_t k = tile.start + idx, from = d.S[k];
+        d.z[cur ^ 1u][k] = d.z[cur][from];
+        const uint32_t a = d.age[cur][from];
+        d.age[cur ^ 1u][k] = (uint8_t)(a < 3u ? a + 1u : 3u);  // class 3 holds three and older
+        if (d.species == 0) d.won[k] = ~0ull;
+    }
+}
+
+__global__ void fill_u64_kernel(uint64_t *p, uint32_t n) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = ~0ull;
+}
+
+__global__ void fill_u8_kernel(uint8_t *p, uint32_t n) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // ---------------------------------------------------------------- allele counts
@@ -894,6 +1102,32 @@ hipError_t launch_offspring(OffShape shape, const OffArgs &a) {
 hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,
                          hipStream_t s) {
     hipLaunchKernelGGL(census_kernel, dim3(n_reps), dim3(kBlock), 0, s, descs, states, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
+                            hipStream_t s) {
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(encounter_kernel, dim3(ntiles), dim3(kBlock), 0, s, descs, states, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_carry(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
+                        hipStream_t s) {
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(carry_kernel, dim3(ntiles), dim3(kBlock), 0, s, descs, states, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, n);
     return hipGetLastError();
 }
 

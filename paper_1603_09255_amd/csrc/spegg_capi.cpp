@@ -2,11 +2,13 @@
 // table upload, and the per-generation launch sequence.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -37,7 +39,7 @@ spegg_status fail(spegg_status st, const char *fmt, ...) {
 }
 
 constexpr size_t kAlign = 256;
-constexpr uint32_t kMaxOffspringGrid = 4096;
+constexpr uint32_t kMaxOffspringGrid = 4096;  // blocks of one offspring launch (they loop over tiles)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -62,14 +64,21 @@ struct RepPlan {
     std::vector<double> vtab;
     std::vector<uint32_t> planes;
     size_t vtab_at = 0, pois_at = 0, binom_at = 0, geo_at = 0, planes_at = 0;
-    uint32_t deme0 = 0, n_demes = 0;  // the replicate's patches are demes deme0 .. deme0 + n_demes - 1
+    uint32_t deme0 = 0, n_demes = 0;  // the replicate's demes are deme0 .. deme0 + n_demes - 1
+    // consumer-resource regime
+    bool cr = false;
+    std::vector<uint64_t> enc, capT, cpois;
+    std::vector<uint32_t> cpois_off;  // (offset, length) per intake
+    size_t enc_at = 0, capT_at = 0, cpois_at = 0, cpois_off_at = 0;
 };
 
-// One patch of one replicate: its tiles and buffers.
+// One patch of one species of one replicate: its tiles and buffers.
 struct DemePlan {
-    uint32_t rep = 0, patch = 0;
+    uint32_t rep = 0, patch = 0, species = 0;
+    uint32_t n0 = 0, cap = 0;
     uint32_t surv_tile0 = 0, surv_ntiles = 0, off_tile0 = 0, off_ntiles = 0;
     size_t genome[2] = {0, 0}, z[2] = {0, 0}, fate = 0, S = 0, owner = 0, mom = 0, dad = 0, src = 0;
+    size_t age[2] = {0, 0}, won = 0, intake = 0;
 };
 
 // Demes sharing one offspring-kernel shape.
@@ -81,16 +90,32 @@ struct OffClass {
     size_t lds;
 };
 
+// Lanes-per-gamete cap by genome length W (the autotuner's choice); a W
+// missing from the map takes the default.
+using GcapMap = std::map<uint32_t, int>;
+
 struct Plan {
     std::vector<RepPlan> reps;
     std::vector<DemePlan> demes;
     std::vector<OffClass> classes;
     std::vector<SurvTile> surv_tiles;
+    std::vector<SurvTile> enc_tiles;    // survival tiles of consumer demes
+    std::vector<SurvTile> carry_tiles;  // survival tiles of consumer-resource demes
     std::vector<OffTile> off_tiles;
-    size_t descs = 0, states = 0, surv_tiles_at = 0, off_tiles_at = 0;
+    size_t descs = 0, states = 0, surv_tiles_at = 0, off_tiles_at = 0, enc_tiles_at = 0, carry_tiles_at = 0;
     size_t static_end = 0;  // [0, static_end) is uploaded at create
     size_t surv_counts = 0, partials = 0, total = 0;
 };
+
+// Most blocks of one offspring launch; SPEGG_OFFSPRING_GRID overrides.
+uint32_t offspring_grid_cap() {
+    const char *e = std::getenv("SPEGG_OFFSPRING_GRID");
+    if (e) {
+        const long v = std::atol(e);
+        if (v >= 64 && v <= (1 << 20)) return (uint32_t)v;
+    }
+    return kMaxOffspringGrid;
+}
 
 // Lanes-per-gamete cap of the offspring kernel.  A tuning knob only:
 // results do not depend on it.  SPEGG_OFFSPRING_GCAP overrides the default.
@@ -112,12 +137,33 @@ spegg_status validate(const spegg_rep_desc &d, uint32_t i) {
     if (d.replicate_id > SPEGG_MAX_REPLICATE_ID)
         return fail(SPEGG_E_INVALID, "replicate %u: replicate_id %u exceeds %u", i, d.replicate_id,
                     SPEGG_MAX_REPLICATE_ID);
-    if (d.regime != SPEGG_WF && d.regime != SPEGG_POISSON_BH)
+    if (d.regime != SPEGG_WF && d.regime != SPEGG_POISSON_BH && d.regime != SPEGG_CONSUMER_RESOURCE)
         return fail(SPEGG_E_INVALID, "replicate %u: unknown regime %u", i, d.regime);
     if (d.n_patches < 1 || d.n_patches > SPEGG_MAX_PATCHES)
         return fail(SPEGG_E_INVALID, "replicate %u: n_patches %u outside 1..%u", i, d.n_patches, SPEGG_MAX_PATCHES);
     if (d.n_patches > 1 && d.regime != SPEGG_WF)
         return fail(SPEGG_E_UNSUPPORTED, "replicate %u: patches need the Wright-Fisher regime", i);
+    if (d.regime == SPEGG_CONSUMER_RESOURCE) {
+        const spegg_ecology *e = d.ecology;
+        if (!e) return fail(SPEGG_E_INVALID, "replicate %u: the consumer-resource regime needs an ecology", i);
+        if (e->capacity_consumer < 1 || e->capacity_consumer > (1u << 30) || e->n0_consumer > e->capacity_consumer)
+            return fail(SPEGG_E_INVALID, "replicate %u: consumer census %u / capacity %u", i, e->n0_consumer,
+                        e->capacity_consumer);
+        if (e->resource_trials < 1 || e->resource_trials > 64)
+            return fail(SPEGG_E_INVALID, "replicate %u: resource_trials %u outside 1..64", i, e->resource_trials);
+        if (!(e->attack >= 0.0 && e->attack <= 1.0) || !(e->match_width > 0.0) || !(e->encounters >= 0.0) ||
+            !(e->conversion >= 0.0) || !(e->resource_q0 >= 0.0 && e->resource_q0 <= 1.0) ||
+            !(e->resource_K > 0.0) || !std::isfinite(e->encounters) || !std::isfinite(e->conversion) ||
+            !std::isfinite(e->resource_K) || !std::isfinite(e->match_width))
+            return fail(SPEGG_E_INVALID, "replicate %u: ecology rates out of range", i);
+        for (int a = 0; a < 4; ++a)
+            if (!(e->surv_resource[a] >= 0.0 && e->surv_resource[a] <= 1.0) ||
+                !(e->surv_consumer[a] >= 0.0 && e->surv_consumer[a] <= 1.0))
+                return fail(SPEGG_E_INVALID, "replicate %u: survival of age class %d outside [0, 1]", i, a);
+        if (d.n_patches != 1) return fail(SPEGG_E_UNSUPPORTED, "replicate %u: the consumer-resource regime has one patch", i);
+    } else if (d.ecology) {
+        return fail(SPEGG_E_INVALID, "replicate %u: ecology given for a one-species regime", i);
+    }
     if (!(d.migration >= 0.0 && d.migration <= 1.0))
         return fail(SPEGG_E_INVALID, "replicate %u: migration %g outside [0, 1]", i, d.migration);
     if (!(d.mu >= 0.0 && d.mu < 1.0)) return fail(SPEGG_E_INVALID, "replicate %u: mu %g outside [0, 1)", i, d.mu);
@@ -136,7 +182,7 @@ spegg_status validate(const spegg_rep_desc &d, uint32_t i) {
     return SPEGG_OK;
 }
 
-spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p) {
+spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const GcapMap *gcaps) {
     spegg_status st = validate(d, i);
     if (st != SPEGG_OK) return st;
     const uint32_t L = d.n_loci;
@@ -171,18 +217,42 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p) {
         return fail(SPEGG_E_UNSUPPORTED, "replicate %u: fecundity %g needs more than %d table entries", i,
                     d.fecundity, kPoissonTableCap);
     if (p.mode == kModeSkip && L > 1) geometric_table(d.r, L - 1u, p.geo);
-    p.shape = offspring_shape(p.W, offspring_gcap());
+    int gcap = offspring_gcap();
+    if (gcaps) {
+        const auto it = gcaps->find(p.W);
+        if (it != gcaps->end()) gcap = it->second;
+    }
+    p.shape = offspring_shape(p.W, gcap);
     p.opt = (uint32_t)offspring_per_tile(p.shape.g);
     p.n_demes = d.n_patches;
+    if (d.regime == SPEGG_CONSUMER_RESOURCE) {
+        const spegg_ecology &e = *d.ecology;
+        p.cr = true;
+        p.n_demes = 2;
+        if (!poisson_table(e.encounters, kPoissonTableCap, p.enc))
+            return fail(SPEGG_E_UNSUPPORTED, "replicate %u: encounters %g need more than %d table entries", i,
+                        e.encounters, kPoissonTableCap);
+        capture_table(e.attack, e.match_width, 2u * (uint32_t)abs_sum + 1u, p.capT);
+        // intake never exceeds the encounters: at most enc.size() - 1
+        for (size_t m = 0; m < p.enc.size(); ++m) {
+            std::vector<uint64_t> T;
+            if (!poisson_table(e.conversion * (double)m, kPoissonTableCap, T))
+                return fail(SPEGG_E_UNSUPPORTED, "replicate %u: consumer fecundity %g needs more than %d entries", i,
+                            e.conversion * (double)m, kPoissonTableCap);
+            p.cpois_off.push_back((uint32_t)p.cpois.size());
+            p.cpois_off.push_back((uint32_t)T.size());
+            p.cpois.insert(p.cpois.end(), T.begin(), T.end());
+        }
+    }
     return SPEGG_OK;
 }
 
-spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
+spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const GcapMap *gcaps = nullptr) {
     if (!reps || n == 0) return fail(SPEGG_E_INVALID, "no replicates");
     P.reps.resize(n);
     uint64_t n_demes = 0;
     for (uint32_t i = 0; i < n; ++i) {
-        const spegg_status st = build_rep(reps[i], i, P.reps[i]);
+        const spegg_status st = build_rep(reps[i], i, P.reps[i], gcaps);
         if (st != SPEGG_OK) return st;
         P.reps[i].deme0 = (uint32_t)n_demes;
         n_demes += P.reps[i].n_demes;
@@ -194,14 +264,23 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
         for (uint32_t k = 0; k < P.reps[i].n_demes; ++k) {
             DemePlan &q = P.demes[P.reps[i].deme0 + k];
             q.rep = i;
-            q.patch = k;
+            const bool consumer = P.reps[i].cr && k == 1;
+            q.patch = P.reps[i].cr ? 0u : k;
+            q.species = P.reps[i].cr ? k : 0u;
+            q.n0 = consumer ? reps[i].ecology->n0_consumer : reps[i].n0;
+            q.cap = consumer ? reps[i].ecology->capacity_consumer : reps[i].capacity;
         }
     // survival tiles, deme by deme
     for (uint32_t u = 0; u < P.demes.size(); ++u) {
         DemePlan &q = P.demes[u];
         q.surv_tile0 = (uint32_t)P.surv_tiles.size();
-        q.surv_ntiles = (reps[q.rep].capacity + kSurvTile - 1) / kSurvTile;
-        for (uint32_t k = 0; k < q.surv_ntiles; ++k) P.surv_tiles.push_back({u, k * (uint32_t)kSurvTile});
+        q.surv_ntiles = (q.cap + kSurvTile - 1) / kSurvTile;
+        for (uint32_t k = 0; k < q.surv_ntiles; ++k) {
+            const SurvTile tile{u, k * (uint32_t)kSurvTile};
+            P.surv_tiles.push_back(tile);
+            if (P.reps[q.rep].cr) P.carry_tiles.push_back(tile);
+            if (P.reps[q.rep].cr && q.species == 1) P.enc_tiles.push_back(tile);
+        }
     }
     // offspring tiles grouped by kernel shape
     std::vector<OffShape> shapes;
@@ -220,7 +299,7 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
             const RepPlan &p = P.reps[q.rep];
             if (p.shape.g != sh.g || p.shape.vpl != sh.vpl || p.shape.nch != sh.nch) continue;
             q.off_tile0 = (uint32_t)P.off_tiles.size();
-            q.off_ntiles = (reps[q.rep].capacity + p.opt - 1) / p.opt;
+            q.off_ntiles = (q.cap + p.opt - 1) / p.opt;
             for (uint32_t k = 0; k < q.off_ntiles; ++k) P.off_tiles.push_back({u, k * p.opt});
             if (p.W > maxW) maxW = p.W;
             planes |= !p.unit;
@@ -229,7 +308,8 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
         }
         c.ntiles = (uint32_t)P.off_tiles.size() - c.tile0;
         c.single_deme = members == 1 ? (int)last : -1;
-        c.grid = c.ntiles < kMaxOffspringGrid ? c.ntiles : kMaxOffspringGrid;
+        const uint32_t gmax = offspring_grid_cap();  // a tuning knob: results do not depend on it
+        c.grid = c.ntiles < gmax ? c.ntiles : gmax;
         c.plane_words = planes ? 6u * maxW : 0u;
         c.lds = c.plane_words * sizeof(uint32_t) + offspring_lds_bytes(sh.g, maxW);
         P.classes.push_back(c);
@@ -238,7 +318,13 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
     P.descs = cv.take(sizeof(RepDesc) * P.demes.size());
     P.states = cv.take(sizeof(RepState) * P.demes.size());
     P.surv_tiles_at = cv.take(sizeof(SurvTile) * P.surv_tiles.size());
-    P.off_tiles_at = cv.take(sizeof(OffTile) * P.off_tiles.size());
+    P.enc_tiles_at = cv.take(sizeof(SurvTile) * P.enc_tiles.size());
+    P.carry_tiles_at = cv.take(sizeof(SurvTile) * P.carry_tiles.size());
+    // offspring tiles and their partials are carved for the smallest tile of
+    // any shape (16 newborns), so a change of shape moves no buffer
+    size_t max_off_tiles = 0;
+    for (const DemePlan &q : P.demes) max_off_tiles += (q.cap + 15u) / 16u;
+    P.off_tiles_at = cv.take(sizeof(OffTile) * max_off_tiles);
     for (uint32_t i = 0; i < n; ++i) {
         RepPlan &p = P.reps[i];
         if (!p.vtab.empty()) p.vtab_at = cv.take(sizeof(double) * p.vtab.size());
@@ -246,13 +332,19 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
         p.binom_at = cv.take(sizeof(uint64_t) * p.binom.size());
         if (!p.geo.empty()) p.geo_at = cv.take(sizeof(uint64_t) * p.geo.size());
         if (!p.planes.empty()) p.planes_at = cv.take(sizeof(uint32_t) * p.planes.size());
+        if (p.cr) {
+            p.enc_at = cv.take(sizeof(uint64_t) * p.enc.size());
+            p.capT_at = cv.take(sizeof(uint64_t) * p.capT.size());
+            p.cpois_at = cv.take(sizeof(uint64_t) * p.cpois.size());
+            p.cpois_off_at = cv.take(sizeof(uint32_t) * p.cpois_off.size());
+        }
     }
     P.static_end = cv.off;
     P.surv_counts = cv.take(sizeof(SurvCount) * P.surv_tiles.size());
-    P.partials = cv.take(sizeof(Partial) * P.off_tiles.size());
+    P.partials = cv.take(sizeof(Partial) * max_off_tiles);
     for (DemePlan &q : P.demes) {
         const RepPlan &p = P.reps[q.rep];
-        const size_t cap = reps[q.rep].capacity;
+        const size_t cap = q.cap;
         const size_t gbytes = cap * 2u * p.W * sizeof(uint32_t);
         q.genome[0] = cv.take(gbytes);
         q.genome[1] = cv.take(gbytes);
@@ -262,10 +354,16 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P) {
         q.z[1] = cv.take(zcap * sizeof(int32_t));
         q.fate = cv.take(zcap * sizeof(uint16_t));
         q.S = cv.take(cap * sizeof(uint32_t));
-        if (reps[q.rep].regime == SPEGG_POISSON_BH) q.owner = cv.take(cap * sizeof(uint32_t));
+        if (reps[q.rep].regime != SPEGG_WF) q.owner = cv.take(cap * sizeof(uint32_t));
         q.mom = cv.take(cap * sizeof(uint32_t));
         q.dad = cv.take(cap * sizeof(uint32_t));
         if (p.mig_T) q.src = cv.take(cap * sizeof(uint32_t));
+        if (p.cr) {
+            q.age[0] = cv.take(zcap);  // padded to whole tiles: read 4 at a time
+            q.age[1] = cv.take(zcap);
+            if (q.species == 0) q.won = cv.take(cap * sizeof(uint64_t));
+            else q.intake = cv.take(cap * sizeof(uint32_t));
+        }
     }
     P.total = cv.off;
     return SPEGG_OK;
@@ -316,7 +414,10 @@ struct spegg_pop {
     uint8_t *base = nullptr;
     uint32_t n_reps = 0, n_demes = 0;
     Plan plan;
-    std::vector<spegg_rep_desc> descs;
+    std::vector<spegg_rep_desc> descs;           // the caller's descriptors, pointing at the copies below
+    std::vector<std::vector<int8_t>> effects;    // copies of the effects
+    std::vector<spegg_ecology> ecology;          // copies of the ecologies
+    GcapMap gcaps;                               // autotuned lanes-per-gamete caps by W
     std::vector<RepDesc> dev_descs;  // host images of the device descriptors, one per deme
     std::vector<uint32_t> deme_gen;  // each deme's generation, tracked on the host
     std::vector<uint8_t> image;      // host image of [0, static_end)
@@ -446,14 +547,17 @@ spegg_status read_state(spegg_pop *pop, uint32_t deme, RepState &s) {
     return sync_stream(pop);
 }
 
-// The deme of (replicate, patch, species).
+// The deme of (replicate, patch, species): patches of a ring, or the two
+// species of the consumer-resource regime.
 spegg_status find_deme(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *deme) {
     if (rep >= pop->n_reps) return fail(SPEGG_E_INVALID, "replicate %u out of range (%u)", rep, pop->n_reps);
     const RepPlan &p = pop->plan.reps[rep];
-    if (patch >= p.n_demes)
-        return fail(SPEGG_E_INVALID, "patch %u out of range (replicate %u has %u)", patch, rep, p.n_demes);
-    if (species != 0) return fail(SPEGG_E_UNSUPPORTED, "one species per patch in this build");
-    *deme = p.deme0 + patch;
+    const uint32_t n_patches = p.cr ? 1u : p.n_demes, n_species = p.cr ? 2u : 1u;
+    if (patch >= n_patches)
+        return fail(SPEGG_E_INVALID, "patch %u out of range (replicate %u has %u)", patch, rep, n_patches);
+    if (species >= n_species)
+        return fail(SPEGG_E_INVALID, "species %u out of range (replicate %u has %u)", species, rep, n_species);
+    *deme = p.deme0 + patch + species;
     return SPEGG_OK;
 }
 
@@ -478,16 +582,42 @@ spegg_status deme_stats(spegg_pop *pop, uint32_t n_demes, std::vector<spegg_rep_
     return SPEGG_OK;
 }
 
+// Consumer-resource demes: every individual of age 0 and no resource
+// captured, in both buffers (before a first generation).
+hipError_t reset_species_state(spegg_pop *pop, uint32_t u) {
+    const DemePlan &q = pop->plan.demes[u];
+    const RepDesc &h = pop->dev_descs[u];
+    if (!pop->plan.reps[q.rep].cr) return hipSuccess;
+    const uint32_t zcap = ((q.cap + kSurvTile - 1) / kSurvTile) * kSurvTile;
+    hipError_t e = launch_fill_u8(h.age[0], zcap, pop->stream);
+    if (e == hipSuccess) e = launch_fill_u8(h.age[1], zcap, pop->stream);
+    if (e == hipSuccess && h.won) e = launch_fill_u64(h.won, q.cap, pop->stream);
+    return e;
+}
+
 // The launches of n generations on the population's stream.
 hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
     Plan &P = pop->plan;
     const uint32_t ns_tiles = (uint32_t)P.surv_tiles.size();
     const int trace = pop->trace ? 1 : 0;
+    const SurvTile *enc_tiles = at<SurvTile>(pop->base, P.enc_tiles_at);
+    const SurvTile *carry_tiles = at<SurvTile>(pop->base, P.carry_tiles_at);
     for (uint32_t g = 0; g < n; ++g) {
         const SelArgs sa{pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), pop->d_surv_counts(), ns_tiles, trace,
                          pop->stream};
-        hipError_t e = timed(pop, SPEGG_KERNEL_SURVIVE, [&] { return launch_survive(sa); });
+        hipError_t e = hipSuccess;
+        if (!P.enc_tiles.empty())
+            e = timed(pop, SPEGG_KERNEL_ENCOUNTER, [&] {
+                return launch_encounter(pop->d_descs(), pop->d_states(), enc_tiles, (uint32_t)P.enc_tiles.size(),
+                                        pop->stream);
+            });
+        if (e == hipSuccess) e = timed(pop, SPEGG_KERNEL_SURVIVE, [&] { return launch_survive(sa); });
         if (e == hipSuccess) e = timed(pop, SPEGG_KERNEL_COMPACT, [&] { return launch_compact(sa); });
+        if (e == hipSuccess && !P.carry_tiles.empty())
+            e = timed(pop, SPEGG_KERNEL_CARRY, [&] {
+                return launch_carry(pop->d_descs(), pop->d_states(), carry_tiles, (uint32_t)P.carry_tiles.size(),
+                                    pop->stream);
+            });
         for (const OffClass &c : P.classes) {
             if (e != hipSuccess) return e;
             const OffArgs oa{pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0, c.ntiles, c.single_deme,
@@ -576,11 +706,11 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         std::memset(&h, 0, sizeof h);
         h.L = d.n_loci;
         h.W = p.W;
-        h.cap = d.capacity;
+        h.cap = q.cap;
         h.regime = d.regime;
         h.key0 = (uint32_t)d.seed;
         h.key1 = (uint32_t)(d.seed >> 32);
-        h.c3 = d.replicate_id << 12 | q.patch;  // species 0
+        h.c3 = d.replicate_id << 12 | q.species << 10 | q.patch;
         h.mode = p.mode;
         h.R = p.R;
         h.geo_len = (uint32_t)p.geo.size();
@@ -619,9 +749,29 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.binom = at<uint64_t>(pop->base, p.binom_at);
         h.geo = p.geo.empty() ? nullptr : at<uint64_t>(pop->base, p.geo_at);
         h.planes = p.planes.empty() ? nullptr : at<uint32_t>(pop->base, p.planes_at);
+        h.species = q.species;
+        if (p.cr) {
+            const spegg_ecology &ec = *d.ecology;
+            h.partner = p.deme0 + (q.species ^ 1u);
+            h.habitat = ec.habitat;
+            h.trials = ec.resource_trials;
+            h.enc_len = (uint32_t)p.enc.size();
+            h.cap_len = (uint32_t)p.capT.size();
+            h.q0 = ec.resource_q0;
+            h.KR = ec.resource_K;
+            for (int a = 0; a < 4; ++a) h.surv_age[a] = q.species == 0 ? ec.surv_resource[a] : ec.surv_consumer[a];
+            h.enc = at<uint64_t>(pop->base, p.enc_at);
+            h.capT = at<uint64_t>(pop->base, p.capT_at);
+            h.cpois = at<uint64_t>(pop->base, p.cpois_at);
+            h.cpois_off = at<uint32_t>(pop->base, p.cpois_off_at);
+            h.age[0] = at<uint8_t>(pop->base, q.age[0]);
+            h.age[1] = at<uint8_t>(pop->base, q.age[1]);
+            h.won = q.won ? at<uint64_t>(pop->base, q.won) : nullptr;
+            h.intake = q.intake ? at<uint32_t>(pop->base, q.intake) : nullptr;
+        }
         pop->dev_descs[u] = h;
         std::memcpy(img + P.descs + u * sizeof(RepDesc), &h, sizeof h);
-        const RepState s0 = initial_state(0, d.n0);
+        const RepState s0 = initial_state(0, q.n0);
         std::memcpy(img + P.states + u * sizeof(RepState), &s0, sizeof s0);
     }
     for (uint32_t i = 0; i < n_reps; ++i) {
@@ -631,9 +781,19 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         std::memcpy(img + p.binom_at, p.binom.data(), sizeof(uint64_t) * p.binom.size());
         if (!p.geo.empty()) std::memcpy(img + p.geo_at, p.geo.data(), sizeof(uint64_t) * p.geo.size());
         if (!p.planes.empty()) std::memcpy(img + p.planes_at, p.planes.data(), sizeof(uint32_t) * p.planes.size());
+        if (p.cr) {
+            std::memcpy(img + p.enc_at, p.enc.data(), sizeof(uint64_t) * p.enc.size());
+            std::memcpy(img + p.capT_at, p.capT.data(), sizeof(uint64_t) * p.capT.size());
+            std::memcpy(img + p.cpois_at, p.cpois.data(), sizeof(uint64_t) * p.cpois.size());
+            std::memcpy(img + p.cpois_off_at, p.cpois_off.data(), sizeof(uint32_t) * p.cpois_off.size());
+        }
     }
     if (!P.surv_tiles.empty())
         std::memcpy(img + P.surv_tiles_at, P.surv_tiles.data(), sizeof(SurvTile) * P.surv_tiles.size());
+    if (!P.enc_tiles.empty())
+        std::memcpy(img + P.enc_tiles_at, P.enc_tiles.data(), sizeof(SurvTile) * P.enc_tiles.size());
+    if (!P.carry_tiles.empty())
+        std::memcpy(img + P.carry_tiles_at, P.carry_tiles.data(), sizeof(SurvTile) * P.carry_tiles.size());
     if (!P.off_tiles.empty())
         std::memcpy(img + P.off_tiles_at, P.off_tiles.data(), sizeof(OffTile) * P.off_tiles.size());
 
@@ -643,16 +803,29 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         return fail(SPEGG_E_DEVICE, "hipMemcpyAsync(tables): %s", hipGetErrorString(e));
     }
     for (uint32_t u = 0; u < pop->n_demes; ++u) {
-        const uint32_t n0 = reps[P.demes[u].rep].n0;
+        const uint32_t n0 = P.demes[u].n0;
         e = launch_init(pop->d_descs() + u, pop->dev_descs[u], n0, pop->stream);
         if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + u, pop->d_states() + u, n0, 0, pop->stream);
+        if (e == hipSuccess) e = reset_species_state(pop, u);
         if (e != hipSuccess) {
             delete pop;
             return fail(SPEGG_E_DEVICE, "initial population: %s", hipGetErrorString(e));
         }
     }
-    // The effects pointer is the caller's; keep only the copy in the tables.
-    for (auto &d : pop->descs) d.effects = nullptr;
+    // The effects and ecology pointers are the caller's: point at copies.
+    pop->effects.resize(n_reps);
+    pop->ecology.resize(n_reps);
+    for (uint32_t i = 0; i < n_reps; ++i) {
+        spegg_rep_desc &d = pop->descs[i];
+        if (d.effects) {
+            pop->effects[i].assign(d.effects, d.effects + d.n_loci);
+            d.effects = pop->effects[i].data();
+        }
+        if (d.ecology) {
+            pop->ecology[i] = *d.ecology;
+            d.ecology = &pop->ecology[i];
+        }
+    }
     *out = pop;
     g_error.clear();
     return SPEGG_OK;
@@ -717,13 +890,13 @@ spegg_status spegg_stats(spegg_pop *pop, spegg_rep_stats *host_out, uint32_t n) 
     return SPEGG_OK;
 }
 
-spegg_status spegg_patch_stats(spegg_pop *pop, uint32_t rep, spegg_rep_stats *host_out, uint32_t n) {
+spegg_status spegg_deme_stats(spegg_pop *pop, uint32_t rep, spegg_rep_stats *host_out, uint32_t n) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
     if (rep >= pop->n_reps) return fail(SPEGG_E_INVALID, "replicate %u out of range (%u)", rep, pop->n_reps);
     const RepPlan &p = pop->plan.reps[rep];
     if (!host_out || n != p.n_demes)
-        return fail(SPEGG_E_INVALID, "patch_stats: replicate %u has %u patches", rep, p.n_demes);
+        return fail(SPEGG_E_INVALID, "deme_stats: replicate %u has %u demes", rep, p.n_demes);
     DeviceGuard guard(pop->device);
     std::vector<spegg_rep_stats> per;
     if ((st = deme_stats(pop, p.deme0 + p.n_demes, per)) != SPEGG_OK) return st;
@@ -776,18 +949,19 @@ spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, u
                            pop->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(pop->d_states() + u, &s0, sizeof s0, hipMemcpyHostToDevice, pop->stream);
     if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + u, pop->d_states() + u, n, buf, pop->stream);
+    if (e == hipSuccess) e = reset_species_state(pop, u);
     if (e != hipSuccess) return device_fail(pop, e, "write_genomes");
     st = sync_stream(pop);
     if (st == SPEGG_OK) pop->deme_gen[u] = generation;
     return st;
 }
 
-spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, uint32_t patch, int32_t *host_z, size_t n,
-                                   uint32_t *n_out) {
+spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, int32_t *host_z,
+                                   size_t n, uint32_t *n_out) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
     uint32_t u;
-    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
+    if ((st = find_deme(pop, rep, patch, species, &u)) != SPEGG_OK) return st;
     DeviceGuard guard(pop->device);
     RepState s;
     if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
@@ -801,12 +975,50 @@ spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, uint32_t patch,
     return sync_stream(pop);
 }
 
-spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *host_idx, size_t n,
-                                  uint32_t *n_out) {
+spegg_status spegg_read_ages(spegg_pop *pop, uint32_t rep, uint32_t species, uint8_t *host_age, size_t n,
+                             uint32_t *n_out) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
     uint32_t u;
-    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
+    if ((st = find_deme(pop, rep, 0, species, &u)) != SPEGG_OK) return st;
+    const RepDesc &h = pop->dev_descs[u];
+    if (!h.age[0]) return fail(SPEGG_E_STATE, "read_ages: replicate %u has no age classes", rep);
+    DeviceGuard guard(pop->device);
+    RepState s;
+    if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
+    const uint32_t cn = s.n[current_pair_host(s)], ct = s.t[current_pair_host(s)];
+    if (n_out) *n_out = cn;
+    if (cn == 0) return SPEGG_OK;
+    if (!host_age || n < cn) return fail(SPEGG_E_INVALID, "read_ages: need room for %u values", cn);
+    hipError_t e = hipMemcpyAsync(host_age, h.age[ct & 1u], cn, hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(ages)");
+    return sync_stream(pop);
+}
+
+spegg_status spegg_read_intake(spegg_pop *pop, uint32_t rep, uint32_t *host_intake, size_t n, uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, 0, 1, &u)) != SPEGG_OK) return st;
+    DeviceGuard guard(pop->device);
+    RepState s;
+    if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
+    const uint32_t m = s.n_prev;  // the consumers the last generation started from
+    if (n_out) *n_out = m;
+    if (m == 0) return SPEGG_OK;
+    if (!host_intake || n < m) return fail(SPEGG_E_INVALID, "read_intake: need room for %u values", m);
+    hipError_t e = hipMemcpyAsync(host_intake, pop->dev_descs[u].intake, (size_t)m * sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(intake)");
+    return sync_stream(pop);
+}
+
+spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *host_idx,
+                                  size_t n, uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, species, &u)) != SPEGG_OK) return st;
     DeviceGuard guard(pop->device);
     RepState s;
     if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
@@ -820,12 +1032,12 @@ spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t patch, 
     return sync_stream(pop);
 }
 
-spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *counts_dev,
+spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *counts_dev,
                                  uint32_t *host_counts, uint32_t n_loci, uint32_t *n_out) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
     uint32_t u;
-    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
+    if ((st = find_deme(pop, rep, patch, species, &u)) != SPEGG_OK) return st;
     const RepDesc &h = pop->dev_descs[u];
     if (n_loci != h.L || !counts_dev || !host_counts)
         return fail(SPEGG_E_INVALID, "allele_counts: need n_loci == %u and both arrays", h.L);
@@ -851,17 +1063,17 @@ spegg_status spegg_set_trace(spegg_pop *pop, int enable) {
     return SPEGG_OK;
 }
 
-spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t *host_mom, uint32_t *host_dad,
-                                uint32_t *host_src, size_t n, uint32_t *n_out) {
+spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *host_mom,
+                                uint32_t *host_dad, uint32_t *host_src, size_t n, uint32_t *n_out) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
     uint32_t u;
-    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
+    if ((st = find_deme(pop, rep, patch, species, &u)) != SPEGG_OK) return st;
     DeviceGuard guard(pop->device);
     RepState s;
     if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
     if (!s.traced) return fail(SPEGG_E_STATE, "read_parents: tracing was off for the last generation");
-    const uint32_t cn = s.n[current_pair_host(s)];
+    const uint32_t cn = s.n[current_pair_host(s)] - s.n_carry;  // newborns
     if (n_out) *n_out = cn;
     if (cn == 0) return SPEGG_OK;
     if (!host_mom || !host_dad || n < cn) return fail(SPEGG_E_INVALID, "read_parents: need room for %u entries", cn);
@@ -913,6 +1125,123 @@ spegg_status spegg_kernel_times(spegg_pop *pop, double *ms, uint64_t *launches, 
     for (int k = 0; k < SPEGG_KERNEL_KINDS; ++k) {
         pop->ms[k] = 0;
         pop->launches[k] = 0;
+    }
+    return SPEGG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Re-plan the offspring kernels with the population's lanes-per-gamete caps:
+// fold pending census sums (they are indexed by the old tiles), then
+// replace the offspring tiles and the descriptors' tile fields.  Buffers do
+// not move: the carve does not depend on the shapes.
+spegg_status apply_shapes(spegg_pop *pop) {
+    Plan P2;
+    spegg_status st = make_plan(pop->descs.data(), pop->n_reps, P2, &pop->gcaps);
+    if (st != SPEGG_OK) return st;
+    if (P2.total != pop->plan.total || P2.static_end != pop->plan.static_end || P2.off_tiles_at != pop->plan.off_tiles_at)
+        return fail(SPEGG_E_STATE, "autotune: a new shape would move buffers");
+    hipError_t e = launch_census(pop->d_descs(), pop->d_states(), pop->d_partials(), pop->n_demes, pop->stream);
+    for (uint32_t u = 0; u < pop->n_demes; ++u) {
+        RepDesc &h = pop->dev_descs[u];
+        h.off_tile0 = P2.demes[u].off_tile0;
+        h.off_ntiles = P2.demes[u].off_ntiles;
+        h.off_per_tile = P2.reps[P2.demes[u].rep].opt;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pop->d_descs(), pop->dev_descs.data(), sizeof(RepDesc) * pop->n_demes,
+                           hipMemcpyHostToDevice, pop->stream);
+    if (e == hipSuccess && !P2.off_tiles.empty())
+        e = hipMemcpyAsync(at<OffTile>(pop->base, P2.off_tiles_at), P2.off_tiles.data(),
+                           sizeof(OffTile) * P2.off_tiles.size(), hipMemcpyHostToDevice, pop->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pop->stream);  // the host arrays are copied before they change
+    if (e != hipSuccess) return device_fail(pop, e, "autotune: new shapes");
+    pop->plan = std::move(P2);
+    pop->drop_graphs();
+    return SPEGG_OK;
+}
+
+// Sum of the cumulative genotype-locus updates of every deme (waits).
+spegg_status total_updates(spegg_pop *pop, uint64_t *out) {
+    std::vector<RepState> s(pop->n_demes);
+    hipError_t e = hipMemcpyAsync(s.data(), pop->d_states(), sizeof(RepState) * pop->n_demes, hipMemcpyDeviceToHost,
+                                  pop->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "autotune: states");
+    *out = 0;
+    for (const RepState &r : s) *out += r.updates;
+    return SPEGG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spegg_status spegg_autotune(spegg_pop *pop, uint32_t generations_per_trial, uint32_t *w_out, uint32_t *gcap_out,
+                            uint32_t cap, uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if (generations_per_trial == 0) return fail(SPEGG_E_INVALID, "autotune: need at least one generation per trial");
+    DeviceGuard guard(pop->device);
+    std::vector<uint32_t> Ws;
+    for (const RepPlan &p : pop->plan.reps)
+        if (std::find(Ws.begin(), Ws.end(), p.W) == Ws.end()) Ws.push_back(p.W);
+    std::sort(Ws.begin(), Ws.end());
+    const uint32_t saved_timing = pop->timing;
+    pop->timing = 1u << SPEGG_KERNEL_OFFSPRING;
+    // pending events of the caller's timing are kept apart
+    std::vector<Timed> caller_pending;
+    caller_pending.swap(pop->pending);
+    for (uint32_t W : Ws) {
+        std::vector<int> cands;
+        std::vector<OffShape> seen;
+        for (int g : {1, 2, 4, 8, 16, 32}) {
+            const OffShape sh = offspring_shape(W, g);
+            bool dup = false;
+            for (const OffShape &x : seen) dup |= x.g == sh.g && x.vpl == sh.vpl && x.nch == sh.nch;
+            if (!dup) {
+                seen.push_back(sh);
+                cands.push_back(g);
+            }
+        }
+        int best = pop->gcaps.count(W) ? pop->gcaps[W] : offspring_gcap();
+        double best_score = 0.0;
+        bool have = false;
+        for (int g : cands) {
+            pop->gcaps[W] = g;
+            if ((st = apply_shapes(pop)) != SPEGG_OK) break;
+            uint64_t u0 = 0, u1 = 0;
+            if ((st = total_updates(pop, &u0)) != SPEGG_OK) break;
+            if ((st = spegg_step_generations(pop, generations_per_trial)) != SPEGG_OK) break;
+            if ((st = total_updates(pop, &u1)) != SPEGG_OK) break;
+            double ms = 0.0;
+            for (const Timed &t : pop->pending) {
+                float x = 0.f;
+                if (hipEventElapsedTime(&x, t.a, t.b) == hipSuccess) ms += x;
+                pop->event_pool.push_back(t.a);
+                pop->event_pool.push_back(t.b);
+            }
+            pop->pending.clear();
+            const double score = ms / (double)(u1 > u0 ? u1 - u0 : 1u);
+            if (!have || score < best_score) {
+                have = true;
+                best_score = score;
+                best = g;
+            }
+        }
+        if (st != SPEGG_OK) break;
+        pop->gcaps[W] = best;
+    }
+    pop->pending.swap(caller_pending);
+    pop->timing = saved_timing;
+    if (st != SPEGG_OK) return st;
+    if ((st = apply_shapes(pop)) != SPEGG_OK) return st;
+    if (n_out) *n_out = (uint32_t)Ws.size();
+    for (uint32_t k = 0; k < Ws.size() && k < cap; ++k) {
+        if (w_out) w_out[k] = Ws[k];
+        if (gcap_out) gcap_out[k] = (uint32_t)pop->gcaps[Ws[k]];
     }
     return SPEGG_OK;
 }

@@ -1,7 +1,8 @@
 // Internal types shared by the host side and the kernels of libspegg.
 //
-// The kernels work on demes: one patch of one replicate.  A replicate of P
-// patches is P consecutive demes sharing its tables.
+// The kernels work on demes: one patch of one species of one replicate.  A
+// replicate of P patches is P consecutive demes sharing its tables; the
+// consumer-resource regime has two demes, resource then consumer.
 //
 // Device memory of a population is one caller-owned block, carved into:
 //   [RepDesc x n_demes][RepState x n_demes][SurvTile...][OffTile...][tables]  uploaded once at create
@@ -30,7 +31,9 @@ enum Stream : uint32_t {
     kStParent = 5,
     kStRecomb = 6,  // + 0 maternal gamete, + 1 paternal
     kStMutate = 8,  // + 0 maternal gamete, + 1 paternal
-    kStMigrate = 10
+    kStMigrate = 10,
+    kStEncounter = 11,
+    kStCapture = 12
 };
 
 // Crossover sampling, a function of r alone.
@@ -63,7 +66,21 @@ struct RepDesc {
     uint64_t mig_T;      // a newborn is a migrant when MIGRATE word 0 < mig_T; 0: no migration
     uint32_t patch;      // patch of the deme within its replicate
     uint32_t left, right;  // demes of the ring neighbours (the deme itself without migration)
-    uint32_t pad1;
+    uint32_t species;    // consumer-resource regime: 0 resource, 1 consumer
+    // consumer-resource regime
+    uint32_t partner;    // deme of the other species
+    uint32_t habitat;    // encounter slots (0: the resource census)
+    uint32_t trials;     // resource offspring trials
+    uint32_t enc_len, cap_len;
+    double q0, KR;       // resource fecundity: Binomial(trials, q0 max(0, 1 - N_R / KR))
+    double surv_age[4];  // survival by age class
+    const uint64_t *enc;   // encounters per consumer (Poisson)
+    const uint64_t *capT;  // capture threshold by |z_c - z_r|
+    const uint64_t *cpois; // consumer offspring tables, Poisson(conversion m), concatenated
+    const uint32_t *cpois_off;  // 2 words per intake m: offset into cpois, length
+    uint8_t *age[2];     // age class, ping-pong with the genomes
+    uint64_t *won;       // resources: lowest capture key this generation, ~0 when not captured
+    uint32_t *intake;    // consumers: credited captures of each adult
     uint32_t *genome[2];
     int32_t *z[2];
     uint16_t *fate;      // per adult: bit 15 survived, bits 0..14 offspring as mother
@@ -89,6 +106,8 @@ struct RepState {
     uint32_t census_pending;  // census sums still sit in the offspring tiles' partials
     uint32_t error;           // set by a kernel that found an impossible state (never expected)
     uint32_t captures;        // consumers: credited captures of the last generation
+    uint32_t n_carry;         // survivors carried into the current census (consumer-resource regime)
+    uint32_t pad0;
     uint64_t near_ties, truncated, updates, sum_threshold;
     int64_t sum_z[kCensusSlots];
     uint64_t sum_z2[kCensusSlots];
@@ -105,6 +124,7 @@ struct SurvCount {
     uint32_t alive, kids, near, par;
     uint64_t sum_t;
     uint32_t t, n;
+    uint32_t intake, pad;  // consumers: credited captures of the tile's adults
 };
 
 struct OffTile {
@@ -186,6 +206,18 @@ hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t 
 hipError_t launch_survive(const SelArgs &a);
 hipError_t launch_compact(const SelArgs &a);
 hipError_t launch_offspring(OffShape shape, const OffArgs &a);
+// Consumer-resource regime: encounters and captures of the consumers in
+// tiles (one block per tile of kSurvTile consumers).
+hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
+                            hipStream_t s);
+// Consumer-resource regime: survivors into the next census (one block per
+// survival tile of the regime's demes).
+hipError_t launch_carry(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
+                        hipStream_t s);
+// Fill n words of a uint64 array with ~0 (capture keys before the first
+// generation) and n bytes with 0 (ages).
+hipError_t launch_fill_u64(uint64_t *p, uint32_t n, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, uint32_t n, hipStream_t s);
 // Fold pending per-tile census sums into each replicate's state.
 hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,
                          hipStream_t s);

@@ -89,4 +89,14 @@ void viability_table(double theta, double omega, int32_t zmin, uint32_t n, std::
     }
 }
 
+// Gaussian phenotype matching of consumer and resource, a exp(-d^2 /
+// (2 sigma^2)) at distance d, as capture thresholds.
+void capture_table(double a, double sigma, uint32_t n, std::vector<uint64_t> &T) {
+    T.resize(n);
+    for (uint32_t d = 0; d < n; ++d) {
+        const double dd = (double)d;
+        T[d] = prob_threshold(a * std::exp(-(dd * dd) / (2.0 * sigma * sigma)));
+    }
+}
+
 }  // namespace spegg

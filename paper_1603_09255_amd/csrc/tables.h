@@ -17,5 +17,8 @@ uint32_t recomb_mode(double r);
 // Bernoulli(p) threshold floor(p 2^32); p >= 1: 2^32 (always), p <= 0: 0.
 uint64_t prob_threshold(double p);
 void viability_table(double theta, double omega, int32_t zmin, uint32_t n, std::vector<double> &v);
+// Capture thresholds floor(a exp(-d^2 / (2 sigma^2)) 2^32) for phenotype
+// distances d = 0 .. n - 1.
+void capture_table(double a, double sigma, uint32_t n, std::vector<uint64_t> &T);
 
 }  // namespace spegg

@@ -14,14 +14,31 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libspegg.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-WF, POISSON_BH = 0, 1
-KERNEL_NAMES = ["survive", "compact", "offspring"]
+WF, POISSON_BH, CONSUMER_RESOURCE = 0, 1, 2
+KERNEL_NAMES = ["survive", "compact", "offspring", "encounter", "carry"]
 
 
 class SpeggError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"spegg status {status}: {message}")
         self.status = status
+
+
+class Ecology(C.Structure):
+    _fields_ = [
+        ("n0_consumer", C.c_uint32),
+        ("capacity_consumer", C.c_uint32),
+        ("resource_trials", C.c_uint32),
+        ("habitat", C.c_uint32),
+        ("attack", C.c_double),
+        ("match_width", C.c_double),
+        ("encounters", C.c_double),
+        ("conversion", C.c_double),
+        ("resource_q0", C.c_double),
+        ("resource_K", C.c_double),
+        ("surv_resource", C.c_double * 4),
+        ("surv_consumer", C.c_double * 4),
+    ]
 
 
 class RepDesc(C.Structure):
@@ -41,6 +58,7 @@ class RepDesc(C.Structure):
         ("fecundity", C.c_double),
         ("migration", C.c_double),
         ("effects", C.POINTER(C.c_int8)),
+        ("ecology", C.POINTER(Ecology)),
     ]
 
 
@@ -90,22 +108,28 @@ def load():
     lib.spegg_step_generations.argtypes = [vp, u32]
     lib.spegg_stats.restype = st
     lib.spegg_stats.argtypes = [vp, C.POINTER(RepStats), u32]
-    lib.spegg_patch_stats.restype = st
-    lib.spegg_patch_stats.argtypes = [vp, u32, C.POINTER(RepStats), u32]
+    lib.spegg_deme_stats.restype = st
+    lib.spegg_deme_stats.argtypes = [vp, u32, C.POINTER(RepStats), u32]
     lib.spegg_read_genomes.restype = st
     lib.spegg_read_genomes.argtypes = [vp, u32, u32, u32, P32, C.c_size_t, P32]
     lib.spegg_write_genomes.restype = st
     lib.spegg_write_genomes.argtypes = [vp, u32, u32, u32, P32, u32, u32]
     lib.spegg_read_phenotypes.restype = st
-    lib.spegg_read_phenotypes.argtypes = [vp, u32, u32, C.POINTER(C.c_int32), C.c_size_t, P32]
+    lib.spegg_read_phenotypes.argtypes = [vp, u32, u32, u32, C.POINTER(C.c_int32), C.c_size_t, P32]
+    lib.spegg_read_ages.restype = st
+    lib.spegg_read_ages.argtypes = [vp, u32, u32, C.POINTER(C.c_uint8), C.c_size_t, P32]
+    lib.spegg_read_intake.restype = st
+    lib.spegg_read_intake.argtypes = [vp, u32, P32, C.c_size_t, P32]
     lib.spegg_read_survivors.restype = st
-    lib.spegg_read_survivors.argtypes = [vp, u32, u32, P32, C.c_size_t, P32]
+    lib.spegg_read_survivors.argtypes = [vp, u32, u32, u32, P32, C.c_size_t, P32]
     lib.spegg_allele_counts.restype = st
-    lib.spegg_allele_counts.argtypes = [vp, u32, u32, vp, P32, u32, P32]
+    lib.spegg_allele_counts.argtypes = [vp, u32, u32, u32, vp, P32, u32, P32]
     lib.spegg_set_trace.restype = st
     lib.spegg_set_trace.argtypes = [vp, C.c_int]
     lib.spegg_read_parents.restype = st
-    lib.spegg_read_parents.argtypes = [vp, u32, u32, P32, P32, P32, C.c_size_t, P32]
+    lib.spegg_read_parents.argtypes = [vp, u32, u32, u32, P32, P32, P32, C.c_size_t, P32]
+    lib.spegg_autotune.restype = st
+    lib.spegg_autotune.argtypes = [vp, u32, P32, P32, u32, P32]
     lib.spegg_set_graph.restype = st
     lib.spegg_set_graph.argtypes = [vp, C.c_int]
     lib.spegg_set_timing.restype = st
@@ -152,7 +176,19 @@ def _p(arr, ctype):
 
 
 DESC_KEYS = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
-             "fecundity", "effects", "n_patches", "migration")
+             "fecundity", "effects", "n_patches", "migration", "ecology")
+
+
+def make_ecology(eco):
+    e = Ecology()
+    for k, v in eco.items():
+        if k in ("surv_resource", "surv_consumer"):
+            arr = getattr(e, k)
+            for a in range(4):
+                arr[a] = float(v[a])
+        else:
+            setattr(e, k, v)
+    return e
 
 
 def make_descs(reps):
@@ -178,6 +214,10 @@ def make_descs(reps):
             e = np.ascontiguousarray(eff, dtype=np.int8)
             keep.append(e)
             arr[k].effects = _p(e, C.c_int8)
+        if d.get("ecology") is not None:
+            eco = make_ecology(d["ecology"])
+            keep.append(eco)
+            arr[k].ecology = C.pointer(eco)
     return arr, keep
 
 
@@ -239,6 +279,8 @@ class Population:
         self.L = [int(d.get("n_loci", 64)) for d in self.reps]
         self.W = [(L + 31) // 32 for L in self.L]
         self.P = [int(d.get("n_patches", 1)) for d in self.reps]
+        # demes per replicate: its patches, or the two species of the consumer-resource regime
+        self.D = [2 if d.get("regime") == CONSUMER_RESOURCE else p for d, p in zip(self.reps, self.P)]
         del keep
 
     def close(self):
@@ -266,55 +308,87 @@ class Population:
         check(self.lib.spegg_stats(self._h, out, self.n_reps))
         return [s.as_dict() for s in out]
 
-    def patch_stats(self, rep=0):
-        """The census of each of replicate rep's patches."""
-        out = (RepStats * self.P[rep])()
-        check(self.lib.spegg_patch_stats(self._h, rep, out, self.P[rep]))
+    def deme_stats(self, rep=0):
+        """The census of each of replicate rep's demes (patches, or species
+        0 resource and 1 consumer)."""
+        out = (RepStats * self.D[rep])()
+        check(self.lib.spegg_deme_stats(self._h, rep, out, self.D[rep]))
         return [s.as_dict() for s in out]
 
-    def _n_of(self, rep, patch=0):
-        per = self.patch_stats(rep)
-        if not 0 <= patch < len(per):
-            raise SpeggError(E_INVALID, f"patch {patch} out of range (replicate {rep} has {len(per)})")
-        return per[patch]["n"]
+    def _n_of(self, rep, patch=0, species=0):
+        per = self.deme_stats(rep)
+        k = patch + species
+        if not 0 <= k < len(per):
+            raise SpeggError(E_INVALID, f"deme {k} out of range (replicate {rep} has {len(per)})")
+        return per[k]["n"]
 
-    def genomes(self, rep=0, patch=0):
-        n = self._n_of(rep, patch)
+    def genomes(self, rep=0, patch=0, species=0):
+        n = self._n_of(rep, patch, species)
         W = self.W[rep]
         out = np.zeros(max(n, 1) * 2 * W, dtype=np.uint32)
         got = C.c_uint32()
-        check(self.lib.spegg_read_genomes(self._h, rep, patch, 0, _p(out, C.c_uint32), out.size, C.byref(got)))
+        check(self.lib.spegg_read_genomes(self._h, rep, patch, species, _p(out, C.c_uint32), out.size,
+                                          C.byref(got)))
         return out[: got.value * 2 * W].reshape(got.value, 2, W)
 
-    def write_genomes(self, rep, words, generation, patch=0):
+    def write_genomes(self, rep, words, generation, patch=0, species=0):
         w = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1)
         n = w.size // (2 * self.W[rep])
-        check(self.lib.spegg_write_genomes(self._h, rep, patch, 0, _p(w, C.c_uint32), n, int(generation)))
+        check(self.lib.spegg_write_genomes(self._h, rep, patch, species, _p(w, C.c_uint32), n, int(generation)))
 
-    def phenotypes(self, rep=0, patch=0):
-        n = self._n_of(rep, patch)
+    def phenotypes(self, rep=0, patch=0, species=0):
+        n = self._n_of(rep, patch, species)
         out = np.zeros(max(n, 1), dtype=np.int32)
         got = C.c_uint32()
-        check(self.lib.spegg_read_phenotypes(self._h, rep, patch, _p(out, C.c_int32), out.size, C.byref(got)))
+        check(self.lib.spegg_read_phenotypes(self._h, rep, patch, species, _p(out, C.c_int32), out.size,
+                                             C.byref(got)))
         return out[: got.value]
 
-    def survivors(self, rep=0, patch=0):
-        n = self.patch_stats(rep)[patch]["n_survivors"]
+    def ages(self, rep=0, species=0):
+        n = self._n_of(rep, 0, species)
+        out = np.zeros(max(n, 1), dtype=np.uint8)
+        got = C.c_uint32()
+        check(self.lib.spegg_read_ages(self._h, rep, species, _p(out, C.c_uint8), out.size, C.byref(got)))
+        return out[: got.value]
+
+    def intake(self, rep=0):
+        """Consumers' credited captures in the last generation, by adult index."""
+        n = self.deme_stats(rep)[1]["n_parents"]
         out = np.zeros(max(n, 1), dtype=np.uint32)
         got = C.c_uint32()
-        check(self.lib.spegg_read_survivors(self._h, rep, patch, _p(out, C.c_uint32), out.size, C.byref(got)))
+        check(self.lib.spegg_read_intake(self._h, rep, _p(out, C.c_uint32), out.size, C.byref(got)))
         return out[: got.value]
 
-    def allele_counts(self, rep=0, patch=0):
-        """Copies of allele 1 per locus over a patch's current census (uint32, L)."""
+    def survivors(self, rep=0, patch=0, species=0):
+        n = self.deme_stats(rep)[patch + species]["n_survivors"]
+        out = np.zeros(max(n, 1), dtype=np.uint32)
+        got = C.c_uint32()
+        check(self.lib.spegg_read_survivors(self._h, rep, patch, species, _p(out, C.c_uint32), out.size,
+                                            C.byref(got)))
+        return out[: got.value]
+
+    def allele_counts(self, rep=0, patch=0, species=0):
+        """Copies of allele 1 per locus over a deme's current census (uint32, L)."""
         import torch
         L = self.L[rep]
         scratch = torch.empty(L, dtype=torch.int32, device=self.workspace.device)
         out = np.zeros(L, dtype=np.uint32)
         got = C.c_uint32()
-        check(self.lib.spegg_allele_counts(self._h, rep, patch, C.c_void_p(scratch.data_ptr()), _p(out, C.c_uint32),
-                                           L, C.byref(got)))
+        check(self.lib.spegg_allele_counts(self._h, rep, patch, species, C.c_void_p(scratch.data_ptr()),
+                                           _p(out, C.c_uint32), L, C.byref(got)))
         return out
+
+    def autotune(self, generations_per_trial=2):
+        """Time the offspring kernel's shapes on real generations and keep the
+        fastest per genome length; returns {W: lanes-per-gamete cap}.  The
+        population advances by the trial generations."""
+        cap = 16
+        w = np.zeros(cap, np.uint32)
+        g = np.zeros(cap, np.uint32)
+        n = C.c_uint32()
+        check(self.lib.spegg_autotune(self._h, int(generations_per_trial), _p(w, C.c_uint32), _p(g, C.c_uint32), cap,
+                                      C.byref(n)))
+        return {int(w[k]): int(g[k]) for k in range(min(n.value, cap))}
 
     def set_graph(self, enable=True):
         """Replay generations as captured HIP graphs (default) or launch eagerly."""
@@ -323,21 +397,22 @@ class Population:
     def set_trace(self, enable=True):
         check(self.lib.spegg_set_trace(self._h, 1 if enable else 0))
 
-    def parents(self, rep=0, patch=0, with_source=False):
-        """Mother and father of each current newborn (indices into the adults
-        of the patch they came from) and, with_source, that patch."""
-        n = self._n_of(rep, patch)
+    def parents(self, rep=0, patch=0, with_source=False, species=0):
+        """Mother and father of each newborn of the last generation (indices
+        into the adults of the patch it came from) and, with_source, that
+        patch."""
+        n = self._n_of(rep, patch, species)
         mom = np.zeros(max(n, 1), dtype=np.uint32)
         dad = np.zeros(max(n, 1), dtype=np.uint32)
         src = np.zeros(max(n, 1), dtype=np.uint32)
         got = C.c_uint32()
-        check(self.lib.spegg_read_parents(self._h, rep, patch, _p(mom, C.c_uint32), _p(dad, C.c_uint32),
+        check(self.lib.spegg_read_parents(self._h, rep, patch, species, _p(mom, C.c_uint32), _p(dad, C.c_uint32),
                                           _p(src, C.c_uint32), mom.size, C.byref(got)))
         if with_source:
             return mom[: got.value], dad[: got.value], src[: got.value]
         return mom[: got.value], dad[: got.value]
 
-    def set_timing(self, kernels=("survive", "compact", "offspring")):
+    def set_timing(self, kernels=("survive", "compact", "offspring", "encounter", "carry")):
         """Bracket the named kernels with HIP events (empty: stop)."""
         mask = 0
         for k in kernels:

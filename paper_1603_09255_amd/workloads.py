@@ -92,3 +92,31 @@ def serve_trace(n_jobs=200, rate=20.0, seed=7, philox_seed=1, reps=(8, 256), gen
         rid += R
         jobs.append((float(arrivals[k]), k, descs, G))
     return jobs
+
+
+CONSUMER_RESOURCE = 2
+
+# Constants of the consumer-resource form (the paper gives none): chosen so
+# that both species persist near R ~ 1.3e5, C ~ 1.2e4 with moderate
+# fluctuations (resource logistic growth, mass-action encounters).
+CR_ECOLOGY = dict(n0_consumer=10_000, capacity_consumer=50_000, resource_trials=4, habitat=200_000, attack=0.5,
+                  match_width=4.0, encounters=20.0, conversion=0.5, resource_q0=0.55, resource_K=250_000.0,
+                  surv_resource=(0.5, 0.8, 0.8, 0.0), surv_consumer=(0.6, 0.8, 0.8, 0.0))
+
+
+def consumer_resource(n_reps=64, seed=1, n_resource=100_000, scale=1.0):
+    """Two coevolving species: resource N0 = 1e5 (capacity 2.5e5), consumer
+    N0 = 1e4 (capacity 5e4), each with L = 256 loci of unit effect, free of
+    viability selection (trait-mediated fitness is the capture of resources
+    by Gaussian phenotype matching, width 4), ages 0-3 with age-specific
+    survival, mu = 1e-5, r = 0.1; 64 replicates, 500 generations.  `scale`
+    shrinks every census, capacity and the habitat together."""
+    eco = dict(CR_ECOLOGY)
+    for k in ("n0_consumer", "capacity_consumer", "habitat"):
+        eco[k] = max(1, int(eco[k] * scale))
+    eco["resource_K"] = CR_ECOLOGY["resource_K"] * scale
+    n0 = max(1, int(n_resource * scale))
+    cap = max(n0, int(250_000 * scale))
+    return [dict(seed=seed, replicate_id=i, regime=CONSUMER_RESOURCE, n0=n0, capacity=cap, n_loci=256, mu=1e-5,
+                 r=0.1, theta=0.0, omega=0.0, K=0.0, fecundity=0.0, effects=None, ecology=eco)
+            for i in range(n_reps)], 500

@@ -8,7 +8,7 @@ import oracle
 from paper_1603_09255_amd import spegg
 
 ORACLE_KEYS = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
-               "fecundity", "effects", "n_patches", "migration")
+               "fecundity", "effects", "n_patches", "migration", "ecology")
 
 
 def say(*args):
@@ -22,28 +22,37 @@ def oracle_pop(desc):
 
 def assert_same_state(gpu, rep, orc, what, parents=False):
     """Every output of replicate rep equal to the oracle's: the replicate's
-    census, and per patch the census, genomes, phenotypes, survivors and
+    census, and per deme (patch, or species of the consumer-resource
+    regime) the census, genomes, phenotypes, ages, survivors, intake and
     (parents=True) the traced parents with their source patch."""
     sg = gpu.stats()[rep]
     so = orc.total_stats()
     assert sg == so, f"{what}: stats differ\n gpu    {sg}\n oracle {so}"
-    per = gpu.patch_stats(rep)
-    for k in range(orc.n_patches):
-        wk = f"{what}, patch {k}"
-        sok = orc.stats(k)
+    per = gpu.deme_stats(rep)
+    cr = orc.n_demes == 2 and orc.n_patches == 1
+    for k in range(orc.n_demes):
+        patch, species = (0, k) if cr else (k, 0)
+        wk = f"{what}, {'species' if cr else 'patch'} {k}"
+        sok = orc.stats(patch, species)
         assert per[k] == sok, f"{wk}: stats differ\n gpu    {per[k]}\n oracle {sok}"
-        g = gpu.genomes(rep, k)
-        o = orc.genomes(k)
+        g = gpu.genomes(rep, patch, species)
+        o = orc.genomes(patch, species)
         assert g.shape == o.shape, f"{wk}: genome shapes {g.shape} vs {o.shape}"
         if not np.array_equal(g, o):
             bad = np.argwhere(g != o)
             raise AssertionError(f"{wk}: {len(bad)} genome words differ, first at {bad[:5].tolist()}")
-        assert np.array_equal(gpu.phenotypes(rep, k), orc.phenotypes(k)), f"{wk}: phenotypes differ"
+        assert np.array_equal(gpu.phenotypes(rep, patch, species), orc.phenotypes(patch, species)), \
+            f"{wk}: phenotypes differ"
+        if cr:
+            assert np.array_equal(gpu.ages(rep, species), orc.ages(species=species)), f"{wk}: ages differ"
         if sok["generation"] > 0 and sok["n_parents"] > 0:
-            assert np.array_equal(gpu.survivors(rep, k), orc.survivors(k)), f"{wk}: survivor lists differ"
-        if parents and sok["n"] > 0:
-            gm, gd, gs = gpu.parents(rep, k, with_source=True)
-            om, od, os_ = orc.parents(k, with_source=True)
+            assert np.array_equal(gpu.survivors(rep, patch, species), orc.survivors(patch, species)), \
+                f"{wk}: survivor lists differ"
+            if cr and species == 1:
+                assert np.array_equal(gpu.intake(rep), orc.intake()), f"{wk}: intake differs"
+        if parents and sok["generation"] > 0 and orc.newborns(patch, species) > 0:
+            gm, gd, gs = gpu.parents(rep, patch, with_source=True, species=species)
+            om, od, os_ = orc.parents(patch, with_source=True, species=species)
             assert np.array_equal(gs, os_), f"{wk}: source patches differ"
             assert np.array_equal(gm, om) and np.array_equal(gd, od), f"{wk}: parents differ"
 

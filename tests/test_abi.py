@@ -86,6 +86,18 @@ def base_desc(**kw):
     (dict(n_patches=1025), "n_patches"),
     (dict(n_patches=2, migration=1.5), "migration"),
     (dict(n_patches=2, regime=1, fecundity=2.0, capacity=200), "Wright-Fisher"),
+    (dict(regime=2), "ecology"),
+    (dict(ecology=dict(n0_consumer=1, capacity_consumer=1)), "one-species"),
+    (dict(regime=2, ecology=dict(n0_consumer=5, capacity_consumer=4, resource_trials=4, match_width=1.0,
+                                 resource_K=10.0)), "consumer census"),
+    (dict(regime=2, ecology=dict(n0_consumer=1, capacity_consumer=4, resource_trials=0, match_width=1.0,
+                                 resource_K=10.0)), "resource_trials"),
+    (dict(regime=2, ecology=dict(n0_consumer=1, capacity_consumer=4, resource_trials=4, match_width=0.0,
+                                 resource_K=10.0)), "ecology rates"),
+    (dict(regime=2, ecology=dict(n0_consumer=1, capacity_consumer=4, resource_trials=4, match_width=1.0,
+                                 resource_K=10.0, surv_consumer=(1, 1, 1.5, 0))), "age class 2"),
+    (dict(regime=2, n_patches=2, ecology=dict(n0_consumer=1, capacity_consumer=4, resource_trials=4,
+                                              match_width=1.0, resource_K=10.0)), "Wright-Fisher"),
 ])
 def test_invalid_descriptors_are_rejected(bad, needle):
     with pytest.raises(spegg.SpeggError) as ei:

@@ -109,7 +109,7 @@ def test_patches_must_share_a_generation():
     assert ei.value.status == spegg.E_STATE
     pop.write_genomes(0, w, 7, patch=0)
     pop.step(1)
-    assert [s["generation"] for s in pop.patch_stats(0)] == [8, 8]
+    assert [s["generation"] for s in pop.deme_stats(0)] == [8, 8]
     with pytest.raises(spegg.SpeggError) as ei:
         pop.genomes(0, patch=2)
     assert ei.value.status == spegg.E_INVALID

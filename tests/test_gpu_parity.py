@@ -160,8 +160,15 @@ def test_kernel_timing_counts_launches():
     pop.set_timing()
     pop.step(5)
     t = pop.kernel_times()
-    assert all(t[k][1] == 5 for k in t)
-    assert all(t[k][0] > 0 for k in t)
+    one_species = ("survive", "compact", "offspring")
+    assert all(t[k][1] == 5 and t[k][0] > 0 for k in one_species)
+    assert t["encounter"][1] == 0 and t["carry"][1] == 0  # consumer-resource kernels only
+    eco = dict(workloads.CR_ECOLOGY, n0_consumer=50, capacity_consumer=200, habitat=0)
+    cr = spegg.Population([dict(seed=3, regime=2, n0=300, capacity=900, n_loci=64, ecology=eco)])
+    cr.set_timing()
+    cr.step(4)
+    assert all(v[1] == 4 for v in cr.kernel_times().values())
+    cr.close()
     pop.set_timing(["offspring"])
     pop.step(3)
     t = pop.kernel_times()
@@ -216,3 +223,24 @@ def test_allele_counts_match_oracle(L, n0):
     expect = orc.alleles().astype(np.int64).sum(axis=(0, 1))
     assert np.array_equal(got.astype(np.int64), expect)
     assert got.max() <= 2 * n0
+
+
+def test_autotune_changes_no_result():
+    # mixed genome lengths: each W gets its own shape; the tuned run must end
+    # where the untuned one (and the oracle) ends
+    reps = [dict(seed=3, replicate_id=40 + i, n0=300, capacity=300, n_loci=L, r=r, mu=1e-3, omega=8.0)
+            for i, (L, r) in enumerate([(1024, 0.01), (256, 0.3), (64, 0.5), (100, 0.05)])]
+    tuned = spegg.Population(reps)
+    chosen = tuned.autotune(generations_per_trial=2)
+    assert sorted(chosen) == [2, 4, 8, 32]
+    done = tuned.stats()[0]["generation"]
+    assert done >= 2 * len(chosen)
+    tuned.step(3)
+    plain = spegg.Population(reps)
+    plain.step(done + 3)
+    for i, d in enumerate(reps):
+        assert tuned.stats()[i] == plain.stats()[i]
+        assert np.array_equal(tuned.genomes(i), plain.genomes(i))
+        orc = oracle_pop(d)
+        orc.step(done + 3)
+        assert_same_state(tuned, i, orc, f"tuned replicate {i}")
