@@ -128,7 +128,9 @@ def main():
     log(f"bench: creating population N0={desc['n0']} L={L}")
     pop = spegg.Population([desc])
     torch.cuda.synchronize()
-    log(f"bench: warmup {args.warmup} generations")
+    # the autotuner's trial generations are ordinary generations: part of the warm-up
+    tuned = pop.autotune(generations_per_trial=2)
+    log(f"bench: autotuned lanes per gamete by W: {tuned}; warmup {args.warmup} generations")
     pop.step(args.warmup)
     torch.cuda.synchronize()
 
@@ -188,6 +190,7 @@ def main():
             "n_loci": L,
             "generations_timed": args.steps,
             "mean_census": updates / args.steps / L,
+            "offspring_lanes_per_gamete_by_W": {str(k): v for k, v in tuned.items()},
         },
         "roofline": {
             "bound": "hbm",
@@ -224,6 +227,8 @@ def bench_batched(args):
     log(f"bench: creating batch of {len(reps)} replicates")
     pop = spegg.Population(reps)
     torch.cuda.synchronize()
+    tuned = pop.autotune(generations_per_trial=2)
+    log(f"bench: autotuned lanes per gamete by W: {tuned}")
     pop.step(args.warmup)
     torch.cuda.synchronize()
     s0 = sum(r["updates"] for r in pop.stats())
@@ -276,7 +281,8 @@ def bench_batched(args):
                                "selection width ~ U[2,16], all advanced together",
                    "replicates": len(reps), "generations_timed": args.steps,
                    "plain_loop_updates_per_s": plain_rate, "plain_loop_sample": len(sample),
-                   "speedup_vs_plain_loop": value / plain_rate},
+                   "speedup_vs_plain_loop": value / plain_rate,
+                   "offspring_lanes_per_gamete_by_W": {str(k): v for k, v in tuned.items()}},
         "roofline": {"bound": "hbm", "kernel": "offspring", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_update": bpu, "launches": off_n, "generations": gens_b},
@@ -296,6 +302,7 @@ def bench_ecology(args):
     torch.cuda.set_device(0)
     log(f"bench: creating {len(reps)} consumer-resource replicates")
     pop = spegg.Population(reps)
+    tuned = pop.autotune(generations_per_trial=2)
     pop.step(args.warmup)
     torch.cuda.synchronize()
     s0 = sum(r["updates"] for r in pop.stats())
@@ -331,7 +338,8 @@ def bench_ecology(args):
                                "Poisson in intake",
                    "replicates": len(reps), "generations_timed": args.steps,
                    "replicate0_resource_n": per[0]["n"], "replicate0_consumer_n": per[1]["n"],
-                   "replicate0_captures": per[1]["captures"]},
+                   "replicate0_captures": per[1]["captures"],
+                   "offspring_lanes_per_gamete_by_W": {str(k): v for k, v in tuned.items()}},
         "roofline": {"bound": "hbm", "kernel": "offspring", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_update": bpu,
                      "launches": off_n, "generations": gens_b},

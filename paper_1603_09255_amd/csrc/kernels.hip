@@ -188,6 +188,43 @@ __device__ __forceinline__ uint32_t current_pair(const RepState &st) {
     return (int32_t)(st.t[1] - st.t[0]) > 0 ? 1u : 0u;
 }
 
+// IT consecutive 16-bit fates (IT = 1, 2 or 4), one access.
+template <int IT>
+__device__ __forceinline__ void store_fates(uint16_t *p, const uint32_t *f) {
+    if constexpr (IT == 4) {
+        *reinterpret_cast<uint2 *>(p) = make_uint2(f[0] | (f[1] << 16), f[2] | (f[3] << 16));
+    } else if constexpr (IT == 2) {
+        *reinterpret_cast<uint32_t *>(p) = f[0] | (f[1] << 16);
+    } else {
+        *p = (uint16_t)f[0];
+    }
+}
+
+template <int IT>
+__device__ __forceinline__ void load_fates(const uint16_t *p, uint32_t *f) {
+    if constexpr (IT == 4) {
+        const uint2 w = *reinterpret_cast<const uint2 *>(p);
+        f[0] = w.x & 0xFFFFu;
+        f[1] = w.x >> 16;
+        f[2] = w.y & 0xFFFFu;
+        f[3] = w.y >> 16;
+    } else if constexpr (IT == 2) {
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(p);
+        f[0] = w & 0xFFFFu;
+        f[1] = w >> 16;
+    } else {
+        f[0] = *p;
+    }
+}
+
+// IT consecutive 8-bit age classes, packed into one word.
+template <int IT>
+__device__ __forceinline__ uint32_t load_ages(const uint8_t *p) {
+    if constexpr (IT == 4) return *reinterpret_cast<const uint32_t *>(p);
+    else if constexpr (IT == 2) return *reinterpret_cast<const uint16_t *>(p);
+    else return *p;
+}
+
 // Words of one stream of one individual read in order, one Philox block
 // per four words.
 struct SeqWords {
@@ -337,7 +374,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
 #pragma unroll
     for (uint32_t q = 0; q < IT; ++q) v[q] = (d.vtab && i0 + q < n) ? d.vtab[(int32_t)zw.v[q] - d.zmin] : 1.0;
     uint32_t age4 = 0;
-    if (cr) age4 = *reinterpret_cast<const uint32_t *>(d.age[t & 1u] + i0);
+    if (cr) age4 = load_ages<IT>(d.age[t & 1u] + i0);
     uint32_t fate[IT], a_loc = 0, k_loc = 0, near = 0, in_loc = 0;
     uint64_t thr_sum = 0;
 #pragma unroll
@@ -384,9 +421,9 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
             }
         }
     }
-    // fates of the thread's adults, one 8-byte store
+    // fates of the thread's adults, one store
     uint16_t *fp = d.fate + i0;
-    *reinterpret_cast<uint2 *>(fp) = make_uint2(fate[0] | (fate[1] << 16), fate[2] | (fate[3] << 16));
+    store_fates<IT>(fp, fate);
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t wa = wave_sum<uint32_t>(a_loc), wk = wave_sum<uint32_t>(k_loc), wn = wave_sum<uint32_t>(near);
     const uint32_t wi = wave_sum<uint32_t>(in_loc);
@@ -532,8 +569,8 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
 
     // survivor and slot ranks of the thread's adults, ascending order
     const uint32_t i0 = tile.start + threadIdx.x * IT;
-    const uint2 fw = *reinterpret_cast<const uint2 *>(d.fate + i0);
-    uint32_t fate[IT] = {fw.x & 0xFFFFu, fw.x >> 16, fw.y & 0xFFFFu, fw.y >> 16};
+    uint32_t fate[IT];
+    load_fates<IT>(d.fate + i0, fate);
     uint32_t a_loc = 0, k_loc = 0;
 #pragma unroll
     for (uint32_t q = 0; q < IT; ++q) {
@@ -577,7 +614,8 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
                                                            int trace) {
     constexpr uint32_t TPO = 2 * G;
     constexpr uint32_t TEAMS = kBlock / TPO;
-    constexpr uint32_t ITERS = TEAMS >= 16 ? 1 : 16 / TEAMS;
+    constexpr uint32_t KF = kOffspringInFlight;  // newborns of a team in flight at once
+    constexpr uint32_t ITERS = (TEAMS >= 16 ? 1 : 16 / TEAMS) * KF;
     constexpr uint32_t OPT = TEAMS * ITERS;
     constexpr uint32_t CH = G * V;  // words of one gamete per chunk
     constexpr int NREG = NCH > 0 ? NCH : 1;
@@ -634,10 +672,16 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
         int64_t my_z = 0;
         uint64_t my_z2 = 0;
 
-        for (uint32_t it = 0; it < ITERS; ++it) {
-            const uint32_t j = start + it * TEAMS + team;
-            if (j >= nn) continue;  // uniform over the team
-
+        // Front of a newborn: its draws, parents and the parents' haplotype
+        // words (loads in flight); KF newborns of a team get their fronts
+        // before the first is finished, so their gathers overlap.
+        struct Front {
+            uint32_t j, mom, dad, src_patch, phase, xk;
+            const uint32_t *src;
+            uint32_t *dst;
+            Words<V> h0[NREG], h1[NREG];
+        };
+        auto front = [&](uint32_t j, Front &f) {
             Words4 sd[SR];
 #pragma unroll
             for (uint32_t r = 0; r < SR; ++r) {
@@ -677,28 +721,36 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             // correct index and keeps every gather inside the buffer
             mom = mom < nprev ? mom : nprev - 1u;
             dad = dad < nprev ? dad : nprev - 1u;
-            const uint32_t *__restrict__ src = sd_src.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
-            uint32_t *__restrict__ dst = d.genome[cur ^ 1u] + (size_t)(base + j) * 2u * W + (size_t)half * W;
-            const uint32_t rs = kStRecomb + half, ms = kStMutate + half;
+            f.j = j;
+            f.mom = mom;
+            f.dad = dad;
+            f.src_patch = sd_src.patch;
+            f.src = sd_src.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
+            f.dst = d.genome[cur ^ 1u] + (size_t)(base + j) * 2u * W + (size_t)half * W;
             const uint32_t phase_m = draw(1, 0), phase_p = draw(2, 0);
             const uint32_t xk_m = draw(3, 0), xk_p = draw(4, 0);
-
+            f.phase = (half ? phase_p : phase_m) & 1u;
+            f.xk = half ? xk_p : xk_m;
             // the parent's haplotypes (all chunks, or the first), in flight
             // while the crossover mask is drawn
-            Words<V> h0[NREG], h1[NREG];
 #pragma unroll
             for (int c = 0; c < NREG; ++c) {
                 const uint32_t w0 = (uint32_t)c * CH + gl * V;
                 if (w0 < W) {
-                    h0[c] = load_words<V>(src + w0);
-                    h1[c] = load_words<V>(src + W + w0);
+                    f.h0[c] = load_words<V>(f.src + w0);
+                    f.h1[c] = load_words<V>(f.src + W + w0);
                 }
             }
-
+        };
+        auto finish = [&](Front &f) {
+            const uint32_t j = f.j;
+            const uint32_t *__restrict__ src = f.src;
+            uint32_t *__restrict__ dst = f.dst;
+            const uint32_t rs = kStRecomb + half, ms = kStMutate + half;
+            const uint32_t phase = f.phase;
             // B1: crossover toggles.  Boundary b (between loci b-1 and b)
             // toggles the source haplotype from locus b on; bit 0 of word 0
             // holds the phase (which haplotype locus 0 copies).
-            const uint32_t phase = (half ? phase_p : phase_m) & 1u;
             if (mode == kModeSkip) {
                 for (uint32_t w = gl * V; w < W; w += CH)
 #pragma unroll
@@ -737,7 +789,7 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             }
 
             // B2: mutation, K ~ Binomial(L, mu) distinct loci flipped
-            const uint32_t xk = half ? xk_p : xk_m;
+            const uint32_t xk = f.xk;
             const uint32_t K = (uint64_t)xk < binom0 ? 0u : table_draw(d.binom, d.binom_len, xk);
             if (K > 0) {
                 for (uint32_t w = gl * V; w < W; w += CH)
@@ -814,10 +866,10 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             };
             if constexpr (NCH > 0) {
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) chunk((uint32_t)c, h0[c], h1[c]);
+                for (int c = 0; c < NCH; ++c) chunk((uint32_t)c, f.h0[c], f.h1[c]);
             } else {
                 const uint32_t nch = (W + CH - 1) / CH;
-                chunk(0, h0[0], h1[0]);
+                chunk(0, f.h0[0], f.h1[0]);
                 for (uint32_t c = 1; c < nch; ++c) {
                     const uint32_t w0 = c * CH + gl * V;
                     Words<V> a{}, b{};
@@ -840,10 +892,24 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
                 my_z += z;
                 my_z2 += (uint64_t)((int64_t)z * (int64_t)z);
                 if (trace) {
-                    d.mom[j] = mom;
-                    d.dad[j] = dad;
-                    if (d.mig_T != 0) d.src[j] = sd_src.patch;  // the buffer exists with migration only
+                    d.mom[j] = f.mom;
+                    d.dad[j] = f.dad;
+                    if (d.mig_T != 0) d.src[j] = f.src_patch;  // the buffer exists with migration only
                 }
+            }
+        };
+
+        for (uint32_t it = 0; it < ITERS; it += KF) {
+            Front fr[KF];
+#pragma unroll
+            for (uint32_t k = 0; k < KF; ++k) {
+                const uint32_t j = start + (it + k) * TEAMS + team;
+                if (j < nn) front(j, fr[k]);  // uniform over the team
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < KF; ++k) {
+                const uint32_t j = start + (it + k) * TEAMS + team;
+                if (j < nn) finish(fr[k]);
             }
         }
         // census sums of the tile, folded later by the census kernel
@@ -920,31 +986,28 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
 
 // ---------------------------------------------------------------- consumer-resource
 
-// One block per tile of kSurvTile consumers, 4 per thread: every capture
-// offers its key (consumer, encounter) to the captured resource, which
-// keeps the lowest.  The keys were reset to ~0 when the resource census was
-// written.
+// kSurvItems blocks per tile of kSurvTile consumers, one consumer per
+// thread: every capture offers its key (consumer, encounter) to the
+// captured resource, which keeps the lowest.  The keys were reset to ~0
+// when the resource census was written.
 __global__ void __launch_bounds__(kBlock) encounter_kernel(const RepDesc *__restrict__ descs,
                                                            const RepState *__restrict__ states,
                                                            const SurvTile *__restrict__ tiles) {
-    const SurvTile tile = tiles[blockIdx.x];
+    const SurvTile tile = tiles[blockIdx.x / kSurvItems];
+    const uint32_t i = tile.start + (blockIdx.x % kSurvItems) * kBlock + threadIdx.x;
     const RepDesc &c = descs[tile.rep];
     const RepState &cs = states[tile.rep];
     const uint32_t par = current_pair(cs);
     const uint32_t t = cs.t[par], n = cs.n[par];
-    if (tile.start >= n) return;
+    if (i >= n) return;
     const RepDesc &r = descs[c.partner];
     const RepState &rs = states[c.partner];
     const uint32_t NR = rs.n[current_pair(rs)];
     const int32_t *zr = r.z[t & 1u];
     const int32_t *zc = c.z[t & 1u];
     unsigned long long *won = reinterpret_cast<unsigned long long *>(r.won);
-    for (uint32_t q = 0; q < kSurvItems; ++q) {
-        const uint32_t i = tile.start + threadIdx.x * kSurvItems + q;
-        if (i >= n) break;
-        consumer_captures(c, i, t, zc[i], zr, NR,
-                          [&](uint32_t e, uint32_t tgt) { atomicMin(won + tgt, (unsigned long long)capture_key(i, e)); });
-    }
+    consumer_captures(c, i, t, zc[i], zr, NR,
+                      [&](uint32_t e, uint32_t tgt) { atomicMin(won + tgt, (unsigned long long)capture_key(i, e)); });
 }
 
 // One block per survival tile of a consumer-resource deme: survivors
@@ -963,11 +1026,21 @@ __global__ void __launch_bounds__(kBlock) carry_kernel(const RepDesc *__restrict
     const uint32_t cur = (st.t[newest] - 1u) & 1u;
     const uint32_t cnt = nc - tile.start < (uint32_t)kSurvTile ? nc - tile.start : (uint32_t)kSurvTile;
     const uint32_t per = 2u * d.W;
-    const uint32_t *__restrict__ src = d.genome[cur];
-    uint32_t *__restrict__ dst = d.genome[cur ^ 1u];
-    for (uint32_t idx = threadIdx.x; idx < cnt * per; idx += kBlock) {
-        const uint32_t k = tile.start + idx / per, w = idx % per;
-        dst[(size_t)k * per + w] = src[(size_t)d.S[k] * per + w];
+    if ((per & 3u) == 0) {  // 16-byte copies
+        const uint32_t per4 = per / 4u;
+        const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(d.genome[cur]);
+        uint4 *__restrict__ dst = reinterpret_cast<uint4 *>(d.genome[cur ^ 1u]);
+        for (uint32_t idx = threadIdx.x; idx < cnt * per4; idx += kBlock) {
+            const uint32_t k = tile.start + idx / per4, w = idx % per4;
+            dst[(size_t)k * per4 + w] = src[(size_t)d.S[k] * per4 + w];
+        }
+    } else {
+        const uint32_t *__restrict__ src = d.genome[cur];
+        uint32_t *__restrict__ dst = d.genome[cur ^ 1u];
+        for (uint32_t idx = threadIdx.x; idx < cnt * per; idx += kBlock) {
+            const uint32_t k = tile.start + idx / per, w = idx % per;
+            dst[(size_t)k * per + w] = src[(size_t)d.S[k] * per + w];
+        }
     }
     for (uint32_t idx = threadIdx.x; idx < cnt; idx += kBlock) {
         const uint32_t k = tile.start + idx, from = d.S[k];
@@ -1108,7 +1181,7 @@ hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *
 hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
                             hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(encounter_kernel, dim3(ntiles), dim3(kBlock), 0, s, descs, states, tiles);
+    hipLaunchKernelGGL(encounter_kernel, dim3(ntiles * kSurvItems), dim3(kBlock), 0, s, descs, states, tiles);
     return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ enum Mode : uint32_t { kModeRaw = 0, kModeZero = 1, kModeSkip = 2, kModeLazy = 3
 constexpr double kSkipBelow = 0.17;  // r < 0.17: geometric gaps; above: bit-serial Bernoulli
 
 constexpr int kBlock = 256;          // threads per block in every kernel
-constexpr int kSurvItems = 4;        // consecutive adults per thread in survive and compact
+constexpr int kSurvItems = 1;        // consecutive adults per thread in survive and compact (1, 2 or 4)
 constexpr int kSurvTile = kBlock * kSurvItems;  // adults per survival tile
 constexpr int kPoissonTableCap = 1024;  // longest Poisson threshold table
 constexpr int kCensusSlots = 16;     // slots of the census sums (init and write_genomes spread atomics)
@@ -147,7 +147,7 @@ struct Partial {
 struct OffShape {
     int g, vpl, nch;
 };
-constexpr int kDefaultGCap = 8;
+constexpr int kDefaultGCap = 4;
 inline OffShape offspring_shape(uint32_t W, int gcap = kDefaultGCap) {
     OffShape s;
     s.vpl = (W % 4 == 0) ? 4 : (W % 2 == 0) ? 2 : 1;
@@ -167,9 +167,12 @@ inline OffShape offspring_shape(uint32_t W, int gcap = kDefaultGCap) {
     }
     return s;
 }
+// Newborns of one team whose parents' words are gathered before the first
+// of them is finished (a latency-hiding knob; results do not depend on it).
+constexpr uint32_t kOffspringInFlight = 1;
 inline int offspring_per_tile(int g) {
     const int teams = kBlock / (2 * g);
-    return teams >= 16 ? teams : 16;
+    return (teams >= 16 ? teams : 16) * (int)kOffspringInFlight;
 }
 inline size_t offspring_lds_bytes(int g, uint32_t W) {
     // per team and gamete: crossover bitmap and flip bitmap, W words each
@@ -207,7 +210,7 @@ hipError_t launch_survive(const SelArgs &a);
 hipError_t launch_compact(const SelArgs &a);
 hipError_t launch_offspring(OffShape shape, const OffArgs &a);
 // Consumer-resource regime: encounters and captures of the consumers in
-// tiles (one block per tile of kSurvTile consumers).
+// tiles (kSurvItems blocks per tile of kSurvTile consumers).
 hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
                             hipStream_t s);
 // Consumer-resource regime: survivors into the next census (one block per
