@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # FETCH_SIZE and WRITE_SIZE counters scaled by a device copy of known size
 # (profiles/offspring_plain_scale_hbm_traffic.md), valid for the kernel
 # source with this SHA-256 prefix only.
-MEASURED_TRAFFIC = {"kernels_sha256_16": "a91e02b96d000174", "bytes_per_update": 0.5877}
+MEASURED_TRAFFIC = {"kernels_sha256_16": "ebbb23ba3cf4c047", "bytes_per_update": 0.5874}
 
 
 def measured_traffic_per_update():

@@ -663,7 +663,9 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
         const bool unit = d.unit_effects != 0;
         const uint64_t binom0 = d.binom0;  // most gametes carry no mutation
         const Rng rng{d.key0, d.key1, d.c3};
-        if (!unit) {
+        // effect planes into LDS: once per block when every tile is of one
+        // deme, else for every tile
+        if (!unit && (single_deme < 0 || ti == blockIdx.x)) {
             for (uint32_t q = threadIdx.x; q < 6u * W; q += kBlock) planes[q] = d.planes[q];
             __syncthreads();
         }
