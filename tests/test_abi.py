@@ -35,7 +35,8 @@ def test_library_exports_every_declared_function(lib):
     assert len(names) >= 15
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.spegg_abi_version() == 2
+    declared = int(re.search(r"#define SPEGG_ABI_VERSION (\d+)", open(HEADER).read()).group(1))
+    assert lib.spegg_abi_version() == declared
 
 
 @pytest.mark.parametrize("lam", [0.0, 0.5, 2.2, 10.0, 30.0, 200.0])
