@@ -31,17 +31,29 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 # HBM bytes per genotype-locus update of the offspring kernel, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE counters scaled by a device copy of known size
-# (profiles/offspring_plain_scale_hbm_traffic.md), valid for the kernel
-# source with this SHA-256 prefix only.
-MEASURED_TRAFFIC = {"kernels_sha256_16": "ebbb23ba3cf4c047", "bytes_per_update": 0.5874}
+# (profiles/offspring_plain_scale_hbm_traffic.md), valid only for the device
+# sources with this SHA-256 prefix and the offspring shape it was taken with
+# (lanes-per-gamete cap by genome words W).
+MEASURED_TRAFFIC = {"device_sources_sha256_16": "3910a38a7b9f5f0a", "lanes_per_gamete_by_W": {32: 4},
+                    "bytes_per_update": 0.7069}
+DEVICE_SOURCES = ("kernels.hip", "philox.h", "spegg_internal.h")
 
 
-def measured_traffic_per_update():
+def device_sources_sha():
     import hashlib
-    src = os.path.join(ROOT, "paper_1603_09255_amd", "csrc", "kernels.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    return MEASURED_TRAFFIC["bytes_per_update"] if sha == MEASURED_TRAFFIC["kernels_sha256_16"] else None
+    h = hashlib.sha256()
+    for name in DEVICE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1603_09255_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic_per_update(tuned):
+    if device_sources_sha() != MEASURED_TRAFFIC["device_sources_sha256_16"]:
+        return None
+    if dict(tuned) != MEASURED_TRAFFIC["lanes_per_gamete_by_W"]:
+        return None
+    return MEASURED_TRAFFIC["bytes_per_update"]
 
 
 def log(*a):
@@ -54,6 +66,18 @@ def bytes_per_update(L):
     # individual over L updates), plus about 20 bytes of per-individual
     # metadata (phenotype read and write, survivor index, two parent indices)
     return 0.5 + 20.0 / L
+
+
+def choose_shapes(pop, descs, gcap, generations_per_trial):
+    """The offspring kernel's lanes-per-gamete cap per genome length W: timed
+    by the autotuner, or pinned (gcap > 0: profiled runs, where a profiler's
+    per-dispatch gaps would swamp the tuner's clock)."""
+    if gcap <= 0:
+        return pop.autotune(generations_per_trial=generations_per_trial)
+    Ws = sorted({(d["n_loci"] + 31) // 32 for d in descs})
+    for W in Ws:
+        pop.set_offspring_cap(W, gcap)
+    return {W: gcap for W in Ws}
 
 
 def cpu_baseline(desc, budget_s):
@@ -101,6 +125,8 @@ def main():
     ap.add_argument("--quantum", type=int, default=8, help="serve: generations per scheduling step")
     ap.add_argument("--full-jobs", action="store_true",
                     help="serve: jobs at their full size (reps U{8..256}, gens U{100..2000}); hours of GPU time")
+    ap.add_argument("--gcap", type=int, default=0,
+                    help="pin the offspring kernel's lanes-per-gamete cap instead of autotuning (0: autotune)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only copy a device buffer of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -129,8 +155,8 @@ def main():
     pop = spegg.Population([desc])
     torch.cuda.synchronize()
     # the autotuner's trial generations are ordinary generations: part of the warm-up
-    tuned = pop.autotune(generations_per_trial=2)
-    log(f"bench: autotuned lanes per gamete by W: {tuned}; warmup {args.warmup} generations")
+    tuned = choose_shapes(pop, [desc], args.gcap, 4)
+    log(f"bench: lanes per gamete by W: {tuned}; warmup {args.warmup} generations")
     pop.step(args.warmup)
     torch.cuda.synchronize()
 
@@ -199,8 +225,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (None if measured_traffic_per_update() is None else
-                        measured_traffic_per_update() * updates_b / max(off_n, 1)),
+            "traffic": (None if measured_traffic_per_update(tuned) is None else
+                        measured_traffic_per_update(tuned) * updates_b / max(off_n, 1)),
             "traffic_unit": "HBM bytes per launch (rocprofv3 counters, scaled)",
             "bytes_per_update": bytes_per_update(L),
             "avg_launch_us": avg_launch_s * 1e6,
@@ -227,8 +253,8 @@ def bench_batched(args):
     log(f"bench: creating batch of {len(reps)} replicates")
     pop = spegg.Population(reps)
     torch.cuda.synchronize()
-    tuned = pop.autotune(generations_per_trial=2)
-    log(f"bench: autotuned lanes per gamete by W: {tuned}")
+    tuned = choose_shapes(pop, reps, args.gcap, 2)
+    log(f"bench: lanes per gamete by W: {tuned}")
     pop.step(args.warmup)
     torch.cuda.synchronize()
     s0 = sum(r["updates"] for r in pop.stats())
@@ -302,7 +328,7 @@ def bench_ecology(args):
     torch.cuda.set_device(0)
     log(f"bench: creating {len(reps)} consumer-resource replicates")
     pop = spegg.Population(reps)
-    tuned = pop.autotune(generations_per_trial=2)
+    tuned = choose_shapes(pop, reps, args.gcap, 2)
     pop.step(args.warmup)
     torch.cuda.synchronize()
     s0 = sum(r["updates"] for r in pop.stats())

@@ -277,15 +277,27 @@ spegg_status spegg_kernel_times(spegg_pop *pop, double *ms, uint64_t *launches, 
 
 /* Pick the offspring kernel's shape (lanes per gamete, words per lane,
  * chunks held in registers) for each genome length W in the population by
- * timing: for each W in turn, every distinct shape runs
- * generations_per_trial real generations with its offspring launches timed
- * by HIP events, and the one with the least time per genotype-locus update
- * stays.  Shapes change no result, so the trial generations are ordinary
- * generations of the simulation (the population advances by their total).
+ * timing: for each W in turn, every distinct shape first runs
+ * generations_per_trial untimed generations (loading its code and capturing
+ * the graphs that replay it), then generations_per_trial generations
+ * bracketed by two HIP events on the population's stream, run as
+ * spegg_step_generations runs them; the shapes take turns over two rounds,
+ * each keeps its least time per genotype-locus update, and the least of
+ * those stays.  Shapes change no result, so the trial generations are
+ * ordinary generations of the simulation (the population advances by
+ * 4 x generations_per_trial per shape and W).  The caller's kernel timing
+ * (spegg_set_timing) is suspended meanwhile and its pending events kept.
  * Reports the distinct W (ascending) and each one's chosen cap on lanes per
  * gamete (arrays of cap entries; *n_out = number of W).  Waits. */
 spegg_status spegg_autotune(spegg_pop *pop, uint32_t generations_per_trial, uint32_t *w_out, uint32_t *gcap_out,
                             uint32_t cap, uint32_t *n_out);
+
+/* Set the offspring kernel's cap on lanes per gamete for the replicates of
+ * W genome words (gcap a power of two in 1..32), as spegg_autotune would
+ * choose it, without timing: e.g. to reuse a tuning found earlier.  Changes
+ * no result.  SPEGG_E_INVALID for another gcap or a W no replicate has.
+ * Waits. */
+spegg_status spegg_set_offspring_cap(spegg_pop *pop, uint32_t W, uint32_t gcap);
 
 /* Release the handle (not the caller's memory or stream).  NULL is a no-op. */
 void spegg_pop_destroy(spegg_pop *pop);

@@ -96,35 +96,65 @@ __device__ __forceinline__ double density_factor(const RepDesc &d, uint32_t n) {
     return 1.0 / (1.0 + (d.lambda - 1.0) * (double)n / d.K);
 }
 
-// Additive contribution sum_l e_l b_l of one haplotype word; P holds the six
-// effect bit-planes (+1, +2, +4, -1, -2, -4), W words each.
-__device__ __forceinline__ int32_t word_effect(bool unit, const uint32_t *P, uint32_t W, uint32_t w, uint32_t g) {
-    if (unit) return (int32_t)__popc(g);
-    return (int32_t)__popc(g & P[w]) + 2 * (int32_t)__popc(g & P[W + w]) + 4 * (int32_t)__popc(g & P[2 * W + w]) -
-           (int32_t)__popc(g & P[3 * W + w]) - 2 * (int32_t)__popc(g & P[4 * W + w]) -
-           4 * (int32_t)__popc(g & P[5 * W + w]);
-}
+// Additive effect sum_l e_l b_l, accumulated word by word.  With the
+// offset effects e_l + 4 in [0, 8] held as four bit-planes Q_k (bit k of
+// e_l + 4, W words each), sum_l e_l b_l = sum_k 2^k popc(g & Q_k) - 4 popc(g):
+// per word four and-popcount pairs and one popcount into counters; the
+// weights are applied once (unit effects: the popcount alone).
+struct EffectSum {
+    uint32_t ones = 0, q[4] = {0, 0, 0, 0};
+    __device__ __forceinline__ void add(bool unit, const uint32_t *Q, uint32_t W, uint32_t w, uint32_t g) {
+        ones += __popc(g);
+        if (!unit) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[k] += __popc(g & Q[k * W + w]);
+        }
+    }
+    __device__ __forceinline__ int32_t value(bool unit) const {
+        if (unit) return (int32_t)ones;
+        return (int32_t)(q[0] + 2u * q[1] + 4u * q[2] + 8u * q[3]) - 4 * (int32_t)ones;
+    }
+};
 
 template <int V>
 struct Words {
     uint32_t v[V];
 };
 
+// Device memory reached through pointers read from descriptors is accessed
+// through the global address space, so loads and stores compile to global
+// instructions: flat ones also count against the LDS wait counter, and every
+// cross-lane or LDS wait would then wait for them too.
+#define SPEGG_GLOBAL __attribute__((address_space(1)))
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T gload(const T *p) {
+    return *(const SPEGG_GLOBAL T *)p;
+}
+
+template <typename T>
+__device__ __forceinline__ void gstore(T *p, const T &v) {
+    *(SPEGG_GLOBAL T *)p = v;
+}
+
 template <int V>
 __device__ __forceinline__ Words<V> load_words(const uint32_t *p) {
     Words<V> w;
     if constexpr (V == 4) {
-        const uint4 q = *reinterpret_cast<const uint4 *>(p);
+        const u32x4 q = gload(reinterpret_cast<const u32x4 *>(p));
         w.v[0] = q.x;
         w.v[1] = q.y;
         w.v[2] = q.z;
         w.v[3] = q.w;
     } else if constexpr (V == 2) {
-        const uint2 q = *reinterpret_cast<const uint2 *>(p);
+        const u32x2 q = gload(reinterpret_cast<const u32x2 *>(p));
         w.v[0] = q.x;
         w.v[1] = q.y;
     } else {
-        w.v[0] = *p;
+        w.v[0] = gload(p);
     }
     return w;
 }
@@ -132,28 +162,39 @@ __device__ __forceinline__ Words<V> load_words(const uint32_t *p) {
 template <int V>
 __device__ __forceinline__ void store_words(uint32_t *p, const Words<V> &w) {
     if constexpr (V == 4) {
-        *reinterpret_cast<uint4 *>(p) = make_uint4(w.v[0], w.v[1], w.v[2], w.v[3]);
+        gstore(reinterpret_cast<u32x4 *>(p), u32x4{w.v[0], w.v[1], w.v[2], w.v[3]});
     } else if constexpr (V == 2) {
-        *reinterpret_cast<uint2 *>(p) = make_uint2(w.v[0], w.v[1]);
+        gstore(reinterpret_cast<u32x2 *>(p), u32x2{w.v[0], w.v[1]});
     } else {
-        *p = w.v[0];
+        gstore(p, w.v[0]);
     }
 }
 
+// Smallest k with x < T[k] in a table in device memory (global loads).
+__device__ __forceinline__ uint32_t table_draw_global(const uint64_t *__restrict__ T, uint32_t len, uint32_t x) {
+    if ((uint64_t)x < gload(T)) return 0;
+    uint32_t lo = 1, hi = len - 1;  // answer in [lo, hi]
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)x < gload(T + mid)) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 // Number of geometric-gap thresholds T[0..len) that are <= x: the gap of
-// the inverse-CDF draw.  A float guess floor(log2(1 - x/2^32) / log2(1 - r))
-// is corrected against the table, so the table alone decides.
-__device__ __forceinline__ uint32_t geometric_gap(const RepDesc &d, uint32_t x) {
-    const uint32_t len = d.geo_len;
-    const float lg = __log2f((float)(4294967296.0 - (double)x)) - 32.0f;
-    const float guess = lg * d.geo_scale;
+// the inverse-CDF draw.  T is the block's copy in LDS (every threshold is
+// below 2^32).  A float guess floor(log2(1 - x/2^32) / log2(1 - r)), with
+// 2^32 - x = ~x + 1, is corrected against the table, so the table alone
+// decides.
+__device__ __forceinline__ uint32_t geometric_gap(const uint32_t *T, uint32_t len, float scale, uint32_t x) {
+    const float lg = __log2f((float)(~x) + 1.0f) - 32.0f;
+    const float guess = lg * scale;
     uint32_t g = guess >= (float)len ? len : (guess > 0.0f ? (uint32_t)guess : 0u);
-    const uint64_t *T = d.geo;
-    const uint64_t below = g > 0 ? T[g - 1] : 0ull;  // both checks load at once
-    const uint64_t above = g < len ? T[g] : kAlways;
-    if (below > (uint64_t)x || above <= (uint64_t)x) {
-        while (g > 0 && T[g - 1] > (uint64_t)x) --g;
-        while (g < len && T[g] <= (uint64_t)x) ++g;
+    const bool low_ok = g == 0 || T[g - 1] <= x;
+    const bool high_ok = g == len || x < T[g];
+    if (!(low_ok && high_ok)) {
+        while (g > 0 && T[g - 1] > x) --g;
+        while (g < len && T[g] <= x) ++g;
     }
     return g;
 }
@@ -192,37 +233,37 @@ __device__ __forceinline__ uint32_t current_pair(const RepState &st) {
 template <int IT>
 __device__ __forceinline__ void store_fates(uint16_t *p, const uint32_t *f) {
     if constexpr (IT == 4) {
-        *reinterpret_cast<uint2 *>(p) = make_uint2(f[0] | (f[1] << 16), f[2] | (f[3] << 16));
+        gstore(reinterpret_cast<u32x2 *>(p), u32x2{f[0] | (f[1] << 16), f[2] | (f[3] << 16)});
     } else if constexpr (IT == 2) {
-        *reinterpret_cast<uint32_t *>(p) = f[0] | (f[1] << 16);
+        gstore(reinterpret_cast<uint32_t *>(p), f[0] | (f[1] << 16));
     } else {
-        *p = (uint16_t)f[0];
+        gstore(p, (uint16_t)f[0]);
     }
 }
 
 template <int IT>
 __device__ __forceinline__ void load_fates(const uint16_t *p, uint32_t *f) {
     if constexpr (IT == 4) {
-        const uint2 w = *reinterpret_cast<const uint2 *>(p);
+        const u32x2 w = gload(reinterpret_cast<const u32x2 *>(p));
         f[0] = w.x & 0xFFFFu;
         f[1] = w.x >> 16;
         f[2] = w.y & 0xFFFFu;
         f[3] = w.y >> 16;
     } else if constexpr (IT == 2) {
-        const uint32_t w = *reinterpret_cast<const uint32_t *>(p);
+        const uint32_t w = gload(reinterpret_cast<const uint32_t *>(p));
         f[0] = w & 0xFFFFu;
         f[1] = w >> 16;
     } else {
-        f[0] = *p;
+        f[0] = gload(p);
     }
 }
 
 // IT consecutive 8-bit age classes, packed into one word.
 template <int IT>
 __device__ __forceinline__ uint32_t load_ages(const uint8_t *p) {
-    if constexpr (IT == 4) return *reinterpret_cast<const uint32_t *>(p);
-    else if constexpr (IT == 2) return *reinterpret_cast<const uint16_t *>(p);
-    else return *p;
+    if constexpr (IT == 4) return gload(reinterpret_cast<const uint32_t *>(p));
+    else if constexpr (IT == 2) return gload(reinterpret_cast<const uint16_t *>(p));
+    else return gload(p);
 }
 
 // Words of one stream of one individual read in order, one Philox block
@@ -255,15 +296,15 @@ __device__ __forceinline__ void consumer_captures(const RepDesc &c, uint32_t i, 
     if (NR == 0) return;
     const Rng rng{c.key0, c.key1, c.c3};
     SeqWords enc(rng, i, kStEncounter, t), cap(rng, i, kStCapture, t);
-    const uint32_t ne = table_draw(c.enc, c.enc_len, enc(0));
+    const uint32_t ne = table_draw_global(c.enc, c.enc_len, enc(0));
     const uint32_t span = c.habitat > NR ? c.habitat : NR;
     for (uint32_t e = 0; e < ne; ++e) {
         const uint32_t lo = enc(1u + 2u * e), hi = enc(2u + 2u * e);
         const uint32_t tgt = uniform_index(lo, hi, span);
         if (tgt >= NR) continue;
-        const int32_t dz = zc - zr[tgt];
+        const int32_t dz = zc - gload(zr + tgt);
         const uint32_t d = (uint32_t)(dz < 0 ? -dz : dz);
-        if ((uint64_t)cap(e) < c.capT[d]) f(e, tgt);
+        if ((uint64_t)cap(e) < gload(c.capT + d)) f(e, tgt);
     }
 }
 
@@ -314,11 +355,12 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
     int64_t z = 0;
     if (i < n) {
         const uint32_t *g = d.genome[buf] + (size_t)i * 2u * d.W;
-        int32_t acc = 0;
-        for (uint32_t w = 0; w < d.W; ++w)
-            acc += word_effect(d.unit_effects, d.planes, d.W, w, g[w]) +
-                   word_effect(d.unit_effects, d.planes, d.W, w, g[d.W + w]);
-        z = (int64_t)acc - d.sum_e;
+        EffectSum es;
+        for (uint32_t w = 0; w < d.W; ++w) {
+            es.add(d.unit_effects, d.planes, d.W, w, g[w]);
+            es.add(d.unit_effects, d.planes, d.W, w, g[d.W + w]);
+        }
+        z = (int64_t)es.value(d.unit_effects) - d.sum_e;
         d.z[buf][i] = (int32_t)z;
     }
     const int64_t sz = wave_sum<int64_t>(z);
@@ -355,7 +397,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     __shared__ uint32_t sh_tlen;
     uint32_t tlen = d.pois_len;  // length of the table in sh_pois
     if (poisson) {
-        for (uint32_t q = threadIdx.x; q < d.pois_len; q += kBlock) sh_pois[q] = d.pois[q];
+        for (uint32_t q = threadIdx.x; q < d.pois_len; q += kBlock) sh_pois[q] = gload(d.pois + q);
         __syncthreads();
     } else if (cr && d.species == 0) {
         // the resource's offspring table of this generation's density
@@ -372,7 +414,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     const Words<IT> zw = load_words<IT>(reinterpret_cast<const uint32_t *>(d.z[t & 1u]) + i0);
     double v[IT];
 #pragma unroll
-    for (uint32_t q = 0; q < IT; ++q) v[q] = (d.vtab && i0 + q < n) ? d.vtab[(int32_t)zw.v[q] - d.zmin] : 1.0;
+    for (uint32_t q = 0; q < IT; ++q) v[q] = (d.vtab && i0 + q < n) ? gload(d.vtab + ((int32_t)zw.v[q] - d.zmin)) : 1.0;
     uint32_t age4 = 0;
     if (cr) age4 = load_ages<IT>(d.age[t & 1u] + i0);
     uint32_t fate[IT], a_loc = 0, k_loc = 0, near = 0, in_loc = 0;
@@ -388,16 +430,16 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
             if (cr) {
                 p = v[q] * d.surv_age[(age4 >> (8u * q)) & 3u];
                 if (d.species == 0) {
-                    captured = d.won[i] != ~0ull;
+                    captured = gload(d.won + i) != ~0ull;
                 } else {
                     // credited captures: those whose resource kept this key
                     const RepDesc &r = descs[d.partner];
                     const RepState &rs = states[d.partner];
                     const uint32_t NR = rs.n[current_pair(rs)];
                     consumer_captures(d, i, t, (int32_t)zw.v[q], r.z[t & 1u], NR, [&](uint32_t e, uint32_t tgt) {
-                        if (r.won[tgt] == capture_key(i, e)) ++intake;
+                        if (gload(r.won + tgt) == capture_key(i, e)) ++intake;
                     });
-                    d.intake[i] = intake;
+                    gstore(d.intake + i, intake);
                     in_loc += intake;
                 }
             }
@@ -411,8 +453,9 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
                     if (poisson || (cr && d.species == 0)) {
                         kids = table_draw(sh_pois, tlen, rng.block(i, kStFecund, 0, t).v[0]);
                     } else if (cr) {
-                        const uint32_t off = d.cpois_off[2u * intake], len = d.cpois_off[2u * intake + 1u];
-                        kids = table_draw(d.cpois + off, len, rng.block(i, kStFecund, 0, t).v[0]);
+                        const uint32_t off = gload(d.cpois_off + 2u * intake),
+                                       len = gload(d.cpois_off + 2u * intake + 1u);
+                        kids = table_draw_global(d.cpois + off, len, rng.block(i, kStFecund, 0, t).v[0]);
                     }
                     fate[q] = 0x8000u | kids;
                     ++a_loc;
@@ -584,13 +627,13 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
 #pragma unroll
     for (uint32_t q = 0; q < IT; ++q) {
         if (fate[q] >> 15) {
-            if (spos < d.cap) d.S[spos] = i0 + q;
+            if (spos < d.cap) gstore(d.S + spos, i0 + q);
             ++spos;
         }
         if (d.regime != SPEGG_WF) {  // mothers with offspring counts own their slots
             const uint32_t kids = fate[q] & 0x7FFFu;
             for (uint32_t m = 0; m < kids; ++m, ++slot)
-                if (slot < d.cap) d.owner[slot] = i0 + q;
+                if (slot < d.cap) gstore(d.owner + slot, i0 + q);
         }
     }
 }
@@ -603,15 +646,19 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
 // words from g x V.  NCH > 0: the gamete is exactly NCH chunks or fewer and
 // all of them are gathered into registers before the crossover mask is
 // drawn; NCH == 0: any number of chunks, gathered one at a time.
-// Dynamic LDS: the effect planes (plane_words) then, per team and gamete,
-// a crossover bitmap and a flip bitmap of W words each.
+// Shapes that hold at most two chunks with at most 8 lanes per gamete run at
+// least five waves per SIMD (measured faster than four waves with more
+// registers at L = 1024); larger ones keep the registers they need.
+// Dynamic LDS: the effect planes (plane_words), the geometric-gap
+// thresholds (geo_words, skip mode), then, per team and gamete, a crossover
+// bitmap and a flip bitmap of W words each.
 template <int G, int V, int NCH>
-__global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__restrict__ descs,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NCH >= 1 && NCH <= 2 && G <= 8) ? 5 : 1, 8))) offspring_kernel(const RepDesc *__restrict__ descs,
                                                            const RepState *__restrict__ states,
                                                            const OffTile *__restrict__ tiles, uint32_t tile0,
                                                            uint32_t ntiles, int single_deme,
                                                            Partial *__restrict__ partials, uint32_t plane_words,
-                                                           int trace) {
+                                                           uint32_t geo_words, int trace) {
     constexpr uint32_t TPO = 2 * G;
     constexpr uint32_t TEAMS = kBlock / TPO;
     constexpr uint32_t KF = kOffspringInFlight;  // newborns of a team in flight at once
@@ -633,6 +680,7 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
     const uint32_t seg0 = lane_id() - gl;  // first wave lane of this gamete's lanes
     const uint32_t segmask = G >= 32 ? 0xFFFFFFFFu : ((1u << G) - 1u);
     uint32_t *planes = lds;
+    uint32_t *geo = lds + plane_words;  // geometric-gap thresholds, as 32-bit words
 
     uint32_t limit = ntiles;
     if (single_deme >= 0) {
@@ -662,14 +710,19 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
         const uint32_t nsd = d.mig_T != 0 ? NSD : NSD - 1u;
         const bool unit = d.unit_effects != 0;
         const uint64_t binom0 = d.binom0;  // most gametes carry no mutation
+        const bool has_tail = d.tail_mask != ~0u;  // L not a multiple of 32
         const Rng rng{d.key0, d.key1, d.c3};
-        // effect planes into LDS: once per block when every tile is of one
-        // deme, else for every tile
-        if (!unit && (single_deme < 0 || ti == blockIdx.x)) {
-            for (uint32_t q = threadIdx.x; q < 6u * W; q += kBlock) planes[q] = d.planes[q];
+        // effect planes and gap thresholds into LDS: once per block when
+        // every tile is of one deme, else for every tile
+        const bool skip_table = mode == kModeSkip && d.geo_len > 0;
+        if ((!unit || skip_table) && (single_deme < 0 || ti == blockIdx.x)) {
+            if (!unit)
+                for (uint32_t q = threadIdx.x; q < 4u * W; q += kBlock) planes[q] = gload(d.planes + q);
+            if (skip_table)
+                for (uint32_t q = threadIdx.x; q < d.geo_len; q += kBlock) geo[q] = (uint32_t)gload(d.geo + q);
             __syncthreads();
         }
-        uint32_t *X = lds + plane_words + (size_t)(team * 2u + half) * 2u * W;  // crossover toggles
+        uint32_t *X = lds + plane_words + geo_words + (size_t)(team * 2u + half) * 2u * W;  // crossover toggles
         uint32_t *F = X + W;                                                     // mutation flips
         int64_t my_z = 0;
         uint64_t my_z2 = 0;
@@ -717,8 +770,8 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             const RepDesc &sd_src = descs[su];
             const uint32_t ns = states[su].n_surv, nprev = states[su].n_prev;
             const uint32_t p0 = draw(0, 0), p1 = draw(0, 1), p2 = draw(0, 2), p3 = draw(0, 3);
-            uint32_t mom = d.regime == SPEGG_WF ? sd_src.S[uniform_index(p0, p1, ns)] : d.owner[j];
-            uint32_t dad = sd_src.S[uniform_index(p2, p3, ns)];
+            uint32_t mom = d.regime == SPEGG_WF ? gload(sd_src.S + uniform_index(p0, p1, ns)) : gload(d.owner + j);
+            uint32_t dad = gload(sd_src.S + uniform_index(p2, p3, ns));
             // parents are adults of the last census; the clamp never changes a
             // correct index and keeps every gather inside the buffer
             mom = mom < nprev ? mom : nprev - 1u;
@@ -767,7 +820,7 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
                     uint32_t acc = 0;
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
-                        acc += 1u + geometric_gap(d, xw.v[c]);
+                        acc += 1u + geometric_gap(geo, d.geo_len, d.geo_scale, xw.v[c]);
                         cum[c] = acc;
                     }
                     uint32_t incl = acc;
@@ -792,7 +845,7 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
 
             // B2: mutation, K ~ Binomial(L, mu) distinct loci flipped
             const uint32_t xk = f.xk;
-            const uint32_t K = (uint64_t)xk < binom0 ? 0u : table_draw(d.binom, d.binom_len, xk);
+            const uint32_t K = (uint64_t)xk < binom0 ? 0u : table_draw_global(d.binom, d.binom_len, xk);
             if (K > 0) {
                 for (uint32_t w = gl * V; w < W; w += CH)
 #pragma unroll
@@ -816,7 +869,7 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
             }
 
             // B3 + C: gamete words, written out; additive phenotype
-            int32_t zc = 0;
+            EffectSum es;
             uint32_t carry = 0;  // parity of the toggles in earlier chunks
             auto chunk = [&](uint32_t c, const Words<V> &a, const Words<V> &b) {
                 const uint32_t w0 = c * CH + gl * V;
@@ -859,9 +912,9 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
                     for (int v = 0; v < V; ++v) {
                         uint32_t x = (a.v[v] & ~M.v[v]) | (b.v[v] & M.v[v]);
                         if (K > 0) x ^= F[w0 + v];
-                        if (w0 + v == W - 1u) x &= d.tail_mask;
+                        if (has_tail && w0 + v == W - 1u) x &= d.tail_mask;
                         g.v[v] = x;
-                        zc += word_effect(unit, planes, W, w0 + v, x);
+                        es.add(unit, planes, W, w0 + v, x);
                     }
                     store_words<V>(dst + w0, g);
                 }
@@ -882,21 +935,22 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
                     chunk(c, a, b);
                 }
             }
+            int32_t zc = es.value(unit);
 #pragma unroll
             for (int o = 1; o < (int)TPO; o <<= 1) zc += __shfl_xor(zc, o, TPO);
             if (lane == 0) {
                 const int32_t z = zc - d.sum_e;
-                d.z[cur ^ 1u][base + j] = z;
+                gstore(d.z[cur ^ 1u] + base + j, z);
                 if (d.regime == SPEGG_CONSUMER_RESOURCE) {
-                    d.age[cur ^ 1u][base + j] = 0;
-                    if (d.species == 0) d.won[base + j] = ~0ull;  // not captured in the next generation yet
+                    gstore(d.age[cur ^ 1u] + base + j, (uint8_t)0);
+                    if (d.species == 0) gstore(d.won + base + j, (uint64_t)~0ull);  // not captured in the next generation yet
                 }
                 my_z += z;
                 my_z2 += (uint64_t)((int64_t)z * (int64_t)z);
                 if (trace) {
-                    d.mom[j] = f.mom;
-                    d.dad[j] = f.dad;
-                    if (d.mig_T != 0) d.src[j] = f.src_patch;  // the buffer exists with migration only
+                    gstore(d.mom + j, f.mom);
+                    gstore(d.dad + j, f.dad);
+                    if (d.mig_T != 0) gstore(d.src + j, f.src_patch);  // the buffer exists with migration only
                 }
             }
         };
@@ -929,7 +983,8 @@ __global__ void __launch_bounds__(kBlock) offspring_kernel(const RepDesc *__rest
                 a += red_z[w];
                 b += red_z2[w];
             }
-            partials[tile0 + ti] = Partial{a, b};
+            gstore(&partials[tile0 + ti].sum_z, a);
+            gstore(&partials[tile0 + ti].sum_z2, b);
         }
         __syncthreads();
     }
@@ -1109,7 +1164,7 @@ inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kB
 template <int G, int V, int NCH>
 hipError_t launch_offspring_gvn(const OffArgs &a) {
     hipLaunchKernelGGL((offspring_kernel<G, V, NCH>), dim3(a.grid), dim3(kBlock), a.lds, a.s, a.descs, a.states,
-                       a.tiles, a.tile0, a.ntiles, a.single_deme, a.partials, a.plane_words, a.trace);
+                       a.tiles, a.tile0, a.ntiles, a.single_deme, a.partials, a.plane_words, a.geo_words, a.trace);
     return hipGetLastError();
 }
 

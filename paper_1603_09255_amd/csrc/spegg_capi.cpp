@@ -87,6 +87,7 @@ struct OffClass {
     uint32_t tile0, ntiles, grid;
     int single_deme;       // the class's only deme, or -1
     uint32_t plane_words;  // LDS words for the effect planes (0: unit effects only)
+    uint32_t geo_words;    // LDS words for the geometric-gap thresholds (0: no skip-mode member)
     size_t lds;
 };
 
@@ -203,12 +204,12 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const Gc
     p.zlen = 2u * (uint32_t)abs_sum + 1u;
     if (d.omega > 0.0) viability_table(d.theta, d.omega, p.zmin, p.zlen, p.vtab);
     if (!p.unit) {
-        p.planes.assign(6u * p.W, 0u);
+        // bit-planes of the offset effects e + 4 in [0, 8]
+        p.planes.assign(4u * p.W, 0u);
         for (uint32_t l = 0; l < L; ++l) {
-            const int e = d.effects[l];
-            const uint32_t mag = (uint32_t)(e < 0 ? -e : e), bit = 1u << (l % 32u), w = l / 32u;
-            for (uint32_t k = 0; k < 3; ++k)
-                if (mag & (1u << k)) p.planes[((e < 0 ? 3u : 0u) + k) * p.W + w] |= bit;
+            const uint32_t m = (uint32_t)(d.effects[l] + 4), bit = 1u << (l % 32u), w = l / 32u;
+            for (uint32_t k = 0; k < 4; ++k)
+                if (m & (1u << k)) p.planes[k * p.W + w] |= bit;
         }
     }
     if (!binomial_table(L, d.mu, (int)L + 1, p.binom))
@@ -291,8 +292,8 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         if (!seen) shapes.push_back(sh);
     }
     for (const OffShape &sh : shapes) {
-        OffClass c{sh, (uint32_t)P.off_tiles.size(), 0, 0, -1, 0, 0};
-        uint32_t maxW = 0, members = 0, last = 0;
+        OffClass c{sh, (uint32_t)P.off_tiles.size(), 0, 0, -1, 0, 0, 0};
+        uint32_t maxW = 0, members = 0, last = 0, maxgeo = 0;
         bool planes = false;
         for (uint32_t u = 0; u < P.demes.size(); ++u) {
             DemePlan &q = P.demes[u];
@@ -302,6 +303,7 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
             q.off_ntiles = (q.cap + p.opt - 1) / p.opt;
             for (uint32_t k = 0; k < q.off_ntiles; ++k) P.off_tiles.push_back({u, k * p.opt});
             if (p.W > maxW) maxW = p.W;
+            if (p.geo.size() > maxgeo) maxgeo = (uint32_t)p.geo.size();
             planes |= !p.unit;
             ++members;
             last = u;
@@ -310,8 +312,9 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         c.single_deme = members == 1 ? (int)last : -1;
         const uint32_t gmax = offspring_grid_cap();  // a tuning knob: results do not depend on it
         c.grid = c.ntiles < gmax ? c.ntiles : gmax;
-        c.plane_words = planes ? 6u * maxW : 0u;
-        c.lds = c.plane_words * sizeof(uint32_t) + offspring_lds_bytes(sh.g, maxW);
+        c.plane_words = planes ? 4u * maxW : 0u;
+        c.geo_words = maxgeo;
+        c.lds = (c.plane_words + c.geo_words) * sizeof(uint32_t) + offspring_lds_bytes(sh.g, maxW);
         P.classes.push_back(c);
     }
     Carver cv;
@@ -392,6 +395,7 @@ struct GenGraph {
 };
 
 constexpr uint32_t kGraphGenerations = 16;  // generations per replay of the long graph
+constexpr int kAutotuneRounds = 2;          // interleaved timing rounds over the shapes
 
 struct DeviceGuard {
     int prev = -1;
@@ -621,7 +625,7 @@ hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
         for (const OffClass &c : P.classes) {
             if (e != hipSuccess) return e;
             const OffArgs oa{pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0, c.ntiles, c.single_deme,
-                             pop->d_partials(), c.plane_words, c.grid, c.lds, trace, pop->stream};
+                             pop->d_partials(), c.plane_words, c.geo_words, c.grid, c.lds, trace, pop->stream};
             e = timed(pop, SPEGG_KERNEL_OFFSPRING, [&] { return launch_offspring(c.shape, oa); });
         }
         if (e != hipSuccess) return e;
@@ -1189,11 +1193,17 @@ spegg_status spegg_autotune(spegg_pop *pop, uint32_t generations_per_trial, uint
     for (const RepPlan &p : pop->plan.reps)
         if (std::find(Ws.begin(), Ws.end(), p.W) == Ws.end()) Ws.push_back(p.W);
     std::sort(Ws.begin(), Ws.end());
+    // Trials run as production does (graph replay when enabled), so no
+    // per-launch events: two events bracket a run of whole generations.
     const uint32_t saved_timing = pop->timing;
-    pop->timing = 1u << SPEGG_KERNEL_OFFSPRING;
-    // pending events of the caller's timing are kept apart
-    std::vector<Timed> caller_pending;
-    caller_pending.swap(pop->pending);
+    pop->timing = 0;
+    hipEvent_t ea = take_event(pop), eb = take_event(pop);
+    if (!ea || !eb) {
+        if (ea) pop->event_pool.push_back(ea);
+        if (eb) pop->event_pool.push_back(eb);
+        pop->timing = saved_timing;
+        return fail(SPEGG_E_DEVICE, "autotune: no events");
+    }
     for (uint32_t W : Ws) {
         std::vector<int> cands;
         std::vector<OffShape> seen;
@@ -1206,35 +1216,46 @@ spegg_status spegg_autotune(spegg_pop *pop, uint32_t generations_per_trial, uint
                 cands.push_back(g);
             }
         }
-        int best = pop->gcaps.count(W) ? pop->gcaps[W] : offspring_gcap();
-        double best_score = 0.0;
-        bool have = false;
-        for (int g : cands) {
-            pop->gcaps[W] = g;
-            if ((st = apply_shapes(pop)) != SPEGG_OK) break;
-            uint64_t u0 = 0, u1 = 0;
-            if ((st = total_updates(pop, &u0)) != SPEGG_OK) break;
-            if ((st = spegg_step_generations(pop, generations_per_trial)) != SPEGG_OK) break;
-            if ((st = total_updates(pop, &u1)) != SPEGG_OK) break;
-            double ms = 0.0;
-            for (const Timed &t : pop->pending) {
-                float x = 0.f;
-                if (hipEventElapsedTime(&x, t.a, t.b) == hipSuccess) ms += x;
-                pop->event_pool.push_back(t.a);
-                pop->event_pool.push_back(t.b);
-            }
-            pop->pending.clear();
-            const double score = ms / (double)(u1 > u0 ? u1 - u0 : 1u);
-            if (!have || score < best_score) {
-                have = true;
-                best_score = score;
-                best = g;
+        std::vector<double> score(cands.size(), -1.0);
+        for (int round = 0; round < kAutotuneRounds && st == SPEGG_OK; ++round) {
+            for (size_t c = 0; c < cands.size() && st == SPEGG_OK; ++c) {
+                pop->gcaps[W] = cands[c];
+                if ((st = apply_shapes(pop)) != SPEGG_OK) break;
+                // untimed: loads the shape's code and captures the graphs the
+                // timed generations replay
+                if ((st = spegg_step_generations(pop, generations_per_trial)) != SPEGG_OK) break;
+                uint64_t u0 = 0, u1 = 0;
+                if ((st = total_updates(pop, &u0)) != SPEGG_OK) break;
+                hipError_t e = hipEventRecord(ea, pop->stream);
+                if (e != hipSuccess) {
+                    st = device_fail(pop, e, "autotune: event");
+                    break;
+                }
+                if ((st = spegg_step_generations(pop, generations_per_trial)) != SPEGG_OK) break;
+                e = hipEventRecord(eb, pop->stream);
+                if (e != hipSuccess) {
+                    st = device_fail(pop, e, "autotune: event");
+                    break;
+                }
+                if ((st = total_updates(pop, &u1)) != SPEGG_OK) break;  // waits for eb too
+                float ms = 0.f;
+                e = hipEventElapsedTime(&ms, ea, eb);
+                if (e != hipSuccess) {
+                    st = device_fail(pop, e, "autotune: event time");
+                    break;
+                }
+                const double s = (double)ms / (double)(u1 > u0 ? u1 - u0 : 1u);
+                if (score[c] < 0.0 || s < score[c]) score[c] = s;
             }
         }
         if (st != SPEGG_OK) break;
-        pop->gcaps[W] = best;
+        size_t best = 0;
+        for (size_t c = 1; c < cands.size(); ++c)
+            if (score[c] < score[best]) best = c;
+        pop->gcaps[W] = cands[best];
     }
-    pop->pending.swap(caller_pending);
+    pop->event_pool.push_back(ea);
+    pop->event_pool.push_back(eb);
     pop->timing = saved_timing;
     if (st != SPEGG_OK) return st;
     if ((st = apply_shapes(pop)) != SPEGG_OK) return st;
@@ -1244,6 +1265,22 @@ spegg_status spegg_autotune(spegg_pop *pop, uint32_t generations_per_trial, uint
         if (gcap_out) gcap_out[k] = (uint32_t)pop->gcaps[Ws[k]];
     }
     return SPEGG_OK;
+}
+
+spegg_status spegg_set_offspring_cap(spegg_pop *pop, uint32_t W, uint32_t gcap) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if (gcap == 0 || gcap > 32 || (gcap & (gcap - 1)) != 0)
+        return fail(SPEGG_E_INVALID, "set_offspring_cap: cap %u is not a power of two in 1..32", gcap);
+    bool have = false;
+    for (const RepPlan &p : pop->plan.reps) have |= p.W == W;
+    if (!have) return fail(SPEGG_E_INVALID, "set_offspring_cap: no replicate has %u genome words", W);
+    DeviceGuard guard(pop->device);
+    const int saved = pop->gcaps.count(W) ? pop->gcaps[W] : offspring_gcap();
+    pop->gcaps[W] = (int)gcap;
+    st = apply_shapes(pop);
+    if (st != SPEGG_OK) pop->gcaps[W] = saved;
+    return st;
 }
 
 void spegg_pop_destroy(spegg_pop *pop) {

@@ -90,7 +90,7 @@ struct RepDesc {
     uint32_t *src;       // parent trace: patch of the parents
     const double *vtab;  // viability by phenotype, NULL: selection off
     const uint64_t *pois, *binom, *geo;
-    const uint32_t *planes;  // 6 x W effect bit-planes: +1,+2,+4 then -1,-2,-4
+    const uint32_t *planes;  // 4 x W bit-planes of the offset effects e + 4 (bit 0, 1, 2, 3)
 };
 
 // Per-deme state.  The census (generation t, size n) is double-buffered:
@@ -197,6 +197,7 @@ struct OffArgs {
     int single_deme;  // >= 0: the class's only replicate, tiles implicit
     Partial *partials;
     uint32_t plane_words;  // LDS words reserved for the effect planes
+    uint32_t geo_words;    // LDS words reserved for the geometric-gap thresholds
     uint32_t grid;
     size_t lds;
     int trace;

@@ -130,6 +130,8 @@ def load():
     lib.spegg_read_parents.argtypes = [vp, u32, u32, u32, P32, P32, P32, C.c_size_t, P32]
     lib.spegg_autotune.restype = st
     lib.spegg_autotune.argtypes = [vp, u32, P32, P32, u32, P32]
+    lib.spegg_set_offspring_cap.restype = st
+    lib.spegg_set_offspring_cap.argtypes = [vp, u32, u32]
     lib.spegg_set_graph.restype = st
     lib.spegg_set_graph.argtypes = [vp, C.c_int]
     lib.spegg_set_timing.restype = st
@@ -381,7 +383,8 @@ class Population:
     def autotune(self, generations_per_trial=2):
         """Time the offspring kernel's shapes on real generations and keep the
         fastest per genome length; returns {W: lanes-per-gamete cap}.  The
-        population advances by the trial generations."""
+        population advances by the trial generations (4 x
+        generations_per_trial per shape and genome length)."""
         cap = 16
         w = np.zeros(cap, np.uint32)
         g = np.zeros(cap, np.uint32)
@@ -389,6 +392,11 @@ class Population:
         check(self.lib.spegg_autotune(self._h, int(generations_per_trial), _p(w, C.c_uint32), _p(g, C.c_uint32), cap,
                                       C.byref(n)))
         return {int(w[k]): int(g[k]) for k in range(min(n.value, cap))}
+
+    def set_offspring_cap(self, W, gcap):
+        """Pin the offspring kernel's cap on lanes per gamete for genome
+        length W words (what autotune would pick), without timing."""
+        check(self.lib.spegg_set_offspring_cap(self._h, int(W), int(gcap)))
 
     def set_graph(self, enable=True):
         """Replay generations as captured HIP graphs (default) or launch eagerly."""

@@ -235,7 +235,15 @@ def test_autotune_changes_no_result():
     assert sorted(chosen) == [2, 4, 8, 32]
     done = tuned.stats()[0]["generation"]
     assert done >= 2 * len(chosen)
-    tuned.step(3)
+    tuned.step(1)
+    # a pinned shape: no timing, no result changes
+    for W, g in ((32, 1), (8, 32), (2, 2)):
+        tuned.set_offspring_cap(W, g)
+    for bad_W, bad_g in ((32, 3), (32, 0), (32, 64), (5, 4)):
+        with pytest.raises(spegg.SpeggError) as ei:
+            tuned.set_offspring_cap(bad_W, bad_g)
+        assert ei.value.status == spegg.E_INVALID
+    tuned.step(2)
     plain = spegg.Population(reps)
     plain.step(done + 3)
     for i, d in enumerate(reps):
