@@ -159,6 +159,20 @@ __device__ __forceinline__ Words<V> load_words(const uint32_t *p) {
     return w;
 }
 
+// Stores that do not allocate in L2 (newborn genomes: written once per
+// generation and gathered by the next, so an L2 copy only costs the write-back
+// of dirty lines when the kernel ends).
+template <int V>
+__device__ __forceinline__ void store_words_nt(uint32_t *p, const Words<V> &w) {
+    if constexpr (V == 4) {
+        __builtin_nontemporal_store(u32x4{w.v[0], w.v[1], w.v[2], w.v[3]}, (SPEGG_GLOBAL u32x4 *)p);
+    } else if constexpr (V == 2) {
+        __builtin_nontemporal_store(u32x2{w.v[0], w.v[1]}, (SPEGG_GLOBAL u32x2 *)p);
+    } else {
+        __builtin_nontemporal_store(w.v[0], (SPEGG_GLOBAL uint32_t *)p);
+    }
+}
+
 template <int V>
 __device__ __forceinline__ void store_words(uint32_t *p, const Words<V> &w) {
     if constexpr (V == 4) {
@@ -647,13 +661,13 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
 // all of them are gathered into registers before the crossover mask is
 // drawn; NCH == 0: any number of chunks, gathered one at a time.
 // Shapes that hold at most two chunks with at most 8 lanes per gamete run at
-// least five waves per SIMD (measured faster than four waves with more
+// least six waves per SIMD (measured faster than five or four waves with more
 // registers at L = 1024); larger ones keep the registers they need.
 // Dynamic LDS: the effect planes (plane_words), the geometric-gap
 // thresholds (geo_words, skip mode), then, per team and gamete, a crossover
 // bitmap and a flip bitmap of W words each.
 template <int G, int V, int NCH>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NCH >= 1 && NCH <= 2 && G <= 8) ? 5 : 1, 8))) offspring_kernel(const RepDesc *__restrict__ descs,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NCH >= 1 && NCH <= 2 && G <= 8) ? 6 : 1, 8))) offspring_kernel(const RepDesc *__restrict__ descs,
                                                            const RepState *__restrict__ states,
                                                            const OffTile *__restrict__ tiles, uint32_t tile0,
                                                            uint32_t ntiles, int single_deme,
@@ -675,10 +689,6 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
     __shared__ int64_t red_z[kBlock / 64];
     __shared__ uint64_t red_z2[kBlock / 64];
 
-    const uint32_t team = threadIdx.x / TPO, lane = threadIdx.x % TPO;
-    const uint32_t half = lane / G, gl = lane % G;
-    const uint32_t seg0 = lane_id() - gl;  // first wave lane of this gamete's lanes
-    const uint32_t segmask = G >= 32 ? 0xFFFFFFFFu : ((1u << G) - 1u);
     uint32_t *planes = lds;
     uint32_t *geo = lds + plane_words;  // geometric-gap thresholds, as 32-bit words
 
@@ -690,6 +700,16 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
         limit = active < ntiles ? active : ntiles;
     }
     for (uint32_t ti = blockIdx.x; ti < limit; ti += gridDim.x) {
+        // Lane constants come from an opaque copy of the thread index, so
+        // they and the Philox counter words built from them are computed in
+        // the tile's body: hoisted above the loop they stay live through it
+        // and spill to scratch.
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const uint32_t team = tid / TPO, lane = tid % TPO;
+        const uint32_t half = lane / G, gl = lane % G;
+        const uint32_t seg0 = (tid & 63u) - gl;  // first wave lane of this gamete's lanes
+        const uint32_t segmask = G >= 32 ? 0xFFFFFFFFu : ((1u << G) - 1u);
         uint32_t rep, start;
         if (single_deme >= 0) {
             rep = (uint32_t)single_deme;
@@ -731,7 +751,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
         // words (loads in flight); KF newborns of a team get their fronts
         // before the first is finished, so their gathers overlap.
         struct Front {
-            uint32_t j, mom, dad, src_patch, phase, xk;
+            uint32_t j, phase, xk;
             const uint32_t *src;
             uint32_t *dst;
             Words<V> h0[NREG], h1[NREG];
@@ -777,9 +797,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
             mom = mom < nprev ? mom : nprev - 1u;
             dad = dad < nprev ? dad : nprev - 1u;
             f.j = j;
-            f.mom = mom;
-            f.dad = dad;
-            f.src_patch = sd_src.patch;
+            // the traced parents leave now rather than staying live in
+            // registers through the newborn
+            if (trace && lane == 0) {
+                gstore(d.mom + j, mom);
+                gstore(d.dad + j, dad);
+                if (d.mig_T != 0) gstore(d.src + j, sd_src.patch);  // the buffer exists with migration only
+            }
             f.src = sd_src.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
             f.dst = d.genome[cur ^ 1u] + (size_t)(base + j) * 2u * W + (size_t)half * W;
             const uint32_t phase_m = draw(1, 0), phase_p = draw(2, 0);
@@ -916,7 +940,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
                         g.v[v] = x;
                         es.add(unit, planes, W, w0 + v, x);
                     }
-                    store_words<V>(dst + w0, g);
+                    store_words_nt<V>(dst + w0, g);
                 }
             };
             if constexpr (NCH > 0) {
@@ -947,11 +971,6 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
                 }
                 my_z += z;
                 my_z2 += (uint64_t)((int64_t)z * (int64_t)z);
-                if (trace) {
-                    gstore(d.mom + j, f.mom);
-                    gstore(d.dad + j, f.dad);
-                    if (d.mig_T != 0) gstore(d.src + j, f.src_patch);  // the buffer exists with migration only
-                }
             }
         };
 

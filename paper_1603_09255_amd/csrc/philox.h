@@ -17,8 +17,11 @@ __device__ __forceinline__ Words4 philox(uint32_t c0, uint32_t c1, uint32_t c2, 
                                          uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo_a = 0xD2511F53u * c0, hi_a = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo_b = 0xCD9E8D57u * c2, hi_b = __umulhi(0xCD9E8D57u, c2);
+        // full 64-bit products: one v_mad_u64_u32 each instead of a
+        // separate low and high multiply
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0, pb = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo_a = (uint32_t)pa, hi_a = (uint32_t)(pa >> 32);
+        const uint32_t lo_b = (uint32_t)pb, hi_b = (uint32_t)(pb >> 32);
         const uint32_t n0 = hi_b ^ c1 ^ k0;
         const uint32_t n2 = hi_a ^ c3 ^ k1;
         c0 = n0;
