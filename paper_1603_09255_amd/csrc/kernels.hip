@@ -394,12 +394,15 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
 __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restrict__ descs,
                                                          const RepState *__restrict__ states,
                                                          const SurvTile *__restrict__ tiles,
-                                                         SurvCount *__restrict__ counts) {
+                                                         SurvCount *__restrict__ counts, int single_deme) {
     constexpr uint32_t IT = kSurvItems;
     __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_n[kBlock / 64], sh_i[kBlock / 64];
     __shared__ uint64_t sh_t[kBlock / 64];
     __shared__ uint64_t sh_pois[kPoissonTableCap];
-    const SurvTile tile = tiles[blockIdx.x];
+    // a population of one deme has its tiles implicit: no load before the
+    // descriptor's
+    const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * (uint32_t)kSurvTile}
+                                           : tiles[blockIdx.x];
     const RepDesc &d = descs[tile.rep];
     const RepState &st = states[tile.rep];
     const uint32_t par = current_pair(st);
@@ -408,6 +411,9 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     if (tile.start >= n && tile.start != 0) return;
     const bool poisson = d.regime == SPEGG_POISSON_BH;
     const bool cr = d.regime == SPEGG_CONSUMER_RESOURCE;
+    // the adults' phenotypes are in flight while the fecundity table fills
+    const uint32_t i0 = tile.start + threadIdx.x * IT;
+    const Words<IT> zw = load_words<IT>(reinterpret_cast<const uint32_t *>(d.z[t & 1u]) + i0);
     __shared__ uint32_t sh_tlen;
     uint32_t tlen = d.pois_len;  // length of the table in sh_pois
     if (poisson) {
@@ -422,10 +428,8 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
         __syncthreads();
         tlen = sh_tlen;
     }
-    const uint32_t i0 = tile.start + threadIdx.x * IT;
     const double s = density_factor(d, n);
     const Rng rng{d.key0, d.key1, d.c3};
-    const Words<IT> zw = load_words<IT>(reinterpret_cast<const uint32_t *>(d.z[t & 1u]) + i0);
     double v[IT];
 #pragma unroll
     for (uint32_t q = 0; q < IT; ++q) v[q] = (d.vtab && i0 + q < n) ? gload(d.vtab + ((int32_t)zw.v[q] - d.zmin)) : 1.0;
@@ -518,13 +522,20 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
 __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restrict__ descs,
                                                          RepState *__restrict__ states,
                                                          const SurvTile *__restrict__ tiles,
-                                                         const SurvCount *__restrict__ counts, int trace) {
+                                                         const SurvCount *__restrict__ counts, int trace,
+                                                         int single_deme) {
     constexpr uint32_t IT = kSurvItems;
     __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_in[kBlock / 64];
     __shared__ uint64_t sh_kk[kBlock / 64], sh_n[kBlock / 64], sh_t[kBlock / 64];
-    const SurvTile tile = tiles[blockIdx.x];
+    const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * (uint32_t)kSurvTile}
+                                           : tiles[blockIdx.x];
     const RepDesc &d = descs[tile.rep];
     RepState &st = states[tile.rep];
+    // the thread's fates, in flight during the prefix (the buffer is padded
+    // to whole tiles)
+    const uint32_t i0 = tile.start + threadIdx.x * IT;
+    uint32_t fate[IT];
+    load_fates<IT>(d.fate + i0, fate);
     const SurvCount *C = counts + d.surv_tile0;
     // the census this generation started from, as survive recorded it: tile 0
     // of this launch rewrites the state's other pair
@@ -535,7 +546,8 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     if (k >= active && k != 0) return;  // beyond the census: uniform over the block
     const uint32_t wave = threadIdx.x >> 6;
 
-    // exclusive prefix of this tile (tile 0: the totals as well)
+    // exclusive prefix of this tile (tile 0: the totals, with the census
+    // statistics only it records)
     const uint32_t span = k == 0 ? active : k;
     uint32_t pa = 0, pi = 0;
     uint64_t pk = 0, pn = 0, pt = 0;
@@ -543,15 +555,19 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
         const SurvCount c = C[q];
         pa += c.alive;
         pk += c.kids;
-        pn += c.near;
-        pt += c.sum_t;
-        pi += c.intake;
+        if (k == 0) {
+            pn += c.near;
+            pt += c.sum_t;
+            pi += c.intake;
+        }
     }
     pa = wave_sum<uint32_t>(pa);
-    pi = wave_sum<uint32_t>(pi);
     pk = wave_sum<uint64_t>(pk);
-    pn = wave_sum<uint64_t>(pn);
-    pt = wave_sum<uint64_t>(pt);
+    if (k == 0) {  // uniform over the block
+        pi = wave_sum<uint32_t>(pi);
+        pn = wave_sum<uint64_t>(pn);
+        pt = wave_sum<uint64_t>(pt);
+    }
     if (lane_id() == 0) {
         sh_a[wave] = pa;
         sh_in[wave] = pi;
@@ -625,9 +641,6 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     const uint64_t koff = k == 0 ? 0ull : sum_k;
 
     // survivor and slot ranks of the thread's adults, ascending order
-    const uint32_t i0 = tile.start + threadIdx.x * IT;
-    uint32_t fate[IT];
-    load_fates<IT>(d.fate + i0, fate);
     uint32_t a_loc = 0, k_loc = 0;
 #pragma unroll
     for (uint32_t q = 0; q < IT; ++q) {
@@ -1229,13 +1242,14 @@ hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t 
 }
 
 hipError_t launch_survive(const SelArgs &a) {
-    hipLaunchKernelGGL(survive_kernel, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles, a.counts);
+    hipLaunchKernelGGL(survive_kernel, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles, a.counts,
+                       a.single_deme);
     return hipGetLastError();
 }
 
 hipError_t launch_compact(const SelArgs &a) {
     hipLaunchKernelGGL(compact_kernel, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles, a.counts,
-                       a.trace);
+                       a.trace, a.single_deme);
     return hipGetLastError();
 }
 

@@ -608,7 +608,7 @@ hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
     const SurvTile *carry_tiles = at<SurvTile>(pop->base, P.carry_tiles_at);
     for (uint32_t g = 0; g < n; ++g) {
         const SelArgs sa{pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), pop->d_surv_counts(), ns_tiles, trace,
-                         pop->stream};
+                         pop->n_demes == 1 ? 0 : -1, pop->stream};
         hipError_t e = hipSuccess;
         if (!P.enc_tiles.empty())
             e = timed(pop, SPEGG_KERNEL_ENCOUNTER, [&] {

@@ -186,6 +186,7 @@ struct SelArgs {
     SurvCount *counts;
     uint32_t ntiles;
     int trace;
+    int single_deme;  // >= 0: the population's only deme, whose tiles are implicit
     hipStream_t s;
 };
 
