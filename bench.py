@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # (profiles/offspring_plain_scale_hbm_traffic.md), valid only for the device
 # sources with this SHA-256 prefix and the offspring shape it was taken with
 # (lanes-per-gamete cap by genome words W).
-MEASURED_TRAFFIC = {"device_sources_sha256_16": "fc3f307f63efd60f", "lanes_per_gamete_by_W": {32: 4},
-                    "bytes_per_update": 0.6846}
+MEASURED_TRAFFIC = {"device_sources_sha256_16": "3caad568053ad97f", "lanes_per_gamete_by_W": {32: 4},
+                    "bytes_per_update": 0.6848}
 DEVICE_SOURCES = ("kernels.hip", "philox.h", "spegg_internal.h")
 
 
@@ -58,6 +58,54 @@ def measured_traffic_per_update(tuned):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def host_cpu():
+    """The host CPU's model name and logical core count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def device_context(torch, spegg):
+    """Figures of the same run to set the kernel against: the achievable
+    device-copy bandwidth (1 GiB, read + write counted) and the throughput of
+    the device Philox generator the kernels use (a probe with no other
+    memory traffic)."""
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(5):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * 4 * n / (a.elapsed_time(b) / 1e3) / 1e9
+    del src, dst
+    threads, m = 1 << 21, 256
+    out = torch.zeros(threads, dtype=torch.int32, device="cuda")
+    spegg.philox_rate(1, m, out)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(5):
+        spegg.philox_rate(1, m, out)
+    b.record()
+    torch.cuda.synchronize()
+    words = 5 * 4 * threads * m / (a.elapsed_time(b) / 1e3)
+    return {"copy_GBs": copy_gbs, "copy_frac_of_peak": copy_gbs / HBM_PEAK_GBS,
+            "copy": "device-to-device copy of 1 GiB, 5 times, events on the current stream",
+            "philox_words_per_s": words,
+            "philox": f"Philox4x32-10 probe: {threads} threads x {m} blocks, 5 launches"}
 
 
 def bytes_per_update(L):
@@ -99,7 +147,8 @@ def cpu_baseline(desc, budget_s):
             break
     upd = orc.stats()["updates"] - start_updates
     orc.close()
-    return {"value": upd / el, "unit": UNIT, "cores": 1, "kind": "oracle",
+    model, nproc = host_cpu()
+    return {"value": upd / el, "unit": UNIT, "cores": 1, "kind": "oracle", "host_cpu": model, "host_nproc": nproc,
             "sample": f"{gens} generations of the same workload from its initial population "
                       f"({upd} updates, {el:.1f} s, initialisation excluded), one thread"}
 
@@ -194,6 +243,11 @@ def main():
     achieved = per_launch_bytes / avg_launch_s / 1e9
     log(f"bench: event pass {(t1b - t0b) * 1e3:.2f} ms; offspring kernel avg {avg_launch_s * 1e6:.2f} us x {off_n}")
     pop.close()
+    context = device_context(torch, spegg)
+    log(f"bench: device copy {context['copy_GBs']:.0f} GB/s, Philox {context['philox_words_per_s']:.3g} words/s")
+    # the same launches against the bytes they would move if every parent
+    # gather missed the caches (parents read once per newborn gamete)
+    gather_miss = 0.75 + 20.0 / L
 
     out = {
         "metric": METRIC,
@@ -232,7 +286,11 @@ def main():
             "avg_launch_us": avg_launch_s * 1e6,
             "launches": off_n,
             "timing": "HIP events around each offspring launch, in a second pass of the same length",
+            "bytes_per_update_gather_miss": gather_miss,
+            "frac_gather_miss": achieved * gather_miss / bytes_per_update(L) / HBM_PEAK_GBS,
+            "frac_of_copy": achieved / context["copy_GBs"],
         },
+        "context": context,
     }
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle sample, about {args.cpu_seconds:.0f} s")

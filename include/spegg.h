@@ -367,6 +367,14 @@ int spegg_recomb_mode(double r);
 spegg_status spegg_philox_fill(uint64_t seed, const uint32_t *ctr_dev, uint32_t *out_dev, uint32_t n,
                                void *hip_stream);
 
+/* Device Philox4x32-10 throughput probe (the same generator the kernels
+ * use, with no other memory traffic): for i < n, out_dev[i] = XOR of the
+ * four words of the blocks with counters (i, k, 0, 0) under key seed, over
+ * k < blocks_per_thread.  out_dev is device memory; enqueued on hip_stream,
+ * does not wait.  4 * n * blocks_per_thread words per launch. */
+spegg_status spegg_philox_rate(uint64_t seed, uint32_t blocks_per_thread, uint32_t *out_dev, uint32_t n,
+                               void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1304,6 +1304,24 @@ hipError_t launch_allele_counts(const RepDesc *d_desc, const RepState *d_state, 
     return hipGetLastError();
 }
 
+// Philox throughput probe: thread i folds (XOR) the four words of blocks
+// with counters (i, k, 0, 0), k < m, into out[i]; no other memory traffic.
+__global__ void __launch_bounds__(kBlock) philox_rate_kernel(uint32_t k0, uint32_t k1, uint32_t m,
+                                                             uint32_t *__restrict__ out, uint32_t n) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    uint32_t acc = 0;
+    for (uint32_t k = 0; k < m; ++k) {
+        const Words4 w = philox(i, k, 0u, 0u, k0, k1);
+        acc ^= w.v[0] ^ w.v[1] ^ w.v[2] ^ w.v[3];
+    }
+    out[i] = acc;
+}
+hipError_t launch_philox_rate(uint32_t k0, uint32_t k1, uint32_t m, uint32_t *out, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(philox_rate_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, k0, k1, m, out, n);
+    return hipGetLastError();
+}
 hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out, uint32_t n,
                               hipStream_t s) {
     if (n == 0) return hipSuccess;

@@ -1326,4 +1326,13 @@ spegg_status spegg_philox_fill(uint64_t seed, const uint32_t *ctr_dev, uint32_t 
     return SPEGG_OK;
 }
 
+spegg_status spegg_philox_rate(uint64_t seed, uint32_t blocks_per_thread, uint32_t *out_dev, uint32_t n,
+                               void *hip_stream) {
+    if (n && !out_dev) return fail(SPEGG_E_INVALID, "philox_rate: null output");
+    const hipError_t e = launch_philox_rate((uint32_t)seed, (uint32_t)(seed >> 32), blocks_per_thread, out_dev, n,
+                                            (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(SPEGG_E_DEVICE, "philox_rate: %s", hipGetErrorString(e));
+    return SPEGG_OK;
+}
+
 }  // extern "C"

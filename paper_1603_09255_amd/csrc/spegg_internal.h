@@ -238,5 +238,6 @@ hipError_t launch_allele_counts(const RepDesc *d_desc, const RepState *d_state, 
                                 uint32_t *counts, hipStream_t s);
 hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out, uint32_t n,
                               hipStream_t s);
+hipError_t launch_philox_rate(uint32_t k0, uint32_t k1, uint32_t m, uint32_t *out, uint32_t n, hipStream_t s);
 
 }  // namespace spegg

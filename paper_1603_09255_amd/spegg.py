@@ -146,6 +146,8 @@ def load():
     lib.spegg_recomb_mode.argtypes = [C.c_double]
     lib.spegg_philox_fill.restype = st
     lib.spegg_philox_fill.argtypes = [C.c_uint64, vp, vp, u32, vp]
+    lib.spegg_philox_rate.restype = st
+    lib.spegg_philox_rate.argtypes = [C.c_uint64, u32, vp, u32, vp]
     lib.spegg_server_create.restype = st
     lib.spegg_server_create.argtypes = [vp, C.c_size_t, vp, u32, C.POINTER(vp)]
     lib.spegg_server_submit.restype = st
@@ -252,6 +254,15 @@ def philox_fill(seed, ctr):
     stream = torch.cuda.current_stream().cuda_stream
     check(load().spegg_philox_fill(int(seed), c.data_ptr(), out.data_ptr(), c.shape[0], stream))
     return out.cpu().numpy().view(np.uint32)
+
+
+def philox_rate(seed, blocks_per_thread, out):
+    """Philox throughput probe on the current stream (no wait): out[i] =
+    XOR of the words of blocks (i, k, 0, 0), k < blocks_per_thread; out is a
+    device int32 tensor of n entries."""
+    import torch
+    stream = torch.cuda.current_stream().cuda_stream
+    check(load().spegg_philox_rate(int(seed), int(blocks_per_thread), out.data_ptr(), out.numel(), stream))
 
 
 class Population:

@@ -34,6 +34,24 @@ def test_device_philox_matches_oracle_on_counter_grid():
         assert np.array_equal(dev[i], oracle.philox4x32_10(ctr[i], key))
 
 
+def test_philox_rate_probe_folds_the_oracle_blocks():
+    import torch
+    seed, m, n = 0xDEAD_BEEF_0123_4567, 5, 3000
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    say("philox rate probe", m, n)
+    out = torch.zeros(n, dtype=torch.int32, device="cuda")
+    spegg.philox_rate(seed, m, out)
+    got = out.cpu().numpy().view(np.uint32)
+    for i in list(range(0, n, 97)) + [n - 1]:
+        acc = 0
+        for k in range(m):
+            w = oracle.philox4x32_10(np.array([i, k, 0, 0], np.uint32), key)
+            acc ^= int(w[0]) ^ int(w[1]) ^ int(w[2]) ^ int(w[3])
+        assert int(got[i]) == acc, i
+    spegg.philox_rate(seed, 0, out)  # no blocks: the fold of nothing
+    assert not out.any().item()
+
+
 @pytest.mark.parametrize("L,n0", [(1, 7), (31, 50), (32, 64), (33, 65), (64, 1000), (100, 257), (1024, 300),
                                   (4000, 40)])
 def test_initial_population_matches_oracle(L, n0):
