@@ -1193,34 +1193,41 @@ __global__ void philox_fill_kernel(uint32_t k0, uint32_t k1, const uint32_t *__r
 
 inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
 
-template <int G, int V, int NCH>
-hipError_t launch_offspring_gvn(const OffArgs &a) {
-    hipLaunchKernelGGL((offspring_kernel<G, V, NCH>), dim3(a.grid), dim3(kBlock), a.lds, a.s, a.descs, a.states,
-                       a.tiles, a.tile0, a.ntiles, a.single_deme, a.partials, a.plane_words, a.geo_words, a.trace);
-    return hipGetLastError();
-}
+// Every offspring kernel instance has this signature.
+using OffspringKernel = void (*)(const RepDesc *, const RepState *, const OffTile *, uint32_t, uint32_t, int,
+                                 Partial *, uint32_t, uint32_t, int);
 
 template <int G, int V>
-hipError_t launch_offspring_gv(int nch, const OffArgs &a) {
+OffspringKernel offspring_kernel_gv(int nch) {
     switch (nch) {
-    case 0: return launch_offspring_gvn<G, V, 0>(a);
-    case 1: return launch_offspring_gvn<G, V, 1>(a);
-    case 2: return launch_offspring_gvn<G, V, 2>(a);
-    case 4: return launch_offspring_gvn<G, V, 4>(a);
-    default: return hipErrorInvalidValue;
+    case 0: return offspring_kernel<G, V, 0>;
+    case 1: return offspring_kernel<G, V, 1>;
+    case 2: return offspring_kernel<G, V, 2>;
+    case 4: return offspring_kernel<G, V, 4>;
+    default: return nullptr;
     }
 }
 
 template <int V>
-hipError_t launch_offspring_v(int g, int nch, const OffArgs &a) {
+OffspringKernel offspring_kernel_v(int g, int nch) {
     switch (g) {
-    case 1: return launch_offspring_gv<1, V>(nch, a);
-    case 2: return launch_offspring_gv<2, V>(nch, a);
-    case 4: return launch_offspring_gv<4, V>(nch, a);
-    case 8: return launch_offspring_gv<8, V>(nch, a);
-    case 16: return launch_offspring_gv<16, V>(nch, a);
-    case 32: return launch_offspring_gv<32, V>(nch, a);
-    default: return hipErrorInvalidValue;
+    case 1: return offspring_kernel_gv<1, V>(nch);
+    case 2: return offspring_kernel_gv<2, V>(nch);
+    case 4: return offspring_kernel_gv<4, V>(nch);
+    case 8: return offspring_kernel_gv<8, V>(nch);
+    case 16: return offspring_kernel_gv<16, V>(nch);
+    case 32: return offspring_kernel_gv<32, V>(nch);
+    default: return nullptr;
+    }
+}
+
+// The kernel instance of a shape, or null for a shape outside the set.
+OffspringKernel offspring_kernel_for(OffShape shape) {
+    switch (shape.vpl) {
+    case 1: return offspring_kernel_v<1>(shape.g, shape.nch);
+    case 2: return offspring_kernel_v<2>(shape.g, shape.nch);
+    case 4: return offspring_kernel_v<4>(shape.g, shape.nch);
+    default: return nullptr;
     }
 }
 
@@ -1254,12 +1261,17 @@ hipError_t launch_compact(const SelArgs &a) {
 }
 
 hipError_t launch_offspring(OffShape shape, const OffArgs &a) {
-    switch (shape.vpl) {
-    case 1: return launch_offspring_v<1>(shape.g, shape.nch, a);
-    case 2: return launch_offspring_v<2>(shape.g, shape.nch, a);
-    case 4: return launch_offspring_v<4>(shape.g, shape.nch, a);
-    default: return hipErrorInvalidValue;
-    }
+    const OffspringKernel k = offspring_kernel_for(shape);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(a.grid), dim3(kBlock), a.lds, a.s, a.descs, a.states, a.tiles, a.tile0, a.ntiles,
+                       a.single_deme, a.partials, a.plane_words, a.geo_words, a.trace);
+    return hipGetLastError();
+}
+
+hipError_t offspring_blocks_per_cu(OffShape shape, size_t lds, int *blocks) {
+    const OffspringKernel k = offspring_kernel_for(shape);
+    if (!k) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, kBlock, lds);
 }
 
 hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,

@@ -39,7 +39,7 @@ spegg_status fail(spegg_status st, const char *fmt, ...) {
 }
 
 constexpr size_t kAlign = 256;
-constexpr uint32_t kMaxOffspringGrid = 4096;  // blocks of one offspring launch (they loop over tiles)
+constexpr uint32_t kMaxOffspringGrid = 1u << 18;  // blocks of one offspring launch of several demes (they loop over tiles)
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -116,6 +116,27 @@ uint32_t offspring_grid_cap() {
         if (v >= 64 && v <= (1 << 20)) return (uint32_t)v;
     }
     return kMaxOffspringGrid;
+}
+
+// Offspring grids of one-deme classes: as many blocks as the device's compute
+// units hold at once (each block loops over tiles), so no tile waits for a
+// second dispatch behind blocks that find no work.  Classes of several demes
+// keep the larger grid: their tiles carry uneven work (censuses, crossover
+// modes), which the dispatcher balances block by block.  SPEGG_OFFSPRING_GRID,
+// when set, keeps the grids make_plan gave.
+hipError_t fit_offspring_grids(Plan &P, int device) {
+    if (std::getenv("SPEGG_OFFSPRING_GRID")) return hipSuccess;
+    int cus = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    for (OffClass &c : P.classes) {
+        if (c.single_deme < 0) continue;
+        int per = 0;
+        if ((e = offspring_blocks_per_cu(c.shape, c.lds, &per)) != hipSuccess) return e;
+        const uint64_t resident = (uint64_t)(per > 0 ? per : 1) * (uint64_t)(cus > 0 ? cus : 1);
+        c.grid = c.ntiles < resident ? c.ntiles : (uint32_t)resident;
+    }
+    return hipSuccess;
 }
 
 // Lanes-per-gamete cap of the offspring kernel.  A tuning knob only:
@@ -691,9 +712,10 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
     pop->n_reps = n_reps;
     pop->descs.assign(reps, reps + n_reps);
     hipError_t e = hipGetDevice(&pop->device);
+    if (e == hipSuccess) e = fit_offspring_grids(pop->plan, pop->device);
     if (e != hipSuccess) {
         delete pop;
-        return fail(SPEGG_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+        return fail(SPEGG_E_DEVICE, "device query: %s", hipGetErrorString(e));
     }
 
     Plan &P = pop->plan;
@@ -1145,6 +1167,8 @@ spegg_status apply_shapes(spegg_pop *pop) {
     Plan P2;
     spegg_status st = make_plan(pop->descs.data(), pop->n_reps, P2, &pop->gcaps);
     if (st != SPEGG_OK) return st;
+    const hipError_t eg = fit_offspring_grids(P2, pop->device);
+    if (eg != hipSuccess) return device_fail(pop, eg, "autotune: grids");
     if (P2.total != pop->plan.total || P2.static_end != pop->plan.static_end || P2.off_tiles_at != pop->plan.off_tiles_at)
         return fail(SPEGG_E_STATE, "autotune: a new shape would move buffers");
     hipError_t e = launch_census(pop->d_descs(), pop->d_states(), pop->d_partials(), pop->n_demes, pop->stream);

@@ -211,6 +211,9 @@ hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t 
 hipError_t launch_survive(const SelArgs &a);
 hipError_t launch_compact(const SelArgs &a);
 hipError_t launch_offspring(OffShape shape, const OffArgs &a);
+// Blocks of the shape's offspring kernel one compute unit holds at once with
+// lds bytes of dynamic LDS (HIP's occupancy calculation).
+hipError_t offspring_blocks_per_cu(OffShape shape, size_t lds, int *blocks);
 // Consumer-resource regime: encounters and captures of the consumers in
 // tiles (kSurvItems blocks per tile of kSurvTile consumers).
 hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
