@@ -135,6 +135,39 @@ def test_batch_equals_each_replicate_alone_and_oracle():
         alone.close()
 
 
+def test_batched_table_full_size_sampled_replicates():
+    # the batched workload at its full size (4096 Wright-Fisher replicates,
+    # N ~ U{500..50000}, L in {64, 256, 1024}, r ~ U[0.001, 0.5]) in the
+    # launch configuration the bench times (graph replay, the lanes-per-gamete
+    # caps its autotuner picks); for every genome length and crossover mode
+    # the first and the largest replicate against the oracle
+    reps = workloads.batched_table(n_reps=4096)
+    say("batched table", len(reps))
+    pop = spegg.Population(reps)
+    for W, g in ((2, 1), (8, 1), (32, 4)):
+        pop.set_offspring_cap(W, g)
+    pop.step(2)
+    stats = pop.stats()
+    groups = {}
+    for i, d in enumerate(reps):
+        groups.setdefault((d["n_loci"], oracle.recomb_mode(d["r"])), []).append(i)
+    assert len(groups) >= 6  # three lengths, geometric and bit-serial crossovers
+    for key in sorted(groups):
+        idx = groups[key]
+        for i in sorted({idx[0], max(idx, key=lambda k: reps[k]["n0"])}):
+            say("batched replicate", i, "L", reps[i]["n_loci"], "mode", key[1], "N", reps[i]["n0"])
+            orc = oracle_pop(reps[i])
+            orc.step(2)
+            assert_same_state(pop, i, orc, f"batched replicate {i}")
+            orc.close()
+    # every replicate: generation 2, and a Wright-Fisher census unchanged
+    # unless the replicate died out
+    for k, st in enumerate(stats):
+        assert st["generation"] == 2
+        assert st["n"] == (0 if st["extinct"] else reps[k]["n0"])
+    pop.close()
+
+
 def test_plain_scale_first_generations_full_size():
     desc, _ = workloads.plain_scale(seed=1)
     say("plain scale full size, 2 generations")
