@@ -349,19 +349,56 @@ __device__ uint32_t small_binomial_table(uint32_t n, double q, uint64_t *T) {
 
 // ---------------------------------------------------------------- init
 
-__global__ void __launch_bounds__(kBlock) init_kernel(const RepDesc *__restrict__ desc, uint32_t n0) {
-    const RepDesc &d = *desc;
-    const uint32_t per = 2u * d.W;
-    const uint64_t idx = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= (uint64_t)n0 * per) return;
-    const uint32_t i = (uint32_t)(idx / per), q = (uint32_t)(idx % per);
-    const Rng rng{d.key0, d.key1, d.c3};
-    uint32_t word = rng.seq(i, kStInit, q, 0);
-    if (q % d.W == d.W - 1) word &= d.tail_mask;
-    d.genome[0][idx] = word;
+// The initial population of every deme in one launch, one thread per
+// individual slot of a survival tile: the individual's 2W genome words (fair
+// bits: word q is word q % 4 of Philox block q / 4 of stream INIT for the
+// individual; bits of word W-1 past locus L-1 cleared), its phenotype, and
+// the census sums (spread over the state's slots).  Consumer-resource demes
+// also start with age class 0 and no capture keys.
+__global__ void __launch_bounds__(kBlock) create_kernel(const RepDesc *__restrict__ descs,
+                                                        RepState *__restrict__ states,
+                                                        const SurvTile *__restrict__ tiles) {
+    const SurvTile tile = tiles[blockIdx.x];
+    const RepDesc &d = descs[tile.rep];
+    RepState &st = states[tile.rep];
+    const uint32_t n0 = st.n[0];
+    const uint32_t i = tile.start + threadIdx.x;  // below the deme's whole tiles
+    if (d.regime == SPEGG_CONSUMER_RESOURCE) {
+        gstore(d.age[0] + i, (uint8_t)0);
+        gstore(d.age[1] + i, (uint8_t)0);
+        if (d.won && i < d.cap) gstore(d.won + i, (uint64_t)~0ull);
+    }
+    int64_t z = 0;
+    if (i < n0) {
+        const Rng rng{d.key0, d.key1, d.c3};
+        const uint32_t W = d.W, per = 2u * W;
+        const bool unit = d.unit_effects != 0;
+        uint32_t *g = d.genome[0] + (size_t)i * per;
+        EffectSum es;
+        for (uint32_t q0 = 0; q0 < per; q0 += 4) {
+            const Words4 blk = rng.block(i, kStInit, q0 >> 2, 0);
+#pragma unroll
+            for (uint32_t c = 0; c < 4; ++c) {
+                const uint32_t q = q0 + c, w = q % W;
+                if (q < per) {
+                    const uint32_t word = w == W - 1 ? blk.v[c] & d.tail_mask : blk.v[c];
+                    gstore(g + q, word);
+                    es.add(unit, d.planes, W, w, word);
+                }
+            }
+        }
+        z = (int64_t)es.value(unit) - d.sum_e;
+        gstore(d.z[0] + i, (int32_t)z);
+    }
+    const int64_t sz = wave_sum<int64_t>(z);
+    const uint64_t sz2 = wave_sum<uint64_t>((uint64_t)(z * z));
+    if (lane_id() == 0 && (sz != 0 || sz2 != 0)) {
+        const uint32_t slot = blockIdx.x % kCensusSlots;
+        atomicAdd((unsigned long long *)&st.sum_z[slot], (unsigned long long)sz);
+        atomicAdd((unsigned long long *)&st.sum_z2[slot], (unsigned long long)sz2);
+    }
 }
 
-// z for n individuals of buffer buf, and their census sums.
 __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__restrict__ desc,
                                                            RepState *__restrict__ state, uint32_t n, uint32_t buf) {
     const RepDesc &d = *desc;
@@ -1235,10 +1272,10 @@ OffspringKernel offspring_kernel_for(OffShape shape) {
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_init(const RepDesc *d_desc, const RepDesc &h, uint32_t n0, hipStream_t s) {
-    const uint64_t words = (uint64_t)n0 * 2u * h.W;
-    if (words == 0) return hipSuccess;
-    hipLaunchKernelGGL(init_kernel, dim3(blocks_for(words)), dim3(kBlock), 0, s, d_desc, n0);
+hipError_t launch_create(const RepDesc *descs, RepState *states, const SurvTile *tiles, uint32_t ntiles,
+                         hipStream_t s) {
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(create_kernel, dim3(ntiles), dim3(kBlock), 0, s, descs, states, tiles);
     return hipGetLastError();
 }
 

@@ -828,15 +828,12 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         delete pop;
         return fail(SPEGG_E_DEVICE, "hipMemcpyAsync(tables): %s", hipGetErrorString(e));
     }
-    for (uint32_t u = 0; u < pop->n_demes; ++u) {
-        const uint32_t n0 = P.demes[u].n0;
-        e = launch_init(pop->d_descs() + u, pop->dev_descs[u], n0, pop->stream);
-        if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + u, pop->d_states() + u, n0, 0, pop->stream);
-        if (e == hipSuccess) e = reset_species_state(pop, u);
-        if (e != hipSuccess) {
-            delete pop;
-            return fail(SPEGG_E_DEVICE, "initial population: %s", hipGetErrorString(e));
-        }
+    // every deme's initial population in one launch
+    e = launch_create(pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), (uint32_t)P.surv_tiles.size(),
+                      pop->stream);
+    if (e != hipSuccess) {
+        delete pop;
+        return fail(SPEGG_E_DEVICE, "initial population: %s", hipGetErrorString(e));
     }
     // The effects and ecology pointers are the caller's: point at copies.
     pop->effects.resize(n_reps);

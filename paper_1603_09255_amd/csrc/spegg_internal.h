@@ -206,7 +206,10 @@ struct OffArgs {
 };
 
 // Host-side launchers (kernels.hip).
-hipError_t launch_init(const RepDesc *d_desc, const RepDesc &h, uint32_t n0, hipStream_t s);
+// The initial population of every deme (genomes, phenotypes, census sums;
+// consumer-resource ages and capture keys) over the survival tiles.
+hipError_t launch_create(const RepDesc *descs, RepState *states, const SurvTile *tiles, uint32_t ntiles,
+                         hipStream_t s);
 hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t n, uint32_t buf, hipStream_t s);
 hipError_t launch_survive(const SelArgs &a);
 hipError_t launch_compact(const SelArgs &a);
