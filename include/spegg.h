@@ -176,7 +176,11 @@ size_t spegg_footprint(const spegg_rep_desc *reps, uint32_t n_reps);
  * tables, and enqueue the initial population on hip_stream (a hipStream_t;
  * NULL is the null stream): every allele an independent fair bit, drawn
  * from the INIT stream in generation 0.  Returns without waiting.  The
- * handle borrows device_mem and the stream; both must outlive it. */
+ * handle borrows device_mem and the stream; both must outlive it.
+ * SPEGG_E_INVALID: a descriptor; SPEGG_E_NOMEM: workspace too small or
+ * misaligned; SPEGG_E_UNSUPPORTED: an offspring kernel block would need more
+ * LDS than the device gives one block (effect planes, gap table and bitmaps
+ * of the longest genome in a shape). */
 spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void *device_mem, size_t device_bytes,
                               void *hip_stream, spegg_pop **out);
 

@@ -139,6 +139,15 @@ hipError_t fit_offspring_grids(Plan &P, int device) {
     return hipSuccess;
 }
 
+// The device's LDS per block against every offspring class's need (effect
+// planes, gap and fecundity tables, per-team bitmaps).
+hipError_t offspring_lds_limit(int device, size_t *limit) {
+    int v = 0;
+    const hipError_t e = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    *limit = e == hipSuccess && v > 0 ? (size_t)v : 0;
+    return e;
+}
+
 // Lanes-per-gamete cap of the offspring kernel.  A tuning knob only:
 // results do not depend on it.  SPEGG_OFFSPRING_GCAP overrides the default.
 int offspring_gcap() {
@@ -713,10 +722,19 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
     pop->descs.assign(reps, reps + n_reps);
     hipError_t e = hipGetDevice(&pop->device);
     if (e == hipSuccess) e = fit_offspring_grids(pop->plan, pop->device);
+    size_t lds_limit = 0;
+    if (e == hipSuccess) e = offspring_lds_limit(pop->device, &lds_limit);
     if (e != hipSuccess) {
         delete pop;
         return fail(SPEGG_E_DEVICE, "device query: %s", hipGetErrorString(e));
     }
+    for (const OffClass &c : pop->plan.classes)
+        if (c.lds > lds_limit) {
+            const size_t need = c.lds;
+            delete pop;
+            return fail(SPEGG_E_UNSUPPORTED, "an offspring block needs %zu bytes of LDS, the device gives %zu", need,
+                        lds_limit);
+        }
 
     Plan &P = pop->plan;
     pop->n_demes = (uint32_t)P.demes.size();

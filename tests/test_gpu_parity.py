@@ -93,6 +93,10 @@ CASES = [
     ("wf-raw-L4000-odd-words", dict(regime=0, n_loci=4000, r=0.5, mu=1e-4, omega=50.0, n0=80), 2),
     ("pois-lazy-L16384", dict(regime=1, n_loci=16384, r=0.3, mu=1e-5, omega=0.0, K=60.0, fecundity=2.0,
                               n0=40, capacity=120), 2),
+    # the largest LDS footprint: the longest genome in skip mode (gap table of L - 1 thresholds) with effect
+    # planes
+    ("wf-skip-L16384-max", dict(regime=0, n_loci=16384, r=0.001, mu=1e-5, omega=90.0, effects="grid", n0=48,
+                                capacity=64), 2),
 ]
 
 
