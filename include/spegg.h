@@ -296,6 +296,13 @@ spegg_status spegg_kernel_times(spegg_pop *pop, double *ms, uint64_t *launches, 
 spegg_status spegg_autotune(spegg_pop *pop, uint32_t generations_per_trial, uint32_t *w_out, uint32_t *gcap_out,
                             uint32_t cap, uint32_t *n_out);
 
+/* Two environment variables, read when a population is created, override
+ * launch choices for experiments; neither changes a result:
+ * SPEGG_OFFSPRING_GCAP (1, 2, 4, 8, 16 or 32) is the default cap on lanes per
+ * gamete; SPEGG_OFFSPRING_GRID (64 .. 2^20) fixes the blocks of every
+ * offspring launch (by default a one-deme class launches as many blocks as
+ * the device holds at once, a class of several demes up to 2^18). */
+
 /* Set the offspring kernel's cap on lanes per gamete for the replicates of
  * W genome words (gcap a power of two in 1..32), as spegg_autotune would
  * choose it, without timing: e.g. to reuse a tuning found earlier.  Changes

@@ -172,6 +172,31 @@ def test_batched_table_full_size_sampled_replicates():
     pop.close()
 
 
+def test_offspring_grid_changes_no_result(monkeypatch):
+    # a grid of 64 blocks: every block loops over many tiles, in a one-deme
+    # class and in a class of several demes
+    one = [dict(seed=4, replicate_id=60, n0=5000, capacity=6000, n_loci=256, r=0.05, mu=1e-3, omega=12.0)]
+    many = [dict(seed=4, replicate_id=61 + i, n0=900 + 300 * i, capacity=2000, n_loci=256, r=r, mu=1e-3,
+                 omega=10.0) for i, r in enumerate((0.05, 0.3, 0.5))]
+    for reps in (one, many):
+        say("grid 64 against the default", len(reps))
+        default = spegg.Population(reps)
+        monkeypatch.setenv("SPEGG_OFFSPRING_GRID", "64")
+        small = spegg.Population(reps)
+        monkeypatch.delenv("SPEGG_OFFSPRING_GRID")
+        default.step(3)
+        small.step(3)
+        for i in range(len(reps)):
+            assert default.stats()[i] == small.stats()[i]
+            assert np.array_equal(default.genomes(i), small.genomes(i))
+        orc = oracle_pop(reps[-1])
+        orc.step(3)
+        assert_same_state(small, len(reps) - 1, orc, "grid 64")
+        orc.close()
+        default.close()
+        small.close()
+
+
 def test_plain_scale_first_generations_full_size():
     desc, _ = workloads.plain_scale(seed=1)
     say("plain scale full size, 2 generations")
