@@ -711,13 +711,15 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
 // all of them are gathered into registers before the crossover mask is
 // drawn; NCH == 0: any number of chunks, gathered one at a time.
 // Shapes that hold at most two chunks with at most 8 lanes per gamete run at
-// least six waves per SIMD (measured faster than five or four waves with more
-// registers at L = 1024); larger ones keep the registers they need.
+// least seven waves per SIMD (measured faster than six, five or four waves
+// with more registers at L = 1024, although the two-chunk shapes then keep a
+// few values used only on cold paths in scratch); larger ones keep the
+// registers they need.
 // Dynamic LDS: the effect planes (plane_words), the geometric-gap
 // thresholds (geo_words, skip mode), then, per team and gamete, a crossover
 // bitmap and a flip bitmap of W words each.
 template <int G, int V, int NCH>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NCH >= 1 && NCH <= 2 && G <= 8) ? 6 : 1, 8))) offspring_kernel(const RepDesc *__restrict__ descs,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NCH >= 1 && NCH <= 2 && G <= 8) ? 7 : 1, 8))) offspring_kernel(const RepDesc *__restrict__ descs,
                                                            const RepState *__restrict__ states,
                                                            const OffTile *__restrict__ tiles, uint32_t tile0,
                                                            uint32_t ntiles, int single_deme,
