@@ -441,6 +441,11 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * (uint32_t)kSurvTile}
                                            : tiles[blockIdx.x];
     const RepDesc &d = descs[tile.rep];
+    // Both phenotype buffers (padded to whole tiles) are read with the census
+    // state, which alone says which one holds the census: no load waits for it.
+    const uint32_t i0 = tile.start + threadIdx.x * IT;
+    const Words<IT> zw0 = load_words<IT>(reinterpret_cast<const uint32_t *>(d.z[0]) + i0);
+    const Words<IT> zw1 = load_words<IT>(reinterpret_cast<const uint32_t *>(d.z[1]) + i0);
     const RepState &st = states[tile.rep];
     const uint32_t par = current_pair(st);
     const uint32_t t = st.t[par], n = st.n[par];
@@ -448,9 +453,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     if (tile.start >= n && tile.start != 0) return;
     const bool poisson = d.regime == SPEGG_POISSON_BH;
     const bool cr = d.regime == SPEGG_CONSUMER_RESOURCE;
-    // the adults' phenotypes are in flight while the fecundity table fills
-    const uint32_t i0 = tile.start + threadIdx.x * IT;
-    const Words<IT> zw = load_words<IT>(reinterpret_cast<const uint32_t *>(d.z[t & 1u]) + i0);
+    const Words<IT> zw = (t & 1u) ? zw1 : zw0;
     __shared__ uint32_t sh_tlen;
     uint32_t tlen = d.pois_len;  // length of the table in sh_pois
     if (poisson) {
@@ -574,30 +577,35 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     uint32_t fate[IT];
     load_fates<IT>(d.fate + i0, fate);
     const SurvCount *C = counts + d.surv_tile0;
+    const uint32_t k = blockIdx.x - d.surv_tile0;  // tile index within the replicate
+    // exclusive prefix of this tile (tile 0: the totals, with the census
+    // statistics only it records).  Past tile 0 the span is the tiles before
+    // this one, known from the block index: those loads go out with the
+    // census header's.
+    uint32_t pa = 0, pi = 0;
+    uint64_t pk = 0, pn = 0, pt = 0;
+    if (k != 0)
+        for (uint32_t q = threadIdx.x; q < k; q += kBlock) {
+            const SurvCount c = C[q];
+            pa += c.alive;
+            pk += c.kids;
+        }
     // the census this generation started from, as survive recorded it: tile 0
     // of this launch rewrites the state's other pair
     const SurvCount c0 = C[0];
     const uint32_t par = c0.par, t = c0.t, n = c0.n;
-    const uint32_t k = blockIdx.x - d.surv_tile0;  // tile index within the replicate
     const uint32_t active = (n + kSurvTile - 1) / kSurvTile;
     if (k >= active && k != 0) return;  // beyond the census: uniform over the block
     const uint32_t wave = threadIdx.x >> 6;
-
-    // exclusive prefix of this tile (tile 0: the totals, with the census
-    // statistics only it records)
-    const uint32_t span = k == 0 ? active : k;
-    uint32_t pa = 0, pi = 0;
-    uint64_t pk = 0, pn = 0, pt = 0;
-    for (uint32_t q = threadIdx.x; q < span; q += kBlock) {
-        const SurvCount c = C[q];
-        pa += c.alive;
-        pk += c.kids;
-        if (k == 0) {
+    if (k == 0)
+        for (uint32_t q = threadIdx.x; q < active; q += kBlock) {
+            const SurvCount c = C[q];
+            pa += c.alive;
+            pk += c.kids;
             pn += c.near;
             pt += c.sum_t;
             pi += c.intake;
         }
-    }
     pa = wave_sum<uint32_t>(pa);
     pk = wave_sum<uint64_t>(pk);
     if (k == 0) {  // uniform over the block
