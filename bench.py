@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # (profiles/offspring_plain_scale_hbm_traffic.md), valid only for the device
 # sources with this SHA-256 prefix and the offspring shape it was taken with
 # (lanes-per-gamete cap by genome words W).
-MEASURED_TRAFFIC = {"device_sources_sha256_16": "917b7f443afbc593", "lanes_per_gamete_by_W": {32: 4},
-                    "bytes_per_update": 0.7556}
+MEASURED_TRAFFIC = {"device_sources_sha256_16": "a15fc226f6016cd8", "lanes_per_gamete_by_W": {32: 4},
+                    "bytes_per_update": 0.7547}
 DEVICE_SOURCES = ("kernels.hip", "philox.h", "spegg_internal.h")
 
 
@@ -354,8 +354,9 @@ def bench_batched(args):
         plain_time += time.perf_counter() - ta
         plain_updates += p.stats()[0]["updates"] - a0
         p.close()
-    plain_rate = plain_updates / plain_time
-    log(f"bench: plain loop over {len(sample)} replicates: {plain_rate:.4g} updates/s")
+    plain_rate = plain_updates / plain_time if plain_time > 0 else None  # --plain-sample 0: not measured
+    if plain_rate:
+        log(f"bench: plain loop over {len(sample)} replicates: {plain_rate:.4g} updates/s")
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
@@ -365,7 +366,7 @@ def bench_batched(args):
                                "selection width ~ U[2,16], all advanced together",
                    "replicates": len(reps), "generations_timed": args.steps,
                    "plain_loop_updates_per_s": plain_rate, "plain_loop_sample": len(sample),
-                   "speedup_vs_plain_loop": value / plain_rate,
+                   "speedup_vs_plain_loop": value / plain_rate if plain_rate else None,
                    "offspring_lanes_per_gamete_by_W": {str(k): v for k, v in tuned.items()}},
         "roofline": {"bound": "hbm", "kernel": "offspring", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
