@@ -215,7 +215,10 @@ __device__ __forceinline__ uint32_t geometric_gap(const uint32_t *T, uint32_t le
 
 // Crossovers of one 32-boundary block under the bit-serial comparison
 // U < R: U's bits, from the top, are successive words of the block's
-// stream; a boundary is decided at its first bit differing from R.
+// stream; a boundary is decided at its first bit differing from R.  Once
+// every boundary is decided, or R has no 1 bit left below the current one,
+// further planes change nothing: the loop leaves at Philox-block
+// granularity (the four planes of a block need no per-plane test).
 __device__ __forceinline__ uint32_t lazy_block(const Rng &rng, uint32_t j, uint32_t rs, uint32_t tp, uint32_t w,
                                                uint32_t R) {
     uint32_t und = ~0u, hit = 0;
@@ -224,8 +227,6 @@ __device__ __forceinline__ uint32_t lazy_block(const Rng &rng, uint32_t j, uint3
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int b = i - c;
-            const uint32_t rest = b == 31 ? R : (R & ((1u << (b + 1)) - 1u));
-            if (rest == 0 || und == 0) return hit;
             const uint32_t x = blk.v[c];
             if ((R >> b) & 1u) {
                 hit |= und & ~x;
@@ -234,6 +235,9 @@ __device__ __forceinline__ uint32_t lazy_block(const Rng &rng, uint32_t j, uint3
                 und &= ~x;
             }
         }
+        // R's bits below plane i - 3: none left, or every boundary decided
+        const uint32_t rest = i >= 4 ? (R & ((1u << (i - 3)) - 1u)) : 0u;
+        if (rest == 0 || und == 0) return hit;
     }
     return hit;
 }
