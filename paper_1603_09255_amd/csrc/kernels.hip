@@ -213,35 +213,6 @@ __device__ __forceinline__ uint32_t geometric_gap(const uint32_t *T, uint32_t le
     return g;
 }
 
-// Crossovers of one 32-boundary block under the bit-serial comparison
-// U < R: U's bits, from the top, are successive words of the block's
-// stream; a boundary is decided at its first bit differing from R.  Once
-// every boundary is decided, or R has no 1 bit left below the current one,
-// further planes change nothing: the loop leaves at Philox-block
-// granularity (the four planes of a block need no per-plane test).
-__device__ __forceinline__ uint32_t lazy_block(const Rng &rng, uint32_t j, uint32_t rs, uint32_t tp, uint32_t w,
-                                               uint32_t R) {
-    uint32_t und = ~0u, hit = 0;
-    for (int i = 31; i >= 0; i -= 4) {
-        const Words4 blk = rng.block(j, rs, 1u + w * 8u + (uint32_t)((31 - i) >> 2), tp);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int b = i - c;
-            const uint32_t x = blk.v[c];
-            if ((R >> b) & 1u) {
-                hit |= und & ~x;
-                und &= x;
-            } else {
-                und &= ~x;
-            }
-        }
-        // R's bits below plane i - 3: none left, or every boundary decided
-        const uint32_t rest = i >= 4 ? (R & ((1u << (i - 3)) - 1u)) : 0u;
-        if (rest == 0 || und == 0) return hit;
-    }
-    return hit;
-}
-
 // Index of the current census pair: the one with the larger generation.
 __device__ __forceinline__ uint32_t current_pair(const RepState &st) {
     return (int32_t)(st.t[1] - st.t[0]) > 0 ? 1u : 0u;
@@ -929,6 +900,44 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
                     blk += G;
                 }
                 wave_lds_sync();
+            } else if (mode == kModeLazy) {
+                // Bit-serial: the crossovers of every word this lane owns
+                // (word c CH + g V + v of chunk c), into its own crossover
+                // words.  One loop walks the lane's words one Philox block at
+                // a time and moves to the next word once one is decided, so
+                // the lanes of a wave wait for the lane with the most blocks
+                // in all, not for the slowest lane of each word.
+                // Rk: R shifted so that its top four bits are the planes of
+                // the word's current block (bit 31 first)
+                uint32_t c = 0, v = 0, k = 0, und = ~0u, hit = 0, Rk = d.R;
+                for (;;) {
+                    const uint32_t w = c * CH + gl * V + v;
+                    if (w >= W) break;  // the lane's later words lie further on
+                    const Words4 blk = rng.block(j, rs, 1u + w * 8u + k, tp);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t x = blk.v[q];
+                        const uint32_t one = (uint32_t)((int32_t)(Rk << q) >> 31);  // ~0 where R's bit is 1
+                        hit |= und & ~x & one;
+                        und &= x ^ ~one;  // R bit 1: keep where x is 1; R bit 0: where x is 0
+                    }
+                    Rk <<= 4;
+                    // R's bits below this block's planes: none left, or every
+                    // boundary decided -- later planes would change nothing
+                    if (Rk == 0 || und == 0) {
+                        X[w] = hit;
+                        hit = 0;
+                        und = ~0u;
+                        k = 0;
+                        Rk = d.R;
+                        if (++v == (uint32_t)V) {
+                            v = 0;
+                            ++c;
+                        }
+                    } else {
+                        ++k;
+                    }
+                }
             }
 
             // B2: mutation, K ~ Binomial(L, mu) distinct loci flipped
@@ -977,8 +986,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
                         const uint32_t w = w0 + v;
                         uint32_t tog = 0;
                         if (valid) {
-                            if (mode == kModeSkip) tog = X[w];
-                            else if (mode == kModeLazy) tog = lazy_block(rng, j, rs, tp, w, d.R);
+                            if (mode == kModeSkip || mode == kModeLazy) tog = X[w];
                             if (w == 0) tog = (tog & ~1u) | phase;
                         }
                         const uint32_t pre = prefix_xor32(tog);
