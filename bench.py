@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # (profiles/offspring_plain_scale_hbm_traffic.md), valid only for the device
 # sources with this SHA-256 prefix and the offspring shape it was taken with
 # (lanes-per-gamete cap by genome words W).
-MEASURED_TRAFFIC = {"device_sources_sha256_16": "a15fc226f6016cd8", "lanes_per_gamete_by_W": {32: 4},
-                    "bytes_per_update": 0.7547}
+MEASURED_TRAFFIC = {"device_sources_sha256_16": "acea3160aaa713d7", "lanes_per_gamete_by_W": {32: 4},
+                    "bytes_per_update": 0.6808}
 DEVICE_SOURCES = ("kernels.hip", "philox.h", "spegg_internal.h")
 
 
@@ -160,8 +160,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20, help="untimed generations first")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["scale", "batched", "serve", "ecology"], default="scale",
+    ap.add_argument("--workload", choices=["scale", "batched", "serve", "ecology", "small"], default="scale",
                     help="scale: one replicate at scale (default); batched: the 4096-replicate batch; "
+                         "small: the small parity configuration (launch- and latency-bound); "
                          "serve: sweep jobs arriving at random, served with continuous batching; "
                          "ecology: 64 replicates of the two-species consumer-resource form")
     ap.add_argument("--reps", type=int, default=4096, help="replicates of the batched workload")
@@ -196,6 +197,8 @@ def main():
         return bench_serve(args)
     if args.workload == "ecology":
         return bench_ecology(args)
+    if args.workload == "small":
+        return bench_small(args)
 
     desc, _ = workloads.plain_scale(seed=1)
     L = desc["n_loci"]
@@ -295,6 +298,44 @@ def main():
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle sample, about {args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(desc, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def bench_small(args):
+    """The small parity configuration (one Wright-Fisher replicate, N = 1000,
+    L = 64): far too little work to fill the device, so it is bound by
+    launch and dependency latency; reported as microseconds per generation,
+    with no roofline claim."""
+    import torch
+
+    from paper_1603_09255_amd import spegg, workloads
+
+    desc, _ = workloads.plain_small(seed=1)
+    torch.cuda.set_device(0)
+    pop = spegg.Population([desc])
+    pop.step(args.warmup)
+    torch.cuda.synchronize()
+    s0 = pop.stats()[0]["updates"]
+    t0 = time.perf_counter()
+    pop.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    updates = pop.stats()[0]["updates"] - s0
+    pop.set_timing()
+    pop.kernel_times()
+    pop.step(min(args.steps, 200))
+    kt = pop.kernel_times()
+    pop.close()
+    out = {
+        "metric": METRIC, "value": updates / elapsed, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "small parity configuration: 1 Wright-Fisher replicate, N=1000, L=64, unit effects, "
+                               "selection width 8, r=0.5, mu=1e-5",
+                   "us_per_generation": elapsed * 1e6 / args.steps,
+                   "kernel_us_per_launch": {k: v[0] * 1e3 / v[1] for k, v in kt.items() if v[1]},
+                   "note": "launch- and latency-bound: 64000 updates per generation"},
+    }
     print(json.dumps(out), flush=True)
 
 
