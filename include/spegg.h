@@ -298,8 +298,10 @@ spegg_status spegg_autotune(spegg_pop *pop, uint32_t generations_per_trial, uint
 
 /* Two environment variables, read when a population is created, override
  * launch choices for experiments; neither changes a result:
- * SPEGG_OFFSPRING_GCAP (1, 2, 4, 8, 16 or 32) is the default cap on lanes per
- * gamete; SPEGG_OFFSPRING_GRID (64 .. 2^20) fixes the blocks of every
+ * SPEGG_OFFSPRING_GCAP (1, 2, 4, 8, 16 or 32) replaces the default cap on
+ * lanes per gamete (by default the shape whose gamete spans two register
+ * chunks, up to 16 lanes per chunk; 4 beyond) for every genome length;
+ * SPEGG_OFFSPRING_GRID (64 .. 2^20) fixes the blocks of every
  * offspring launch (by default a one-deme class launches as many blocks as
  * the device holds at once, a class of several demes up to 2^18). */
 

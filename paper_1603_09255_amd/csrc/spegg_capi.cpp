@@ -148,15 +148,24 @@ hipError_t offspring_lds_limit(int device, size_t *limit) {
     return e;
 }
 
-// Lanes-per-gamete cap of the offspring kernel.  A tuning knob only:
-// results do not depend on it.  SPEGG_OFFSPRING_GCAP overrides the default.
-int offspring_gcap() {
+// Default lanes-per-gamete cap of the offspring kernel for a genome of W
+// words (a tuning choice only: results do not depend on it).  Up to 16
+// lanes' worth of words per chunk, the shape whose gamete spans two register
+// chunks -- the autotuner's pick wherever it was measured (L = 64, 256,
+// 1024); longer genomes keep a cap of 4 (the chunk-loop shapes).
+// SPEGG_OFFSPRING_GCAP overrides for every W.
+int offspring_gcap(uint32_t W) {
     const char *e = std::getenv("SPEGG_OFFSPRING_GCAP");
     if (e) {
         const int v = std::atoi(e);
         if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32) return v;
     }
-    return kDefaultGCap;
+    const uint32_t vpl = W % 4 == 0 ? 4u : W % 2 == 0 ? 2u : 1u;
+    const uint32_t per = W / vpl;  // lanes of a gamete in one chunk
+    if (per > 16) return kDefaultGCap;
+    int g = 1;
+    while ((uint32_t)(2 * g) <= per / 2) g *= 2;
+    return g;
 }
 
 spegg_status validate(const spegg_rep_desc &d, uint32_t i) {
@@ -248,7 +257,7 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const Gc
         return fail(SPEGG_E_UNSUPPORTED, "replicate %u: fecundity %g needs more than %d table entries", i,
                     d.fecundity, kPoissonTableCap);
     if (p.mode == kModeSkip && L > 1) geometric_table(d.r, L - 1u, p.geo);
-    int gcap = offspring_gcap();
+    int gcap = offspring_gcap(p.W);
     if (gcaps) {
         const auto it = gcaps->find(p.W);
         if (it != gcaps->end()) gcap = it->second;
@@ -1315,7 +1324,7 @@ spegg_status spegg_set_offspring_cap(spegg_pop *pop, uint32_t W, uint32_t gcap) 
     for (const RepPlan &p : pop->plan.reps) have |= p.W == W;
     if (!have) return fail(SPEGG_E_INVALID, "set_offspring_cap: no replicate has %u genome words", W);
     DeviceGuard guard(pop->device);
-    const int saved = pop->gcaps.count(W) ? pop->gcaps[W] : offspring_gcap();
+    const int saved = pop->gcaps.count(W) ? pop->gcaps[W] : offspring_gcap(W);
     pop->gcaps[W] = (int)gcap;
     st = apply_shapes(pop);
     if (st != SPEGG_OK) pop->gcaps[W] = saved;
