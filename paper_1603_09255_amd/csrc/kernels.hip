@@ -11,6 +11,8 @@
 //              + C (additive phenotype by popcounts) + census partials; one
 //              team of 2G lanes per newborn, V consecutive words per lane
 //   census     (on demand) folds the partials into the census sums
+//   create     (once) every deme's initial population: genomes, phenotypes,
+//              census sums
 //   encounter  (consumer-resource regime, before survive) consumers meet
 //              and capture resources; each captured resource keeps the
 //              lowest (consumer, encounter) key by a 64-bit atomic minimum
