@@ -339,36 +339,41 @@ __global__ void __launch_bounds__(kBlock) create_kernel(const RepDesc *__restric
     const RepDesc &d = descs[tile.rep];
     RepState &st = states[tile.rep];
     const uint32_t n0 = st.n[0];
-    const uint32_t i = tile.start + threadIdx.x;  // below the deme's whole tiles
-    if (d.regime == SPEGG_CONSUMER_RESOURCE) {
-        gstore(d.age[0] + i, (uint8_t)0);
-        gstore(d.age[1] + i, (uint8_t)0);
-        if (d.won && i < d.cap) gstore(d.won + i, (uint64_t)~0ull);
-    }
-    int64_t z = 0;
-    if (i < n0) {
-        const Rng rng{d.key0, d.key1, d.c3};
-        const uint32_t W = d.W, per = 2u * W;
-        const bool unit = d.unit_effects != 0;
-        uint32_t *g = d.genome[0] + (size_t)i * per;
-        EffectSum es;
-        for (uint32_t q0 = 0; q0 < per; q0 += 4) {
-            const Words4 blk = rng.block(i, kStInit, q0 >> 2, 0);
+    const Rng rng{d.key0, d.key1, d.c3};
+    const uint32_t W = d.W, per = 2u * W;
+    const bool unit = d.unit_effects != 0;
+    int64_t sz = 0;
+    uint64_t sz2 = 0;
+    for (uint32_t slot = threadIdx.x; slot < d.surv_tile; slot += kBlock) {
+        const uint32_t i = tile.start + slot;  // below the deme's whole tiles
+        if (d.regime == SPEGG_CONSUMER_RESOURCE) {
+            gstore(d.age[0] + i, (uint8_t)0);
+            gstore(d.age[1] + i, (uint8_t)0);
+            if (d.won && i < d.cap) gstore(d.won + i, (uint64_t)~0ull);
+        }
+        if (i < n0) {
+            uint32_t *g = d.genome[0] + (size_t)i * per;
+            EffectSum es;
+            for (uint32_t q0 = 0; q0 < per; q0 += 4) {
+                const Words4 blk = rng.block(i, kStInit, q0 >> 2, 0);
 #pragma unroll
-            for (uint32_t c = 0; c < 4; ++c) {
-                const uint32_t q = q0 + c, w = q % W;
-                if (q < per) {
-                    const uint32_t word = w == W - 1 ? blk.v[c] & d.tail_mask : blk.v[c];
-                    gstore(g + q, word);
-                    es.add(unit, d.planes, W, w, word);
+                for (uint32_t c = 0; c < 4; ++c) {
+                    const uint32_t q = q0 + c, w = q % W;
+                    if (q < per) {
+                        const uint32_t word = w == W - 1 ? blk.v[c] & d.tail_mask : blk.v[c];
+                        gstore(g + q, word);
+                        es.add(unit, d.planes, W, w, word);
+                    }
                 }
             }
+            const int64_t z = (int64_t)es.value(unit) - d.sum_e;
+            gstore(d.z[0] + i, (int32_t)z);
+            sz += z;
+            sz2 += (uint64_t)(z * z);
         }
-        z = (int64_t)es.value(unit) - d.sum_e;
-        gstore(d.z[0] + i, (int32_t)z);
     }
-    const int64_t sz = wave_sum<int64_t>(z);
-    const uint64_t sz2 = wave_sum<uint64_t>((uint64_t)(z * z));
+    sz = wave_sum<int64_t>(sz);
+    sz2 = wave_sum<uint64_t>(sz2);
     if (lane_id() == 0 && (sz != 0 || sz2 != 0)) {
         const uint32_t slot = blockIdx.x % kCensusSlots;
         atomicAdd((unsigned long long *)&st.sum_z[slot], (unsigned long long)sz);
@@ -402,20 +407,20 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
 
 // ---------------------------------------------------------------- survive
 
-// One block per tile of kSurvTile adults; thread x holds the kSurvItems
-// consecutive adults from tile start + x kSurvItems (z and fate buffers are
-// padded to whole tiles, so the vector accesses stay inside).
+// One block per tile of kBlock x IT adults; thread x holds the IT
+// consecutive adults from tile start + x IT (z and fate buffers are padded to
+// whole tiles, so the vector accesses stay inside).
+template <int IT>
 __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restrict__ descs,
                                                          const RepState *__restrict__ states,
                                                          const SurvTile *__restrict__ tiles,
                                                          SurvCount *__restrict__ counts, int single_deme) {
-    constexpr uint32_t IT = kSurvItems;
     __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_n[kBlock / 64], sh_i[kBlock / 64];
     __shared__ uint64_t sh_t[kBlock / 64];
     __shared__ uint64_t sh_pois[kPoissonTableCap];
     // a population of one deme has its tiles implicit: no load before the
     // descriptor's
-    const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * (uint32_t)kSurvTile}
+    const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * (uint32_t)(kBlock * IT)}
                                            : tiles[blockIdx.x];
     const RepDesc &d = descs[tile.rep];
     // Both phenotype buffers (padded to whole tiles) are read with the census
@@ -536,15 +541,16 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
 // replicate's earlier tiles (written by survive, a launch earlier), then
 // block ranks place its survivors and its mothers' offspring slots.  Tile 0
 // of each replicate sums all the tiles and advances the census.
+template <int IT>
 __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restrict__ descs,
                                                          RepState *__restrict__ states,
                                                          const SurvTile *__restrict__ tiles,
                                                          const SurvCount *__restrict__ counts, int trace,
                                                          int single_deme) {
-    constexpr uint32_t IT = kSurvItems;
+    constexpr uint32_t TILE = kBlock * IT;
     __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_in[kBlock / 64];
     __shared__ uint64_t sh_kk[kBlock / 64], sh_n[kBlock / 64], sh_t[kBlock / 64];
-    const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * (uint32_t)kSurvTile}
+    const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * TILE}
                                            : tiles[blockIdx.x];
     const RepDesc &d = descs[tile.rep];
     RepState &st = states[tile.rep];
@@ -571,7 +577,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     // of this launch rewrites the state's other pair
     const SurvCount c0 = C[0];
     const uint32_t par = c0.par, t = c0.t, n = c0.n;
-    const uint32_t active = (n + kSurvTile - 1) / kSurvTile;
+    const uint32_t active = (n + TILE - 1) / TILE;
     if (k >= active && k != 0) return;  // beyond the census: uniform over the block
     const uint32_t wave = threadIdx.x >> 6;
     if (k == 0)
@@ -618,7 +624,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
         uint32_t x = 0;
         for (int side = 0; side < 2; ++side) {
             const SurvCount *CE = counts + descs[side ? d.right : d.left].surv_tile0;
-            const uint32_t act = (CE[0].n + kSurvTile - 1) / kSurvTile;
+            const uint32_t act = (CE[0].n + TILE - 1) / TILE;
             for (uint32_t q = threadIdx.x; q < act; q += kBlock) x += CE[q].alive;
         }
         x = wave_sum<uint32_t>(x);
@@ -1136,15 +1142,15 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
 
 // ---------------------------------------------------------------- consumer-resource
 
-// kSurvItems blocks per tile of kSurvTile consumers, one consumer per
-// thread: every capture offers its key (consumer, encounter) to the
+// One block per survival tile (kBlock consumers: this regime runs one adult
+// per thread), one consumer per thread: every capture offers its key (consumer, encounter) to the
 // captured resource, which keeps the lowest.  The keys were reset to ~0
 // when the resource census was written.
 __global__ void __launch_bounds__(kBlock) encounter_kernel(const RepDesc *__restrict__ descs,
                                                            const RepState *__restrict__ states,
                                                            const SurvTile *__restrict__ tiles) {
-    const SurvTile tile = tiles[blockIdx.x / kSurvItems];
-    const uint32_t i = tile.start + (blockIdx.x % kSurvItems) * kBlock + threadIdx.x;
+    const SurvTile tile = tiles[blockIdx.x];
+    const uint32_t i = tile.start + threadIdx.x;  // tiles of kBlock adults in this regime
     const RepDesc &c = descs[tile.rep];
     const RepState &cs = states[tile.rep];
     const uint32_t par = current_pair(cs);
@@ -1174,7 +1180,7 @@ __global__ void __launch_bounds__(kBlock) carry_kernel(const RepDesc *__restrict
     const uint32_t nc = st.n_carry;
     if (tile.start >= nc) return;
     const uint32_t cur = (st.t[newest] - 1u) & 1u;
-    const uint32_t cnt = nc - tile.start < (uint32_t)kSurvTile ? nc - tile.start : (uint32_t)kSurvTile;
+    const uint32_t cnt = nc - tile.start < d.surv_tile ? nc - tile.start : d.surv_tile;
     const uint32_t per = 2u * d.W;
     if ((per & 3u) == 0) {  // 16-byte copies
         const uint32_t per4 = per / 4u;
@@ -1310,14 +1316,26 @@ hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t 
 }
 
 hipError_t launch_survive(const SelArgs &a) {
-    hipLaunchKernelGGL(survive_kernel, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles, a.counts,
-                       a.single_deme);
+    if (a.items == 4)
+        hipLaunchKernelGGL(survive_kernel<4>, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles,
+                           a.counts, a.single_deme);
+    else if (a.items == 1)
+        hipLaunchKernelGGL(survive_kernel<1>, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles,
+                           a.counts, a.single_deme);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 hipError_t launch_compact(const SelArgs &a) {
-    hipLaunchKernelGGL(compact_kernel, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles, a.counts,
-                       a.trace, a.single_deme);
+    if (a.items == 4)
+        hipLaunchKernelGGL(compact_kernel<4>, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles,
+                           a.counts, a.trace, a.single_deme);
+    else if (a.items == 1)
+        hipLaunchKernelGGL(compact_kernel<1>, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles,
+                           a.counts, a.trace, a.single_deme);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1344,7 +1362,7 @@ hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *
 hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
                             hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(encounter_kernel, dim3(ntiles * kSurvItems), dim3(kBlock), 0, s, descs, states, tiles);
+    hipLaunchKernelGGL(encounter_kernel, dim3(ntiles), dim3(kBlock), 0, s, descs, states, tiles);
     return hipGetLastError();
 }
 

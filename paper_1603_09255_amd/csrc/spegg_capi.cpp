@@ -106,6 +106,7 @@ struct Plan {
     size_t descs = 0, states = 0, surv_tiles_at = 0, off_tiles_at = 0, enc_tiles_at = 0, carry_tiles_at = 0;
     size_t static_end = 0;  // [0, static_end) is uploaded at create
     size_t surv_counts = 0, partials = 0, total = 0;
+    uint32_t surv_items = 1;  // adults per thread in survive and compact
 };
 
 // Most blocks of one offspring launch; SPEGG_OFFSPRING_GRID overrides.
@@ -310,13 +311,20 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
             q.n0 = consumer ? reps[i].ecology->n0_consumer : reps[i].n0;
             q.cap = consumer ? reps[i].ecology->capacity_consumer : reps[i].capacity;
         }
-    // survival tiles, deme by deme
+    // survival tiles, deme by deme: four adults per thread where the
+    // population has several demes and no consumer-resource replicate (fewer,
+    // longer blocks; measured faster on the batched table), else one (more
+    // blocks in flight for one deme; the consumer-resource kernels assume it)
+    bool any_cr = false;
+    for (const RepPlan &p : P.reps) any_cr |= p.cr;
+    P.surv_items = (!any_cr && P.demes.size() > 1) ? (uint32_t)kSurvItemsMax : 1u;
+    const uint32_t surv_tile = kBlock * P.surv_items;
     for (uint32_t u = 0; u < P.demes.size(); ++u) {
         DemePlan &q = P.demes[u];
         q.surv_tile0 = (uint32_t)P.surv_tiles.size();
-        q.surv_ntiles = (q.cap + kSurvTile - 1) / kSurvTile;
+        q.surv_ntiles = (q.cap + surv_tile - 1) / surv_tile;
         for (uint32_t k = 0; k < q.surv_ntiles; ++k) {
-            const SurvTile tile{u, k * (uint32_t)kSurvTile};
+            const SurvTile tile{u, k * surv_tile};
             P.surv_tiles.push_back(tile);
             if (P.reps[q.rep].cr) P.carry_tiles.push_back(tile);
             if (P.reps[q.rep].cr && q.species == 1) P.enc_tiles.push_back(tile);
@@ -391,7 +399,7 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         q.genome[0] = cv.take(gbytes);
         q.genome[1] = cv.take(gbytes);
         // phenotypes padded to whole select tiles (read as vectors)
-        const size_t zcap = ((cap + kSurvTile - 1) / kSurvTile) * kSurvTile;
+        const size_t zcap = ((cap + kSurvTileMax - 1) / kSurvTileMax) * kSurvTileMax;
         q.z[0] = cv.take(zcap * sizeof(int32_t));
         q.z[1] = cv.take(zcap * sizeof(int32_t));
         q.fate = cv.take(zcap * sizeof(uint16_t));
@@ -631,7 +639,7 @@ hipError_t reset_species_state(spegg_pop *pop, uint32_t u) {
     const DemePlan &q = pop->plan.demes[u];
     const RepDesc &h = pop->dev_descs[u];
     if (!pop->plan.reps[q.rep].cr) return hipSuccess;
-    const uint32_t zcap = ((q.cap + kSurvTile - 1) / kSurvTile) * kSurvTile;
+    const uint32_t zcap = ((q.cap + kSurvTileMax - 1) / kSurvTileMax) * kSurvTileMax;
     hipError_t e = launch_fill_u8(h.age[0], zcap, pop->stream);
     if (e == hipSuccess) e = launch_fill_u8(h.age[1], zcap, pop->stream);
     if (e == hipSuccess && h.won) e = launch_fill_u64(h.won, q.cap, pop->stream);
@@ -647,7 +655,7 @@ hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
     const SurvTile *carry_tiles = at<SurvTile>(pop->base, P.carry_tiles_at);
     for (uint32_t g = 0; g < n; ++g) {
         const SelArgs sa{pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), pop->d_surv_counts(), ns_tiles, trace,
-                         pop->n_demes == 1 ? 0 : -1, pop->stream};
+                         pop->n_demes == 1 ? 0 : -1, (int)P.surv_items, pop->stream};
         hipError_t e = hipSuccess;
         if (!P.enc_tiles.empty())
             e = timed(pop, SPEGG_KERNEL_ENCOUNTER, [&] {
@@ -776,6 +784,7 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.unit_effects = p.unit ? 1u : 0u;
         h.tail_mask = (d.n_loci % 32u) ? ((1u << (d.n_loci % 32u)) - 1u) : ~0u;
         h.surv_tile0 = q.surv_tile0;
+        h.surv_tile = kBlock * P.surv_items;
         h.surv_ntiles = q.surv_ntiles;
         h.off_tile0 = q.off_tile0;
         h.off_ntiles = q.off_ntiles;

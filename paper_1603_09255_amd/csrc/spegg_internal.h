@@ -42,8 +42,12 @@ enum Mode : uint32_t { kModeRaw = 0, kModeZero = 1, kModeSkip = 2, kModeLazy = 3
 constexpr double kSkipBelow = 0.17;  // r < 0.17: geometric gaps; above: bit-serial Bernoulli
 
 constexpr int kBlock = 256;          // threads per block in every kernel
-constexpr int kSurvItems = 1;        // consecutive adults per thread in survive and compact (1, 2 or 4)
-constexpr int kSurvTile = kBlock * kSurvItems;  // adults per survival tile
+// Consecutive adults per thread in survive and compact, chosen per
+// population: 1 (one deme, or any consumer-resource replicate) or 4 (several
+// demes); a survival tile holds kBlock times that many adults.  Per-adult
+// buffers are padded to whole tiles of the largest size.
+constexpr int kSurvItemsMax = 4;
+constexpr int kSurvTileMax = kBlock * kSurvItemsMax;
 constexpr int kPoissonTableCap = 1024;  // longest Poisson threshold table
 constexpr int kCensusSlots = 16;     // slots of the census sums (init and write_genomes spread atomics)
 
@@ -60,6 +64,7 @@ struct RepDesc {
     uint32_t unit_effects;
     uint32_t tail_mask;  // valid bits of word W-1
     uint32_t surv_tile0, surv_ntiles;
+    uint32_t surv_tile;  // adults per survival tile of the population (kBlock x adults per thread)
     uint32_t off_tile0, off_ntiles, off_per_tile;  // offspring tiles: global index of the first
     float geo_scale;     // 1 / log2(1 - r): first guess of a geometric gap (checked against geo)
     double K, lambda;    // Beverton-Holt density factor; 0 < K enables it
@@ -187,6 +192,7 @@ struct SelArgs {
     uint32_t ntiles;
     int trace;
     int single_deme;  // >= 0: the population's only deme, whose tiles are implicit
+    int items;        // adults per thread (1 or 4)
     hipStream_t s;
 };
 
@@ -217,8 +223,8 @@ hipError_t launch_offspring(OffShape shape, const OffArgs &a);
 // Blocks of the shape's offspring kernel one compute unit holds at once with
 // lds bytes of dynamic LDS (HIP's occupancy calculation).
 hipError_t offspring_blocks_per_cu(OffShape shape, size_t lds, int *blocks);
-// Consumer-resource regime: encounters and captures of the consumers in
-// tiles (kSurvItems blocks per tile of kSurvTile consumers).
+// Consumer-resource regime (one adult per thread in the survival tiles):
+// encounters and captures of the consumers, one block per tile.
 hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
                             hipStream_t s);
 // Consumer-resource regime: survivors into the next census (one block per
