@@ -206,8 +206,11 @@ __device__ __forceinline__ uint32_t geometric_gap(const uint32_t *T, uint32_t le
     const float lg = __log2f((float)(~x) + 1.0f) - 32.0f;
     const float guess = lg * scale;
     uint32_t g = guess >= (float)len ? len : (guess > 0.0f ? (uint32_t)guess : 0u);
-    const bool low_ok = g == 0 || T[g - 1] <= x;
-    const bool high_ok = g == len || x < T[g];
+    if (len == 0) return 0;  // uniform: one locus, no boundary
+    // both neighbours read unconditionally (indices clamped into the table)
+    const uint32_t t_lo = T[g == 0 ? 0u : g - 1u], t_hi = T[g < len ? g : len - 1u];
+    const bool low_ok = g == 0 || t_lo <= x;
+    const bool high_ok = g == len || x < t_hi;
     if (!(low_ok && high_ok)) {
         while (g > 0 && T[g - 1] > x) --g;
         while (g < len && T[g] <= x) ++g;

@@ -22,8 +22,18 @@ __device__ __forceinline__ Words4 philox(uint32_t c0, uint32_t c1, uint32_t c2, 
         const uint64_t pa = (uint64_t)0xD2511F53u * c0, pb = (uint64_t)0xCD9E8D57u * c2;
         const uint32_t lo_a = (uint32_t)pa, hi_a = (uint32_t)(pa >> 32);
         const uint32_t lo_b = (uint32_t)pb, hi_b = (uint32_t)(pb >> 32);
-        const uint32_t n0 = hi_b ^ c1 ^ k0;
-        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        // From the third round on every counter word differs between lanes:
+        // each three-way XOR is then one v_bitop3_b32 (truth table 0x96)
+        // instead of two VALU XORs.  The first two rounds keep plain XORs,
+        // so that words shared by the wave are combined on the scalar unit.
+        uint32_t n0, n2;
+        if (round >= 2) {
+            n0 = __builtin_amdgcn_bitop3_b32(hi_b, c1, k0, 0x96);
+            n2 = __builtin_amdgcn_bitop3_b32(hi_a, c3, k1, 0x96);
+        } else {
+            n0 = hi_b ^ c1 ^ k0;
+            n2 = hi_a ^ c3 ^ k1;
+        }
         c0 = n0;
         c1 = lo_b;
         c2 = n2;
