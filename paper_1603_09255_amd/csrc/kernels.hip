@@ -197,7 +197,7 @@ __device__ __forceinline__ uint32_t table_draw_global(const uint64_t *__restrict
     return lo;
 }
 
-// Number of geometric-gap thresholds T[0..len) that are <= x: the gap of
+// Number of geometric-gap thresholds T[0..len) (len >= 1) that are <= x: the gap of
 // the inverse-CDF draw.  T is the block's copy in LDS (every threshold is
 // below 2^32).  A float guess floor(log2(1 - x/2^32) / log2(1 - r)), with
 // 2^32 - x = ~x + 1, is corrected against the table, so the table alone
@@ -206,8 +206,8 @@ __device__ __forceinline__ uint32_t geometric_gap(const uint32_t *T, uint32_t le
     const float lg = __log2f((float)(~x) + 1.0f) - 32.0f;
     const float guess = lg * scale;
     uint32_t g = guess >= (float)len ? len : (guess > 0.0f ? (uint32_t)guess : 0u);
-    if (len == 0) return 0;  // uniform: one locus, no boundary
-    // both neighbours read unconditionally (indices clamped into the table)
+    // both neighbours read unconditionally (indices clamped into the table,
+    // which holds at least one threshold)
     const uint32_t t_lo = T[g == 0 ? 0u : g - 1u], t_hi = T[g < len ? g : len - 1u];
     const bool low_ok = g == 0 || t_lo <= x;
     const bool high_ok = g == len || x < t_hi;
@@ -882,9 +882,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
                     for (int v = 0; v < V; ++v) X[w + v] = 0;
                 wave_lds_sync();
                 // gaps come four to a Philox block from block 1 on; lane g
-                // takes block blk + g, so a pass places up to 4G crossovers
+                // takes block blk + g, so a pass places up to 4G crossovers.
+                // One locus (an empty table) has no boundary.
                 uint32_t b = 0, blk = 1;
-                for (;;) {
+                for (; d.geo_len > 0;) {
                     const Words4 xw = rng.block(j, rs, blk + gl, tp);
                     uint32_t cum[4];
                     uint32_t acc = 0;
