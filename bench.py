@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # (profiles/offspring_plain_scale_hbm_traffic.md), valid only for the device
 # sources with this SHA-256 prefix and the offspring shape it was taken with
 # (lanes-per-gamete cap by genome words W).
-MEASURED_TRAFFIC = {"device_sources_sha256_16": "c361f0a3174756d3", "lanes_per_gamete_by_W": {32: 4},
-                    "bytes_per_update": 0.6806}
+MEASURED_TRAFFIC = {"device_sources_sha256_16": "375815c25d6f5a30", "lanes_per_gamete_by_W": {32: 4},
+                    "bytes_per_update": 0.6804}
 DEVICE_SOURCES = ("kernels.hip", "philox.h", "spegg_internal.h")
 
 
