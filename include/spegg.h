@@ -271,7 +271,9 @@ enum {
 
 /* Bracket the kernels of the kinds in kinds_mask (bit k: kind k; 0 stops)
  * launched by later spegg_step_generations calls with HIP events on the
- * population's stream. */
+ * population's stream.  The events carry no system-scope fence, so that
+ * recording them neither writes back nor invalidates the caches the timed
+ * kernels use. */
 spegg_status spegg_set_timing(spegg_pop *pop, uint32_t kinds_mask);
 
 /* Wait, then report per kernel kind the summed event time in milliseconds

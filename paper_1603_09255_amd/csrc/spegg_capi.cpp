@@ -513,8 +513,11 @@ hipEvent_t take_event(spegg_pop *pop) {
         pop->event_pool.pop_back();
         return e;
     }
+    // These events only time work on the population's stream: without the
+    // system-scope fence a record does not write back and invalidate the
+    // caches, which would slow the kernel it brackets and add to its time.
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
