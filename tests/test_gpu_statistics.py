@@ -1,0 +1,70 @@
+"""Statistical checks of the HIP library's gametes against the model itself,
+not against the oracle: with every parent heterozygous at every locus (one
+haplotype all 0, the other all 1), no mutation and no selection, a change of
+allele between adjacent loci of a newborn's haplotype is exactly a crossover
+at that boundary.  Gametes follow Fig. 1B and the genetics of
+Supplementary Information S2 (r = 1/2 is free recombination; for linked
+loci the reading taken is a crossover at each boundary independently with
+probability r, without interference): the haplotype copied at the first
+locus is either parent haplotype with probability 1/2, and bits past locus
+L - 1 stay 0."""
+import numpy as np
+import pytest
+
+from gpu_helpers import say
+from paper_1603_09255_amd import spegg
+
+pytestmark = pytest.mark.gpu
+
+N = 20000
+
+
+def het_parents(n, L):
+    W = (L + 31) // 32
+    words = np.zeros((n, 2, W), np.uint32)
+    words[:, 1, :] = 0xFFFFFFFF
+    if L % 32:
+        words[:, 1, -1] = (1 << (L % 32)) - 1
+    return words
+
+
+def one_generation(L, r, seed):
+    d = dict(seed=seed, replicate_id=1, regime=0, n0=N, capacity=N, n_loci=L, mu=0.0, r=r, theta=0.0,
+             omega=0.0, K=0.0, fecundity=0.0)
+    pop = spegg.Population([d])
+    pop.write_genomes(0, het_parents(N, L), 10)
+    pop.step(1)
+    g = pop.genomes(0)
+    pop.close()
+    assert g.shape == (N, 2, (L + 31) // 32)
+    bits = np.unpackbits(np.ascontiguousarray(g).view(np.uint8), bitorder="little").reshape(N, 2, -1)
+    return bits
+
+
+@pytest.mark.parametrize("L,r", [(1000, 0.01), (1000, 0.1), (1000, 0.3), (64, 0.5), (257, 0.0)],
+                         ids=["skip-0.01", "skip-0.1", "lazy-0.3", "raw-0.5", "zero"])
+def test_crossovers_are_independent_bernoulli_per_boundary(L, r):
+    say("recombination statistics L", L, "r", r)
+    bits = one_generation(L, r, seed=31 + L)
+    assert not bits[:, :, L:].any(), "bits past the last locus must stay 0"
+    hap = bits[:, :, :L].reshape(2 * N, L)
+    # the first locus copies either parent haplotype with probability 1/2
+    p0 = hap[:, 0].mean()
+    assert abs(p0 - 0.5) < 6 * np.sqrt(0.25 / (2 * N)), p0
+    switches = hap[:, 1:] != hap[:, :-1]
+    m = switches.size
+    frac = switches.mean()
+    if r == 0.0:
+        assert frac == 0.0
+        return
+    sd = np.sqrt(r * (1 - r) / m)
+    assert abs(frac - r) < 6 * sd, (frac, r, sd)
+    # per-gamete counts: Binomial(L - 1, r) -- variance r (1 - r) (L - 1); a
+    # random word reused across boundaries would inflate it
+    counts = switches.sum(axis=1)
+    var = r * (1 - r) * (L - 1)
+    assert abs(counts.var() - var) < 6 * var * np.sqrt(2.0 / counts.size) + 0.05, (counts.var(), var)
+    # neighbouring boundaries uncorrelated
+    a, b = switches[:, :-1], switches[:, 1:]
+    cov = np.count_nonzero(a & b) / a.size - a.mean() * b.mean()
+    assert abs(cov) < 6 * r * (1 - r) / np.sqrt(a.size), cov
