@@ -1,5 +1,7 @@
-"""Statistical checks of the HIP library's gametes against the model itself,
-not against the oracle: with every parent heterozygous at every locus (one
+"""Statistical checks of the HIP library against the model itself, not
+against the oracle: crossovers, mutations and Wright-Fisher parents.
+
+Crossovers: with every parent heterozygous at every locus (one
 haplotype all 0, the other all 1), no mutation and no selection, a change of
 allele between adjacent loci of a newborn's haplotype is exactly a crossover
 at that boundary.  Gametes follow Fig. 1B and the genetics of
@@ -68,3 +70,49 @@ def test_crossovers_are_independent_bernoulli_per_boundary(L, r):
     a, b = switches[:, :-1], switches[:, 1:]
     cov = np.count_nonzero(a & b) / a.size - a.mean() * b.mean()
     assert abs(cov) < 6 * r * (1 - r) / np.sqrt(a.size), cov
+
+
+@pytest.mark.parametrize("mu", [1e-3, 0.05])
+def test_mutations_flip_each_locus_with_probability_mu(mu):
+    # every parent homozygous 0: a newborn's 1 bits are exactly its gametes'
+    # mutations, K ~ Binomial(L, mu) distinct loci per gamete, so each locus
+    # flips with probability mu and a gamete's count has variance L mu (1 - mu)
+    L = 1000
+    say("mutation statistics mu", mu)
+    d = dict(seed=41, replicate_id=2, regime=0, n0=N, capacity=N, n_loci=L, mu=mu, r=0.5, theta=0.0, omega=0.0,
+             K=0.0, fecundity=0.0)
+    pop = spegg.Population([d])
+    pop.write_genomes(0, np.zeros((N, 2, (L + 31) // 32), np.uint32), 3)
+    pop.step(1)
+    g = pop.genomes(0)
+    pop.close()
+    bits = np.unpackbits(np.ascontiguousarray(g).view(np.uint8), bitorder="little").reshape(N, 2, -1)
+    assert not bits[:, :, L:].any()
+    per_gamete = bits[:, :, :L].reshape(2 * N, L).sum(axis=1)
+    m = 2 * N * L
+    frac = per_gamete.sum() / m
+    assert abs(frac - mu) < 6 * np.sqrt(mu * (1 - mu) / m), frac
+    var = L * mu * (1 - mu)
+    assert abs(per_gamete.var() - var) < 6 * np.sqrt((2 * var * var + var) / per_gamete.size), per_gamete.var()
+
+
+def test_wright_fisher_parents_are_uniform_over_the_adults():
+    # no selection: every adult survives, and each newborn's mother and father
+    # are uniform over the N adults, so an adult's offspring count is
+    # Binomial(2N, 1/N): mean 2, variance 2 (1 - 1/N)
+    L = 64
+    d = dict(seed=43, replicate_id=3, regime=0, n0=N, capacity=N, n_loci=L, mu=0.0, r=0.5, theta=0.0, omega=0.0,
+             K=0.0, fecundity=0.0)
+    pop = spegg.Population([d])
+    pop.set_trace(True)
+    pop.step(1)
+    mom, dad = pop.parents(0)
+    assert pop.stats()[0]["n_survivors"] == N
+    pop.close()
+    assert mom.size == N and dad.size == N and mom.max() < N and dad.max() < N
+    kids = np.bincount(mom, minlength=N) + np.bincount(dad, minlength=N)
+    assert kids.sum() == 2 * N
+    var = 2.0 * (1 - 1.0 / N)
+    assert abs(kids.var() - var) < 6 * np.sqrt((2 * var * var + var) / N), kids.var()
+    # mothers and fathers drawn independently
+    assert abs(np.corrcoef(mom.astype(np.float64), dad.astype(np.float64))[0, 1]) < 6 / np.sqrt(N)
