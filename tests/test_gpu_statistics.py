@@ -1,5 +1,6 @@
 """Statistical checks of the HIP library against the model itself, not
-against the oracle: crossovers, mutations and Wright-Fisher parents.
+against the oracle: crossovers, mutations, Wright-Fisher parents, and
+survival and fecundity in the Poisson / Beverton-Holt regime.
 
 Crossovers: with every parent heterozygous at every locus (one
 haplotype all 0, the other all 1), no mutation and no selection, a change of
@@ -116,3 +117,24 @@ def test_wright_fisher_parents_are_uniform_over_the_adults():
     assert abs(kids.var() - var) < 6 * np.sqrt((2 * var * var + var) / N), kids.var()
     # mothers and fathers drawn independently
     assert abs(np.corrcoef(mom.astype(np.float64), dad.astype(np.float64))[0, 1]) < 6 / np.sqrt(N)
+
+
+def test_poisson_bh_survival_and_fecundity_match_the_model():
+    # every adult has phenotype z = 0 (heterozygous at every locus, unit
+    # effects): it survives with probability v(0) s(N), Gaussian viability
+    # v(z) = exp(-(z - theta)^2 / (2 omega^2)) times the Beverton-Holt factor
+    # s(N) = 1 / (1 + (lambda - 1) N / K), and each survivor leaves
+    # Poisson(lambda) newborns
+    L, theta, omega, lam, K = 256, 5.0, 10.0, 2.2, float(N)
+    d = dict(seed=47, replicate_id=4, regime=1, n0=N, capacity=4 * N, n_loci=L, mu=0.0, r=0.5, theta=theta,
+             omega=omega, K=K, fecundity=lam)
+    pop = spegg.Population([d])
+    pop.write_genomes(0, het_parents(N, L), 5)
+    pop.step(1)
+    st = pop.stats()[0]
+    pop.close()
+    p = np.exp(-(theta ** 2) / (2 * omega ** 2)) / (1 + (lam - 1) * N / K)
+    S = st["n_survivors"]
+    assert abs(S - N * p) < 6 * np.sqrt(N * p * (1 - p)), (S, N * p)
+    assert st["truncated"] == 0
+    assert abs(st["n"] - lam * S) < 6 * np.sqrt(lam * S), (st["n"], lam * S)
