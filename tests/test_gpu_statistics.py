@@ -1,6 +1,7 @@
 """Statistical checks of the HIP library against the model itself, not
-against the oracle: crossovers, mutations, Wright-Fisher parents, and
-survival and fecundity in the Poisson / Beverton-Holt regime.
+against the oracle: crossovers, mutations, Wright-Fisher parents, survival
+and fecundity in the Poisson / Beverton-Holt regime, and migration on a
+ring of patches.
 
 Crossovers: with every parent heterozygous at every locus (one
 haplotype all 0, the other all 1), no mutation and no selection, a change of
@@ -138,3 +139,26 @@ def test_poisson_bh_survival_and_fecundity_match_the_model():
     assert abs(S - N * p) < 6 * np.sqrt(N * p * (1 - p)), (S, N * p)
     assert st["truncated"] == 0
     assert abs(st["n"] - lam * S) < 6 * np.sqrt(lam * S), (st["n"], lam * S)
+
+
+def test_ring_migrants_at_rate_m_split_evenly():
+    # patches on a ring, all with survivors: a newborn's parents come from a
+    # ring neighbour with probability m, either side with probability 1/2
+    # (Supplementary Information S3)
+    P, n, m = 4, 8000, 0.1
+    d = dict(seed=53, replicate_id=6, regime=0, n0=n, capacity=n, n_loci=64, mu=0.0, r=0.5, theta=0.0, omega=0.0,
+             K=0.0, fecundity=0.0, n_patches=P, migration=m)
+    pop = spegg.Population([d])
+    pop.set_trace(True)
+    pop.step(1)
+    moved = right = total = 0
+    for k in range(P):
+        _, _, src = pop.parents(0, patch=k, with_source=True)
+        total += src.size
+        moved += int(np.count_nonzero(src != k))
+        right += int(np.count_nonzero(src == (k + 1) % P))
+        assert np.all((src == k) | (src == (k + 1) % P) | (src == (k - 1) % P))
+    pop.close()
+    assert total == P * n
+    assert abs(moved / total - m) < 6 * np.sqrt(m * (1 - m) / total), moved / total
+    assert abs(right / moved - 0.5) < 6 * np.sqrt(0.25 / moved), right / moved
