@@ -75,7 +75,7 @@ typedef enum {
     SPEGG_E_NOMEM = -2,       /* the caller's workspace is too small or misaligned */
     SPEGG_E_DEVICE = -3,      /* a HIP call failed; the handle is now sticky-errored */
     SPEGG_E_STATE = -4,       /* the handle is errored, or the call needs a mode that is off */
-    SPEGG_E_UNSUPPORTED = -5  /* valid model, but outside what this build implements */
+    SPEGG_E_UNSUPPORTED = -5  /* valid model, but outside what this library implements */
 } spegg_status;
 
 typedef enum {
