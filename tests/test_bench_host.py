@@ -1,10 +1,12 @@
 """Host-side contract of bench.py (no GPU): one GPU only, the algorithmic
-byte count per genotype-locus update, host description."""
+byte count per genotype-locus update, host description, the CPU-baseline
+block."""
 import os
 import subprocess
 import sys
 
 import bench
+from paper_1603_09255_amd import workloads
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -41,3 +43,13 @@ def test_measured_traffic_is_keyed_to_sources_and_shape():
         assert bench.measured_traffic_per_update(shape) == bench.MEASURED_TRAFFIC["bytes_per_update"]
     else:
         assert bench.measured_traffic_per_update(shape) is None
+
+
+def test_cpu_baseline_block_is_the_oracle_on_a_bounded_sample():
+    desc, _ = workloads.plain_small(seed=3)
+    cb = bench.cpu_baseline(desc, 0.2)
+    assert set(cb) >= {"value", "unit", "cores", "kind", "sample"}
+    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["unit"] == bench.UNIT
+    assert cb["value"] > 0
+    gens = int(cb["sample"].split()[0])
+    assert 1 <= gens <= 200
