@@ -40,7 +40,8 @@
  *
  * Randomness: Philox4x32-10 keyed by the replicate's 64-bit seed, with
  * counter (index, stream << 24 | block, generation, replicate_id << 12 |
- * patch).  No counter field encodes a batch position, a thread or a tile,
+ * species << 10 | patch); species is 0 outside the consumer-resource
+ * regime.  No counter field encodes a batch position, a thread or a tile,
  * so a replicate's trajectory is the same alone or in any batch.
  *
  * Memory: the caller owns the device memory (one block of
@@ -371,6 +372,17 @@ void spegg_server_destroy(spegg_server *srv);
  * 2: geometric crossover gaps for r = a over b entries.  Returns the length,
  * or -1 if cap is too small or the arguments are invalid. */
 int spegg_threshold_table(int kind, double a, uint32_t b, uint64_t *out, int cap);
+
+/* Host-only test hook: the geometric gap the offspring kernel draws from
+ * word x for crossover probability r (0 < r < 1/2) in a genome of n_loci
+ * (>= 2) loci, starting its table search from the first guess `guess`: the
+ * smallest k with x < T_k, T_k = floor((1 - (1-r)^(k+1)) 2^32) (Supplementary
+ * S2, "Genetics": crossovers at independent boundaries; the gap between
+ * crossovers is geometric), over the table the kernel holds -- its entries
+ * before the first T_k of 2^32, as 32-bit words -- or the table's length when
+ * x reaches every entry.  *gap gets the gap; returns that table length, or
+ * -1 for invalid arguments.  The result does not depend on the guess. */
+int spegg_geometric_gap(double r, uint32_t n_loci, uint32_t x, uint32_t guess, uint32_t *gap);
 
 /* Host-only: crossover-sampling mode for r (0 raw bits, r = 1/2; 1 none,
  * r = 0; 2 geometric skips, 0 < r < 0.17; 3 bit-serial comparison). */

@@ -10,11 +10,13 @@ from .oracle import (  # noqa: F401
     OraclePop,
     OracleStats,
     binomial_thresholds,
+    find_gap_word,
     geometric_thresholds,
     load,
     philox4x32_10,
     poisson_thresholds,
     prob_threshold,
     recomb_mode,
+    skip_gap,
     small_binomial_thresholds,
 )

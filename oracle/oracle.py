@@ -150,6 +150,10 @@ def load():
     lib.oracle_sample_gametes.restype = C.c_int
     lib.oracle_phenotype.argtypes = [vp, C.POINTER(C.c_uint8), C.POINTER(C.c_uint8)]
     lib.oracle_phenotype.restype = i32
+    lib.oracle_skip_gap.argtypes = [C.c_double, u32, u32]
+    lib.oracle_skip_gap.restype = u32
+    lib.oracle_find_gap_word.argtypes = [u64, u32, C.c_double, u32, u32, u32, u32, u32, P32]
+    lib.oracle_find_gap_word.restype = C.c_int
     _lib = lib
     return lib
 
@@ -197,6 +201,21 @@ def small_binomial_thresholds(n, q):
 
 def recomb_mode(r):
     return MODE_NAMES[load().oracle_recomb_mode(float(r))]
+
+
+def skip_gap(r, L, x):
+    """Geometric crossover gap of word x (smallest k with x < T_k, else L-1)."""
+    return int(load().oracle_skip_gap(float(r), int(L), int(x)))
+
+
+def find_gap_word(seed, c3, r, L, n_slots, t_begin, t_end, x_target):
+    """First (t, j, stream, word, boundary) whose gamete walk consumes
+    x_target with a crossover still to follow, or None.  Releases the GIL,
+    so disjoint generation ranges can be searched from several threads."""
+    out = np.zeros(5, dtype=np.uint32)
+    found = load().oracle_find_gap_word(int(seed), int(c3), float(r), int(L), int(n_slots), int(t_begin),
+                                        int(t_end), int(x_target), _p(out, C.c_uint32))
+    return tuple(int(v) for v in out) if found else None
 
 
 class OraclePop:

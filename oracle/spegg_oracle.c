@@ -535,6 +535,17 @@ static int lazy_crossover(rng_ctx *g, uint32_t j, uint32_t stream, uint32_t gen,
     return 0; /* U == R */
 }
 
+/* Geometric gap drawn by word x from the L-1 thresholds of the gap table:
+ * the smallest k with x < T_k, or L-1 when x reaches every entry (then the
+ * next crossover would lie past the last boundary). */
+static uint32_t skip_gap(const uint64_t *geo, uint32_t L, uint32_t x)
+{
+    uint32_t gap = 0;
+    while (gap + 1u < L && (uint64_t)x >= geo[gap])
+        ++gap;
+    return gap;
+}
+
 static void recombination_mask(const oracle_pop *P, rng_ctx *g, uint32_t j, uint32_t stream, uint32_t gen, uint8_t *mask,
                                uint8_t *toggles)
 {
@@ -556,11 +567,7 @@ static void recombination_mask(const oracle_pop *P, rng_ctx *g, uint32_t j, uint
         uint64_t b = 0;
         uint32_t q = 4;
         for (;;) {
-            uint32_t x = seq_word(g, j, stream, gen, q++);
-            uint32_t gap = 0; /* smallest k with x < T_k, else L - 1 */
-            while (gap + 1u < L && (uint64_t)x >= P->geo[gap])
-                ++gap;
-            b += 1u + gap;
+            b += 1u + skip_gap(P->geo, L, seq_word(g, j, stream, gen, q++));
             if (b > L - 1u)
                 break;
             toggles[b] = 1;
@@ -1081,3 +1088,68 @@ int oracle_sample_gametes(oracle_pop *P, const uint8_t *parent, uint32_t j0, uin
 
 /* The phenotype of given allele rows (for pins of the map). */
 int32_t oracle_phenotype(const oracle_pop *P, const uint8_t *h0, const uint8_t *h1) { return phenotype(P, h0, h1); }
+
+/* The geometric gap of word x for crossover probability r in a genome of L
+ * loci (tests compare the GPU library's lookup with it). */
+uint32_t oracle_skip_gap(double r, uint32_t L, uint32_t x)
+{
+    uint64_t *geo;
+    uint32_t gap;
+    if (L < 2)
+        return 0;
+    geo = (uint64_t *)malloc(sizeof(uint64_t) * (L - 1u));
+    oracle_geometric_thresholds(r, L - 1u, geo);
+    gap = skip_gap(geo, L, x);
+    free(geo);
+    return gap;
+}
+
+/* Search for a test case: over generations t in [t_begin, t_end), offspring
+ * slots j < n_slots and both gametes (RECOMB streams of mother and father)
+ * of a deme whose counter field is c3, walk the geometric-gap crossovers of
+ * a gamete of L loci at crossover probability r as recombination_mask does,
+ * and stop at the first consumed gap word equal to x_target after which
+ * the next crossover still falls on a boundary (b + 1 + gap <= L - 1).
+ * out = {t, j, stream, word index, boundary before the word}; returns 1 if
+ * found, else 0.  A test-fixture generator: it draws the oracle's own
+ * words and uses the oracle's own table. */
+int oracle_find_gap_word(uint64_t seed, uint32_t c3, double r, uint32_t L, uint32_t n_slots, uint32_t t_begin,
+                         uint32_t t_end, uint32_t x_target, uint32_t out[5])
+{
+    uint64_t *geo;
+    rng_ctx g;
+    uint32_t t, j, s;
+    if (L < 2)
+        return 0;
+    geo = (uint64_t *)malloc(sizeof(uint64_t) * (L - 1u));
+    oracle_geometric_thresholds(r, L - 1u, geo);
+    g.key[0] = (uint32_t)seed;
+    g.key[1] = (uint32_t)(seed >> 32);
+    g.c3 = c3;
+    g.memo_valid = 0;
+    for (t = t_begin; t < t_end; ++t)
+        for (j = 0; j < n_slots; ++j)
+            for (s = ST_RECOMB_MAT; s <= ST_RECOMB_PAT; ++s) {
+                uint64_t b = 0;
+                uint32_t q = 4;
+                for (;;) {
+                    uint32_t x = seq_word(&g, j, s, t, q);
+                    uint32_t gap = skip_gap(geo, L, x);
+                    if (x == x_target && b + 1u + gap <= L - 1u) {
+                        out[0] = t;
+                        out[1] = j;
+                        out[2] = s;
+                        out[3] = q;
+                        out[4] = (uint32_t)b;
+                        free(geo);
+                        return 1;
+                    }
+                    ++q;
+                    b += 1u + gap;
+                    if (b > L - 1u)
+                        break;
+                }
+            }
+    free(geo);
+    return 0;
+}

@@ -197,25 +197,21 @@ __device__ __forceinline__ uint32_t table_draw_global(const uint64_t *__restrict
     return lo;
 }
 
-// Number of geometric-gap thresholds T[0..len) (len >= 1) that are <= x: the gap of
-// the inverse-CDF draw.  T is the block's copy in LDS (every threshold is
-// below 2^32).  A float guess floor(log2(1 - x/2^32) / log2(1 - r)), with
-// 2^32 - x = ~x + 1, is corrected against the table, so the table alone
-// decides.
+// Geometric gap of word x (the smallest k with x < T_k, or len): T is the
+// block's LDS copy of the gap table up to its first threshold of 2^32, whose
+// entries all fit 32 bits (len >= 1).  A float guess floor(log2(1 - x/2^32) /
+// log2(1 - r)), with 2^32 - x = ~x + 1, is checked against its two table
+// neighbours and corrected when it is off, so the table alone decides.
 __device__ __forceinline__ uint32_t geometric_gap(const uint32_t *T, uint32_t len, float scale, uint32_t x) {
     const float lg = __log2f((float)(~x) + 1.0f) - 32.0f;
     const float guess = lg * scale;
-    uint32_t g = guess >= (float)len ? len : (guess > 0.0f ? (uint32_t)guess : 0u);
+    const uint32_t g = guess >= (float)len ? len : (guess > 0.0f ? (uint32_t)guess : 0u);
     // both neighbours read unconditionally (indices clamped into the table,
     // which holds at least one threshold)
     const uint32_t t_lo = T[g == 0 ? 0u : g - 1u], t_hi = T[g < len ? g : len - 1u];
     const bool low_ok = g == 0 || t_lo <= x;
     const bool high_ok = g == len || x < t_hi;
-    if (!(low_ok && high_ok)) {
-        while (g > 0 && T[g - 1] > x) --g;
-        while (g < len && T[g] <= x) ++g;
-    }
-    return g;
+    return (low_ok && high_ok) ? g : geometric_gap_fix(T, len, g, x);
 }
 
 // Index of the current census pair: the one with the larger generation.
@@ -417,7 +413,8 @@ template <int IT>
 __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restrict__ descs,
                                                          const RepState *__restrict__ states,
                                                          const SurvTile *__restrict__ tiles,
-                                                         SurvCount *__restrict__ counts, int single_deme) {
+                                                         SurvCount *__restrict__ counts,
+                                                         SurvGroup *__restrict__ groups, int single_deme) {
     __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_n[kBlock / 64], sh_i[kBlock / 64];
     __shared__ uint64_t sh_t[kBlock / 64];
     __shared__ uint64_t sh_pois[kPoissonTableCap];
@@ -535,6 +532,17 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
         c.t = t;
         c.n = n;
         counts[blockIdx.x] = c;
+        // a census of more than one tile group: the tile's counts into its
+        // group's sums as well
+        const uint32_t active = (n + kBlock * IT - 1) / (kBlock * IT);
+        if (active > kGroupTiles) {
+            SurvGroup &g = groups[d.grp0 + (t & 1u) * d.grp_n + (blockIdx.x - d.surv_tile0) / kGroupTiles];
+            if (c.alive) atomicAdd(&g.alive, c.alive);
+            if (c.kids) atomicAdd((unsigned long long *)&g.kids, (unsigned long long)c.kids);
+            if (c.near) atomicAdd(&g.near, c.near);
+            if (c.sum_t) atomicAdd((unsigned long long *)&g.sum_t, (unsigned long long)c.sum_t);
+            if (c.intake) atomicAdd(&g.intake, c.intake);
+        }
     }
 }
 
@@ -543,12 +551,16 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
 // One block per tile: its prefix is summed from the counts of the
 // replicate's earlier tiles (written by survive, a launch earlier), then
 // block ranks place its survivors and its mothers' offspring slots.  Tile 0
-// of each replicate sums all the tiles and advances the census.
+// of each replicate sums all the tiles and advances the census.  A census
+// of more than kGroupTiles tiles also has group sums (survive added each
+// tile into its group): a tile then sums the earlier groups and the earlier
+// tiles of its own group, at most one load per thread each.
 template <int IT>
 __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restrict__ descs,
                                                          RepState *__restrict__ states,
                                                          const SurvTile *__restrict__ tiles,
-                                                         const SurvCount *__restrict__ counts, int trace,
+                                                         const SurvCount *__restrict__ counts,
+                                                         SurvGroup *__restrict__ groups, int trace,
                                                          int single_deme) {
     constexpr uint32_t TILE = kBlock * IT;
     __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_in[kBlock / 64];
@@ -564,34 +576,59 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     load_fates<IT>(d.fate + i0, fate);
     const SurvCount *C = counts + d.surv_tile0;
     const uint32_t k = blockIdx.x - d.surv_tile0;  // tile index within the replicate
+    const uint32_t kg0 = k - k % kGroupTiles;      // first tile of its group
     // exclusive prefix of this tile (tile 0: the totals, with the census
-    // statistics only it records).  Past tile 0 the span is the tiles before
-    // this one, known from the block index: those loads go out with the
+    // statistics only it records).  Past tile 0 the tiles of its own group
+    // before it are known from the block index: those loads go out with the
     // census header's.
     uint32_t pa = 0, pi = 0;
     uint64_t pk = 0, pn = 0, pt = 0;
-    if (k != 0)
-        for (uint32_t q = threadIdx.x; q < k; q += kBlock) {
-            const SurvCount c = C[q];
-            pa += c.alive;
-            pk += c.kids;
-        }
+    if (k != 0 && threadIdx.x < k - kg0) {
+        const SurvCount c = C[kg0 + threadIdx.x];
+        pa += c.alive;
+        pk += c.kids;
+    }
     // the census this generation started from, as survive recorded it: tile 0
     // of this launch rewrites the state's other pair
     const SurvCount c0 = C[0];
     const uint32_t par = c0.par, t = c0.t, n = c0.n;
     const uint32_t active = (n + TILE - 1) / TILE;
     if (k >= active && k != 0) return;  // beyond the census: uniform over the block
+    const bool grouped = active > kGroupTiles;
+    const SurvGroup *G = groups + d.grp0 + (t & 1u) * d.grp_n;
     const uint32_t wave = threadIdx.x >> 6;
-    if (k == 0)
-        for (uint32_t q = threadIdx.x; q < active; q += kBlock) {
-            const SurvCount c = C[q];
-            pa += c.alive;
-            pk += c.kids;
-            pn += c.near;
-            pt += c.sum_t;
-            pi += c.intake;
+    if (k == 0) {
+        if (grouped) {
+            for (uint32_t q = threadIdx.x; q * kGroupTiles < active; q += kBlock) {
+                const SurvGroup g = G[q];
+                pa += g.alive;
+                pk += g.kids;
+                pn += g.near;
+                pt += g.sum_t;
+                pi += g.intake;
+            }
+        } else {
+            for (uint32_t q = threadIdx.x; q < active; q += kBlock) {
+                const SurvCount c = C[q];
+                pa += c.alive;
+                pk += c.kids;
+                pn += c.near;
+                pt += c.sum_t;
+                pi += c.intake;
+            }
         }
+        // The other parity's group sums start the next generation from zero,
+        // whether or not this census used groups (a later census of the
+        // same parity may).
+        SurvGroup *Gn = groups + d.grp0 + ((t + 1u) & 1u) * d.grp_n;
+        for (uint32_t q = threadIdx.x; q < d.grp_n; q += kBlock) Gn[q] = SurvGroup{0, 0, 0, 0, 0, 0};
+    } else {
+        for (uint32_t q = threadIdx.x; q < kg0 / kGroupTiles; q += kBlock) {  // the earlier groups
+            const SurvGroup g = G[q];
+            pa += g.alive;
+            pk += g.kids;
+        }
+    }
     pa = wave_sum<uint32_t>(pa);
     pk = wave_sum<uint64_t>(pk);
     if (k == 0) {  // uniform over the block
@@ -838,10 +875,15 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
             const uint32_t p0 = draw(0, 0), p1 = draw(0, 1), p2 = draw(0, 2), p3 = draw(0, 3);
             uint32_t mom = d.regime == SPEGG_WF ? gload(sd_src.S + uniform_index(p0, p1, ns)) : gload(d.owner + j);
             uint32_t dad = gload(sd_src.S + uniform_index(p2, p3, ns));
-            // parents are adults of the last census; the clamp never changes a
-            // correct index and keeps every gather inside the buffer
-            mom = mom < nprev ? mom : nprev - 1u;
-            dad = dad < nprev ? dad : nprev - 1u;
+            // Parents are adults of the last census.  An index beyond it means
+            // a broken survivor or slot list: the deme is flagged (the next
+            // census read reports it as a device error) and the index clamped
+            // only so that the gather stays inside the buffer.
+            if (mom >= nprev || dad >= nprev) {
+                atomicOr(const_cast<uint32_t *>(&st.error), 1u);
+                mom = mom < nprev ? mom : nprev - 1u;
+                dad = dad < nprev ? dad : nprev - 1u;
+            }
             f.j = j;
             // the traced parents leave now rather than staying live in
             // registers through the newborn
@@ -1221,6 +1263,11 @@ __global__ void fill_u8_kernel(uint8_t *p, uint32_t n) {
     if (i < n) p[i] = 0;
 }
 
+__global__ void fill_u32_kernel(uint32_t *p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 // ---------------------------------------------------------------- allele counts
 
 // Copies of allele 1 at each locus over the current census (2N genes per
@@ -1322,10 +1369,10 @@ hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t 
 hipError_t launch_survive(const SelArgs &a) {
     if (a.items == 4)
         hipLaunchKernelGGL(survive_kernel<4>, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles,
-                           a.counts, a.single_deme);
+                           a.counts, a.groups, a.single_deme);
     else if (a.items == 1)
         hipLaunchKernelGGL(survive_kernel<1>, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles,
-                           a.counts, a.single_deme);
+                           a.counts, a.groups, a.single_deme);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1334,10 +1381,10 @@ hipError_t launch_survive(const SelArgs &a) {
 hipError_t launch_compact(const SelArgs &a) {
     if (a.items == 4)
         hipLaunchKernelGGL(compact_kernel<4>, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles,
-                           a.counts, a.trace, a.single_deme);
+                           a.counts, a.groups, a.trace, a.single_deme);
     else if (a.items == 1)
         hipLaunchKernelGGL(compact_kernel<1>, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles,
-                           a.counts, a.trace, a.single_deme);
+                           a.counts, a.groups, a.trace, a.single_deme);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1386,6 +1433,12 @@ hipError_t launch_fill_u64(uint64_t *p, uint32_t n, hipStream_t s) {
 hipError_t launch_fill_u8(uint8_t *p, uint32_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(fill_u8_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -77,6 +77,7 @@ struct DemePlan {
     uint32_t rep = 0, patch = 0, species = 0;
     uint32_t n0 = 0, cap = 0;
     uint32_t surv_tile0 = 0, surv_ntiles = 0, off_tile0 = 0, off_ntiles = 0;
+    uint32_t grp0 = 0, grp_n = 0;  // tile-group sums (two parities of grp_n records)
     size_t genome[2] = {0, 0}, z[2] = {0, 0}, fate = 0, S = 0, owner = 0, mom = 0, dad = 0, src = 0;
     size_t age[2] = {0, 0}, won = 0, intake = 0;
 };
@@ -105,7 +106,8 @@ struct Plan {
     std::vector<OffTile> off_tiles;
     size_t descs = 0, states = 0, surv_tiles_at = 0, off_tiles_at = 0, enc_tiles_at = 0, carry_tiles_at = 0;
     size_t static_end = 0;  // [0, static_end) is uploaded at create
-    size_t surv_counts = 0, partials = 0, total = 0;
+    size_t surv_counts = 0, surv_groups = 0, partials = 0, total = 0;
+    uint32_t n_groups = 0;  // tile-group records, both parities
     uint32_t surv_items = 1;  // adults per thread in survive and compact
 };
 
@@ -257,7 +259,11 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const Gc
     if (d.regime == SPEGG_POISSON_BH && !poisson_table(d.fecundity, kPoissonTableCap, p.pois))
         return fail(SPEGG_E_UNSUPPORTED, "replicate %u: fecundity %g needs more than %d table entries", i,
                     d.fecundity, kPoissonTableCap);
-    if (p.mode == kModeSkip && L > 1) geometric_table(d.r, L - 1u, p.geo);
+    if (p.mode == kModeSkip && L > 1) {
+        // the kernel keeps the gap table up to its first threshold of 2^32
+        geometric_table(d.r, L - 1u, p.geo);
+        p.geo.resize(geometric_device_len(p.geo));
+    }
     int gcap = offspring_gcap(p.W);
     if (gcaps) {
         const auto it = gcaps->find(p.W);
@@ -323,6 +329,9 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         DemePlan &q = P.demes[u];
         q.surv_tile0 = (uint32_t)P.surv_tiles.size();
         q.surv_ntiles = (q.cap + surv_tile - 1) / surv_tile;
+        q.grp0 = P.n_groups;
+        q.grp_n = q.surv_ntiles > kGroupTiles ? (q.surv_ntiles + kGroupTiles - 1) / kGroupTiles : 0u;
+        P.n_groups += 2u * q.grp_n;
         for (uint32_t k = 0; k < q.surv_ntiles; ++k) {
             const SurvTile tile{u, k * surv_tile};
             P.surv_tiles.push_back(tile);
@@ -391,6 +400,7 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
     }
     P.static_end = cv.off;
     P.surv_counts = cv.take(sizeof(SurvCount) * P.surv_tiles.size());
+    P.surv_groups = cv.take(sizeof(SurvGroup) * (P.n_groups ? P.n_groups : 1u));
     P.partials = cv.take(sizeof(Partial) * max_off_tiles);
     for (DemePlan &q : P.demes) {
         const RepPlan &p = P.reps[q.rep];
@@ -491,6 +501,7 @@ struct spegg_pop {
     SurvTile *d_surv_tiles() { return at<SurvTile>(base, plan.surv_tiles_at); }
     OffTile *d_off_tiles() { return at<OffTile>(base, plan.off_tiles_at); }
     SurvCount *d_surv_counts() { return at<SurvCount>(base, plan.surv_counts); }
+    SurvGroup *d_surv_groups() { return at<SurvGroup>(base, plan.surv_groups); }
     Partial *d_partials() { return at<Partial>(base, plan.partials); }
 };
 
@@ -657,8 +668,9 @@ hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
     const SurvTile *enc_tiles = at<SurvTile>(pop->base, P.enc_tiles_at);
     const SurvTile *carry_tiles = at<SurvTile>(pop->base, P.carry_tiles_at);
     for (uint32_t g = 0; g < n; ++g) {
-        const SelArgs sa{pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), pop->d_surv_counts(), ns_tiles, trace,
-                         pop->n_demes == 1 ? 0 : -1, (int)P.surv_items, pop->stream};
+        const SelArgs sa{pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), pop->d_surv_counts(),
+                         pop->d_surv_groups(), ns_tiles, trace, pop->n_demes == 1 ? 0 : -1, (int)P.surv_items,
+                         pop->stream};
         hipError_t e = hipSuccess;
         if (!P.enc_tiles.empty())
             e = timed(pop, SPEGG_KERNEL_ENCOUNTER, [&] {
@@ -789,6 +801,8 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.surv_tile0 = q.surv_tile0;
         h.surv_tile = kBlock * P.surv_items;
         h.surv_ntiles = q.surv_ntiles;
+        h.grp0 = q.grp0;
+        h.grp_n = q.grp_n;
         h.off_tile0 = q.off_tile0;
         h.off_ntiles = q.off_ntiles;
         h.off_per_tile = p.opt;
@@ -866,6 +880,14 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
     if (e != hipSuccess) {
         delete pop;
         return fail(SPEGG_E_DEVICE, "hipMemcpyAsync(tables): %s", hipGetErrorString(e));
+    }
+    // tile-group sums start from zero (the kernels keep them so afterwards)
+    if (P.n_groups)
+        e = launch_fill_u32((uint32_t *)pop->d_surv_groups(), (size_t)P.n_groups * sizeof(SurvGroup) / sizeof(uint32_t),
+                            pop->stream);
+    if (e != hipSuccess) {
+        delete pop;
+        return fail(SPEGG_E_DEVICE, "tile groups: %s", hipGetErrorString(e));
     }
     // every deme's initial population in one launch
     e = launch_create(pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), (uint32_t)P.surv_tiles.size(),
@@ -1012,6 +1034,11 @@ spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, u
     if (e == hipSuccess) e = hipMemcpyAsync(pop->d_states() + u, &s0, sizeof s0, hipMemcpyHostToDevice, pop->stream);
     if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + u, pop->d_states() + u, n, buf, pop->stream);
     if (e == hipSuccess) e = reset_species_state(pop, u);
+    // the census restarts at an arbitrary generation: both parities of the
+    // deme's tile-group sums from zero
+    if (e == hipSuccess && h.grp_n)
+        e = launch_fill_u32((uint32_t *)(pop->d_surv_groups() + h.grp0),
+                            (size_t)2u * h.grp_n * sizeof(SurvGroup) / sizeof(uint32_t), pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "write_genomes");
     st = sync_stream(pop);
     if (st == SPEGG_OK) pop->deme_gen[u] = generation;
@@ -1375,6 +1402,19 @@ int spegg_threshold_table(int kind, double a, uint32_t b, uint64_t *out, int cap
 }
 
 int spegg_recomb_mode(double r) { return (int)recomb_mode(r); }
+
+int spegg_geometric_gap(double r, uint32_t n_loci, uint32_t x, uint32_t guess, uint32_t *gap) {
+    if (!gap || !(r > 0.0 && r < 0.5) || n_loci < 2 || n_loci > SPEGG_MAX_LOCI) return -1;
+    // the table as the offspring kernel holds it: up to the first threshold
+    // of 2^32, narrowed to 32-bit words
+    std::vector<uint64_t> T;
+    geometric_table(r, n_loci - 1u, T);
+    const uint32_t len = geometric_device_len(T);
+    if (len == 0) return -1;
+    std::vector<uint32_t> T32(T.begin(), T.begin() + len);
+    *gap = geometric_gap_fix(T32.data(), len, guess, x);
+    return (int)len;
+}
 
 spegg_status spegg_philox_fill(uint64_t seed, const uint32_t *ctr_dev, uint32_t *out_dev, uint32_t n,
                                void *hip_stream) {

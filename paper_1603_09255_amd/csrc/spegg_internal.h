@@ -39,6 +39,20 @@ enum Stream : uint32_t {
 // Crossover sampling, a function of r alone.
 enum Mode : uint32_t { kModeRaw = 0, kModeZero = 1, kModeSkip = 2, kModeLazy = 3 };
 
+// Geometric gap drawn by word x: the number of thresholds T[0..len) that are
+// <= x, i.e. the smallest k with x < T_k, or len when x reaches them all.  T
+// holds the entries of the gap table below its first threshold of 2^32 (a
+// word is always below that one), as 32-bit words, nondecreasing.  g is a
+// first guess in [0, len]; the table alone decides, so any guess gives the
+// same result.  constexpr: the offspring kernel and the host test hook run
+// this one definition.
+constexpr uint32_t geometric_gap_fix(const uint32_t *T, uint32_t len, uint32_t g, uint32_t x) {
+    if (g > len) g = len;
+    while (g > 0 && T[g - 1] > x) --g;
+    while (g < len && T[g] <= x) ++g;
+    return g;
+}
+
 constexpr double kSkipBelow = 0.17;  // r < 0.17: geometric gaps; above: bit-serial Bernoulli
 
 constexpr int kBlock = 256;          // threads per block in every kernel
@@ -55,7 +69,7 @@ struct RepDesc {
     uint32_t L, W, cap, regime;
     uint32_t key0, key1, c3, mode;
     uint32_t R;          // floor(r 2^32), bit-serial mode
-    uint32_t geo_len;    // L - 1 (skip mode)
+    uint32_t geo_len;    // skip mode: gap thresholds kept, those of the L - 1 before the first 2^32
     uint32_t binom_len, pois_len;
     uint64_t binom0;     // binom[0]: a gamete draws no mutation when x < binom0
     int32_t zmin;        // vtab[z - zmin]
@@ -65,6 +79,7 @@ struct RepDesc {
     uint32_t tail_mask;  // valid bits of word W-1
     uint32_t surv_tile0, surv_ntiles;
     uint32_t surv_tile;  // adults per survival tile of the population (kBlock x adults per thread)
+    uint32_t grp0, grp_n;  // the deme's tile groups: first record, records per parity (0: one group suffices)
     uint32_t off_tile0, off_ntiles, off_per_tile;  // offspring tiles: global index of the first
     float geo_scale;     // 1 / log2(1 - r): first guess of a geometric gap (checked against geo)
     double K, lambda;    // Beverton-Holt density factor; 0 < K enables it
@@ -132,6 +147,18 @@ struct SurvCount {
     uint32_t intake, pad;  // consumers: credited captures of the tile's adults
 };
 
+// Sums over a group of kGroupTiles consecutive survival tiles of a deme, for
+// demes whose census spans more than one group: survive adds each tile's
+// counts (atomics, one per nonzero field), compact reads whole groups, so a
+// tile's prefix costs at most one load per thread of a group's tiles plus
+// one per earlier group.  Double-buffered by the parity of the census
+// generation: compact clears the other parity, which the next survive fills.
+constexpr uint32_t kGroupTiles = 256;
+struct SurvGroup {
+    uint64_t kids, sum_t;
+    uint32_t alive, near, intake, pad;
+};
+
 struct OffTile {
     uint32_t rep, start;
 };
@@ -189,6 +216,7 @@ struct SelArgs {
     RepState *states;
     const SurvTile *tiles;
     SurvCount *counts;
+    SurvGroup *groups;
     uint32_t ntiles;
     int trace;
     int single_deme;  // >= 0: the population's only deme, whose tiles are implicit
@@ -235,6 +263,8 @@ hipError_t launch_carry(const RepDesc *descs, const RepState *states, const Surv
 // generation) and n bytes with 0 (ages).
 hipError_t launch_fill_u64(uint64_t *p, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint32_t n, hipStream_t s);
+// Clear n 32-bit words (a fill kernel, so it may sit in captured work).
+hipError_t launch_fill_u32(uint32_t *p, size_t n, hipStream_t s);
 // Fold pending per-tile census sums into each replicate's state.
 hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *partials, uint32_t n_reps,
                          hipStream_t s);

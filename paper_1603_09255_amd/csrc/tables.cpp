@@ -73,6 +73,12 @@ void geometric_table(double r, uint32_t n, std::vector<uint64_t> &T) {
     for (uint32_t k = 0; k < n; ++k) T[k] = (uint64_t)floorl((1.0L - powl(q, (long double)(k + 1u))) * kTwo32);
 }
 
+uint32_t geometric_device_len(const std::vector<uint64_t> &T) {
+    uint32_t k = 0;
+    while (k < T.size() && T[k] < kAlways) ++k;
+    return k;
+}
+
 uint32_t recomb_mode(double r) {
     if (r == 0.5) return kModeRaw;
     if (r == 0.0) return kModeZero;

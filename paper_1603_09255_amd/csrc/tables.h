@@ -13,6 +13,11 @@ namespace spegg {
 bool poisson_table(double lambda, int cap, std::vector<uint64_t> &T);
 bool binomial_table(uint32_t L, double mu, int cap, std::vector<uint64_t> &T);
 void geometric_table(double r, uint32_t n, std::vector<uint64_t> &T);
+// Entries of a geometric-gap table the offspring kernel holds: those before
+// the first threshold of 2^32.  Every word x is below that threshold, so the
+// smallest k with x < T_k never lies beyond it, and the entries the kernel
+// keeps (as 32-bit words in LDS) are all below 2^32.
+uint32_t geometric_device_len(const std::vector<uint64_t> &T);
 uint32_t recomb_mode(double r);
 // Bernoulli(p) threshold floor(p 2^32); p >= 1: 2^32 (always), p <= 0: 0.
 uint64_t prob_threshold(double p);

@@ -144,6 +144,8 @@ def load():
     lib.spegg_threshold_table.argtypes = [C.c_int, C.c_double, u32, C.POINTER(C.c_uint64), C.c_int]
     lib.spegg_recomb_mode.restype = C.c_int
     lib.spegg_recomb_mode.argtypes = [C.c_double]
+    lib.spegg_geometric_gap.restype = C.c_int
+    lib.spegg_geometric_gap.argtypes = [C.c_double, u32, u32, u32, P32]
     lib.spegg_philox_fill.restype = st
     lib.spegg_philox_fill.argtypes = [C.c_uint64, vp, vp, u32, vp]
     lib.spegg_philox_rate.restype = st
@@ -244,6 +246,16 @@ def threshold_table(kind, a, b=0, cap=None):
 
 def recomb_mode(r):
     return {0: "raw", 1: "zero", 2: "skip", 3: "lazy"}[load().spegg_recomb_mode(float(r))]
+
+
+def geometric_gap(r, n_loci, x, guess):
+    """(gap, table length) the offspring kernel's gap lookup gives for word
+    x, searching from the first guess (host run of the same code)."""
+    g = C.c_uint32(0)
+    n = load().spegg_geometric_gap(float(r), int(n_loci), int(x), int(guess), C.byref(g))
+    if n < 0:
+        raise SpeggError(E_INVALID, "geometric_gap rejected its arguments")
+    return int(g.value), int(n)
 
 
 def philox_fill(seed, ctr):
