@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of the per-generation update on one MI355X.
 
-Workload: the plain method at scale -- one replicate, N0 = 100000 diploids
-(capacity 250000), L = 1024 loci packed in uint32 words, allelic effects on
-the integer grid [-4, 4], adjacent-locus crossover probability 0.01,
-mutation 1e-6 per locus, Poisson(2.2) fecundity with Beverton-Holt
-density-dependent survival (K = 100000) and Gaussian stabilising selection
-of width 64.  A step is one generation (survival, compaction, fecundity,
-parents, gametes, phenotypes, census) of that population; the data are
-synthetic (seeded Philox initial genomes).
+Default workload: the batched form -- 4096 Wright-Fisher replicates of
+uneven census N ~ U{500..50000} and genome length L in {64, 256, 1024}
+(bit-packed uint32 words), mu log-uniform in [1e-7, 1e-4], r ~ U[0.001,
+0.5], Gaussian stabilising selection of width ~ U[2, 16], all advanced
+together (Supplementary Fig. S5(B): one flattened loop over replicates and
+individuals).  A step is one generation of every replicate (survival,
+compaction, parents, gametes, phenotypes, census); the data are synthetic
+(seeded parameter table and Philox initial genomes).
 
-Prints one JSON line: genotype-locus updates/s (sum over timed generations
-of N_t x L, divided by wall time with inputs resident on the device), the
-roofline of the offspring kernel measured with HIP events in the timed
-region, and the CPU oracle timed on a bounded sample on the host.
+Prints one JSON line: genotype-locus updates/s (sum over the timed
+generations of N_t x L, divided by wall time with the populations resident
+on the device), the roofline of the dominant kernel (the offspring launches)
+from HIP events in a second pass, the plain per-replicate GPU loop on a
+sample, and the CPU oracle on a replicate subset on the host cores.
+Other workloads: --workload scale (one replicate at scale), small, ecology,
+serve.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -29,13 +33,13 @@ UNIT = "genotype-locus updates/s"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-# HBM bytes per genotype-locus update of the offspring kernel, from rocprofv3
+# HBM bytes per newborn of the dominant offspring launch, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE counters scaled by a device copy of known size
-# (profiles/offspring_plain_scale_hbm_traffic.md), valid only for the device
-# sources with this SHA-256 prefix and the offspring shape it was taken with
-# (lanes-per-gamete cap by genome words W).
-MEASURED_TRAFFIC = {"device_sources_sha256_16": "375815c25d6f5a30", "lanes_per_gamete_by_W": {32: 4},
-                    "bytes_per_update": 0.6804}
+# (profiles/*_hbm_traffic.md), by workload; each entry is valid only for the
+# device sources with its SHA-256 prefix and the offspring shapes it was
+# taken with (lanes-per-gamete cap by genome words W); otherwise the
+# traffic figure is null until re-measured.
+MEASURED_TRAFFIC = {}
 DEVICE_SOURCES = ("kernels.hip", "philox.h", "spegg_internal.h")
 
 
@@ -48,12 +52,14 @@ def device_sources_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic_per_update(tuned):
-    if device_sources_sha() != MEASURED_TRAFFIC["device_sources_sha256_16"]:
+def measured_traffic(workload, tuned):
+    """Counted HBM bytes per newborn of the dominant launch, or None."""
+    m = MEASURED_TRAFFIC.get(workload)
+    if m is None or device_sources_sha() != m["device_sources_sha256_16"]:
         return None
-    if dict(tuned) != MEASURED_TRAFFIC["lanes_per_gamete_by_W"]:
+    if {int(k): v for k, v in tuned.items()} != m["lanes_per_gamete_by_W"]:
         return None
-    return MEASURED_TRAFFIC["bytes_per_update"]
+    return m["bytes_per_newborn"]
 
 
 def log(*a):
@@ -156,12 +162,14 @@ def cpu_baseline(desc, budget_s):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000, help="timed generations")
-    ap.add_argument("--warmup", type=int, default=20, help="untimed generations first")
+    ap.add_argument("--steps", type=int, default=50, help="timed generations")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed generations first")
+    ap.add_argument("--cpu-reps", type=int, default=64, help="batched: replicates of the CPU oracle subset")
+    ap.add_argument("--cpu-gens", type=int, default=2, help="batched: generations of the CPU oracle subset")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["scale", "batched", "serve", "ecology", "small"], default="scale",
-                    help="scale: one replicate at scale (default); batched: the 4096-replicate batch; "
+    ap.add_argument("--workload", choices=["scale", "batched", "serve", "ecology", "small"], default="batched",
+                    help="batched: the 4096-replicate batch (default); scale: one replicate at scale; "
                          "small: the small parity configuration (launch- and latency-bound); "
                          "serve: sweep jobs arriving at random, served with continuous batching; "
                          "ecology: 64 replicates of the two-species consumer-resource form")
@@ -199,6 +207,14 @@ def main():
         return bench_ecology(args)
     if args.workload == "small":
         return bench_small(args)
+    return bench_scale(args)
+
+
+def bench_scale(args):
+    """One replicate at scale (Poisson(2.2) + Beverton-Holt, N0 = 1e5, L = 1024)."""
+    import torch
+
+    from paper_1603_09255_amd import spegg, workloads
 
     desc, _ = workloads.plain_scale(seed=1)
     L = desc["n_loci"]
@@ -210,6 +226,7 @@ def main():
     tuned = choose_shapes(pop, [desc], args.gcap, 4)
     log(f"bench: lanes per gamete by W: {tuned}; warmup {args.warmup} generations")
     pop.step(args.warmup)
+    pop.prepare_graphs()  # the graphs the timed region replays, captured before it
     torch.cuda.synchronize()
 
     # Timed region: K generations, nothing but the generation launches.
@@ -282,8 +299,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (None if measured_traffic_per_update(tuned) is None else
-                        measured_traffic_per_update(tuned) * updates_b / max(off_n, 1)),
+            "traffic": (None if measured_traffic("scale", tuned) is None else
+                        measured_traffic("scale", tuned) * updates_b / L / max(off_n, 1)),
             "traffic_unit": "HBM bytes per launch (rocprofv3 counters, scaled)",
             "bytes_per_update": bytes_per_update(L),
             "avg_launch_us": avg_launch_s * 1e6,
@@ -339,47 +356,157 @@ def bench_small(args):
     print(json.dumps(out), flush=True)
 
 
+ALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9  # VALU lane operations/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+PHILOX_OPS = 40  # VALU operations per Philox4x32-10 block: 10 rounds of 2 v_mad_u64_u32 + 2 v_bitop3_b32
+
+
+def offspring_bytes_per_newborn(L):
+    """Compulsory bytes of the offspring launch per newborn: the parental
+    genomes read once (L/4 per newborn when parents and newborns are as
+    many) and the newborn written once (L/4), two parent indices read and
+    the phenotype written (12 B)."""
+    return L / 2.0 + 12.0
+
+
+def recomb_mode(r):
+    return "raw" if r == 0.5 else "zero" if r == 0.0 else "skip" if r < 0.17 else "lazy"
+
+
+def philox_blocks_per_newborn(L, r, mu, migration=False):
+    """Expected Philox4x32-10 blocks the model's draws take per newborn in
+    the library's stream layout: one for the parents, one per gamete for
+    the mutation count, one for a migration draw; per gamete the crossover
+    words -- raw bits (one word per 32 loci), the phase block plus one word
+    per geometric gap (skip), or the phase block plus, per word of 32
+    boundaries, bit planes until every boundary is decided or R has no bit
+    left (bit-serial) -- and about two words per mutated locus."""
+    W = (L + 31) // 32
+    mode = recomb_mode(r)
+    if mode == "raw":
+        gam = math.ceil(W / 4)
+    elif mode == "zero":
+        gam = 1.0
+    elif mode == "skip":
+        gam = 1.0 + (r * (L - 1) + 1.0) / 4.0
+    else:
+        R = int(math.floor(r * 4294967296.0))
+        nsig = 32 - ((R & -R).bit_length() - 1)  # planes until R has no 1 bit left
+        gam = 1.0
+        for w in range(W):
+            b = min(32 * w + 32, L) - max(32 * w, 1)  # boundaries 32w .. 32w + 31 within 1 .. L - 1
+            if b <= 0:
+                continue
+            gam += sum(1.0 - (1.0 - 2.0 ** (-4 * m)) ** b if m else 1.0 for m in range((nsig + 3) // 4))
+    return 3.0 + (1.0 if migration else 0.0) + 2.0 * (gam + L * mu / 2.0)
+
+
+def cpu_baseline_batched(reps, n_sample, gens, threads):
+    """The oracle (plain serial loop per replicate) on an evenly spaced
+    subset of the replicates, replicates spread over host threads (ctypes
+    releases the interpreter lock for the oracle's calls)."""
+    import concurrent.futures
+
+    import oracle
+
+    keys = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
+            "fecundity", "effects", "n_patches", "migration")
+    stride = max(1, len(reps) // n_sample)
+    sample = reps[::stride][:n_sample]
+    with concurrent.futures.ThreadPoolExecutor(threads) as ex:
+        pops = list(ex.map(lambda d: oracle.OraclePop(**{k: d[k] for k in keys if k in d}), sample))
+        t0 = time.perf_counter()
+        list(ex.map(lambda o: o.step(gens), pops))
+        el = time.perf_counter() - t0
+    upd = sum(o.stats()["updates"] for o in pops)
+    for o in pops:
+        o.close()
+    model, nproc = host_cpu()
+    return {"value": upd / el, "unit": UNIT, "cores": threads, "kind": "oracle", "host_cpu": model,
+            "host_nproc": nproc,
+            "sample": f"{len(sample)} of the {len(reps)} replicates (every {stride}th), {gens} generations each "
+                      f"from the initial populations, {upd} updates in {el:.1f} s on {threads} threads, one "
+                      "replicate per thread at a time; a rate of the same workload mix, not extrapolated"}
+
+
+def per_rep_updates(s0, s1):
+    return [b["updates"] - a["updates"] for a, b in zip(s0, s1)]
+
+
 def bench_batched(args):
     """Replicates of uneven N and L advanced together, against the plain
     per-replicate loop (the same kernels, one replicate at a time, eager
     launches) on a sample of the same replicates."""
     import torch
 
-    from paper_1603_09255_amd import spegg, workloads
+    from paper_1603_09255_amd import spegg
+
+    from paper_1603_09255_amd import workloads
 
     reps = workloads.batched_table(n_reps=args.reps)
+    Ls = [d["n_loci"] for d in reps]
     torch.cuda.set_device(0)
     log(f"bench: creating batch of {len(reps)} replicates")
     pop = spegg.Population(reps)
     torch.cuda.synchronize()
     tuned = choose_shapes(pop, reps, args.gcap, 2)
-    log(f"bench: lanes per gamete by W: {tuned}")
+    log(f"bench: lanes per gamete by W: {tuned}; warmup {args.warmup} generations")
     pop.step(args.warmup)
+    pop.prepare_graphs()  # the graphs the timed region replays, captured before it
     torch.cuda.synchronize()
-    s0 = sum(r["updates"] for r in pop.stats())
+    s0 = pop.stats()
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} generations of the batch")
     t0 = time.perf_counter()
     pop.step(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    s1 = sum(r["updates"] for r in pop.stats())
+    s1 = pop.stats()
     elapsed = t1 - t0
-    updates = s1 - s0
+    du = per_rep_updates(s0, s1)
+    updates = sum(du)
     value = updates / elapsed
+    gen_bytes = sum(u * bytes_per_update(L) for u, L in zip(du, Ls))
     log(f"bench: batch {updates} updates in {elapsed:.3f} s ({value:.4g}/s)")
-    pop.set_timing(["offspring"])
+
+    # Roofline pass: the same generations launched eagerly with every kernel
+    # bracketed by HIP events on the population's stream.
+    gens_b = min(args.steps, 20)
+    pop.set_timing()
     pop.kernel_times()
-    sb0 = sum(r["updates"] for r in pop.stats())
-    pop.step(min(args.steps, 20))
+    pop.offspring_class_times()
+    sb0 = pop.stats()
+    pop.step(gens_b)
     kt = pop.kernel_times()
-    sb1 = sum(r["updates"] for r in pop.stats())
+    ct = pop.offspring_class_times()
+    sb1 = pop.stats()
     pop.set_timing([])
     pop.close()
-    bpu = sum(workloads_bytes(r) for r in reps) / sum(r["n0"] * r["n_loci"] for r in reps)
+    dub = per_rep_updates(sb0, sb1)
+    W_of = [(L + 31) // 32 for L in Ls]
+    classes = []
+    for wmin, wmax, ms, n in ct:
+        members = [i for i in range(len(reps)) if wmin <= W_of[i] <= wmax]
+        newborns = sum(dub[i] / Ls[i] for i in members)
+        byts = sum(dub[i] / Ls[i] * offspring_bytes_per_newborn(Ls[i]) for i in members)
+        blocks = sum(dub[i] / Ls[i] * philox_blocks_per_newborn(Ls[i], reps[i]["r"], reps[i]["mu"])
+                     for i in members)
+        avg_s = ms / 1e3 / max(n, 1)
+        ach = byts / max(n, 1) / avg_s / 1e9 if n else 0.0
+        alu = blocks * PHILOX_OPS / max(n, 1) / avg_s if n else 0.0
+        classes.append({"n_loci": sorted({Ls[i] for i in members}), "replicates": len(members),
+                        "newborns_per_launch": newborns / max(n, 1), "avg_launch_us": avg_s * 1e6, "launches": n,
+                        "bytes_per_launch": byts / max(n, 1), "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS,
+                        "philox_blocks_per_launch": blocks / max(n, 1),
+                        "alu_frac": alu / ALU_PEAK_OPS})
+    dom = max(classes, key=lambda c: c["avg_launch_us"] * c["launches"])
     off_ms, off_n = kt["offspring"]
-    gens_b = min(args.steps, 20)
-    achieved = (sb1 - sb0) * bpu / (off_ms / 1e3) / 1e9
+    off_bytes = sum(dub[i] / Ls[i] * offspring_bytes_per_newborn(Ls[i]) for i in range(len(reps)))
+    per_kind_us = {k: v[0] * 1e3 / gens_b for k, v in kt.items() if v[1]}
+    log(f"bench: event pass, per generation: " + ", ".join(f"{k} {v:.0f} us" for k, v in per_kind_us.items()))
+    for c in classes:
+        log(f"bench: offspring L={c['n_loci']}: {c['avg_launch_us']:.0f} us, {c['achieved_GBs']:.0f} GB/s "
+            f"(frac {c['frac']:.3f}), Philox ALU frac {c['alu_frac']:.3f}")
+
     # plain per-replicate loop on a sample
     sample = reps[: args.plain_sample]
     plain_updates, plain_time = 0, 0.0
@@ -398,21 +525,43 @@ def bench_batched(args):
     plain_rate = plain_updates / plain_time if plain_time > 0 else None  # --plain-sample 0: not measured
     if plain_rate:
         log(f"bench: plain loop over {len(sample)} replicates: {plain_rate:.4g} updates/s")
+    context = device_context(torch, spegg)
+    traffic = measured_traffic("batched", tuned)
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"batched form: {len(reps)} Wright-Fisher replicates, N ~ U{{500..50000}}, "
-                               "L from {64,256,1024}, mu log-uniform [1e-7,1e-4], r ~ U[0.001,0.5], "
-                               "selection width ~ U[2,16], all advanced together",
+                               "L from {64,256,1024} (uint32 words), mu log-uniform [1e-7,1e-4], r ~ U[0.001,0.5], "
+                               "selection width ~ U[2,16], all advanced together, one graph replay per 16 "
+                               "generations",
                    "replicates": len(reps), "generations_timed": args.steps,
+                   "mean_census_total": updates / args.steps / (sum(Ls) / len(Ls)) if Ls else 0,
                    "plain_loop_updates_per_s": plain_rate, "plain_loop_sample": len(sample),
                    "speedup_vs_plain_loop": value / plain_rate if plain_rate else None,
-                   "offspring_lanes_per_gamete_by_W": {str(k): v for k, v in tuned.items()}},
-        "roofline": {"bound": "hbm", "kernel": "offspring", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_update": bpu, "launches": off_n, "generations": gens_b},
+                   "offspring_lanes_per_gamete_by_W": {str(k): v for k, v in tuned.items()},
+                   "kernel_us_per_generation": per_kind_us},
+        "roofline": {"bound": "hbm", "kernel": f"offspring, L={dom['n_loci']} launch class",
+                     "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["frac"],
+                     "traffic": None if traffic is None else traffic * dom["newborns_per_launch"],
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 counters, scaled)",
+                     "bytes_per_newborn": "L/2 + 12", "avg_launch_us": dom["avg_launch_us"],
+                     "launches": dom["launches"],
+                     "timing": "HIP events around each launch, in a second pass of " + str(gens_b) + " generations",
+                     "alu": {"philox_blocks_per_launch": dom["philox_blocks_per_launch"],
+                             "ops_per_block": PHILOX_OPS, "peak_ops_per_s": ALU_PEAK_OPS,
+                             "frac": dom["alu_frac"]},
+                     "classes": classes,
+                     "offspring_all": {"achieved": off_bytes / (off_ms / 1e3) / 1e9 if off_ms else None,
+                                       "frac": off_bytes / (off_ms / 1e3) / 1e9 / HBM_PEAK_GBS if off_ms else None},
+                     "generation": {"bytes_per_update": "0.5 + 20/L", "achieved": gen_bytes / elapsed / 1e9,
+                                    "frac": gen_bytes / elapsed / 1e9 / HBM_PEAK_GBS}},
+        "context": context,
     }
+    if not args.no_cpu_baseline:
+        threads = min(os.cpu_count() or 1, 16)
+        log(f"bench: CPU oracle on a replicate subset, {threads} threads")
+        out["cpu_baseline"] = cpu_baseline_batched(reps, args.cpu_reps, args.cpu_gens, threads)
     print(json.dumps(out), flush=True)
 
 

@@ -258,6 +258,13 @@ spegg_status spegg_read_parents(spegg_pop *pop, uint32_t rep, uint32_t patch, ui
  * while no kernel timing is on; results are the same either way. */
 spegg_status spegg_set_graph(spegg_pop *pop, int enable);
 
+/* Capture, without running them, the generation graphs that
+ * spegg_step_generations replays (one generation and a run of 16), and
+ * upload them to the device, so that a later step replays them at once.
+ * Nothing is enqueued that changes the population; waits for the stream.
+ * A no-op when graphs are off or timing is on. */
+spegg_status spegg_prepare_graphs(spegg_pop *pop);
+
 /* Kernel kinds timed by spegg_set_timing. */
 enum {
     SPEGG_KERNEL_SURVIVE = 0,   /* step D and the offspring count of A */
@@ -281,6 +288,15 @@ spegg_status spegg_set_timing(spegg_pop *pop, uint32_t kinds_mask);
  * and the number of launches timed since the last call, and reset them.
  * Arrays hold n_kinds (<= SPEGG_KERNEL_KINDS) entries. */
 spegg_status spegg_kernel_times(spegg_pop *pop, double *ms, uint64_t *launches, uint32_t n_kinds);
+
+/* Wait, then report the offspring launches timed since the last call, by
+ * launch class (the replicates that share one kernel shape: one launch per
+ * class and generation): the class's least and greatest genome words W,
+ * the summed event milliseconds and the launches, for up to cap classes
+ * (*n_out = the number of classes); resets these sums.  Kernel-kind sums of
+ * spegg_kernel_times are kept apart. */
+spegg_status spegg_offspring_class_times(spegg_pop *pop, uint32_t *w_min, uint32_t *w_max, double *ms,
+                                         uint64_t *launches, uint32_t cap, uint32_t *n_out);
 
 /* Pick the offspring kernel's shape (lanes per gamete, words per lane,
  * chunks held in registers) for each genome length W in the population by

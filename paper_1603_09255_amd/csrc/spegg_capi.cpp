@@ -436,6 +436,7 @@ T *at(uint8_t *base, size_t off) {
 
 struct Timed {
     int kind;
+    int cls;  // offspring launches: the class (kernel shape) index; else -1
     hipEvent_t a, b;
 };
 
@@ -495,6 +496,8 @@ struct spegg_pop {
     std::vector<hipEvent_t> event_pool;
     double ms[SPEGG_KERNEL_KINDS] = {0};
     uint64_t launches[SPEGG_KERNEL_KINDS] = {0};
+    std::vector<double> class_ms;         // offspring event time by class since the last read
+    std::vector<uint64_t> class_launches;
 
     RepDesc *d_descs() { return at<RepDesc>(base, plan.descs); }
     RepState *d_states() { return at<RepState>(base, plan.states); }
@@ -534,7 +537,7 @@ hipEvent_t take_event(spegg_pop *pop) {
 
 // Launch through f, bracketed by events when timing is on.
 template <typename F>
-hipError_t timed(spegg_pop *pop, int kind, F &&f) {
+hipError_t timed(spegg_pop *pop, int kind, F &&f, int cls = -1) {
     if (!(pop->timing & (1u << kind))) return f();
     hipEvent_t a = take_event(pop), b = take_event(pop);
     if (!a || !b) return hipErrorOutOfMemory;
@@ -544,7 +547,7 @@ hipError_t timed(spegg_pop *pop, int kind, F &&f) {
     if (e != hipSuccess) return e;
     e = hipEventRecord(b, pop->stream);
     if (e != hipSuccess) return e;
-    pop->pending.push_back({kind, a, b});
+    pop->pending.push_back({kind, cls, a, b});
     return hipSuccess;
 }
 
@@ -684,15 +687,41 @@ hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
                 return launch_carry(pop->d_descs(), pop->d_states(), carry_tiles, (uint32_t)P.carry_tiles.size(),
                                     pop->stream);
             });
-        for (const OffClass &c : P.classes) {
+        for (size_t ci = 0; ci < P.classes.size(); ++ci) {
+            const OffClass &c = P.classes[ci];
             if (e != hipSuccess) return e;
             const OffArgs oa{pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0, c.ntiles, c.single_deme,
                              pop->d_partials(), c.plane_words, c.geo_words, c.grid, c.lds, trace, pop->stream};
-            e = timed(pop, SPEGG_KERNEL_OFFSPRING, [&] { return launch_offspring(c.shape, oa); });
+            e = timed(pop, SPEGG_KERNEL_OFFSPRING, [&] { return launch_offspring(c.shape, oa); }, (int)ci);
         }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Fold the finished timing events into the per-kind and per-class sums.
+spegg_status collect_times(spegg_pop *pop) {
+    spegg_status st = sync_stream(pop);
+    if (st != SPEGG_OK) return st;
+    for (const Timed &t : pop->pending) {
+        float x = 0.f;
+        const hipError_t e = hipEventElapsedTime(&x, t.a, t.b);
+        if (e != hipSuccess) return device_fail(pop, e, "hipEventElapsedTime");
+        pop->ms[t.kind] += x;
+        pop->launches[t.kind] += 1;
+        if (t.cls >= 0) {
+            if (pop->class_ms.size() <= (size_t)t.cls) {
+                pop->class_ms.resize(t.cls + 1, 0.0);
+                pop->class_launches.resize(t.cls + 1, 0);
+            }
+            pop->class_ms[t.cls] += x;
+            pop->class_launches[t.cls] += 1;
+        }
+        pop->event_pool.push_back(t.a);
+        pop->event_pool.push_back(t.b);
+    }
+    pop->pending.clear();
+    return SPEGG_OK;
 }
 
 // Capture n generations (with the current trace setting) as a graph.
@@ -951,6 +980,23 @@ spegg_status spegg_step_generations(spegg_pop *pop, uint32_t n_generations) {
     return SPEGG_OK;
 }
 
+spegg_status spegg_prepare_graphs(spegg_pop *pop) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    if (!(pop->use_graph && pop->stream != nullptr && pop->timing == 0)) return SPEGG_OK;  // no replay to prepare
+    DeviceGuard guard(pop->device);
+    hipError_t e = hipSuccess;
+    if (!pop->graph_many.exec) e = capture(pop, kGraphGenerations, pop->graph_many);
+    if (e == hipSuccess && !pop->graph_one.exec) e = capture(pop, 1, pop->graph_one);
+    // the executable graphs' resources onto the device now, not at their
+    // first replay
+    if (e == hipSuccess) e = hipGraphUpload(pop->graph_many.exec, pop->stream);
+    if (e == hipSuccess) e = hipGraphUpload(pop->graph_one.exec, pop->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "prepare_graphs");
+    return SPEGG_OK;
+}
+
 spegg_status spegg_set_graph(spegg_pop *pop, int enable) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
@@ -1190,23 +1236,41 @@ spegg_status spegg_set_timing(spegg_pop *pop, uint32_t kinds_mask) {
     return SPEGG_OK;
 }
 
+spegg_status spegg_offspring_class_times(spegg_pop *pop, uint32_t *w_min, uint32_t *w_max, double *ms,
+                                         uint64_t *launches, uint32_t cap, uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    const uint32_t nc = (uint32_t)pop->plan.classes.size();
+    if (!n_out || (cap && (!w_min || !w_max || !ms || !launches)))
+        return fail(SPEGG_E_INVALID, "offspring_class_times: null argument");
+    DeviceGuard guard(pop->device);
+    if ((st = collect_times(pop)) != SPEGG_OK) return st;
+    *n_out = nc;
+    for (uint32_t c = 0; c < nc && c < cap; ++c) {
+        uint32_t lo = ~0u, hi = 0;
+        for (const RepPlan &p : pop->plan.reps) {
+            const OffShape &a = p.shape, &b = pop->plan.classes[c].shape;
+            if (a.g != b.g || a.vpl != b.vpl || a.nch != b.nch) continue;
+            lo = p.W < lo ? p.W : lo;
+            hi = p.W > hi ? p.W : hi;
+        }
+        w_min[c] = lo;
+        w_max[c] = hi;
+        ms[c] = c < pop->class_ms.size() ? pop->class_ms[c] : 0.0;
+        launches[c] = c < pop->class_launches.size() ? pop->class_launches[c] : 0;
+    }
+    pop->class_ms.assign(nc, 0.0);
+    pop->class_launches.assign(nc, 0);
+    return SPEGG_OK;
+}
+
 spegg_status spegg_kernel_times(spegg_pop *pop, double *ms, uint64_t *launches, uint32_t n_kinds) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;
     if (n_kinds > SPEGG_KERNEL_KINDS || (n_kinds && (!ms || !launches)))
         return fail(SPEGG_E_INVALID, "kernel_times: n_kinds <= %d and two arrays", SPEGG_KERNEL_KINDS);
     DeviceGuard guard(pop->device);
-    if ((st = sync_stream(pop)) != SPEGG_OK) return st;
-    for (const Timed &t : pop->pending) {
-        float x = 0.f;
-        const hipError_t e = hipEventElapsedTime(&x, t.a, t.b);
-        if (e != hipSuccess) return device_fail(pop, e, "hipEventElapsedTime");
-        pop->ms[t.kind] += x;
-        pop->launches[t.kind] += 1;
-        pop->event_pool.push_back(t.a);
-        pop->event_pool.push_back(t.b);
-    }
-    pop->pending.clear();
+    if ((st = collect_times(pop)) != SPEGG_OK) return st;
     for (uint32_t k = 0; k < n_kinds; ++k) {
         ms[k] = pop->ms[k];
         launches[k] = pop->launches[k];

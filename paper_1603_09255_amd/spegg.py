@@ -136,6 +136,10 @@ def load():
     lib.spegg_set_graph.argtypes = [vp, C.c_int]
     lib.spegg_set_timing.restype = st
     lib.spegg_set_timing.argtypes = [vp, u32]
+    lib.spegg_offspring_class_times.restype = st
+    lib.spegg_offspring_class_times.argtypes = [vp, P32, P32, C.POINTER(C.c_double), C.POINTER(C.c_uint64), u32, P32]
+    lib.spegg_prepare_graphs.restype = st
+    lib.spegg_prepare_graphs.argtypes = [vp]
     lib.spegg_kernel_times.restype = st
     lib.spegg_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64), u32]
     lib.spegg_pop_destroy.restype = None
@@ -449,6 +453,20 @@ class Population:
         for k in kernels:
             mask |= 1 << KERNEL_NAMES.index(k)
         check(self.lib.spegg_set_timing(self._h, mask))
+
+    def prepare_graphs(self):
+        """Capture and upload the generation graphs before they are replayed."""
+        check(self.lib.spegg_prepare_graphs(self._h))
+
+    def offspring_class_times(self):
+        """[(W min, W max, ms summed, launches)] per offspring launch class
+        since the last call."""
+        cap = 64
+        lo, hi = (C.c_uint32 * cap)(), (C.c_uint32 * cap)()
+        ms, n = (C.c_double * cap)(), (C.c_uint64 * cap)()
+        k = C.c_uint32()
+        check(self.lib.spegg_offspring_class_times(self._h, lo, hi, ms, n, cap, C.byref(k)))
+        return [(lo[i], hi[i], ms[i], n[i]) for i in range(min(k.value, cap))]
 
     def kernel_times(self):
         """{kernel: (ms summed, launches)} since the last call."""
