@@ -65,7 +65,7 @@
 extern "C" {
 #endif
 
-#define SPEGG_ABI_VERSION 2
+#define SPEGG_ABI_VERSION 3
 #define SPEGG_MAX_LOCI 16384u
 #define SPEGG_MAX_REPLICATE_ID ((1u << 20) - 1u)
 #define SPEGG_MAX_PATCHES 1024u
@@ -363,11 +363,30 @@ spegg_status spegg_server_submit(spegg_server *srv, uint64_t job_id, const spegg
                                  uint32_t n_generations);
 
 /* Admit waiting jobs that fit (oldest first, stopping at the first that
- * does not) onto the least loaded stream, advance every resident job by
- * min(n_generations, its remaining generations), wait for all streams, and
- * retire the jobs that finished.  Reports the jobs resident after admission and those still
- * waiting (either pointer may be NULL). */
+ * does not) onto the least loaded stream and enqueue min(n_generations, its
+ * remaining generations) for every resident job; a job's census is copied
+ * to pinned host memory behind its last generation.  Then wait for the
+ * previous step's work only (at most two steps are queued, so the device
+ * runs one while the host admits and retires around the next) and retire
+ * the jobs that finished before this step: results recorded, memory freed
+ * (or held, spegg_server_keep).  n_generations = 0 drains instead: it waits
+ * for all enqueued work and retires every finished job, then admits.
+ * Reports the jobs resident (finished ones not yet retired included) and
+ * those still waiting (either pointer may be NULL). */
 spegg_status spegg_server_step(spegg_server *srv, uint32_t n_generations, uint32_t *n_resident, uint32_t *n_waiting);
+
+/* Hold a waiting or running job's population after it finishes: its result
+ * is reported as usual, and its population stays in the arena, readable
+ * through spegg_server_population (e.g. its genomes), until
+ * spegg_server_release.  SPEGG_E_INVALID for an unknown or finished job. */
+spegg_status spegg_server_keep(spegg_server *srv, uint64_t job_id);
+
+/* The population handle of a finished, kept job (valid until
+ * spegg_server_release; do not destroy or step it). */
+spegg_status spegg_server_population(spegg_server *srv, uint64_t job_id, spegg_pop **out);
+
+/* Free a finished, kept job's population and memory (waits for its stream). */
+spegg_status spegg_server_release(spegg_server *srv, uint64_t job_id);
 
 /* Ids of the jobs finished since the last poll, in completion order (at
  * most cap; *n_out = how many were written). */

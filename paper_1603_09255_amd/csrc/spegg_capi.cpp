@@ -1439,6 +1439,19 @@ void spegg_pop_destroy(spegg_pop *pop) {
     {
         DeviceGuard guard(pop->device);
         (void)hipStreamSynchronize(pop->stream);
+    }
+    spegg::pop_release_done(pop);
+}
+
+}  // extern "C"
+
+// Internal helpers of the job server (spegg_internal.h).
+namespace spegg {
+
+void pop_release_done(spegg_pop *pop) {
+    if (!pop) return;
+    {
+        DeviceGuard guard(pop->device);
         for (const Timed &t : pop->pending) {
             (void)hipEventDestroy(t.a);
             (void)hipEventDestroy(t.b);
@@ -1448,6 +1461,38 @@ void spegg_pop_destroy(spegg_pop *pop) {
     }
     delete pop;
 }
+
+size_t pop_state_bytes(const spegg_pop *pop) { return sizeof(RepState) * pop->n_demes; }
+
+hipError_t pop_census_async(spegg_pop *pop, void *host_states) {
+    DeviceGuard guard(pop->device);
+    hipError_t e = launch_census(pop->d_descs(), pop->d_states(), pop->d_partials(), pop->n_demes, pop->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_states, pop->d_states(), pop_state_bytes(pop), hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) pop->errored = true;
+    return e;
+}
+
+spegg_status pop_results(spegg_pop *pop, const void *host_states, spegg_rep_stats *out) {
+    const RepState *s = static_cast<const RepState *>(host_states);
+    std::vector<spegg_rep_stats> per(pop->n_demes);
+    for (uint32_t u = 0; u < pop->n_demes; ++u) {
+        if (s[u].error) {
+            pop->errored = true;
+            return fail(SPEGG_E_DEVICE, "deme %u: a kernel reported an impossible state", u);
+        }
+        per[u] = census_of(s[u]);
+    }
+    for (uint32_t i = 0; i < pop->n_reps; ++i) {
+        const RepPlan &p = pop->plan.reps[i];
+        out[i] = sum_of(per.data() + p.deme0, p.n_demes);
+    }
+    return SPEGG_OK;
+}
+
+}  // namespace spegg
+
+extern "C" {
 
 int spegg_threshold_table(int kind, double a, uint32_t b, uint64_t *out, int cap) {
     std::vector<uint64_t> T;

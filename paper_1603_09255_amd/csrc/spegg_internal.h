@@ -272,6 +272,16 @@ hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *
 // Set the calling thread's message returned by spegg_last_error.
 void set_last_error(const char *msg);
 
+// For the job server.  Bytes of a population's per-deme state; enqueue the
+// census fold and a copy of every deme's state into host_states (pinned,
+// pop_state_bytes) on the population's stream, without waiting; the
+// per-replicate census from such a copy once it has landed; release a
+// handle whose enqueued work is known to be complete (no stream wait).
+size_t pop_state_bytes(const spegg_pop *pop);
+hipError_t pop_census_async(spegg_pop *pop, void *host_states);
+spegg_status pop_results(spegg_pop *pop, const void *host_states, spegg_rep_stats *out);
+void pop_release_done(spegg_pop *pop);
+
 // Host twin of the kernels' choice of the current census pair.
 inline uint32_t current_pair_host(const RepState &st) { return (int32_t)(st.t[1] - st.t[0]) > 0 ? 1u : 0u; }
 // Per-locus copies of allele 1 over the current census of n individuals

@@ -3,8 +3,11 @@
 // batching -- between steps finished jobs leave and waiting jobs join.
 // Each resident job is one population handle carved from the arena, on one
 // of the server's streams (the least loaded at admission), so the kernels
-// of different jobs overlap on the device; a step replays each job's
-// generation graphs on its stream and then waits for every stream.
+// of different jobs overlap on the device.  A step enqueues each job's
+// generations, and a finishing job's census is copied into pinned host
+// memory behind its last generation; the step then waits only for the
+// previous step's work, so the device runs one step while the host admits
+// and retires around the next.
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
@@ -85,6 +88,10 @@ struct Job {
     uint32_t lane = 0;   // stream index
     double load = 0.0;   // genotype-locus updates per generation at admission
     spegg_pop *pop = nullptr;
+    bool keep = false;        // hold the population after it finishes (spegg_server_keep)
+    bool finishing = false;   // last generation and census copy enqueued
+    uint64_t finish_step = 0; // the step that enqueued them
+    void *host_states = nullptr;  // pinned copy of the census, filled behind the last generation
 };
 
 constexpr uint32_t kMaxStreams = 8;
@@ -105,9 +112,12 @@ struct spegg_server {
     uint8_t *base = nullptr;
     std::vector<hipStream_t> lanes;  // lanes[0] is the caller's stream
     std::vector<double> lane_load;
+    std::vector<hipEvent_t> step_ev[2];  // per lane, the end of the last two steps' work
+    uint64_t steps = 0;                  // steps that enqueued work
     Arena arena{0};
     std::deque<Job> waiting;
-    std::vector<Job> resident;
+    std::vector<Job> resident;       // admitted, finishing ones included until retired
+    std::vector<Job> held;           // finished and kept
     std::vector<uint64_t> finished;  // not yet polled
     std::unordered_map<uint64_t, std::vector<spegg_rep_stats>> results;
     bool errored = false;
@@ -116,6 +126,8 @@ struct spegg_server {
         for (const Job &j : waiting)
             if (j.id == id) return true;
         for (const Job &j : resident)
+            if (j.id == id) return true;
+        for (const Job &j : held)
             if (j.id == id) return true;
         return results.count(id) != 0;
     }
@@ -131,11 +143,43 @@ spegg_status pass_on(spegg_server *s, spegg_status st, const char *what) {
     return sfail(st, "%s: %s", what, inner.c_str());
 }
 
+// Release a job whose enqueued work is complete: its handle, pinned census
+// copy and arena memory.
 void drop(spegg_server *s, Job &j) {
-    if (j.pop) spegg_pop_destroy(j.pop);
+    if (j.pop) spegg::pop_release_done(j.pop);
     j.pop = nullptr;
+    if (j.host_states) (void)hipHostFree(j.host_states);
+    j.host_states = nullptr;
     s->arena.release(j.off, j.bytes);
-    s->lane_load[j.lane] -= j.load;
+    if (!j.keep) s->lane_load[j.lane] -= j.load;
+}
+
+// Retire the finishing jobs whose census copies have landed (those that
+// finished before step `before`, or all of them): record their results
+// and release or hold them.
+spegg_status retire(spegg_server *s, uint64_t before, bool all) {
+    std::vector<Job> keep;
+    keep.reserve(s->resident.size());
+    spegg_status bad = SPEGG_OK;
+    for (Job &j : s->resident) {
+        if (!j.finishing || (!all && j.finish_step >= before)) {
+            keep.push_back(std::move(j));
+            continue;
+        }
+        std::vector<spegg_rep_stats> res(j.reps.size());
+        const spegg_status st = spegg::pop_results(j.pop, j.host_states, res.data());
+        if (st != SPEGG_OK && bad == SPEGG_OK) bad = pass_on(s, st, "reading a finished job");
+        s->results[j.id] = std::move(res);
+        s->finished.push_back(j.id);
+        if (j.keep) {
+            s->lane_load[j.lane] -= j.load;  // no more work on its lane
+            s->held.push_back(std::move(j));
+        } else {
+            drop(s, j);
+        }
+    }
+    s->resident = std::move(keep);
+    return bad;
 }
 
 hipError_t sync_lanes(spegg_server *s) {
@@ -213,6 +257,16 @@ spegg_status spegg_server_submit(spegg_server *s, uint64_t job_id, const spegg_r
 spegg_status spegg_server_step(spegg_server *s, uint32_t n_generations, uint32_t *n_resident, uint32_t *n_waiting) {
     if (!s) return sfail(SPEGG_E_INVALID, "null server");
     if (s->errored) return sfail(SPEGG_E_STATE, "server is errored by an earlier device failure");
+    if (n_generations == 0) {
+        // drain: every enqueued step done, every finished job retired
+        const hipError_t e = sync_lanes(s);
+        if (e != hipSuccess) {
+            s->errored = true;
+            return sfail(SPEGG_E_DEVICE, "server_step: %s", hipGetErrorString(e));
+        }
+        const spegg_status st = retire(s, 0, true);
+        if (st != SPEGG_OK) return st;
+    }
     // admission: oldest first, while the oldest fits
     while (!s->waiting.empty()) {
         Job &j = s->waiting.front();
@@ -224,11 +278,23 @@ spegg_status spegg_server_step(spegg_server *s, uint32_t n_generations, uint32_t
             if (s->lane_load[k] < s->lane_load[j.lane]) j.lane = k;
         j.load = 0.0;
         for (const auto &r : j.reps) j.load += (double)r.n0 * r.n_patches * r.n_loci;
-        const spegg_status st = spegg_pop_create(j.reps.data(), (uint32_t)j.reps.size(), s->base + off,
-                                                 align_up(j.bytes), s->lanes[j.lane], &j.pop);
+        spegg_status st = spegg_pop_create(j.reps.data(), (uint32_t)j.reps.size(), s->base + off, align_up(j.bytes),
+                                           s->lanes[j.lane], &j.pop);
+        if (st == SPEGG_OK) {
+            const hipError_t e = hipHostMalloc(&j.host_states, spegg::pop_state_bytes(j.pop), hipHostMallocDefault);
+            if (e != hipSuccess) {
+                j.host_states = nullptr;
+                spegg_pop_destroy(j.pop);
+                j.pop = nullptr;
+                st = sfail(SPEGG_E_DEVICE, "admitting a job: pinned census buffer: %s", hipGetErrorString(e));
+            }
+        } else {
+            st = pass_on(s, st, "admitting a job");
+        }
         if (st != SPEGG_OK) {
             s->arena.release(off, j.bytes);
-            return pass_on(s, st, "admitting a job");
+            if (st == SPEGG_E_DEVICE) s->errored = true;
+            return st;
         }
         s->lane_load[j.lane] += j.load;
         for (auto &r : j.reps) r.effects = nullptr;  // copied into the job's tables
@@ -236,37 +302,92 @@ spegg_status spegg_server_step(spegg_server *s, uint32_t n_generations, uint32_t
         s->resident.push_back(std::move(j));
         s->waiting.pop_front();
     }
+    if (n_generations > 0 && !s->resident.empty()) {
+        // the step events, made at the first step with work (a server can be
+        // created, and take submissions, before any device work)
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < 2 && e == hipSuccess; ++r)
+            while (s->step_ev[r].size() < s->lanes.size() && e == hipSuccess) {
+                hipEvent_t ev = nullptr;
+                e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                if (e == hipSuccess) s->step_ev[r].push_back(ev);
+            }
+        if (e != hipSuccess) {
+            s->errored = true;
+            return sfail(SPEGG_E_DEVICE, "server_step: events: %s", hipGetErrorString(e));
+        }
+        const uint64_t step = s->steps++;
+        for (Job &j : s->resident) {
+            if (j.finishing) continue;
+            const uint32_t k = j.remaining < n_generations ? j.remaining : n_generations;
+            const spegg_status st = spegg_step_generations(j.pop, k);
+            if (st != SPEGG_OK) return pass_on(s, st, "stepping a job");
+            j.remaining -= k;
+            if (j.remaining == 0) {
+                // the census lands in pinned memory behind the last generation
+                const hipError_t e = spegg::pop_census_async(j.pop, j.host_states);
+                if (e != hipSuccess) {
+                    s->errored = true;
+                    return sfail(SPEGG_E_DEVICE, "server_step: census of job %llu: %s",
+                                 (unsigned long long)j.id, hipGetErrorString(e));
+                }
+                j.finishing = true;
+                j.finish_step = step;
+            }
+        }
+        // this step's work is marked on every lane; the previous step's must
+        // be done before the host goes on, so at most two steps are queued
+        for (size_t k = 0; k < s->lanes.size() && e == hipSuccess; ++k)
+            e = hipEventRecord(s->step_ev[step & 1u][k], s->lanes[k]);
+        if (step > 0)
+            for (size_t k = 0; k < s->lanes.size() && e == hipSuccess; ++k)
+                e = hipEventSynchronize(s->step_ev[(step - 1) & 1u][k]);
+        if (e != hipSuccess) {
+            s->errored = true;
+            return sfail(SPEGG_E_DEVICE, "server_step: %s", hipGetErrorString(e));
+        }
+        const spegg_status st = retire(s, step, false);
+        if (st != SPEGG_OK) return st;
+    }
     if (n_resident) *n_resident = (uint32_t)s->resident.size();
     if (n_waiting) *n_waiting = (uint32_t)s->waiting.size();
-    if (n_generations == 0 || s->resident.empty()) return SPEGG_OK;
-    for (Job &j : s->resident) {
-        const uint32_t k = j.remaining < n_generations ? j.remaining : n_generations;
-        const spegg_status st = spegg_step_generations(j.pop, k);
-        if (st != SPEGG_OK) return pass_on(s, st, "stepping a job");
-        j.remaining -= k;
-    }
-    const hipError_t e = sync_lanes(s);
-    if (e != hipSuccess) {
-        s->errored = true;
-        return sfail(SPEGG_E_DEVICE, "server_step: %s", hipGetErrorString(e));
-    }
-    // retire finished jobs, in residence order
-    std::vector<Job> keep;
-    keep.reserve(s->resident.size());
-    for (Job &j : s->resident) {
-        if (j.remaining > 0) {
-            keep.push_back(std::move(j));
-            continue;
-        }
-        std::vector<spegg_rep_stats> res(j.reps.size());
-        const spegg_status st = spegg_stats(j.pop, res.data(), (uint32_t)res.size());
-        if (st != SPEGG_OK) return pass_on(s, st, "reading a finished job");
-        s->results[j.id] = std::move(res);
-        s->finished.push_back(j.id);
-        drop(s, j);
-    }
-    s->resident = std::move(keep);
     return SPEGG_OK;
+}
+
+spegg_status spegg_server_keep(spegg_server *s, uint64_t job_id) {
+    if (!s) return sfail(SPEGG_E_INVALID, "null server");
+    for (Job &j : s->waiting)
+        if (j.id == job_id) return j.keep = true, SPEGG_OK;
+    for (Job &j : s->resident)
+        if (j.id == job_id && !j.finishing) return j.keep = true, SPEGG_OK;
+    return sfail(SPEGG_E_INVALID, "server_keep: job %llu is not waiting or running", (unsigned long long)job_id);
+}
+
+spegg_status spegg_server_population(spegg_server *s, uint64_t job_id, spegg_pop **out) {
+    if (!s || !out) return sfail(SPEGG_E_INVALID, "server_population: null argument");
+    *out = nullptr;
+    for (Job &j : s->held)
+        if (j.id == job_id) return *out = j.pop, SPEGG_OK;
+    return sfail(SPEGG_E_INVALID, "server_population: job %llu is not a finished, kept job",
+                 (unsigned long long)job_id);
+}
+
+spegg_status spegg_server_release(spegg_server *s, uint64_t job_id) {
+    if (!s) return sfail(SPEGG_E_INVALID, "null server");
+    for (size_t k = 0; k < s->held.size(); ++k)
+        if (s->held[k].id == job_id) {
+            Job &j = s->held[k];
+            // the caller may have enqueued reads on the job's lane
+            const hipError_t e = hipStreamSynchronize(s->lanes[j.lane]);
+            if (e != hipSuccess) {
+                s->errored = true;
+                return sfail(SPEGG_E_DEVICE, "server_release: %s", hipGetErrorString(e));
+            }
+            drop(s, j);
+            s->held.erase(s->held.begin() + k);
+            return SPEGG_OK;
+        }
+    return sfail(SPEGG_E_INVALID, "server_release: job %llu is not a finished, kept job", (unsigned long long)job_id);
 }
 
 spegg_status spegg_server_poll(spegg_server *s, uint64_t *job_ids, uint32_t cap, uint32_t *n_out) {
@@ -302,6 +423,9 @@ void spegg_server_destroy(spegg_server *s) {
     if (!s) return;
     (void)sync_lanes(s);
     for (Job &j : s->resident) drop(s, j);
+    for (Job &j : s->held) drop(s, j);
+    for (int r = 0; r < 2; ++r)
+        for (hipEvent_t ev : s->step_ev[r]) (void)hipEventDestroy(ev);
     for (size_t k = 1; k < s->lanes.size(); ++k) (void)hipStreamDestroy(s->lanes[k]);
     delete s;
 }

@@ -166,6 +166,12 @@ def load():
     lib.spegg_server_result.argtypes = [vp, C.c_uint64, C.POINTER(RepStats), u32]
     lib.spegg_server_usage.restype = st
     lib.spegg_server_usage.argtypes = [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+    lib.spegg_server_keep.restype = st
+    lib.spegg_server_keep.argtypes = [vp, C.c_uint64]
+    lib.spegg_server_population.restype = st
+    lib.spegg_server_population.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
+    lib.spegg_server_release.restype = st
+    lib.spegg_server_release.argtypes = [vp, C.c_uint64]
     lib.spegg_server_destroy.restype = None
     lib.spegg_server_destroy.argtypes = [vp]
     _lib = lib
@@ -310,11 +316,30 @@ class Population:
         self.P = [int(d.get("n_patches", 1)) for d in self.reps]
         # demes per replicate: its patches, or the two species of the consumer-resource regime
         self.D = [2 if d.get("regime") == CONSUMER_RESOURCE else p for d, p in zip(self.reps, self.P)]
+        self._owned = True
         del keep
+
+    @classmethod
+    def view(cls, handle, reps):
+        """A non-owning view of a population handle held elsewhere (a kept
+        job of the server); close() leaves the handle alone."""
+        self = cls.__new__(cls)
+        self.lib = load()
+        self.reps = [dict(d) for d in reps]
+        self.n_reps = len(reps)
+        self.workspace, self.stream, self.footprint = None, None, None
+        self._h = handle
+        self._owned = False
+        self.L = [int(d.get("n_loci", 64)) for d in self.reps]
+        self.W = [(L + 31) // 32 for L in self.L]
+        self.P = [int(d.get("n_patches", 1)) for d in self.reps]
+        self.D = [2 if d.get("regime") == CONSUMER_RESOURCE else p for d, p in zip(self.reps, self.P)]
+        return self
 
     def close(self):
         if getattr(self, "_h", None):
-            self.lib.spegg_pop_destroy(self._h)
+            if getattr(self, "_owned", True):
+                self.lib.spegg_pop_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -518,13 +543,33 @@ class Server:
         arr, keep = make_descs(reps)
         check(self.lib.spegg_server_submit(self._h, int(job_id), arr, len(reps), int(generations)))
         self.n_reps[int(job_id)] = len(reps)
+        self.descs = getattr(self, "descs", {})
+        self.descs[int(job_id)] = [dict(d) for d in reps]
         del keep
 
     def step(self, generations=1):
-        """One scheduling step; returns (resident, waiting)."""
+        """One scheduling step; returns (resident, waiting).  Jobs that
+        finished in this step are retired (polled) at a later step or drain."""
         res, wait = C.c_uint32(), C.c_uint32()
         check(self.lib.spegg_server_step(self._h, int(generations), C.byref(res), C.byref(wait)))
         return res.value, wait.value
+
+    def drain(self):
+        """Wait for all enqueued work, retire finished jobs, then admit."""
+        return self.step(0)
+
+    def keep(self, job_id):
+        """Hold the job's population after it finishes (until release)."""
+        check(self.lib.spegg_server_keep(self._h, int(job_id)))
+
+    def population(self, job_id):
+        """A view of a finished, kept job's population (genomes etc.)."""
+        h = C.c_void_p()
+        check(self.lib.spegg_server_population(self._h, int(job_id), C.byref(h)))
+        return Population.view(h, self.descs[int(job_id)])
+
+    def release(self, job_id):
+        check(self.lib.spegg_server_release(self._h, int(job_id)))
 
     def poll(self, cap=1024):
         ids = (C.c_uint64 * cap)()

@@ -23,6 +23,8 @@ def test_served_jobs_equal_alone_and_oracle():
     srv = spegg.Server(arena)
     for _, jid, descs, gens in jobs:
         srv.submit(jid, descs, gens)
+    for jid in (10, 12):  # their populations stay readable after they finish
+        srv.keep(jid)
     finished = []
     for _ in range(20):
         srv.step(2)  # uneven lengths: jobs leave after different steps
@@ -34,12 +36,26 @@ def test_served_jobs_equal_alone_and_oracle():
         alone = spegg.Population(descs)
         alone.step(gens)
         assert got == alone.stats(), f"job {jid}"
+        if jid in (10, 12):
+            # in the mix and alone: the same genomes, replicate by replicate and patch by patch
+            mixed = srv.population(jid)
+            for i in range(len(descs)):
+                for patch in range(descs[i].get("n_patches", 1)):
+                    assert np.array_equal(mixed.genomes(i, patch), alone.genomes(i, patch)), (jid, i, patch)
         alone.close()
         for i, d in enumerate(descs):
             orc = oracle_pop(d)
             orc.step(gens)
             assert got[i] == orc.total_stats(), f"job {jid} replicate {i}"
+            if jid in (10, 12):
+                for patch in range(d.get("n_patches", 1)):
+                    assert np.array_equal(srv.population(jid).genomes(i, patch), orc.genomes(patch))
+    assert srv.usage()[0] > 0  # the kept jobs hold their memory
+    srv.release(10)
+    srv.release(12)
     assert srv.usage()[0] == 0
+    with pytest.raises(spegg.SpeggError):
+        srv.release(12)
     srv.close()
 
 
@@ -51,9 +67,12 @@ def test_admission_waits_for_memory_and_fills_freed_space():
     srv.submit(2, b, 3)
     srv.submit(3, c, 3)  # fits beside job 1, but waits behind job 2 (oldest first)
     assert srv.step(1) == (1, 2)
-    assert srv.step(2) == (1, 2)
+    assert srv.step(2) == (1, 2)  # job 1 finished on the device; retired at the next step or drain
+    assert srv.poll() == []
+    assert srv.drain() == (2, 0)  # job 1 retired, then 2 and 3 admitted together
     assert srv.poll() == [1]
-    assert srv.step(3) == (2, 0)  # 2 and 3 admitted together
+    assert srv.step(3) == (2, 0)
+    assert srv.drain() == (0, 0)
     assert sorted(srv.poll()) == [2, 3]
     for jid, descs in ((1, a), (2, b), (3, c)):
         alone = spegg.Population(descs)
