@@ -241,6 +241,18 @@ spegg_status spegg_read_survivors(spegg_pop *pop, uint32_t rep, uint32_t patch, 
 spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, uint32_t *counts_dev,
                                  uint32_t *host_counts, uint32_t n_loci, uint32_t *n_out);
 
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * result of spegg_allele_counts without the caller's counts_dev.  The
+ * per-locus counters live in a library-owned device array of
+ * SPEGG_MAX_LOCI uint32 (64 KiB per device, held until the process ends);
+ * the call allocates nothing.  n_loci must equal the replicate's L (at most
+ * SPEGG_MAX_LOCI; SPEGG_E_INVALID otherwise).  Every call on one device
+ * shares that array: calls on one device must not overlap (from two threads
+ * or two streams), or their counts race.  Waits for the stream. */
+spegg_status spegg_allele_counts_noalloc(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species,
+                                         uint32_t *host_counts, uint32_t n_loci, uint32_t *n_out);
+
 /* Record each newborn's mother and father (indices into the previous
  * adults) from the next generation on.  Off by default. */
 spegg_status spegg_set_trace(spegg_pop *pop, int enable);

@@ -30,10 +30,18 @@
 // generations can be replayed as graphs.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "philox.h"
 #include "spegg_internal.h"
 
 namespace spegg {
+
+// Device scratch of the allocation-free allele counts: one counter per locus
+// for the longest genome the library takes (64 KiB), one copy per device,
+// held until the process ends.  Host code never passes this name as an
+// address: allele_scratch() asks each device for its copy's address.
+static __device__ __align__(256) uint32_t scratch[SPEGG_MAX_LOCI];
 
 namespace {
 
@@ -1440,6 +1448,27 @@ hipError_t launch_fill_u32(uint32_t *p, size_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, p, n);
     return hipGetLastError();
+}
+
+hipError_t allele_scratch(uint32_t **out, size_t *words) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static uint32_t *addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        // the device's own address of its copy, taken with that device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<uint32_t *>(p);
+    }
+    *out = addr[dev];
+    *words = SPEGG_MAX_LOCI;
+    return hipSuccess;
 }
 
 hipError_t launch_allele_counts(const RepDesc *d_desc, const RepState *d_state, const RepDesc &h, uint32_t n,

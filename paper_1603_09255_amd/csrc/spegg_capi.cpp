@@ -1190,6 +1190,35 @@ spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t patch, u
     return sync_stream(pop);
 }
 
+spegg_status spegg_allele_counts_noalloc(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species,
+                                         uint32_t *host_counts, uint32_t n_loci, uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, species, &u)) != SPEGG_OK) return st;
+    const RepDesc &h = pop->dev_descs[u];
+    if (n_loci != h.L || !host_counts)
+        return fail(SPEGG_E_INVALID, "allele_counts_noalloc: need n_loci == %u and a host array", h.L);
+    DeviceGuard guard(pop->device);
+    uint32_t *counts = nullptr;
+    size_t words = 0;
+    hipError_t e = allele_scratch(&counts, &words);
+    if (e != hipSuccess) return device_fail(pop, e, "allele_counts_noalloc: scratch address");
+    if (h.L > words)
+        return fail(SPEGG_E_INVALID, "allele_counts_noalloc: %u loci exceed the scratch of %zu counters", h.L, words);
+    RepState s;
+    if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
+    const uint32_t n = s.n[current_pair_host(s)];
+    if (n_out) *n_out = n;
+    // counters from zero by a fill kernel (the array keeps the last call's counts)
+    e = launch_fill_u32(counts, h.L, pop->stream);
+    if (e == hipSuccess) e = launch_allele_counts(pop->d_descs() + u, pop->d_states() + u, h, n, counts, pop->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_counts, counts, sizeof(uint32_t) * h.L, hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "allele_counts_noalloc");
+    return sync_stream(pop);
+}
+
 spegg_status spegg_set_trace(spegg_pop *pop, int enable) {
     spegg_status st = check_pop(pop);
     if (st != SPEGG_OK) return st;

@@ -288,6 +288,9 @@ inline uint32_t current_pair_host(const RepState &st) { return (int32_t)(st.t[1]
 // into counts (L words, zeroed by the caller).
 hipError_t launch_allele_counts(const RepDesc *d_desc, const RepState *d_state, const RepDesc &h, uint32_t n,
                                 uint32_t *counts, hipStream_t s);
+// The current device's copy of the file-scope allele-count scratch (its
+// address, fetched once per device) and its size in words.
+hipError_t allele_scratch(uint32_t **out, size_t *words);
 hipError_t launch_philox_fill(uint32_t k0, uint32_t k1, const uint32_t *ctr, uint32_t *out, uint32_t n,
                               hipStream_t s);
 hipError_t launch_philox_rate(uint32_t k0, uint32_t k1, uint32_t m, uint32_t *out, uint32_t n, hipStream_t s);

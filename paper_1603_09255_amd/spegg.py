@@ -124,6 +124,8 @@ def load():
     lib.spegg_read_survivors.argtypes = [vp, u32, u32, u32, P32, C.c_size_t, P32]
     lib.spegg_allele_counts.restype = st
     lib.spegg_allele_counts.argtypes = [vp, u32, u32, u32, vp, P32, u32, P32]
+    lib.spegg_allele_counts_noalloc.restype = st
+    lib.spegg_allele_counts_noalloc.argtypes = [vp, u32, u32, u32, P32, u32, P32]
     lib.spegg_set_trace.restype = st
     lib.spegg_set_trace.argtypes = [vp, C.c_int]
     lib.spegg_read_parents.restype = st
@@ -430,6 +432,16 @@ class Population:
         got = C.c_uint32()
         check(self.lib.spegg_allele_counts(self._h, rep, patch, species, C.c_void_p(scratch.data_ptr()),
                                            _p(out, C.c_uint32), L, C.byref(got)))
+        return out
+
+    def allele_counts_noalloc(self, rep=0, patch=0, species=0):
+        """As allele_counts, with the library's own device counters (the
+        call allocates no device memory)."""
+        L = self.L[rep]
+        out = np.zeros(L, dtype=np.uint32)
+        got = C.c_uint32()
+        check(self.lib.spegg_allele_counts_noalloc(self._h, rep, patch, species, _p(out, C.c_uint32), L,
+                                                   C.byref(got)))
         return out
 
     def autotune(self, generations_per_trial=2):
