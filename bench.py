@@ -126,6 +126,10 @@ def choose_shapes(pop, descs, gcap, generations_per_trial):
     """The offspring kernel's lanes-per-gamete cap per genome length W: timed
     by the autotuner, or pinned (gcap > 0: profiled runs, where a profiler's
     per-dispatch gaps would swamp the tuner's clock)."""
+    if isinstance(gcap, dict):
+        for W, g in gcap.items():
+            pop.set_offspring_cap(W, g)
+        return dict(gcap)
     if gcap <= 0:
         return pop.autotune(generations_per_trial=generations_per_trial)
     Ws = sorted({(d["n_loci"] + 31) // 32 for d in descs})
@@ -185,9 +189,14 @@ def main():
                     help="serve: jobs at their full size (reps U{8..256}, gens U{100..2000}); hours of GPU time")
     ap.add_argument("--gcap", type=int, default=0,
                     help="pin the offspring kernel's lanes-per-gamete cap instead of autotuning (0: autotune)")
+    ap.add_argument("--gcaps", type=str, default="",
+                    help="pin the cap per genome words instead, as W:cap,W:cap (profiled runs)")
+    ap.add_argument("--no-context", action="store_true", help="skip the device copy and Philox probe")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only copy a device buffer of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.gcaps:
+        args.gcap = {int(a): int(b) for a, b in (x.split(":") for x in args.gcaps.split(","))}
     if args.calibrate_copy_mib:
         return calibrate_copy(args.calibrate_copy_mib)
     if args.gpus != 1:
@@ -525,7 +534,7 @@ def bench_batched(args):
     plain_rate = plain_updates / plain_time if plain_time > 0 else None  # --plain-sample 0: not measured
     if plain_rate:
         log(f"bench: plain loop over {len(sample)} replicates: {plain_rate:.4g} updates/s")
-    context = device_context(torch, spegg)
+    context = None if args.no_context else device_context(torch, spegg)
     traffic = measured_traffic("batched", tuned)
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -30,7 +30,8 @@
  *
  * Patches: a replicate may be a ring of n_patches patches (Supplementary
  * Information S3: patches linked by migration to their neighbours), each a
- * Wright-Fisher deme of its own census.  With probability `migration` a
+ * Wright-Fisher deme of its own census; or patches under biased island
+ * dispersal (spegg_rep_desc.dispersal, below).  With probability `migration` a
  * newborn of patch k descends from parents in patch k-1 or k+1 (backward
  * migration; one fair bit picks the side); a source patch without
  * survivors passes the draw on (drawn patch, home, picked side, other
@@ -122,6 +123,22 @@ typedef struct spegg_ecology {
 
 typedef struct spegg_pop spegg_pop; /* opaque; owns no device memory */
 
+/* Dispersal among the patches of a replicate (Supplementary Information
+ * S3).  SPEGG_RING: patches on a ring, a migrant's parents live in patch
+ * k-1 or k+1 (bit 0 of MIGRATE word 1 picks the side).  SPEGG_ISLAND: the
+ * biased island model of Supplementary Fig. S3 -- a share home_return of
+ * would-be migrants returns to its patch of origin (MIGRATE word 1 below
+ * floor(home_return 2^32)), the others' parents live in a patch drawn
+ * uniformly among the other P-1 (index i from MIGRATE words 2 and 3, i
+ * below the home patch as is, from it on as i+1); the effective migration
+ * rate is migration x (1 - home_return).  A newborn is a would-be migrant
+ * when MIGRATE word 0 is below floor(migration 2^32).  A source patch
+ * without survivors passes the draw on: ring -- home, the drawn side, the
+ * other side; island -- home, then the patches after the drawn one in ring
+ * order; a patch keeps its census while any patch it can draw from has
+ * survivors. */
+enum { SPEGG_RING = 0, SPEGG_ISLAND = 1 };
+
 /* One replicate.  The per-deme parameter table of Supplementary Fig. S5(B):
  * every individual looks up its replicate's entry. */
 typedef struct spegg_rep_desc {
@@ -138,7 +155,9 @@ typedef struct spegg_rep_desc {
     double omega;          /* its width, v(z) = exp(-(z-theta)^2 / (2 omega^2)); omega <= 0: no selection */
     double K;              /* Beverton-Holt carrying capacity (POISSON_BH); K <= 0: no density dependence */
     double fecundity;      /* Poisson mean lambda (POISSON_BH) */
-    double migration;      /* backward migration rate to the ring neighbours, 0..1; unused with one patch */
+    double migration;      /* backward migration rate, 0..1; unused with one patch */
+    uint32_t dispersal;    /* SPEGG_RING (0) or SPEGG_ISLAND (1), the patches a migrant's parents may live in */
+    double home_return;    /* SPEGG_ISLAND: share of would-be migrants that stay home, 0..1 */
     const int8_t *effects; /* n_loci allelic effects in [-4, 4], copied at create; NULL: all +1 */
     const spegg_ecology *ecology; /* SPEGG_CONSUMER_RESOURCE only (copied at create); else NULL */
 } spegg_rep_desc;

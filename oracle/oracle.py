@@ -60,6 +60,8 @@ class OracleParams(C.Structure):
         ("K", C.c_double),
         ("fecundity", C.c_double),
         ("migration", C.c_double),
+        ("dispersal", C.c_uint32),
+        ("home_return", C.c_double),
         ("effects", C.POINTER(C.c_int8)),
         ("ecology", C.POINTER(OracleEcology)),
     ]
@@ -227,7 +229,7 @@ class OraclePop:
 
     def __init__(self, seed=1, replicate_id=0, regime=0, n0=100, capacity=None, n_loci=64,
                  mu=0.0, r=0.5, theta=0.0, omega=0.0, K=0.0, fecundity=0.0, effects=None,
-                 n_patches=1, migration=0.0, ecology=None):
+                 n_patches=1, migration=0.0, ecology=None, dispersal=0, home_return=0.0):
         lib = load()
         self.L = int(n_loci)
         self.W = (self.L + 31) // 32
@@ -242,7 +244,7 @@ class OraclePop:
         prm = OracleParams(seed=seed, replicate_id=replicate_id, regime=regime, n0=n0,
                            capacity=n0 if capacity is None else capacity, n_loci=n_loci, n_patches=n_patches,
                            mu=mu, r=r, theta=theta, omega=omega, K=K, fecundity=fecundity, migration=migration,
-                           effects=eff_ptr, ecology=C.pointer(self._eco) if self._eco is not None else None)
+                           dispersal=dispersal, home_return=home_return, effects=eff_ptr, ecology=C.pointer(self._eco) if self._eco is not None else None)
         self.capacity = prm.capacity
         self._h = lib.oracle_create(C.byref(prm))
         if not self._h:

@@ -238,7 +238,9 @@ typedef struct {
     uint32_t n_loci;
     uint32_t n_patches; /* patches on a ring, >= 1 */
     double mu, r, theta, omega, K, fecundity;
-    double migration; /* backward migration rate to the two ring neighbours */
+    double migration; /* backward migration rate */
+    uint32_t dispersal; /* 0: to the two ring neighbours; 1: biased island model */
+    double home_return; /* island model: share of migrants that return to their patch of origin */
     const int8_t *effects; /* n_loci values, NULL: all +1 */
     const oracle_ecology *ecology; /* consumer-resource regime only */
 } oracle_params;
@@ -281,6 +283,7 @@ typedef struct {
     uint64_t *pois;
     int pois_len;
     uint64_t mig_T; /* migration threshold, 0: no migration */
+    uint64_t home_T; /* island model: a migrant returns home when MIGRATE word 1 < home_T */
     uint32_t generation, n_patches, n_demes;
     oracle_deme *deme;
     /* consumer-resource regime */
@@ -445,6 +448,7 @@ oracle_pop *oracle_create(const oracle_params *prm)
     int cr = prm->regime == REGIME_CONSUMER_RESOURCE;
     if (L == 0 || prm->n0 > prm->capacity || !(prm->mu >= 0.0 && prm->mu < 1.0) || !(prm->r >= 0.0 && prm->r <= 0.5) ||
         prm->n_patches < 1 || prm->n_patches > 1024 || !(prm->migration >= 0.0 && prm->migration <= 1.0) ||
+        prm->dispersal > 1 || !(prm->home_return >= 0.0 && prm->home_return <= 1.0) ||
         (prm->n_patches > 1 && prm->regime != REGIME_WF) || prm->regime > REGIME_CONSUMER_RESOURCE ||
         (cr && !ecology_ok(prm->ecology)))
         return NULL;
@@ -468,6 +472,7 @@ oracle_pop *oracle_create(const oracle_params *prm)
     P->n_patches = prm->n_patches;
     P->n_demes = cr ? 2u : prm->n_patches;
     P->mig_T = prm->n_patches > 1 ? oracle_prob_threshold(prm->migration) : 0;
+    P->home_T = oracle_prob_threshold(prm->home_return);
     if (cr) {
         P->eco = *prm->ecology;
         build_ecology(P);
@@ -809,10 +814,13 @@ static void neonates(oracle_pop *P, uint32_t k)
     D->owner = NULL;
     D->n_carry = 0;
     if (P->prm.regime == REGIME_WF) {
-        uint32_t left = (k + P->n_patches - 1u) % P->n_patches, right = (k + 1u) % P->n_patches;
+        uint32_t left = (k + P->n_patches - 1u) % P->n_patches, right = (k + 1u) % P->n_patches, q;
         uint32_t sources = D->n_survivors;
-        if (P->mig_T > 0)
+        if (P->mig_T > 0 && P->prm.dispersal == 0)
             sources += P->deme[left].n_survivors + P->deme[right].n_survivors;
+        else if (P->mig_T > 0 && P->home_T < ORACLE_ALWAYS) /* island model: every patch can be a source */
+            for (q = 0; q < P->n_patches; ++q)
+                sources += P->deme[q].n_survivors;
         nn = sources > 0 ? D->n : 0;
     } else {
         uint64_t ktot = 0;
@@ -839,12 +847,16 @@ static void neonates(oracle_pop *P, uint32_t k)
  * is a migrant whose parents live in a ring neighbour (bit 0 of MIGRATE
  * word 1 picks the side); a source without survivors passes the draw on,
  * in the order: drawn patch, home, the picked side, the other side. */
+static uint32_t island_source(oracle_pop *P, uint32_t k, uint32_t j, uint32_t t);
+
 static uint32_t source_patch(oracle_pop *P, uint32_t k, uint32_t j, uint32_t t)
 {
     oracle_deme *D = &P->deme[k];
     uint32_t left, right, side, other, drawn, order[4], q;
     if (P->mig_T == 0)
         return k;
+    if (P->prm.dispersal == 1)
+        return island_source(P, k, j, t);
     left = (k + P->n_patches - 1u) % P->n_patches;
     right = (k + 1u) % P->n_patches;
     side = (seq_word(&D->rng, j, ST_MIGRATE, t, 1) & 1u) ? right : left;
@@ -857,6 +869,33 @@ static uint32_t source_patch(oracle_pop *P, uint32_t k, uint32_t j, uint32_t t)
     for (q = 0; q < 4; ++q)
         if (P->deme[order[q]].n_survivors > 0)
             return order[q];
+    return k; /* unreachable: a patch with no source has no offspring */
+}
+
+/* Biased island dispersal (Supplementary S3, Fig. S3 caption: a share pi
+ * of migrants returns to its patch of origin; the others settle in any
+ * other patch).  Offspring j of patch k is a would-be migrant when MIGRATE
+ * word 0 < T(m); it returns home when word 1 < T(pi); otherwise its parents
+ * live in patch i of the other P-1, i uniform from words 2 and 3 (i < k
+ * counts as i, i >= k as i + 1).  A source without survivors passes the
+ * draw on: home, then the patches after the drawn one in ring order. */
+static uint32_t island_source(oracle_pop *P, uint32_t k, uint32_t j, uint32_t t)
+{
+    oracle_deme *D = &P->deme[k];
+    uint32_t n = P->n_patches, drawn = k, q;
+    if ((uint64_t)seq_word(&D->rng, j, ST_MIGRATE, t, 0) < P->mig_T &&
+        !((uint64_t)seq_word(&D->rng, j, ST_MIGRATE, t, 1) < P->home_T)) {
+        uint32_t i = uniform_index(seq_word(&D->rng, j, ST_MIGRATE, t, 2), seq_word(&D->rng, j, ST_MIGRATE, t, 3),
+                                   n - 1u);
+        drawn = i < k ? i : i + 1u;
+    }
+    if (P->deme[drawn].n_survivors > 0)
+        return drawn;
+    if (P->deme[k].n_survivors > 0)
+        return k;
+    for (q = 1; q < n; ++q)
+        if (P->deme[(drawn + q) % n].n_survivors > 0)
+            return (drawn + q) % n;
     return k; /* unreachable: a patch with no source has no offspring */
 }
 

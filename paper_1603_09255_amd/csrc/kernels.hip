@@ -222,6 +222,25 @@ __device__ __forceinline__ uint32_t geometric_gap(const uint32_t *T, uint32_t le
     return (low_ok && high_ok) ? g : geometric_gap_fix(T, len, g, x);
 }
 
+// Four bit planes of U (the components of Philox block b, planes p0 ..
+// p0 + 3 counted from the top) against R's bits at the same places, for the
+// 32 boundaries of a word at once: where R's bit is 1 an undecided boundary
+// with a 0 in U has U < R (a crossover), one with a 1 stays undecided; where
+// R's bit is 0 a 1 in U decides U > R and a 0 stays undecided.  R is
+// wave-uniform, so each bit's all-ones-or-zero mask is a scalar and every
+// update one three-input bit operation.
+__device__ __forceinline__ void planes_uniform(const Words4 &b, uint32_t R, int p0, uint32_t &und, uint32_t &hit) {
+    uint32_t t[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t x = b.v[q];
+        const uint32_t one = (uint32_t)((int32_t)(R << (p0 + q)) >> 31);  // ~0 where R's bit is 1
+        t[q] = und & ~x & one;
+        und &= ~(x ^ one);
+    }
+    hit |= t[0] | t[1] | t[2] | t[3];
+}
+
 // Index of the current census pair: the one with the larger generation.
 __device__ __forceinline__ uint32_t current_pair(const RepState &st) {
     return (int32_t)(st.t[1] - st.t[0]) > 0 ? 1u : 0u;
@@ -664,14 +683,18 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     }
     __syncthreads();
 
-    // A patch whose adults all died keeps its census when a ring neighbour
-    // has survivors to supply its newborns: count the neighbours' survivors
-    // (uniform over the block: only tile 0 of such a deme enters).
+    // A patch whose adults all died keeps its census when a patch it can
+    // draw parents from has survivors to supply its newborns: count their
+    // survivors (uniform over the block: only tile 0 of such a deme enters).
     uint32_t nb_alive = 0;
-    if (k == 0 && sum_a == 0 && n > 0 && d.mig_T != 0) {
+    if (k == 0 && sum_a == 0 && n > 0 && d.mig_T != 0 && !(d.island && d.home_T >= kAlways)) {
+        // the ring's two neighbours, or under island dispersal every patch
+        // (none when every would-be migrant stays home)
         uint32_t x = 0;
-        for (int side = 0; side < 2; ++side) {
-            const SurvCount *CE = counts + descs[side ? d.right : d.left].surv_tile0;
+        const uint32_t nsrc = d.island ? d.n_patches : 2u;
+        for (uint32_t e = 0; e < nsrc; ++e) {
+            const uint32_t u = d.island ? d.deme0 + e : (e ? d.right : d.left);
+            const SurvCount *CE = counts + descs[u].surv_tile0;
             const uint32_t act = (CE[0].n + TILE - 1) / TILE;
             for (uint32_t q = threadIdx.x; q < act; q += kBlock) x += CE[q].alive;
         }
@@ -872,7 +895,30 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
             // home, picked side, other side), then parents uniform over its
             // survivors (Poisson: the slot's mother)
             uint32_t su = rep;
-            if (d.mig_T != 0) {
+            if (d.mig_T != 0 && d.island) {
+                // biased island model: a would-be migrant stays home with
+                // probability pi, else its parents live in one of the other
+                // patches, uniformly; a source without survivors passes the
+                // draw on: home, then the patches after the drawn one
+                const uint32_t m0 = draw(5, 0), m1 = draw(5, 1), m2 = draw(5, 2), m3 = draw(5, 3);
+                uint32_t dp = d.patch;
+                if ((uint64_t)m0 < d.mig_T && !((uint64_t)m1 < d.home_T)) {
+                    const uint32_t i = uniform_index(m2, m3, d.n_patches - 1u);
+                    dp = i < d.patch ? i : i + 1u;
+                }
+                su = d.deme0 + dp;
+                if (!states[su].n_surv) {
+                    su = rep;
+                    if (!st.n_surv)
+                        for (uint32_t q = 1; q < d.n_patches; ++q) {
+                            const uint32_t u = d.deme0 + (dp + q) % d.n_patches;
+                            if (states[u].n_surv) {
+                                su = u;
+                                break;
+                            }
+                        }
+                }
+            } else if (d.mig_T != 0) {
                 const uint32_t m0 = draw(5, 0), m1 = draw(5, 1);
                 const uint32_t side = (m1 & 1u) ? d.right : d.left, other = (m1 & 1u) ? d.left : d.right;
                 const uint32_t drawn = (uint64_t)m0 < d.mig_T ? side : rep;
@@ -964,17 +1010,61 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
                 wave_lds_sync();
             } else if (mode == kModeLazy) {
                 // Bit-serial: the crossovers of every word this lane owns
-                // (word c CH + g V + v of chunk c), into its own crossover
-                // words.  One loop walks the lane's words one Philox block at
-                // a time and moves to the next word once one is decided, so
-                // the lanes of a wave wait for the lane with the most blocks
-                // in all, not for the slowest lane of each word.
+                // (word c CH + g V + v of chunk c), into its crossover words
+                // X.  Bit planes of U come four to a Philox block, the top
+                // bit first; a word is decided once none of its boundaries
+                // is undecided or R has no 1 bit left.
+                // Pass 1: blocks 0 and 1 of every word (eight planes), which
+                // decide all 32 boundaries of about 88% of words.  R is the
+                // same for the whole wave (one replicate per tile), so each
+                // plane's R bit is a uniform branch, not a per-lane mask.
+                // Pass 2: the words still undecided (their state parked in
+                // F, free until mutation) walk on a block at a time in one
+                // flattened loop, so the wave waits for the lane with the
+                // most remaining blocks in all.
+                const uint32_t R = d.R;
+                const bool second = (R << 4) != 0;  // planes 4..7 can decide a boundary
+                const bool more = (R << 8) != 0;    // planes past 7 can
+                uint32_t pend = 0;  // bit i: the lane's i-th word undecided after pass 1 (at most 16 words)
+                uint32_t idx = 0;
+                for (uint32_t w0 = gl * V; w0 < W; w0 += CH) {  // V divides W: all V words exist
+#pragma unroll
+                    for (int v = 0; v < V; ++v, ++idx) {
+                        const uint32_t w = w0 + v;
+                        uint32_t und = ~0u, hit = 0;
+                        const Words4 b0 = rng.block(j, rs, 1u + w * 8u, tp);
+                        planes_uniform(b0, R, 0, und, hit);
+                        if (second) {
+                            // the second block starts once the first is folded
+                            // in (interleaving the two spills registers)
+                            uint32_t blk1 = 2u + w * 8u;
+                            asm volatile("" : "+v"(blk1) : "v"(und));
+                            const Words4 b1 = rng.block(j, rs, blk1, tp);
+                            planes_uniform(b1, R, 4, und, hit);
+                        }
+                        X[w] = hit;
+                        if (more && und != 0) {
+                            F[w] = und;
+                            pend |= 1u << idx;
+                        }
+                    }
+                }
                 // Rk: R shifted so that its top four bits are the planes of
-                // the word's current block (bit 31 first)
-                uint32_t c = 0, v = 0, k = 0, und = ~0u, hit = 0, Rk = d.R;
+                // the word's current block
+                uint32_t w = 0, k = 0, und = 0, hit = 0, Rk = 0;
+                bool live = false;
                 for (;;) {
-                    const uint32_t w = c * CH + gl * V + v;
-                    if (w >= W) break;  // the lane's later words lie further on
+                    if (!live) {
+                        if (pend == 0) break;
+                        const uint32_t i = __builtin_ctz(pend);
+                        pend &= pend - 1u;
+                        w = (i / V) * CH + gl * V + i % V;
+                        und = F[w];
+                        hit = X[w];
+                        k = 2;
+                        Rk = R << 8;
+                        live = true;
+                    }
                     const Words4 blk = rng.block(j, rs, 1u + w * 8u + k, tp);
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
@@ -984,18 +1074,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
                         und &= x ^ ~one;  // R bit 1: keep where x is 1; R bit 0: where x is 0
                     }
                     Rk <<= 4;
-                    // R's bits below this block's planes: none left, or every
-                    // boundary decided -- later planes would change nothing
                     if (Rk == 0 || und == 0) {
                         X[w] = hit;
-                        hit = 0;
-                        und = ~0u;
-                        k = 0;
-                        Rk = d.R;
-                        if (++v == (uint32_t)V) {
-                            v = 0;
-                            ++c;
-                        }
+                        live = false;
                     } else {
                         ++k;
                     }

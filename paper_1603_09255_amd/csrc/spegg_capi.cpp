@@ -209,6 +209,10 @@ spegg_status validate(const spegg_rep_desc &d, uint32_t i) {
     }
     if (!(d.migration >= 0.0 && d.migration <= 1.0))
         return fail(SPEGG_E_INVALID, "replicate %u: migration %g outside [0, 1]", i, d.migration);
+    if (d.dispersal != SPEGG_RING && d.dispersal != SPEGG_ISLAND)
+        return fail(SPEGG_E_INVALID, "replicate %u: unknown dispersal %u", i, d.dispersal);
+    if (!(d.home_return >= 0.0 && d.home_return <= 1.0))
+        return fail(SPEGG_E_INVALID, "replicate %u: home_return %g outside [0, 1]", i, d.home_return);
     if (!(d.mu >= 0.0 && d.mu < 1.0)) return fail(SPEGG_E_INVALID, "replicate %u: mu %g outside [0, 1)", i, d.mu);
     if (!(d.r >= 0.0 && d.r <= 0.5)) return fail(SPEGG_E_INVALID, "replicate %u: r %g outside [0, 1/2]", i, d.r);
     if (!std::isfinite(d.theta) || std::isnan(d.omega))
@@ -842,6 +846,10 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.patch = q.patch;
         h.left = p.mig_T ? p.deme0 + (q.patch + p.n_demes - 1u) % p.n_demes : u;
         h.right = p.mig_T ? p.deme0 + (q.patch + 1u) % p.n_demes : u;
+        h.island = d.dispersal == SPEGG_ISLAND ? 1u : 0u;
+        h.n_patches = p.cr ? 1u : p.n_demes;
+        h.deme0 = p.deme0;
+        h.home_T = prob_threshold(d.home_return);
         h.genome[0] = at<uint32_t>(pop->base, q.genome[0]);
         h.genome[1] = at<uint32_t>(pop->base, q.genome[1]);
         h.z[0] = at<int32_t>(pop->base, q.z[0]);

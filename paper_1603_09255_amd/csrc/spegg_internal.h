@@ -86,6 +86,9 @@ struct RepDesc {
     uint64_t mig_T;      // a newborn is a migrant when MIGRATE word 0 < mig_T; 0: no migration
     uint32_t patch;      // patch of the deme within its replicate
     uint32_t left, right;  // demes of the ring neighbours (the deme itself without migration)
+    uint32_t island;       // biased island dispersal (else the ring)
+    uint32_t n_patches, deme0;  // the replicate's patches and the deme of its patch 0
+    uint64_t home_T;       // island: a would-be migrant stays home when MIGRATE word 1 < home_T
     uint32_t species;    // consumer-resource regime: 0 resource, 1 consumer
     // consumer-resource regime
     uint32_t partner;    // deme of the other species

@@ -57,6 +57,8 @@ class RepDesc(C.Structure):
         ("K", C.c_double),
         ("fecundity", C.c_double),
         ("migration", C.c_double),
+        ("dispersal", C.c_uint32),
+        ("home_return", C.c_double),
         ("effects", C.POINTER(C.c_int8)),
         ("ecology", C.POINTER(Ecology)),
     ]
@@ -194,7 +196,8 @@ def _p(arr, ctype):
 
 
 DESC_KEYS = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
-             "fecundity", "effects", "n_patches", "migration", "ecology")
+             "fecundity", "effects", "n_patches", "migration", "ecology", "dispersal", "home_return")
+RING, ISLAND = 0, 1
 
 
 def make_ecology(eco):
@@ -225,8 +228,9 @@ def make_descs(reps):
         arr[k].capacity = int(d.get("capacity", n0))
         arr[k].n_loci = int(d.get("n_loci", 64))
         arr[k].n_patches = int(d.get("n_patches", 1))
-        for f in ("mu", "r", "theta", "omega", "K", "fecundity", "migration"):
+        for f in ("mu", "r", "theta", "omega", "K", "fecundity", "migration", "home_return"):
             setattr(arr[k], f, float(d.get(f, 0.5 if f == "r" else 0.0)))
+        arr[k].dispersal = int(d.get("dispersal", RING))
         eff = d.get("effects")
         if eff is not None:
             e = np.ascontiguousarray(eff, dtype=np.int8)

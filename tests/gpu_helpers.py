@@ -8,7 +8,7 @@ import oracle
 from paper_1603_09255_amd import spegg
 
 ORACLE_KEYS = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
-               "fecundity", "effects", "n_patches", "migration", "ecology")
+               "fecundity", "effects", "n_patches", "migration", "ecology", "dispersal", "home_return")
 
 
 def say(*args):

@@ -16,6 +16,8 @@ typedef struct {
     uint64_t seed;
     uint32_t replicate_id, regime, n0, capacity, n_loci, n_patches;
     double mu, r, theta, omega, K, fecundity, migration;
+    uint32_t dispersal;
+    double home_return;
     const int8_t *effects;
     const oracle_ecology *ecology;
 } oracle_params;
@@ -63,7 +65,7 @@ int main(void)
     uint32_t out[5], k;
     oracle_ecology eco = {3000, 6000, 4, 30000, 0.5, 4.0, 20.0, 0.5, 0.55, 25000.0,
                           {0.5, 0.8, 0.8, 0.0}, {0.6, 0.8, 0.8, 0.0}};
-    oracle_params base = {1, 3, 0, 400, 400, 64, 1, 1e-3, 0.5, 0.0, 8.0, 0.0, 0.0, 0.0, NULL, NULL};
+    oracle_params base = {1, 3, 0, 400, 400, 64, 1, 1e-3, 0.5, 0.0, 8.0, 0.0, 0.0, 0.0, 0, 0.0, NULL, NULL};
     oracle_params p;
     for (k = 0; k < 300; ++k)
         eff[k] = (int8_t)((int)(k * 7u % 9u) - 4);
@@ -78,6 +80,8 @@ int main(void)
     p = base; p.omega = 0.3; p.theta = 500.0; run(p, 2);    /* extinction */
     p = base; p.n0 = 1; p.capacity = 1; run(p, 2);
     p = base; p.n_patches = 5; p.migration = 0.2; p.n0 = 100; p.capacity = 100; run(p, 3);
+    p = base; p.n_patches = 7; p.migration = 0.3; p.dispersal = 1; p.home_return = 0.4; p.n0 = 80; p.capacity = 80;
+    run(p, 3);
     p = base; p.regime = 2; p.n0 = 8000; p.capacity = 20000; p.n_loci = 96; p.r = 0.2; p.omega = 0.0;
     p.ecology = &eco; run(p, 3);
     oracle_poisson_thresholds(2.2, T, 1024);
