@@ -13,6 +13,7 @@ from .oracle import (  # noqa: F401
     find_gap_word,
     geometric_thresholds,
     load,
+    normals,
     philox4x32_10,
     poisson_thresholds,
     prob_threshold,

@@ -64,6 +64,12 @@ class OracleParams(C.Structure):
         ("home_return", C.c_double),
         ("effects", C.POINTER(C.c_int8)),
         ("ecology", C.POINTER(OracleEcology)),
+        ("genetics", C.c_uint32),
+        ("allele_mean", C.c_double),
+        ("allele_sd", C.c_double),
+        ("mut_sd_factor", C.c_double),
+        ("noise_sd", C.c_double),
+        ("exp_transform", C.c_uint32),
     ]
 
 
@@ -81,6 +87,8 @@ class OracleStats(C.Structure):
         ("truncated", C.c_uint64),
         ("sum_threshold", C.c_uint64),
         ("updates", C.c_uint64),
+        ("sum_zf", C.c_double),
+        ("sum_zf2", C.c_double),
     ]
 
     def as_dict(self):
@@ -156,6 +164,19 @@ def load():
     lib.oracle_skip_gap.restype = u32
     lib.oracle_find_gap_word.argtypes = [u64, u32, C.c_double, u32, u32, u32, u32, u32, P32]
     lib.oracle_find_gap_word.restype = C.c_int
+    PF = C.POINTER(C.c_float)
+    lib.oracle_get_alleles.argtypes = [vp, u32, PF, C.c_size_t]
+    lib.oracle_get_alleles.restype = C.c_int
+    lib.oracle_set_alleles.argtypes = [vp, u32, PF, u32, u32]
+    lib.oracle_set_alleles.restype = C.c_int
+    lib.oracle_get_phenotypes_f.argtypes = [vp, u32, PF, C.c_size_t]
+    lib.oracle_get_phenotypes_f.restype = C.c_int
+    lib.oracle_sample_gametes_cont.argtypes = [vp, PF, u32, u32, u32, C.c_int, PF]
+    lib.oracle_sample_gametes_cont.restype = C.c_int
+    lib.oracle_phenotype_cont.argtypes = [vp, PF, PF, u32, u32, u32]
+    lib.oracle_phenotype_cont.restype = C.c_float
+    lib.oracle_normals.argtypes = [u64, u32, u32, u32, u32, u32, u32, C.POINTER(C.c_double)]
+    lib.oracle_normals.restype = None
     _lib = lib
     return lib
 
@@ -210,6 +231,14 @@ def skip_gap(r, L, x):
     return int(load().oracle_skip_gap(float(r), int(L), int(x)))
 
 
+def normals(seed, c3, index, stream, gen, sub0, n):
+    """Box-Muller deviates of Philox blocks (index, stream, gen, sub0 + k)."""
+    out = np.zeros(int(n), dtype=np.float64)
+    load().oracle_normals(int(seed), int(c3), int(index), int(stream), int(gen), int(sub0), int(n),
+                          _p(out, C.c_double))
+    return out
+
+
 def find_gap_word(seed, c3, r, L, n_slots, t_begin, t_end, x_target):
     """First (t, j, stream, word, boundary) whose gamete walk consumes
     x_target with a crossover still to follow, or None.  Releases the GIL,
@@ -229,7 +258,8 @@ class OraclePop:
 
     def __init__(self, seed=1, replicate_id=0, regime=0, n0=100, capacity=None, n_loci=64,
                  mu=0.0, r=0.5, theta=0.0, omega=0.0, K=0.0, fecundity=0.0, effects=None,
-                 n_patches=1, migration=0.0, ecology=None, dispersal=0, home_return=0.0):
+                 n_patches=1, migration=0.0, ecology=None, dispersal=0, home_return=0.0, genetics=0,
+                 allele_mean=0.0, allele_sd=0.0, mut_sd_factor=0.0, noise_sd=0.0, exp_transform=0):
         lib = load()
         self.L = int(n_loci)
         self.W = (self.L + 31) // 32
@@ -244,7 +274,11 @@ class OraclePop:
         prm = OracleParams(seed=seed, replicate_id=replicate_id, regime=regime, n0=n0,
                            capacity=n0 if capacity is None else capacity, n_loci=n_loci, n_patches=n_patches,
                            mu=mu, r=r, theta=theta, omega=omega, K=K, fecundity=fecundity, migration=migration,
-                           dispersal=dispersal, home_return=home_return, effects=eff_ptr, ecology=C.pointer(self._eco) if self._eco is not None else None)
+                           dispersal=dispersal, home_return=home_return, effects=eff_ptr,
+                           ecology=C.pointer(self._eco) if self._eco is not None else None, genetics=genetics,
+                           allele_mean=allele_mean, allele_sd=allele_sd, mut_sd_factor=mut_sd_factor,
+                           noise_sd=noise_sd, exp_transform=exp_transform)
+        self.continuous = int(genetics) == 1
         self.capacity = prm.capacity
         self._h = lib.oracle_create(C.byref(prm))
         if not self._h:
@@ -370,6 +404,42 @@ class OraclePop:
         self._lib.oracle_sample_gametes(self._h, _p(par, C.c_uint8), int(j0), int(count), int(gen),
                                         1 if paternal else 0, _p(out, C.c_uint8))
         return out
+
+    def allele_values(self, patch=0, species=0):
+        """Continuous alleles, shape (n, 2, L) float32."""
+        d = self._deme(patch, species)
+        n = self.n_of(d)
+        out = np.zeros(max(n, 1) * 2 * self.L, dtype=np.float32)
+        assert self._lib.oracle_get_alleles(self._h, d, _p(out, C.c_float), out.size) == 0
+        return out[: n * 2 * self.L].reshape(n, 2, self.L)
+
+    def set_allele_values(self, values, generation, patch=0, species=0):
+        v = np.ascontiguousarray(values, dtype=np.float32).reshape(-1)
+        n = v.size // (2 * self.L)
+        assert self._lib.oracle_set_alleles(self._h, self._deme(patch, species), _p(v, C.c_float), n,
+                                            int(generation)) == 0
+
+    def phenotypes_f(self, patch=0, species=0):
+        """Continuous alleles: expressed phenotypes, float32."""
+        d = self._deme(patch, species)
+        n = self.n_of(d)
+        out = np.zeros(max(n, 1), dtype=np.float32)
+        assert self._lib.oracle_get_phenotypes_f(self._h, d, _p(out, C.c_float), out.size) == 0
+        return out[:n]
+
+    def sample_gametes_cont(self, parent_values, j0, count, gen=0, paternal=False):
+        """Continuous-allele gametes (count, L) float32 of a parent given as (2, L) values."""
+        par = np.ascontiguousarray(parent_values, dtype=np.float32).reshape(2 * self.L)
+        out = np.zeros((count, self.L), dtype=np.float32)
+        assert self._lib.oracle_sample_gametes_cont(self._h, _p(par, C.c_float), int(j0), int(count), int(gen),
+                                                    1 if paternal else 0, _p(out, C.c_float)) == 0
+        return out
+
+    def phenotype_cont_of(self, h0, h1, j=0, gen=0, sub=0):
+        a = np.ascontiguousarray(h0, dtype=np.float32)
+        b = np.ascontiguousarray(h1, dtype=np.float32)
+        return float(self._lib.oracle_phenotype_cont(self._h, _p(a, C.c_float), _p(b, C.c_float), int(j), int(gen),
+                                                     int(sub)))
 
     def phenotype_of(self, h0, h1):
         a = np.ascontiguousarray(h0, dtype=np.uint8)

@@ -50,8 +50,13 @@ enum {
     ST_MUTATE_PAT = 9,
     ST_MIGRATE = 10,
     ST_ENCOUNTER = 11,
-    ST_CAPTURE = 12
+    ST_CAPTURE = 12,
+    ST_MUTVAL_MAT = 13, /* continuous alleles: deviate of a mutated locus */
+    ST_MUTVAL_PAT = 14,
+    ST_NOISE = 15 /* continuous alleles: residual phenotypic noise */
 };
+
+enum { GENETICS_BIALLELIC = 0, GENETICS_CONTINUOUS = 1 };
 
 enum { REGIME_WF = 0, REGIME_POISSON_BH = 1, REGIME_CONSUMER_RESOURCE = 2 };
 enum { MODE_RAW = 0, MODE_ZERO = 1, MODE_SKIP = 2, MODE_LAZY = 3 };
@@ -124,6 +129,20 @@ static uint32_t uniform_index(uint32_t lo, uint32_t hi, uint32_t n)
 {
     unsigned __int128 x = ((unsigned __int128)hi << 32) | lo;
     return (uint32_t)((x * n) >> 64);
+}
+
+/* Standard normal deviate from one Philox block by the Box-Muller
+ * transform (Box & Muller 1958): u1 in (0, 1] from words 0 (low) and 1
+ * (high), u2 in [0, 1) from words 2 and 3, 53 bits each, and
+ * n = sqrt(-2 ln u1) cos(2 pi u2).  Continuous alleles only. */
+static double normal_deviate(rng_ctx *g, uint32_t index, uint32_t stream, uint32_t gen, uint32_t sub)
+{
+    const double two_pi = 6.283185307179586476925;
+    uint64_t a = ((uint64_t)rng_word(g, index, stream, gen, sub, 1) << 32) | rng_word(g, index, stream, gen, sub, 0);
+    uint64_t b = ((uint64_t)rng_word(g, index, stream, gen, sub, 3) << 32) | rng_word(g, index, stream, gen, sub, 2);
+    double u1 = ((double)(a >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+    double u2 = (double)(b >> 11) * (1.0 / 9007199254740992.0);
+    return sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
 }
 
 /* ------------------------------------------------------------------ */
@@ -243,6 +262,15 @@ typedef struct {
     double home_return; /* island model: share of migrants that return to their patch of origin */
     const int8_t *effects; /* n_loci values, NULL: all +1 */
     const oracle_ecology *ecology; /* consumer-resource regime only */
+    /* Continuous allelic values (Supplementary S2, "Genetics"): genetics =
+     * GENETICS_CONTINUOUS replaces the biallelic bits by one float per
+     * allele. */
+    uint32_t genetics;
+    double allele_mean;   /* mean initial allelic value a0 */
+    double allele_sd;     /* standard deviation of the initial allelic values */
+    double mut_sd_factor; /* varpi: a mutation adds N(0, (varpi a0)^2) */
+    double noise_sd;      /* varrho: residual phenotypic noise */
+    uint32_t exp_transform; /* 1: the expressed phenotype is exp(z) */
 } oracle_params;
 
 typedef struct {
@@ -251,6 +279,7 @@ typedef struct {
     int64_t sum_z, sum_z2;
     uint64_t near_ties, truncated, sum_threshold;
     uint64_t updates; /* cumulative genotype-locus updates, sum of N_t L */
+    double sum_zf, sum_zf2; /* continuous alleles: sums of the expressed phenotypes (serial order) */
 } oracle_stats;
 
 /* One patch of one species of a replicate (a deme): its own individuals
@@ -262,6 +291,8 @@ typedef struct {
     uint32_t n;
     uint8_t *genome; /* genome[i][h][l], one byte per allele */
     int32_t *z;
+    float *cg;       /* continuous alleles: cg[i][h][l] */
+    float *zf;       /* continuous alleles: expressed phenotype */
     uint8_t *age;    /* consumer-resource regime: age of each individual */
     /* the last generation's survivors, fecundities and parents */
     uint32_t *survivors, n_survivors;
@@ -341,6 +372,41 @@ static int32_t phenotype(const oracle_pop *P, const uint8_t *h0, const uint8_t *
     return (int32_t)z;
 }
 
+/* Continuous alleles: viability of an expressed phenotype (a float). */
+static double viability_f(const oracle_pop *P, float z)
+{
+    double d;
+    if (!(P->prm.omega > 0.0))
+        return 1.0;
+    d = (double)z - P->prm.theta;
+    return exp(-(d * d) / (2.0 * P->prm.omega * P->prm.omega));
+}
+
+/* Continuous alleles (Supplementary S2, "Genetics", phenotype value): the
+ * genotypic value is the sum over loci of the midpoint of the two
+ * inherited allelic values; the phenotype adds residual noise
+ * N(0, varrho^2) (NOISE block `sub` of individual `index` in generation
+ * gen) and is expressed as exp(z) under the transform.  Stored as float. */
+static float phenotype_cont(const oracle_pop *P, oracle_deme *D, const float *h0, const float *h1, uint32_t index,
+                            uint32_t gen, uint32_t sub)
+{
+    double g = 0.0, z;
+    uint32_t l;
+    for (l = 0; l < P->L; ++l)
+        g += 0.5 * ((double)h0[l] + (double)h1[l]);
+    z = g;
+    if (P->prm.noise_sd > 0.0)
+        z += P->prm.noise_sd * normal_deviate(&D->rng, index, ST_NOISE, gen, sub);
+    if (P->prm.exp_transform)
+        z = exp(z);
+    return (float)z;
+}
+
+static float *allele_row_f(const oracle_pop *P, float *g, uint32_t i, uint32_t h)
+{
+    return g + ((size_t)i * 2u + h) * P->L;
+}
+
 static uint8_t *allele_row(const oracle_pop *P, uint8_t *g, uint32_t i, uint32_t h)
 {
     return g + ((size_t)i * 2u + h) * P->L;
@@ -350,6 +416,10 @@ static void free_deme(oracle_deme *D)
 {
     free(D->genome);
     free(D->z);
+    free(D->cg);
+    free(D->zf);
+    D->cg = NULL;
+    D->zf = NULL;
     free(D->age);
     free(D->won);
     free(D->intake);
@@ -394,6 +464,15 @@ static void census(const oracle_pop *P, oracle_deme *D)
     D->stats.n = D->n;
     D->stats.sum_z = 0;
     D->stats.sum_z2 = 0;
+    D->stats.sum_zf = 0.0;
+    D->stats.sum_zf2 = 0.0;
+    if (P->prm.genetics == GENETICS_CONTINUOUS) {
+        for (i = 0; i < D->n; ++i) {
+            D->stats.sum_zf += (double)D->zf[i];
+            D->stats.sum_zf2 += (double)D->zf[i] * (double)D->zf[i];
+        }
+        return;
+    }
     for (i = 0; i < D->n; ++i) {
         D->stats.sum_z += D->z[i];
         D->stats.sum_z2 += (int64_t)D->z[i] * (int64_t)D->z[i];
@@ -450,7 +529,10 @@ oracle_pop *oracle_create(const oracle_params *prm)
         prm->n_patches < 1 || prm->n_patches > 1024 || !(prm->migration >= 0.0 && prm->migration <= 1.0) ||
         prm->dispersal > 1 || !(prm->home_return >= 0.0 && prm->home_return <= 1.0) ||
         (prm->n_patches > 1 && prm->regime != REGIME_WF) || prm->regime > REGIME_CONSUMER_RESOURCE ||
-        (cr && !ecology_ok(prm->ecology)))
+        (cr && !ecology_ok(prm->ecology)) || prm->genetics > GENETICS_CONTINUOUS ||
+        (prm->genetics == GENETICS_CONTINUOUS &&
+         (cr || prm->effects || !(prm->allele_sd >= 0.0) || !(prm->mut_sd_factor >= 0.0) || !(prm->noise_sd >= 0.0) ||
+          !isfinite(prm->allele_mean))))
         return NULL;
     P = (oracle_pop *)calloc(1, sizeof *P);
     if (!P)
@@ -496,7 +578,25 @@ oracle_pop *oracle_create(const oracle_params *prm)
         D->genome = (uint8_t *)malloc((size_t)(n0 ? n0 : 1) * 2u * L);
         D->z = (int32_t *)malloc(sizeof(int32_t) * (n0 ? n0 : 1));
         D->age = (uint8_t *)calloc(n0 ? n0 : 1, 1);
-        for (i = 0; i < n0; ++i) {
+        if (prm->genetics == GENETICS_CONTINUOUS) {
+            /* Continuous alleles: each an independent N(a0, s0^2) value,
+             * allele (h, l) from INIT block h L + l of individual i in
+             * generation 0, rounded to float; the founder's phenotype noise
+             * from NOISE block 1. */
+            D->cg = (float *)malloc(sizeof(float) * (size_t)(n0 ? n0 : 1) * 2u * L);
+            D->zf = (float *)malloc(sizeof(float) * (n0 ? n0 : 1));
+            memset(D->genome, 0, (size_t)(n0 ? n0 : 1) * 2u * L);
+            for (i = 0; i < n0; ++i) {
+                for (h = 0; h < 2; ++h) {
+                    float *row = allele_row_f(P, D->cg, i, h);
+                    for (l = 0; l < L; ++l)
+                        row[l] = (float)(prm->allele_mean + prm->allele_sd * normal_deviate(&D->rng, i, ST_INIT, 0, h * L + l));
+                }
+                D->zf[i] = phenotype_cont(P, D, allele_row_f(P, D->cg, i, 0), allele_row_f(P, D->cg, i, 1), i, 0, 1);
+                D->z[i] = 0;
+            }
+        }
+        for (i = 0; prm->genetics == GENETICS_BIALLELIC && i < n0; ++i) {
             for (h = 0; h < 2; ++h) {
                 uint8_t *row = allele_row(P, D->genome, i, h);
                 for (l = 0; l < L; ++l) {
@@ -626,6 +726,44 @@ static void make_gamete(const oracle_pop *P, rng_ctx *g, const uint8_t *h0, cons
     }
 }
 
+/* Continuous alleles (Supplementary S2, "Genetics"): the gamete takes at
+ * each locus the allelic value of the haplotype the crossover mask picks
+ * (the same mask as a biallelic gamete); the mutated loci are the
+ * biallelic rule's K ~ Binomial(L, mu) distinct loci, and each receives a
+ * new value drawn from a normal distribution centred on its value, with
+ * standard deviation varpi times the mean initial allelic value:
+ * value + varpi |a0| n, n from MUTVAL block `locus` of the offspring,
+ * rounded to float. */
+static void make_gamete_cont(const oracle_pop *P, rng_ctx *g, const float *h0, const float *h1, uint32_t j, uint32_t gen,
+                             int paternal, float *out, uint8_t *scratch)
+{
+    uint32_t L = P->L, l;
+    uint8_t *mask = scratch, *toggles = scratch + L, *chosen = scratch + 2u * L;
+    uint32_t rstream = paternal ? ST_RECOMB_PAT : ST_RECOMB_MAT;
+    uint32_t mstream = paternal ? ST_MUTATE_PAT : ST_MUTATE_MAT;
+    uint32_t vstream = paternal ? ST_MUTVAL_PAT : ST_MUTVAL_MAT;
+    double sd = P->prm.mut_sd_factor * fabs(P->prm.allele_mean);
+    uint32_t K, accepted = 0, cand = 0;
+    recombination_mask(P, g, j, rstream, gen, mask, toggles);
+    for (l = 0; l < L; ++l)
+        out[l] = mask[l] ? h1[l] : h0[l];
+    K = draw_by_table(seq_word(g, j, mstream, gen, 0), P->binom, P->binom_len);
+    if (K == 0)
+        return;
+    memset(chosen, 0, L);
+    while (accepted < K && cand < (1u << 23)) {
+        uint32_t lo = seq_word(g, j, mstream, gen, 1u + 2u * cand);
+        uint32_t hi = seq_word(g, j, mstream, gen, 2u + 2u * cand);
+        uint32_t pos = uniform_index(lo, hi, L);
+        ++cand;
+        if (chosen[pos])
+            continue;
+        chosen[pos] = 1;
+        out[pos] = (float)((double)out[pos] + sd * normal_deviate(g, j, vstream, gen, pos));
+        ++accepted;
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* One generation (Fig. 1): survival under the selective environment   */
 /* (D), removal of the dead (E), parents and neonate count (A),        */
@@ -734,6 +872,8 @@ int oracle_small_binomial_thresholds(uint32_t n, double q, uint64_t *T)
  * (consumer-resource regime). */
 static double survival_probability(const oracle_pop *P, const oracle_deme *D, uint32_t i, double s)
 {
+    if (P->prm.genetics == GENETICS_CONTINUOUS)
+        return viability_f(P, D->zf[i]) * s;
     if (P->prm.regime == REGIME_CONSUMER_RESOURCE) {
         const double *sa = D->species == 0 ? P->eco.surv_resource : P->eco.surv_consumer;
         return viability(P, D->z[i]) * sa[D->age[i]];
@@ -902,12 +1042,20 @@ static uint32_t island_source(oracle_pop *P, uint32_t k, uint32_t j, uint32_t t)
 /* The next census of deme k into *next, *znext, *anext: carried survivors
  * first (consumer-resource regime: genomes and phenotypes copied, one age
  * class older), then the newborns -- A (parents) + B + C. */
-static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int32_t **znext, uint8_t **anext)
+static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int32_t **znext, uint8_t **anext,
+                      float **cnext, float **zfnext)
 {
     oracle_deme *D = &P->deme[k];
     uint32_t nc = D->n_carry, nn = D->n_next, j, L = P->L;
     uint32_t total = nc + nn;
+    int cont = P->prm.genetics == GENETICS_CONTINUOUS;
     uint8_t *scratch = (uint8_t *)malloc(3u * L);
+    *cnext = NULL;
+    *zfnext = NULL;
+    if (cont) {
+        *cnext = (float *)malloc(sizeof(float) * (size_t)(total ? total : 1) * 2u * L);
+        *zfnext = (float *)malloc(sizeof(float) * (total ? total : 1));
+    }
     free(D->mom);
     free(D->dad);
     free(D->src);
@@ -939,6 +1087,19 @@ static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int
         D->mom[j] = mom;
         D->dad[j] = dad;
         D->src[j] = P->prm.regime == REGIME_CONSUMER_RESOURCE ? 0u : sp; /* the source's patch */
+        if (cont) {
+            /* offspring genetic value at a locus: the midpoint of the two
+             * gametes' values (phenotype_cont) */
+            make_gamete_cont(P, &D->rng, allele_row_f(P, S->cg, mom, 0), allele_row_f(P, S->cg, mom, 1), j, t, 0,
+                             allele_row_f(P, *cnext, pos, 0), scratch);
+            make_gamete_cont(P, &D->rng, allele_row_f(P, S->cg, dad, 0), allele_row_f(P, S->cg, dad, 1), j, t, 1,
+                             allele_row_f(P, *cnext, pos, 1), scratch);
+            (*zfnext)[pos] = phenotype_cont(P, D, allele_row_f(P, *cnext, pos, 0), allele_row_f(P, *cnext, pos, 1), j,
+                                            t, 0);
+            memset(allele_row(P, *next, pos, 0), 0, 2u * L);
+            (*znext)[pos] = 0;
+            continue;
+        }
         make_gamete(P, &D->rng, allele_row(P, S->genome, mom, 0), allele_row(P, S->genome, mom, 1), j, t, 0,
                     allele_row(P, *next, pos, 0), scratch);
         make_gamete(P, &D->rng, allele_row(P, S->genome, dad, 0), allele_row(P, S->genome, dad, 1), j, t, 1,
@@ -954,6 +1115,8 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
     uint8_t **next = (uint8_t **)calloc(nd, sizeof(uint8_t *));
     int32_t **znext = (int32_t **)calloc(nd, sizeof(int32_t *));
     uint8_t **anext = (uint8_t **)calloc(nd, sizeof(uint8_t *));
+    float **cnext = (float **)calloc(nd, sizeof(float *));
+    float **zfnext = (float **)calloc(nd, sizeof(float *));
     for (it = 0; it < n_generations; ++it) {
         uint32_t t = P->generation;
         if (P->prm.regime == REGIME_CONSUMER_RESOURCE)
@@ -963,7 +1126,7 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
         for (k = 0; k < nd; ++k)
             neonates(P, k);
         for (k = 0; k < nd; ++k)
-            offspring(P, k, t, &next[k], &znext[k], &anext[k]);
+            offspring(P, k, t, &next[k], &znext[k], &anext[k], &cnext[k], &zfnext[k]);
         P->generation = t + 1;
         for (k = 0; k < nd; ++k) {
             oracle_deme *D = &P->deme[k];
@@ -973,6 +1136,10 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
             D->genome = next[k];
             D->z = znext[k];
             D->age = anext[k];
+            free(D->cg);
+            free(D->zf);
+            D->cg = cnext[k];
+            D->zf = zfnext[k];
             D->stats.n_parents = D->n;
             D->stats.n_survivors = D->n_survivors;
             D->n = D->n_carry + D->n_next;
@@ -985,6 +1152,8 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
     free(next);
     free(znext);
     free(anext);
+    free(cnext);
+    free(zfnext);
     return 0;
 }
 
@@ -1034,7 +1203,7 @@ int oracle_set_genomes(oracle_pop *P, uint32_t deme, const uint32_t *words, uint
 {
     uint32_t W = (P->L + 31u) / 32u, i, h, l;
     oracle_deme *D = deme_of(P, deme);
-    if (!D || n > D->cap)
+    if (!D || n > D->cap || P->prm.genetics != GENETICS_BIALLELIC)
         return -1;
     free_deme(D);
     D->genome = (uint8_t *)malloc((size_t)(n ? n : 1) * 2u * P->L);
@@ -1123,6 +1292,94 @@ int oracle_sample_gametes(oracle_pop *P, const uint8_t *parent, uint32_t j0, uin
         make_gamete(P, &P->deme[0].rng, parent, parent + P->L, j0 + c, gen, paternal, out + (size_t)c * P->L, scratch);
     free(scratch);
     return 0;
+}
+
+/* Continuous alleles: a deme's allelic values, individual-major,
+ * haplotype 0 then 1, L floats each. */
+int oracle_get_alleles(const oracle_pop *P, uint32_t deme, float *out, size_t n_values)
+{
+    oracle_deme *D = deme_of(P, deme);
+    if (!D || P->prm.genetics != GENETICS_CONTINUOUS || n_values < (size_t)D->n * 2u * P->L)
+        return -1;
+    memcpy(out, D->cg, sizeof(float) * (size_t)D->n * 2u * P->L);
+    return 0;
+}
+
+int oracle_get_phenotypes_f(const oracle_pop *P, uint32_t deme, float *z, size_t n)
+{
+    oracle_deme *D = deme_of(P, deme);
+    if (!D || P->prm.genetics != GENETICS_CONTINUOUS || n < D->n)
+        return -1;
+    memcpy(z, D->zf, sizeof(float) * D->n);
+    return 0;
+}
+
+/* Continuous alleles: replace a deme's population by n individuals of the
+ * given values at generation `generation`; each phenotype takes a
+ * founder's noise (NOISE block 1 of individual i in that generation). */
+int oracle_set_alleles(oracle_pop *P, uint32_t deme, const float *values, uint32_t n, uint32_t generation)
+{
+    uint32_t i;
+    oracle_deme *D = deme_of(P, deme);
+    if (!D || P->prm.genetics != GENETICS_CONTINUOUS || n > D->cap)
+        return -1;
+    free_deme(D);
+    D->genome = (uint8_t *)calloc((size_t)(n ? n : 1) * 2u, P->L);
+    D->z = (int32_t *)calloc(n ? n : 1, sizeof(int32_t));
+    D->age = (uint8_t *)calloc(n ? n : 1, 1);
+    D->cg = (float *)malloc(sizeof(float) * (size_t)(n ? n : 1) * 2u * P->L);
+    D->zf = (float *)malloc(sizeof(float) * (n ? n : 1));
+    memcpy(D->cg, values, sizeof(float) * (size_t)n * 2u * P->L);
+    for (i = 0; i < n; ++i)
+        D->zf[i] = phenotype_cont(P, D, allele_row_f(P, D->cg, i, 0), allele_row_f(P, D->cg, i, 1), i, generation, 1);
+    D->n = n;
+    P->generation = generation;
+    D->n_survivors = 0;
+    D->n_next = 0;
+    D->n_carry = 0;
+    memset(&D->stats, 0, sizeof D->stats);
+    D->stats.extinct = n == 0;
+    census(P, D);
+    return 0;
+}
+
+/* Continuous alleles: gametes of one parent (2L floats, haplotype 0 then
+ * 1) for offspring slots j0 .. j0+count-1 of patch 0 in generation gen. */
+int oracle_sample_gametes_cont(oracle_pop *P, const float *parent, uint32_t j0, uint32_t count, uint32_t gen,
+                               int paternal, float *out)
+{
+    uint32_t c;
+    uint8_t *scratch;
+    if (P->prm.genetics != GENETICS_CONTINUOUS)
+        return -1;
+    scratch = (uint8_t *)malloc(3u * P->L);
+    for (c = 0; c < count; ++c)
+        make_gamete_cont(P, &P->deme[0].rng, parent, parent + P->L, j0 + c, gen, paternal, out + (size_t)c * P->L,
+                         scratch);
+    free(scratch);
+    return 0;
+}
+
+/* Continuous alleles: phenotype of given allele rows as newborn j of
+ * generation gen (sub 0) or founder j (sub 1) of patch 0. */
+float oracle_phenotype_cont(oracle_pop *P, const float *h0, const float *h1, uint32_t j, uint32_t gen, uint32_t sub)
+{
+    return phenotype_cont(P, &P->deme[0], h0, h1, j, gen, sub);
+}
+
+/* The normal deviates of Philox blocks (index, stream, gen, sub0 + k) for
+ * k < n under key seed and counter field c3. */
+void oracle_normals(uint64_t seed, uint32_t c3, uint32_t index, uint32_t stream, uint32_t gen, uint32_t sub0, uint32_t n,
+                    double *out)
+{
+    rng_ctx g;
+    uint32_t k;
+    g.key[0] = (uint32_t)seed;
+    g.key[1] = (uint32_t)(seed >> 32);
+    g.c3 = c3;
+    g.memo_valid = 0;
+    for (k = 0; k < n; ++k)
+        out[k] = normal_deviate(&g, index, stream, gen, sub0 + k);
 }
 
 /* The phenotype of given allele rows (for pins of the map). */

@@ -20,6 +20,9 @@ typedef struct {
     double home_return;
     const int8_t *effects;
     const oracle_ecology *ecology;
+    uint32_t genetics;
+    double allele_mean, allele_sd, mut_sd_factor, noise_sd;
+    uint32_t exp_transform;
 } oracle_params;
 
 oracle_pop *oracle_create(const oracle_params *prm);
@@ -28,6 +31,8 @@ int oracle_step(oracle_pop *P, uint32_t n);
 int oracle_get_genomes(const oracle_pop *P, uint32_t deme, uint32_t *words, size_t n_words);
 int oracle_set_genomes(oracle_pop *P, uint32_t deme, const uint32_t *words, uint32_t n, uint32_t generation);
 uint32_t oracle_get_n(const oracle_pop *P, uint32_t deme);
+int oracle_get_alleles(const oracle_pop *P, uint32_t deme, float *out, size_t n_values);
+int oracle_set_alleles(oracle_pop *P, uint32_t deme, const float *values, uint32_t n, uint32_t generation);
 int oracle_poisson_thresholds(double lambda, uint64_t *T, int cap);
 int oracle_binomial_thresholds(uint32_t L, double mu, uint64_t *T, int cap);
 void oracle_geometric_thresholds(double r, uint32_t n, uint64_t *T);
@@ -50,6 +55,15 @@ static void run(oracle_params p, uint32_t gens)
     }
     oracle_step(P, gens);
     n = oracle_get_n(P, 0);
+    if (p.genetics == 1) {
+        float *v = (float *)calloc((size_t)(n ? n : 1) * 2u * p.n_loci, sizeof(float));
+        oracle_get_alleles(P, 0, v, (size_t)(n ? n : 1) * 2u * p.n_loci);
+        oracle_set_alleles(P, 0, v, n, 77);
+        oracle_step(P, 1);
+        free(v);
+        oracle_destroy(P);
+        return;
+    }
     w = (uint32_t *)calloc((size_t)(n ? n : 1) * 2u * W, sizeof(uint32_t));
     oracle_get_genomes(P, 0, w, (size_t)(n ? n : 1) * 2u * W);
     oracle_set_genomes(P, 0, w, n, 77);
@@ -65,7 +79,8 @@ int main(void)
     uint32_t out[5], k;
     oracle_ecology eco = {3000, 6000, 4, 30000, 0.5, 4.0, 20.0, 0.5, 0.55, 25000.0,
                           {0.5, 0.8, 0.8, 0.0}, {0.6, 0.8, 0.8, 0.0}};
-    oracle_params base = {1, 3, 0, 400, 400, 64, 1, 1e-3, 0.5, 0.0, 8.0, 0.0, 0.0, 0.0, 0, 0.0, NULL, NULL};
+    oracle_params base = {1, 3, 0, 400, 400, 64, 1, 1e-3, 0.5, 0.0, 8.0, 0.0, 0.0, 0.0, 0, 0.0, NULL, NULL,
+                          0, 0.0, 0.0, 0.0, 0.0, 0};
     oracle_params p;
     for (k = 0; k < 300; ++k)
         eff[k] = (int8_t)((int)(k * 7u % 9u) - 4);
@@ -84,6 +99,11 @@ int main(void)
     run(p, 3);
     p = base; p.regime = 2; p.n0 = 8000; p.capacity = 20000; p.n_loci = 96; p.r = 0.2; p.omega = 0.0;
     p.ecology = &eco; run(p, 3);
+    /* continuous alleles: Gaussian mutation, noise, exp transform */
+    p = base; p.genetics = 1; p.allele_mean = 0.01; p.allele_sd = 0.005; p.mut_sd_factor = 0.5; p.noise_sd = 0.1;
+    p.mu = 0.02; p.r = 0.05; p.n_loci = 70; p.omega = 2.0; p.theta = 1.0; p.exp_transform = 1; run(p, 3);
+    p = base; p.genetics = 1; p.allele_mean = 1.0; p.allele_sd = 0.1; p.mut_sd_factor = 0.1; p.r = 0.3; p.regime = 1;
+    p.capacity = 900; p.K = 400.0; p.fecundity = 2.2; p.omega = 0.0; run(p, 3);
     oracle_poisson_thresholds(2.2, T, 1024);
     oracle_poisson_thresholds(700.0, T, 1024);
     oracle_binomial_thresholds(1024, 1e-4, T, 1025);
