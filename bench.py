@@ -144,7 +144,8 @@ def cpu_baseline(desc, budget_s):
     import oracle
 
     keys = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
-            "fecundity", "effects", "n_patches", "migration")
+            "fecundity", "effects", "n_patches", "migration", "genetics", "allele_mean", "allele_sd",
+            "mut_sd_factor", "noise_sd", "exp_transform")
     orc = oracle.OraclePop(**{k: desc[k] for k in keys if k in desc})
     start_updates = orc.stats()["updates"]
     gens = 0
@@ -172,11 +173,13 @@ def main():
     ap.add_argument("--cpu-gens", type=int, default=2, help="batched: generations of the CPU oracle subset")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["scale", "batched", "serve", "ecology", "small"], default="batched",
+    ap.add_argument("--workload", choices=["scale", "batched", "serve", "ecology", "small", "continuous"],
+                    default="batched",
                     help="batched: the 4096-replicate batch (default); scale: one replicate at scale; "
                          "small: the small parity configuration (launch- and latency-bound); "
                          "serve: sweep jobs arriving at random, served with continuous batching; "
-                         "ecology: 64 replicates of the two-species consumer-resource form")
+                         "ecology: 64 replicates of the two-species consumer-resource form; "
+                         "continuous: one replicate of continuous allelic values (float32) at scale")
     ap.add_argument("--reps", type=int, default=4096, help="replicates of the batched workload")
     ap.add_argument("--plain-sample", type=int, default=64,
                     help="batched: replicates timed one at a time for the plain per-replicate loop")
@@ -216,6 +219,8 @@ def main():
         return bench_ecology(args)
     if args.workload == "small":
         return bench_small(args)
+    if args.workload == "continuous":
+        return bench_continuous(args)
     return bench_scale(args)
 
 
@@ -320,6 +325,104 @@ def bench_scale(args):
             "frac_of_copy": achieved / context["copy_GBs"],
         },
         "context": context,
+    }
+    if not args.no_cpu_baseline:
+        log(f"bench: CPU oracle sample, about {args.cpu_seconds:.0f} s")
+        out["cpu_baseline"] = cpu_baseline(desc, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cont_bytes_per_update(L):
+    # continuous alleles: read the parents' values once and write the
+    # newborns' once (2 x 2 x 4 bytes per locus and individual over one
+    # update per locus), plus the same ~20 bytes of per-individual metadata
+    return 16.0 + 20.0 / L
+
+
+def bench_continuous(args):
+    """One replicate of continuous allelic values (Supplementary S2,
+    "Genetics"): N = 100000, L = 256 float32 loci, Wright-Fisher."""
+    import torch
+
+    from paper_1603_09255_amd import spegg, workloads
+
+    desc, _ = workloads.continuous_scale(seed=1)
+    L = desc["n_loci"]
+    torch.cuda.set_device(0)
+    log(f"bench: creating continuous population N={desc['n0']} L={L}")
+    pop = spegg.Population([desc])
+    torch.cuda.synchronize()
+    tuned = pop.autotune(generations_per_trial=2) if args.gcap == 0 else {}
+    if args.gcap and not isinstance(args.gcap, dict):
+        pop.set_offspring_cap(((L + 3) // 4 * 4) | 0x80000000, args.gcap)
+        tuned = {((L + 3) // 4 * 4) | 0x80000000: args.gcap}
+    log(f"bench: lanes per gamete by genome key: {tuned}; warmup {args.warmup} generations")
+    pop.step(args.warmup)
+    pop.prepare_graphs()
+    torch.cuda.synchronize()
+    s0 = pop.stats()[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pop.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1 = pop.stats()[0]
+    elapsed = t1 - t0
+    updates = s1["updates"] - s0["updates"]
+    value = updates / elapsed
+    log(f"bench: {updates} updates in {elapsed * 1e3:.2f} ms ({value:.4g}/s)")
+    pop.set_timing(["survive", "compact", "offspring"])
+    pop.kernel_times()
+    s0b = pop.stats()[0]
+    pop.step(args.steps)
+    torch.cuda.synchronize()
+    s1b = pop.stats()[0]
+    kt = pop.kernel_times()
+    pop.set_timing([])
+    pop.close()
+    updates_b = s1b["updates"] - s0b["updates"]
+    off_ms, off_n = kt["offspring"]
+    avg_launch_s = off_ms / 1e3 / max(off_n, 1)
+    achieved = updates_b / max(off_n, 1) * cont_bytes_per_update(L) / avg_launch_s / 1e9
+    gather_miss = 24.0 + 20.0 / L  # each newborn gamete reads both parental haplotypes
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "continuous allelic values (Supplementary S2): 1 Wright-Fisher replicate, N=100000, "
+                        "L=256 float32 loci, free recombination, mu=1e-3 with N(0, 0.005^2) changes, noise 0.2, "
+                        "stabilising selection (optimum 2.6, width 1)",
+            "replicates": 1,
+            "n_loci": L,
+            "generations_timed": args.steps,
+            "offspring_lanes_per_gamete": {str(k): v for k, v in tuned.items()},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "offspring (continuous alleles)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_update": cont_bytes_per_update(L),
+            "avg_launch_us": avg_launch_s * 1e6,
+            "launches": off_n,
+            "timing": "HIP events around each offspring launch, in a second pass of the same length",
+            "bytes_per_update_gather_miss": gather_miss,
+            "frac_gather_miss": achieved * gather_miss / cont_bytes_per_update(L) / HBM_PEAK_GBS,
+            "kernel_us": {k: (v[0] * 1e3 / max(v[1], 1)) for k, v in kt.items() if v[1]},
+        },
     }
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle sample, about {args.cpu_seconds:.0f} s")

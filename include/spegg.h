@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define SPEGG_ABI_VERSION 3
+#define SPEGG_ABI_VERSION 4
 #define SPEGG_MAX_LOCI 16384u
 #define SPEGG_MAX_REPLICATE_ID ((1u << 20) - 1u)
 #define SPEGG_MAX_PATCHES 1024u
@@ -139,6 +139,32 @@ typedef struct spegg_pop spegg_pop; /* opaque; owns no device memory */
  * survivors. */
 enum { SPEGG_RING = 0, SPEGG_ISLAND = 1 };
 
+/* Genetics of a replicate.  SPEGG_BIALLELIC: the bit-packed biallelic loci
+ * described at the top of this header.  SPEGG_CONTINUOUS: the paper's own
+ * genetic model (Supplementary Information S2, "Genetics"): every allele is
+ * a continuous value (a float); a gamete takes at each locus the value of
+ * the haplotype its crossover mask picks (the mask a biallelic gamete would
+ * draw: same crossover law, same random words); each locus mutates with
+ * probability mu (the biallelic rule's loci) to a value drawn from a
+ * normal distribution centred on the old value with standard deviation
+ * mut_sd_factor x |allele_mean| (varpi times the mean initial allelic
+ * value); the newborn's genetic value is the sum over loci of the
+ * midpoints of its two inherited values, its phenotype that plus
+ * N(0, noise_sd^2) residual noise, expressed as exp(z) when exp_transform
+ * is 1 (the S2 transform); selection acts on the expressed phenotype.
+ * Initial values are N(allele_mean, allele_sd^2).  Normal deviates come
+ * from one Philox block each by the Box-Muller transform (u1 in (0, 1] from
+ * words 0 and 1, u2 in [0, 1) from words 2 and 3, 53 bits each,
+ * sqrt(-2 ln u1) cos(2 pi u2)): allele (h, l) of founder i from INIT block
+ * h L + l; the mutation of locus l of newborn j's maternal (paternal)
+ * gamete from stream 13 (14) block l; newborn j's noise from stream 15
+ * block 0, a founder's from block 1.  Values are computed in double and
+ * stored as float, so results agree with a serial evaluation to rounding:
+ * genomes and survivors match except where a rounding straddles a float
+ * or a threshold boundary.  Regimes SPEGG_WF and SPEGG_POISSON_BH, with or
+ * without patches; effects must be NULL. */
+enum { SPEGG_BIALLELIC = 0, SPEGG_CONTINUOUS = 1 };
+
 /* One replicate.  The per-deme parameter table of Supplementary Fig. S5(B):
  * every individual looks up its replicate's entry. */
 typedef struct spegg_rep_desc {
@@ -160,6 +186,12 @@ typedef struct spegg_rep_desc {
     double home_return;    /* SPEGG_ISLAND: share of would-be migrants that stay home, 0..1 */
     const int8_t *effects; /* n_loci allelic effects in [-4, 4], copied at create; NULL: all +1 */
     const spegg_ecology *ecology; /* SPEGG_CONSUMER_RESOURCE only (copied at create); else NULL */
+    uint32_t genetics;     /* SPEGG_BIALLELIC (0) or SPEGG_CONTINUOUS (1) */
+    double allele_mean;    /* SPEGG_CONTINUOUS: mean initial allelic value a0 */
+    double allele_sd;      /* SPEGG_CONTINUOUS: standard deviation of the initial values, >= 0 */
+    double mut_sd_factor;  /* SPEGG_CONTINUOUS: varpi, mutation sd = varpi |a0|, >= 0 */
+    double noise_sd;       /* SPEGG_CONTINUOUS: residual phenotypic noise varrho, >= 0 */
+    uint32_t exp_transform; /* SPEGG_CONTINUOUS: 1 expresses exp(z) */
 } spegg_rep_desc;
 
 /* Census of one deme (a patch, or a species of the consumer-resource
@@ -178,6 +210,8 @@ typedef struct spegg_rep_stats {
     uint64_t truncated;     /* cumulative offspring dropped at the capacity */
     uint64_t sum_threshold; /* sum over the last adults of floor(p 2^32): mean viability x 2^32 x n_parents */
     uint64_t updates;       /* cumulative genotype-locus updates: sum over generations of N_t x L */
+    double sum_zf;          /* SPEGG_CONTINUOUS: sum of the expressed phenotypes (sum_z, sum_z2 are 0) */
+    double sum_zf2;         /* SPEGG_CONTINUOUS: sum of their squares */
 } spegg_rep_stats;
 
 /* ABI version of the loaded library; equals SPEGG_ABI_VERSION. */
@@ -234,9 +268,31 @@ spegg_status spegg_read_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, ui
 spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species,
                                  const uint32_t *host_words, uint32_t n, uint32_t generation);
 
-/* Wait, then copy the phenotypes z (N int32) of a deme into host_z. */
+/* Wait, then copy the phenotypes z (N int32) of a deme into host_z.  For
+ * continuous alleles the values are the bits of the float phenotypes
+ * (spegg_read_phenotypes_f reads them as floats). */
 spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint32_t species, int32_t *host_z,
                                    size_t n, uint32_t *n_out);
+
+/* Continuous alleles (Supplementary Information S2, "Genetics"; see
+ * SPEGG_CONTINUOUS).  spegg_read_alleles waits, then copies the allelic
+ * values of patch `patch` of replicate rep as N x 2 x L floats
+ * (individual-major, haplotype 0 then 1, locus l at position l) into
+ * host_values (room for n_values floats); *n_out = N.
+ * spegg_write_alleles replaces that patch's population by n individuals
+ * given in the same layout (finite values, n <= capacity) at generation
+ * `generation`: phenotypes are recomputed (noise from NOISE block 1, as for
+ * founders) and the census and counters reset; it waits before returning.
+ * spegg_read_phenotypes_f waits, then copies the N expressed phenotypes.
+ * SPEGG_E_STATE for a replicate of biallelic genomes (the genome calls
+ * above return it for continuous ones); SPEGG_E_INVALID for short room or a
+ * missing patch. */
+spegg_status spegg_read_alleles(spegg_pop *pop, uint32_t rep, uint32_t patch, float *host_values, size_t n_values,
+                                uint32_t *n_out);
+spegg_status spegg_write_alleles(spegg_pop *pop, uint32_t rep, uint32_t patch, const float *host_values, uint32_t n,
+                                 uint32_t generation);
+spegg_status spegg_read_phenotypes_f(spegg_pop *pop, uint32_t rep, uint32_t patch, float *host_z, size_t n,
+                                     uint32_t *n_out);
 
 /* Wait, then copy the age classes (N uint8, 0..3) of a deme of the
  * consumer-resource regime into host_age. */

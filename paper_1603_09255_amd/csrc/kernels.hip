@@ -106,6 +106,38 @@ __device__ __forceinline__ double density_factor(const RepDesc &d, uint32_t n) {
     return 1.0 / (1.0 + (d.lambda - 1.0) * (double)n / d.K);
 }
 
+// Continuous alleles: a standard normal deviate from one Philox block by
+// the Box-Muller transform (Box & Muller 1958): u1 in (0, 1] from words 0
+// (low) and 1 (high), u2 in [0, 1) from words 2 and 3, 53 bits each;
+// sqrt(-2 ln u1) cos(2 pi u2) in double.
+__device__ __forceinline__ double normal_of(const Words4 &b) {
+    const uint64_t a = ((uint64_t)b.v[1] << 32) | b.v[0];
+    const uint64_t c = ((uint64_t)b.v[3] << 32) | b.v[2];
+    const double u1 = ((double)(a >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+    const double u2 = (double)(c >> 11) * (1.0 / 9007199254740992.0);
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2);
+}
+
+// Continuous alleles: Gaussian viability of an expressed phenotype (the
+// bits of a float), exp(-(z - theta)^2 / (2 omega^2)); omega <= 0: 1.
+__device__ __forceinline__ double viability_cont(const RepDesc &d, uint32_t zbits) {
+    if (!(d.omega > 0.0)) return 1.0;
+    const double dz = (double)__uint_as_float(zbits) - d.theta;
+    return exp(-(dz * dz) / (2.0 * d.omega * d.omega));
+}
+
+// Continuous alleles (Supplementary S2, phenotype value): the expressed
+// phenotype of genetic value g (the sum of the loci's midpoints): plus
+// noise_sd times the deviate of NOISE block `sub` of individual `index` in
+// generation gen, then exp under the transform; rounded to float.
+__device__ __forceinline__ float phenotype_cont(const RepDesc &d, const Rng &rng, double g, uint32_t index,
+                                                uint32_t gen, uint32_t sub) {
+    double z = g;
+    if (d.noise_sd > 0.0) z += d.noise_sd * normal_of(rng.block(index, kStNoise, sub, gen));
+    if (d.exp_tf) z = exp(z);
+    return (float)z;
+}
+
 // Additive effect sum_l e_l b_l, accumulated word by word.  With the
 // offset effects e_l + 4 in [0, 8] held as four bit-planes Q_k (bit k of
 // e_l + 4, W words each), sum_l e_l b_l = sum_k 2^k popc(g & Q_k) - 4 popc(g):
@@ -370,6 +402,40 @@ __global__ void __launch_bounds__(kBlock) create_kernel(const RepDesc *__restric
     const bool unit = d.unit_effects != 0;
     int64_t sz = 0;
     uint64_t sz2 = 0;
+    if (d.cont) {
+        // Continuous alleles: allele (h, l) is N(a0, s0^2) from INIT block
+        // h L + l of the individual, rounded to float; the pad loci are 0.
+        // The genetic value is summed locus by locus in order.
+        double fz = 0.0, fz2 = 0.0;
+        for (uint32_t slot = threadIdx.x; slot < d.surv_tile; slot += kBlock) {
+            const uint32_t i = tile.start + slot;
+            if (i >= n0) continue;
+            float *g = reinterpret_cast<float *>(d.genome[0] + (size_t)i * per);
+            double gv = 0.0;
+            for (uint32_t l = 0; l < W; ++l) {
+                float a = 0.0f, b = 0.0f;
+                if (l < d.L) {
+                    a = (float)(d.a0 + d.s0 * normal_of(rng.block(i, kStInit, l, 0)));
+                    b = (float)(d.a0 + d.s0 * normal_of(rng.block(i, kStInit, d.L + l, 0)));
+                    gv += 0.5 * ((double)a + (double)b);
+                }
+                gstore(g + l, a);
+                gstore(g + W + l, b);
+            }
+            const float z = phenotype_cont(d, rng, gv, i, 0, 1);
+            gstore(d.z[0] + i, (int32_t)__float_as_uint(z));
+            fz += (double)z;
+            fz2 += (double)z * (double)z;
+        }
+        fz = wave_sum<double>(fz);
+        fz2 = wave_sum<double>(fz2);
+        if (lane_id() == 0 && (fz != 0.0 || fz2 != 0.0)) {
+            const uint32_t slot = blockIdx.x % kCensusSlots;
+            atomicAdd(&st.sum_zf[slot], fz);
+            atomicAdd(&st.sum_zf2[slot], fz2);
+        }
+        return;
+    }
     for (uint32_t slot = threadIdx.x; slot < d.surv_tile; slot += kBlock) {
         const uint32_t i = tile.start + slot;  // below the deme's whole tiles
         if (d.regime == SPEGG_CONSUMER_RESOURCE) {
@@ -408,9 +474,32 @@ __global__ void __launch_bounds__(kBlock) create_kernel(const RepDesc *__restric
 }
 
 __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__restrict__ desc,
-                                                           RepState *__restrict__ state, uint32_t n, uint32_t buf) {
+                                                           RepState *__restrict__ state, uint32_t n, uint32_t buf,
+                                                           uint32_t gen) {
     const RepDesc &d = *desc;
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (d.cont) {
+        // continuous alleles written by the caller: founders of generation gen
+        double fz = 0.0, fz2 = 0.0;
+        if (i < n) {
+            const float *g = reinterpret_cast<const float *>(d.genome[buf] + (size_t)i * 2u * d.W);
+            double gv = 0.0;
+            for (uint32_t l = 0; l < d.L; ++l) gv += 0.5 * ((double)g[l] + (double)g[d.W + l]);
+            const Rng rng{d.key0, d.key1, d.c3};
+            const float z = phenotype_cont(d, rng, gv, i, gen, 1);
+            d.z[buf][i] = (int32_t)__float_as_uint(z);
+            fz = (double)z;
+            fz2 = fz * fz;
+        }
+        fz = wave_sum<double>(fz);
+        fz2 = wave_sum<double>(fz2);
+        if (lane_id() == 0 && (fz != 0.0 || fz2 != 0.0)) {
+            const uint32_t slot = blockIdx.x % kCensusSlots;
+            atomicAdd(&state->sum_zf[slot], fz);
+            atomicAdd(&state->sum_zf2[slot], fz2);
+        }
+        return;
+    }
     int64_t z = 0;
     if (i < n) {
         const uint32_t *g = d.genome[buf] + (size_t)i * 2u * d.W;
@@ -481,7 +570,10 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     const Rng rng{d.key0, d.key1, d.c3};
     double v[IT];
 #pragma unroll
-    for (uint32_t q = 0; q < IT; ++q) v[q] = (d.vtab && i0 + q < n) ? gload(d.vtab + ((int32_t)zw.v[q] - d.zmin)) : 1.0;
+    for (uint32_t q = 0; q < IT; ++q)
+        v[q] = (d.vtab && i0 + q < n) ? gload(d.vtab + ((int32_t)zw.v[q] - d.zmin))
+               : (d.cont && i0 + q < n) ? viability_cont(d, zw.v[q])
+                                        : 1.0;
     uint32_t age4 = 0;
     if (cr) age4 = load_ages<IT>(d.age[t & 1u] + i0);
     uint32_t fate[IT], a_loc = 0, k_loc = 0, near = 0, in_loc = 0;
@@ -766,6 +858,45 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
 
 // ---------------------------------------------------------------- offspring
 
+// A: the deme a newborn of deme `rep` descends from.  Without migration its
+// own; on a ring a migrant's parents live in patch k-1 or k+1; under biased
+// island dispersal a would-be migrant stays home with probability pi, else
+// its parents live in one of the other patches, uniformly.  A source
+// without survivors passes the draw on (ring: drawn, home, picked side,
+// other side; island: drawn, home, then the patches after the drawn one).
+// mig(c) is word c of the newborn's MIGRATE block.
+template <typename Mig>
+__device__ __forceinline__ uint32_t source_deme(const RepDesc &d, const RepState &st, const RepState *states,
+                                                uint32_t rep, Mig mig) {
+    uint32_t su = rep;
+    if (d.mig_T != 0 && d.island) {
+        const uint32_t m0 = mig(0), m1 = mig(1), m2 = mig(2), m3 = mig(3);
+        uint32_t dp = d.patch;
+        if ((uint64_t)m0 < d.mig_T && !((uint64_t)m1 < d.home_T)) {
+            const uint32_t i = uniform_index(m2, m3, d.n_patches - 1u);
+            dp = i < d.patch ? i : i + 1u;
+        }
+        su = d.deme0 + dp;
+        if (!states[su].n_surv) {
+            su = rep;
+            if (!st.n_surv)
+                for (uint32_t q = 1; q < d.n_patches; ++q) {
+                    const uint32_t u = d.deme0 + (dp + q) % d.n_patches;
+                    if (states[u].n_surv) {
+                        su = u;
+                        break;
+                    }
+                }
+        }
+    } else if (d.mig_T != 0) {
+        const uint32_t m0 = mig(0), m1 = mig(1);
+        const uint32_t side = (m1 & 1u) ? d.right : d.left, other = (m1 & 1u) ? d.left : d.right;
+        const uint32_t drawn = (uint64_t)m0 < d.mig_T ? side : rep;
+        su = states[drawn].n_surv ? drawn : st.n_surv ? rep : states[side].n_surv ? side : other;
+    }
+    return su;
+}
+
 // One team of 2G lanes makes one newborn: lanes [0, G) build the maternal
 // gamete (haplotype 0), lanes [G, 2G) the paternal one.  A gamete's W words
 // are cut into chunks of G x V; in each chunk lane g handles V consecutive
@@ -894,36 +1025,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
             // neighbour; a patch without survivors passes the draw on: drawn,
             // home, picked side, other side), then parents uniform over its
             // survivors (Poisson: the slot's mother)
-            uint32_t su = rep;
-            if (d.mig_T != 0 && d.island) {
-                // biased island model: a would-be migrant stays home with
-                // probability pi, else its parents live in one of the other
-                // patches, uniformly; a source without survivors passes the
-                // draw on: home, then the patches after the drawn one
-                const uint32_t m0 = draw(5, 0), m1 = draw(5, 1), m2 = draw(5, 2), m3 = draw(5, 3);
-                uint32_t dp = d.patch;
-                if ((uint64_t)m0 < d.mig_T && !((uint64_t)m1 < d.home_T)) {
-                    const uint32_t i = uniform_index(m2, m3, d.n_patches - 1u);
-                    dp = i < d.patch ? i : i + 1u;
-                }
-                su = d.deme0 + dp;
-                if (!states[su].n_surv) {
-                    su = rep;
-                    if (!st.n_surv)
-                        for (uint32_t q = 1; q < d.n_patches; ++q) {
-                            const uint32_t u = d.deme0 + (dp + q) % d.n_patches;
-                            if (states[u].n_surv) {
-                                su = u;
-                                break;
-                            }
-                        }
-                }
-            } else if (d.mig_T != 0) {
-                const uint32_t m0 = draw(5, 0), m1 = draw(5, 1);
-                const uint32_t side = (m1 & 1u) ? d.right : d.left, other = (m1 & 1u) ? d.left : d.right;
-                const uint32_t drawn = (uint64_t)m0 < d.mig_T ? side : rep;
-                su = states[drawn].n_surv ? drawn : st.n_surv ? rep : states[side].n_surv ? side : other;
-            }
+            const uint32_t su = source_deme(d, st, states, rep, [&](int c) { return draw(5, c); });
             const RepDesc &sd_src = descs[su];
             const uint32_t ns = states[su].n_surv, nprev = states[su].n_prev;
             const uint32_t p0 = draw(0, 0), p1 = draw(0, 1), p2 = draw(0, 2), p3 = draw(0, 3);
@@ -1224,6 +1326,315 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
     }
 }
 
+// ---------------------------------------------------------------- offspring, continuous alleles
+
+// Continuous alleles (Supplementary S2, "Genetics"): W floats per haplotype
+// (L rounded up to a multiple of 4, the pad zero).  One team of 2G lanes
+// makes one newborn, lanes [0, G) the maternal gamete (haplotype 0) and
+// [G, 2G) the paternal one; in each chunk of 4G loci lane g holds loci
+// 4g .. 4g+3 as one 16-byte access.  The crossover mask comes from the
+// draws a biallelic gamete would use: crossover toggles (geometric gaps or
+// bit-serial comparisons) into the gamete's LDS words, turned into mask
+// words by a prefix XOR; each lane then reads the four mask bits of its
+// loci.  The mutated loci are the biallelic rule's K distinct loci (flip
+// bitmap in LDS); each moves by mut_sd times the deviate of its own MUTVAL
+// block (keyed by the locus).  The genetic value is half the sum of both
+// gametes' values; lane 0 adds the noise and stores the phenotype.
+// NCH > 0: a gamete spans at most NCH chunks, all gathered before the mask
+// is drawn; NCH == 0: any number, gathered one at a time.
+// Dynamic LDS: the geometric-gap thresholds (geo_words), then per team and
+// gamete a mask bitmap and a flip bitmap of mask_words words each.
+template <int G, int NCH>
+__global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *__restrict__ descs,
+                                                                const RepState *__restrict__ states,
+                                                                const OffTile *__restrict__ tiles, uint32_t tile0,
+                                                                uint32_t ntiles, int single_deme,
+                                                                Partial *__restrict__ partials, uint32_t mask_words,
+                                                                uint32_t geo_words, int trace) {
+    constexpr uint32_t TPO = 2 * G;
+    constexpr uint32_t TEAMS = kBlock / TPO;
+    constexpr uint32_t ITERS = TEAMS >= 16 ? 1 : 16 / TEAMS;
+    constexpr uint32_t OPT = TEAMS * ITERS;
+    constexpr uint32_t CH = 4 * G;  // loci of one gamete per chunk
+    constexpr int NREG = NCH > 0 ? NCH : 1;
+    // per-newborn draws, one Philox block each, spread over the team: 0
+    // parents, 1/2 crossover phase, 3/4 mutation count (maternal/paternal),
+    // 5 migration, 6 phenotypic noise
+    constexpr uint32_t NSD = 7;
+    constexpr uint32_t SR = (NSD + TPO - 1) / TPO;
+    extern __shared__ uint32_t lds[];
+    __shared__ double red_z[kBlock / 64], red_z2[kBlock / 64];
+    uint32_t *geo = lds;
+
+    uint32_t limit = ntiles;
+    if (single_deme >= 0) {
+        const RepState &s1 = states[single_deme];
+        const uint32_t active = (s1.n[current_pair(s1)] + OPT - 1) / OPT;
+        limit = active < ntiles ? active : ntiles;
+    }
+    for (uint32_t ti = blockIdx.x; ti < limit; ti += gridDim.x) {
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const uint32_t team = tid / TPO, lane = tid % TPO;
+        const uint32_t half = lane / G, gl = lane % G;
+        const uint32_t seg0 = (tid & 63u) - gl;
+        const uint32_t segmask = G >= 32 ? 0xFFFFFFFFu : ((1u << G) - 1u);
+        uint32_t rep, start;
+        if (single_deme >= 0) {
+            rep = (uint32_t)single_deme;
+            start = ti * OPT;
+        } else {
+            const OffTile tile = tiles[tile0 + ti];
+            rep = tile.rep;
+            start = tile.start;
+        }
+        const RepDesc &d = descs[rep];
+        const RepState &st = states[rep];
+        const uint32_t newest = current_pair(st);
+        const uint32_t nn = st.n[newest];
+        if (start >= nn || st.error) continue;  // uniform over the block
+        const uint32_t tp = st.t[newest] - 1u, cur = tp & 1u;
+        const uint32_t W = d.W, L = d.L, Wb = (L + 31u) / 32u, mode = d.mode;
+        const Rng rng{d.key0, d.key1, d.c3};
+        const bool skip_table = mode == kModeSkip && d.geo_len > 0;
+        if (skip_table && (single_deme < 0 || ti == blockIdx.x)) {
+            for (uint32_t q = threadIdx.x; q < d.geo_len; q += kBlock) geo[q] = (uint32_t)gload(d.geo + q);
+            __syncthreads();
+        }
+        uint32_t *X = lds + geo_words + (size_t)(team * 2u + half) * 2u * mask_words;  // toggles, then mask words
+        uint32_t *F = X + mask_words;                                                   // mutation flips
+        double my_z = 0.0, my_z2 = 0.0;
+
+        for (uint32_t it = 0; it < ITERS; ++it) {
+            const uint32_t j = start + it * TEAMS + team;
+            if (j >= nn) continue;  // uniform over the team
+            Words4 sd[SR];
+#pragma unroll
+            for (uint32_t r = 0; r < SR; ++r) {
+                const uint32_t kd = lane + r * TPO;
+                const uint32_t stream = kd == 0   ? kStParent
+                                        : kd <= 2 ? kStRecomb + kd - 1u
+                                        : kd <= 4 ? kStMutate + kd - 3u
+                                        : kd == 5 ? kStMigrate
+                                                  : kStNoise;
+                if (kd < NSD && (kd != 5 || d.mig_T != 0) && (kd != 6 || d.noise_sd > 0.0)) {
+                    sd[r] = rng.block(j, stream, 0, tp);
+                } else {
+                    sd[r].v[0] = sd[r].v[1] = sd[r].v[2] = sd[r].v[3] = 0;
+                }
+            }
+            auto draw = [&](uint32_t kd, int c) -> uint32_t {
+                return (uint32_t)__shfl((int)sd[kd / TPO].v[c], (int)(kd % TPO), (int)TPO);
+            };
+            // A: parents
+            const uint32_t su = source_deme(d, st, states, rep, [&](int c) { return draw(5, c); });
+            const RepDesc &sd_src = descs[su];
+            const uint32_t ns = states[su].n_surv, nprev = states[su].n_prev;
+            const uint32_t p0 = draw(0, 0), p1 = draw(0, 1), p2 = draw(0, 2), p3 = draw(0, 3);
+            uint32_t mom = d.regime == SPEGG_WF ? gload(sd_src.S + uniform_index(p0, p1, ns)) : gload(d.owner + j);
+            uint32_t dad = gload(sd_src.S + uniform_index(p2, p3, ns));
+            if (mom >= nprev || dad >= nprev) {
+                atomicOr(const_cast<uint32_t *>(&st.error), 1u);
+                mom = mom < nprev ? mom : nprev - 1u;
+                dad = dad < nprev ? dad : nprev - 1u;
+            }
+            if (trace && lane == 0) {
+                gstore(d.mom + j, mom);
+                gstore(d.dad + j, dad);
+                if (d.mig_T != 0) gstore(d.src + j, sd_src.patch);
+            }
+            const uint32_t *src = sd_src.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
+            uint32_t *dst = d.genome[cur ^ 1u] + (size_t)j * 2u * W + (size_t)half * W;
+            // every lane takes part in each cross-lane read, then selects
+            const uint32_t phase_m = draw(1, 0), phase_p = draw(2, 0);
+            const uint32_t xk_m = draw(3, 0), xk_p = draw(4, 0);
+            const uint32_t phase = (half ? phase_p : phase_m) & 1u;
+            const uint32_t xk = half ? xk_p : xk_m;
+            const uint32_t nz0 = draw(6, 0), nz1 = draw(6, 1), nz2 = draw(6, 2), nz3 = draw(6, 3);
+            // the parent's values (all chunks, or the first), in flight while
+            // the mask is drawn
+            Words<4> h0[NREG], h1[NREG];
+#pragma unroll
+            for (int c = 0; c < NREG; ++c) {
+                const uint32_t l0 = (uint32_t)c * CH + gl * 4u;
+                if (l0 < W) {
+                    h0[c] = load_words<4>(src + l0);
+                    h1[c] = load_words<4>(src + W + l0);
+                }
+            }
+            const uint32_t rs = kStRecomb + half, ms = kStMutate + half;
+            // B1: crossover mask words of the gamete into X
+            if (mode == kModeRaw) {
+                for (uint32_t w = gl; w < Wb; w += G) X[w] = rng.seq(j, rs, w, tp);
+            } else {
+                for (uint32_t w = gl; w < Wb; w += G) X[w] = 0;
+                wave_lds_sync();
+                if (mode == kModeSkip) {
+                    // geometric gaps, four to a Philox block from block 1 on;
+                    // lane g takes block blk + g
+                    uint32_t b = 0, blk = 1;
+                    for (; d.geo_len > 0;) {
+                        const Words4 xw = rng.block(j, rs, blk + gl, tp);
+                        uint32_t cum[4];
+                        uint32_t acc = 0;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            acc += 1u + geometric_gap(geo, d.geo_len, d.geo_scale, xw.v[c]);
+                            cum[c] = acc;
+                        }
+                        uint32_t incl = acc;
+#pragma unroll
+                        for (int o = 1; o < G; o <<= 1) {
+                            const uint32_t y = __shfl_up(incl, o, G);
+                            if (gl >= (uint32_t)o) incl += y;
+                        }
+                        const uint32_t base = b + incl - acc;
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const uint32_t pos = base + cum[c];
+                            if (pos <= L - 1u) atomicOr(&X[pos >> 5], 1u << (pos & 31u));
+                        }
+                        const uint32_t last = __shfl(b + incl, G - 1, G);
+                        if (last > L - 1u) break;
+                        b = last;
+                        blk += G;
+                    }
+                } else if (mode == kModeLazy) {
+                    // bit-serial U < R per 32-boundary word, U's bits from
+                    // the top, four planes per Philox block
+                    const uint32_t R = d.R;
+                    for (uint32_t w = gl; w < Wb; w += G) {
+                        uint32_t und = ~0u, hit = 0, Rk = R;
+                        for (uint32_t k = 0;; ++k) {
+                            const Words4 blk = rng.block(j, rs, 1u + w * 8u + k, tp);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                const uint32_t x = blk.v[q];
+                                const uint32_t one = (uint32_t)((int32_t)(Rk << q) >> 31);
+                                hit |= und & ~x & one;
+                                und &= x ^ ~one;
+                            }
+                            Rk <<= 4;
+                            if (Rk == 0 || und == 0) break;
+                        }
+                        X[w] = hit;
+                    }
+                }
+                wave_lds_sync();
+                // toggles -> mask words: prefix XOR within each word, the
+                // parity of the gamete's earlier words carried across
+                uint32_t carry = 0;
+                for (uint32_t wb = 0; wb < Wb; wb += G) {
+                    const uint32_t w = wb + gl;
+                    uint32_t tog = w < Wb ? X[w] : 0u;
+                    if (w == 0) tog = (tog & ~1u) | phase;
+                    const uint32_t pre = prefix_xor32(tog);
+                    const uint64_t bal = __ballot(w < Wb && (pre >> 31));
+                    const uint32_t seg = (uint32_t)(bal >> seg0) & segmask;
+                    const uint32_t below = __popc(seg & ((1u << gl) - 1u));
+                    const uint32_t m = pre ^ (((below + carry) & 1u) ? ~0u : 0u);
+                    carry = (carry + __popc(seg)) & 1u;
+                    wave_lds_sync();
+                    if (w < Wb) X[w] = m;
+                }
+            }
+            // B2: mutation, K ~ Binomial(L, mu) distinct loci
+            const uint32_t K = (uint64_t)xk < d.binom0 ? 0u : table_draw_global(d.binom, d.binom_len, xk);
+            if (K > 0) {
+                for (uint32_t w = gl; w < Wb; w += G) F[w] = 0;
+                wave_lds_sync();
+                if (gl == 0) {
+                    uint32_t accepted = 0;
+                    for (uint32_t m = 0; accepted < K && m < (1u << 23); ++m) {
+                        const uint32_t lo = rng.seq(j, ms, 1u + 2u * m, tp);
+                        const uint32_t hi = rng.seq(j, ms, 2u + 2u * m, tp);
+                        const uint32_t pos = uniform_index(lo, hi, L);
+                        const uint32_t bit = 1u << (pos & 31u);
+                        if (!(F[pos >> 5] & bit)) {
+                            F[pos >> 5] |= bit;
+                            ++accepted;
+                        }
+                    }
+                }
+            }
+            wave_lds_sync();
+            // B3 + C: the gamete's values, written out; their sum
+            double acc = 0.0;
+            auto chunk = [&](uint32_t c, const Words<4> &a, const Words<4> &b) {
+                const uint32_t l0 = c * CH + gl * 4u;
+                if (l0 >= W) return;
+                const uint32_t msk = (X[l0 >> 5] >> (l0 & 31u)) & 0xFu;
+                const uint32_t flp = K > 0 ? (F[l0 >> 5] >> (l0 & 31u)) & 0xFu : 0u;
+                Words<4> g;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    uint32_t x = ((msk >> v) & 1u) ? b.v[v] : a.v[v];
+                    if (l0 + v >= L) x = 0;  // pad
+                    if ((flp >> v) & 1u) {
+                        const double y = (double)__uint_as_float(x) +
+                                         d.mut_sd * normal_of(rng.block(j, kStMutVal + half, l0 + v, tp));
+                        x = __float_as_uint((float)y);
+                    }
+                    g.v[v] = x;
+                    acc += (double)__uint_as_float(x);
+                }
+                store_words_nt<4>(dst + l0, g);
+            };
+            if constexpr (NCH > 0) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) chunk((uint32_t)c, h0[c], h1[c]);
+            } else {
+                chunk(0, h0[0], h1[0]);
+                for (uint32_t c = 1; c * CH < W; ++c) {
+                    const uint32_t l0 = c * CH + gl * 4u;
+                    Words<4> a{}, b{};
+                    if (l0 < W) {
+                        a = load_words<4>(src + l0);
+                        b = load_words<4>(src + W + l0);
+                    }
+                    chunk(c, a, b);
+                }
+            }
+#pragma unroll
+            for (int o = 1; o < (int)TPO; o <<= 1) acc += __shfl_xor(acc, o, TPO);
+            if (lane == 0) {
+                double z = 0.5 * acc;
+                if (d.noise_sd > 0.0) {
+                    Words4 nb;
+                    nb.v[0] = nz0;
+                    nb.v[1] = nz1;
+                    nb.v[2] = nz2;
+                    nb.v[3] = nz3;
+                    z += d.noise_sd * normal_of(nb);
+                }
+                if (d.exp_tf) z = exp(z);
+                const float zf = (float)z;
+                gstore(d.z[cur ^ 1u] + j, (int32_t)__float_as_uint(zf));
+                my_z += (double)zf;
+                my_z2 += (double)zf * (double)zf;
+            }
+            wave_lds_sync();  // X and F are rewritten by the team's next newborn
+        }
+        const double wz = wave_sum<double>(my_z);
+        const double wz2 = wave_sum<double>(my_z2);
+        if (lane_id() == 0) {
+            red_z[threadIdx.x >> 6] = wz;
+            red_z2[threadIdx.x >> 6] = wz2;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                a += red_z[w];
+                b += red_z2[w];
+            }
+            gstore(&partials[tile0 + ti].sum_z, (int64_t)__double_as_longlong(a));
+            gstore(&partials[tile0 + ti].sum_z2, (uint64_t)__double_as_longlong(b));
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- census
 
 // One block per replicate: sums of the tile partials of the newest census.
@@ -1236,6 +1647,36 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
     RepState &st = states[rep];
     if (!st.census_pending) return;  // uniform over the block
     const RepDesc &d = descs[rep];
+    if (d.cont) {
+        // continuous alleles: the partials hold doubles
+        double fa = 0.0, fb = 0.0;
+        const uint32_t used = (st.n[current_pair(st)] + d.off_per_tile - 1u) / d.off_per_tile;
+        for (uint32_t k = threadIdx.x; k < used; k += kBlock) {
+            const Partial p = partials[d.off_tile0 + k];
+            fa += __longlong_as_double(p.sum_z);
+            fb += __longlong_as_double((int64_t)p.sum_z2);
+        }
+        fa = wave_sum<double>(fa);
+        fb = wave_sum<double>(fb);
+        __shared__ double fsz[kBlock / 64], fsz2[kBlock / 64];
+        if (lane_id() == 0) {
+            fsz[threadIdx.x >> 6] = fa;
+            fsz2[threadIdx.x >> 6] = fb;
+        }
+        __syncthreads();
+        if (threadIdx.x < kCensusSlots) {
+            double sa = 0.0, sb = 0.0;
+            if (threadIdx.x == 0)
+                for (int w = 0; w < kBlock / 64; ++w) {
+                    sa += fsz[w];
+                    sb += fsz2[w];
+                }
+            st.sum_zf[threadIdx.x] = sa;
+            st.sum_zf2[threadIdx.x] = sb;
+        }
+        if (threadIdx.x == 0) st.census_pending = 0;
+        return;
+    }
     int64_t a = 0;
     uint64_t b = 0;
     if (d.regime == SPEGG_CONSUMER_RESOURCE) {
@@ -1428,8 +1869,32 @@ OffspringKernel offspring_kernel_v(int g, int nch) {
     }
 }
 
+template <int G>
+OffspringKernel offspring_cont_kernel_g(int nch) {
+    switch (nch) {
+    case 0: return offspring_cont_kernel<G, 0>;
+    case 1: return offspring_cont_kernel<G, 1>;
+    case 2: return offspring_cont_kernel<G, 2>;
+    case 4: return offspring_cont_kernel<G, 4>;
+    default: return nullptr;
+    }
+}
+
+OffspringKernel offspring_cont_kernel_for(int g, int nch) {
+    switch (g) {
+    case 1: return offspring_cont_kernel_g<1>(nch);
+    case 2: return offspring_cont_kernel_g<2>(nch);
+    case 4: return offspring_cont_kernel_g<4>(nch);
+    case 8: return offspring_cont_kernel_g<8>(nch);
+    case 16: return offspring_cont_kernel_g<16>(nch);
+    case 32: return offspring_cont_kernel_g<32>(nch);
+    default: return nullptr;
+    }
+}
+
 // The kernel instance of a shape, or null for a shape outside the set.
 OffspringKernel offspring_kernel_for(OffShape shape) {
+    if (shape.cont) return shape.vpl == 4 ? offspring_cont_kernel_for(shape.g, shape.nch) : nullptr;
     switch (shape.vpl) {
     case 1: return offspring_kernel_v<1>(shape.g, shape.nch);
     case 2: return offspring_kernel_v<2>(shape.g, shape.nch);
@@ -1449,9 +1914,10 @@ hipError_t launch_create(const RepDesc *descs, RepState *states, const SurvTile 
     return hipGetLastError();
 }
 
-hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t n, uint32_t buf, hipStream_t s) {
+hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t n, uint32_t buf, uint32_t gen,
+                             hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(phenotype_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, d_desc, d_state, n, buf);
+    hipLaunchKernelGGL(phenotype_kernel, dim3(blocks_for(n)), dim3(kBlock), 0, s, d_desc, d_state, n, buf, gen);
     return hipGetLastError();
 }
 
@@ -1483,7 +1949,7 @@ hipError_t launch_offspring(OffShape shape, const OffArgs &a) {
     const OffspringKernel k = offspring_kernel_for(shape);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3(a.grid), dim3(kBlock), a.lds, a.s, a.descs, a.states, a.tiles, a.tile0, a.ntiles,
-                       a.single_deme, a.partials, a.plane_words, a.geo_words, a.trace);
+                       a.single_deme, a.partials, shape.cont ? a.mask_words : a.plane_words, a.geo_words, a.trace);
     return hipGetLastError();
 }
 

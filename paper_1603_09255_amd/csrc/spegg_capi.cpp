@@ -55,6 +55,7 @@ struct Carver {
 // Everything the host derives from one descriptor, and its shared tables.
 struct RepPlan {
     uint32_t W = 0, mode = 0, R = 0, opt = 0;
+    bool cont = false;  // continuous alleles: W floats per haplotype
     OffShape shape{1, 1, 1};
     int32_t zmin = 0, sum_e = 0;
     uint32_t zlen = 0;
@@ -89,8 +90,17 @@ struct OffClass {
     int single_deme;       // the class's only deme, or -1
     uint32_t plane_words;  // LDS words for the effect planes (0: unit effects only)
     uint32_t geo_words;    // LDS words for the geometric-gap thresholds (0: no skip-mode member)
+    uint32_t mask_words;   // continuous alleles: LDS words of one gamete's bitmaps
     size_t lds;
 };
+
+// Key of a genome's offspring-shape cap: the words per haplotype, with the
+// top bit set for continuous alleles (their shapes are of another kernel).
+constexpr uint32_t kContKey = 0x80000000u;
+uint32_t shape_key(const RepPlan &p) { return p.cont ? (p.W | kContKey) : p.W; }
+OffShape shape_of_key(uint32_t key, int gcap) {
+    return (key & kContKey) ? offspring_cont_shape(key & ~kContKey, gcap) : offspring_shape(key, gcap);
+}
 
 // Lanes-per-gamete cap by genome length W (the autotuner's choice); a W
 // missing from the map takes the default.
@@ -226,6 +236,19 @@ spegg_status validate(const spegg_rep_desc &d, uint32_t i) {
         for (uint32_t l = 0; l < d.n_loci; ++l)
             if (d.effects[l] < -4 || d.effects[l] > 4)
                 return fail(SPEGG_E_INVALID, "replicate %u: effect %d at locus %u outside [-4, 4]", i, d.effects[l], l);
+    if (d.genetics != SPEGG_BIALLELIC && d.genetics != SPEGG_CONTINUOUS)
+        return fail(SPEGG_E_INVALID, "replicate %u: unknown genetics %u", i, d.genetics);
+    if (d.genetics == SPEGG_CONTINUOUS) {
+        if (d.regime == SPEGG_CONSUMER_RESOURCE)
+            return fail(SPEGG_E_UNSUPPORTED, "replicate %u: continuous alleles with the consumer-resource regime", i);
+        if (d.effects)
+            return fail(SPEGG_E_INVALID, "replicate %u: continuous alleles carry their own effects (effects must be NULL)",
+                        i);
+        if (!std::isfinite(d.allele_mean) || !(d.allele_sd >= 0.0) || !std::isfinite(d.allele_sd) ||
+            !(d.mut_sd_factor >= 0.0) || !std::isfinite(d.mut_sd_factor) || !(d.noise_sd >= 0.0) ||
+            !std::isfinite(d.noise_sd) || d.exp_transform > 1)
+            return fail(SPEGG_E_INVALID, "replicate %u: continuous-allele parameters out of range", i);
+    }
     return SPEGG_OK;
 }
 
@@ -233,7 +256,8 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const Gc
     spegg_status st = validate(d, i);
     if (st != SPEGG_OK) return st;
     const uint32_t L = d.n_loci;
-    p.W = (L + 31u) / 32u;
+    p.cont = d.genetics == SPEGG_CONTINUOUS;
+    p.W = p.cont ? (L + 3u) / 4u * 4u : (L + 31u) / 32u;
     p.mode = recomb_mode(d.r);
     p.R = (uint32_t)std::floor(d.r * 4294967296.0);
     p.mig_T = d.n_patches > 1 ? prob_threshold(d.migration) : 0;
@@ -248,7 +272,8 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const Gc
     }
     p.zmin = -abs_sum;
     p.zlen = 2u * (uint32_t)abs_sum + 1u;
-    if (d.omega > 0.0) viability_table(d.theta, d.omega, p.zmin, p.zlen, p.vtab);
+    // continuous phenotypes take their viability on the device
+    if (d.omega > 0.0 && !p.cont) viability_table(d.theta, d.omega, p.zmin, p.zlen, p.vtab);
     if (!p.unit) {
         // bit-planes of the offset effects e + 4 in [0, 8]
         p.planes.assign(4u * p.W, 0u);
@@ -268,12 +293,12 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const Gc
         geometric_table(d.r, L - 1u, p.geo);
         p.geo.resize(geometric_device_len(p.geo));
     }
-    int gcap = offspring_gcap(p.W);
+    int gcap = p.cont ? kDefaultContGCap : offspring_gcap(p.W);
     if (gcaps) {
-        const auto it = gcaps->find(p.W);
+        const auto it = gcaps->find(shape_key(p));
         if (it != gcaps->end()) gcap = it->second;
     }
-    p.shape = offspring_shape(p.W, gcap);
+    p.shape = shape_of_key(shape_key(p), gcap);
     p.opt = (uint32_t)offspring_per_tile(p.shape.g);
     p.n_demes = d.n_patches;
     if (d.regime == SPEGG_CONSUMER_RESOURCE) {
@@ -348,21 +373,23 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
     for (uint32_t i = 0; i < n; ++i) {
         const OffShape sh = P.reps[i].shape;
         bool seen = false;
-        for (const OffShape &x : shapes) seen |= x.g == sh.g && x.vpl == sh.vpl && x.nch == sh.nch;
+        for (const OffShape &x : shapes) seen |= same_shape(x, sh);
         if (!seen) shapes.push_back(sh);
     }
     for (const OffShape &sh : shapes) {
-        OffClass c{sh, (uint32_t)P.off_tiles.size(), 0, 0, -1, 0, 0, 0};
-        uint32_t maxW = 0, members = 0, last = 0, maxgeo = 0;
+        OffClass c{sh, (uint32_t)P.off_tiles.size(), 0, 0, -1, 0, 0, 0, 0};
+        uint32_t maxW = 0, members = 0, last = 0, maxgeo = 0, maxWb = 0;
         bool planes = false;
         for (uint32_t u = 0; u < P.demes.size(); ++u) {
             DemePlan &q = P.demes[u];
             const RepPlan &p = P.reps[q.rep];
-            if (p.shape.g != sh.g || p.shape.vpl != sh.vpl || p.shape.nch != sh.nch) continue;
+            if (!same_shape(p.shape, sh)) continue;
             q.off_tile0 = (uint32_t)P.off_tiles.size();
             q.off_ntiles = (q.cap + p.opt - 1) / p.opt;
             for (uint32_t k = 0; k < q.off_ntiles; ++k) P.off_tiles.push_back({u, k * p.opt});
             if (p.W > maxW) maxW = p.W;
+            const uint32_t Wb = (reps[q.rep].n_loci + 31u) / 32u;
+            if (Wb > maxWb) maxWb = Wb;
             if (p.geo.size() > maxgeo) maxgeo = (uint32_t)p.geo.size();
             planes |= !p.unit;
             ++members;
@@ -374,7 +401,11 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         c.grid = c.ntiles < gmax ? c.ntiles : gmax;
         c.plane_words = planes ? 4u * maxW : 0u;
         c.geo_words = maxgeo;
-        c.lds = (c.plane_words + c.geo_words) * sizeof(uint32_t) + offspring_lds_bytes(sh.g, maxW);
+        // continuous alleles: a crossover and a flip bitmap of one bit per
+        // locus per team and gamete (the biallelic formula over bitmap words)
+        c.mask_words = sh.cont ? maxWb : 0u;
+        c.lds = (c.plane_words + c.geo_words) * sizeof(uint32_t) +
+                offspring_lds_bytes(sh.g, sh.cont ? c.mask_words : maxW);
         P.classes.push_back(c);
     }
     Carver cv;
@@ -580,6 +611,8 @@ spegg_rep_stats census_of(const RepState &s) {
     for (int k = 0; k < kCensusSlots; ++k) {
         c.sum_z += s.sum_z[k];
         c.sum_z2 += (int64_t)s.sum_z2[k];
+        c.sum_zf += s.sum_zf[k];
+        c.sum_zf2 += s.sum_zf2[k];
     }
     c.near_ties = s.near_ties;
     c.truncated = s.truncated;
@@ -599,6 +632,8 @@ spegg_rep_stats sum_of(const spegg_rep_stats *p, uint32_t n) {
         c.captures += p[k].captures;
         c.sum_z += p[k].sum_z;
         c.sum_z2 += p[k].sum_z2;
+        c.sum_zf += p[k].sum_zf;
+        c.sum_zf2 += p[k].sum_zf2;
         c.near_ties += p[k].near_ties;
         c.truncated += p[k].truncated;
         c.sum_threshold += p[k].sum_threshold;
@@ -695,7 +730,8 @@ hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
             const OffClass &c = P.classes[ci];
             if (e != hipSuccess) return e;
             const OffArgs oa{pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0, c.ntiles, c.single_deme,
-                             pop->d_partials(), c.plane_words, c.geo_words, c.grid, c.lds, trace, pop->stream};
+                             pop->d_partials(), c.plane_words, c.geo_words, c.mask_words, c.grid, c.lds, trace,
+                             pop->stream};
             e = timed(pop, SPEGG_KERNEL_OFFSPRING, [&] { return launch_offspring(c.shape, oa); }, (int)ci);
         }
         if (e != hipSuccess) return e;
@@ -865,6 +901,14 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.binom = at<uint64_t>(pop->base, p.binom_at);
         h.geo = p.geo.empty() ? nullptr : at<uint64_t>(pop->base, p.geo_at);
         h.planes = p.planes.empty() ? nullptr : at<uint32_t>(pop->base, p.planes_at);
+        h.cont = p.cont ? 1u : 0u;
+        h.exp_tf = d.exp_transform ? 1u : 0u;
+        h.theta = d.theta;
+        h.omega = d.omega;
+        h.a0 = d.allele_mean;
+        h.s0 = d.allele_sd;
+        h.mut_sd = d.mut_sd_factor * std::fabs(d.allele_mean);
+        h.noise_sd = d.noise_sd;
         h.species = q.species;
         if (p.cr) {
             const spegg_ecology &ec = *d.ecology;
@@ -1048,6 +1092,8 @@ spegg_status spegg_read_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, ui
     if (st != SPEGG_OK) return st;
     uint32_t u;
     if ((st = find_deme(pop, rep, patch, species, &u)) != SPEGG_OK) return st;
+    if (pop->dev_descs[u].cont)
+        return fail(SPEGG_E_STATE, "read_genomes: replicate %u has continuous alleles (spegg_read_alleles)", rep);
     DeviceGuard guard(pop->device);
     RepState s;
     if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
@@ -1071,6 +1117,8 @@ spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, u
     uint32_t u;
     if ((st = find_deme(pop, rep, patch, species, &u)) != SPEGG_OK) return st;
     const RepDesc &h = pop->dev_descs[u];
+    if (h.cont)
+        return fail(SPEGG_E_STATE, "write_genomes: replicate %u has continuous alleles (spegg_write_alleles)", rep);
     if (n > h.cap) return fail(SPEGG_E_INVALID, "write_genomes: %u individuals exceed capacity %u", n, h.cap);
     if (n > 0 && !host_words) return fail(SPEGG_E_INVALID, "write_genomes: null words");
     for (uint32_t i = 0; i < n; ++i)
@@ -1086,7 +1134,7 @@ spegg_status spegg_write_genomes(spegg_pop *pop, uint32_t rep, uint32_t patch, u
         e = hipMemcpyAsync(h.genome[buf], host_words, (size_t)n * 2u * h.W * sizeof(uint32_t), hipMemcpyHostToDevice,
                            pop->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(pop->d_states() + u, &s0, sizeof s0, hipMemcpyHostToDevice, pop->stream);
-    if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + u, pop->d_states() + u, n, buf, pop->stream);
+    if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + u, pop->d_states() + u, n, buf, generation, pop->stream);
     if (e == hipSuccess) e = reset_species_state(pop, u);
     // the census restarts at an arbitrary generation: both parities of the
     // deme's tile-group sums from zero
@@ -1116,6 +1164,79 @@ spegg_status spegg_read_phenotypes(spegg_pop *pop, uint32_t rep, uint32_t patch,
                                   hipMemcpyDeviceToHost, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(phenotypes)");
     return sync_stream(pop);
+}
+
+spegg_status spegg_read_alleles(spegg_pop *pop, uint32_t rep, uint32_t patch, float *host_values, size_t n_values,
+                                uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
+    const RepDesc &h = pop->dev_descs[u];
+    if (!h.cont) return fail(SPEGG_E_STATE, "read_alleles: replicate %u has biallelic genomes", rep);
+    DeviceGuard guard(pop->device);
+    RepState s;
+    if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
+    const uint32_t n = s.n[current_pair_host(s)], t = s.t[current_pair_host(s)];
+    const size_t values = (size_t)n * 2u * h.L;
+    if (n_out) *n_out = n;
+    if (values == 0) return SPEGG_OK;
+    if (!host_values || n_values < values)
+        return fail(SPEGG_E_INVALID, "read_alleles: need room for %zu values, have %zu", values, n_values);
+    // the device rows are W >= L floats (the pad zero): copy, then drop the pad
+    std::vector<float> rows((size_t)n * 2u * h.W);
+    hipError_t e = hipMemcpyAsync(rows.data(), h.genome[t & 1u], rows.size() * sizeof(float), hipMemcpyDeviceToHost,
+                                  pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(alleles)");
+    if ((st = sync_stream(pop)) != SPEGG_OK) return st;
+    for (size_t r = 0; r < (size_t)n * 2u; ++r)
+        std::memcpy(host_values + r * h.L, rows.data() + r * h.W, sizeof(float) * h.L);
+    return SPEGG_OK;
+}
+
+spegg_status spegg_write_alleles(spegg_pop *pop, uint32_t rep, uint32_t patch, const float *host_values, uint32_t n,
+                                 uint32_t generation) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
+    const RepDesc &h = pop->dev_descs[u];
+    if (!h.cont) return fail(SPEGG_E_STATE, "write_alleles: replicate %u has biallelic genomes", rep);
+    if (n > h.cap) return fail(SPEGG_E_INVALID, "write_alleles: %u individuals exceed capacity %u", n, h.cap);
+    if (n > 0 && !host_values) return fail(SPEGG_E_INVALID, "write_alleles: null values");
+    for (size_t k = 0; k < (size_t)n * 2u * h.L; ++k)
+        if (!std::isfinite(host_values[k])) return fail(SPEGG_E_INVALID, "write_alleles: value %zu is not finite", k);
+    std::vector<float> rows((size_t)n * 2u * h.W, 0.0f);
+    for (size_t r = 0; r < (size_t)n * 2u; ++r)
+        std::memcpy(rows.data() + r * h.W, host_values + r * h.L, sizeof(float) * h.L);
+    DeviceGuard guard(pop->device);
+    if ((st = sync_stream(pop)) != SPEGG_OK) return st;
+    const uint32_t buf = generation & 1u;
+    const RepState s0 = initial_state(generation, n);
+    hipError_t e = hipSuccess;
+    if (n > 0)
+        e = hipMemcpyAsync(h.genome[buf], rows.data(), rows.size() * sizeof(float), hipMemcpyHostToDevice, pop->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(pop->d_states() + u, &s0, sizeof s0, hipMemcpyHostToDevice, pop->stream);
+    if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + u, pop->d_states() + u, n, buf, generation, pop->stream);
+    if (e == hipSuccess && h.grp_n)
+        e = launch_fill_u32((uint32_t *)(pop->d_surv_groups() + h.grp0),
+                            (size_t)2u * h.grp_n * sizeof(SurvGroup) / sizeof(uint32_t), pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "write_alleles");
+    st = sync_stream(pop);  // the host rows are copied before they are freed
+    if (st == SPEGG_OK) pop->deme_gen[u] = generation;
+    return st;
+}
+
+spegg_status spegg_read_phenotypes_f(spegg_pop *pop, uint32_t rep, uint32_t patch, float *host_z, size_t n,
+                                     uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
+    if (!pop->dev_descs[u].cont)
+        return fail(SPEGG_E_STATE, "read_phenotypes_f: replicate %u has integer phenotypes", rep);
+    static_assert(sizeof(float) == sizeof(int32_t), "phenotype buffers hold float bits");
+    return spegg_read_phenotypes(pop, rep, patch, 0, reinterpret_cast<int32_t *>(host_z), n, n_out);
 }
 
 spegg_status spegg_read_ages(spegg_pop *pop, uint32_t rep, uint32_t species, uint8_t *host_age, size_t n,
@@ -1182,6 +1303,7 @@ spegg_status spegg_allele_counts(spegg_pop *pop, uint32_t rep, uint32_t patch, u
     uint32_t u;
     if ((st = find_deme(pop, rep, patch, species, &u)) != SPEGG_OK) return st;
     const RepDesc &h = pop->dev_descs[u];
+    if (h.cont) return fail(SPEGG_E_UNSUPPORTED, "allele_counts: replicate %u has continuous alleles", rep);
     if (n_loci != h.L || !counts_dev || !host_counts)
         return fail(SPEGG_E_INVALID, "allele_counts: need n_loci == %u and both arrays", h.L);
     DeviceGuard guard(pop->device);
@@ -1205,6 +1327,7 @@ spegg_status spegg_allele_counts_noalloc(spegg_pop *pop, uint32_t rep, uint32_t 
     uint32_t u;
     if ((st = find_deme(pop, rep, patch, species, &u)) != SPEGG_OK) return st;
     const RepDesc &h = pop->dev_descs[u];
+    if (h.cont) return fail(SPEGG_E_UNSUPPORTED, "allele_counts_noalloc: replicate %u has continuous alleles", rep);
     if (n_loci != h.L || !host_counts)
         return fail(SPEGG_E_INVALID, "allele_counts_noalloc: need n_loci == %u and a host array", h.L);
     DeviceGuard guard(pop->device);
@@ -1287,9 +1410,9 @@ spegg_status spegg_offspring_class_times(spegg_pop *pop, uint32_t *w_min, uint32
         uint32_t lo = ~0u, hi = 0;
         for (const RepPlan &p : pop->plan.reps) {
             const OffShape &a = p.shape, &b = pop->plan.classes[c].shape;
-            if (a.g != b.g || a.vpl != b.vpl || a.nch != b.nch) continue;
-            lo = p.W < lo ? p.W : lo;
-            hi = p.W > hi ? p.W : hi;
+            if (!same_shape(a, b)) continue;
+            lo = shape_key(p) < lo ? shape_key(p) : lo;
+            hi = shape_key(p) > hi ? shape_key(p) : hi;
         }
         w_min[c] = lo;
         w_max[c] = hi;
@@ -1377,9 +1500,10 @@ spegg_status spegg_autotune(spegg_pop *pop, uint32_t generations_per_trial, uint
     if (st != SPEGG_OK) return st;
     if (generations_per_trial == 0) return fail(SPEGG_E_INVALID, "autotune: need at least one generation per trial");
     DeviceGuard guard(pop->device);
+    // one cap per genome key: words per haplotype, continuous alleles flagged
     std::vector<uint32_t> Ws;
     for (const RepPlan &p : pop->plan.reps)
-        if (std::find(Ws.begin(), Ws.end(), p.W) == Ws.end()) Ws.push_back(p.W);
+        if (std::find(Ws.begin(), Ws.end(), shape_key(p)) == Ws.end()) Ws.push_back(shape_key(p));
     std::sort(Ws.begin(), Ws.end());
     // Trials run as production does (graph replay when enabled), so no
     // per-launch events: two events bracket a run of whole generations.
@@ -1396,9 +1520,9 @@ spegg_status spegg_autotune(spegg_pop *pop, uint32_t generations_per_trial, uint
         std::vector<int> cands;
         std::vector<OffShape> seen;
         for (int g : {1, 2, 4, 8, 16, 32}) {
-            const OffShape sh = offspring_shape(W, g);
+            const OffShape sh = shape_of_key(W, g);
             bool dup = false;
-            for (const OffShape &x : seen) dup |= x.g == sh.g && x.vpl == sh.vpl && x.nch == sh.nch;
+            for (const OffShape &x : seen) dup |= same_shape(x, sh);
             if (!dup) {
                 seen.push_back(sh);
                 cands.push_back(g);
@@ -1461,10 +1585,10 @@ spegg_status spegg_set_offspring_cap(spegg_pop *pop, uint32_t W, uint32_t gcap) 
     if (gcap == 0 || gcap > 32 || (gcap & (gcap - 1)) != 0)
         return fail(SPEGG_E_INVALID, "set_offspring_cap: cap %u is not a power of two in 1..32", gcap);
     bool have = false;
-    for (const RepPlan &p : pop->plan.reps) have |= p.W == W;
-    if (!have) return fail(SPEGG_E_INVALID, "set_offspring_cap: no replicate has %u genome words", W);
+    for (const RepPlan &p : pop->plan.reps) have |= shape_key(p) == W;
+    if (!have) return fail(SPEGG_E_INVALID, "set_offspring_cap: no replicate has genome key %#x", W);
     DeviceGuard guard(pop->device);
-    const int saved = pop->gcaps.count(W) ? pop->gcaps[W] : offspring_gcap(W);
+    const int saved = pop->gcaps.count(W) ? pop->gcaps[W] : (W & kContKey) ? kDefaultContGCap : offspring_gcap(W);
     pop->gcaps[W] = (int)gcap;
     st = apply_shapes(pop);
     if (st != SPEGG_OK) pop->gcaps[W] = saved;

@@ -33,7 +33,9 @@ enum Stream : uint32_t {
     kStMutate = 8,  // + 0 maternal gamete, + 1 paternal
     kStMigrate = 10,
     kStEncounter = 11,
-    kStCapture = 12
+    kStCapture = 12,
+    kStMutVal = 13,  // continuous alleles: deviate of a mutated locus, + 0 maternal, + 1 paternal
+    kStNoise = 15    // continuous alleles: residual phenotypic noise
 };
 
 // Crossover sampling, a function of r alone.
@@ -114,6 +116,14 @@ struct RepDesc {
     const double *vtab;  // viability by phenotype, NULL: selection off
     const uint64_t *pois, *binom, *geo;
     const uint32_t *planes;  // 4 x W bit-planes of the offset effects e + 4 (bit 0, 1, 2, 3)
+    // Continuous alleles: W = L rounded up to a multiple of 4 floats per
+    // haplotype (the pad zero); the phenotype buffers hold float bits.
+    uint32_t cont;       // 1: continuous allelic values
+    uint32_t exp_tf;     // 1: the expressed phenotype is exp(z)
+    double theta, omega; // Gaussian viability of the expressed phenotype (omega <= 0: none)
+    double a0, s0;       // initial allelic values N(a0, s0^2)
+    double mut_sd;       // a mutation adds N(0, mut_sd^2): varpi |a0|
+    double noise_sd;     // residual phenotypic noise
 };
 
 // Per-deme state.  The census (generation t, size n) is double-buffered:
@@ -134,6 +144,8 @@ struct RepState {
     uint64_t near_ties, truncated, updates, sum_threshold;
     int64_t sum_z[kCensusSlots];
     uint64_t sum_z2[kCensusSlots];
+    double sum_zf[kCensusSlots];   // continuous alleles: sums of the expressed phenotypes
+    double sum_zf2[kCensusSlots];
 };
 
 struct SurvTile {
@@ -166,7 +178,8 @@ struct OffTile {
     uint32_t rep, start;
 };
 
-// Census sums of one offspring tile.
+// Census sums of one offspring tile (continuous alleles: the bits of two
+// doubles).
 struct Partial {
     int64_t sum_z;
     uint64_t sum_z2;
@@ -181,6 +194,7 @@ struct Partial {
 // depend on it.
 struct OffShape {
     int g, vpl, nch;
+    int cont = 0;  // continuous alleles (offspring_cont_kernel; vpl is 4 floats)
 };
 constexpr int kDefaultGCap = 4;
 inline OffShape offspring_shape(uint32_t W, int gcap = kDefaultGCap) {
@@ -201,6 +215,25 @@ inline OffShape offspring_shape(uint32_t W, int gcap = kDefaultGCap) {
         s.nch = (per + s.g - 1) / s.g <= 1 ? 1 : 0;
     }
     return s;
+}
+// Continuous alleles: W floats per haplotype (a multiple of 4), 4 per lane
+// per chunk, G lanes per gamete (a power of two, at most gcap); a gamete
+// spans nch chunks of 4G floats gathered up front (nch <= 4), or any number
+// gathered one at a time (nch = 0).  Any shape gives the same results.
+constexpr int kDefaultContGCap = 16;
+inline OffShape offspring_cont_shape(uint32_t W, int gcap = kDefaultContGCap) {
+    OffShape s;
+    s.cont = 1;
+    s.vpl = 4;
+    const uint32_t per = W / 4u;
+    s.g = 1;
+    while ((uint32_t)s.g < per && s.g < gcap) s.g <<= 1;
+    const uint32_t chunks = (per + s.g - 1) / s.g;
+    s.nch = chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 0;
+    return s;
+}
+inline bool same_shape(const OffShape &a, const OffShape &b) {
+    return a.g == b.g && a.vpl == b.vpl && a.nch == b.nch && a.cont == b.cont;
 }
 // Newborns of one team whose parents' words are gathered before the first
 // of them is finished (a latency-hiding knob; results do not depend on it).
@@ -236,6 +269,7 @@ struct OffArgs {
     Partial *partials;
     uint32_t plane_words;  // LDS words reserved for the effect planes
     uint32_t geo_words;    // LDS words reserved for the geometric-gap thresholds
+    uint32_t mask_words;   // continuous alleles: LDS words of one gamete's crossover (and flip) bitmap
     uint32_t grid;
     size_t lds;
     int trace;
@@ -247,7 +281,10 @@ struct OffArgs {
 // consumer-resource ages and capture keys) over the survival tiles.
 hipError_t launch_create(const RepDesc *descs, RepState *states, const SurvTile *tiles, uint32_t ntiles,
                          hipStream_t s);
-hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t n, uint32_t buf, hipStream_t s);
+// Phenotypes and census sums of a deme's n individuals in buffer buf,
+// written at generation gen (continuous alleles: founders' noise of gen).
+hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t n, uint32_t buf, uint32_t gen,
+                             hipStream_t s);
 hipError_t launch_survive(const SelArgs &a);
 hipError_t launch_compact(const SelArgs &a);
 hipError_t launch_offspring(OffShape shape, const OffArgs &a);

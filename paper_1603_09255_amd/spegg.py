@@ -61,6 +61,12 @@ class RepDesc(C.Structure):
         ("home_return", C.c_double),
         ("effects", C.POINTER(C.c_int8)),
         ("ecology", C.POINTER(Ecology)),
+        ("genetics", C.c_uint32),
+        ("allele_mean", C.c_double),
+        ("allele_sd", C.c_double),
+        ("mut_sd_factor", C.c_double),
+        ("noise_sd", C.c_double),
+        ("exp_transform", C.c_uint32),
     ]
 
 
@@ -78,6 +84,8 @@ class RepStats(C.Structure):
         ("truncated", C.c_uint64),
         ("sum_threshold", C.c_uint64),
         ("updates", C.c_uint64),
+        ("sum_zf", C.c_double),
+        ("sum_zf2", C.c_double),
     ]
 
     def as_dict(self):
@@ -118,6 +126,13 @@ def load():
     lib.spegg_write_genomes.argtypes = [vp, u32, u32, u32, P32, u32, u32]
     lib.spegg_read_phenotypes.restype = st
     lib.spegg_read_phenotypes.argtypes = [vp, u32, u32, u32, C.POINTER(C.c_int32), C.c_size_t, P32]
+    PF = C.POINTER(C.c_float)
+    lib.spegg_read_alleles.restype = st
+    lib.spegg_read_alleles.argtypes = [vp, u32, u32, PF, C.c_size_t, P32]
+    lib.spegg_write_alleles.restype = st
+    lib.spegg_write_alleles.argtypes = [vp, u32, u32, PF, u32, u32]
+    lib.spegg_read_phenotypes_f.restype = st
+    lib.spegg_read_phenotypes_f.argtypes = [vp, u32, u32, PF, C.c_size_t, P32]
     lib.spegg_read_ages.restype = st
     lib.spegg_read_ages.argtypes = [vp, u32, u32, C.POINTER(C.c_uint8), C.c_size_t, P32]
     lib.spegg_read_intake.restype = st
@@ -196,8 +211,10 @@ def _p(arr, ctype):
 
 
 DESC_KEYS = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
-             "fecundity", "effects", "n_patches", "migration", "ecology", "dispersal", "home_return")
+             "fecundity", "effects", "n_patches", "migration", "ecology", "dispersal", "home_return", "genetics",
+             "allele_mean", "allele_sd", "mut_sd_factor", "noise_sd", "exp_transform")
 RING, ISLAND = 0, 1
+BIALLELIC, CONTINUOUS = 0, 1
 
 
 def make_ecology(eco):
@@ -231,6 +248,10 @@ def make_descs(reps):
         for f in ("mu", "r", "theta", "omega", "K", "fecundity", "migration", "home_return"):
             setattr(arr[k], f, float(d.get(f, 0.5 if f == "r" else 0.0)))
         arr[k].dispersal = int(d.get("dispersal", RING))
+        arr[k].genetics = int(d.get("genetics", BIALLELIC))
+        for f in ("allele_mean", "allele_sd", "mut_sd_factor", "noise_sd"):
+            setattr(arr[k], f, float(d.get(f, 0.0)))
+        arr[k].exp_transform = int(d.get("exp_transform", 0))
         eff = d.get("effects")
         if eff is not None:
             e = np.ascontiguousarray(eff, dtype=np.int8)
@@ -402,6 +423,28 @@ class Population:
         got = C.c_uint32()
         check(self.lib.spegg_read_phenotypes(self._h, rep, patch, species, _p(out, C.c_int32), out.size,
                                              C.byref(got)))
+        return out[: got.value]
+
+    def alleles(self, rep=0, patch=0):
+        """Continuous allelic values of a patch, shape (n, 2, L) float32."""
+        n = self._n_of(rep, patch)
+        L = self.L[rep]
+        out = np.zeros(max(n, 1) * 2 * L, dtype=np.float32)
+        got = C.c_uint32()
+        check(self.lib.spegg_read_alleles(self._h, rep, patch, _p(out, C.c_float), out.size, C.byref(got)))
+        return out[: got.value * 2 * L].reshape(got.value, 2, L)
+
+    def write_alleles(self, rep, values, generation, patch=0):
+        v = np.ascontiguousarray(values, dtype=np.float32).reshape(-1)
+        n = v.size // (2 * self.L[rep])
+        check(self.lib.spegg_write_alleles(self._h, rep, patch, _p(v, C.c_float), n, int(generation)))
+
+    def phenotypes_f(self, rep=0, patch=0):
+        """Continuous alleles: expressed phenotypes, float32."""
+        n = self._n_of(rep, patch)
+        out = np.zeros(max(n, 1), dtype=np.float32)
+        got = C.c_uint32()
+        check(self.lib.spegg_read_phenotypes_f(self._h, rep, patch, _p(out, C.c_float), out.size, C.byref(got)))
         return out[: got.value]
 
     def ages(self, rep=0, species=0):

@@ -39,6 +39,22 @@ def plain_scale(seed=1):
                 effects=plain_scale_effects()), 1000
 
 
+CONTINUOUS = 1
+
+
+def continuous_scale(seed=1):
+    """The paper's own genetics (Supplementary S2, "Genetics") at scale: one
+    Wright-Fisher replicate of N = 100000 diploids with L = 256 loci of
+    continuous allelic values (float32), initial values N(0.01, 0.01^2),
+    free recombination (S2: all loci freely recombining), mutation with
+    probability 1e-3 per locus to N(value, (0.5 x 0.01)^2), residual
+    phenotypic noise 0.2, Gaussian stabilising selection of the phenotype
+    (optimum 2.6, width 1); 100 generations."""
+    return dict(seed=seed, replicate_id=0, regime=WF, n0=100_000, capacity=100_000, n_loci=256, mu=1e-3, r=0.5,
+                theta=2.6, omega=1.0, K=0.0, fecundity=0.0, effects=None, genetics=CONTINUOUS, allele_mean=0.01,
+                allele_sd=0.01, mut_sd_factor=0.5, noise_sd=0.2, exp_transform=0), 100
+
+
 def batched_table(n_reps=4096, seed=20260101, philox_seed=1):
     """Per-replicate parameters of the batched form: N ~ U{500..50000},
     L from {64, 256, 1024}, mu log-uniform in [1e-7, 1e-4], r ~ U[0.001, 0.5],
