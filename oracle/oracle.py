@@ -70,6 +70,12 @@ class OracleParams(C.Structure):
         ("mut_sd_factor", C.c_double),
         ("noise_sd", C.c_double),
         ("exp_transform", C.c_uint32),
+        ("linkage", C.POINTER(C.c_double)),
+        ("sexes", C.c_uint32),
+        ("mating", C.c_uint32),
+        ("pref_optimum", C.c_double),
+        ("pref_width", C.c_double),
+        ("monogamy", C.c_uint32),
     ]
 
 
@@ -177,6 +183,8 @@ def load():
     lib.oracle_phenotype_cont.restype = C.c_float
     lib.oracle_normals.argtypes = [u64, u32, u32, u32, u32, u32, u32, C.POINTER(C.c_double)]
     lib.oracle_normals.restype = None
+    lib.oracle_get_sexes.argtypes = [vp, u32, C.POINTER(C.c_uint8), C.c_size_t]
+    lib.oracle_get_sexes.restype = C.c_int
     _lib = lib
     return lib
 
@@ -259,7 +267,8 @@ class OraclePop:
     def __init__(self, seed=1, replicate_id=0, regime=0, n0=100, capacity=None, n_loci=64,
                  mu=0.0, r=0.5, theta=0.0, omega=0.0, K=0.0, fecundity=0.0, effects=None,
                  n_patches=1, migration=0.0, ecology=None, dispersal=0, home_return=0.0, genetics=0,
-                 allele_mean=0.0, allele_sd=0.0, mut_sd_factor=0.0, noise_sd=0.0, exp_transform=0):
+                 allele_mean=0.0, allele_sd=0.0, mut_sd_factor=0.0, noise_sd=0.0, exp_transform=0,
+                 linkage=None, sexes=0, mating=0, pref_optimum=0.0, pref_width=0.0, monogamy=0):
         lib = load()
         self.L = int(n_loci)
         self.W = (self.L + 31) // 32
@@ -271,13 +280,20 @@ class OraclePop:
             assert self._effects.shape == (self.L,)
             eff_ptr = _p(self._effects, C.c_int8)
         self._eco = make_ecology(ecology) if ecology is not None else None
+        self._linkage = None
+        link_ptr = None
+        if linkage is not None:
+            self._linkage = np.ascontiguousarray(linkage, dtype=np.float64)
+            assert self._linkage.shape == (max(self.L - 1, 0),)
+            link_ptr = _p(self._linkage, C.c_double)
         prm = OracleParams(seed=seed, replicate_id=replicate_id, regime=regime, n0=n0,
                            capacity=n0 if capacity is None else capacity, n_loci=n_loci, n_patches=n_patches,
                            mu=mu, r=r, theta=theta, omega=omega, K=K, fecundity=fecundity, migration=migration,
                            dispersal=dispersal, home_return=home_return, effects=eff_ptr,
                            ecology=C.pointer(self._eco) if self._eco is not None else None, genetics=genetics,
                            allele_mean=allele_mean, allele_sd=allele_sd, mut_sd_factor=mut_sd_factor,
-                           noise_sd=noise_sd, exp_transform=exp_transform)
+                           noise_sd=noise_sd, exp_transform=exp_transform, linkage=link_ptr, sexes=sexes,
+                           mating=mating, pref_optimum=pref_optimum, pref_width=pref_width, monogamy=monogamy)
         self.continuous = int(genetics) == 1
         self.capacity = prm.capacity
         self._h = lib.oracle_create(C.byref(prm))
@@ -357,6 +373,14 @@ class OraclePop:
         n = self.n_of(d)
         out = np.zeros(max(n, 1), dtype=np.int32)
         assert self._lib.oracle_get_phenotypes(self._h, d, _p(out, C.c_int32), out.size) == 0
+        return out[:n]
+
+    def sexes(self, patch=0, species=0):
+        """Separate sexes: 0 female, 1 male, per individual."""
+        d = self._deme(patch, species)
+        n = self.n_of(d)
+        out = np.zeros(max(n, 1), dtype=np.uint8)
+        assert self._lib.oracle_get_sexes(self._h, d, _p(out, C.c_uint8), out.size) == 0
         return out[:n]
 
     def ages(self, patch=0, species=0):

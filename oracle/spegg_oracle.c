@@ -53,13 +53,19 @@ enum {
     ST_CAPTURE = 12,
     ST_MUTVAL_MAT = 13, /* continuous alleles: deviate of a mutated locus */
     ST_MUTVAL_PAT = 14,
-    ST_NOISE = 15 /* continuous alleles: residual phenotypic noise */
+    ST_NOISE = 15, /* continuous alleles: residual phenotypic noise */
+    ST_SEX = 16,    /* separate sexes: sex of a newborn (block 0) or founder (block 1) */
+    ST_FEMALE = 17, /* separate sexes: proposals for a mother */
+    ST_MATE = 18    /* proposals for a father (sexes, mate choice or monogamy) */
 };
+
+enum { MATING_RANDOM = 0, MATING_PREFERENCE = 1, MATING_ASSORTATIVE = 2 };
+#define PARTNER_PROPOSALS 4096u /* proposals before the fallback rule (mate_of) */
 
 enum { GENETICS_BIALLELIC = 0, GENETICS_CONTINUOUS = 1 };
 
 enum { REGIME_WF = 0, REGIME_POISSON_BH = 1, REGIME_CONSUMER_RESOURCE = 2 };
-enum { MODE_RAW = 0, MODE_ZERO = 1, MODE_SKIP = 2, MODE_LAZY = 3 };
+enum { MODE_RAW = 0, MODE_ZERO = 1, MODE_SKIP = 2, MODE_LAZY = 3, MODE_MAP = 4 };
 
 /* ------------------------------------------------------------------ */
 /* Philox4x32-10, written from its published definition (Salmon et al. */
@@ -271,6 +277,14 @@ typedef struct {
     double mut_sd_factor; /* varpi: a mutation adds N(0, (varpi a0)^2) */
     double noise_sd;      /* varrho: residual phenotypic noise */
     uint32_t exp_transform; /* 1: the expressed phenotype is exp(z) */
+    /* Linkage map and mating systems (main text, the mating-system and
+     * linkage paragraph; Supplementary S2, "Reproduction"). */
+    const double *linkage; /* n_loci - 1 crossover probabilities, boundary b at [b-1]; NULL: r everywhere */
+    uint32_t sexes;        /* 1: separate sexes (mothers female, fathers male) */
+    uint32_t mating;       /* MATING_RANDOM, MATING_PREFERENCE (shared), MATING_ASSORTATIVE */
+    double pref_optimum;   /* shared preference: males near this phenotype are preferred */
+    double pref_width;     /* width of the preference or of the assortment, > 0 */
+    uint32_t monogamy;     /* 1: all offspring of a mother in a generation share one father */
 } oracle_params;
 
 typedef struct {
@@ -294,6 +308,8 @@ typedef struct {
     float *cg;       /* continuous alleles: cg[i][h][l] */
     float *zf;       /* continuous alleles: expressed phenotype */
     uint8_t *age;    /* consumer-resource regime: age of each individual */
+    uint8_t *sex;    /* separate sexes: 0 female, 1 male */
+    uint32_t n_surv_f; /* separate sexes: surviving females of the last generation */
     /* the last generation's survivors, fecundities and parents */
     uint32_t *survivors, n_survivors;
     uint32_t *kids, *owner, n_next, n_carry;
@@ -314,6 +330,7 @@ typedef struct {
     uint64_t *pois;
     int pois_len;
     uint64_t mig_T; /* migration threshold, 0: no migration */
+    uint32_t *Rmap; /* linkage map: floor(r_b 2^32) of boundary b (index b, 1..L-1); NULL: none */
     uint64_t home_T; /* island model: a migrant returns home when MIGRATE word 1 < home_T */
     uint32_t generation, n_patches, n_demes;
     oracle_deme *deme;
@@ -407,6 +424,24 @@ static float *allele_row_f(const oracle_pop *P, float *g, uint32_t i, uint32_t h
     return g + ((size_t)i * 2u + h) * P->L;
 }
 
+/* Separate sexes: an individual is female (0) or male (1) by one fair bit,
+ * bit 0 of word 0 of SEX block `sub` (0: newborn `index` of generation gen;
+ * 1: founder `index` of generation gen). */
+static uint8_t sex_of(rng_ctx *g, uint32_t index, uint32_t gen, uint32_t sub)
+{
+    return (uint8_t)(rng_word(g, index, ST_SEX, gen, sub, 0) & 1u);
+}
+
+static void founders_sex(const oracle_pop *P, oracle_deme *D, uint32_t n, uint32_t gen)
+{
+    uint32_t i;
+    free(D->sex);
+    D->sex = (uint8_t *)calloc(n ? n : 1, 1);
+    if (P->prm.sexes)
+        for (i = 0; i < n; ++i)
+            D->sex[i] = sex_of(&D->rng, i, gen, 1);
+}
+
 static uint8_t *allele_row(const oracle_pop *P, uint8_t *g, uint32_t i, uint32_t h)
 {
     return g + ((size_t)i * 2u + h) * P->L;
@@ -420,6 +455,8 @@ static void free_deme(oracle_deme *D)
     free(D->zf);
     D->cg = NULL;
     D->zf = NULL;
+    free(D->sex);
+    D->sex = NULL;
     free(D->age);
     free(D->won);
     free(D->intake);
@@ -454,6 +491,7 @@ void oracle_destroy(oracle_pop *P)
     free(P->geo);
     free(P->binom);
     free(P->pois);
+    free(P->Rmap);
     free(P);
 }
 
@@ -532,8 +570,16 @@ oracle_pop *oracle_create(const oracle_params *prm)
         (cr && !ecology_ok(prm->ecology)) || prm->genetics > GENETICS_CONTINUOUS ||
         (prm->genetics == GENETICS_CONTINUOUS &&
          (cr || prm->effects || !(prm->allele_sd >= 0.0) || !(prm->mut_sd_factor >= 0.0) || !(prm->noise_sd >= 0.0) ||
-          !isfinite(prm->allele_mean))))
+          !isfinite(prm->allele_mean))) ||
+        prm->sexes > 1 || prm->mating > MATING_ASSORTATIVE || prm->monogamy > 1 ||
+        (prm->mating != MATING_RANDOM && !(prm->pref_width > 0.0 && isfinite(prm->pref_width) &&
+                                           isfinite(prm->pref_optimum))) ||
+        ((prm->sexes || prm->mating || prm->monogamy) && (prm->n_patches != 1 || cr)))
         return NULL;
+    if (prm->linkage)
+        for (l = 0; l + 1 < L; ++l)
+            if (!(prm->linkage[l] >= 0.0 && prm->linkage[l] <= 0.5))
+                return NULL;
     P = (oracle_pop *)calloc(1, sizeof *P);
     if (!P)
         return NULL;
@@ -545,6 +591,15 @@ oracle_pop *oracle_create(const oracle_params *prm)
     P->prm.effects = P->effects;
     P->prm.ecology = NULL;
     P->mode = oracle_recomb_mode(prm->r);
+    P->prm.linkage = NULL;
+    if (prm->linkage) {
+        /* a linkage map: boundary b crosses over with its own probability
+         * r_b, by the exact bit-serial comparison against floor(r_b 2^32) */
+        P->mode = MODE_MAP;
+        P->Rmap = (uint32_t *)calloc(L, sizeof(uint32_t));
+        for (l = 1; l < L; ++l)
+            P->Rmap[l] = (uint32_t)floor(prm->linkage[l - 1] * TWO32);
+    }
     P->geo = (uint64_t *)malloc(sizeof(uint64_t) * (L > 1 ? L - 1 : 1));
     oracle_geometric_thresholds(prm->r, L - 1, P->geo);
     P->binom = (uint64_t *)malloc(sizeof(uint64_t) * (L + 1u));
@@ -606,6 +661,7 @@ oracle_pop *oracle_create(const oracle_params *prm)
             }
             D->z[i] = phenotype(P, allele_row(P, D->genome, i, 0), allele_row(P, D->genome, i, 1));
         }
+        founders_sex(P, D, n0, 0);
         census(P, D);
         D->stats.n_parents = 0;
         D->stats.extinct = n0 == 0;
@@ -682,6 +738,12 @@ static void recombination_mask(const oracle_pop *P, rng_ctx *g, uint32_t j, uint
         uint32_t bnd;
         for (bnd = 1; bnd < L; ++bnd)
             toggles[bnd] = (uint8_t)lazy_crossover(g, j, stream, gen, bnd / 32u, bnd % 32u, R);
+    } else if (P->mode == MODE_MAP) {
+        /* linkage map: the bit-serial comparison of each boundary against
+         * its own threshold, from the same words as a uniform r would use */
+        uint32_t bnd;
+        for (bnd = 1; bnd < L; ++bnd)
+            toggles[bnd] = (uint8_t)lazy_crossover(g, j, stream, gen, bnd / 32u, bnd % 32u, P->Rmap[bnd]);
     }
     /* MODE_ZERO: no crossover, the phase alone. */
     {
@@ -907,9 +969,13 @@ static void select_and_count(oracle_pop *P, oracle_deme *D, uint32_t t)
     /* Removal of the dead: survivors in ascending index order. */
     free(D->survivors);
     D->survivors = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    D->n_surv_f = 0;
     for (i = 0; i < n; ++i)
-        if (alive[i])
+        if (alive[i]) {
             D->survivors[ns++] = i;
+            if (P->prm.sexes && D->sex[i] == 0)
+                D->n_surv_f++;
+        }
     D->n_survivors = ns;
     D->stats.sum_threshold = sumT;
     free(alive);
@@ -919,9 +985,12 @@ static void select_and_count(oracle_pop *P, oracle_deme *D, uint32_t t)
     free(D->kids);
     D->kids = NULL;
     if (P->prm.regime == REGIME_POISSON_BH) {
+        /* with separate sexes only the females are mothers */
         D->kids = (uint32_t *)malloc(sizeof(uint32_t) * (ns ? ns : 1));
         for (i = 0; i < ns; ++i)
-            D->kids[i] = draw_by_table(seq_word(&D->rng, D->survivors[i], ST_FECUND, t, 0), P->pois, P->pois_len);
+            D->kids[i] = (P->prm.sexes && D->sex[D->survivors[i]] != 0)
+                             ? 0u
+                             : draw_by_table(seq_word(&D->rng, D->survivors[i], ST_FECUND, t, 0), P->pois, P->pois_len);
     } else if (cr) {
         D->kids = (uint32_t *)malloc(sizeof(uint32_t) * (ns ? ns : 1));
         if (D->species == 0) {
@@ -962,6 +1031,9 @@ static void neonates(oracle_pop *P, uint32_t k)
             for (q = 0; q < P->n_patches; ++q)
                 sources += P->deme[q].n_survivors;
         nn = sources > 0 ? D->n : 0;
+        /* separate sexes: a female and a male must survive */
+        if (P->prm.sexes && (D->n_surv_f == 0 || D->n_surv_f == D->n_survivors))
+            nn = 0;
     } else {
         uint64_t ktot = 0;
         uint32_t slot = 0, room;
@@ -970,6 +1042,9 @@ static void neonates(oracle_pop *P, uint32_t k)
         room = D->cap - D->n_carry;
         for (i = 0; i < D->n_survivors; ++i)
             ktot += D->kids[i];
+        /* separate sexes: eggs need a surviving male (and a female) */
+        if (P->prm.sexes && (D->n_surv_f == 0 || D->n_surv_f == D->n_survivors))
+            ktot = 0;
         nn = ktot > room ? room : (uint32_t)ktot;
         D->stats.truncated += ktot - nn;
         D->owner = (uint32_t *)malloc(sizeof(uint32_t) * (nn ? nn : 1));
@@ -1039,11 +1114,65 @@ static uint32_t island_source(oracle_pop *P, uint32_t k, uint32_t j, uint32_t t)
     return k; /* unreachable: a patch with no source has no offspring */
 }
 
+/* Phenotype of adult i as a double (integer or continuous alleles). */
+static double adult_z(const oracle_pop *P, const oracle_deme *D, uint32_t i)
+{
+    return P->prm.genetics == GENETICS_CONTINUOUS ? (double)D->zf[i] : (double)D->z[i];
+}
+
+/* Mate choice (main text: shared preference or assortative mating): the
+ * probability that a mother of adult index m accepts candidate c, as the
+ * threshold of its Bernoulli decision.  Shared preference: every mother
+ * prefers males near pref_optimum, a(c) = exp(-(z_c - opt)^2 / (2 w^2));
+ * assortative: a(c) = exp(-(z_m - z_c)^2 / (2 w^2)). */
+static uint64_t choice_threshold(const oracle_pop *P, const oracle_deme *D, uint32_t c, uint32_t m)
+{
+    double d, w = P->prm.pref_width;
+    if (P->prm.mating == MATING_PREFERENCE)
+        d = adult_z(P, D, c) - P->prm.pref_optimum;
+    else
+        d = adult_z(P, D, m) - adult_z(P, D, c);
+    return oracle_prob_threshold(exp(-(d * d) / (2.0 * w * w)));
+}
+
+/* A parent by proposals (Supplementary S2, "Reproduction": mothers among
+ * the females, fathers among the males, each egg's father drawn by the
+ * mothers' preference).  Proposal p is survivor S[idx(words 0, 1)] of
+ * block p of `stream` for index `key` in generation t; it is accepted when
+ * it has the wanted sex (want_sex 0 or 1; -1: any) and, with choice, word 2
+ * lies below its mate-choice threshold.  Rejection keeps the law exact:
+ * uniform over the eligible, times the acceptance probability.  After
+ * PARTNER_PROPOSALS rejected proposals the parent is the first survivor of
+ * the wanted sex at or after the last proposal in survivor order
+ * (wrapping), or the last proposal itself when any sex will do. */
+static uint32_t partner(const oracle_pop *P, oracle_deme *D, uint32_t stream, uint32_t key, uint32_t t, int want_sex,
+                        int choice, uint32_t mom)
+{
+    uint32_t p, r = 0, c, ns = D->n_survivors;
+    for (p = 0; p < PARTNER_PROPOSALS; ++p) {
+        r = uniform_index(rng_word(&D->rng, key, stream, t, p, 0), rng_word(&D->rng, key, stream, t, p, 1), ns);
+        c = D->survivors[r];
+        if (want_sex >= 0 && D->sex[c] != (uint8_t)want_sex)
+            continue;
+        if (choice && !((uint64_t)rng_word(&D->rng, key, stream, t, p, 2) < choice_threshold(P, D, c, mom)))
+            continue;
+        return c;
+    }
+    if (want_sex < 0)
+        return D->survivors[r];
+    for (p = 0; p < ns; ++p) {
+        c = D->survivors[(r + p) % ns];
+        if (D->sex[c] == (uint8_t)want_sex)
+            return c;
+    }
+    return D->survivors[r]; /* unreachable: the wanted sex survived */
+}
+
 /* The next census of deme k into *next, *znext, *anext: carried survivors
  * first (consumer-resource regime: genomes and phenotypes copied, one age
  * class older), then the newborns -- A (parents) + B + C. */
 static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int32_t **znext, uint8_t **anext,
-                      float **cnext, float **zfnext)
+                      float **cnext, float **zfnext, uint8_t **snext)
 {
     oracle_deme *D = &P->deme[k];
     uint32_t nc = D->n_carry, nn = D->n_next, j, L = P->L;
@@ -1065,6 +1194,7 @@ static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int
     *next = (uint8_t *)malloc((size_t)(total ? total : 1) * 2u * L);
     *znext = (int32_t *)malloc(sizeof(int32_t) * (total ? total : 1));
     *anext = (uint8_t *)calloc(total ? total : 1, 1);
+    *snext = (uint8_t *)calloc(total ? total : 1, 1);
     for (j = 0; j < nc; ++j) {
         uint32_t i = D->survivors[j];
         memcpy(allele_row(P, *next, j, 0), allele_row(P, D->genome, i, 0), 2u * L);
@@ -1080,10 +1210,17 @@ static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int
         oracle_deme *S = &P->deme[sp];
         uint32_t mom, dad, pos = nc + j;
         if (P->prm.regime == REGIME_WF)
-            mom = S->survivors[uniform_index(w0, w1, S->n_survivors)];
+            mom = P->prm.sexes ? partner(P, S, ST_FEMALE, j, t, 0, 0, 0)
+                               : S->survivors[uniform_index(w0, w1, S->n_survivors)];
         else
             mom = D->owner[j];
-        dad = S->survivors[uniform_index(w2, w3, S->n_survivors)];
+        if (!P->prm.sexes && P->prm.mating == MATING_RANDOM && !P->prm.monogamy)
+            dad = S->survivors[uniform_index(w2, w3, S->n_survivors)];
+        else /* monogamy: the father is the mother's one mate of the generation */
+            dad = partner(P, S, ST_MATE, P->prm.monogamy ? mom : j, t, P->prm.sexes ? 1 : -1,
+                          P->prm.mating != MATING_RANDOM, mom);
+        if (P->prm.sexes)
+            (*snext)[pos] = sex_of(&D->rng, j, t, 0);
         D->mom[j] = mom;
         D->dad[j] = dad;
         D->src[j] = P->prm.regime == REGIME_CONSUMER_RESOURCE ? 0u : sp; /* the source's patch */
@@ -1117,6 +1254,7 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
     uint8_t **anext = (uint8_t **)calloc(nd, sizeof(uint8_t *));
     float **cnext = (float **)calloc(nd, sizeof(float *));
     float **zfnext = (float **)calloc(nd, sizeof(float *));
+    uint8_t **snext = (uint8_t **)calloc(nd, sizeof(uint8_t *));
     for (it = 0; it < n_generations; ++it) {
         uint32_t t = P->generation;
         if (P->prm.regime == REGIME_CONSUMER_RESOURCE)
@@ -1126,7 +1264,7 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
         for (k = 0; k < nd; ++k)
             neonates(P, k);
         for (k = 0; k < nd; ++k)
-            offspring(P, k, t, &next[k], &znext[k], &anext[k], &cnext[k], &zfnext[k]);
+            offspring(P, k, t, &next[k], &znext[k], &anext[k], &cnext[k], &zfnext[k], &snext[k]);
         P->generation = t + 1;
         for (k = 0; k < nd; ++k) {
             oracle_deme *D = &P->deme[k];
@@ -1140,6 +1278,8 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
             free(D->zf);
             D->cg = cnext[k];
             D->zf = zfnext[k];
+            free(D->sex);
+            D->sex = snext[k];
             D->stats.n_parents = D->n;
             D->stats.n_survivors = D->n_survivors;
             D->n = D->n_carry + D->n_next;
@@ -1154,6 +1294,7 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
     free(anext);
     free(cnext);
     free(zfnext);
+    free(snext);
     return 0;
 }
 
@@ -1223,6 +1364,7 @@ int oracle_set_genomes(oracle_pop *P, uint32_t deme, const uint32_t *words, uint
     D->n_survivors = 0;
     D->n_next = 0;
     D->n_carry = 0;
+    founders_sex(P, D, n, generation);
     memset(&D->stats, 0, sizeof D->stats);
     D->stats.extinct = n == 0;
     census(P, D);
@@ -1235,6 +1377,16 @@ int oracle_get_phenotypes(const oracle_pop *P, uint32_t deme, int32_t *z, size_t
     if (!D || n < D->n)
         return -1;
     memcpy(z, D->z, sizeof(int32_t) * D->n);
+    return 0;
+}
+
+/* Separate sexes: 0 female, 1 male, per individual of the current census. */
+int oracle_get_sexes(const oracle_pop *P, uint32_t deme, uint8_t *sex, size_t n)
+{
+    oracle_deme *D = deme_of(P, deme);
+    if (!D || n < D->n)
+        return -1;
+    memcpy(sex, D->sex, D->n);
     return 0;
 }
 
@@ -1337,6 +1489,7 @@ int oracle_set_alleles(oracle_pop *P, uint32_t deme, const float *values, uint32
     D->n_survivors = 0;
     D->n_next = 0;
     D->n_carry = 0;
+    founders_sex(P, D, n, generation);
     memset(&D->stats, 0, sizeof D->stats);
     D->stats.extinct = n == 0;
     census(P, D);

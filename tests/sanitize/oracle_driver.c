@@ -23,6 +23,10 @@ typedef struct {
     uint32_t genetics;
     double allele_mean, allele_sd, mut_sd_factor, noise_sd;
     uint32_t exp_transform;
+    const double *linkage;
+    uint32_t sexes, mating;
+    double pref_optimum, pref_width;
+    uint32_t monogamy;
 } oracle_params;
 
 oracle_pop *oracle_create(const oracle_params *prm);
@@ -80,7 +84,7 @@ int main(void)
     oracle_ecology eco = {3000, 6000, 4, 30000, 0.5, 4.0, 20.0, 0.5, 0.55, 25000.0,
                           {0.5, 0.8, 0.8, 0.0}, {0.6, 0.8, 0.8, 0.0}};
     oracle_params base = {1, 3, 0, 400, 400, 64, 1, 1e-3, 0.5, 0.0, 8.0, 0.0, 0.0, 0.0, 0, 0.0, NULL, NULL,
-                          0, 0.0, 0.0, 0.0, 0.0, 0};
+                          0, 0.0, 0.0, 0.0, 0.0, 0, NULL, 0, 0, 0.0, 0.0, 0};
     oracle_params p;
     for (k = 0; k < 300; ++k)
         eff[k] = (int8_t)((int)(k * 7u % 9u) - 4);
@@ -99,6 +103,18 @@ int main(void)
     run(p, 3);
     p = base; p.regime = 2; p.n0 = 8000; p.capacity = 20000; p.n_loci = 96; p.r = 0.2; p.omega = 0.0;
     p.ecology = &eco; run(p, 3);
+    /* linkage map; separate sexes with preference, assortative, monogamy */
+    {
+        static double map[255];
+        for (k = 0; k < 255; ++k)
+            map[k] = (k % 5) * 0.1;
+        p = base; p.n_loci = 256; p.linkage = map; run(p, 3);
+    }
+    p = base; p.sexes = 1; p.mating = 1; p.pref_optimum = 2.0; p.pref_width = 3.0; run(p, 3);
+    p = base; p.sexes = 1; p.mating = 2; p.pref_width = 2.0; p.regime = 1; p.capacity = 900; p.K = 400.0;
+    p.fecundity = 2.2; run(p, 3);
+    p = base; p.monogamy = 1; p.mating = 2; p.pref_width = 0.5; run(p, 3);
+    p = base; p.sexes = 1; p.n0 = 2; p.capacity = 2; run(p, 4); /* one sex dies out */
     /* continuous alleles: Gaussian mutation, noise, exp transform */
     p = base; p.genetics = 1; p.allele_mean = 0.01; p.allele_sd = 0.005; p.mut_sd_factor = 0.5; p.noise_sd = 0.1;
     p.mu = 0.02; p.r = 0.05; p.n_loci = 70; p.omega = 2.0; p.theta = 1.0; p.exp_transform = 1; run(p, 3);
