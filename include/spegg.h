@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define SPEGG_ABI_VERSION 4
+#define SPEGG_ABI_VERSION 5
 #define SPEGG_MAX_LOCI 16384u
 #define SPEGG_MAX_REPLICATE_ID ((1u << 20) - 1u)
 #define SPEGG_MAX_PATCHES 1024u
@@ -165,6 +165,38 @@ enum { SPEGG_RING = 0, SPEGG_ISLAND = 1 };
  * without patches; effects must be NULL. */
 enum { SPEGG_BIALLELIC = 0, SPEGG_CONTINUOUS = 1 };
 
+/* Linkage map and mating systems (main text: arbitrary linkage; random,
+ * shared-preference or assortative mating, monogamy or polygynandry;
+ * Supplementary Information S2, "Reproduction": mothers among the females,
+ * fathers among the males).
+ *
+ * linkage: n_loci - 1 crossover probabilities in [0, 1/2], boundary b
+ * (between loci b-1 and b) at linkage[b-1]; boundary b crosses over when
+ * the bit-serial comparison of its uniform U against R_b = floor(r_b 2^32)
+ * finds U < R_b, U's bits from the top taken from bit b % 32 of words
+ * 1 + 8 (b / 32) + ... of the RECOMB stream, as for a uniform r of at least
+ * 0.17.  NULL: r at every boundary.
+ *
+ * sexes = 1: each individual is female or male by bit 0 of word 0 of stream
+ * 16 (block 0 for newborn j, block 1 for a founder); mothers are females,
+ * fathers males; in the Poisson regime only females have offspring; a
+ * population without a surviving female or male has no newborns.
+ *
+ * A parent of a wanted sex, and a father chosen by the mothers (mating =
+ * SPEGG_PREFERENCE: acceptance exp(-(z - pref_optimum)^2 / (2
+ * pref_width^2)), shared by every mother; SPEGG_ASSORTATIVE: exp(-(z_mother
+ * - z)^2 / (2 pref_width^2))), come from proposals: proposal p is survivor
+ * S[floor(x64 N_s / 2^64)] with x64 from words 0 (low) and 1 of block p of
+ * stream 17 (mothers) or 18 (fathers) for the newborn (or, under monogamy,
+ * for the mother's adult index, so that all her offspring of a generation
+ * share one father), accepted when it has the wanted sex and word 2 lies
+ * below floor(acceptance 2^32).  After 4096 rejected proposals the parent is
+ * the first survivor of the wanted sex at or after the last proposal in
+ * survivor order (wrapping), or that proposal when any sex will do.
+ * Without sexes, mate choice or monogamy the parents are drawn as before.
+ * Mating options need one patch and a one-species regime. */
+enum { SPEGG_RANDOM_MATING = 0, SPEGG_PREFERENCE = 1, SPEGG_ASSORTATIVE = 2 };
+
 /* One replicate.  The per-deme parameter table of Supplementary Fig. S5(B):
  * every individual looks up its replicate's entry. */
 typedef struct spegg_rep_desc {
@@ -192,6 +224,12 @@ typedef struct spegg_rep_desc {
     double mut_sd_factor;  /* SPEGG_CONTINUOUS: varpi, mutation sd = varpi |a0|, >= 0 */
     double noise_sd;       /* SPEGG_CONTINUOUS: residual phenotypic noise varrho, >= 0 */
     uint32_t exp_transform; /* SPEGG_CONTINUOUS: 1 expresses exp(z) */
+    const double *linkage; /* n_loci - 1 per-boundary crossover probabilities (copied at create); NULL: r */
+    uint32_t sexes;        /* 1: separate sexes */
+    uint32_t mating;       /* SPEGG_RANDOM_MATING, SPEGG_PREFERENCE or SPEGG_ASSORTATIVE */
+    double pref_optimum;   /* SPEGG_PREFERENCE: the preferred phenotype */
+    double pref_width;     /* mate choice: width of the acceptance, > 0 */
+    uint32_t monogamy;     /* 1: one father for all of a mother's offspring of a generation */
 } spegg_rep_desc;
 
 /* Census of one deme (a patch, or a species of the consumer-resource
@@ -293,6 +331,12 @@ spegg_status spegg_write_alleles(spegg_pop *pop, uint32_t rep, uint32_t patch, c
                                  uint32_t generation);
 spegg_status spegg_read_phenotypes_f(spegg_pop *pop, uint32_t rep, uint32_t patch, float *host_z, size_t n,
                                      uint32_t *n_out);
+
+/* Separate sexes: wait, then copy each individual's sex (N uint8, 0
+ * female, 1 male) of patch `patch` of replicate rep into host_sex; all 0
+ * without sexes. */
+spegg_status spegg_read_sexes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint8_t *host_sex, size_t n,
+                              uint32_t *n_out);
 
 /* Wait, then copy the age classes (N uint8, 0..3) of a deme of the
  * consumer-resource regime into host_age. */

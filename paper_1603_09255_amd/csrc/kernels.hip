@@ -315,6 +315,88 @@ __device__ __forceinline__ uint32_t load_ages(const uint8_t *p) {
     else return gload(p);
 }
 
+// Linkage map: the crossovers of 32-boundary word w of a gamete (bit b:
+// boundary 32w + b), each boundary's uniform U compared bit by bit against
+// its own threshold R_b from the top, U's plane p from bit b of word p % 4 of
+// RECOMB block 1 + 8w + p / 4; a boundary is decided at the first plane where
+// U and R_b differ (U < R_b: a crossover) or once R_b has no 1 bit left.
+__device__ __forceinline__ uint32_t map_word(const Rng &rng, uint32_t j, uint32_t rs, uint32_t tp,
+                                             const uint32_t *__restrict__ map, uint32_t w) {
+    const uint32_t *m = map + (size_t)w * kMapWords;
+    uint32_t und = gload(m + 64), hit = 0;
+    for (uint32_t k = 0; und != 0 && k < 8u; ++k) {
+        const Words4 b = rng.block(j, rs, 1u + w * 8u + k, tp);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t p = 4u * k + (uint32_t)q;
+            const uint32_t one = gload(m + p), x = b.v[q];
+            hit |= und & ~x & one;
+            und &= ~(x ^ one) & gload(m + 32u + p);
+        }
+    }
+    return hit;
+}
+
+// Mate choice: the threshold floor(a 2^32) of a mother (adult m) accepting
+// candidate c, from the host table for integer phenotypes (shared
+// preference by z, assortment by |z_m - z_c|) or computed in double for
+// continuous ones; cur is the adults' buffer.
+__device__ __forceinline__ uint64_t choice_threshold(const RepDesc &d, uint32_t cur, uint32_t c, uint32_t m) {
+    if (d.cont) {
+        const float *zf = reinterpret_cast<const float *>(d.z[cur]);
+        const double dz = d.mating == SPEGG_PREFERENCE ? (double)gload(zf + c) - d.pref_opt
+                                                       : (double)gload(zf + m) - (double)gload(zf + c);
+        const double a = exp(-(dz * dz) / (2.0 * d.pref_w * d.pref_w));
+        return a >= 1.0 ? kAlways : (a > 0.0 ? (uint64_t)floor(a * 4294967296.0) : 0ull);
+    }
+    const int32_t zc = gload(d.z[cur] + c);
+    if (d.mating == SPEGG_PREFERENCE) return gload(d.choiceT + (zc - d.choice_zmin));
+    const int32_t dz = gload(d.z[cur] + m) - zc;
+    return gload(d.choiceT + (dz < 0 ? -dz : dz));
+}
+
+// A parent by proposals, the TPO lanes of a team (lane `lane`, the team's
+// first wave lane seg0) testing proposals p0 + lane at once: proposal p is
+// survivor S[idx(words 0, 1)] of block p of `stream` for index `key`,
+// accepted when it has the wanted sex (want_sex 0 / 1; -1: any) and, with
+// choice, word 2 lies below its mate-choice threshold for mother `mom`; the
+// lowest accepted p wins.  After kPartnerProposals rejections: the first
+// survivor of the wanted sex at or after the last proposal in survivor order
+// (wrapping), or the last proposal when any sex will do.  Every lane of the
+// team returns the same adult index.
+template <uint32_t TPO>
+__device__ uint32_t team_partner(const RepDesc &d, const Rng &rng, uint32_t stream, uint32_t key, uint32_t tp,
+                                 uint32_t cur, int want_sex, bool choice, uint32_t mom, uint32_t ns, uint32_t lane,
+                                 uint32_t seg0) {
+    constexpr uint64_t tmask = TPO >= 64 ? ~0ull : ((1ull << TPO) - 1ull);
+    const uint8_t *sex = d.sex[cur];
+    uint32_t last = 0;
+    for (uint32_t p0 = 0; p0 < kPartnerProposals; p0 += TPO) {
+        const Words4 b = rng.block(key, stream, p0 + lane, tp);
+        const uint32_t r = uniform_index(b.v[0], b.v[1], ns);
+        const uint32_t c = gload(d.S + r);
+        bool ok = want_sex < 0 || (int)gload(sex + c) == want_sex;
+        if (ok && choice) ok = (uint64_t)b.v[2] < choice_threshold(d, cur, c, mom);
+        const uint64_t seg = (__ballot(ok) >> seg0) & tmask;
+        if (seg) return (uint32_t)__shfl((int)c, (int)__ffsll((unsigned long long)seg) - 1, (int)TPO);
+        last = (uint32_t)__shfl((int)r, (int)TPO - 1, (int)TPO);
+    }
+    if (want_sex < 0) return gload(d.S + last);
+    // the team scans survivor ranks from the last proposal, TPO at a time
+    for (uint32_t q0 = 0; q0 < ns; q0 += TPO) {
+        const uint32_t q = q0 + lane;
+        uint32_t c = 0;
+        bool ok = false;
+        if (q < ns) {
+            c = gload(d.S + (last + q) % ns);
+            ok = (int)gload(sex + c) == want_sex;
+        }
+        const uint64_t seg = (__ballot(ok) >> seg0) & tmask;
+        if (seg) return (uint32_t)__shfl((int)c, (int)__ffsll((unsigned long long)seg) - 1, (int)TPO);
+    }
+    return gload(d.S + last);  // unreachable: the wanted sex survived
+}
+
 // Words of one stream of one individual read in order, one Philox block
 // per four words.
 struct SeqWords {
@@ -424,6 +506,7 @@ __global__ void __launch_bounds__(kBlock) create_kernel(const RepDesc *__restric
             }
             const float z = phenotype_cont(d, rng, gv, i, 0, 1);
             gstore(d.z[0] + i, (int32_t)__float_as_uint(z));
+            if (d.sexes) gstore(d.sex[0] + i, (uint8_t)(rng.block(i, kStSex, 1, 0).v[0] & 1u));
             fz += (double)z;
             fz2 += (double)z * (double)z;
         }
@@ -460,6 +543,7 @@ __global__ void __launch_bounds__(kBlock) create_kernel(const RepDesc *__restric
             }
             const int64_t z = (int64_t)es.value(unit) - d.sum_e;
             gstore(d.z[0] + i, (int32_t)z);
+            if (d.sexes) gstore(d.sex[0] + i, (uint8_t)(rng.block(i, kStSex, 1, 0).v[0] & 1u));
             sz += z;
             sz2 += (uint64_t)(z * z);
         }
@@ -488,6 +572,7 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
             const Rng rng{d.key0, d.key1, d.c3};
             const float z = phenotype_cont(d, rng, gv, i, gen, 1);
             d.z[buf][i] = (int32_t)__float_as_uint(z);
+            if (d.sexes) d.sex[buf][i] = (uint8_t)(rng.block(i, kStSex, 1, gen).v[0] & 1u);
             fz = (double)z;
             fz2 = fz * fz;
         }
@@ -510,6 +595,10 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
         }
         z = (int64_t)es.value(d.unit_effects) - d.sum_e;
         d.z[buf][i] = (int32_t)z;
+        if (d.sexes) {
+            const Rng rng{d.key0, d.key1, d.c3};
+            d.sex[buf][i] = (uint8_t)(rng.block(i, kStSex, 1, gen).v[0] & 1u);
+        }
     }
     const int64_t sz = wave_sum<int64_t>(z);
     const uint64_t sz2 = wave_sum<uint64_t>((uint64_t)(z * z));
@@ -532,6 +621,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
                                                          SurvCount *__restrict__ counts,
                                                          SurvGroup *__restrict__ groups, int single_deme) {
     __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_n[kBlock / 64], sh_i[kBlock / 64];
+    __shared__ uint32_t sh_f[kBlock / 64];
     __shared__ uint64_t sh_t[kBlock / 64];
     __shared__ uint64_t sh_pois[kPoissonTableCap];
     // a population of one deme has its tiles implicit: no load before the
@@ -574,9 +664,10 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
         v[q] = (d.vtab && i0 + q < n) ? gload(d.vtab + ((int32_t)zw.v[q] - d.zmin))
                : (d.cont && i0 + q < n) ? viability_cont(d, zw.v[q])
                                         : 1.0;
-    uint32_t age4 = 0;
+    uint32_t age4 = 0, sex4 = 0;
     if (cr) age4 = load_ages<IT>(d.age[t & 1u] + i0);
-    uint32_t fate[IT], a_loc = 0, k_loc = 0, near = 0, in_loc = 0;
+    if (d.sexes) sex4 = load_ages<IT>(d.sex[t & 1u] + i0);  // 0 female, 1 male per byte
+    uint32_t fate[IT], a_loc = 0, k_loc = 0, near = 0, in_loc = 0, f_loc = 0;
     uint64_t thr_sum = 0;
 #pragma unroll
     for (uint32_t q = 0; q < IT; ++q) {
@@ -609,7 +700,11 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
                 near += (p > 0.0 && p < 1.0 && fabs((double)x * (1.0 / 4294967296.0) - p) < 1e-6) ? 1u : 0u;
                 if ((uint64_t)x < thr) {
                     uint32_t kids = 0;
-                    if (poisson || (cr && d.species == 0)) {
+                    const bool male = d.sexes && ((sex4 >> (8u * q)) & 1u);
+                    if (d.sexes && !male) ++f_loc;
+                    if (male) {
+                        // separate sexes: only females are mothers
+                    } else if (poisson || (cr && d.species == 0)) {
                         kids = table_draw(sh_pois, tlen, rng.block(i, kStFecund, 0, t).v[0]);
                     } else if (cr) {
                         const uint32_t off = gload(d.cpois_off + 2u * intake),
@@ -629,12 +724,14 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t wa = wave_sum<uint32_t>(a_loc), wk = wave_sum<uint32_t>(k_loc), wn = wave_sum<uint32_t>(near);
     const uint32_t wi = wave_sum<uint32_t>(in_loc);
+    const uint32_t wf = wave_sum<uint32_t>(f_loc);
     const uint64_t wt = wave_sum<uint64_t>(thr_sum);
     if (lane_id() == 0) {
         sh_a[wave] = wa;
         sh_k[wave] = wk;
         sh_n[wave] = wn;
         sh_i[wave] = wi;
+        sh_f[wave] = wf;
         sh_t[wave] = wt;
     }
     __syncthreads();
@@ -645,6 +742,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
             c.kids += sh_k[w];
             c.near += sh_n[w];
             c.intake += sh_i[w];
+            c.alive_f += sh_f[w];
             c.sum_t += sh_t[w];
         }
         c.par = par;
@@ -661,6 +759,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
             if (c.near) atomicAdd(&g.near, c.near);
             if (c.sum_t) atomicAdd((unsigned long long *)&g.sum_t, (unsigned long long)c.sum_t);
             if (c.intake) atomicAdd(&g.intake, c.intake);
+            if (c.alive_f) atomicAdd(&g.alive_f, c.alive_f);
         }
     }
 }
@@ -682,7 +781,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
                                                          SurvGroup *__restrict__ groups, int trace,
                                                          int single_deme) {
     constexpr uint32_t TILE = kBlock * IT;
-    __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_in[kBlock / 64];
+    __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_in[kBlock / 64], sh_f[kBlock / 64];
     __shared__ uint64_t sh_kk[kBlock / 64], sh_n[kBlock / 64], sh_t[kBlock / 64];
     const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * TILE}
                                            : tiles[blockIdx.x];
@@ -700,7 +799,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     // statistics only it records).  Past tile 0 the tiles of its own group
     // before it are known from the block index: those loads go out with the
     // census header's.
-    uint32_t pa = 0, pi = 0;
+    uint32_t pa = 0, pi = 0, pf = 0;
     uint64_t pk = 0, pn = 0, pt = 0;
     if (k != 0 && threadIdx.x < k - kg0) {
         const SurvCount c = C[kg0 + threadIdx.x];
@@ -725,6 +824,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
                 pn += g.near;
                 pt += g.sum_t;
                 pi += g.intake;
+                pf += g.alive_f;
             }
         } else {
             for (uint32_t q = threadIdx.x; q < active; q += kBlock) {
@@ -734,6 +834,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
                 pn += c.near;
                 pt += c.sum_t;
                 pi += c.intake;
+                pf += c.alive_f;
             }
         }
         // The other parity's group sums start the next generation from zero,
@@ -752,23 +853,26 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     pk = wave_sum<uint64_t>(pk);
     if (k == 0) {  // uniform over the block
         pi = wave_sum<uint32_t>(pi);
+        pf = wave_sum<uint32_t>(pf);
         pn = wave_sum<uint64_t>(pn);
         pt = wave_sum<uint64_t>(pt);
     }
     if (lane_id() == 0) {
         sh_a[wave] = pa;
         sh_in[wave] = pi;
+        sh_f[wave] = pf;
         sh_kk[wave] = pk;
         sh_n[wave] = pn;
         sh_t[wave] = pt;
     }
     __syncthreads();
-    uint32_t sum_a = 0, sum_i = 0;
+    uint32_t sum_a = 0, sum_i = 0, sum_f = 0;
     uint64_t sum_k = 0, sum_n = 0, sum_t = 0;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) {
         sum_a += sh_a[w];
         sum_i += sh_in[w];
+        sum_f += sh_f[w];
         sum_k += sh_kk[w];
         sum_n += sh_n[w];
         sum_t += sh_t[w];
@@ -803,8 +907,8 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
         const uint32_t ns = sum_a;
         const bool cr = d.regime == SPEGG_CONSUMER_RESOURCE;
         uint32_t nn;
-        if (ns + nb_alive == 0) {
-            nn = 0;
+        if (ns + nb_alive == 0 || (d.sexes && (sum_f == 0 || sum_f == ns))) {
+            nn = 0;  // no survivor, or (separate sexes) no surviving female or male
         } else if (d.regime == SPEGG_WF) {
             nn = n;
         } else {
@@ -818,6 +922,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
         st.captures = sum_i;
         st.n_prev = n;
         st.n_surv = ns;
+        st.n_surv_f = sum_f;
         st.t[par ^ 1u] = t + 1;
         st.n[par ^ 1u] = nn;
         if (nn == 0) st.extinct = 1;
@@ -911,8 +1016,10 @@ __device__ __forceinline__ uint32_t source_deme(const RepDesc &d, const RepState
 // Dynamic LDS: the effect planes (plane_words), the geometric-gap
 // thresholds (geo_words, skip mode), then, per team and gamete, a crossover
 // bitmap and a flip bitmap of W words each.
-template <int G, int V, int NCH>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NCH >= 1 && NCH <= 2 && G <= 8) ? 7 : 1, 8))) offspring_kernel(const RepDesc *__restrict__ descs,
+// EXT: the instance for replicates with a linkage map or a mating system
+// (separate sexes, mate choice, monogamy); the others run without that code.
+template <int G, int V, int NCH, bool EXT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((!EXT && NCH >= 1 && NCH <= 2 && G <= 8) ? 7 : 1, 8))) offspring_kernel(const RepDesc *__restrict__ descs,
                                                            const RepState *__restrict__ states,
                                                            const OffTile *__restrict__ tiles, uint32_t tile0,
                                                            uint32_t ntiles, int single_deme,
@@ -927,8 +1034,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
     constexpr int NREG = NCH > 0 ? NCH : 1;
     // per-newborn draws, one Philox block each, spread over the team:
     // 0 parents, 1/2 crossover phase (maternal/paternal), 3/4 mutation
-    // count, 5 migration (only where the deme has migration)
-    constexpr uint32_t NSD = 6;
+    // count, 5 migration (only where the deme has migration), 6 sex (EXT,
+    // separate sexes)
+    constexpr uint32_t NSD = EXT ? 7 : 6;
     constexpr uint32_t SR = (NSD + TPO - 1) / TPO;
     extern __shared__ uint32_t lds[];
     __shared__ int64_t red_z[kBlock / 64];
@@ -972,7 +1080,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
         if (start >= nn || st.error) continue;  // uniform over the block
         const uint32_t tp = st.t[newest] - 1u, cur = tp & 1u;
         const uint32_t W = d.W, L = d.L, mode = d.mode;
-        const uint32_t nsd = d.mig_T != 0 ? NSD : NSD - 1u;
+        const uint32_t nsd = d.mig_T != 0 ? 6u : 5u;  // draws 0..4, and 5 with migration
         const bool unit = d.unit_effects != 0;
         const uint64_t binom0 = d.binom0;  // most gametes carry no mutation
         const bool has_tail = d.tail_mask != ~0u;  // L not a multiple of 32
@@ -996,7 +1104,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
         // words (loads in flight); KF newborns of a team get their fronts
         // before the first is finished, so their gathers overlap.
         struct Front {
-            uint32_t j, phase, xk;
+            uint32_t j, phase, xk, sex;
             const uint32_t *src;
             uint32_t *dst;
             Words<V> h0[NREG], h1[NREG];
@@ -1009,8 +1117,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
                 const uint32_t stream = kd == 0   ? kStParent
                                         : kd <= 2 ? kStRecomb + kd - 1u
                                         : kd <= 4 ? kStMutate + kd - 3u
-                                                  : kStMigrate;
-                if (kd < nsd) {
+                                        : kd == 5 ? kStMigrate
+                                                  : kStSex;
+                const bool need = EXT ? kd < nsd || (kd == 6 && d.sexes) : kd < nsd;
+                if (need) {
                     sd[r] = rng.block(j, stream, 0, tp);
                 } else {
                     sd[r].v[0] = sd[r].v[1] = sd[r].v[2] = sd[r].v[3] = 0;
@@ -1031,6 +1141,18 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
             const uint32_t p0 = draw(0, 0), p1 = draw(0, 1), p2 = draw(0, 2), p3 = draw(0, 3);
             uint32_t mom = d.regime == SPEGG_WF ? gload(sd_src.S + uniform_index(p0, p1, ns)) : gload(d.owner + j);
             uint32_t dad = gload(sd_src.S + uniform_index(p2, p3, ns));
+            if constexpr (EXT) {
+                // mating systems (one patch: the source is the deme itself)
+                const uint32_t sx = draw(6, 0);
+                f.sex = sx & 1u;
+                if (d.sexes || d.mating != SPEGG_RANDOM_MATING || d.monogamy) {  // uniform over the block
+                    const uint32_t tseg0 = (tid & 63u) - lane;
+                    if (d.regime == SPEGG_WF && d.sexes)
+                        mom = team_partner<TPO>(d, rng, kStFemale, j, tp, cur, 0, false, 0u, ns, lane, tseg0);
+                    dad = team_partner<TPO>(d, rng, kStMate, d.monogamy ? mom : j, tp, cur, d.sexes ? 1 : -1,
+                                            d.mating != SPEGG_RANDOM_MATING, mom, ns, lane, tseg0);
+                }
+            }
             // Parents are adults of the last census.  An index beyond it means
             // a broken survivor or slot list: the deme is flagged (the next
             // census read reports it as a device error) and the index clamped
@@ -1183,6 +1305,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
                         ++k;
                     }
                 }
+            } else if (EXT && mode == kModeMap) {
+                // linkage map: each boundary against its own threshold
+                for (uint32_t w0 = gl * V; w0 < W; w0 += CH)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) X[w0 + v] = map_word(rng, j, rs, tp, d.map, w0 + v);
             }
 
             // B2: mutation, K ~ Binomial(L, mu) distinct loci flipped
@@ -1231,7 +1358,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
                         const uint32_t w = w0 + v;
                         uint32_t tog = 0;
                         if (valid) {
-                            if (mode == kModeSkip || mode == kModeLazy) tog = X[w];
+                            if (mode == kModeSkip || mode == kModeLazy || (EXT && mode == kModeMap)) tog = X[w];
                             if (w == 0) tog = (tog & ~1u) | phase;
                         }
                         const uint32_t pre = prefix_xor32(tog);
@@ -1282,6 +1409,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((NC
             if (lane == 0) {
                 const int32_t z = zc - d.sum_e;
                 gstore(d.z[cur ^ 1u] + base + j, z);
+                if (EXT && d.sexes) gstore(d.sex[cur ^ 1u] + base + j, (uint8_t)f.sex);
                 if (d.regime == SPEGG_CONSUMER_RESOURCE) {
                     gstore(d.age[cur ^ 1u] + base + j, (uint8_t)0);
                     if (d.species == 0) gstore(d.won + base + j, (uint64_t)~0ull);  // not captured in the next generation yet
@@ -1359,8 +1487,8 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
     constexpr int NREG = NCH > 0 ? NCH : 1;
     // per-newborn draws, one Philox block each, spread over the team: 0
     // parents, 1/2 crossover phase, 3/4 mutation count (maternal/paternal),
-    // 5 migration, 6 phenotypic noise
-    constexpr uint32_t NSD = 7;
+    // 5 migration, 6 phenotypic noise, 7 sex
+    constexpr uint32_t NSD = 8;
     constexpr uint32_t SR = (NSD + TPO - 1) / TPO;
     extern __shared__ uint32_t lds[];
     __shared__ double red_z[kBlock / 64], red_z2[kBlock / 64];
@@ -1416,8 +1544,9 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
                                         : kd <= 2 ? kStRecomb + kd - 1u
                                         : kd <= 4 ? kStMutate + kd - 3u
                                         : kd == 5 ? kStMigrate
-                                                  : kStNoise;
-                if (kd < NSD && (kd != 5 || d.mig_T != 0) && (kd != 6 || d.noise_sd > 0.0)) {
+                                        : kd == 6 ? kStNoise
+                                                  : kStSex;
+                if (kd < NSD && (kd != 5 || d.mig_T != 0) && (kd != 6 || d.noise_sd > 0.0) && (kd != 7 || d.sexes)) {
                     sd[r] = rng.block(j, stream, 0, tp);
                 } else {
                     sd[r].v[0] = sd[r].v[1] = sd[r].v[2] = sd[r].v[3] = 0;
@@ -1433,6 +1562,14 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
             const uint32_t p0 = draw(0, 0), p1 = draw(0, 1), p2 = draw(0, 2), p3 = draw(0, 3);
             uint32_t mom = d.regime == SPEGG_WF ? gload(sd_src.S + uniform_index(p0, p1, ns)) : gload(d.owner + j);
             uint32_t dad = gload(sd_src.S + uniform_index(p2, p3, ns));
+            const uint32_t sx = draw(7, 0) & 1u;
+            if (d.sexes || d.mating != SPEGG_RANDOM_MATING || d.monogamy) {  // uniform over the block; one patch
+                const uint32_t tseg0 = (tid & 63u) - lane;
+                if (d.regime == SPEGG_WF && d.sexes)
+                    mom = team_partner<TPO>(d, rng, kStFemale, j, tp, cur, 0, false, 0u, ns, lane, tseg0);
+                dad = team_partner<TPO>(d, rng, kStMate, d.monogamy ? mom : j, tp, cur, d.sexes ? 1 : -1,
+                                        d.mating != SPEGG_RANDOM_MATING, mom, ns, lane, tseg0);
+            }
             if (mom >= nprev || dad >= nprev) {
                 atomicOr(const_cast<uint32_t *>(&st.error), 1u);
                 mom = mom < nprev ? mom : nprev - 1u;
@@ -1443,6 +1580,7 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
                 gstore(d.dad + j, dad);
                 if (d.mig_T != 0) gstore(d.src + j, sd_src.patch);
             }
+            if (d.sexes && lane == 0) gstore(d.sex[cur ^ 1u] + j, (uint8_t)sx);
             const uint32_t *src = sd_src.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
             uint32_t *dst = d.genome[cur ^ 1u] + (size_t)j * 2u * W + (size_t)half * W;
             // every lane takes part in each cross-lane read, then selects
@@ -1519,6 +1657,9 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
                         }
                         X[w] = hit;
                     }
+                } else if (mode == kModeMap) {
+                    // linkage map: each boundary against its own threshold
+                    for (uint32_t w = gl; w < Wb; w += G) X[w] = map_word(rng, j, rs, tp, d.map, w);
                 }
                 wave_lds_sync();
                 // toggles -> mask words: prefix XOR within each word, the
@@ -1845,26 +1986,36 @@ inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kB
 using OffspringKernel = void (*)(const RepDesc *, const RepState *, const OffTile *, uint32_t, uint32_t, int,
                                  Partial *, uint32_t, uint32_t, int);
 
-template <int G, int V>
+template <int G, int V, bool EXT>
 OffspringKernel offspring_kernel_gv(int nch) {
     switch (nch) {
-    case 0: return offspring_kernel<G, V, 0>;
-    case 1: return offspring_kernel<G, V, 1>;
-    case 2: return offspring_kernel<G, V, 2>;
-    case 4: return offspring_kernel<G, V, 4>;
+    case 0: return offspring_kernel<G, V, 0, EXT>;
+    case 1: return offspring_kernel<G, V, 1, EXT>;
+    case 2: return offspring_kernel<G, V, 2, EXT>;
+    case 4: return offspring_kernel<G, V, 4, EXT>;
     default: return nullptr;
     }
 }
 
-template <int V>
+template <int V, bool EXT>
 OffspringKernel offspring_kernel_v(int g, int nch) {
     switch (g) {
-    case 1: return offspring_kernel_gv<1, V>(nch);
-    case 2: return offspring_kernel_gv<2, V>(nch);
-    case 4: return offspring_kernel_gv<4, V>(nch);
-    case 8: return offspring_kernel_gv<8, V>(nch);
-    case 16: return offspring_kernel_gv<16, V>(nch);
-    case 32: return offspring_kernel_gv<32, V>(nch);
+    case 1: return offspring_kernel_gv<1, V, EXT>(nch);
+    case 2: return offspring_kernel_gv<2, V, EXT>(nch);
+    case 4: return offspring_kernel_gv<4, V, EXT>(nch);
+    case 8: return offspring_kernel_gv<8, V, EXT>(nch);
+    case 16: return offspring_kernel_gv<16, V, EXT>(nch);
+    case 32: return offspring_kernel_gv<32, V, EXT>(nch);
+    default: return nullptr;
+    }
+}
+
+template <bool EXT>
+OffspringKernel offspring_kernel_ext(OffShape shape) {
+    switch (shape.vpl) {
+    case 1: return offspring_kernel_v<1, EXT>(shape.g, shape.nch);
+    case 2: return offspring_kernel_v<2, EXT>(shape.g, shape.nch);
+    case 4: return offspring_kernel_v<4, EXT>(shape.g, shape.nch);
     default: return nullptr;
     }
 }
@@ -1895,12 +2046,7 @@ OffspringKernel offspring_cont_kernel_for(int g, int nch) {
 // The kernel instance of a shape, or null for a shape outside the set.
 OffspringKernel offspring_kernel_for(OffShape shape) {
     if (shape.cont) return shape.vpl == 4 ? offspring_cont_kernel_for(shape.g, shape.nch) : nullptr;
-    switch (shape.vpl) {
-    case 1: return offspring_kernel_v<1>(shape.g, shape.nch);
-    case 2: return offspring_kernel_v<2>(shape.g, shape.nch);
-    case 4: return offspring_kernel_v<4>(shape.g, shape.nch);
-    default: return nullptr;
-    }
+    return shape.ext ? offspring_kernel_ext<true>(shape) : offspring_kernel_ext<false>(shape);
 }
 
 }  // namespace

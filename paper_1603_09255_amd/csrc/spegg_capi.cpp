@@ -56,6 +56,11 @@ struct Carver {
 struct RepPlan {
     uint32_t W = 0, mode = 0, R = 0, opt = 0;
     bool cont = false;  // continuous alleles: W floats per haplotype
+    bool ext = false;   // a linkage map or a mating system (the biallelic kernel's extended instance)
+    std::vector<uint32_t> map;      // linkage map planes (kModeMap)
+    std::vector<uint64_t> choiceT;  // mate-choice thresholds over integer phenotypes
+    int32_t choice_zmin = 0;
+    size_t map_at = 0, choiceT_at = 0;
     OffShape shape{1, 1, 1};
     int32_t zmin = 0, sum_e = 0;
     uint32_t zlen = 0;
@@ -79,7 +84,7 @@ struct DemePlan {
     uint32_t n0 = 0, cap = 0;
     uint32_t surv_tile0 = 0, surv_ntiles = 0, off_tile0 = 0, off_ntiles = 0;
     uint32_t grp0 = 0, grp_n = 0;  // tile-group sums (two parities of grp_n records)
-    size_t genome[2] = {0, 0}, z[2] = {0, 0}, fate = 0, S = 0, owner = 0, mom = 0, dad = 0, src = 0;
+    size_t genome[2] = {0, 0}, z[2] = {0, 0}, fate = 0, S = 0, owner = 0, mom = 0, dad = 0, src = 0, sex[2] = {0, 0};
     size_t age[2] = {0, 0}, won = 0, intake = 0;
 };
 
@@ -249,6 +254,18 @@ spegg_status validate(const spegg_rep_desc &d, uint32_t i) {
             !std::isfinite(d.noise_sd) || d.exp_transform > 1)
             return fail(SPEGG_E_INVALID, "replicate %u: continuous-allele parameters out of range", i);
     }
+    if (d.linkage)
+        for (uint32_t l = 0; l + 1 < d.n_loci; ++l)
+            if (!(d.linkage[l] >= 0.0 && d.linkage[l] <= 0.5))
+                return fail(SPEGG_E_INVALID, "replicate %u: linkage rate %g at boundary %u outside [0, 1/2]", i,
+                            d.linkage[l], l + 1);
+    if (d.sexes > 1 || d.monogamy > 1 || d.mating > SPEGG_ASSORTATIVE)
+        return fail(SPEGG_E_INVALID, "replicate %u: unknown sexes / mating / monogamy setting", i);
+    if (d.mating != SPEGG_RANDOM_MATING &&
+        !(d.pref_width > 0.0 && std::isfinite(d.pref_width) && std::isfinite(d.pref_optimum)))
+        return fail(SPEGG_E_INVALID, "replicate %u: mate choice needs a finite pref_width > 0", i);
+    if ((d.sexes || d.mating || d.monogamy) && (d.n_patches != 1 || d.regime == SPEGG_CONSUMER_RESOURCE))
+        return fail(SPEGG_E_UNSUPPORTED, "replicate %u: mating systems need one patch of a one-species regime", i);
     return SPEGG_OK;
 }
 
@@ -260,6 +277,11 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const Gc
     p.W = p.cont ? (L + 3u) / 4u * 4u : (L + 31u) / 32u;
     p.mode = recomb_mode(d.r);
     p.R = (uint32_t)std::floor(d.r * 4294967296.0);
+    p.ext = d.linkage || d.sexes || d.mating || d.monogamy;
+    if (d.linkage) {
+        p.mode = kModeMap;
+        linkage_planes(d.linkage, L, p.map);
+    }
     p.mig_T = d.n_patches > 1 ? prob_threshold(d.migration) : 0;
     int32_t abs_sum = 0;
     p.sum_e = 0;
@@ -288,6 +310,12 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const Gc
     if (d.regime == SPEGG_POISSON_BH && !poisson_table(d.fecundity, kPoissonTableCap, p.pois))
         return fail(SPEGG_E_UNSUPPORTED, "replicate %u: fecundity %g needs more than %d table entries", i,
                     d.fecundity, kPoissonTableCap);
+    if (d.mating != SPEGG_RANDOM_MATING && !p.cont) {
+        // integer phenotypes: acceptance by phenotype (shared preference) or
+        // by phenotype distance (assortment), both over the range of z
+        p.choice_zmin = p.zmin;
+        choice_table(d.mating == SPEGG_PREFERENCE, d.pref_optimum, d.pref_width, p.zmin, p.zlen, p.choiceT);
+    }
     if (p.mode == kModeSkip && L > 1) {
         // the kernel keeps the gap table up to its first threshold of 2^32
         geometric_table(d.r, L - 1u, p.geo);
@@ -299,6 +327,7 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const Gc
         if (it != gcaps->end()) gcap = it->second;
     }
     p.shape = shape_of_key(shape_key(p), gcap);
+    p.shape.ext = p.ext && !p.cont ? 1 : 0;  // the continuous kernel carries these paths itself
     p.opt = (uint32_t)offspring_per_tile(p.shape.g);
     p.n_demes = d.n_patches;
     if (d.regime == SPEGG_CONSUMER_RESOURCE) {
@@ -426,6 +455,8 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         p.binom_at = cv.take(sizeof(uint64_t) * p.binom.size());
         if (!p.geo.empty()) p.geo_at = cv.take(sizeof(uint64_t) * p.geo.size());
         if (!p.planes.empty()) p.planes_at = cv.take(sizeof(uint32_t) * p.planes.size());
+        if (!p.map.empty()) p.map_at = cv.take(sizeof(uint32_t) * p.map.size());
+        if (!p.choiceT.empty()) p.choiceT_at = cv.take(sizeof(uint64_t) * p.choiceT.size());
         if (p.cr) {
             p.enc_at = cv.take(sizeof(uint64_t) * p.enc.size());
             p.capT_at = cv.take(sizeof(uint64_t) * p.capT.size());
@@ -453,6 +484,10 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         q.mom = cv.take(cap * sizeof(uint32_t));
         q.dad = cv.take(cap * sizeof(uint32_t));
         if (p.mig_T) q.src = cv.take(cap * sizeof(uint32_t));
+        if (reps[q.rep].sexes) {
+            q.sex[0] = cv.take(zcap);  // padded to whole tiles: read 4 at a time
+            q.sex[1] = cv.take(zcap);
+        }
         if (p.cr) {
             q.age[0] = cv.take(zcap);  // padded to whole tiles: read 4 at a time
             q.age[1] = cv.take(zcap);
@@ -513,6 +548,7 @@ struct spegg_pop {
     Plan plan;
     std::vector<spegg_rep_desc> descs;           // the caller's descriptors, pointing at the copies below
     std::vector<std::vector<int8_t>> effects;    // copies of the effects
+    std::vector<std::vector<double>> linkage;    // copies of the linkage maps
     std::vector<spegg_ecology> ecology;          // copies of the ecologies
     GcapMap gcaps;                               // autotuned lanes-per-gamete caps by W
     std::vector<RepDesc> dev_descs;  // host images of the device descriptors, one per deme
@@ -909,6 +945,17 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.s0 = d.allele_sd;
         h.mut_sd = d.mut_sd_factor * std::fabs(d.allele_mean);
         h.noise_sd = d.noise_sd;
+        h.sexes = d.sexes;
+        h.mating = d.mating;
+        h.monogamy = d.monogamy;
+        h.pref_opt = d.pref_optimum;
+        h.pref_w = d.pref_width;
+        h.choice_len = (uint32_t)p.choiceT.size();
+        h.choice_zmin = p.choice_zmin;
+        h.choiceT = p.choiceT.empty() ? nullptr : at<uint64_t>(pop->base, p.choiceT_at);
+        h.map = p.map.empty() ? nullptr : at<uint32_t>(pop->base, p.map_at);
+        h.sex[0] = q.sex[0] ? at<uint8_t>(pop->base, q.sex[0]) : nullptr;
+        h.sex[1] = q.sex[1] ? at<uint8_t>(pop->base, q.sex[1]) : nullptr;
         h.species = q.species;
         if (p.cr) {
             const spegg_ecology &ec = *d.ecology;
@@ -941,6 +988,9 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         std::memcpy(img + p.binom_at, p.binom.data(), sizeof(uint64_t) * p.binom.size());
         if (!p.geo.empty()) std::memcpy(img + p.geo_at, p.geo.data(), sizeof(uint64_t) * p.geo.size());
         if (!p.planes.empty()) std::memcpy(img + p.planes_at, p.planes.data(), sizeof(uint32_t) * p.planes.size());
+        if (!p.map.empty()) std::memcpy(img + p.map_at, p.map.data(), sizeof(uint32_t) * p.map.size());
+        if (!p.choiceT.empty())
+            std::memcpy(img + p.choiceT_at, p.choiceT.data(), sizeof(uint64_t) * p.choiceT.size());
         if (p.cr) {
             std::memcpy(img + p.enc_at, p.enc.data(), sizeof(uint64_t) * p.enc.size());
             std::memcpy(img + p.capT_at, p.capT.data(), sizeof(uint64_t) * p.capT.size());
@@ -977,8 +1027,9 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         delete pop;
         return fail(SPEGG_E_DEVICE, "initial population: %s", hipGetErrorString(e));
     }
-    // The effects and ecology pointers are the caller's: point at copies.
+    // The effects, linkage and ecology pointers are the caller's: point at copies.
     pop->effects.resize(n_reps);
+    pop->linkage.resize(n_reps);
     pop->ecology.resize(n_reps);
     for (uint32_t i = 0; i < n_reps; ++i) {
         spegg_rep_desc &d = pop->descs[i];
@@ -989,6 +1040,10 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         if (d.ecology) {
             pop->ecology[i] = *d.ecology;
             d.ecology = &pop->ecology[i];
+        }
+        if (d.linkage) {
+            pop->linkage[i].assign(d.linkage, d.linkage + (d.n_loci > 1 ? d.n_loci - 1 : 0));
+            d.linkage = pop->linkage[i].data();
         }
     }
     *out = pop;
@@ -1237,6 +1292,29 @@ spegg_status spegg_read_phenotypes_f(spegg_pop *pop, uint32_t rep, uint32_t patc
         return fail(SPEGG_E_STATE, "read_phenotypes_f: replicate %u has integer phenotypes", rep);
     static_assert(sizeof(float) == sizeof(int32_t), "phenotype buffers hold float bits");
     return spegg_read_phenotypes(pop, rep, patch, 0, reinterpret_cast<int32_t *>(host_z), n, n_out);
+}
+
+spegg_status spegg_read_sexes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint8_t *host_sex, size_t n,
+                              uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, patch, 0, &u)) != SPEGG_OK) return st;
+    DeviceGuard guard(pop->device);
+    RepState s;
+    if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
+    const uint32_t cn = s.n[current_pair_host(s)], ct = s.t[current_pair_host(s)];
+    if (n_out) *n_out = cn;
+    if (cn == 0) return SPEGG_OK;
+    if (!host_sex || n < cn) return fail(SPEGG_E_INVALID, "read_sexes: need room for %u values", cn);
+    const RepDesc &h = pop->dev_descs[u];
+    if (!h.sex[0]) {
+        std::memset(host_sex, 0, cn);
+        return SPEGG_OK;
+    }
+    hipError_t e = hipMemcpyAsync(host_sex, h.sex[ct & 1u], cn, hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(sexes)");
+    return sync_stream(pop);
 }
 
 spegg_status spegg_read_ages(spegg_pop *pop, uint32_t rep, uint32_t species, uint8_t *host_age, size_t n,

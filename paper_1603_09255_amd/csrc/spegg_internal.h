@@ -35,11 +35,26 @@ enum Stream : uint32_t {
     kStEncounter = 11,
     kStCapture = 12,
     kStMutVal = 13,  // continuous alleles: deviate of a mutated locus, + 0 maternal, + 1 paternal
-    kStNoise = 15    // continuous alleles: residual phenotypic noise
+    kStNoise = 15,   // continuous alleles: residual phenotypic noise
+    kStSex = 16,     // separate sexes: newborn's sex (block 0), founder's (block 1)
+    kStFemale = 17,  // separate sexes: proposals for a mother
+    kStMate = 18     // proposals for a father (sexes, mate choice, monogamy)
 };
 
+// Proposals for a parent before the fallback rule (the next survivor of the
+// wanted sex); the team tests this many in rounds of its lane count.
+constexpr uint32_t kPartnerProposals = 4096;
+
 // Crossover sampling, a function of r alone.
-enum Mode : uint32_t { kModeRaw = 0, kModeZero = 1, kModeSkip = 2, kModeLazy = 3 };
+enum Mode : uint32_t { kModeRaw = 0, kModeZero = 1, kModeSkip = 2, kModeLazy = 3, kModeMap = 4 };
+
+// Linkage map: per 32-boundary word w of a gamete, kMapWords words at
+// map + w kMapWords: [0, 32) the bit planes of the boundaries' thresholds
+// R_b = floor(r_b 2^32) (word p: bit 31 - p of each R_b, top bit first),
+// [32, 64) after plane p the boundaries whose R_b has a 1 bit below it,
+// [64] the boundaries with R_b != 0 (boundary 0 and those past L - 1
+// excluded).
+constexpr uint32_t kMapWords = 65;
 
 // Geometric gap drawn by word x: the number of thresholds T[0..len) that are
 // <= x, i.e. the smallest k with x < T_k, or len when x reaches them all.  T
@@ -124,6 +139,16 @@ struct RepDesc {
     double a0, s0;       // initial allelic values N(a0, s0^2)
     double mut_sd;       // a mutation adds N(0, mut_sd^2): varpi |a0|
     double noise_sd;     // residual phenotypic noise
+    // Mating systems and linkage map
+    uint32_t sexes;      // 1: separate sexes, sex[] holds 0 female / 1 male
+    uint32_t mating;     // SPEGG_RANDOM_MATING, SPEGG_PREFERENCE, SPEGG_ASSORTATIVE
+    uint32_t monogamy;   // 1: a mother's offspring share one father
+    uint32_t choice_len; // entries of choiceT (biallelic phenotypes)
+    int32_t choice_zmin; // shared preference: choiceT[z - choice_zmin]; assortative: choiceT[|dz|]
+    double pref_opt, pref_w;  // mate-choice optimum and width (continuous phenotypes: on the device)
+    const uint64_t *choiceT;  // acceptance thresholds floor(a 2^32) (biallelic phenotypes)
+    const uint32_t *map;      // linkage map planes, kMapWords per 32-boundary word (kModeMap)
+    uint8_t *sex[2];          // separate sexes, ping-pong with the genomes
 };
 
 // Per-deme state.  The census (generation t, size n) is double-buffered:
@@ -140,7 +165,7 @@ struct RepState {
     uint32_t error;           // set by a kernel that found an impossible state (never expected)
     uint32_t captures;        // consumers: credited captures of the last generation
     uint32_t n_carry;         // survivors carried into the current census (consumer-resource regime)
-    uint32_t pad0;
+    uint32_t n_surv_f;        // separate sexes: females among the survivors
     uint64_t near_ties, truncated, updates, sum_threshold;
     int64_t sum_z[kCensusSlots];
     uint64_t sum_z2[kCensusSlots];
@@ -159,7 +184,8 @@ struct SurvCount {
     uint32_t alive, kids, near, par;
     uint64_t sum_t;
     uint32_t t, n;
-    uint32_t intake, pad;  // consumers: credited captures of the tile's adults
+    uint32_t intake;   // consumers: credited captures of the tile's adults
+    uint32_t alive_f;  // separate sexes: surviving females
 };
 
 // Sums over a group of kGroupTiles consecutive survival tiles of a deme, for
@@ -171,7 +197,7 @@ struct SurvCount {
 constexpr uint32_t kGroupTiles = 256;
 struct SurvGroup {
     uint64_t kids, sum_t;
-    uint32_t alive, near, intake, pad;
+    uint32_t alive, near, intake, alive_f;
 };
 
 struct OffTile {
@@ -195,6 +221,7 @@ struct Partial {
 struct OffShape {
     int g, vpl, nch;
     int cont = 0;  // continuous alleles (offspring_cont_kernel; vpl is 4 floats)
+    int ext = 0;   // a linkage map or a mating system (the biallelic kernel's extended instance)
 };
 constexpr int kDefaultGCap = 4;
 inline OffShape offspring_shape(uint32_t W, int gcap = kDefaultGCap) {
@@ -233,7 +260,7 @@ inline OffShape offspring_cont_shape(uint32_t W, int gcap = kDefaultContGCap) {
     return s;
 }
 inline bool same_shape(const OffShape &a, const OffShape &b) {
-    return a.g == b.g && a.vpl == b.vpl && a.nch == b.nch && a.cont == b.cont;
+    return a.g == b.g && a.vpl == b.vpl && a.nch == b.nch && a.cont == b.cont && a.ext == b.ext;
 }
 // Newborns of one team whose parents' words are gathered before the first
 // of them is finished (a latency-hiding knob; results do not depend on it).

@@ -83,6 +83,8 @@ struct Job {
     uint64_t id = 0;
     std::vector<spegg_rep_desc> reps;
     std::vector<std::vector<int8_t>> effects;  // owned copies behind reps[i].effects
+    std::vector<std::vector<double>> linkage;  // owned copies behind reps[i].linkage
+    std::vector<spegg_ecology> ecology;        // owned copies behind reps[i].ecology
     uint32_t remaining = 0;
     size_t bytes = 0, off = 0;
     uint32_t lane = 0;   // stream index
@@ -243,11 +245,22 @@ spegg_status spegg_server_submit(spegg_server *s, uint64_t job_id, const spegg_r
     j.id = job_id;
     j.reps.assign(reps, reps + n_reps);
     j.effects.resize(n_reps);
-    for (uint32_t i = 0; i < n_reps; ++i)
+    j.linkage.resize(n_reps);
+    j.ecology.resize(n_reps);
+    for (uint32_t i = 0; i < n_reps; ++i) {
         if (reps[i].effects) {
             j.effects[i].assign(reps[i].effects, reps[i].effects + reps[i].n_loci);
             j.reps[i].effects = j.effects[i].data();
         }
+        if (reps[i].linkage) {
+            j.linkage[i].assign(reps[i].linkage, reps[i].linkage + (reps[i].n_loci > 1 ? reps[i].n_loci - 1 : 0));
+            j.reps[i].linkage = j.linkage[i].data();
+        }
+        if (reps[i].ecology) {
+            j.ecology[i] = *reps[i].ecology;
+            j.reps[i].ecology = &j.ecology[i];
+        }
+    }
     j.remaining = n_generations;
     j.bytes = bytes;
     s->waiting.push_back(std::move(j));
@@ -297,8 +310,14 @@ spegg_status spegg_server_step(spegg_server *s, uint32_t n_generations, uint32_t
             return st;
         }
         s->lane_load[j.lane] += j.load;
-        for (auto &r : j.reps) r.effects = nullptr;  // copied into the job's tables
+        for (auto &r : j.reps) {  // copied into the job's tables
+            r.effects = nullptr;
+            r.linkage = nullptr;
+            r.ecology = nullptr;
+        }
         j.effects.clear();
+        j.linkage.clear();
+        j.ecology.clear();
         s->resident.push_back(std::move(j));
         s->waiting.pop_front();
     }

@@ -105,4 +105,30 @@ void capture_table(double a, double sigma, uint32_t n, std::vector<uint64_t> &T)
     }
 }
 
+// Mate choice over integer phenotypes (acceptance thresholds).
+void choice_table(bool preference, double opt, double w, int32_t zmin, uint32_t n, std::vector<uint64_t> &T) {
+    T.resize(n);
+    for (uint32_t k = 0; k < n; ++k) {
+        const double d = preference ? (double)(zmin + (int32_t)k) - opt : (double)k;
+        T[k] = prob_threshold(std::exp(-(d * d) / (2.0 * w * w)));
+    }
+}
+
+// Linkage map: threshold bit planes per 32-boundary word.
+void linkage_planes(const double *r, uint32_t L, std::vector<uint32_t> &M) {
+    const uint32_t Wb = (L + 31u) / 32u;
+    M.assign((size_t)Wb * kMapWords, 0u);
+    for (uint32_t b = 1; b < L; ++b) {
+        const uint32_t R = (uint32_t)std::floor(r[b - 1] * 4294967296.0);
+        uint32_t *m = M.data() + (size_t)(b / 32u) * kMapWords;
+        const uint32_t bit = 1u << (b % 32u);
+        if (R != 0) m[64] |= bit;
+        for (uint32_t p = 0; p < 32; ++p) {
+            const uint32_t i = 31u - p;  // the bit of R that plane p compares
+            if ((R >> i) & 1u) m[p] |= bit;
+            if (R & ((1u << i) - 1u)) m[32 + p] |= bit;  // a 1 bit below it
+        }
+    }
+}
+
 }  // namespace spegg

@@ -25,5 +25,13 @@ void viability_table(double theta, double omega, int32_t zmin, uint32_t n, std::
 // Capture thresholds floor(a exp(-d^2 / (2 sigma^2)) 2^32) for phenotype
 // distances d = 0 .. n - 1.
 void capture_table(double a, double sigma, uint32_t n, std::vector<uint64_t> &T);
+// Mate choice over integer phenotypes: acceptance thresholds floor(a 2^32)
+// of a = exp(-d^2 / (2 w^2)); shared preference: d = z - opt for z = zmin +
+// k; assortment (opt ignored): d = k, the phenotype distance (k < n).
+void choice_table(bool preference, double opt, double w, int32_t zmin, uint32_t n, std::vector<uint64_t> &T);
+// Linkage map planes of a gamete of L loci (rates r[b-1] of boundaries
+// b = 1..L-1), kMapWords words per 32-boundary word (layout in
+// spegg_internal.h).
+void linkage_planes(const double *r, uint32_t L, std::vector<uint32_t> &M);
 
 }  // namespace spegg

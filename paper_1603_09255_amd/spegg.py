@@ -67,6 +67,12 @@ class RepDesc(C.Structure):
         ("mut_sd_factor", C.c_double),
         ("noise_sd", C.c_double),
         ("exp_transform", C.c_uint32),
+        ("linkage", C.POINTER(C.c_double)),
+        ("sexes", C.c_uint32),
+        ("mating", C.c_uint32),
+        ("pref_optimum", C.c_double),
+        ("pref_width", C.c_double),
+        ("monogamy", C.c_uint32),
     ]
 
 
@@ -133,6 +139,8 @@ def load():
     lib.spegg_write_alleles.argtypes = [vp, u32, u32, PF, u32, u32]
     lib.spegg_read_phenotypes_f.restype = st
     lib.spegg_read_phenotypes_f.argtypes = [vp, u32, u32, PF, C.c_size_t, P32]
+    lib.spegg_read_sexes.restype = st
+    lib.spegg_read_sexes.argtypes = [vp, u32, u32, C.POINTER(C.c_uint8), C.c_size_t, P32]
     lib.spegg_read_ages.restype = st
     lib.spegg_read_ages.argtypes = [vp, u32, u32, C.POINTER(C.c_uint8), C.c_size_t, P32]
     lib.spegg_read_intake.restype = st
@@ -212,9 +220,11 @@ def _p(arr, ctype):
 
 DESC_KEYS = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
              "fecundity", "effects", "n_patches", "migration", "ecology", "dispersal", "home_return", "genetics",
-             "allele_mean", "allele_sd", "mut_sd_factor", "noise_sd", "exp_transform")
+             "allele_mean", "allele_sd", "mut_sd_factor", "noise_sd", "exp_transform", "linkage", "sexes", "mating",
+             "pref_optimum", "pref_width", "monogamy")
 RING, ISLAND = 0, 1
 BIALLELIC, CONTINUOUS = 0, 1
+RANDOM_MATING, PREFERENCE, ASSORTATIVE = 0, 1, 2
 
 
 def make_ecology(eco):
@@ -252,6 +262,14 @@ def make_descs(reps):
         for f in ("allele_mean", "allele_sd", "mut_sd_factor", "noise_sd"):
             setattr(arr[k], f, float(d.get(f, 0.0)))
         arr[k].exp_transform = int(d.get("exp_transform", 0))
+        for f in ("sexes", "mating", "monogamy"):
+            setattr(arr[k], f, int(d.get(f, 0)))
+        for f in ("pref_optimum", "pref_width"):
+            setattr(arr[k], f, float(d.get(f, 0.0)))
+        if d.get("linkage") is not None:
+            lk = np.ascontiguousarray(d["linkage"], dtype=np.float64)
+            keep.append(lk)
+            arr[k].linkage = _p(lk, C.c_double)
         eff = d.get("effects")
         if eff is not None:
             e = np.ascontiguousarray(eff, dtype=np.int8)
@@ -445,6 +463,14 @@ class Population:
         out = np.zeros(max(n, 1), dtype=np.float32)
         got = C.c_uint32()
         check(self.lib.spegg_read_phenotypes_f(self._h, rep, patch, _p(out, C.c_float), out.size, C.byref(got)))
+        return out[: got.value]
+
+    def sexes(self, rep=0, patch=0):
+        """Separate sexes: 0 female, 1 male, per individual (all 0 without sexes)."""
+        n = self._n_of(rep, patch)
+        out = np.zeros(max(n, 1), dtype=np.uint8)
+        got = C.c_uint32()
+        check(self.lib.spegg_read_sexes(self._h, rep, patch, _p(out, C.c_uint8), out.size, C.byref(got)))
         return out[: got.value]
 
     def ages(self, rep=0, species=0):
