@@ -44,6 +44,32 @@ def make_ecology(eco):
     return e
 
 
+class OraclePhysiology(C.Structure):
+    _fields_ = [
+        ("alpha", C.c_double), ("gamma", C.c_double), ("delta", C.c_double),
+        ("attack", C.c_double), ("handling", C.c_double),
+        ("K", C.c_double * 2), ("growth", C.c_double * 2), ("growth_sd", C.c_double * 2), ("R0", C.c_double * 2),
+        ("steepness", C.c_double), ("switch_frac", C.c_double), ("w_max", C.c_double),
+        ("kappa", C.c_double), ("qJ", C.c_double), ("qA", C.c_double),
+        ("beta1", C.c_double), ("beta2", C.c_double), ("beta_s", C.c_double),
+        ("maturity", C.c_double),
+        ("v_f", C.c_double), ("v_m", C.c_double),
+        ("kappa1", C.c_double), ("kappa2", C.c_double), ("kappa3", C.c_double),
+        ("breed_every", C.c_uint32),
+    ]
+
+
+def make_physiology(phy):
+    f = OraclePhysiology()
+    for k, v in phy.items():
+        if k in ("K", "growth", "growth_sd", "R0"):
+            arr = getattr(f, k)
+            arr[0], arr[1] = float(v[0]), float(v[1])
+        else:
+            setattr(f, k, v)
+    return f
+
+
 class OracleParams(C.Structure):
     _fields_ = [
         ("seed", C.c_uint64),
@@ -76,6 +102,7 @@ class OracleParams(C.Structure):
         ("pref_optimum", C.c_double),
         ("pref_width", C.c_double),
         ("monogamy", C.c_uint32),
+        ("physiology", C.POINTER(OraclePhysiology)),
     ]
 
 
@@ -95,10 +122,14 @@ class OracleStats(C.Structure):
         ("updates", C.c_uint64),
         ("sum_zf", C.c_double),
         ("sum_zf2", C.c_double),
+        ("resource", C.c_double * 2),
+        ("eggs", C.c_double),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {name: getattr(self, name) for name, _ in self._fields_}
+        out["resource"] = (self.resource[0], self.resource[1])
+        return out
 
 
 _lib = None
@@ -185,6 +216,8 @@ def load():
     lib.oracle_normals.restype = None
     lib.oracle_get_sexes.argtypes = [vp, u32, C.POINTER(C.c_uint8), C.c_size_t]
     lib.oracle_get_sexes.restype = C.c_int
+    lib.oracle_get_body.argtypes = [vp, u32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_size_t]
+    lib.oracle_get_body.restype = C.c_int
     _lib = lib
     return lib
 
@@ -268,7 +301,7 @@ class OraclePop:
                  mu=0.0, r=0.5, theta=0.0, omega=0.0, K=0.0, fecundity=0.0, effects=None,
                  n_patches=1, migration=0.0, ecology=None, dispersal=0, home_return=0.0, genetics=0,
                  allele_mean=0.0, allele_sd=0.0, mut_sd_factor=0.0, noise_sd=0.0, exp_transform=0,
-                 linkage=None, sexes=0, mating=0, pref_optimum=0.0, pref_width=0.0, monogamy=0):
+                 linkage=None, sexes=0, mating=0, pref_optimum=0.0, pref_width=0.0, monogamy=0, physiology=None):
         lib = load()
         self.L = int(n_loci)
         self.W = (self.L + 31) // 32
@@ -280,6 +313,7 @@ class OraclePop:
             assert self._effects.shape == (self.L,)
             eff_ptr = _p(self._effects, C.c_int8)
         self._eco = make_ecology(ecology) if ecology is not None else None
+        self._phy = make_physiology(physiology) if physiology is not None else None
         self._linkage = None
         link_ptr = None
         if linkage is not None:
@@ -293,7 +327,8 @@ class OraclePop:
                            ecology=C.pointer(self._eco) if self._eco is not None else None, genetics=genetics,
                            allele_mean=allele_mean, allele_sd=allele_sd, mut_sd_factor=mut_sd_factor,
                            noise_sd=noise_sd, exp_transform=exp_transform, linkage=link_ptr, sexes=sexes,
-                           mating=mating, pref_optimum=pref_optimum, pref_width=pref_width, monogamy=monogamy)
+                           mating=mating, pref_optimum=pref_optimum, pref_width=pref_width, monogamy=monogamy,
+                           physiology=C.pointer(self._phy) if self._phy is not None else None)
         self.continuous = int(genetics) == 1
         self.capacity = prm.capacity
         self._h = lib.oracle_create(C.byref(prm))
@@ -343,7 +378,8 @@ class OraclePop:
     def total_stats(self):
         """The census summed over demes (generation: shared; extinct: all)."""
         per = [self.stats(k) for k in range(self.n_demes)]
-        out = {k: sum(p[k] for p in per) for k in per[0]}
+        out = {k: sum(p[k] for p in per) for k in per[0] if k != "resource"}
+        out["resource"] = per[0]["resource"]  # one patch carries resources (physiology regime)
         out["generation"] = per[0]["generation"]
         out["extinct"] = int(all(p["extinct"] for p in per))
         return out
@@ -374,6 +410,14 @@ class OraclePop:
         out = np.zeros(max(n, 1), dtype=np.int32)
         assert self._lib.oracle_get_phenotypes(self._h, d, _p(out, C.c_int32), out.size) == 0
         return out[:n]
+
+    def body(self, patch=0):
+        """Physiology regime: (X, Y) float64 arrays, irreversible and reversible mass."""
+        n = self.n_of(patch)
+        X = np.zeros(max(n, 1), dtype=np.float64)
+        Y = np.zeros(max(n, 1), dtype=np.float64)
+        assert self._lib.oracle_get_body(self._h, int(patch), _p(X, C.c_double), _p(Y, C.c_double), X.size) == 0
+        return X[:n], Y[:n]
 
     def sexes(self, patch=0, species=0):
         """Separate sexes: 0 female, 1 male, per individual."""

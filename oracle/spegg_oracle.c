@@ -56,7 +56,8 @@ enum {
     ST_NOISE = 15, /* continuous alleles: residual phenotypic noise */
     ST_SEX = 16,    /* separate sexes: sex of a newborn (block 0) or founder (block 1) */
     ST_FEMALE = 17, /* separate sexes: proposals for a mother */
-    ST_MATE = 18    /* proposals for a father (sexes, mate choice or monogamy) */
+    ST_MATE = 18,   /* proposals for a father (sexes, mate choice or monogamy) */
+    ST_RESOURCE = 19 /* physiology regime: resource growth noise (index 0, block j) */
 };
 
 enum { MATING_RANDOM = 0, MATING_PREFERENCE = 1, MATING_ASSORTATIVE = 2 };
@@ -64,7 +65,7 @@ enum { MATING_RANDOM = 0, MATING_PREFERENCE = 1, MATING_ASSORTATIVE = 2 };
 
 enum { GENETICS_BIALLELIC = 0, GENETICS_CONTINUOUS = 1 };
 
-enum { REGIME_WF = 0, REGIME_POISSON_BH = 1, REGIME_CONSUMER_RESOURCE = 2 };
+enum { REGIME_WF = 0, REGIME_POISSON_BH = 1, REGIME_CONSUMER_RESOURCE = 2, REGIME_PHYSIOLOGY = 3 };
 enum { MODE_RAW = 0, MODE_ZERO = 1, MODE_SKIP = 2, MODE_LAZY = 3, MODE_MAP = 4 };
 
 /* ------------------------------------------------------------------ */
@@ -255,6 +256,22 @@ typedef struct {
     double surv_resource[4], surv_consumer[4]; /* survival by age class 0, 1, 2, 3 and older */
 } oracle_ecology;
 
+/* The physiologically structured consumer of Supplementary S2 (resource
+ * consumption, somatic growth, reproduction, mortality), with two dynamic
+ * resources.  Symbols as in S2. */
+typedef struct oracle_physiology {
+    double alpha, gamma, delta;   /* intake alpha W^gamma at carrying capacity; metabolism delta W */
+    double attack, handling;      /* h(R, K) = a (R/K) / (1 + a T_H R/K) */
+    double K[2], growth[2], growth_sd[2], R0[2]; /* resources: capacity, growth rate mean and sd, initial */
+    double steepness, switch_frac, w_max; /* diet share of resource 1: logistic in l[W] - u l[W_max] */
+    double kappa, qJ, qA;         /* allocation to irreversible mass; reserve ratios (newborn, adult) */
+    double beta1, beta2, beta_s;  /* survival: size logistic and starvation */
+    double maturity;              /* sigma: mature when X >= sigma */
+    double v_f, v_m;              /* reproductive skew of mothers (eggs) and fathers (X) */
+    double kappa1, kappa2, kappa3; /* recruits Phi = kappa1 F / (1 + (F/kappa2)^kappa3) */
+    uint32_t breed_every;         /* T: reproduction every T time steps */
+} oracle_physiology;
+
 typedef struct {
     uint64_t seed;
     uint32_t replicate_id;
@@ -285,6 +302,7 @@ typedef struct {
     double pref_optimum;   /* shared preference: males near this phenotype are preferred */
     double pref_width;     /* width of the preference or of the assortment, > 0 */
     uint32_t monogamy;     /* 1: all offspring of a mother in a generation share one father */
+    const struct oracle_physiology *physiology; /* REGIME_PHYSIOLOGY only */
 } oracle_params;
 
 typedef struct {
@@ -294,6 +312,8 @@ typedef struct {
     uint64_t near_ties, truncated, sum_threshold;
     uint64_t updates; /* cumulative genotype-locus updates, sum of N_t L */
     double sum_zf, sum_zf2; /* continuous alleles: sums of the expressed phenotypes (serial order) */
+    double resource[2];     /* physiology regime: resource densities R_1, R_2 */
+    double eggs;            /* physiology regime: eggs F laid at the last step (0 off breeding steps) */
 } oracle_stats;
 
 /* One patch of one species of a replicate (a deme): its own individuals
@@ -307,6 +327,7 @@ typedef struct {
     int32_t *z;
     float *cg;       /* continuous alleles: cg[i][h][l] */
     float *zf;       /* continuous alleles: expressed phenotype */
+    double *X, *Y, *G; /* physiology regime: irreversible, reversible and gonadal mass */
     uint8_t *age;    /* consumer-resource regime: age of each individual */
     uint8_t *sex;    /* separate sexes: 0 female, 1 male */
     uint32_t n_surv_f; /* separate sexes: surviving females of the last generation */
@@ -336,6 +357,9 @@ typedef struct {
     oracle_deme *deme;
     /* consumer-resource regime */
     oracle_ecology eco;
+    /* physiology regime */
+    oracle_physiology phy;
+    double R[2];
     uint64_t *enc;  /* encounters per consumer, Poisson(encounters) */
     int enc_len;
     uint64_t *capT; /* capture threshold by |z_c - z_r| */
@@ -432,6 +456,96 @@ static uint8_t sex_of(rng_ctx *g, uint32_t index, uint32_t gen, uint32_t sub)
     return (uint8_t)(rng_word(g, index, ST_SEX, gen, sub, 0) & 1u);
 }
 
+/* Physiology regime (Supplementary S2).  A founder (or a written
+ * individual) is born at its own neonate mass: X = Omega (its expressed
+ * phenotype), Y = q_J X, no gonads. */
+static void founders_body(const oracle_pop *P, oracle_deme *D, uint32_t n)
+{
+    uint32_t i;
+    free(D->X);
+    free(D->Y);
+    free(D->G);
+    D->X = D->Y = D->G = NULL;
+    if (P->prm.regime != REGIME_PHYSIOLOGY)
+        return;
+    D->X = (double *)malloc(sizeof(double) * (n ? n : 1));
+    D->Y = (double *)malloc(sizeof(double) * (n ? n : 1));
+    D->G = (double *)calloc(n ? n : 1, sizeof(double));
+    for (i = 0; i < n; ++i) {
+        D->X[i] = (double)D->zf[i];
+        D->Y[i] = P->phy.qJ * D->X[i];
+    }
+}
+
+/* S2, Resource Consumption: the proportion h(R, K) by which scarcity of a
+ * resource cuts consumption, a Holling type-II response in R/K. */
+static double resource_h(const oracle_physiology *F, double R, double K)
+{
+    double x = F->attack * R / K;
+    return x / (1.0 + F->handling * x);
+}
+
+/* S2, Resource Consumption and Somatic Growth, for adult i in one time
+ * step: intake alpha W^gamma split between the resources by the diet share
+ * pi(W, 1) = 1 / (1 + exp(-p (l[W] - u l[W_max]))), l[W] = W^(1/3) (body
+ * length from mass), each scaled by its h; net production dW = intake -
+ * delta W.  A surplus goes to irreversible mass in the share min(1,
+ * kappa Y/X), the rest to reserves; a deficit is drawn from the reserves
+ * (irreversible mass is not starved away).  At a breeding step a mature
+ * individual (X >= sigma) sets aside the reserves above q_A X as gonads.
+ * Adds its consumption to e[0], e[1]. */
+static void grow(const oracle_pop *P, oracle_deme *D, uint32_t i, const double h[2], int breeding, double e[2])
+{
+    const oracle_physiology *F = &P->phy;
+    double X = D->X[i], Y = D->Y[i], W = X + Y, G = 0.0;
+    double pi1 = 1.0 / (1.0 + exp(-F->steepness * (cbrt(W) - F->switch_frac * cbrt(F->w_max))));
+    double intake = F->alpha * pow(W, F->gamma);
+    double e1 = h[0] * pi1 * intake, e2 = h[1] * (1.0 - pi1) * intake;
+    double dW = e1 + e2 - F->delta * W;
+    e[0] += e1;
+    e[1] += e2;
+    if (dW > 0.0) {
+        double f = F->kappa * Y / X;
+        if (f > 1.0)
+            f = 1.0;
+        X += f * dW;
+        Y += (1.0 - f) * dW;
+    } else {
+        Y += dW;
+    }
+    if (breeding && X >= F->maturity) {
+        G = Y - F->qA * X;
+        if (G < 0.0)
+            G = 0.0;
+        Y -= G;
+    }
+    D->X[i] = X;
+    D->Y[i] = Y;
+    D->G[i] = G;
+}
+
+/* S2, Mortality: survival from one time step to the next, starvation risk
+ * times the size logistic, (1 - exp(-beta_s Y/X)) / (1 + exp(-beta_2 (X -
+ * beta_1))); no reserves left: death. */
+static double phys_survival(const oracle_physiology *F, double X, double Y)
+{
+    if (!(Y > 0.0))
+        return 0.0;
+    return (1.0 - exp(-F->beta_s * Y / X)) / (1.0 + exp(-F->beta2 * (X - F->beta1)));
+}
+
+static int breeding_step(const oracle_pop *P, uint32_t t)
+{
+    return P->prm.regime == REGIME_PHYSIOLOGY && t % P->phy.breed_every == P->phy.breed_every - 1u;
+}
+
+/* S2, Reproduction: the eggs of female i, G_i / (Omega_i + q_J Omega_i). */
+static double eggs_of(const oracle_pop *P, const oracle_deme *D, uint32_t i)
+{
+    double om = (double)D->zf[i];
+    return D->G[i] / (om + P->phy.qJ * om);
+}
+
 static void founders_sex(const oracle_pop *P, oracle_deme *D, uint32_t n, uint32_t gen)
 {
     uint32_t i;
@@ -457,6 +571,10 @@ static void free_deme(oracle_deme *D)
     D->zf = NULL;
     free(D->sex);
     D->sex = NULL;
+    free(D->X);
+    free(D->Y);
+    free(D->G);
+    D->X = D->Y = D->G = NULL;
     free(D->age);
     free(D->won);
     free(D->intake);
@@ -504,6 +622,8 @@ static void census(const oracle_pop *P, oracle_deme *D)
     D->stats.sum_z2 = 0;
     D->stats.sum_zf = 0.0;
     D->stats.sum_zf2 = 0.0;
+    D->stats.resource[0] = P->prm.regime == REGIME_PHYSIOLOGY ? P->R[0] : 0.0;
+    D->stats.resource[1] = P->prm.regime == REGIME_PHYSIOLOGY ? P->R[1] : 0.0;
     if (P->prm.genetics == GENETICS_CONTINUOUS) {
         for (i = 0; i < D->n; ++i) {
             D->stats.sum_zf += (double)D->zf[i];
@@ -566,7 +686,7 @@ oracle_pop *oracle_create(const oracle_params *prm)
     if (L == 0 || prm->n0 > prm->capacity || !(prm->mu >= 0.0 && prm->mu < 1.0) || !(prm->r >= 0.0 && prm->r <= 0.5) ||
         prm->n_patches < 1 || prm->n_patches > 1024 || !(prm->migration >= 0.0 && prm->migration <= 1.0) ||
         prm->dispersal > 1 || !(prm->home_return >= 0.0 && prm->home_return <= 1.0) ||
-        (prm->n_patches > 1 && prm->regime != REGIME_WF) || prm->regime > REGIME_CONSUMER_RESOURCE ||
+        (prm->n_patches > 1 && prm->regime != REGIME_WF) || prm->regime > REGIME_PHYSIOLOGY ||
         (cr && !ecology_ok(prm->ecology)) || prm->genetics > GENETICS_CONTINUOUS ||
         (prm->genetics == GENETICS_CONTINUOUS &&
          (cr || prm->effects || !(prm->allele_sd >= 0.0) || !(prm->mut_sd_factor >= 0.0) || !(prm->noise_sd >= 0.0) ||
@@ -580,6 +700,25 @@ oracle_pop *oracle_create(const oracle_params *prm)
         for (l = 0; l + 1 < L; ++l)
             if (!(prm->linkage[l] >= 0.0 && prm->linkage[l] <= 0.5))
                 return NULL;
+    if (prm->regime == REGIME_PHYSIOLOGY) {
+        /* the S2 consumer: continuous alleles expressed as exp(z) (neonate
+         * mass), one patch, separate sexes, mates drawn by S2's weights */
+        const oracle_physiology *F = prm->physiology;
+        int j;
+        if (!F || prm->genetics != GENETICS_CONTINUOUS || !prm->exp_transform || prm->n_patches != 1 ||
+            prm->mating || prm->monogamy || !(F->alpha > 0.0) || !(F->gamma > 0.0 && F->gamma <= 1.0) ||
+            !(F->delta >= 0.0) || !(F->attack >= 0.0) || !(F->handling >= 0.0) || !(F->w_max > 0.0) ||
+            !(F->kappa >= 0.0) || !(F->qJ > 0.0) || !(F->qA >= 0.0) || !(F->maturity > 0.0) ||
+            !(F->v_f >= 0.0) || !(F->v_m >= 0.0) || !(F->kappa1 >= 0.0) || !(F->kappa2 > 0.0) ||
+            !(F->kappa3 >= 0.0) || F->breed_every < 1 || !isfinite(F->steepness) || !isfinite(F->switch_frac) ||
+            !isfinite(F->beta1) || !isfinite(F->beta2) || !(F->beta_s >= 0.0))
+            return NULL;
+        for (j = 0; j < 2; ++j)
+            if (!(F->K[j] > 0.0) || !(F->R0[j] >= 0.0) || !isfinite(F->growth[j]) || !(F->growth_sd[j] >= 0.0))
+                return NULL;
+    } else if (prm->physiology) {
+        return NULL;
+    }
     P = (oracle_pop *)calloc(1, sizeof *P);
     if (!P)
         return NULL;
@@ -590,6 +729,13 @@ oracle_pop *oracle_create(const oracle_params *prm)
         P->effects[l] = prm->effects ? prm->effects[l] : 1;
     P->prm.effects = P->effects;
     P->prm.ecology = NULL;
+    if (prm->regime == REGIME_PHYSIOLOGY) {
+        P->phy = *prm->physiology;
+        P->prm.sexes = 1; /* S2: a sexually reproducing population */
+        P->R[0] = P->phy.R0[0];
+        P->R[1] = P->phy.R0[1];
+    }
+    P->prm.physiology = NULL;
     P->mode = oracle_recomb_mode(prm->r);
     P->prm.linkage = NULL;
     if (prm->linkage) {
@@ -662,6 +808,7 @@ oracle_pop *oracle_create(const oracle_params *prm)
             D->z[i] = phenotype(P, allele_row(P, D->genome, i, 0), allele_row(P, D->genome, i, 1));
         }
         founders_sex(P, D, n0, 0);
+        founders_body(P, D, n0);
         census(P, D);
         D->stats.n_parents = 0;
         D->stats.extinct = n0 == 0;
@@ -934,6 +1081,8 @@ int oracle_small_binomial_thresholds(uint32_t n, double q, uint64_t *T)
  * (consumer-resource regime). */
 static double survival_probability(const oracle_pop *P, const oracle_deme *D, uint32_t i, double s)
 {
+    if (P->prm.regime == REGIME_PHYSIOLOGY)
+        return phys_survival(&P->phy, D->X[i], D->Y[i]);
     if (P->prm.genetics == GENETICS_CONTINUOUS)
         return viability_f(P, D->zf[i]) * s;
     if (P->prm.regime == REGIME_CONSUMER_RESOURCE) {
@@ -951,6 +1100,25 @@ static void select_and_count(oracle_pop *P, oracle_deme *D, uint32_t t)
     double s = density_factor(P, n);
     int cr = P->prm.regime == REGIME_CONSUMER_RESOURCE;
     uint8_t *alive = (uint8_t *)calloc(n ? n : 1, 1);
+    if (P->prm.regime == REGIME_PHYSIOLOGY) {
+        /* S2: every adult eats and grows on this step's resources, then the
+         * resources take their growth (Beverton-Holt-like, the per-capita
+         * rate r_j + e_{r,j} n_j of this step) minus the consumption. */
+        const oracle_physiology *F = &P->phy;
+        double h[2], e[2] = {0.0, 0.0};
+        int j, breeding = breeding_step(P, t);
+        h[0] = resource_h(F, P->R[0], F->K[0]);
+        h[1] = resource_h(F, P->R[1], F->K[1]);
+        for (i = 0; i < n; ++i)
+            grow(P, D, i, h, breeding, e);
+        for (j = 0; j < 2; ++j) {
+            double r = F->growth[j], Rn;
+            if (F->growth_sd[j] > 0.0)
+                r += F->growth_sd[j] * normal_deviate(&D->rng, 0, ST_RESOURCE, t, (uint32_t)j);
+            Rn = r * P->R[j] / (1.0 + P->R[j] / F->K[j]) - e[j];
+            P->R[j] = Rn > 0.0 ? Rn : 0.0;
+        }
+    }
     /* Survival: Bernoulli(p) per adult; a captured resource dies. */
     for (i = 0; i < n; ++i) {
         double p;
@@ -1034,6 +1202,38 @@ static void neonates(oracle_pop *P, uint32_t k)
         /* separate sexes: a female and a male must survive */
         if (P->prm.sexes && (D->n_surv_f == 0 || D->n_surv_f == D->n_survivors))
             nn = 0;
+    } else if (P->prm.regime == REGIME_PHYSIOLOGY) {
+        /* S2: survivors stay; at a breeding step the mature surviving
+         * females lay F = sum of their eggs, and Phi = kappa1 F / (1 +
+         * (F/kappa2)^kappa3) recruits (rounded down) join, up to the
+         * capacity, when a mature male survived too */
+        const oracle_physiology *F = &P->phy;
+        uint32_t room, nf = 0, nm = 0;
+        double eggs = 0.0, phi;
+        uint64_t want = 0;
+        D->n_carry = D->n_survivors;
+        room = D->cap - D->n_carry;
+        D->stats.eggs = 0.0;
+        if (breeding_step(P, P->generation)) { /* the step being taken */
+            for (i = 0; i < D->n_survivors; ++i) {
+                uint32_t a = D->survivors[i];
+                if (D->X[a] >= F->maturity) {
+                    if (D->sex[a] == 0) {
+                        eggs += eggs_of(P, D, a);
+                        ++nf;
+                    } else {
+                        ++nm;
+                    }
+                }
+            }
+            D->stats.eggs = eggs;
+            if (nf > 0 && nm > 0) {
+                phi = F->kappa1 * eggs / (1.0 + pow(eggs / F->kappa2, F->kappa3));
+                want = phi >= 4294967295.0 ? 4294967295ull : (uint64_t)floor(phi);
+            }
+        }
+        nn = want > room ? room : (uint32_t)want;
+        D->stats.truncated += want - nn;
     } else {
         uint64_t ktot = 0;
         uint32_t slot = 0, room;
@@ -1168,16 +1368,65 @@ static uint32_t partner(const oracle_pop *P, oracle_deme *D, uint32_t stream, ui
     return D->survivors[r]; /* unreachable: the wanted sex survived */
 }
 
+/* S2, Reproduction: the mother of an egg among the mature females with
+ * probability proportional to her eggs^v_f, the father among the mature
+ * males proportional to X^v_m, by proposals: survivor S[idx(words 0, 1)] of
+ * block p of `stream` for index key, accepted when it is of the wanted sex
+ * and mature and word 2 lies below floor((w / w_max)^v 2^32), w_max the
+ * largest weight of the generation's eligible.  After PARTNER_PROPOSALS
+ * rejections: the first eligible survivor at or after the last proposal. */
+static uint32_t phys_partner(const oracle_pop *P, oracle_deme *D, uint32_t stream, uint32_t key, uint32_t t, int male,
+                             double wmax)
+{
+    const oracle_physiology *F = &P->phy;
+    double v = male ? F->v_m : F->v_f;
+    uint32_t p, r = 0, c, ns = D->n_survivors;
+    for (p = 0; p < PARTNER_PROPOSALS; ++p) {
+        double a;
+        r = uniform_index(rng_word(&D->rng, key, stream, t, p, 0), rng_word(&D->rng, key, stream, t, p, 1), ns);
+        c = D->survivors[r];
+        if (D->sex[c] != (uint8_t)male || !(D->X[c] >= F->maturity))
+            continue;
+        a = (male ? D->X[c] : eggs_of(P, D, c)) / wmax;
+        if (v != 1.0)
+            a = pow(a, v);
+        if ((uint64_t)rng_word(&D->rng, key, stream, t, p, 2) < oracle_prob_threshold(a))
+            return c;
+    }
+    for (p = 0; p < ns; ++p) {
+        c = D->survivors[(r + p) % ns];
+        if (D->sex[c] == (uint8_t)male && D->X[c] >= F->maturity)
+            return c;
+    }
+    return D->survivors[r]; /* unreachable: an eligible parent survived */
+}
+
 /* The next census of deme k into *next, *znext, *anext: carried survivors
  * first (consumer-resource regime: genomes and phenotypes copied, one age
  * class older), then the newborns -- A (parents) + B + C. */
 static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int32_t **znext, uint8_t **anext,
-                      float **cnext, float **zfnext, uint8_t **snext)
+                      float **cnext, float **zfnext, uint8_t **snext, double **xnext, double **ynext)
 {
     oracle_deme *D = &P->deme[k];
     uint32_t nc = D->n_carry, nn = D->n_next, j, L = P->L;
     uint32_t total = nc + nn;
     int cont = P->prm.genetics == GENETICS_CONTINUOUS;
+    int phys = P->prm.regime == REGIME_PHYSIOLOGY;
+    double emax = 0.0, xmax = 0.0;
+    *xnext = *ynext = NULL;
+    if (phys) {
+        *xnext = (double *)malloc(sizeof(double) * (total ? total : 1));
+        *ynext = (double *)malloc(sizeof(double) * (total ? total : 1));
+        for (j = 0; j < D->n_survivors; ++j) {
+            uint32_t a = D->survivors[j];
+            if (!(D->X[a] >= P->phy.maturity))
+                continue;
+            if (D->sex[a] == 0 && eggs_of(P, D, a) > emax)
+                emax = eggs_of(P, D, a);
+            if (D->sex[a] == 1 && D->X[a] > xmax)
+                xmax = D->X[a];
+        }
+    }
     uint8_t *scratch = (uint8_t *)malloc(3u * L);
     *cnext = NULL;
     *zfnext = NULL;
@@ -1200,6 +1449,15 @@ static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int
         memcpy(allele_row(P, *next, j, 0), allele_row(P, D->genome, i, 0), 2u * L);
         (*znext)[j] = D->z[i];
         (*anext)[j] = (uint8_t)(D->age[i] < 3u ? D->age[i] + 1u : 3u); /* class 3: three and older */
+        (*snext)[j] = D->sex[i];
+        if (cont) {
+            memcpy(allele_row_f(P, *cnext, j, 0), allele_row_f(P, D->cg, i, 0), sizeof(float) * 2u * L);
+            (*zfnext)[j] = D->zf[i];
+        }
+        if (phys) {
+            (*xnext)[j] = D->X[i];
+            (*ynext)[j] = D->Y[i];
+        }
     }
     for (j = 0; j < nn; ++j) {
         uint32_t w0 = seq_word(&D->rng, j, ST_PARENT, t, 0);
@@ -1209,12 +1467,20 @@ static void offspring(oracle_pop *P, uint32_t k, uint32_t t, uint8_t **next, int
         uint32_t sp = P->prm.regime == REGIME_WF ? source_patch(P, k, j, t) : k;
         oracle_deme *S = &P->deme[sp];
         uint32_t mom, dad, pos = nc + j;
-        if (P->prm.regime == REGIME_WF)
+        if (phys) {
+            mom = phys_partner(P, S, ST_FEMALE, j, t, 0, emax);
+            dad = phys_partner(P, S, ST_MATE, j, t, 1, xmax);
+            /* the egg's irreversible mass is the mother's neonate mass, its
+             * reserves the newborn maximum q_J of it */
+            (*xnext)[pos] = (double)S->zf[mom];
+            (*ynext)[pos] = P->phy.qJ * (double)S->zf[mom];
+        } else if (P->prm.regime == REGIME_WF)
             mom = P->prm.sexes ? partner(P, S, ST_FEMALE, j, t, 0, 0, 0)
                                : S->survivors[uniform_index(w0, w1, S->n_survivors)];
         else
             mom = D->owner[j];
-        if (!P->prm.sexes && P->prm.mating == MATING_RANDOM && !P->prm.monogamy)
+        if (phys) {
+        } else if (!P->prm.sexes && P->prm.mating == MATING_RANDOM && !P->prm.monogamy)
             dad = S->survivors[uniform_index(w2, w3, S->n_survivors)];
         else /* monogamy: the father is the mother's one mate of the generation */
             dad = partner(P, S, ST_MATE, P->prm.monogamy ? mom : j, t, P->prm.sexes ? 1 : -1,
@@ -1255,6 +1521,8 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
     float **cnext = (float **)calloc(nd, sizeof(float *));
     float **zfnext = (float **)calloc(nd, sizeof(float *));
     uint8_t **snext = (uint8_t **)calloc(nd, sizeof(uint8_t *));
+    double **xnext = (double **)calloc(nd, sizeof(double *));
+    double **ynext = (double **)calloc(nd, sizeof(double *));
     for (it = 0; it < n_generations; ++it) {
         uint32_t t = P->generation;
         if (P->prm.regime == REGIME_CONSUMER_RESOURCE)
@@ -1264,7 +1532,7 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
         for (k = 0; k < nd; ++k)
             neonates(P, k);
         for (k = 0; k < nd; ++k)
-            offspring(P, k, t, &next[k], &znext[k], &anext[k], &cnext[k], &zfnext[k], &snext[k]);
+            offspring(P, k, t, &next[k], &znext[k], &anext[k], &cnext[k], &zfnext[k], &snext[k], &xnext[k], &ynext[k]);
         P->generation = t + 1;
         for (k = 0; k < nd; ++k) {
             oracle_deme *D = &P->deme[k];
@@ -1280,6 +1548,14 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
             D->zf = zfnext[k];
             free(D->sex);
             D->sex = snext[k];
+            if (P->prm.regime == REGIME_PHYSIOLOGY) {
+                free(D->X);
+                free(D->Y);
+                free(D->G);
+                D->X = xnext[k];
+                D->Y = ynext[k];
+                D->G = (double *)calloc(D->n_carry + D->n_next ? D->n_carry + D->n_next : 1, sizeof(double));
+            }
             D->stats.n_parents = D->n;
             D->stats.n_survivors = D->n_survivors;
             D->n = D->n_carry + D->n_next;
@@ -1295,6 +1571,8 @@ int oracle_step(oracle_pop *P, uint32_t n_generations)
     free(cnext);
     free(zfnext);
     free(snext);
+    free(xnext);
+    free(ynext);
     return 0;
 }
 
@@ -1365,6 +1643,7 @@ int oracle_set_genomes(oracle_pop *P, uint32_t deme, const uint32_t *words, uint
     D->n_next = 0;
     D->n_carry = 0;
     founders_sex(P, D, n, generation);
+    founders_body(P, D, n);
     memset(&D->stats, 0, sizeof D->stats);
     D->stats.extinct = n == 0;
     census(P, D);
@@ -1377,6 +1656,18 @@ int oracle_get_phenotypes(const oracle_pop *P, uint32_t deme, int32_t *z, size_t
     if (!D || n < D->n)
         return -1;
     memcpy(z, D->z, sizeof(int32_t) * D->n);
+    return 0;
+}
+
+/* Physiology regime: irreversible and reversible mass of each individual
+ * of the current census. */
+int oracle_get_body(const oracle_pop *P, uint32_t deme, double *X, double *Y, size_t n)
+{
+    oracle_deme *D = deme_of(P, deme);
+    if (!D || P->prm.regime != REGIME_PHYSIOLOGY || n < D->n)
+        return -1;
+    memcpy(X, D->X, sizeof(double) * D->n);
+    memcpy(Y, D->Y, sizeof(double) * D->n);
     return 0;
 }
 
@@ -1490,6 +1781,7 @@ int oracle_set_alleles(oracle_pop *P, uint32_t deme, const float *values, uint32
     D->n_next = 0;
     D->n_carry = 0;
     founders_sex(P, D, n, generation);
+    founders_body(P, D, n);
     memset(&D->stats, 0, sizeof D->stats);
     D->stats.extinct = n == 0;
     census(P, D);

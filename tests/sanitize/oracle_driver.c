@@ -13,6 +13,13 @@ typedef struct {
     double surv_resource[4], surv_consumer[4];
 } oracle_ecology;
 typedef struct {
+    double alpha, gamma, delta, attack, handling;
+    double K[2], growth[2], growth_sd[2], R0[2];
+    double steepness, switch_frac, w_max, kappa, qJ, qA, beta1, beta2, beta_s, maturity, v_f, v_m;
+    double kappa1, kappa2, kappa3;
+    uint32_t breed_every;
+} oracle_physiology;
+typedef struct {
     uint64_t seed;
     uint32_t replicate_id, regime, n0, capacity, n_loci, n_patches;
     double mu, r, theta, omega, K, fecundity, migration;
@@ -27,6 +34,7 @@ typedef struct {
     uint32_t sexes, mating;
     double pref_optimum, pref_width;
     uint32_t monogamy;
+    const oracle_physiology *physiology;
 } oracle_params;
 
 oracle_pop *oracle_create(const oracle_params *prm);
@@ -84,7 +92,10 @@ int main(void)
     oracle_ecology eco = {3000, 6000, 4, 30000, 0.5, 4.0, 20.0, 0.5, 0.55, 25000.0,
                           {0.5, 0.8, 0.8, 0.0}, {0.6, 0.8, 0.8, 0.0}};
     oracle_params base = {1, 3, 0, 400, 400, 64, 1, 1e-3, 0.5, 0.0, 8.0, 0.0, 0.0, 0.0, 0, 0.0, NULL, NULL,
-                          0, 0.0, 0.0, 0.0, 0.0, 0, NULL, 0, 0, 0.0, 0.0, 0};
+                          0, 0.0, 0.0, 0.0, 0.0, 0, NULL, 0, 0, 0.0, 0.0, 0, NULL};
+    oracle_physiology phy = {0.3, 0.75, 0.1, 2.0, 1.0, {3000.0, 3000.0}, {2.0, 2.0}, {0.1, 0.1},
+                             {3000.0, 3000.0}, 5.0, 0.5, 8.0, 1.0, 0.2, 0.4, 0.05, 20.0, 20.0, 1.0, 1.0, 1.0,
+                             0.5, 1000.0, 1.0, 2};
     oracle_params p;
     for (k = 0; k < 300; ++k)
         eff[k] = (int8_t)((int)(k * 7u % 9u) - 4);
@@ -115,6 +126,9 @@ int main(void)
     p.fecundity = 2.2; run(p, 3);
     p = base; p.monogamy = 1; p.mating = 2; p.pref_width = 0.5; run(p, 3);
     p = base; p.sexes = 1; p.n0 = 2; p.capacity = 2; run(p, 4); /* one sex dies out */
+    /* physiologically structured consumer */
+    p = base; p.regime = 3; p.genetics = 1; p.exp_transform = 1; p.allele_mean = -0.15; p.allele_sd = 0.02;
+    p.noise_sd = 0.05; p.n_loci = 16; p.capacity = 4000; p.physiology = &phy; run(p, 12);
     /* continuous alleles: Gaussian mutation, noise, exp transform */
     p = base; p.genetics = 1; p.allele_mean = 0.01; p.allele_sd = 0.005; p.mut_sd_factor = 0.5; p.noise_sd = 0.1;
     p.mu = 0.02; p.r = 0.05; p.n_loci = 70; p.omega = 2.0; p.theta = 1.0; p.exp_transform = 1; run(p, 3);
