@@ -145,7 +145,7 @@ def cpu_baseline(desc, budget_s):
 
     keys = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
             "fecundity", "effects", "n_patches", "migration", "genetics", "allele_mean", "allele_sd",
-            "mut_sd_factor", "noise_sd", "exp_transform")
+            "mut_sd_factor", "noise_sd", "exp_transform", "physiology")
     orc = oracle.OraclePop(**{k: desc[k] for k in keys if k in desc})
     start_updates = orc.stats()["updates"]
     gens = 0
@@ -173,13 +173,15 @@ def main():
     ap.add_argument("--cpu-gens", type=int, default=2, help="batched: generations of the CPU oracle subset")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["scale", "batched", "serve", "ecology", "small", "continuous"],
+    ap.add_argument("--workload", choices=["scale", "batched", "serve", "ecology", "small", "continuous",
+                                           "physiology"],
                     default="batched",
                     help="batched: the 4096-replicate batch (default); scale: one replicate at scale; "
                          "small: the small parity configuration (launch- and latency-bound); "
                          "serve: sweep jobs arriving at random, served with continuous batching; "
                          "ecology: 64 replicates of the two-species consumer-resource form; "
-                         "continuous: one replicate of continuous allelic values (float32) at scale")
+                         "continuous: one replicate of continuous allelic values (float32) at scale; "
+                         "physiology: 100 replicates of the size-structured consumer of two resources")
     ap.add_argument("--reps", type=int, default=4096, help="replicates of the batched workload")
     ap.add_argument("--plain-sample", type=int, default=64,
                     help="batched: replicates timed one at a time for the plain per-replicate loop")
@@ -221,6 +223,8 @@ def main():
         return bench_small(args)
     if args.workload == "continuous":
         return bench_continuous(args)
+    if args.workload == "physiology":
+        return bench_physiology(args)
     return bench_scale(args)
 
 
@@ -734,6 +738,80 @@ def bench_ecology(args):
     print(json.dumps(out), flush=True)
 
 
+def phys_bytes_per_individual(L):
+    """Compulsory HBM bytes of one time step per individual of the
+    physiology regime: survive reads X, Y (doubles), the phenotype (float)
+    and the sex and writes X, Y, the gonads and the fate (47 B); compact
+    reads the fate and writes a survivor index (6 B); a survivor moves to the
+    next census with its genome (2 x 4 L bytes read and written) and its
+    masses, phenotype and sex (2 x 21 B)."""
+    return 47.0 + 6.0 + 2.0 * 8.0 * L + 42.0
+
+
+def bench_physiology(args):
+    """100 replicates of the physiologically structured consumer of
+    Supplementary S2 (50000 founders each, L = 16 continuous loci), all
+    advanced together, one time step per generation."""
+    import torch
+
+    from paper_1603_09255_amd import spegg, workloads
+
+    reps, _ = workloads.physiology_batch(n_reps=100)
+    L = reps[0]["n_loci"]
+    torch.cuda.set_device(0)
+    log(f"bench: creating {len(reps)} physiology replicates")
+    pop = spegg.Population(reps)
+    pop.step(args.warmup)
+    pop.prepare_graphs()
+    torch.cuda.synchronize()
+    st0 = pop.stats()
+    s0 = sum(r["updates"] for r in st0)
+    t0 = time.perf_counter()
+    pop.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = pop.stats()
+    updates = sum(r["updates"] for r in st) - s0
+    inds = updates / L  # individual-steps
+    value = updates / elapsed
+    log(f"bench: {updates} updates ({inds:.4g} individual-steps) in {elapsed:.3f} s ({value:.4g}/s)")
+    pop.set_timing(["survive", "compact", "offspring", "carry"])
+    pop.kernel_times()
+    gens_b = min(args.steps, 50)
+    pop.step(gens_b)
+    kt = pop.kernel_times()
+    pop.set_timing([])
+    per_kind_us = {k: v[0] * 1e3 / gens_b for k, v in kt.items() if v[1]}
+    log("bench: per step: " + ", ".join(f"{k} {v:.0f} us" for k, v in per_kind_us.items()))
+    pop.close()
+    gen_bytes = inds * phys_bytes_per_individual(L)
+    achieved = gen_bytes / elapsed / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "physiologically structured consumer of two resources (Supplementary S2): 100 "
+                               "replicates of 50000 founders (capacity 200000), neonate mass exp(z) from 16 "
+                               "continuous loci, masses in double, breeding every 5 steps",
+                   "replicates": len(reps), "generations_timed": args.steps,
+                   "individual_steps_per_s": inds / elapsed,
+                   "mean_census": inds / args.steps / len(reps),
+                   "replicate0_resources": st[0]["resource"],
+                   "kernel_us_per_step": per_kind_us},
+        "roofline": {"bound": "hbm", "kernel": "whole time step (survive, compact, carry, offspring)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_individual_step": phys_bytes_per_individual(L),
+                     "timing": "wall clock of the timed steps; kernel times from HIP events in a second pass"},
+        "context": {"paper": "the paper reports more than 200x over one CPU core for its size-structured case "
+                             "study on one commodity GPGPU (main text, Fig. 2B), hardware and parameters other "
+                             "than these"},
+    }
+    if not args.no_cpu_baseline:
+        log(f"bench: CPU oracle sample, about {args.cpu_seconds:.0f} s")
+        out["cpu_baseline"] = cpu_baseline(reps[0], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 SERVE_SCALED = dict(reps=(1, 8), gens=(20, 200))  # the served jobs, cut to fit a bench run
 
 
@@ -754,7 +832,8 @@ def bench_serve(args):
     def one(rate, n_jobs):
         jobs = workloads.serve_trace(n_jobs=n_jobs, rate=rate, **shape)
         log(f"bench: serving {n_jobs} jobs at {rate}/s")
-        out = serve.run_trace(jobs, arena, quantum=args.quantum, server=srv)
+        # full-size jobs run for minutes: a line per finished job shows progress
+        out = serve.run_trace(jobs, arena, quantum=args.quantum, server=srv, log=log if args.full_jobs else None)
         return {"rate_per_s": rate, "jobs": n_jobs, "p50_s": out["p50_s"], "p99_s": out["p99_s"],
                 "makespan_s": out["makespan_s"], "updates_per_s": out["updates"] / out["makespan_s"],
                 "max_resident": out["max_resident"], "steps": out["steps"]}

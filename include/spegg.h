@@ -66,7 +66,7 @@
 extern "C" {
 #endif
 
-#define SPEGG_ABI_VERSION 5
+#define SPEGG_ABI_VERSION 6
 #define SPEGG_MAX_LOCI 16384u
 #define SPEGG_MAX_REPLICATE_ID ((1u << 20) - 1u)
 #define SPEGG_MAX_PATCHES 1024u
@@ -83,7 +83,8 @@ typedef enum {
 typedef enum {
     SPEGG_WF = 0,                /* Wright-Fisher: N constant, viability selection, parents uniform over survivors */
     SPEGG_POISSON_BH = 1,        /* Poisson(fecundity) offspring per surviving mother, survival x Beverton-Holt s(N) */
-    SPEGG_CONSUMER_RESOURCE = 2  /* two coevolving species with age classes (spegg_ecology) */
+    SPEGG_CONSUMER_RESOURCE = 2, /* two coevolving species with age classes (spegg_ecology) */
+    SPEGG_PHYSIOLOGY = 3         /* physiologically structured consumer of two resources (spegg_physiology) */
 } spegg_regime;
 
 /* The consumer-resource regime (Supplementary Information S3: a consumer
@@ -120,6 +121,46 @@ typedef struct spegg_ecology {
     double resource_K;        /* > 0 */
     double surv_resource[4], surv_consumer[4]; /* survival by age class 0, 1, 2, 3 and older; each 0..1 */
 } spegg_ecology;
+
+/* The physiologically structured consumer of Supplementary Information S2
+ * (resource consumption, somatic growth, reproduction, mortality), one
+ * generation = one time step.  Each individual has irreversible and
+ * reversible mass X, Y and a sex; its phenotype is its neonate mass Omega =
+ * exp(z) (continuous alleles with exp_transform = 1 are required).  A step:
+ *   1. every individual eats: W = X + Y, intake alpha W^gamma, a share
+ *      pi = 1 / (1 + exp(-steepness (W^(1/3) - switch_frac w_max^(1/3)))) of
+ *      it on resource 1 and 1 - pi on resource 2, each cut by the scarcity
+ *      h = x / (1 + handling x), x = attack R_j / K_j; net production dW =
+ *      intake - delta W; a surplus goes to X in the share min(1, kappa Y/X)
+ *      and to Y otherwise, a deficit comes out of Y; at a breeding step
+ *      (step t with t % breed_every == breed_every - 1) a mature individual
+ *      (X >= maturity) moves its reserves above qA X into gonads G;
+ *   2. it survives with (1 - exp(-beta_s Y/X)) / (1 + exp(-beta2 (X -
+ *      beta1))) (0 without reserves), a SURVIVE word against floor(p 2^32);
+ *   3. the resources take r_j R/(1 + R/K_j) minus what was eaten (at least
+ *      0), r_j = growth[j] + growth_sd[j] n_j, n_j the Box-Muller deviate
+ *      of block j of stream 19 for index 0 in step t;
+ *   4. at a breeding step the mature surviving females lay F = sum of
+ *      G/(Omega + qJ Omega) eggs and floor(kappa1 F / (1 + (F/kappa2)^kappa3))
+ *      recruits join (up to the capacity; none without a mature male);
+ *      mothers are drawn in proportion to eggs^v_f, fathers to X^v_m among
+ *      the mature, by proposals as for mate choice (stream 17 mothers, 18
+ *      fathers; acceptance (w / w_max)^v, w_max the generation's largest);
+ *      a recruit is born with X = its mother's Omega and Y = qJ X;
+ *   5. the survivors stay (first, in order), the recruits follow.
+ * Founders and written individuals start at X = their own Omega, Y = qJ X. */
+typedef struct spegg_physiology {
+    double alpha, gamma, delta;        /* intake alpha W^gamma (0 < gamma <= 1), metabolism delta W */
+    double attack, handling;           /* scarcity h of a resource */
+    double K[2], growth[2], growth_sd[2], R0[2]; /* resources: K > 0, growth rate mean and sd, initial density */
+    double steepness, switch_frac, w_max; /* diet share of resource 1 */
+    double kappa, qJ, qA;              /* allocation to X; reserve ratios of newborns (> 0) and adults */
+    double beta1, beta2, beta_s;       /* survival */
+    double maturity;                   /* mature when X >= maturity (> 0) */
+    double v_f, v_m;                   /* reproductive skew of mothers and fathers */
+    double kappa1, kappa2, kappa3;     /* recruitment, kappa2 > 0 */
+    uint32_t breed_every;              /* >= 1 */
+} spegg_physiology;
 
 typedef struct spegg_pop spegg_pop; /* opaque; owns no device memory */
 
@@ -230,6 +271,7 @@ typedef struct spegg_rep_desc {
     double pref_optimum;   /* SPEGG_PREFERENCE: the preferred phenotype */
     double pref_width;     /* mate choice: width of the acceptance, > 0 */
     uint32_t monogamy;     /* 1: one father for all of a mother's offspring of a generation */
+    const spegg_physiology *physiology; /* SPEGG_PHYSIOLOGY only (copied at create); else NULL */
 } spegg_rep_desc;
 
 /* Census of one deme (a patch, or a species of the consumer-resource
@@ -250,6 +292,8 @@ typedef struct spegg_rep_stats {
     uint64_t updates;       /* cumulative genotype-locus updates: sum over generations of N_t x L */
     double sum_zf;          /* SPEGG_CONTINUOUS: sum of the expressed phenotypes (sum_z, sum_z2 are 0) */
     double sum_zf2;         /* SPEGG_CONTINUOUS: sum of their squares */
+    double resource[2];     /* SPEGG_PHYSIOLOGY: resource densities R_1, R_2 after the last step */
+    double eggs;            /* SPEGG_PHYSIOLOGY: eggs laid at the last step (0 off breeding steps) */
 } spegg_rep_stats;
 
 /* ABI version of the loaded library; equals SPEGG_ABI_VERSION. */
@@ -331,6 +375,11 @@ spegg_status spegg_write_alleles(spegg_pop *pop, uint32_t rep, uint32_t patch, c
                                  uint32_t generation);
 spegg_status spegg_read_phenotypes_f(spegg_pop *pop, uint32_t rep, uint32_t patch, float *host_z, size_t n,
                                      uint32_t *n_out);
+
+/* SPEGG_PHYSIOLOGY: wait, then copy each individual's irreversible and
+ * reversible mass (N doubles each) of replicate rep into host_X, host_Y. */
+spegg_status spegg_read_body(spegg_pop *pop, uint32_t rep, double *host_X, double *host_Y, size_t n,
+                             uint32_t *n_out);
 
 /* Separate sexes: wait, then copy each individual's sex (N uint8, 0
  * female, 1 male) of patch `patch` of replicate rep into host_sex; all 0

@@ -138,6 +138,59 @@ __device__ __forceinline__ float phenotype_cont(const RepDesc &d, const Rng &rng
     return (float)z;
 }
 
+// Physiology regime (Supplementary S2).  Resource scarcity h(R, K) = x /
+// (1 + T_H x), x = a R / K.
+__device__ __forceinline__ double resource_h(const RepDesc &d, double R, double K) {
+    const double x = d.attack * R / K;
+    return x / (1.0 + d.handling * x);
+}
+
+// One time step of adult i's consumption and growth (S2, Resource
+// Consumption and Somatic Growth): intake alpha W^gamma shared between the
+// resources by the diet share logistic in W^(1/3), each cut by its h; the
+// surplus over metabolism delta W to X in the share min(1, kappa Y/X), a
+// deficit from Y; at a breeding step a mature individual's reserves above
+// q_A X become gonads.  Updates X, Y; returns the gonads; adds the
+// consumption to e1, e2.
+__device__ __forceinline__ double phys_grow(const RepDesc &d, double h1, double h2, bool breeding, double &X,
+                                            double &Y, double &e1, double &e2) {
+    const double W = X + Y;
+    const double pi1 = 1.0 / (1.0 + exp(-d.steepness * (cbrt(W) - d.ulmax)));
+    const double intake = d.alpha * pow(W, d.gamma);
+    const double c1 = h1 * pi1 * intake, c2 = h2 * (1.0 - pi1) * intake;
+    const double dW = c1 + c2 - d.delta * W;
+    e1 += c1;
+    e2 += c2;
+    if (dW > 0.0) {
+        double f = d.kappa * Y / X;
+        if (f > 1.0) f = 1.0;
+        X += f * dW;
+        Y += (1.0 - f) * dW;
+    } else {
+        Y += dW;
+    }
+    double G = 0.0;
+    if (breeding && X >= d.maturity) {
+        G = Y - d.qA * X;
+        if (G < 0.0) G = 0.0;
+        Y -= G;
+    }
+    return G;
+}
+
+// S2, Mortality: (1 - exp(-beta_s Y/X)) / (1 + exp(-beta_2 (X - beta_1))),
+// 0 without reserves.
+__device__ __forceinline__ double phys_survival(const RepDesc &d, double X, double Y) {
+    if (!(Y > 0.0)) return 0.0;
+    return (1.0 - exp(-d.beta_s * Y / X)) / (1.0 + exp(-d.beta2 * (X - d.beta1)));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 // Additive effect sum_l e_l b_l, accumulated word by word.  With the
 // offset effects e_l + 4 in [0, 8] held as four bit-planes Q_k (bit k of
 // e_l + 4, W words each), sum_l e_l b_l = sum_k 2^k popc(g & Q_k) - 4 popc(g):
@@ -397,6 +450,56 @@ __device__ uint32_t team_partner(const RepDesc &d, const Rng &rng, uint32_t stre
     return gload(d.S + last);  // unreachable: the wanted sex survived
 }
 
+// Physiology regime (S2, Reproduction): a mother among the mature
+// surviving females in proportion to her eggs^v_f, a father among the mature
+// surviving males in proportion to X^v_m, by proposals as in team_partner:
+// proposal p accepted when eligible and word 2 lies below floor((w /
+// w_max)^v 2^32), w_max the step's largest weight (from compact).  After
+// kPartnerProposals rejections: the first eligible survivor at or after the
+// last proposal.  cur is the adults' buffer (masses grown in place).
+template <uint32_t TPO>
+__device__ uint32_t team_phys_partner(const RepDesc &d, const RepState &st, const Rng &rng, uint32_t stream,
+                                      uint32_t key, uint32_t tp, uint32_t cur, uint32_t male, uint32_t ns,
+                                      uint32_t lane, uint32_t seg0) {
+    constexpr uint64_t tmask = TPO >= 64 ? ~0ull : ((1ull << TPO) - 1ull);
+    const double v = male ? d.v_m : d.v_f, wmax = male ? st.xmax : st.emax;
+    const float *zf = reinterpret_cast<const float *>(d.z[cur]);
+    uint32_t last = 0;
+    for (uint32_t p0 = 0; p0 < kPartnerProposals; p0 += TPO) {
+        const Words4 b = rng.block(key, stream, p0 + lane, tp);
+        const uint32_t r = uniform_index(b.v[0], b.v[1], ns);
+        const uint32_t c = gload(d.S + r);
+        const double X = gload(d.X[cur] + c);
+        bool ok = gload(d.sex[cur] + c) == male && X >= d.maturity;
+        if (ok) {
+            double w = X;
+            if (!male) {
+                const double om = (double)gload(zf + c);
+                w = gload(d.G + c) / (om + d.qJ * om);
+            }
+            double a = w / wmax;
+            if (v != 1.0) a = pow(a, v);
+            const uint64_t T = a >= 1.0 ? kAlways : (a > 0.0 ? (uint64_t)floor(a * 4294967296.0) : 0ull);
+            ok = (uint64_t)b.v[2] < T;
+        }
+        const uint64_t seg = (__ballot(ok) >> seg0) & tmask;
+        if (seg) return (uint32_t)__shfl((int)c, (int)__ffsll((unsigned long long)seg) - 1, (int)TPO);
+        last = (uint32_t)__shfl((int)r, (int)TPO - 1, (int)TPO);
+    }
+    for (uint32_t q0 = 0; q0 < ns; q0 += TPO) {
+        const uint32_t q = q0 + lane;
+        uint32_t c = 0;
+        bool ok = false;
+        if (q < ns) {
+            c = gload(d.S + (last + q) % ns);
+            ok = gload(d.sex[cur] + c) == male && gload(d.X[cur] + c) >= d.maturity;
+        }
+        const uint64_t seg = (__ballot(ok) >> seg0) & tmask;
+        if (seg) return (uint32_t)__shfl((int)c, (int)__ffsll((unsigned long long)seg) - 1, (int)TPO);
+    }
+    return gload(d.S + last);  // unreachable: an eligible parent survived
+}
+
 // Words of one stream of one individual read in order, one Philox block
 // per four words.
 struct SeqWords {
@@ -507,6 +610,10 @@ __global__ void __launch_bounds__(kBlock) create_kernel(const RepDesc *__restric
             const float z = phenotype_cont(d, rng, gv, i, 0, 1);
             gstore(d.z[0] + i, (int32_t)__float_as_uint(z));
             if (d.sexes) gstore(d.sex[0] + i, (uint8_t)(rng.block(i, kStSex, 1, 0).v[0] & 1u));
+            if (d.X[0]) {  // physiology regime: born at its own neonate mass
+                gstore(d.X[0] + i, (double)z);
+                gstore(d.Y[0] + i, d.qJ * (double)z);
+            }
             fz += (double)z;
             fz2 += (double)z * (double)z;
         }
@@ -573,6 +680,10 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
             const float z = phenotype_cont(d, rng, gv, i, gen, 1);
             d.z[buf][i] = (int32_t)__float_as_uint(z);
             if (d.sexes) d.sex[buf][i] = (uint8_t)(rng.block(i, kStSex, 1, gen).v[0] & 1u);
+            if (d.X[0]) {
+                d.X[buf][i] = (double)z;
+                d.Y[buf][i] = d.qJ * (double)z;
+            }
             fz = (double)z;
             fz2 = fz * fz;
         }
@@ -658,6 +769,14 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     }
     const double s = density_factor(d, n);
     const Rng rng{d.key0, d.key1, d.c3};
+    const bool phys = d.regime == SPEGG_PHYSIOLOGY;
+    const bool breeding = phys && t % d.breed_every == d.breed_every - 1u;
+    double h1 = 0.0, h2 = 0.0, pe1 = 0.0, pe2 = 0.0, peggs = 0.0, pemax = 0.0, pxmax = 0.0;
+    uint32_t pnf = 0, pnm = 0;
+    if (phys) {
+        h1 = resource_h(d, st.R[0], d.KR2[0]);
+        h2 = resource_h(d, st.R[1], d.KR2[1]);
+    }
     double v[IT];
 #pragma unroll
     for (uint32_t q = 0; q < IT; ++q)
@@ -677,6 +796,17 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
             uint32_t intake = 0;
             bool captured = false;
             double p = v[q] * s;
+            double PX = 0.0, PY = 0.0, PG = 0.0;
+            if (phys) {
+                // grow on this step's resources, in place; survival from the new masses
+                PX = gload(d.X[t & 1u] + i);
+                PY = gload(d.Y[t & 1u] + i);
+                PG = phys_grow(d, h1, h2, breeding, PX, PY, pe1, pe2);
+                gstore(d.X[t & 1u] + i, PX);
+                gstore(d.Y[t & 1u] + i, PY);
+                gstore(d.G + i, PG);
+                p = phys_survival(d, PX, PY);
+            }
             if (cr) {
                 p = v[q] * d.surv_age[(age4 >> (8u * q)) & 3u];
                 if (d.species == 0) {
@@ -702,6 +832,19 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
                     uint32_t kids = 0;
                     const bool male = d.sexes && ((sex4 >> (8u * q)) & 1u);
                     if (d.sexes && !male) ++f_loc;
+                    if (phys && PX >= d.maturity) {
+                        // eligible parents of a breeding step and their weights
+                        if (male) {
+                            ++pnm;
+                            pxmax = fmax(pxmax, PX);
+                        } else {
+                            const double om = (double)__uint_as_float(zw.v[q]);
+                            const double e = PG / (om + d.qJ * om);
+                            ++pnf;
+                            peggs += e;
+                            pemax = fmax(pemax, e);
+                        }
+                    }
                     if (male) {
                         // separate sexes: only females are mothers
                     } else if (poisson || (cr && d.species == 0)) {
@@ -722,6 +865,41 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     uint16_t *fp = d.fate + i0;
     store_fates<IT>(fp, fate);
     const uint32_t wave = threadIdx.x >> 6;
+    if (phys) {
+        // the tile's consumption, eggs and largest weights (uniform over the block)
+        __shared__ double sh_p[kBlock / 64][5];
+        __shared__ uint32_t sh_pn[kBlock / 64][2];
+        pe1 = wave_sum<double>(pe1);
+        pe2 = wave_sum<double>(pe2);
+        peggs = wave_sum<double>(peggs);
+        pemax = wave_max(pemax);
+        pxmax = wave_max(pxmax);
+        pnf = wave_sum<uint32_t>(pnf);
+        pnm = wave_sum<uint32_t>(pnm);
+        if (lane_id() == 0) {
+            sh_p[wave][0] = pe1;
+            sh_p[wave][1] = pe2;
+            sh_p[wave][2] = peggs;
+            sh_p[wave][3] = pemax;
+            sh_p[wave][4] = pxmax;
+            sh_pn[wave][0] = pnf;
+            sh_pn[wave][1] = pnm;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            PhysTile pt{};
+            for (int w = 0; w < kBlock / 64; ++w) {
+                pt.e[0] += sh_p[w][0];
+                pt.e[1] += sh_p[w][1];
+                pt.eggs += sh_p[w][2];
+                pt.emax = fmax(pt.emax, sh_p[w][3]);
+                pt.xmax = fmax(pt.xmax, sh_p[w][4]);
+                pt.nf += sh_pn[w][0];
+                pt.nm += sh_pn[w][1];
+            }
+            d.ptiles[blockIdx.x - d.surv_tile0] = pt;
+        }
+    }
     const uint32_t wa = wave_sum<uint32_t>(a_loc), wk = wave_sum<uint32_t>(k_loc), wn = wave_sum<uint32_t>(near);
     const uint32_t wi = wave_sum<uint32_t>(in_loc);
     const uint32_t wf = wave_sum<uint32_t>(f_loc);
@@ -902,12 +1080,76 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
         __syncthreads();
     }
 
+    // Physiology regime, tile 0: the step's consumption, eggs and weights
+    // over the tiles (uniform over the block)
+    __shared__ double sh_ph[kBlock / 64][5];
+    __shared__ uint32_t sh_phn[kBlock / 64][2];
+    double ph[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // e1, e2, eggs, emax, xmax
+    uint32_t phn[2] = {0, 0};                    // mature surviving females, males
+    const bool phys = d.regime == SPEGG_PHYSIOLOGY;
+    if (k == 0 && phys) {
+        for (uint32_t q = threadIdx.x; q < active; q += kBlock) {
+            const PhysTile pt = d.ptiles[q];
+            ph[0] += pt.e[0];
+            ph[1] += pt.e[1];
+            ph[2] += pt.eggs;
+            ph[3] = fmax(ph[3], pt.emax);
+            ph[4] = fmax(ph[4], pt.xmax);
+            phn[0] += pt.nf;
+            phn[1] += pt.nm;
+        }
+        for (int c = 0; c < 3; ++c) ph[c] = wave_sum<double>(ph[c]);
+        ph[3] = wave_max(ph[3]);
+        ph[4] = wave_max(ph[4]);
+        phn[0] = wave_sum<uint32_t>(phn[0]);
+        phn[1] = wave_sum<uint32_t>(phn[1]);
+        if (lane_id() == 0) {
+            for (int c = 0; c < 5; ++c) sh_ph[wave][c] = ph[c];
+            sh_phn[wave][0] = phn[0];
+            sh_phn[wave][1] = phn[1];
+        }
+        __syncthreads();
+        for (int c = 0; c < 5; ++c) ph[c] = 0.0;
+        phn[0] = phn[1] = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            for (int c = 0; c < 3; ++c) ph[c] += sh_ph[w][c];
+            ph[3] = fmax(ph[3], sh_ph[w][3]);
+            ph[4] = fmax(ph[4], sh_ph[w][4]);
+            phn[0] += sh_phn[w][0];
+            phn[1] += sh_phn[w][1];
+        }
+    }
+
     if (k == 0 && threadIdx.x == 0) {
         // census of the newborns, into the pair the other blocks do not read
         const uint32_t ns = sum_a;
         const bool cr = d.regime == SPEGG_CONSUMER_RESOURCE;
         uint32_t nn;
-        if (ns + nb_alive == 0 || (d.sexes && (sum_f == 0 || sum_f == ns))) {
+        if (phys) {
+            // resources: growth at this step's rate, less what was eaten
+            const Rng rng{d.key0, d.key1, d.c3};
+            for (int j = 0; j < 2; ++j) {
+                double r = d.growth[j];
+                if (d.growth_sd[j] > 0.0) r += d.growth_sd[j] * normal_of(rng.block(0, kStResource, (uint32_t)j, t));
+                const double R = st.R[j];
+                const double Rn = r * R / (1.0 + R / d.KR2[j]) - ph[j];
+                st.R[j] = Rn > 0.0 ? Rn : 0.0;
+            }
+            // recruits of a breeding step: kappa1 F / (1 + (F/kappa2)^kappa3)
+            const bool breeding = t % d.breed_every == d.breed_every - 1u;
+            uint64_t want = 0;
+            if (breeding && phn[0] > 0 && phn[1] > 0) {
+                const double phi = d.kappa1 * ph[2] / (1.0 + pow(ph[2] / d.kappa2, d.kappa3));
+                want = phi >= 4294967295.0 ? 4294967295ull : (uint64_t)floor(phi);
+            }
+            st.eggs = breeding ? ph[2] : 0.0;
+            st.emax = ph[3];
+            st.xmax = ph[4];
+            const uint32_t room = d.cap - ns;
+            const uint32_t nb = want > room ? room : (uint32_t)want;
+            st.truncated += want - nb;
+            nn = ns + nb;
+        } else if (ns + nb_alive == 0 || (d.sexes && (sum_f == 0 || sum_f == ns))) {
             nn = 0;  // no survivor, or (separate sexes) no surviving female or male
         } else if (d.regime == SPEGG_WF) {
             nn = n;
@@ -918,7 +1160,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
             st.truncated += sum_k - nb;
             nn = (cr ? ns : 0u) + nb;
         }
-        st.n_carry = cr ? ns : 0u;
+        st.n_carry = (cr || phys) ? ns : 0u;
         st.captures = sum_i;
         st.n_prev = n;
         st.n_surv = ns;
@@ -1497,7 +1739,7 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
     uint32_t limit = ntiles;
     if (single_deme >= 0) {
         const RepState &s1 = states[single_deme];
-        const uint32_t active = (s1.n[current_pair(s1)] + OPT - 1) / OPT;
+        const uint32_t active = (s1.n[current_pair(s1)] - s1.n_carry + OPT - 1) / OPT;
         limit = active < ntiles ? active : ntiles;
     }
     for (uint32_t ti = blockIdx.x; ti < limit; ti += gridDim.x) {
@@ -1519,7 +1761,8 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
         const RepDesc &d = descs[rep];
         const RepState &st = states[rep];
         const uint32_t newest = current_pair(st);
-        const uint32_t nn = st.n[newest];
+        const uint32_t base = st.n_carry;        // carried survivors come first (physiology regime)
+        const uint32_t nn = st.n[newest] - base;  // newborns
         if (start >= nn || st.error) continue;  // uniform over the block
         const uint32_t tp = st.t[newest] - 1u, cur = tp & 1u;
         const uint32_t W = d.W, L = d.L, Wb = (L + 31u) / 32u, mode = d.mode;
@@ -1563,7 +1806,11 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
             uint32_t mom = d.regime == SPEGG_WF ? gload(sd_src.S + uniform_index(p0, p1, ns)) : gload(d.owner + j);
             uint32_t dad = gload(sd_src.S + uniform_index(p2, p3, ns));
             const uint32_t sx = draw(7, 0) & 1u;
-            if (d.sexes || d.mating != SPEGG_RANDOM_MATING || d.monogamy) {  // uniform over the block; one patch
+            if (d.regime == SPEGG_PHYSIOLOGY) {  // uniform over the block
+                const uint32_t tseg0 = (tid & 63u) - lane;
+                mom = team_phys_partner<TPO>(d, st, rng, kStFemale, j, tp, cur, 0u, ns, lane, tseg0);
+                dad = team_phys_partner<TPO>(d, st, rng, kStMate, j, tp, cur, 1u, ns, lane, tseg0);
+            } else if (d.sexes || d.mating != SPEGG_RANDOM_MATING || d.monogamy) {  // uniform over the block; one patch
                 const uint32_t tseg0 = (tid & 63u) - lane;
                 if (d.regime == SPEGG_WF && d.sexes)
                     mom = team_partner<TPO>(d, rng, kStFemale, j, tp, cur, 0, false, 0u, ns, lane, tseg0);
@@ -1580,9 +1827,15 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
                 gstore(d.dad + j, dad);
                 if (d.mig_T != 0) gstore(d.src + j, sd_src.patch);
             }
-            if (d.sexes && lane == 0) gstore(d.sex[cur ^ 1u] + j, (uint8_t)sx);
+            if (d.sexes && lane == 0) gstore(d.sex[cur ^ 1u] + base + j, (uint8_t)sx);
+            if (d.regime == SPEGG_PHYSIOLOGY && lane == 0) {
+                // a recruit is born at its mother's neonate mass
+                const double om = (double)__uint_as_float((uint32_t)gload(d.z[cur] + mom));
+                gstore(d.X[cur ^ 1u] + base + j, om);
+                gstore(d.Y[cur ^ 1u] + base + j, d.qJ * om);
+            }
             const uint32_t *src = sd_src.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
-            uint32_t *dst = d.genome[cur ^ 1u] + (size_t)j * 2u * W + (size_t)half * W;
+            uint32_t *dst = d.genome[cur ^ 1u] + (size_t)(base + j) * 2u * W + (size_t)half * W;
             // every lane takes part in each cross-lane read, then selects
             const uint32_t phase_m = draw(1, 0), phase_p = draw(2, 0);
             const uint32_t xk_m = draw(3, 0), xk_p = draw(4, 0);
@@ -1750,7 +2003,7 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
                 }
                 if (d.exp_tf) z = exp(z);
                 const float zf = (float)z;
-                gstore(d.z[cur ^ 1u] + j, (int32_t)__float_as_uint(zf));
+                gstore(d.z[cur ^ 1u] + base + j, (int32_t)__float_as_uint(zf));
                 my_z += (double)zf;
                 my_z2 += (double)zf * (double)zf;
             }
@@ -1789,13 +2042,24 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
     if (!st.census_pending) return;  // uniform over the block
     const RepDesc &d = descs[rep];
     if (d.cont) {
-        // continuous alleles: the partials hold doubles
+        // continuous alleles: the partials hold doubles; with carried
+        // survivors (physiology regime) the census is summed directly
         double fa = 0.0, fb = 0.0;
-        const uint32_t used = (st.n[current_pair(st)] + d.off_per_tile - 1u) / d.off_per_tile;
-        for (uint32_t k = threadIdx.x; k < used; k += kBlock) {
-            const Partial p = partials[d.off_tile0 + k];
-            fa += __longlong_as_double(p.sum_z);
-            fb += __longlong_as_double((int64_t)p.sum_z2);
+        if (d.regime == SPEGG_PHYSIOLOGY) {
+            const uint32_t par = current_pair(st), n = st.n[par];
+            const float *zf = reinterpret_cast<const float *>(d.z[st.t[par] & 1u]);
+            for (uint32_t k = threadIdx.x; k < n; k += kBlock) {
+                const double z = (double)zf[k];
+                fa += z;
+                fb += z * z;
+            }
+        } else {
+            const uint32_t used = (st.n[current_pair(st)] + d.off_per_tile - 1u) / d.off_per_tile;
+            for (uint32_t k = threadIdx.x; k < used; k += kBlock) {
+                const Partial p = partials[d.off_tile0 + k];
+                fa += __longlong_as_double(p.sum_z);
+                fb += __longlong_as_double((int64_t)p.sum_z2);
+            }
         }
         fa = wave_sum<double>(fa);
         fb = wave_sum<double>(fb);
@@ -1918,9 +2182,16 @@ __global__ void __launch_bounds__(kBlock) carry_kernel(const RepDesc *__restrict
     for (uint32_t idx = threadIdx.x; idx < cnt; idx += kBlock) {
         const uint32_t k = tile.start + idx, from = d.S[k];
         d.z[cur ^ 1u][k] = d.z[cur][from];
-        const uint32_t a = d.age[cur][from];
-        d.age[cur ^ 1u][k] = (uint8_t)(a < 3u ? a + 1u : 3u);  // class 3 holds three and older
-        if (d.species == 0) d.won[k] = ~0ull;
+        if (d.age[0]) {
+            const uint32_t a = d.age[cur][from];
+            d.age[cur ^ 1u][k] = (uint8_t)(a < 3u ? a + 1u : 3u);  // class 3 holds three and older
+        }
+        if (d.won) d.won[k] = ~0ull;
+        if (d.sexes) d.sex[cur ^ 1u][k] = d.sex[cur][from];
+        if (d.X[0]) {  // physiology regime: the grown masses
+            d.X[cur ^ 1u][k] = d.X[cur][from];
+            d.Y[cur ^ 1u][k] = d.Y[cur][from];
+        }
     }
 }
 

@@ -57,6 +57,7 @@ struct RepPlan {
     uint32_t W = 0, mode = 0, R = 0, opt = 0;
     bool cont = false;  // continuous alleles: W floats per haplotype
     bool ext = false;   // a linkage map or a mating system (the biallelic kernel's extended instance)
+    bool phys = false;  // physiology regime: masses, carried survivors, separate sexes
     std::vector<uint32_t> map;      // linkage map planes (kModeMap)
     std::vector<uint64_t> choiceT;  // mate-choice thresholds over integer phenotypes
     int32_t choice_zmin = 0;
@@ -86,6 +87,7 @@ struct DemePlan {
     uint32_t grp0 = 0, grp_n = 0;  // tile-group sums (two parities of grp_n records)
     size_t genome[2] = {0, 0}, z[2] = {0, 0}, fate = 0, S = 0, owner = 0, mom = 0, dad = 0, src = 0, sex[2] = {0, 0};
     size_t age[2] = {0, 0}, won = 0, intake = 0;
+    size_t X[2] = {0, 0}, Y[2] = {0, 0}, G = 0, ptiles = 0;  // physiology regime
 };
 
 // Demes sharing one offspring-kernel shape.
@@ -195,8 +197,30 @@ spegg_status validate(const spegg_rep_desc &d, uint32_t i) {
     if (d.replicate_id > SPEGG_MAX_REPLICATE_ID)
         return fail(SPEGG_E_INVALID, "replicate %u: replicate_id %u exceeds %u", i, d.replicate_id,
                     SPEGG_MAX_REPLICATE_ID);
-    if (d.regime != SPEGG_WF && d.regime != SPEGG_POISSON_BH && d.regime != SPEGG_CONSUMER_RESOURCE)
+    if (d.regime != SPEGG_WF && d.regime != SPEGG_POISSON_BH && d.regime != SPEGG_CONSUMER_RESOURCE &&
+        d.regime != SPEGG_PHYSIOLOGY)
         return fail(SPEGG_E_INVALID, "replicate %u: unknown regime %u", i, d.regime);
+    if (d.regime == SPEGG_PHYSIOLOGY) {
+        const spegg_physiology *F = d.physiology;
+        if (!F) return fail(SPEGG_E_INVALID, "replicate %u: the physiology regime needs its parameters", i);
+        if (d.genetics != SPEGG_CONTINUOUS || d.exp_transform != 1)
+            return fail(SPEGG_E_INVALID, "replicate %u: the physiology regime's trait is exp(z) of continuous alleles",
+                        i);
+        if (d.n_patches != 1 || d.mating != SPEGG_RANDOM_MATING || d.monogamy)
+            return fail(SPEGG_E_UNSUPPORTED, "replicate %u: the physiology regime has one patch and its own mating", i);
+        bool ok = F->alpha > 0.0 && F->gamma > 0.0 && F->gamma <= 1.0 && F->delta >= 0.0 && F->attack >= 0.0 &&
+                  F->handling >= 0.0 && F->w_max > 0.0 && F->kappa >= 0.0 && F->qJ > 0.0 && F->qA >= 0.0 &&
+                  F->maturity > 0.0 && F->v_f >= 0.0 && F->v_m >= 0.0 && F->kappa1 >= 0.0 && F->kappa2 > 0.0 &&
+                  F->kappa3 >= 0.0 && F->breed_every >= 1 && std::isfinite(F->steepness) &&
+                  std::isfinite(F->switch_frac) && std::isfinite(F->beta1) && std::isfinite(F->beta2) &&
+                  F->beta_s >= 0.0 && std::isfinite(F->alpha) && std::isfinite(F->kappa1);
+        for (int j = 0; j < 2; ++j)
+            ok = ok && F->K[j] > 0.0 && F->R0[j] >= 0.0 && std::isfinite(F->growth[j]) && F->growth_sd[j] >= 0.0 &&
+                 std::isfinite(F->R0[j]) && std::isfinite(F->growth_sd[j]);
+        if (!ok) return fail(SPEGG_E_INVALID, "replicate %u: physiology parameters out of range", i);
+    } else if (d.physiology) {
+        return fail(SPEGG_E_INVALID, "replicate %u: physiology given for another regime", i);
+    }
     if (d.n_patches < 1 || d.n_patches > SPEGG_MAX_PATCHES)
         return fail(SPEGG_E_INVALID, "replicate %u: n_patches %u outside 1..%u", i, d.n_patches, SPEGG_MAX_PATCHES);
     if (d.n_patches > 1 && d.regime != SPEGG_WF)
@@ -278,6 +302,7 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const Gc
     p.mode = recomb_mode(d.r);
     p.R = (uint32_t)std::floor(d.r * 4294967296.0);
     p.ext = d.linkage || d.sexes || d.mating || d.monogamy;
+    p.phys = d.regime == SPEGG_PHYSIOLOGY;
     if (d.linkage) {
         p.mode = kModeMap;
         linkage_planes(d.linkage, L, p.map);
@@ -379,8 +404,8 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
     // population has several demes and no consumer-resource replicate (fewer,
     // longer blocks; measured faster on the batched table), else one (more
     // blocks in flight for one deme; the consumer-resource kernels assume it)
-    bool any_cr = false;
-    for (const RepPlan &p : P.reps) any_cr |= p.cr;
+    bool any_cr = false;  // consumer-resource or physiology: one adult per thread, carried survivors
+    for (const RepPlan &p : P.reps) any_cr |= p.cr || p.phys;
     P.surv_items = (!any_cr && P.demes.size() > 1) ? (uint32_t)kSurvItemsMax : 1u;
     const uint32_t surv_tile = kBlock * P.surv_items;
     for (uint32_t u = 0; u < P.demes.size(); ++u) {
@@ -393,7 +418,7 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         for (uint32_t k = 0; k < q.surv_ntiles; ++k) {
             const SurvTile tile{u, k * surv_tile};
             P.surv_tiles.push_back(tile);
-            if (P.reps[q.rep].cr) P.carry_tiles.push_back(tile);
+            if (P.reps[q.rep].cr || P.reps[q.rep].phys) P.carry_tiles.push_back(tile);
             if (P.reps[q.rep].cr && q.species == 1) P.enc_tiles.push_back(tile);
         }
     }
@@ -484,9 +509,17 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         q.mom = cv.take(cap * sizeof(uint32_t));
         q.dad = cv.take(cap * sizeof(uint32_t));
         if (p.mig_T) q.src = cv.take(cap * sizeof(uint32_t));
-        if (reps[q.rep].sexes) {
+        if (reps[q.rep].sexes || p.phys) {
             q.sex[0] = cv.take(zcap);  // padded to whole tiles: read 4 at a time
             q.sex[1] = cv.take(zcap);
+        }
+        if (p.phys) {
+            q.X[0] = cv.take(cap * sizeof(double));
+            q.X[1] = cv.take(cap * sizeof(double));
+            q.Y[0] = cv.take(cap * sizeof(double));
+            q.Y[1] = cv.take(cap * sizeof(double));
+            q.G = cv.take(cap * sizeof(double));
+            q.ptiles = cv.take(q.surv_ntiles * sizeof(PhysTile));
         }
         if (p.cr) {
             q.age[0] = cv.take(zcap);  // padded to whole tiles: read 4 at a time
@@ -549,6 +582,7 @@ struct spegg_pop {
     std::vector<spegg_rep_desc> descs;           // the caller's descriptors, pointing at the copies below
     std::vector<std::vector<int8_t>> effects;    // copies of the effects
     std::vector<std::vector<double>> linkage;    // copies of the linkage maps
+    std::vector<spegg_physiology> physiology;    // copies of the physiology parameters
     std::vector<spegg_ecology> ecology;          // copies of the ecologies
     GcapMap gcaps;                               // autotuned lanes-per-gamete caps by W
     std::vector<RepDesc> dev_descs;  // host images of the device descriptors, one per deme
@@ -652,6 +686,9 @@ spegg_rep_stats census_of(const RepState &s) {
     }
     c.near_ties = s.near_ties;
     c.truncated = s.truncated;
+    c.resource[0] = s.R[0];
+    c.resource[1] = s.R[1];
+    c.eggs = s.eggs;
     c.sum_threshold = s.sum_threshold;
     c.updates = s.updates;
     return c;
@@ -670,6 +707,7 @@ spegg_rep_stats sum_of(const spegg_rep_stats *p, uint32_t n) {
         c.sum_z2 += p[k].sum_z2;
         c.sum_zf += p[k].sum_zf;
         c.sum_zf2 += p[k].sum_zf2;
+        c.eggs += p[k].eggs;
         c.near_ties += p[k].near_ties;
         c.truncated += p[k].truncated;
         c.sum_threshold += p[k].sum_threshold;
@@ -945,7 +983,7 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.s0 = d.allele_sd;
         h.mut_sd = d.mut_sd_factor * std::fabs(d.allele_mean);
         h.noise_sd = d.noise_sd;
-        h.sexes = d.sexes;
+        h.sexes = p.phys ? 1u : d.sexes;  // the physiology regime's consumer has two sexes
         h.mating = d.mating;
         h.monogamy = d.monogamy;
         h.pref_opt = d.pref_optimum;
@@ -956,6 +994,40 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.map = p.map.empty() ? nullptr : at<uint32_t>(pop->base, p.map_at);
         h.sex[0] = q.sex[0] ? at<uint8_t>(pop->base, q.sex[0]) : nullptr;
         h.sex[1] = q.sex[1] ? at<uint8_t>(pop->base, q.sex[1]) : nullptr;
+        if (p.phys) {
+            const spegg_physiology &F = *d.physiology;
+            h.alpha = F.alpha;
+            h.gamma = F.gamma;
+            h.delta = F.delta;
+            h.attack = F.attack;
+            h.handling = F.handling;
+            for (int j = 0; j < 2; ++j) {
+                h.KR2[j] = F.K[j];
+                h.growth[j] = F.growth[j];
+                h.growth_sd[j] = F.growth_sd[j];
+            }
+            h.steepness = F.steepness;
+            h.ulmax = F.switch_frac * std::cbrt(F.w_max);
+            h.kappa = F.kappa;
+            h.qJ = F.qJ;
+            h.qA = F.qA;
+            h.beta1 = F.beta1;
+            h.beta2 = F.beta2;
+            h.beta_s = F.beta_s;
+            h.maturity = F.maturity;
+            h.v_f = F.v_f;
+            h.v_m = F.v_m;
+            h.kappa1 = F.kappa1;
+            h.kappa2 = F.kappa2;
+            h.kappa3 = F.kappa3;
+            h.breed_every = F.breed_every;
+            for (int b = 0; b < 2; ++b) {
+                h.X[b] = at<double>(pop->base, q.X[b]);
+                h.Y[b] = at<double>(pop->base, q.Y[b]);
+            }
+            h.G = at<double>(pop->base, q.G);
+            h.ptiles = at<PhysTile>(pop->base, q.ptiles);
+        }
         h.species = q.species;
         if (p.cr) {
             const spegg_ecology &ec = *d.ecology;
@@ -978,7 +1050,11 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         }
         pop->dev_descs[u] = h;
         std::memcpy(img + P.descs + u * sizeof(RepDesc), &h, sizeof h);
-        const RepState s0 = initial_state(0, q.n0);
+        RepState s0 = initial_state(0, q.n0);
+        if (p.phys) {
+            s0.R[0] = d.physiology->R0[0];
+            s0.R[1] = d.physiology->R0[1];
+        }
         std::memcpy(img + P.states + u * sizeof(RepState), &s0, sizeof s0);
     }
     for (uint32_t i = 0; i < n_reps; ++i) {
@@ -1031,6 +1107,7 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
     pop->effects.resize(n_reps);
     pop->linkage.resize(n_reps);
     pop->ecology.resize(n_reps);
+    pop->physiology.resize(n_reps);
     for (uint32_t i = 0; i < n_reps; ++i) {
         spegg_rep_desc &d = pop->descs[i];
         if (d.effects) {
@@ -1044,6 +1121,10 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         if (d.linkage) {
             pop->linkage[i].assign(d.linkage, d.linkage + (d.n_loci > 1 ? d.n_loci - 1 : 0));
             d.linkage = pop->linkage[i].data();
+        }
+        if (d.physiology) {
+            pop->physiology[i] = *d.physiology;
+            d.physiology = &pop->physiology[i];
         }
     }
     *out = pop;
@@ -1259,6 +1340,11 @@ spegg_status spegg_write_alleles(spegg_pop *pop, uint32_t rep, uint32_t patch, c
     if (!h.cont) return fail(SPEGG_E_STATE, "write_alleles: replicate %u has biallelic genomes", rep);
     if (n > h.cap) return fail(SPEGG_E_INVALID, "write_alleles: %u individuals exceed capacity %u", n, h.cap);
     if (n > 0 && !host_values) return fail(SPEGG_E_INVALID, "write_alleles: null values");
+    RepState cur_state;
+    if (h.X[0]) {  // the resources carry over
+        DeviceGuard g0(pop->device);
+        if ((st = read_state(pop, u, cur_state)) != SPEGG_OK) return st;
+    }
     for (size_t k = 0; k < (size_t)n * 2u * h.L; ++k)
         if (!std::isfinite(host_values[k])) return fail(SPEGG_E_INVALID, "write_alleles: value %zu is not finite", k);
     std::vector<float> rows((size_t)n * 2u * h.W, 0.0f);
@@ -1267,7 +1353,11 @@ spegg_status spegg_write_alleles(spegg_pop *pop, uint32_t rep, uint32_t patch, c
     DeviceGuard guard(pop->device);
     if ((st = sync_stream(pop)) != SPEGG_OK) return st;
     const uint32_t buf = generation & 1u;
-    const RepState s0 = initial_state(generation, n);
+    RepState s0 = initial_state(generation, n);
+    if (h.X[0]) {
+        s0.R[0] = cur_state.R[0];
+        s0.R[1] = cur_state.R[1];
+    }
     hipError_t e = hipSuccess;
     if (n > 0)
         e = hipMemcpyAsync(h.genome[buf], rows.data(), rows.size() * sizeof(float), hipMemcpyHostToDevice, pop->stream);
@@ -1292,6 +1382,28 @@ spegg_status spegg_read_phenotypes_f(spegg_pop *pop, uint32_t rep, uint32_t patc
         return fail(SPEGG_E_STATE, "read_phenotypes_f: replicate %u has integer phenotypes", rep);
     static_assert(sizeof(float) == sizeof(int32_t), "phenotype buffers hold float bits");
     return spegg_read_phenotypes(pop, rep, patch, 0, reinterpret_cast<int32_t *>(host_z), n, n_out);
+}
+
+spegg_status spegg_read_body(spegg_pop *pop, uint32_t rep, double *host_X, double *host_Y, size_t n,
+                             uint32_t *n_out) {
+    spegg_status st = check_pop(pop);
+    if (st != SPEGG_OK) return st;
+    uint32_t u;
+    if ((st = find_deme(pop, rep, 0, 0, &u)) != SPEGG_OK) return st;
+    const RepDesc &h = pop->dev_descs[u];
+    if (!h.X[0]) return fail(SPEGG_E_STATE, "read_body: replicate %u is not of the physiology regime", rep);
+    DeviceGuard guard(pop->device);
+    RepState s;
+    if ((st = read_state(pop, u, s)) != SPEGG_OK) return st;
+    const uint32_t cn = s.n[current_pair_host(s)], ct = s.t[current_pair_host(s)];
+    if (n_out) *n_out = cn;
+    if (cn == 0) return SPEGG_OK;
+    if (!host_X || !host_Y || n < cn) return fail(SPEGG_E_INVALID, "read_body: need room for %u values", cn);
+    hipError_t e = hipMemcpyAsync(host_X, h.X[ct & 1u], cn * sizeof(double), hipMemcpyDeviceToHost, pop->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_Y, h.Y[ct & 1u], cn * sizeof(double), hipMemcpyDeviceToHost, pop->stream);
+    if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(body)");
+    return sync_stream(pop);
 }
 
 spegg_status spegg_read_sexes(spegg_pop *pop, uint32_t rep, uint32_t patch, uint8_t *host_sex, size_t n,

@@ -38,7 +38,8 @@ enum Stream : uint32_t {
     kStNoise = 15,   // continuous alleles: residual phenotypic noise
     kStSex = 16,     // separate sexes: newborn's sex (block 0), founder's (block 1)
     kStFemale = 17,  // separate sexes: proposals for a mother
-    kStMate = 18     // proposals for a father (sexes, mate choice, monogamy)
+    kStMate = 18,    // proposals for a father (sexes, mate choice, monogamy)
+    kStResource = 19 // physiology regime: resource growth deviates (index 0, block j)
 };
 
 // Proposals for a parent before the fallback rule (the next survivor of the
@@ -149,6 +150,15 @@ struct RepDesc {
     const uint64_t *choiceT;  // acceptance thresholds floor(a 2^32) (biallelic phenotypes)
     const uint32_t *map;      // linkage map planes, kMapWords per 32-boundary word (kModeMap)
     uint8_t *sex[2];          // separate sexes, ping-pong with the genomes
+    // Physiology regime (Supplementary S2); symbols as in spegg_physiology
+    double alpha, gamma, delta, attack, handling;
+    double KR2[2], growth[2], growth_sd[2];
+    double steepness, ulmax;  // ulmax = switch_frac w_max^(1/3), host-computed
+    double kappa, qJ, qA, beta1, beta2, beta_s, maturity, v_f, v_m, kappa1, kappa2, kappa3;
+    uint32_t breed_every;
+    double *X[2], *Y[2];      // irreversible and reversible mass, ping-pong with the genomes
+    double *G;                // gonads set aside at this step's growth
+    struct PhysTile *ptiles;  // per survival tile: consumption, eggs and the largest weights
 };
 
 // Per-deme state.  The census (generation t, size n) is double-buffered:
@@ -166,6 +176,8 @@ struct RepState {
     uint32_t captures;        // consumers: credited captures of the last generation
     uint32_t n_carry;         // survivors carried into the current census (consumer-resource regime)
     uint32_t n_surv_f;        // separate sexes: females among the survivors
+    double R[2];              // physiology regime: resource densities
+    double eggs, emax, xmax;  // physiology regime: eggs of the step, largest eggs and X of the eligible parents
     uint64_t near_ties, truncated, updates, sum_threshold;
     int64_t sum_z[kCensusSlots];
     uint64_t sum_z2[kCensusSlots];
@@ -202,6 +214,14 @@ struct SurvGroup {
 
 struct OffTile {
     uint32_t rep, start;
+};
+
+// Physiology regime, per survival tile: consumption of each resource, eggs
+// of the mature surviving females and the largest eggs, largest X of the
+// mature surviving males, and their counts.
+struct PhysTile {
+    double e[2], eggs, emax, xmax;
+    uint32_t nf, nm;
 };
 
 // Census sums of one offspring tile (continuous alleles: the bits of two

@@ -85,6 +85,7 @@ struct Job {
     std::vector<std::vector<int8_t>> effects;  // owned copies behind reps[i].effects
     std::vector<std::vector<double>> linkage;  // owned copies behind reps[i].linkage
     std::vector<spegg_ecology> ecology;        // owned copies behind reps[i].ecology
+    std::vector<spegg_physiology> physiology;  // owned copies behind reps[i].physiology
     uint32_t remaining = 0;
     size_t bytes = 0, off = 0;
     uint32_t lane = 0;   // stream index
@@ -247,7 +248,12 @@ spegg_status spegg_server_submit(spegg_server *s, uint64_t job_id, const spegg_r
     j.effects.resize(n_reps);
     j.linkage.resize(n_reps);
     j.ecology.resize(n_reps);
+    j.physiology.resize(n_reps);
     for (uint32_t i = 0; i < n_reps; ++i) {
+        if (reps[i].physiology) {
+            j.physiology[i] = *reps[i].physiology;
+            j.reps[i].physiology = &j.physiology[i];
+        }
         if (reps[i].effects) {
             j.effects[i].assign(reps[i].effects, reps[i].effects + reps[i].n_loci);
             j.reps[i].effects = j.effects[i].data();
@@ -314,10 +320,12 @@ spegg_status spegg_server_step(spegg_server *s, uint32_t n_generations, uint32_t
             r.effects = nullptr;
             r.linkage = nullptr;
             r.ecology = nullptr;
+            r.physiology = nullptr;
         }
         j.effects.clear();
         j.linkage.clear();
         j.ecology.clear();
+        j.physiology.clear();
         s->resident.push_back(std::move(j));
         s->waiting.pop_front();
     }

@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libspegg.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-WF, POISSON_BH, CONSUMER_RESOURCE = 0, 1, 2
+WF, POISSON_BH, CONSUMER_RESOURCE, PHYSIOLOGY = 0, 1, 2, 3
 KERNEL_NAMES = ["survive", "compact", "offspring", "encounter", "carry"]
 
 
@@ -39,6 +39,32 @@ class Ecology(C.Structure):
         ("surv_resource", C.c_double * 4),
         ("surv_consumer", C.c_double * 4),
     ]
+
+
+class Physiology(C.Structure):
+    _fields_ = [
+        ("alpha", C.c_double), ("gamma", C.c_double), ("delta", C.c_double),
+        ("attack", C.c_double), ("handling", C.c_double),
+        ("K", C.c_double * 2), ("growth", C.c_double * 2), ("growth_sd", C.c_double * 2), ("R0", C.c_double * 2),
+        ("steepness", C.c_double), ("switch_frac", C.c_double), ("w_max", C.c_double),
+        ("kappa", C.c_double), ("qJ", C.c_double), ("qA", C.c_double),
+        ("beta1", C.c_double), ("beta2", C.c_double), ("beta_s", C.c_double),
+        ("maturity", C.c_double),
+        ("v_f", C.c_double), ("v_m", C.c_double),
+        ("kappa1", C.c_double), ("kappa2", C.c_double), ("kappa3", C.c_double),
+        ("breed_every", C.c_uint32),
+    ]
+
+
+def make_physiology(phy):
+    f = Physiology()
+    for k, v in phy.items():
+        if k in ("K", "growth", "growth_sd", "R0"):
+            arr = getattr(f, k)
+            arr[0], arr[1] = float(v[0]), float(v[1])
+        else:
+            setattr(f, k, v)
+    return f
 
 
 class RepDesc(C.Structure):
@@ -73,6 +99,7 @@ class RepDesc(C.Structure):
         ("pref_optimum", C.c_double),
         ("pref_width", C.c_double),
         ("monogamy", C.c_uint32),
+        ("physiology", C.POINTER(Physiology)),
     ]
 
 
@@ -92,10 +119,14 @@ class RepStats(C.Structure):
         ("updates", C.c_uint64),
         ("sum_zf", C.c_double),
         ("sum_zf2", C.c_double),
+        ("resource", C.c_double * 2),
+        ("eggs", C.c_double),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {name: getattr(self, name) for name, _ in self._fields_}
+        out["resource"] = (self.resource[0], self.resource[1])
+        return out
 
 
 _lib = None
@@ -139,6 +170,8 @@ def load():
     lib.spegg_write_alleles.argtypes = [vp, u32, u32, PF, u32, u32]
     lib.spegg_read_phenotypes_f.restype = st
     lib.spegg_read_phenotypes_f.argtypes = [vp, u32, u32, PF, C.c_size_t, P32]
+    lib.spegg_read_body.restype = st
+    lib.spegg_read_body.argtypes = [vp, u32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_size_t, P32]
     lib.spegg_read_sexes.restype = st
     lib.spegg_read_sexes.argtypes = [vp, u32, u32, C.POINTER(C.c_uint8), C.c_size_t, P32]
     lib.spegg_read_ages.restype = st
@@ -221,7 +254,7 @@ def _p(arr, ctype):
 DESC_KEYS = ("seed", "replicate_id", "regime", "n0", "capacity", "n_loci", "mu", "r", "theta", "omega", "K",
              "fecundity", "effects", "n_patches", "migration", "ecology", "dispersal", "home_return", "genetics",
              "allele_mean", "allele_sd", "mut_sd_factor", "noise_sd", "exp_transform", "linkage", "sexes", "mating",
-             "pref_optimum", "pref_width", "monogamy")
+             "pref_optimum", "pref_width", "monogamy", "physiology")
 RING, ISLAND = 0, 1
 BIALLELIC, CONTINUOUS = 0, 1
 RANDOM_MATING, PREFERENCE, ASSORTATIVE = 0, 1, 2
@@ -266,6 +299,10 @@ def make_descs(reps):
             setattr(arr[k], f, int(d.get(f, 0)))
         for f in ("pref_optimum", "pref_width"):
             setattr(arr[k], f, float(d.get(f, 0.0)))
+        if d.get("physiology") is not None:
+            ph = make_physiology(d["physiology"])
+            keep.append(ph)
+            arr[k].physiology = C.pointer(ph)
         if d.get("linkage") is not None:
             lk = np.ascontiguousarray(d["linkage"], dtype=np.float64)
             keep.append(lk)
@@ -464,6 +501,15 @@ class Population:
         got = C.c_uint32()
         check(self.lib.spegg_read_phenotypes_f(self._h, rep, patch, _p(out, C.c_float), out.size, C.byref(got)))
         return out[: got.value]
+
+    def body(self, rep=0):
+        """Physiology regime: (X, Y) float64, irreversible and reversible mass."""
+        n = self._n_of(rep)
+        X = np.zeros(max(n, 1), dtype=np.float64)
+        Y = np.zeros(max(n, 1), dtype=np.float64)
+        got = C.c_uint32()
+        check(self.lib.spegg_read_body(self._h, rep, _p(X, C.c_double), _p(Y, C.c_double), X.size, C.byref(got)))
+        return X[: got.value], Y[: got.value]
 
     def sexes(self, rep=0, patch=0):
         """Separate sexes: 0 female, 1 male, per individual (all 0 without sexes)."""

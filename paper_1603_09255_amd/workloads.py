@@ -55,6 +55,36 @@ def continuous_scale(seed=1):
                 allele_sd=0.01, mut_sd_factor=0.5, noise_sd=0.2, exp_transform=0), 100
 
 
+PHYSIOLOGY = 3
+
+# Synthetic parameters of the physiologically structured consumer
+# (Supplementary S2 gives the model but not its values): intake 0.3 W^0.75,
+# metabolism 0.1 W, Holling scarcity with attack 2 and handling 1, the diet
+# switching from resource 2 to resource 1 at W = 1 (w_max 8, u 1/2,
+# steepness 5), reserves 0.2 X at birth and gonads above 0.4 X, maturity at
+# X = 1, survival 1/(1 + exp(-20 (X - 0.05))) times 1 - exp(-20 Y/X),
+# recruitment 0.5 F / (1 + F/kappa2), breeding every 5 steps; a population
+# of n0 = 50000 settles near 4e4 with the adults' resource drawn down.
+PHYSIOLOGY_PARAMS = dict(alpha=0.3, gamma=0.75, delta=0.1, attack=2.0, handling=1.0, K=[75000.0, 75000.0],
+                         growth=[2.0, 2.0], growth_sd=[0.1, 0.1], R0=[75000.0, 75000.0], steepness=5.0,
+                         switch_frac=0.5, w_max=8.0, kappa=1.0, qJ=0.2, qA=0.4, beta1=0.05, beta2=20.0, beta_s=20.0,
+                         maturity=1.0, v_f=1.0, v_m=1.0, kappa1=0.5, kappa2=25000.0, kappa3=1.0, breed_every=5)
+
+
+def physiology_batch(n_reps=100, seed=1, L=16):
+    """The physiologically structured consumer of Supplementary S2 at the
+    paper's scale (about 50000 individuals per patch, up to 100 patches,
+    250 iterations): n_reps independent replicates of n0 = 50000 founders
+    (capacity 200000), neonate mass exp(z) from L = 16 continuous loci
+    (initial values N(-2.3/L, 0.02^2), so Omega near 0.1), mutation 1e-3 per
+    locus to N(value, (0.2 x 2.3/L)^2), phenotypic noise 0.05, free
+    recombination; 250 time steps."""
+    return [dict(seed=seed, replicate_id=i, regime=PHYSIOLOGY, n0=50_000, capacity=200_000, n_loci=L, mu=1e-3,
+                 r=0.5, theta=0.0, omega=0.0, K=0.0, fecundity=0.0, effects=None, genetics=CONTINUOUS,
+                 allele_mean=-2.3 / L, allele_sd=0.02, mut_sd_factor=0.2, noise_sd=0.05, exp_transform=1,
+                 physiology=dict(PHYSIOLOGY_PARAMS)) for i in range(n_reps)], 250
+
+
 def batched_table(n_reps=4096, seed=20260101, philox_seed=1):
     """Per-replicate parameters of the batched form: N ~ U{500..50000},
     L from {64, 256, 1024}, mu log-uniform in [1e-7, 1e-4], r ~ U[0.001, 0.5],
