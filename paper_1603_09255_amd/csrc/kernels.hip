@@ -11,13 +11,17 @@
 //              + C (additive phenotype by popcounts) + census partials; one
 //              team of 2G lanes per newborn, V consecutive words per lane
 //   census     (on demand) folds the partials into the census sums
+//              (continuous alleles: sums the census itself, in a fixed order)
 //   create     (once) every deme's initial population: genomes, phenotypes,
-//              census sums
+//              census sums (integer phenotypes)
 //   encounter  (consumer-resource regime, before survive) consumers meet
 //              and capture resources; each captured resource keeps the
 //              lowest (consumer, encounter) key by a 64-bit atomic minimum
-//   carry      (consumer-resource regime, after compact) survivors move to
-//              the front of the next census, one age class older
+//   carry      (consumer-resource and physiology regimes, after compact)
+//              survivors move to the front of the next census
+//   plan_tiles (populations of several demes whose censuses can fall below
+//              their capacities) lists the tiles a generation occupies;
+//              the launches then walk the lists with resident grids
 //
 // All of it is integer work except p = v s (IEEE double, no contraction),
 // so every result is reproducible bit for bit.  No kernel waits on another
@@ -54,8 +58,8 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const uint32_t lane = lane_id();
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t tid = threadIdx.x) {
+    const uint32_t lane = tid & 63u;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t t = __shfl_up(v, o, 64);
@@ -66,10 +70,11 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 
 // Exclusive prefix over the block (kBlock threads = 4 waves); *total gets
 // the block sum.  Every thread of the block must call it.
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t *total) {
-    const uint32_t incl = wave_incl_scan(v);
-    const uint32_t wave = threadIdx.x >> 6;
-    if (lane_id() == 63) sh[wave] = incl;
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t *total,
+                                                    uint32_t tid = threadIdx.x) {
+    const uint32_t incl = wave_incl_scan(v, tid);
+    const uint32_t wave = tid >> 6;
+    if ((tid & 63u) == 63) sh[wave] = incl;
     __syncthreads();
     uint32_t off = 0, tot = 0;
 #pragma unroll
@@ -573,8 +578,9 @@ __device__ uint32_t small_binomial_table(uint32_t n, double q, uint64_t *T) {
 // individual slot of a survival tile: the individual's 2W genome words (fair
 // bits: word q is word q % 4 of Philox block q / 4 of stream INIT for the
 // individual; bits of word W-1 past locus L-1 cleared), its phenotype, and
-// the census sums (spread over the state's slots).  Consumer-resource demes
-// also start with age class 0 and no capture keys.
+// the census sums of integer phenotypes (spread over the state's slots;
+// continuous phenotypes are summed on demand).  Consumer-resource demes also
+// start with age class 0 and no capture keys.
 __global__ void __launch_bounds__(kBlock) create_kernel(const RepDesc *__restrict__ descs,
                                                         RepState *__restrict__ states,
                                                         const SurvTile *__restrict__ tiles) {
@@ -591,7 +597,6 @@ __global__ void __launch_bounds__(kBlock) create_kernel(const RepDesc *__restric
         // Continuous alleles: allele (h, l) is N(a0, s0^2) from INIT block
         // h L + l of the individual, rounded to float; the pad loci are 0.
         // The genetic value is summed locus by locus in order.
-        double fz = 0.0, fz2 = 0.0;
         for (uint32_t slot = threadIdx.x; slot < d.surv_tile; slot += kBlock) {
             const uint32_t i = tile.start + slot;
             if (i >= n0) continue;
@@ -614,17 +619,8 @@ __global__ void __launch_bounds__(kBlock) create_kernel(const RepDesc *__restric
                 gstore(d.X[0] + i, (double)z);
                 gstore(d.Y[0] + i, d.qJ * (double)z);
             }
-            fz += (double)z;
-            fz2 += (double)z * (double)z;
         }
-        fz = wave_sum<double>(fz);
-        fz2 = wave_sum<double>(fz2);
-        if (lane_id() == 0 && (fz != 0.0 || fz2 != 0.0)) {
-            const uint32_t slot = blockIdx.x % kCensusSlots;
-            atomicAdd(&st.sum_zf[slot], fz);
-            atomicAdd(&st.sum_zf2[slot], fz2);
-        }
-        return;
+        return;  // the census sums are folded on demand, in a fixed order (the state says so)
     }
     for (uint32_t slot = threadIdx.x; slot < d.surv_tile; slot += kBlock) {
         const uint32_t i = tile.start + slot;  // below the deme's whole tiles
@@ -671,7 +667,6 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (d.cont) {
         // continuous alleles written by the caller: founders of generation gen
-        double fz = 0.0, fz2 = 0.0;
         if (i < n) {
             const float *g = reinterpret_cast<const float *>(d.genome[buf] + (size_t)i * 2u * d.W);
             double gv = 0.0;
@@ -684,17 +679,8 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
                 d.X[buf][i] = (double)z;
                 d.Y[buf][i] = d.qJ * (double)z;
             }
-            fz = (double)z;
-            fz2 = fz * fz;
         }
-        fz = wave_sum<double>(fz);
-        fz2 = wave_sum<double>(fz2);
-        if (lane_id() == 0 && (fz != 0.0 || fz2 != 0.0)) {
-            const uint32_t slot = blockIdx.x % kCensusSlots;
-            atomicAdd(&state->sum_zf[slot], fz);
-            atomicAdd(&state->sum_zf2[slot], fz2);
-        }
-        return;
+        return;  // the census sums are folded on demand, in a fixed order (the state says so)
     }
     int64_t z = 0;
     if (i < n) {
@@ -725,24 +711,25 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
 // One block per tile of kBlock x IT adults; thread x holds the IT
 // consecutive adults from tile start + x IT (z and fate buffers are padded to
 // whole tiles, so the vector accesses stay inside).
-template <int IT>
-__global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restrict__ descs,
-                                                         const RepState *__restrict__ states,
-                                                         const SurvTile *__restrict__ tiles,
-                                                         SurvCount *__restrict__ counts,
-                                                         SurvGroup *__restrict__ groups, int single_deme) {
+// The tile's global index gi is the block index in a launch of one block per
+// tile; a block that walks a list of tiles derives it from the tile.
+template <int IT, bool LIST>
+__device__ __forceinline__ void survive_tile(const RepDesc *__restrict__ descs, const RepState *__restrict__ states,
+                                             const SurvTile tile, SurvCount *__restrict__ counts,
+                                             SurvGroup *__restrict__ groups) {
+    // the thread index, opaque to the compiler in a list-walking loop: no
+    // value derived from it is hoisted out of the loop and held across tiles
+    uint32_t tid = threadIdx.x;
+    if (LIST) asm volatile("" : "+v"(tid));
     __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_n[kBlock / 64], sh_i[kBlock / 64];
     __shared__ uint32_t sh_f[kBlock / 64];
     __shared__ uint64_t sh_t[kBlock / 64];
     __shared__ uint64_t sh_pois[kPoissonTableCap];
-    // a population of one deme has its tiles implicit: no load before the
-    // descriptor's
-    const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * (uint32_t)(kBlock * IT)}
-                                           : tiles[blockIdx.x];
     const RepDesc &d = descs[tile.rep];
+    const uint32_t gi = LIST ? d.surv_tile0 + tile.start / (uint32_t)(kBlock * IT) : blockIdx.x;
     // Both phenotype buffers (padded to whole tiles) are read with the census
     // state, which alone says which one holds the census: no load waits for it.
-    const uint32_t i0 = tile.start + threadIdx.x * IT;
+    const uint32_t i0 = tile.start + tid * IT;
     const Words<IT> zw0 = load_words<IT>(reinterpret_cast<const uint32_t *>(d.z[0]) + i0);
     const Words<IT> zw1 = load_words<IT>(reinterpret_cast<const uint32_t *>(d.z[1]) + i0);
     const RepState &st = states[tile.rep];
@@ -756,11 +743,11 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     __shared__ uint32_t sh_tlen;
     uint32_t tlen = d.pois_len;  // length of the table in sh_pois
     if (poisson) {
-        for (uint32_t q = threadIdx.x; q < d.pois_len; q += kBlock) sh_pois[q] = gload(d.pois + q);
+        for (uint32_t q = tid; q < d.pois_len; q += kBlock) sh_pois[q] = gload(d.pois + q);
         __syncthreads();
     } else if (cr && d.species == 0) {
         // the resource's offspring table of this generation's density
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             const double x = 1.0 - (double)n / d.KR;
             sh_tlen = small_binomial_table(d.trials, d.q0 * (x > 0.0 ? x : 0.0), sh_pois);
         }
@@ -864,7 +851,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
     // fates of the thread's adults, one store
     uint16_t *fp = d.fate + i0;
     store_fates<IT>(fp, fate);
-    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t wave = tid >> 6;
     if (phys) {
         // the tile's consumption, eggs and largest weights (uniform over the block)
         __shared__ double sh_p[kBlock / 64][5];
@@ -876,7 +863,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
         pxmax = wave_max(pxmax);
         pnf = wave_sum<uint32_t>(pnf);
         pnm = wave_sum<uint32_t>(pnm);
-        if (lane_id() == 0) {
+        if ((tid & 63u) == 0) {
             sh_p[wave][0] = pe1;
             sh_p[wave][1] = pe2;
             sh_p[wave][2] = peggs;
@@ -886,7 +873,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
             sh_pn[wave][1] = pnm;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             PhysTile pt{};
             for (int w = 0; w < kBlock / 64; ++w) {
                 pt.e[0] += sh_p[w][0];
@@ -897,14 +884,14 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
                 pt.nf += sh_pn[w][0];
                 pt.nm += sh_pn[w][1];
             }
-            d.ptiles[blockIdx.x - d.surv_tile0] = pt;
+            d.ptiles[gi - d.surv_tile0] = pt;
         }
     }
     const uint32_t wa = wave_sum<uint32_t>(a_loc), wk = wave_sum<uint32_t>(k_loc), wn = wave_sum<uint32_t>(near);
     const uint32_t wi = wave_sum<uint32_t>(in_loc);
     const uint32_t wf = wave_sum<uint32_t>(f_loc);
     const uint64_t wt = wave_sum<uint64_t>(thr_sum);
-    if (lane_id() == 0) {
+    if ((tid & 63u) == 0) {
         sh_a[wave] = wa;
         sh_k[wave] = wk;
         sh_n[wave] = wn;
@@ -913,7 +900,7 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
         sh_t[wave] = wt;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         SurvCount c{};
         for (int w = 0; w < kBlock / 64; ++w) {
             c.alive += sh_a[w];
@@ -926,12 +913,12 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
         c.par = par;
         c.t = t;
         c.n = n;
-        counts[blockIdx.x] = c;
+        counts[gi] = c;
         // a census of more than one tile group: the tile's counts into its
         // group's sums as well
         const uint32_t active = (n + kBlock * IT - 1) / (kBlock * IT);
         if (active > kGroupTiles) {
-            SurvGroup &g = groups[d.grp0 + (t & 1u) * d.grp_n + (blockIdx.x - d.surv_tile0) / kGroupTiles];
+            SurvGroup &g = groups[d.grp0 + (t & 1u) * d.grp_n + (gi - d.surv_tile0) / kGroupTiles];
             if (c.alive) atomicAdd(&g.alive, c.alive);
             if (c.kids) atomicAdd((unsigned long long *)&g.kids, (unsigned long long)c.kids);
             if (c.near) atomicAdd(&g.near, c.near);
@@ -939,6 +926,35 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
             if (c.intake) atomicAdd(&g.intake, c.intake);
             if (c.alive_f) atomicAdd(&g.alive_f, c.alive_f);
         }
+    }
+}
+
+// One block per survival tile of the plan (a population of one deme has its
+// tiles implicit: no load before the descriptor's).
+template <int IT>
+__global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restrict__ descs,
+                                                         const RepState *__restrict__ states,
+                                                         const SurvTile *__restrict__ tiles,
+                                                         SurvCount *__restrict__ counts,
+                                                         SurvGroup *__restrict__ groups, int single_deme) {
+    const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * (uint32_t)(kBlock * IT)}
+                                           : tiles[blockIdx.x];
+    survive_tile<IT, false>(descs, states, tile, counts, groups);
+}
+
+// A resident grid over the list of this generation's occupied tiles (the
+// tiles of the censuses, written by plan_tiles_kernel).
+template <int IT>
+__global__ void __launch_bounds__(kBlock) survive_list_kernel(const RepDesc *__restrict__ descs,
+                                                              const RepState *__restrict__ states,
+                                                              const SurvTile *__restrict__ list,
+                                                              const uint32_t *__restrict__ list_n,
+                                                              SurvCount *__restrict__ counts,
+                                                              SurvGroup *__restrict__ groups) {
+    const uint32_t m = *list_n;
+    for (uint32_t v = blockIdx.x; v < m; v += gridDim.x) {
+        survive_tile<IT, true>(descs, states, list[v], counts, groups);
+        __syncthreads();  // the next tile reuses the block's LDS
     }
 }
 
@@ -951,27 +967,26 @@ __global__ void __launch_bounds__(kBlock) survive_kernel(const RepDesc *__restri
 // of more than kGroupTiles tiles also has group sums (survive added each
 // tile into its group): a tile then sums the earlier groups and the earlier
 // tiles of its own group, at most one load per thread each.
-template <int IT>
-__global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restrict__ descs,
-                                                         RepState *__restrict__ states,
-                                                         const SurvTile *__restrict__ tiles,
-                                                         const SurvCount *__restrict__ counts,
-                                                         SurvGroup *__restrict__ groups, int trace,
-                                                         int single_deme) {
+template <int IT, bool LIST>
+__device__ __forceinline__ void compact_tile(const RepDesc *__restrict__ descs, RepState *__restrict__ states,
+                                             const SurvTile tile, const SurvCount *__restrict__ counts,
+                                             SurvGroup *__restrict__ groups, int trace) {
+    // the thread index, opaque to the compiler in a list-walking loop: no
+    // value derived from it is hoisted out of the loop and held across tiles
+    uint32_t tid = threadIdx.x;
+    if (LIST) asm volatile("" : "+v"(tid));
     constexpr uint32_t TILE = kBlock * IT;
     __shared__ uint32_t sh_a[kBlock / 64], sh_k[kBlock / 64], sh_in[kBlock / 64], sh_f[kBlock / 64];
     __shared__ uint64_t sh_kk[kBlock / 64], sh_n[kBlock / 64], sh_t[kBlock / 64];
-    const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * TILE}
-                                           : tiles[blockIdx.x];
     const RepDesc &d = descs[tile.rep];
     RepState &st = states[tile.rep];
     // the thread's fates, in flight during the prefix (the buffer is padded
     // to whole tiles)
-    const uint32_t i0 = tile.start + threadIdx.x * IT;
+    const uint32_t i0 = tile.start + tid * IT;
     uint32_t fate[IT];
     load_fates<IT>(d.fate + i0, fate);
     const SurvCount *C = counts + d.surv_tile0;
-    const uint32_t k = blockIdx.x - d.surv_tile0;  // tile index within the replicate
+    const uint32_t k = LIST ? tile.start / TILE : blockIdx.x - d.surv_tile0;  // tile index within the replicate
     const uint32_t kg0 = k - k % kGroupTiles;      // first tile of its group
     // exclusive prefix of this tile (tile 0: the totals, with the census
     // statistics only it records).  Past tile 0 the tiles of its own group
@@ -979,8 +994,8 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     // census header's.
     uint32_t pa = 0, pi = 0, pf = 0;
     uint64_t pk = 0, pn = 0, pt = 0;
-    if (k != 0 && threadIdx.x < k - kg0) {
-        const SurvCount c = C[kg0 + threadIdx.x];
+    if (k != 0 && tid < k - kg0) {
+        const SurvCount c = C[kg0 + tid];
         pa += c.alive;
         pk += c.kids;
     }
@@ -992,10 +1007,10 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     if (k >= active && k != 0) return;  // beyond the census: uniform over the block
     const bool grouped = active > kGroupTiles;
     const SurvGroup *G = groups + d.grp0 + (t & 1u) * d.grp_n;
-    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t wave = tid >> 6;
     if (k == 0) {
         if (grouped) {
-            for (uint32_t q = threadIdx.x; q * kGroupTiles < active; q += kBlock) {
+            for (uint32_t q = tid; q * kGroupTiles < active; q += kBlock) {
                 const SurvGroup g = G[q];
                 pa += g.alive;
                 pk += g.kids;
@@ -1005,7 +1020,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
                 pf += g.alive_f;
             }
         } else {
-            for (uint32_t q = threadIdx.x; q < active; q += kBlock) {
+            for (uint32_t q = tid; q < active; q += kBlock) {
                 const SurvCount c = C[q];
                 pa += c.alive;
                 pk += c.kids;
@@ -1019,9 +1034,9 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
         // whether or not this census used groups (a later census of the
         // same parity may).
         SurvGroup *Gn = groups + d.grp0 + ((t + 1u) & 1u) * d.grp_n;
-        for (uint32_t q = threadIdx.x; q < d.grp_n; q += kBlock) Gn[q] = SurvGroup{0, 0, 0, 0, 0, 0};
+        for (uint32_t q = tid; q < d.grp_n; q += kBlock) Gn[q] = SurvGroup{0, 0, 0, 0, 0, 0};
     } else {
-        for (uint32_t q = threadIdx.x; q < kg0 / kGroupTiles; q += kBlock) {  // the earlier groups
+        for (uint32_t q = tid; q < kg0 / kGroupTiles; q += kBlock) {  // the earlier groups
             const SurvGroup g = G[q];
             pa += g.alive;
             pk += g.kids;
@@ -1035,7 +1050,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
         pn = wave_sum<uint64_t>(pn);
         pt = wave_sum<uint64_t>(pt);
     }
-    if (lane_id() == 0) {
+    if ((tid & 63u) == 0) {
         sh_a[wave] = pa;
         sh_in[wave] = pi;
         sh_f[wave] = pf;
@@ -1070,10 +1085,10 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
             const uint32_t u = d.island ? d.deme0 + e : (e ? d.right : d.left);
             const SurvCount *CE = counts + descs[u].surv_tile0;
             const uint32_t act = (CE[0].n + TILE - 1) / TILE;
-            for (uint32_t q = threadIdx.x; q < act; q += kBlock) x += CE[q].alive;
+            for (uint32_t q = tid; q < act; q += kBlock) x += CE[q].alive;
         }
         x = wave_sum<uint32_t>(x);
-        if (lane_id() == 0) sh_a[wave] = x;
+        if ((tid & 63u) == 0) sh_a[wave] = x;
         __syncthreads();
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) nb_alive += sh_a[w];
@@ -1088,7 +1103,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
     uint32_t phn[2] = {0, 0};                    // mature surviving females, males
     const bool phys = d.regime == SPEGG_PHYSIOLOGY;
     if (k == 0 && phys) {
-        for (uint32_t q = threadIdx.x; q < active; q += kBlock) {
+        for (uint32_t q = tid; q < active; q += kBlock) {
             const PhysTile pt = d.ptiles[q];
             ph[0] += pt.e[0];
             ph[1] += pt.e[1];
@@ -1103,7 +1118,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
         ph[4] = wave_max(ph[4]);
         phn[0] = wave_sum<uint32_t>(phn[0]);
         phn[1] = wave_sum<uint32_t>(phn[1]);
-        if (lane_id() == 0) {
+        if ((tid & 63u) == 0) {
             for (int c = 0; c < 5; ++c) sh_ph[wave][c] = ph[c];
             sh_phn[wave][0] = phn[0];
             sh_phn[wave][1] = phn[1];
@@ -1120,7 +1135,7 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
         }
     }
 
-    if (k == 0 && threadIdx.x == 0) {
+    if (k == 0 && tid == 0) {
         // census of the newborns, into the pair the other blocks do not read
         const uint32_t ns = sum_a;
         const bool cr = d.regime == SPEGG_CONSUMER_RESOURCE;
@@ -1187,8 +1202,8 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
         k_loc += fate[q] & 0x7FFFu;
     }
     uint32_t atot, ktot;
-    uint32_t spos = aoff + block_excl_scan(a_loc, sh_a, &atot);
-    uint64_t slot = koff + block_excl_scan(k_loc, sh_k, &ktot);
+    uint32_t spos = aoff + block_excl_scan(a_loc, sh_a, &atot, tid);
+    uint64_t slot = koff + block_excl_scan(k_loc, sh_k, &ktot, tid);
 #pragma unroll
     for (uint32_t q = 0; q < IT; ++q) {
         if (fate[q] >> 15) {
@@ -1200,6 +1215,33 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restri
             for (uint32_t m = 0; m < kids; ++m, ++slot)
                 if (slot < d.cap) gstore(d.owner + slot, i0 + q);
         }
+    }
+}
+
+template <int IT>
+__global__ void __launch_bounds__(kBlock) compact_kernel(const RepDesc *__restrict__ descs,
+                                                         RepState *__restrict__ states,
+                                                         const SurvTile *__restrict__ tiles,
+                                                         const SurvCount *__restrict__ counts,
+                                                         SurvGroup *__restrict__ groups, int trace,
+                                                         int single_deme) {
+    const SurvTile tile = single_deme >= 0 ? SurvTile{(uint32_t)single_deme, blockIdx.x * (uint32_t)(kBlock * IT)}
+                                           : tiles[blockIdx.x];
+    compact_tile<IT, false>(descs, states, tile, counts, groups, trace);
+}
+
+// A resident grid over the same list of occupied tiles as survive's.
+template <int IT>
+__global__ void __launch_bounds__(kBlock) compact_list_kernel(const RepDesc *__restrict__ descs,
+                                                              RepState *__restrict__ states,
+                                                              const SurvTile *__restrict__ list,
+                                                              const uint32_t *__restrict__ list_n,
+                                                              const SurvCount *__restrict__ counts,
+                                                              SurvGroup *__restrict__ groups, int trace) {
+    const uint32_t m = *list_n;
+    for (uint32_t v = blockIdx.x; v < m; v += gridDim.x) {
+        compact_tile<IT, true>(descs, states, list[v], counts, groups, trace);
+        __syncthreads();  // the next tile reuses the block's LDS
     }
 }
 
@@ -1266,7 +1308,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((!E
                                                            const OffTile *__restrict__ tiles, uint32_t tile0,
                                                            uint32_t ntiles, int single_deme,
                                                            Partial *__restrict__ partials, uint32_t plane_words,
-                                                           uint32_t geo_words, int trace) {
+                                                           uint32_t geo_words, int trace,
+                                                           const uint32_t *__restrict__ list_n) {
     constexpr uint32_t TPO = 2 * G;
     constexpr uint32_t TEAMS = kBlock / TPO;
     constexpr uint32_t KF = kOffspringInFlight;  // newborns of a team in flight at once
@@ -1287,8 +1330,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((!E
     uint32_t *planes = lds;
     uint32_t *geo = lds + plane_words;  // geometric-gap thresholds, as 32-bit words
 
+    // tiles: the plan's (one deme: those of its newborns), or the list of
+    // this generation's occupied tiles
     uint32_t limit = ntiles;
-    if (single_deme >= 0) {
+    if (list_n) {
+        const uint32_t m = *list_n;
+        limit = m < ntiles ? m : ntiles;
+    } else if (single_deme >= 0) {
         const RepState &s1 = states[single_deme];
         const uint32_t nb1 = s1.n[current_pair(s1)] - s1.n_carry;
         const uint32_t active = (nb1 + OPT - 1) / OPT;
@@ -1689,8 +1737,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((!E
                 a += red_z[w];
                 b += red_z2[w];
             }
-            gstore(&partials[tile0 + ti].sum_z, a);
-            gstore(&partials[tile0 + ti].sum_z2, b);
+            // the tile's own slot (a listed tile sits elsewhere in the list)
+            const uint32_t slot = list_n ? d.off_tile0 + start / OPT : tile0 + ti;
+            gstore(&partials[slot].sum_z, a);
+            gstore(&partials[slot].sum_z2, b);
         }
         __syncthreads();
     }
@@ -1713,14 +1763,16 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((!E
 // NCH > 0: a gamete spans at most NCH chunks, all gathered before the mask
 // is drawn; NCH == 0: any number, gathered one at a time.
 // Dynamic LDS: the geometric-gap thresholds (geo_words), then per team and
-// gamete a mask bitmap and a flip bitmap of mask_words words each.
+// gamete a mask bitmap and a flip bitmap of mask_words words each.  No
+// census partials: the census kernel sums continuous phenotypes itself.
 template <int G, int NCH>
 __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *__restrict__ descs,
                                                                 const RepState *__restrict__ states,
                                                                 const OffTile *__restrict__ tiles, uint32_t tile0,
                                                                 uint32_t ntiles, int single_deme,
                                                                 Partial *__restrict__ partials, uint32_t mask_words,
-                                                                uint32_t geo_words, int trace) {
+                                                                uint32_t geo_words, int trace,
+                                                                const uint32_t *__restrict__ list_n) {
     constexpr uint32_t TPO = 2 * G;
     constexpr uint32_t TEAMS = kBlock / TPO;
     constexpr uint32_t ITERS = TEAMS >= 16 ? 1 : 16 / TEAMS;
@@ -1733,11 +1785,13 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
     constexpr uint32_t NSD = 8;
     constexpr uint32_t SR = (NSD + TPO - 1) / TPO;
     extern __shared__ uint32_t lds[];
-    __shared__ double red_z[kBlock / 64], red_z2[kBlock / 64];
     uint32_t *geo = lds;
 
     uint32_t limit = ntiles;
-    if (single_deme >= 0) {
+    if (list_n) {
+        const uint32_t m = *list_n;
+        limit = m < ntiles ? m : ntiles;
+    } else if (single_deme >= 0) {
         const RepState &s1 = states[single_deme];
         const uint32_t active = (s1.n[current_pair(s1)] - s1.n_carry + OPT - 1) / OPT;
         limit = active < ntiles ? active : ntiles;
@@ -1774,7 +1828,6 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
         }
         uint32_t *X = lds + geo_words + (size_t)(team * 2u + half) * 2u * mask_words;  // toggles, then mask words
         uint32_t *F = X + mask_words;                                                   // mutation flips
-        double my_z = 0.0, my_z2 = 0.0;
 
         for (uint32_t it = 0; it < ITERS; ++it) {
             const uint32_t j = start + it * TEAMS + team;
@@ -2004,34 +2057,77 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
                 if (d.exp_tf) z = exp(z);
                 const float zf = (float)z;
                 gstore(d.z[cur ^ 1u] + base + j, (int32_t)__float_as_uint(zf));
-                my_z += (double)zf;
-                my_z2 += (double)zf * (double)zf;
             }
             wave_lds_sync();  // X and F are rewritten by the team's next newborn
         }
-        const double wz = wave_sum<double>(my_z);
-        const double wz2 = wave_sum<double>(my_z2);
-        if (lane_id() == 0) {
-            red_z[threadIdx.x >> 6] = wz;
-            red_z2[threadIdx.x >> 6] = wz2;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double a = 0.0, b = 0.0;
-            for (int w = 0; w < kBlock / 64; ++w) {
-                a += red_z[w];
-                b += red_z2[w];
-            }
-            gstore(&partials[tile0 + ti].sum_z, (int64_t)__double_as_longlong(a));
-            gstore(&partials[tile0 + ti].sum_z2, (uint64_t)__double_as_longlong(b));
-        }
-        __syncthreads();
+        __syncthreads();  // the next tile may reload the gap table
+    }
+}
+
+// ---------------------------------------------------------------- tile lists
+
+// This generation's occupied tiles, for populations whose censuses can fall
+// far below their capacities: the launches then walk these lists with
+// resident grids instead of dispatching one block per tile of the capacity.
+// One block per deme; a deme's tiles go to positions taken by an atomic add
+// on the list's count, so the order of the demes in a list varies from run
+// to run, which no result depends on (every tile writes only its own
+// outputs).  Phase 0, before encounter and survive: the survival tiles of
+// the census (tile 0 always: it records the census) and, for consumers,
+// their encounter tiles.  Phase 1, after compact: the carry tiles of the
+// carried survivors and the offspring tiles of the newborns, in the list of
+// the deme's kernel class.  Each phase clears the counts of the other
+// phase's lists, which it does not touch; all start at zero.
+__global__ void __launch_bounds__(kBlock) plan_tiles_kernel(const RepDesc *__restrict__ descs,
+                                                            const RepState *__restrict__ states, TileLists lists,
+                                                            int phase) {
+    __shared__ uint32_t base[2];
+    const uint32_t u = blockIdx.x;
+    const RepDesc &d = descs[u];
+    const RepState &st = states[u];
+    const uint32_t T = d.surv_tile;
+    uint32_t m0 = 0, m1 = 0;  // tiles of this deme in the phase's two lists
+    uint32_t *c0, *c1;
+    if (phase == 0) {
+        if (u == 0)
+            for (uint32_t q = threadIdx.x; q < 1u + lists.n_classes; q += kBlock) lists.counts[2u + q] = 0;
+        const uint32_t n = st.n[current_pair(st)];
+        m0 = n == 0 ? 1u : (n + T - 1u) / T;
+        if (d.regime == SPEGG_CONSUMER_RESOURCE && d.species == 1) m1 = (n + T - 1u) / T;
+        c0 = lists.counts;
+        c1 = lists.counts + 1;
+    } else {
+        if (u == 0 && threadIdx.x < 2) lists.counts[threadIdx.x] = 0;
+        const uint32_t nc = st.n_carry, nn = st.n[current_pair(st)] - nc;
+        if (d.regime == SPEGG_CONSUMER_RESOURCE || d.regime == SPEGG_PHYSIOLOGY) m0 = (nc + T - 1u) / T;
+        m1 = (nn + d.off_per_tile - 1u) / d.off_per_tile;
+        c0 = lists.counts + 2;
+        c1 = lists.counts + 3u + d.off_class;
+    }
+    // a census beyond the capacity is an impossible state (the kernels that
+    // find one report it): never write past the deme's share of a list
+    const uint32_t cap1 = phase == 0 ? d.surv_ntiles : d.off_ntiles;
+    m0 = m0 < d.surv_ntiles ? m0 : d.surv_ntiles;
+    m1 = m1 < cap1 ? m1 : cap1;
+    if (threadIdx.x == 0) {
+        base[0] = m0 ? atomicAdd(c0, m0) : 0u;
+        base[1] = m1 ? atomicAdd(c1, m1) : 0u;
+    }
+    __syncthreads();
+    if (phase == 0) {
+        for (uint32_t k = threadIdx.x; k < m0; k += kBlock) lists.surv[base[0] + k] = SurvTile{u, k * T};
+        for (uint32_t k = threadIdx.x; k < m1; k += kBlock) lists.enc[base[1] + k] = SurvTile{u, k * T};
+    } else {
+        for (uint32_t k = threadIdx.x; k < m0; k += kBlock) lists.carry[base[0] + k] = SurvTile{u, k * T};
+        OffTile *off = lists.off + d.off_list0 + base[1];
+        for (uint32_t k = threadIdx.x; k < m1; k += kBlock) off[k] = OffTile{u, k * d.off_per_tile};
     }
 }
 
 // ---------------------------------------------------------------- census
 
-// One block per replicate: sums of the tile partials of the newest census.
+// One block per deme: sums of the tile partials of the newest census, or of
+// the census itself (continuous alleles; carried survivors).
 __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restrict__ descs,
                                                         RepState *__restrict__ states,
                                                         const Partial *__restrict__ partials) {
@@ -2042,24 +2138,16 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
     if (!st.census_pending) return;  // uniform over the block
     const RepDesc &d = descs[rep];
     if (d.cont) {
-        // continuous alleles: the partials hold doubles; with carried
-        // survivors (physiology regime) the census is summed directly
+        // continuous alleles: the census is summed directly, in a fixed
+        // order (floating-point sums: neither the tiles that made the census
+        // nor the order of their atomics may change the result)
         double fa = 0.0, fb = 0.0;
-        if (d.regime == SPEGG_PHYSIOLOGY) {
-            const uint32_t par = current_pair(st), n = st.n[par];
-            const float *zf = reinterpret_cast<const float *>(d.z[st.t[par] & 1u]);
-            for (uint32_t k = threadIdx.x; k < n; k += kBlock) {
-                const double z = (double)zf[k];
-                fa += z;
-                fb += z * z;
-            }
-        } else {
-            const uint32_t used = (st.n[current_pair(st)] + d.off_per_tile - 1u) / d.off_per_tile;
-            for (uint32_t k = threadIdx.x; k < used; k += kBlock) {
-                const Partial p = partials[d.off_tile0 + k];
-                fa += __longlong_as_double(p.sum_z);
-                fb += __longlong_as_double((int64_t)p.sum_z2);
-            }
+        const uint32_t par = current_pair(st), n = st.n[par];
+        const float *zf = reinterpret_cast<const float *>(d.z[st.t[par] & 1u]);
+        for (uint32_t k = threadIdx.x; k < n; k += kBlock) {
+            const double z = (double)zf[k];
+            fa += z;
+            fb += z * z;
         }
         fa = wave_sum<double>(fa);
         fb = wave_sum<double>(fb);
@@ -2127,10 +2215,8 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
 // per thread), one consumer per thread: every capture offers its key (consumer, encounter) to the
 // captured resource, which keeps the lowest.  The keys were reset to ~0
 // when the resource census was written.
-__global__ void __launch_bounds__(kBlock) encounter_kernel(const RepDesc *__restrict__ descs,
-                                                           const RepState *__restrict__ states,
-                                                           const SurvTile *__restrict__ tiles) {
-    const SurvTile tile = tiles[blockIdx.x];
+__device__ __forceinline__ void encounter_tile(const RepDesc *__restrict__ descs, const RepState *__restrict__ states,
+                                               const SurvTile tile) {
     const uint32_t i = tile.start + threadIdx.x;  // tiles of kBlock adults in this regime
     const RepDesc &c = descs[tile.rep];
     const RepState &cs = states[tile.rep];
@@ -2147,14 +2233,22 @@ __global__ void __launch_bounds__(kBlock) encounter_kernel(const RepDesc *__rest
                       [&](uint32_t e, uint32_t tgt) { atomicMin(won + tgt, (unsigned long long)capture_key(i, e)); });
 }
 
+// Tiles [0, ntiles) of the plan, one block each, or the list_n occupied
+// tiles of this generation's list, walked by a resident grid.
+__global__ void __launch_bounds__(kBlock) encounter_kernel(const RepDesc *__restrict__ descs,
+                                                           const RepState *__restrict__ states,
+                                                           const SurvTile *__restrict__ tiles, uint32_t ntiles,
+                                                           const uint32_t *__restrict__ list_n) {
+    const uint32_t m = list_n ? *list_n : ntiles;
+    for (uint32_t v = blockIdx.x; v < m; v += gridDim.x) encounter_tile(descs, states, tiles[v]);
+}
+
 // One block per survival tile of a consumer-resource deme: survivors
 // S[k], k in the tile, move to position k of the next census with their
 // genome, phenotype and age class plus one (compact advanced the census and
 // recorded how many are carried).
-__global__ void __launch_bounds__(kBlock) carry_kernel(const RepDesc *__restrict__ descs,
-                                                       const RepState *__restrict__ states,
-                                                       const SurvTile *__restrict__ tiles) {
-    const SurvTile tile = tiles[blockIdx.x];
+__device__ __forceinline__ void carry_tile(const RepDesc *__restrict__ descs, const RepState *__restrict__ states,
+                                           const SurvTile tile) {
     const RepDesc &d = descs[tile.rep];
     const RepState &st = states[tile.rep];
     const uint32_t newest = current_pair(st);
@@ -2193,6 +2287,15 @@ __global__ void __launch_bounds__(kBlock) carry_kernel(const RepDesc *__restrict
             d.Y[cur ^ 1u][k] = d.Y[cur][from];
         }
     }
+}
+
+// Tiles as in encounter_kernel.
+__global__ void __launch_bounds__(kBlock) carry_kernel(const RepDesc *__restrict__ descs,
+                                                       const RepState *__restrict__ states,
+                                                       const SurvTile *__restrict__ tiles, uint32_t ntiles,
+                                                       const uint32_t *__restrict__ list_n) {
+    const uint32_t m = list_n ? *list_n : ntiles;
+    for (uint32_t v = blockIdx.x; v < m; v += gridDim.x) carry_tile(descs, states, tiles[v]);
 }
 
 __global__ void fill_u64_kernel(uint64_t *p, uint32_t n) {
@@ -2255,7 +2358,7 @@ inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kB
 
 // Every offspring kernel instance has this signature.
 using OffspringKernel = void (*)(const RepDesc *, const RepState *, const OffTile *, uint32_t, uint32_t, int,
-                                 Partial *, uint32_t, uint32_t, int);
+                                 Partial *, uint32_t, uint32_t, int, const uint32_t *);
 
 template <int G, int V, bool EXT>
 OffspringKernel offspring_kernel_gv(int nch) {
@@ -2339,6 +2442,17 @@ hipError_t launch_phenotypes(const RepDesc *d_desc, RepState *d_state, uint32_t 
 }
 
 hipError_t launch_survive(const SelArgs &a) {
+    if (a.list_n) {
+        if (a.items == 4)
+            hipLaunchKernelGGL(survive_list_kernel<4>, dim3(a.grid_survive), dim3(kBlock), 0, a.s, a.descs, a.states,
+                               a.tiles, a.list_n, a.counts, a.groups);
+        else if (a.items == 1)
+            hipLaunchKernelGGL(survive_list_kernel<1>, dim3(a.grid_survive), dim3(kBlock), 0, a.s, a.descs, a.states,
+                               a.tiles, a.list_n, a.counts, a.groups);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (a.items == 4)
         hipLaunchKernelGGL(survive_kernel<4>, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles,
                            a.counts, a.groups, a.single_deme);
@@ -2351,6 +2465,17 @@ hipError_t launch_survive(const SelArgs &a) {
 }
 
 hipError_t launch_compact(const SelArgs &a) {
+    if (a.list_n) {
+        if (a.items == 4)
+            hipLaunchKernelGGL(compact_list_kernel<4>, dim3(a.grid_compact), dim3(kBlock), 0, a.s, a.descs, a.states,
+                               a.tiles, a.list_n, a.counts, a.groups, a.trace);
+        else if (a.items == 1)
+            hipLaunchKernelGGL(compact_list_kernel<1>, dim3(a.grid_compact), dim3(kBlock), 0, a.s, a.descs, a.states,
+                               a.tiles, a.list_n, a.counts, a.groups, a.trace);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (a.items == 4)
         hipLaunchKernelGGL(compact_kernel<4>, dim3(a.ntiles), dim3(kBlock), 0, a.s, a.descs, a.states, a.tiles,
                            a.counts, a.groups, a.trace, a.single_deme);
@@ -2366,7 +2491,8 @@ hipError_t launch_offspring(OffShape shape, const OffArgs &a) {
     const OffspringKernel k = offspring_kernel_for(shape);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3(a.grid), dim3(kBlock), a.lds, a.s, a.descs, a.states, a.tiles, a.tile0, a.ntiles,
-                       a.single_deme, a.partials, shape.cont ? a.mask_words : a.plane_words, a.geo_words, a.trace);
+                       a.single_deme, a.partials, shape.cont ? a.mask_words : a.plane_words, a.geo_words, a.trace,
+                       a.list_n);
     return hipGetLastError();
 }
 
@@ -2383,17 +2509,37 @@ hipError_t launch_census(const RepDesc *descs, RepState *states, const Partial *
 }
 
 hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
-                            hipStream_t s) {
+                            const uint32_t *list_n, uint32_t grid, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(encounter_kernel, dim3(ntiles), dim3(kBlock), 0, s, descs, states, tiles);
+    const uint32_t blocks = list_n ? (grid < ntiles ? grid : ntiles) : ntiles;
+    hipLaunchKernelGGL(encounter_kernel, dim3(blocks), dim3(kBlock), 0, s, descs, states, tiles, ntiles, list_n);
     return hipGetLastError();
 }
 
 hipError_t launch_carry(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
-                        hipStream_t s) {
+                        const uint32_t *list_n, uint32_t grid, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(carry_kernel, dim3(ntiles), dim3(kBlock), 0, s, descs, states, tiles);
+    const uint32_t blocks = list_n ? (grid < ntiles ? grid : ntiles) : ntiles;
+    hipLaunchKernelGGL(carry_kernel, dim3(blocks), dim3(kBlock), 0, s, descs, states, tiles, ntiles, list_n);
     return hipGetLastError();
+}
+
+hipError_t launch_plan_tiles(const RepDesc *descs, const RepState *states, uint32_t n_demes, const TileLists &lists,
+                             int phase, hipStream_t s) {
+    if (n_demes == 0) return hipSuccess;
+    hipLaunchKernelGGL(plan_tiles_kernel, dim3(n_demes), dim3(kBlock), 0, s, descs, states, lists, phase);
+    return hipGetLastError();
+}
+
+hipError_t list_blocks_per_cu(int kind, int items, int *blocks) {
+    *blocks = 0;
+    const void *k = nullptr;
+    if (kind == 0) k = items == 4 ? (const void *)survive_list_kernel<4> : (const void *)survive_list_kernel<1>;
+    else if (kind == 1) k = items == 4 ? (const void *)compact_list_kernel<4> : (const void *)compact_list_kernel<1>;
+    else if (kind == 2) k = (const void *)encounter_kernel;
+    else if (kind == 3) k = (const void *)carry_kernel;
+    else return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, kBlock, 0);
 }
 
 hipError_t launch_fill_u64(uint64_t *p, uint32_t n, hipStream_t s) {

@@ -40,6 +40,7 @@ spegg_status fail(spegg_status st, const char *fmt, ...) {
 
 constexpr size_t kAlign = 256;
 constexpr uint32_t kMaxOffspringGrid = 1u << 18;  // blocks of one offspring launch of several demes (they loop over tiles)
+constexpr uint32_t kListGridFactor = 2;  // resident grids' worth of blocks of a launch that walks a tile list
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -84,6 +85,7 @@ struct DemePlan {
     uint32_t rep = 0, patch = 0, species = 0;
     uint32_t n0 = 0, cap = 0;
     uint32_t surv_tile0 = 0, surv_ntiles = 0, off_tile0 = 0, off_ntiles = 0;
+    uint32_t off_class = 0;  // index of the deme's offspring-kernel class
     uint32_t grp0 = 0, grp_n = 0;  // tile-group sums (two parities of grp_n records)
     size_t genome[2] = {0, 0}, z[2] = {0, 0}, fate = 0, S = 0, owner = 0, mom = 0, dad = 0, src = 0, sex[2] = {0, 0};
     size_t age[2] = {0, 0}, won = 0, intake = 0;
@@ -126,7 +128,38 @@ struct Plan {
     size_t surv_counts = 0, surv_groups = 0, partials = 0, total = 0;
     uint32_t n_groups = 0;  // tile-group records, both parities
     uint32_t surv_items = 1;  // adults per thread in survive and compact
+    // Lists of each generation's occupied tiles, walked by resident grids
+    // (populations of several demes whose censuses can fall below their
+    // capacities): their counts (3 + one per possible class) and arrays.
+    bool listed = false;
+    size_t list_counts_at = 0, list_surv_at = 0, list_enc_at = 0, list_carry_at = 0, list_off_at = 0;
+    uint32_t list_counts = 0;
+    uint32_t grid_survive = 0, grid_compact = 0, grid_encounter = 0, grid_carry = 0;
 };
+
+// Resident grids per list-walking launch (a tuning knob: results do not
+// depend on it); SPEGG_LIST_GRID_FACTOR overrides.
+uint32_t list_grid_factor() {
+    const char *e = std::getenv("SPEGG_LIST_GRID_FACTOR");
+    if (e) {
+        const long v = std::atol(e);
+        if (v >= 1 && v <= 64) return (uint32_t)v;
+    }
+    return kListGridFactor;
+}
+
+// Tile lists or one block per tile of the capacity: SPEGG_TILE_LISTS=0 or 1
+// forces the choice (results do not depend on it), else lists wherever a
+// population of several demes has one whose census can fall below its
+// capacity (any regime but Wright-Fisher at full capacity).
+bool want_tile_lists(const Plan &P, const spegg_rep_desc *reps) {
+    const char *e = std::getenv("SPEGG_TILE_LISTS");
+    if (e && (e[0] == '0' || e[0] == '1') && e[1] == 0) return e[0] == '1';
+    if (P.demes.size() < 2) return false;
+    for (const DemePlan &q : P.demes)
+        if (reps[q.rep].regime != SPEGG_WF || q.cap > q.n0) return true;
+    return false;
+}
 
 // Most blocks of one offspring launch; SPEGG_OFFSPRING_GRID overrides.
 uint32_t offspring_grid_cap() {
@@ -145,15 +178,32 @@ uint32_t offspring_grid_cap() {
 // modes), which the dispatcher balances block by block.  SPEGG_OFFSPRING_GRID,
 // when set, keeps the grids make_plan gave.
 hipError_t fit_offspring_grids(Plan &P, int device) {
-    if (std::getenv("SPEGG_OFFSPRING_GRID")) return hipSuccess;
     int cus = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
+    if (cus <= 0) cus = 1;
+    const uint32_t factor = list_grid_factor();
+    if (P.listed) {
+        // the list-walking launches: a few resident grids' worth of blocks
+        const auto fit = [&](int kind, uint32_t ntiles, uint32_t *grid) {
+            int per = 0;
+            const hipError_t r = list_blocks_per_cu(kind, (int)P.surv_items, &per);
+            const uint64_t g = (uint64_t)(per > 0 ? per : 1) * (uint64_t)cus * factor;
+            *grid = ntiles == 0 ? 0u : ntiles < g ? ntiles : (uint32_t)g;
+            return r;
+        };
+        const uint32_t ns = (uint32_t)P.surv_tiles.size();
+        if ((e = fit(0, ns, &P.grid_survive)) != hipSuccess) return e;
+        if ((e = fit(1, ns, &P.grid_compact)) != hipSuccess) return e;
+        if ((e = fit(2, (uint32_t)P.enc_tiles.size(), &P.grid_encounter)) != hipSuccess) return e;
+        if ((e = fit(3, (uint32_t)P.carry_tiles.size(), &P.grid_carry)) != hipSuccess) return e;
+    }
+    if (std::getenv("SPEGG_OFFSPRING_GRID")) return hipSuccess;
     for (OffClass &c : P.classes) {
-        if (c.single_deme < 0) continue;
+        if (c.single_deme < 0 && !P.listed) continue;
         int per = 0;
         if ((e = offspring_blocks_per_cu(c.shape, c.lds, &per)) != hipSuccess) return e;
-        const uint64_t resident = (uint64_t)(per > 0 ? per : 1) * (uint64_t)(cus > 0 ? cus : 1);
+        const uint64_t resident = (uint64_t)(per > 0 ? per : 1) * (uint64_t)cus * (c.single_deme < 0 ? factor : 1u);
         c.grid = c.ntiles < resident ? c.ntiles : (uint32_t)resident;
     }
     return hipSuccess;
@@ -377,7 +427,8 @@ spegg_status build_rep(const spegg_rep_desc &d, uint32_t i, RepPlan &p, const Gc
     return SPEGG_OK;
 }
 
-spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const GcapMap *gcaps = nullptr) {
+spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const GcapMap *gcaps = nullptr,
+                       int listed = -1) {
     if (!reps || n == 0) return fail(SPEGG_E_INVALID, "no replicates");
     P.reps.resize(n);
     uint64_t n_demes = 0;
@@ -440,6 +491,7 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
             if (!same_shape(p.shape, sh)) continue;
             q.off_tile0 = (uint32_t)P.off_tiles.size();
             q.off_ntiles = (q.cap + p.opt - 1) / p.opt;
+            q.off_class = (uint32_t)P.classes.size();
             for (uint32_t k = 0; k < q.off_ntiles; ++k) P.off_tiles.push_back({u, k * p.opt});
             if (p.W > maxW) maxW = p.W;
             const uint32_t Wb = (reps[q.rep].n_loci + 31u) / 32u;
@@ -493,6 +545,16 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
     P.surv_counts = cv.take(sizeof(SurvCount) * P.surv_tiles.size());
     P.surv_groups = cv.take(sizeof(SurvGroup) * (P.n_groups ? P.n_groups : 1u));
     P.partials = cv.take(sizeof(Partial) * max_off_tiles);
+    P.listed = listed < 0 ? want_tile_lists(P, reps) : listed != 0;
+    if (P.listed) {
+        // room for one class per deme, whatever shapes a re-plan picks
+        P.list_counts = 3u + (uint32_t)P.demes.size();
+        P.list_counts_at = cv.take(sizeof(uint32_t) * P.list_counts);
+        P.list_surv_at = cv.take(sizeof(SurvTile) * P.surv_tiles.size());
+        P.list_enc_at = cv.take(sizeof(SurvTile) * P.enc_tiles.size());
+        P.list_carry_at = cv.take(sizeof(SurvTile) * P.carry_tiles.size());
+        P.list_off_at = cv.take(sizeof(OffTile) * max_off_tiles);
+    }
     for (DemePlan &q : P.demes) {
         const RepPlan &p = P.reps[q.rep];
         const size_t cap = q.cap;
@@ -611,6 +673,12 @@ struct spegg_pop {
     SurvCount *d_surv_counts() { return at<SurvCount>(base, plan.surv_counts); }
     SurvGroup *d_surv_groups() { return at<SurvGroup>(base, plan.surv_groups); }
     Partial *d_partials() { return at<Partial>(base, plan.partials); }
+    uint32_t *d_list_counts() { return at<uint32_t>(base, plan.list_counts_at); }
+    TileLists lists() {
+        return TileLists{at<SurvTile>(base, plan.list_surv_at), at<SurvTile>(base, plan.list_enc_at),
+                         at<SurvTile>(base, plan.list_carry_at), at<OffTile>(base, plan.list_off_at),
+                         d_list_counts(), (uint32_t)plan.classes.size()};
+    }
 };
 
 namespace {
@@ -783,29 +851,43 @@ hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
     const int trace = pop->trace ? 1 : 0;
     const SurvTile *enc_tiles = at<SurvTile>(pop->base, P.enc_tiles_at);
     const SurvTile *carry_tiles = at<SurvTile>(pop->base, P.carry_tiles_at);
+    // listed: every launch walks this generation's lists of occupied tiles
+    const TileLists lists = pop->lists();
+    const uint32_t *ln = P.listed ? lists.counts : nullptr;
+    if (P.listed) {
+        enc_tiles = lists.enc;
+        carry_tiles = lists.carry;
+    }
     for (uint32_t g = 0; g < n; ++g) {
-        const SelArgs sa{pop->d_descs(), pop->d_states(), pop->d_surv_tiles(), pop->d_surv_counts(),
-                         pop->d_surv_groups(), ns_tiles, trace, pop->n_demes == 1 ? 0 : -1, (int)P.surv_items,
-                         pop->stream};
+        SelArgs sa{pop->d_descs(), pop->d_states(), P.listed ? lists.surv : pop->d_surv_tiles(), pop->d_surv_counts(),
+                   pop->d_surv_groups(), ns_tiles, trace, pop->n_demes == 1 ? 0 : -1, (int)P.surv_items,
+                   pop->stream};
+        sa.list_n = ln;
+        sa.grid_survive = P.grid_survive;
+        sa.grid_compact = P.grid_compact;
         hipError_t e = hipSuccess;
-        if (!P.enc_tiles.empty())
+        if (P.listed) e = launch_plan_tiles(pop->d_descs(), pop->d_states(), pop->n_demes, lists, 0, pop->stream);
+        if (e == hipSuccess && !P.enc_tiles.empty())
             e = timed(pop, SPEGG_KERNEL_ENCOUNTER, [&] {
                 return launch_encounter(pop->d_descs(), pop->d_states(), enc_tiles, (uint32_t)P.enc_tiles.size(),
-                                        pop->stream);
+                                        ln ? ln + 1 : nullptr, P.grid_encounter, pop->stream);
             });
         if (e == hipSuccess) e = timed(pop, SPEGG_KERNEL_SURVIVE, [&] { return launch_survive(sa); });
         if (e == hipSuccess) e = timed(pop, SPEGG_KERNEL_COMPACT, [&] { return launch_compact(sa); });
+        if (e == hipSuccess && P.listed)
+            e = launch_plan_tiles(pop->d_descs(), pop->d_states(), pop->n_demes, lists, 1, pop->stream);
         if (e == hipSuccess && !P.carry_tiles.empty())
             e = timed(pop, SPEGG_KERNEL_CARRY, [&] {
                 return launch_carry(pop->d_descs(), pop->d_states(), carry_tiles, (uint32_t)P.carry_tiles.size(),
-                                    pop->stream);
+                                    ln ? ln + 2 : nullptr, P.grid_carry, pop->stream);
             });
         for (size_t ci = 0; ci < P.classes.size(); ++ci) {
             const OffClass &c = P.classes[ci];
             if (e != hipSuccess) return e;
-            const OffArgs oa{pop->d_descs(), pop->d_states(), pop->d_off_tiles(), c.tile0, c.ntiles, c.single_deme,
-                             pop->d_partials(), c.plane_words, c.geo_words, c.mask_words, c.grid, c.lds, trace,
-                             pop->stream};
+            OffArgs oa{pop->d_descs(), pop->d_states(), P.listed ? lists.off : pop->d_off_tiles(), c.tile0, c.ntiles,
+                       c.single_deme, pop->d_partials(), c.plane_words, c.geo_words, c.mask_words, c.grid, c.lds,
+                       trace, pop->stream};
+            oa.list_n = ln ? ln + 3 + ci : nullptr;
             e = timed(pop, SPEGG_KERNEL_OFFSPRING, [&] { return launch_offspring(c.shape, oa); }, (int)ci);
         }
         if (e != hipSuccess) return e;
@@ -949,6 +1031,8 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         h.off_tile0 = q.off_tile0;
         h.off_ntiles = q.off_ntiles;
         h.off_per_tile = p.opt;
+        h.off_class = q.off_class;
+        h.off_list0 = P.classes[q.off_class].tile0;
         h.geo_scale = p.mode == kModeSkip ? (float)(1.0 / std::log2(1.0 - d.r)) : 0.0f;
         h.K = d.K;
         h.lambda = d.fecundity;
@@ -1051,6 +1135,7 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         pop->dev_descs[u] = h;
         std::memcpy(img + P.descs + u * sizeof(RepDesc), &h, sizeof h);
         RepState s0 = initial_state(0, q.n0);
+        s0.census_pending = p.cont && q.n0 > 0;  // continuous alleles: sums folded on demand
         if (p.phys) {
             s0.R[0] = d.physiology->R0[0];
             s0.R[1] = d.physiology->R0[1];
@@ -1092,6 +1177,8 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
     if (P.n_groups)
         e = launch_fill_u32((uint32_t *)pop->d_surv_groups(), (size_t)P.n_groups * sizeof(SurvGroup) / sizeof(uint32_t),
                             pop->stream);
+    // so do the counts of the tile lists
+    if (e == hipSuccess && P.listed) e = launch_fill_u32(pop->d_list_counts(), P.list_counts, pop->stream);
     if (e != hipSuccess) {
         delete pop;
         return fail(SPEGG_E_DEVICE, "tile groups: %s", hipGetErrorString(e));
@@ -1354,6 +1441,7 @@ spegg_status spegg_write_alleles(spegg_pop *pop, uint32_t rep, uint32_t patch, c
     if ((st = sync_stream(pop)) != SPEGG_OK) return st;
     const uint32_t buf = generation & 1u;
     RepState s0 = initial_state(generation, n);
+    s0.census_pending = n > 0;  // the census sums are folded on demand
     if (h.X[0]) {
         s0.R[0] = cur_state.R[0];
         s0.R[1] = cur_state.R[1];
@@ -1642,7 +1730,7 @@ namespace {
 // not move: the carve does not depend on the shapes.
 spegg_status apply_shapes(spegg_pop *pop) {
     Plan P2;
-    spegg_status st = make_plan(pop->descs.data(), pop->n_reps, P2, &pop->gcaps);
+    spegg_status st = make_plan(pop->descs.data(), pop->n_reps, P2, &pop->gcaps, pop->plan.listed ? 1 : 0);
     if (st != SPEGG_OK) return st;
     const hipError_t eg = fit_offspring_grids(P2, pop->device);
     if (eg != hipSuccess) return device_fail(pop, eg, "autotune: grids");
@@ -1654,6 +1742,8 @@ spegg_status apply_shapes(spegg_pop *pop) {
         h.off_tile0 = P2.demes[u].off_tile0;
         h.off_ntiles = P2.demes[u].off_ntiles;
         h.off_per_tile = P2.reps[P2.demes[u].rep].opt;
+        h.off_class = P2.demes[u].off_class;
+        h.off_list0 = P2.classes[h.off_class].tile0;
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(pop->d_descs(), pop->dev_descs.data(), sizeof(RepDesc) * pop->n_demes,

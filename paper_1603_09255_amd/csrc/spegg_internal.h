@@ -99,6 +99,7 @@ struct RepDesc {
     uint32_t surv_tile;  // adults per survival tile of the population (kBlock x adults per thread)
     uint32_t grp0, grp_n;  // the deme's tile groups: first record, records per parity (0: one group suffices)
     uint32_t off_tile0, off_ntiles, off_per_tile;  // offspring tiles: global index of the first
+    uint32_t off_class, off_list0;  // kernel class of the deme and the start of that class's tile list
     float geo_scale;     // 1 / log2(1 - r): first guess of a geometric gap (checked against geo)
     double K, lambda;    // Beverton-Holt density factor; 0 < K enables it
     uint64_t mig_T;      // a newborn is a migrant when MIGRATE word 0 < mig_T; 0: no migration
@@ -305,6 +306,21 @@ struct SelArgs {
     int single_deme;  // >= 0: the population's only deme, whose tiles are implicit
     int items;        // adults per thread (1 or 4)
     hipStream_t s;
+    // non-null: tiles is this generation's list of occupied tiles, list_n
+    // its length on the device, walked by grid blocks (survive, compact)
+    const uint32_t *list_n = nullptr;
+    uint32_t grid_survive = 0, grid_compact = 0;
+};
+
+// This generation's lists of occupied tiles (plan_tiles_kernel), in device
+// memory: counts[0] survival tiles, [1] encounter tiles, [2] carry tiles,
+// [3 + c] offspring tiles of kernel class c, whose list starts at off +
+// the class's first tile index (the class's share of the plan's tiles).
+struct TileLists {
+    SurvTile *surv, *enc, *carry;
+    OffTile *off;
+    uint32_t *counts;
+    uint32_t n_classes;
 };
 
 struct OffArgs {
@@ -321,6 +337,7 @@ struct OffArgs {
     size_t lds;
     int trace;
     hipStream_t s;
+    const uint32_t *list_n = nullptr;  // non-null: tiles + tile0 is the class's list of occupied tiles
 };
 
 // Host-side launchers (kernels.hip).
@@ -339,13 +356,23 @@ hipError_t launch_offspring(OffShape shape, const OffArgs &a);
 // lds bytes of dynamic LDS (HIP's occupancy calculation).
 hipError_t offspring_blocks_per_cu(OffShape shape, size_t lds, int *blocks);
 // Consumer-resource regime (one adult per thread in the survival tiles):
-// encounters and captures of the consumers, one block per tile.
+// encounters and captures of the consumers, one block per tile; with
+// list_n non-null, tiles is a list of list_n tiles on the device walked by
+// grid blocks.
 hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
-                            hipStream_t s);
-// Consumer-resource regime: survivors into the next census (one block per
-// survival tile of the regime's demes).
+                            const uint32_t *list_n, uint32_t grid, hipStream_t s);
+// Consumer-resource and physiology regimes: survivors into the next census
+// (one block per survival tile of the regime's demes, or a list as above).
 hipError_t launch_carry(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
-                        hipStream_t s);
+                        const uint32_t *list_n, uint32_t grid, hipStream_t s);
+// The lists of occupied tiles of phase 0 (before encounter and survive) or
+// phase 1 (after compact), one block per deme.
+hipError_t launch_plan_tiles(const RepDesc *descs, const RepState *states, uint32_t n_demes, const TileLists &lists,
+                             int phase, hipStream_t s);
+// Blocks per compute unit of the list-walking kernels (HIP's occupancy
+// calculation): kind 0 survive, 1 compact (items adults per thread), 2
+// encounter, 3 carry.
+hipError_t list_blocks_per_cu(int kind, int items, int *blocks);
 // Fill n words of a uint64 array with ~0 (capture keys before the first
 // generation) and n bytes with 0 (ages).
 hipError_t launch_fill_u64(uint64_t *p, uint32_t n, hipStream_t s);
