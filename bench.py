@@ -40,14 +40,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # taken with (lanes-per-gamete cap by genome words W); otherwise the
 # traffic figure is null until re-measured.
 MEASURED_TRAFFIC = {}
-DEVICE_SOURCES = ("kernels.hip", "philox.h", "spegg_internal.h")
+# the device code and the compiler flags it is built with
+DEVICE_SOURCES = ("csrc/kernels.hip", "csrc/philox.h", "csrc/spegg_internal.h", "build.py")
 
 
 def device_sources_sha():
     import hashlib
     h = hashlib.sha256()
     for name in DEVICE_SOURCES:
-        with open(os.path.join(ROOT, "paper_1603_09255_amd", "csrc", name), "rb") as f:
+        with open(os.path.join(ROOT, "paper_1603_09255_amd", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 

@@ -19,6 +19,11 @@ HIPCC_FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no hoisting of loop-invariant machine instructions: it kept math-library
+    # constants and lane-index values live across whole tile loops (e.g. 175
+    # instead of 100 VGPRs in the continuous-allele offspring kernel, half the
+    # waves per SIMD); measured faster on every workload without it
+    "-mllvm", "-disable-machine-licm",
     "-Wall",
 ]
 
