@@ -39,7 +39,16 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # device sources with its SHA-256 prefix and the offspring shapes it was
 # taken with (lanes-per-gamete cap by genome words W); otherwise the
 # traffic figure is null until re-measured.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # offspring L = 1024 class of the 4096-replicate table: FETCH 7123623 KiB x 2.00 + WRITE 11728834 KiB x 1.00
+    # per launch over 33832793 newborns (profiles/offspring_batched_table_kernel_trace.md)
+    "batched": {"device_sources_sha256_16": "5181600b8d606d87", "lanes_per_gamete_by_W": {2: 1, 8: 1, 32: 4},
+                "bytes_per_newborn": 786.2},
+    # continuous alleles, N = 1e5, L = 256: FETCH 202977 KiB x 2.00 + WRITE 200434 KiB x 1.00 per launch
+    # (profiles/offspring_continuous_kernel_trace.md)
+    "continuous": {"device_sources_sha256_16": "5181600b8d606d87", "lanes_per_gamete_by_W": {0x80000100: 8},
+                   "bytes_per_newborn": 6209.4},
+}
 # the device code and the compiler flags it is built with
 DEVICE_SOURCES = ("csrc/kernels.hip", "csrc/philox.h", "csrc/spegg_internal.h", "build.py")
 
@@ -419,7 +428,9 @@ def bench_continuous(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": (None if measured_traffic("continuous", tuned) is None else
+                        measured_traffic("continuous", tuned) * updates_b / L / max(off_n, 1)),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 counters, scaled)",
             "bytes_per_update": cont_bytes_per_update(L),
             "avg_launch_us": avg_launch_s * 1e6,
             "launches": off_n,
