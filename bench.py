@@ -750,14 +750,22 @@ def bench_ecology(args):
     print(json.dumps(out), flush=True)
 
 
-def phys_bytes_per_individual(L):
+def phys_bytes_per_individual():
     """Compulsory HBM bytes of one time step per individual of the
     physiology regime: survive reads X, Y (doubles), the phenotype (float)
     and the sex and writes X, Y, the gonads and the fate (47 B); compact
     reads the fate and writes a survivor index (6 B); a survivor moves to the
-    next census with its genome (2 x 4 L bytes read and written) and its
-    masses, phenotype and sex (2 x 21 B)."""
-    return 47.0 + 6.0 + 2.0 * 8.0 * L + 42.0
+    next census with its masses, phenotype and sex (2 x 21 B).  Its allelic
+    values need not move (the library keeps them in place)."""
+    return 47.0 + 6.0 + 42.0
+
+
+def phys_bytes_per_recruit(L):
+    """Compulsory bytes of one recruit: its parents' allelic values read
+    (2 x 2 x 4 L bytes, each gamete taking every locus from one of a
+    parent's two haplotypes: 8 B per locus) and its own written (8 L), its
+    masses, phenotype and sex written (21 B)."""
+    return 16.0 * L + 21.0
 
 
 def bench_physiology(args):
@@ -787,16 +795,25 @@ def bench_physiology(args):
     inds = updates / L  # individual-steps
     value = updates / elapsed
     log(f"bench: {updates} updates ({inds:.4g} individual-steps) in {elapsed:.3f} s ({value:.4g}/s)")
+    # second pass, step by step: kernel times from events, and the recruits
+    # per individual-step (census minus survivors after each step)
     pop.set_timing(["survive", "compact", "offspring", "carry"])
     pop.kernel_times()
     gens_b = min(args.steps, 50)
-    pop.step(gens_b)
+    recruits, inds_b = 0, 0
+    for _ in range(gens_b):
+        pop.step(1)
+        for r in pop.stats():
+            recruits += r["n"] - r["n_survivors"]
+            inds_b += r["n"]
     kt = pop.kernel_times()
     pop.set_timing([])
     per_kind_us = {k: v[0] * 1e3 / gens_b for k, v in kt.items() if v[1]}
     log("bench: per step: " + ", ".join(f"{k} {v:.0f} us" for k, v in per_kind_us.items()))
     pop.close()
-    gen_bytes = inds * phys_bytes_per_individual(L)
+    recruit_rate = recruits / max(inds_b, 1)
+    bytes_per_ind = phys_bytes_per_individual() + recruit_rate * phys_bytes_per_recruit(L)
+    gen_bytes = inds * bytes_per_ind
     achieved = gen_bytes / elapsed / 1e9
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -812,7 +829,10 @@ def bench_physiology(args):
                    "kernel_us_per_step": per_kind_us},
         "roofline": {"bound": "hbm", "kernel": "whole time step (survive, compact, carry, offspring)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_individual_step": phys_bytes_per_individual(L),
+                     "traffic": None, "bytes_per_individual_step": bytes_per_ind,
+                     "bytes_model": "95 B per individual-step (survive 47, compact 6, survivors' masses, phenotype "
+                                    "and sex moved 42) + (16 L + 21) B per recruit, recruits per individual-step "
+                                    f"{recruit_rate:.4g} from the second pass",
                      "timing": "wall clock of the timed steps; kernel times from HIP events in a second pass"},
         "context": {"paper": "the paper reports more than 200x over one CPU core for its size-structured case "
                              "study on one commodity GPGPU (main text, Fig. 2B), hardware and parameters other "

@@ -596,9 +596,15 @@ __global__ void __launch_bounds__(kBlock) create_kernel(const RepDesc *__restric
     if (d.cont) {
         // Continuous alleles: allele (h, l) is N(a0, s0^2) from INIT block
         // h L + l of the individual, rounded to float; the pad loci are 0.
-        // The genetic value is summed locus by locus in order.
+        // The genetic value is summed locus by locus in order.  Physiology
+        // regime: founder i in storage slot i, the free stack holding the
+        // slots above n0 with n0 on top.
         for (uint32_t slot = threadIdx.x; slot < d.surv_tile; slot += kBlock) {
             const uint32_t i = tile.start + slot;
+            if (d.gfree && i < d.cap) {
+                if (i < n0) gstore(d.gslot[0] + i, i);
+                else gstore(d.gfree + (d.cap - 1u - i), i);
+            }
             if (i >= n0) continue;
             float *g = reinterpret_cast<float *>(d.genome[0] + (size_t)i * per);
             double gv = 0.0;
@@ -668,7 +674,8 @@ __global__ void __launch_bounds__(kBlock) phenotype_kernel(const RepDesc *__rest
     if (d.cont) {
         // continuous alleles written by the caller: founders of generation gen
         if (i < n) {
-            const float *g = reinterpret_cast<const float *>(d.genome[buf] + (size_t)i * 2u * d.W);
+            // physiology regime: written individual i sits in storage slot i
+            const float *g = reinterpret_cast<const float *>(d.genome[d.gfree ? 0u : buf] + (size_t)i * 2u * d.W);
             double gv = 0.0;
             for (uint32_t l = 0; l < d.L; ++l) gv += 0.5 * ((double)g[l] + (double)g[d.W + l]);
             const Rng rng{d.key0, d.key1, d.c3};
@@ -1164,6 +1171,10 @@ __device__ __forceinline__ void compact_tile(const RepDesc *__restrict__ descs, 
             const uint32_t nb = want > room ? room : (uint32_t)want;
             st.truncated += want - nb;
             nn = ns + nb;
+            // free storage slots: the recruits pop the nb below the top
+            const uint32_t top = st.gfree_n[t & 1u] + (n - ns);
+            st.gfree_top = top;
+            st.gfree_n[(t + 1u) & 1u] = top - nb;
         } else if (ns + nb_alive == 0 || (d.sexes && (sum_f == 0 || sum_f == ns))) {
             nn = 0;  // no survivor, or (separate sexes) no surviving female or male
         } else if (d.regime == SPEGG_WF) {
@@ -1209,6 +1220,12 @@ __device__ __forceinline__ void compact_tile(const RepDesc *__restrict__ descs, 
         if (fate[q] >> 15) {
             if (spos < d.cap) gstore(d.S + spos, i0 + q);
             ++spos;
+        } else if (d.gfree && i0 + q < n) {
+            // physiology regime: the storage slot of the dead onto the free
+            // stack, above the slots already free, in census order
+            const uint32_t at = st.gfree_n[t & 1u] + (i0 + q - spos);  // above the free ones and the dead before
+            if (at < d.cap) gstore(d.gfree + at, gload(d.gslot[t & 1u] + i0 + q));
+            else atomicOr(&st.error, 1u);  // free and living slots exceed the capacity: impossible
         }
         if (d.regime != SPEGG_WF) {  // mothers with offspring counts own their slots
             const uint32_t kids = fate[q] & 0x7FFFu;
@@ -1887,8 +1904,25 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
                 gstore(d.X[cur ^ 1u] + base + j, om);
                 gstore(d.Y[cur ^ 1u] + base + j, d.qJ * om);
             }
-            const uint32_t *src = sd_src.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
-            uint32_t *dst = d.genome[cur ^ 1u] + (size_t)(base + j) * 2u * W + (size_t)half * W;
+            const uint32_t *src;
+            uint32_t *dst;
+            if (d.gfree) {  // physiology regime: values by storage slot, the recruit's popped off the free stack
+                const uint32_t top = st.gfree_top;
+                const bool popped = j < top && top <= d.cap;  // compact left room for every recruit
+                uint32_t pslot = gload(d.gslot[cur] + (half ? dad : mom));
+                uint32_t nslot = popped ? gload(d.gfree + (top - 1u - j)) : 0u;
+                if (!popped || pslot >= d.cap || nslot >= d.cap) {  // a broken slot map: flagged, kept in bounds
+                    atomicOr(const_cast<uint32_t *>(&st.error), 1u);
+                    pslot = pslot < d.cap ? pslot : 0u;
+                    nslot = nslot < d.cap ? nslot : 0u;
+                }
+                if (lane == 0) gstore(d.gslot[cur ^ 1u] + base + j, nslot);
+                src = d.genome[0] + (size_t)pslot * 2u * W;
+                dst = d.genome[0] + (size_t)nslot * 2u * W + (size_t)half * W;
+            } else {
+                src = sd_src.genome[cur] + (size_t)(half ? dad : mom) * 2u * W;
+                dst = d.genome[cur ^ 1u] + (size_t)(base + j) * 2u * W + (size_t)half * W;
+            }
             // every lane takes part in each cross-lane read, then selects
             const uint32_t phase_m = draw(1, 0), phase_p = draw(2, 0);
             const uint32_t xk_m = draw(3, 0), xk_p = draw(4, 0);
@@ -2257,7 +2291,12 @@ __device__ __forceinline__ void carry_tile(const RepDesc *__restrict__ descs, co
     const uint32_t cur = (st.t[newest] - 1u) & 1u;
     const uint32_t cnt = nc - tile.start < d.surv_tile ? nc - tile.start : d.surv_tile;
     const uint32_t per = 2u * d.W;
-    if ((per & 3u) == 0) {  // 16-byte copies
+    if (d.gfree) {  // physiology regime: the values stay in their slots, the slot moves
+        for (uint32_t idx = threadIdx.x; idx < cnt; idx += kBlock) {
+            const uint32_t k = tile.start + idx;
+            d.gslot[cur ^ 1u][k] = d.gslot[cur][d.S[k]];
+        }
+    } else if ((per & 3u) == 0) {  // 16-byte copies
         const uint32_t per4 = per / 4u;
         const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(d.genome[cur]);
         uint4 *__restrict__ dst = reinterpret_cast<uint4 *>(d.genome[cur ^ 1u]);

@@ -40,7 +40,7 @@ spegg_status fail(spegg_status st, const char *fmt, ...) {
 
 constexpr size_t kAlign = 256;
 constexpr uint32_t kMaxOffspringGrid = 1u << 18;  // blocks of one offspring launch of several demes (they loop over tiles)
-constexpr uint32_t kListGridFactor = 2;  // resident grids' worth of blocks of a launch that walks a tile list
+constexpr uint32_t kListGridFactor = 8;  // resident grids' worth of blocks of a launch that walks a tile list
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -90,6 +90,7 @@ struct DemePlan {
     size_t genome[2] = {0, 0}, z[2] = {0, 0}, fate = 0, S = 0, owner = 0, mom = 0, dad = 0, src = 0, sex[2] = {0, 0};
     size_t age[2] = {0, 0}, won = 0, intake = 0;
     size_t X[2] = {0, 0}, Y[2] = {0, 0}, G = 0, ptiles = 0;  // physiology regime
+    size_t gslot[2] = {0, 0}, gfree = 0;                      // physiology regime: genome slots
 };
 
 // Demes sharing one offspring-kernel shape.
@@ -582,6 +583,9 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
             q.Y[1] = cv.take(cap * sizeof(double));
             q.G = cv.take(cap * sizeof(double));
             q.ptiles = cv.take(q.surv_ntiles * sizeof(PhysTile));
+            q.gslot[0] = cv.take(cap * sizeof(uint32_t));
+            q.gslot[1] = cv.take(cap * sizeof(uint32_t));
+            q.gfree = cv.take(cap * sizeof(uint32_t));
         }
         if (p.cr) {
             q.age[0] = cv.take(zcap);  // padded to whole tiles: read 4 at a time
@@ -1111,6 +1115,9 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
             }
             h.G = at<double>(pop->base, q.G);
             h.ptiles = at<PhysTile>(pop->base, q.ptiles);
+            h.gslot[0] = at<uint32_t>(pop->base, q.gslot[0]);
+            h.gslot[1] = at<uint32_t>(pop->base, q.gslot[1]);
+            h.gfree = at<uint32_t>(pop->base, q.gfree);
         }
         h.species = q.species;
         if (p.cr) {
@@ -1137,6 +1144,7 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         RepState s0 = initial_state(0, q.n0);
         s0.census_pending = p.cont && q.n0 > 0;  // continuous alleles: sums folded on demand
         if (p.phys) {
+            s0.gfree_n[0] = q.cap - q.n0;  // create_kernel fills the slot map and the free stack
             s0.R[0] = d.physiology->R0[0];
             s0.R[1] = d.physiology->R0[1];
         }
@@ -1406,14 +1414,28 @@ spegg_status spegg_read_alleles(spegg_pop *pop, uint32_t rep, uint32_t patch, fl
     if (values == 0) return SPEGG_OK;
     if (!host_values || n_values < values)
         return fail(SPEGG_E_INVALID, "read_alleles: need room for %zu values, have %zu", values, n_values);
-    // the device rows are W >= L floats (the pad zero): copy, then drop the pad
-    std::vector<float> rows((size_t)n * 2u * h.W);
-    hipError_t e = hipMemcpyAsync(rows.data(), h.genome[t & 1u], rows.size() * sizeof(float), hipMemcpyDeviceToHost,
-                                  pop->stream);
+    // the device rows are W >= L floats (the pad zero): copy, then drop the
+    // pad.  Physiology regime: rows by storage slot, through the census's
+    // slot map.
+    const bool slots = h.gfree != nullptr;
+    std::vector<uint32_t> slot(slots ? n : 0);
+    std::vector<float> rows((size_t)(slots ? h.cap : n) * 2u * h.W);
+    hipError_t e = hipMemcpyAsync(rows.data(), h.genome[slots ? 0u : t & 1u], rows.size() * sizeof(float),
+                                  hipMemcpyDeviceToHost, pop->stream);
+    if (e == hipSuccess && slots)
+        e = hipMemcpyAsync(slot.data(), h.gslot[t & 1u], n * sizeof(uint32_t), hipMemcpyDeviceToHost, pop->stream);
     if (e != hipSuccess) return device_fail(pop, e, "hipMemcpyAsync(alleles)");
     if ((st = sync_stream(pop)) != SPEGG_OK) return st;
-    for (size_t r = 0; r < (size_t)n * 2u; ++r)
-        std::memcpy(host_values + r * h.L, rows.data() + r * h.W, sizeof(float) * h.L);
+    for (size_t i = 0; i < n; ++i) {
+        const size_t from = slots ? slot[i] : i;
+        if (from >= h.cap) {
+            pop->errored = true;
+            return fail(SPEGG_E_DEVICE, "read_alleles: individual %zu in storage slot %zu beyond capacity %u", i, from,
+                        h.cap);
+        }
+        for (size_t hh = 0; hh < 2; ++hh)
+            std::memcpy(host_values + (2u * i + hh) * h.L, rows.data() + (2u * from + hh) * h.W, sizeof(float) * h.L);
+    }
     return SPEGG_OK;
 }
 
@@ -1446,9 +1468,26 @@ spegg_status spegg_write_alleles(spegg_pop *pop, uint32_t rep, uint32_t patch, c
         s0.R[0] = cur_state.R[0];
         s0.R[1] = cur_state.R[1];
     }
+    // physiology regime: individual i in storage slot i, the free stack
+    // holding the slots above n with n on top
+    const bool slots = h.gfree != nullptr;
+    std::vector<uint32_t> slot_map, free_stack;
+    if (slots) {
+        s0.gfree_n[buf] = h.cap - n;
+        slot_map.resize(n);
+        for (uint32_t i = 0; i < n; ++i) slot_map[i] = i;
+        free_stack.resize(h.cap - n);
+        for (uint32_t k = 0; k < h.cap - n; ++k) free_stack[k] = h.cap - 1u - k;
+    }
     hipError_t e = hipSuccess;
     if (n > 0)
-        e = hipMemcpyAsync(h.genome[buf], rows.data(), rows.size() * sizeof(float), hipMemcpyHostToDevice, pop->stream);
+        e = hipMemcpyAsync(h.genome[slots ? 0u : buf], rows.data(), rows.size() * sizeof(float), hipMemcpyHostToDevice,
+                           pop->stream);
+    if (e == hipSuccess && slots && n > 0)
+        e = hipMemcpyAsync(h.gslot[buf], slot_map.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, pop->stream);
+    if (e == hipSuccess && slots && h.cap > n)
+        e = hipMemcpyAsync(h.gfree, free_stack.data(), free_stack.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           pop->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(pop->d_states() + u, &s0, sizeof s0, hipMemcpyHostToDevice, pop->stream);
     if (e == hipSuccess) e = launch_phenotypes(pop->d_descs() + u, pop->d_states() + u, n, buf, generation, pop->stream);
     if (e == hipSuccess && h.grp_n)

@@ -158,6 +158,12 @@ struct RepDesc {
     double kappa, qJ, qA, beta1, beta2, beta_s, maturity, v_f, v_m, kappa1, kappa2, kappa3;
     uint32_t breed_every;
     double *X[2], *Y[2];      // irreversible and reversible mass, ping-pong with the genomes
+    // Physiology regime: allelic values stay in place for an individual's
+    // life.  genome[0] holds them by storage slot; gslot[t & 1][k] is the
+    // slot of census position k of generation t; gfree is a stack of the
+    // free slots (the dead's, and those never used), recruits pop it.
+    uint32_t *gslot[2];
+    uint32_t *gfree;
     double *G;                // gonads set aside at this step's growth
     struct PhysTile *ptiles;  // per survival tile: consumption, eggs and the largest weights
 };
@@ -179,6 +185,8 @@ struct RepState {
     uint32_t n_surv_f;        // separate sexes: females among the survivors
     double R[2];              // physiology regime: resource densities
     double eggs, emax, xmax;  // physiology regime: eggs of the step, largest eggs and X of the eligible parents
+    uint32_t gfree_n[2];      // physiology regime: free slots at the census of generation t, by t & 1
+    uint32_t gfree_top;       // physiology regime: free slots after this step's deaths (recruits pop below it)
     uint64_t near_ties, truncated, updates, sum_threshold;
     int64_t sum_z[kCensusSlots];
     uint64_t sum_z2[kCensusSlots];
