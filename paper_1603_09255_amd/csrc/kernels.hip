@@ -806,14 +806,9 @@ __device__ __forceinline__ void survive_tile(const RepDesc *__restrict__ descs, 
                 if (d.species == 0) {
                     captured = gload(d.won + i) != ~0ull;
                 } else {
-                    // credited captures: those whose resource kept this key
-                    const RepDesc &r = descs[d.partner];
-                    const RepState &rs = states[d.partner];
-                    const uint32_t NR = rs.n[current_pair(rs)];
-                    consumer_captures(d, i, t, (int32_t)zw.v[q], r.z[t & 1u], NR, [&](uint32_t e, uint32_t tgt) {
-                        if (gload(r.won + tgt) == capture_key(i, e)) ++intake;
-                    });
-                    gstore(d.intake + i, intake);
+                    // credited captures: those whose resource kept this
+                    // consumer's key (counted by credit_kernel)
+                    intake = gload(d.intake + i);
                     in_loc += intake;
                 }
             }
@@ -2257,6 +2252,7 @@ __device__ __forceinline__ void encounter_tile(const RepDesc *__restrict__ descs
     const uint32_t par = current_pair(cs);
     const uint32_t t = cs.t[par], n = cs.n[par];
     if (i >= n) return;
+    gstore(c.intake + i, 0u);  // credit_kernel counts this generation's credited captures
     const RepDesc &r = descs[c.partner];
     const RepState &rs = states[c.partner];
     const uint32_t NR = rs.n[current_pair(rs)];
@@ -2265,6 +2261,37 @@ __device__ __forceinline__ void encounter_tile(const RepDesc *__restrict__ descs
     unsigned long long *won = reinterpret_cast<unsigned long long *>(r.won);
     consumer_captures(c, i, t, zc[i], zr, NR,
                       [&](uint32_t e, uint32_t tgt) { atomicMin(won + tgt, (unsigned long long)capture_key(i, e)); });
+}
+
+// A captured resource credits the consumer whose key it kept (the lowest
+// (consumer, encounter) key of its captures): one atomic add to that
+// consumer's intake.  Survival tiles of every deme; only the resources'
+// act.
+__device__ __forceinline__ void credit_tile(const RepDesc *__restrict__ descs, const RepState *__restrict__ states,
+                                            const SurvTile tile) {
+    const RepDesc &r = descs[tile.rep];
+    if (r.regime != SPEGG_CONSUMER_RESOURCE || r.species != 0) return;  // uniform over the block
+    const RepState &rs = states[tile.rep];
+    const uint32_t NR = rs.n[current_pair(rs)];
+    for (uint32_t k = threadIdx.x; k < r.surv_tile; k += kBlock) {
+        const uint32_t j = tile.start + k;
+        if (j >= NR) break;
+        const uint64_t key = gload(r.won + j);
+        if (key == ~0ull) continue;
+        const RepDesc &c = descs[r.partner];
+        const uint32_t i = (uint32_t)(key >> 32);
+        const RepState &cs = states[r.partner];
+        if (i < cs.n[current_pair(cs)]) atomicAdd(c.intake + i, 1u);
+        else atomicOr(const_cast<uint32_t *>(&rs.error), 1u);  // a key of no consumer: impossible
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) credit_kernel(const RepDesc *__restrict__ descs,
+                                                        const RepState *__restrict__ states,
+                                                        const SurvTile *__restrict__ tiles, uint32_t ntiles,
+                                                        const uint32_t *__restrict__ list_n) {
+    const uint32_t m = list_n ? *list_n : ntiles;
+    for (uint32_t v = blockIdx.x; v < m; v += gridDim.x) credit_tile(descs, states, tiles[v]);
 }
 
 // Tiles [0, ntiles) of the plan, one block each, or the list_n occupied
@@ -2552,6 +2579,14 @@ hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const 
     if (ntiles == 0) return hipSuccess;
     const uint32_t blocks = list_n ? (grid < ntiles ? grid : ntiles) : ntiles;
     hipLaunchKernelGGL(encounter_kernel, dim3(blocks), dim3(kBlock), 0, s, descs, states, tiles, ntiles, list_n);
+    return hipGetLastError();
+}
+
+hipError_t launch_credit(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
+                         const uint32_t *list_n, uint32_t grid, hipStream_t s) {
+    if (ntiles == 0) return hipSuccess;
+    const uint32_t blocks = list_n ? (grid < ntiles ? grid : ntiles) : ntiles;
+    hipLaunchKernelGGL(credit_kernel, dim3(blocks), dim3(kBlock), 0, s, descs, states, tiles, ntiles, list_n);
     return hipGetLastError();
 }
 

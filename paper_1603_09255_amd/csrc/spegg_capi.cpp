@@ -873,8 +873,13 @@ hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
         if (P.listed) e = launch_plan_tiles(pop->d_descs(), pop->d_states(), pop->n_demes, lists, 0, pop->stream);
         if (e == hipSuccess && !P.enc_tiles.empty())
             e = timed(pop, SPEGG_KERNEL_ENCOUNTER, [&] {
-                return launch_encounter(pop->d_descs(), pop->d_states(), enc_tiles, (uint32_t)P.enc_tiles.size(),
-                                        ln ? ln + 1 : nullptr, P.grid_encounter, pop->stream);
+                hipError_t r = launch_encounter(pop->d_descs(), pop->d_states(), enc_tiles,
+                                                (uint32_t)P.enc_tiles.size(), ln ? ln + 1 : nullptr, P.grid_encounter,
+                                                pop->stream);
+                if (r == hipSuccess)  // captured resources credit their consumers
+                    r = launch_credit(pop->d_descs(), pop->d_states(), sa.tiles, ns_tiles, ln, P.grid_survive,
+                                      pop->stream);
+                return r;
             });
         if (e == hipSuccess) e = timed(pop, SPEGG_KERNEL_SURVIVE, [&] { return launch_survive(sa); });
         if (e == hipSuccess) e = timed(pop, SPEGG_KERNEL_COMPACT, [&] { return launch_compact(sa); });

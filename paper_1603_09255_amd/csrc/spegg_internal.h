@@ -369,6 +369,10 @@ hipError_t offspring_blocks_per_cu(OffShape shape, size_t lds, int *blocks);
 // grid blocks.
 hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
                             const uint32_t *list_n, uint32_t grid, hipStream_t s);
+// Consumer-resource regime, after encounter: each captured resource credits
+// the consumer whose key it kept (survival tiles of every deme, or a list).
+hipError_t launch_credit(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
+                         const uint32_t *list_n, uint32_t grid, hipStream_t s);
 // Consumer-resource and physiology regimes: survivors into the next census
 // (one block per survival tile of the regime's demes, or a list as above).
 hipError_t launch_carry(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
