@@ -448,10 +448,11 @@ spegg_status spegg_prepare_graphs(spegg_pop *pop);
 /* Kernel kinds timed by spegg_set_timing. */
 enum {
     SPEGG_KERNEL_SURVIVE = 0,   /* step D and the offspring count of A */
-    SPEGG_KERNEL_COMPACT = 1,   /* step E: survivor list, offspring slots, census advance */
+    SPEGG_KERNEL_COMPACT = 1,   /* step E: survivor list, offspring slots, census advance; consumer-resource
+                                   and physiology survivors carried into the next census */
     SPEGG_KERNEL_OFFSPRING = 2, /* steps A (parents), B and C, census partials */
-    SPEGG_KERNEL_ENCOUNTER = 3, /* consumer-resource: encounters and captures */
-    SPEGG_KERNEL_CARRY = 4,     /* consumer-resource: survivors carried into the next census */
+    SPEGG_KERNEL_ENCOUNTER = 3, /* consumer-resource: encounters, captures and their credit to consumers */
+    SPEGG_KERNEL_CARRY = 4,     /* no launch of its own any more (the carry is part of compact): always 0 */
     SPEGG_KERNEL_KINDS = 5
 };
 

@@ -6,7 +6,8 @@
 //   compact    E: each tile's prefix is the sum of the counts of the
 //              replicate's earlier tiles; survivor ranks give the ascending
 //              survivor list, kid ranks each mother's offspring slots; tile 0
-//              of each replicate advances the census
+//              of each replicate advances the census; consumer-resource and
+//              physiology survivors move to the front of the next census
 //   offspring  A (parents) + B (gametes: crossover mask, mutation flips)
 //              + C (additive phenotype by popcounts) + census partials; one
 //              team of 2G lanes per newborn, V consecutive words per lane
@@ -17,8 +18,8 @@
 //   encounter  (consumer-resource regime, before survive) consumers meet
 //              and capture resources; each captured resource keeps the
 //              lowest (consumer, encounter) key by a 64-bit atomic minimum
-//   carry      (consumer-resource and physiology regimes, after compact)
-//              survivors move to the front of the next census
+//   credit     (consumer-resource regime, after encounter) each captured
+//              resource adds one to its consumer's intake
 //   plan_tiles (populations of several demes whose censuses can fall below
 //              their capacities) lists the tiles a generation occupies;
 //              the launches then walk the lists with resident grids
@@ -962,6 +963,28 @@ __global__ void __launch_bounds__(kBlock) survive_list_kernel(const RepDesc *__r
 
 // ---------------------------------------------------------------- compact
 
+// Consumer-resource and physiology regimes: survivor `from` of the census
+// in buffers `cur` moves to position k of the next census (compact places it
+// as it lists it) with its phenotype, its age class plus one, its sex and
+// masses, and -- where the allelic values stay in place (physiology) -- its
+// storage slot; a genome that moves is copied by compact's whole block.  A
+// resource starts the next generation uncaptured.
+__device__ __forceinline__ void carry_one(const RepDesc &d, uint32_t cur, uint32_t from, uint32_t k) {
+    if (d.gfree) gstore(d.gslot[cur ^ 1u] + k, gload(d.gslot[cur] + from));
+    d.z[cur ^ 1u][k] = d.z[cur][from];
+    if (d.age[0]) {
+        const uint32_t a = d.age[cur][from];
+        d.age[cur ^ 1u][k] = (uint8_t)(a < 3u ? a + 1u : 3u);  // class 3 holds three and older
+    }
+    if (d.won) d.won[k] = ~0ull;
+    if (d.sexes) d.sex[cur ^ 1u][k] = d.sex[cur][from];
+    if (d.X[0]) {  // physiology regime: the grown masses
+        d.X[cur ^ 1u][k] = d.X[cur][from];
+        d.Y[cur ^ 1u][k] = d.Y[cur][from];
+    }
+}
+
+
 // One block per tile: its prefix is summed from the counts of the
 // replicate's earlier tiles (written by survive, a launch earlier), then
 // block ranks place its survivors and its mothers' offspring slots.  Tile 0
@@ -1210,10 +1233,21 @@ __device__ __forceinline__ void compact_tile(const RepDesc *__restrict__ descs, 
     uint32_t atot, ktot;
     uint32_t spos = aoff + block_excl_scan(a_loc, sh_a, &atot, tid);
     uint64_t slot = koff + block_excl_scan(k_loc, sh_k, &ktot, tid);
+    // consumer-resource and physiology survivors lead the next census: the
+    // thread moves its survivors' small values; genomes are copied by the
+    // whole block below, its survivors' sources listed in LDS
+    const bool carries = d.regime == SPEGG_CONSUMER_RESOURCE || d.regime == SPEGG_PHYSIOLOGY;
+    const bool copy_genomes = carries && !d.gfree;  // uniform over the block
+    __shared__ uint32_t sh_from[kBlock * IT];
+    const uint32_t tile_pos0 = aoff;  // the tile's first survivor position
 #pragma unroll
     for (uint32_t q = 0; q < IT; ++q) {
         if (fate[q] >> 15) {
-            if (spos < d.cap) gstore(d.S + spos, i0 + q);
+            if (spos < d.cap) {
+                gstore(d.S + spos, i0 + q);
+                if (carries) carry_one(d, t & 1u, i0 + q, spos);
+                if (copy_genomes) sh_from[spos - tile_pos0] = i0 + q;
+            }
             ++spos;
         } else if (d.gfree && i0 + q < n) {
             // physiology regime: the storage slot of the dead onto the free
@@ -1226,6 +1260,27 @@ __device__ __forceinline__ void compact_tile(const RepDesc *__restrict__ descs, 
             const uint32_t kids = fate[q] & 0x7FFFu;
             for (uint32_t m = 0; m < kids; ++m, ++slot)
                 if (slot < d.cap) gstore(d.owner + slot, i0 + q);
+        }
+    }
+    if (copy_genomes) {
+        __syncthreads();
+        const uint32_t cnt = tile_pos0 + atot <= d.cap ? atot : (tile_pos0 < d.cap ? d.cap - tile_pos0 : 0u);
+        const uint32_t cur = t & 1u, per = 2u * d.W;
+        if ((per & 3u) == 0) {  // 16-byte copies, consecutive threads on consecutive words
+            const uint32_t per4 = per / 4u;
+            const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(d.genome[cur]);
+            uint4 *__restrict__ dst = reinterpret_cast<uint4 *>(d.genome[cur ^ 1u]);
+            for (uint32_t idx = tid; idx < cnt * per4; idx += kBlock) {
+                const uint32_t k = idx / per4, w = idx % per4;
+                dst[(size_t)(tile_pos0 + k) * per4 + w] = src[(size_t)sh_from[k] * per4 + w];
+            }
+        } else {
+            const uint32_t *__restrict__ src = d.genome[cur];
+            uint32_t *__restrict__ dst = d.genome[cur ^ 1u];
+            for (uint32_t idx = tid; idx < cnt * per; idx += kBlock) {
+                const uint32_t k = idx / per, w = idx % per;
+                dst[(size_t)(tile_pos0 + k) * per + w] = src[(size_t)sh_from[k] * per + w];
+            }
         }
     }
 }
@@ -2103,10 +2158,10 @@ __global__ void __launch_bounds__(kBlock) offspring_cont_kernel(const RepDesc *_
 // to run, which no result depends on (every tile writes only its own
 // outputs).  Phase 0, before encounter and survive: the survival tiles of
 // the census (tile 0 always: it records the census) and, for consumers,
-// their encounter tiles.  Phase 1, after compact: the carry tiles of the
-// carried survivors and the offspring tiles of the newborns, in the list of
-// the deme's kernel class.  Each phase clears the counts of the other
-// phase's lists, which it does not touch; all start at zero.
+// their encounter tiles.  Phase 1, after compact: the offspring tiles of the
+// newborns, in the list of the deme's kernel class.  Each phase clears the
+// counts of the other phase's lists, which it does not touch; all start at
+// zero.
 __global__ void __launch_bounds__(kBlock) plan_tiles_kernel(const RepDesc *__restrict__ descs,
                                                             const RepState *__restrict__ states, TileLists lists,
                                                             int phase) {
@@ -2115,41 +2170,32 @@ __global__ void __launch_bounds__(kBlock) plan_tiles_kernel(const RepDesc *__res
     const RepDesc &d = descs[u];
     const RepState &st = states[u];
     const uint32_t T = d.surv_tile;
-    uint32_t m0 = 0, m1 = 0;  // tiles of this deme in the phase's two lists
-    uint32_t *c0, *c1;
     if (phase == 0) {
         if (u == 0)
-            for (uint32_t q = threadIdx.x; q < 1u + lists.n_classes; q += kBlock) lists.counts[2u + q] = 0;
+            for (uint32_t q = threadIdx.x; q < lists.n_classes; q += kBlock) lists.counts[2u + q] = 0;
         const uint32_t n = st.n[current_pair(st)];
-        m0 = n == 0 ? 1u : (n + T - 1u) / T;
-        if (d.regime == SPEGG_CONSUMER_RESOURCE && d.species == 1) m1 = (n + T - 1u) / T;
-        c0 = lists.counts;
-        c1 = lists.counts + 1;
+        // a census beyond the capacity is an impossible state (the kernels
+        // that find one report it): never write past the deme's share
+        uint32_t ms = n == 0 ? 1u : (n + T - 1u) / T, me = 0;
+        if (d.regime == SPEGG_CONSUMER_RESOURCE && d.species == 1) me = (n + T - 1u) / T;
+        ms = ms < d.surv_ntiles ? ms : d.surv_ntiles;
+        me = me < d.surv_ntiles ? me : d.surv_ntiles;
+        if (threadIdx.x == 0) {
+            base[0] = atomicAdd(lists.counts, ms);
+            base[1] = me ? atomicAdd(lists.counts + 1, me) : 0u;
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < ms; k += kBlock) lists.surv[base[0] + k] = SurvTile{u, k * T};
+        for (uint32_t k = threadIdx.x; k < me; k += kBlock) lists.enc[base[1] + k] = SurvTile{u, k * T};
     } else {
         if (u == 0 && threadIdx.x < 2) lists.counts[threadIdx.x] = 0;
-        const uint32_t nc = st.n_carry, nn = st.n[current_pair(st)] - nc;
-        if (d.regime == SPEGG_CONSUMER_RESOURCE || d.regime == SPEGG_PHYSIOLOGY) m0 = (nc + T - 1u) / T;
-        m1 = (nn + d.off_per_tile - 1u) / d.off_per_tile;
-        c0 = lists.counts + 2;
-        c1 = lists.counts + 3u + d.off_class;
-    }
-    // a census beyond the capacity is an impossible state (the kernels that
-    // find one report it): never write past the deme's share of a list
-    const uint32_t cap1 = phase == 0 ? d.surv_ntiles : d.off_ntiles;
-    m0 = m0 < d.surv_ntiles ? m0 : d.surv_ntiles;
-    m1 = m1 < cap1 ? m1 : cap1;
-    if (threadIdx.x == 0) {
-        base[0] = m0 ? atomicAdd(c0, m0) : 0u;
-        base[1] = m1 ? atomicAdd(c1, m1) : 0u;
-    }
-    __syncthreads();
-    if (phase == 0) {
-        for (uint32_t k = threadIdx.x; k < m0; k += kBlock) lists.surv[base[0] + k] = SurvTile{u, k * T};
-        for (uint32_t k = threadIdx.x; k < m1; k += kBlock) lists.enc[base[1] + k] = SurvTile{u, k * T};
-    } else {
-        for (uint32_t k = threadIdx.x; k < m0; k += kBlock) lists.carry[base[0] + k] = SurvTile{u, k * T};
-        OffTile *off = lists.off + d.off_list0 + base[1];
-        for (uint32_t k = threadIdx.x; k < m1; k += kBlock) off[k] = OffTile{u, k * d.off_per_tile};
+        const uint32_t nn = st.n[current_pair(st)] - st.n_carry;
+        uint32_t mo = (nn + d.off_per_tile - 1u) / d.off_per_tile;
+        mo = mo < d.off_ntiles ? mo : d.off_ntiles;
+        if (threadIdx.x == 0) base[0] = mo ? atomicAdd(lists.counts + 2u + d.off_class, mo) : 0u;
+        __syncthreads();
+        OffTile *off = lists.off + d.off_list0 + base[0];
+        for (uint32_t k = threadIdx.x; k < mo; k += kBlock) off[k] = OffTile{u, k * d.off_per_tile};
     }
 }
 
@@ -2302,66 +2348,6 @@ __global__ void __launch_bounds__(kBlock) encounter_kernel(const RepDesc *__rest
                                                            const uint32_t *__restrict__ list_n) {
     const uint32_t m = list_n ? *list_n : ntiles;
     for (uint32_t v = blockIdx.x; v < m; v += gridDim.x) encounter_tile(descs, states, tiles[v]);
-}
-
-// One block per survival tile of a consumer-resource deme: survivors
-// S[k], k in the tile, move to position k of the next census with their
-// genome, phenotype and age class plus one (compact advanced the census and
-// recorded how many are carried).
-__device__ __forceinline__ void carry_tile(const RepDesc *__restrict__ descs, const RepState *__restrict__ states,
-                                           const SurvTile tile) {
-    const RepDesc &d = descs[tile.rep];
-    const RepState &st = states[tile.rep];
-    const uint32_t newest = current_pair(st);
-    const uint32_t nc = st.n_carry;
-    if (tile.start >= nc) return;
-    const uint32_t cur = (st.t[newest] - 1u) & 1u;
-    const uint32_t cnt = nc - tile.start < d.surv_tile ? nc - tile.start : d.surv_tile;
-    const uint32_t per = 2u * d.W;
-    if (d.gfree) {  // physiology regime: the values stay in their slots, the slot moves
-        for (uint32_t idx = threadIdx.x; idx < cnt; idx += kBlock) {
-            const uint32_t k = tile.start + idx;
-            d.gslot[cur ^ 1u][k] = d.gslot[cur][d.S[k]];
-        }
-    } else if ((per & 3u) == 0) {  // 16-byte copies
-        const uint32_t per4 = per / 4u;
-        const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(d.genome[cur]);
-        uint4 *__restrict__ dst = reinterpret_cast<uint4 *>(d.genome[cur ^ 1u]);
-        for (uint32_t idx = threadIdx.x; idx < cnt * per4; idx += kBlock) {
-            const uint32_t k = tile.start + idx / per4, w = idx % per4;
-            dst[(size_t)k * per4 + w] = src[(size_t)d.S[k] * per4 + w];
-        }
-    } else {
-        const uint32_t *__restrict__ src = d.genome[cur];
-        uint32_t *__restrict__ dst = d.genome[cur ^ 1u];
-        for (uint32_t idx = threadIdx.x; idx < cnt * per; idx += kBlock) {
-            const uint32_t k = tile.start + idx / per, w = idx % per;
-            dst[(size_t)k * per + w] = src[(size_t)d.S[k] * per + w];
-        }
-    }
-    for (uint32_t idx = threadIdx.x; idx < cnt; idx += kBlock) {
-        const uint32_t k = tile.start + idx, from = d.S[k];
-        d.z[cur ^ 1u][k] = d.z[cur][from];
-        if (d.age[0]) {
-            const uint32_t a = d.age[cur][from];
-            d.age[cur ^ 1u][k] = (uint8_t)(a < 3u ? a + 1u : 3u);  // class 3 holds three and older
-        }
-        if (d.won) d.won[k] = ~0ull;
-        if (d.sexes) d.sex[cur ^ 1u][k] = d.sex[cur][from];
-        if (d.X[0]) {  // physiology regime: the grown masses
-            d.X[cur ^ 1u][k] = d.X[cur][from];
-            d.Y[cur ^ 1u][k] = d.Y[cur][from];
-        }
-    }
-}
-
-// Tiles as in encounter_kernel.
-__global__ void __launch_bounds__(kBlock) carry_kernel(const RepDesc *__restrict__ descs,
-                                                       const RepState *__restrict__ states,
-                                                       const SurvTile *__restrict__ tiles, uint32_t ntiles,
-                                                       const uint32_t *__restrict__ list_n) {
-    const uint32_t m = list_n ? *list_n : ntiles;
-    for (uint32_t v = blockIdx.x; v < m; v += gridDim.x) carry_tile(descs, states, tiles[v]);
 }
 
 __global__ void fill_u64_kernel(uint64_t *p, uint32_t n) {
@@ -2590,14 +2576,6 @@ hipError_t launch_credit(const RepDesc *descs, const RepState *states, const Sur
     return hipGetLastError();
 }
 
-hipError_t launch_carry(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
-                        const uint32_t *list_n, uint32_t grid, hipStream_t s) {
-    if (ntiles == 0) return hipSuccess;
-    const uint32_t blocks = list_n ? (grid < ntiles ? grid : ntiles) : ntiles;
-    hipLaunchKernelGGL(carry_kernel, dim3(blocks), dim3(kBlock), 0, s, descs, states, tiles, ntiles, list_n);
-    return hipGetLastError();
-}
-
 hipError_t launch_plan_tiles(const RepDesc *descs, const RepState *states, uint32_t n_demes, const TileLists &lists,
                              int phase, hipStream_t s) {
     if (n_demes == 0) return hipSuccess;
@@ -2611,7 +2589,6 @@ hipError_t list_blocks_per_cu(int kind, int items, int *blocks) {
     if (kind == 0) k = items == 4 ? (const void *)survive_list_kernel<4> : (const void *)survive_list_kernel<1>;
     else if (kind == 1) k = items == 4 ? (const void *)compact_list_kernel<4> : (const void *)compact_list_kernel<1>;
     else if (kind == 2) k = (const void *)encounter_kernel;
-    else if (kind == 3) k = (const void *)carry_kernel;
     else return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k, kBlock, 0);
 }

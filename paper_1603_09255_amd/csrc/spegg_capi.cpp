@@ -122,9 +122,8 @@ struct Plan {
     std::vector<OffClass> classes;
     std::vector<SurvTile> surv_tiles;
     std::vector<SurvTile> enc_tiles;    // survival tiles of consumer demes
-    std::vector<SurvTile> carry_tiles;  // survival tiles of consumer-resource demes
     std::vector<OffTile> off_tiles;
-    size_t descs = 0, states = 0, surv_tiles_at = 0, off_tiles_at = 0, enc_tiles_at = 0, carry_tiles_at = 0;
+    size_t descs = 0, states = 0, surv_tiles_at = 0, off_tiles_at = 0, enc_tiles_at = 0;
     size_t static_end = 0;  // [0, static_end) is uploaded at create
     size_t surv_counts = 0, surv_groups = 0, partials = 0, total = 0;
     uint32_t n_groups = 0;  // tile-group records, both parities
@@ -133,9 +132,9 @@ struct Plan {
     // (populations of several demes whose censuses can fall below their
     // capacities): their counts (3 + one per possible class) and arrays.
     bool listed = false;
-    size_t list_counts_at = 0, list_surv_at = 0, list_enc_at = 0, list_carry_at = 0, list_off_at = 0;
+    size_t list_counts_at = 0, list_surv_at = 0, list_enc_at = 0, list_off_at = 0;
     uint32_t list_counts = 0;
-    uint32_t grid_survive = 0, grid_compact = 0, grid_encounter = 0, grid_carry = 0;
+    uint32_t grid_survive = 0, grid_compact = 0, grid_encounter = 0;
 };
 
 // Resident grids per list-walking launch (a tuning knob: results do not
@@ -197,7 +196,6 @@ hipError_t fit_offspring_grids(Plan &P, int device) {
         if ((e = fit(0, ns, &P.grid_survive)) != hipSuccess) return e;
         if ((e = fit(1, ns, &P.grid_compact)) != hipSuccess) return e;
         if ((e = fit(2, (uint32_t)P.enc_tiles.size(), &P.grid_encounter)) != hipSuccess) return e;
-        if ((e = fit(3, (uint32_t)P.carry_tiles.size(), &P.grid_carry)) != hipSuccess) return e;
     }
     if (std::getenv("SPEGG_OFFSPRING_GRID")) return hipSuccess;
     for (OffClass &c : P.classes) {
@@ -470,7 +468,6 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         for (uint32_t k = 0; k < q.surv_ntiles; ++k) {
             const SurvTile tile{u, k * surv_tile};
             P.surv_tiles.push_back(tile);
-            if (P.reps[q.rep].cr || P.reps[q.rep].phys) P.carry_tiles.push_back(tile);
             if (P.reps[q.rep].cr && q.species == 1) P.enc_tiles.push_back(tile);
         }
     }
@@ -520,7 +517,6 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
     P.states = cv.take(sizeof(RepState) * P.demes.size());
     P.surv_tiles_at = cv.take(sizeof(SurvTile) * P.surv_tiles.size());
     P.enc_tiles_at = cv.take(sizeof(SurvTile) * P.enc_tiles.size());
-    P.carry_tiles_at = cv.take(sizeof(SurvTile) * P.carry_tiles.size());
     // offspring tiles and their partials are carved for the smallest tile of
     // any shape (16 newborns), so a change of shape moves no buffer
     size_t max_off_tiles = 0;
@@ -549,11 +545,10 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
     P.listed = listed < 0 ? want_tile_lists(P, reps) : listed != 0;
     if (P.listed) {
         // room for one class per deme, whatever shapes a re-plan picks
-        P.list_counts = 3u + (uint32_t)P.demes.size();
+        P.list_counts = 2u + (uint32_t)P.demes.size();
         P.list_counts_at = cv.take(sizeof(uint32_t) * P.list_counts);
         P.list_surv_at = cv.take(sizeof(SurvTile) * P.surv_tiles.size());
         P.list_enc_at = cv.take(sizeof(SurvTile) * P.enc_tiles.size());
-        P.list_carry_at = cv.take(sizeof(SurvTile) * P.carry_tiles.size());
         P.list_off_at = cv.take(sizeof(OffTile) * max_off_tiles);
     }
     for (DemePlan &q : P.demes) {
@@ -680,8 +675,7 @@ struct spegg_pop {
     uint32_t *d_list_counts() { return at<uint32_t>(base, plan.list_counts_at); }
     TileLists lists() {
         return TileLists{at<SurvTile>(base, plan.list_surv_at), at<SurvTile>(base, plan.list_enc_at),
-                         at<SurvTile>(base, plan.list_carry_at), at<OffTile>(base, plan.list_off_at),
-                         d_list_counts(), (uint32_t)plan.classes.size()};
+                         at<OffTile>(base, plan.list_off_at), d_list_counts(), (uint32_t)plan.classes.size()};
     }
 };
 
@@ -853,15 +847,10 @@ hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
     Plan &P = pop->plan;
     const uint32_t ns_tiles = (uint32_t)P.surv_tiles.size();
     const int trace = pop->trace ? 1 : 0;
-    const SurvTile *enc_tiles = at<SurvTile>(pop->base, P.enc_tiles_at);
-    const SurvTile *carry_tiles = at<SurvTile>(pop->base, P.carry_tiles_at);
     // listed: every launch walks this generation's lists of occupied tiles
     const TileLists lists = pop->lists();
     const uint32_t *ln = P.listed ? lists.counts : nullptr;
-    if (P.listed) {
-        enc_tiles = lists.enc;
-        carry_tiles = lists.carry;
-    }
+    const SurvTile *enc_tiles = P.listed ? lists.enc : at<SurvTile>(pop->base, P.enc_tiles_at);
     for (uint32_t g = 0; g < n; ++g) {
         SelArgs sa{pop->d_descs(), pop->d_states(), P.listed ? lists.surv : pop->d_surv_tiles(), pop->d_surv_counts(),
                    pop->d_surv_groups(), ns_tiles, trace, pop->n_demes == 1 ? 0 : -1, (int)P.surv_items,
@@ -885,18 +874,13 @@ hipError_t enqueue_generations(spegg_pop *pop, uint32_t n) {
         if (e == hipSuccess) e = timed(pop, SPEGG_KERNEL_COMPACT, [&] { return launch_compact(sa); });
         if (e == hipSuccess && P.listed)
             e = launch_plan_tiles(pop->d_descs(), pop->d_states(), pop->n_demes, lists, 1, pop->stream);
-        if (e == hipSuccess && !P.carry_tiles.empty())
-            e = timed(pop, SPEGG_KERNEL_CARRY, [&] {
-                return launch_carry(pop->d_descs(), pop->d_states(), carry_tiles, (uint32_t)P.carry_tiles.size(),
-                                    ln ? ln + 2 : nullptr, P.grid_carry, pop->stream);
-            });
         for (size_t ci = 0; ci < P.classes.size(); ++ci) {
             const OffClass &c = P.classes[ci];
             if (e != hipSuccess) return e;
             OffArgs oa{pop->d_descs(), pop->d_states(), P.listed ? lists.off : pop->d_off_tiles(), c.tile0, c.ntiles,
                        c.single_deme, pop->d_partials(), c.plane_words, c.geo_words, c.mask_words, c.grid, c.lds,
                        trace, pop->stream};
-            oa.list_n = ln ? ln + 3 + ci : nullptr;
+            oa.list_n = ln ? ln + 2 + ci : nullptr;
             e = timed(pop, SPEGG_KERNEL_OFFSPRING, [&] { return launch_offspring(c.shape, oa); }, (int)ci);
         }
         if (e != hipSuccess) return e;
@@ -1176,8 +1160,6 @@ spegg_status spegg_pop_create(const spegg_rep_desc *reps, uint32_t n_reps, void 
         std::memcpy(img + P.surv_tiles_at, P.surv_tiles.data(), sizeof(SurvTile) * P.surv_tiles.size());
     if (!P.enc_tiles.empty())
         std::memcpy(img + P.enc_tiles_at, P.enc_tiles.data(), sizeof(SurvTile) * P.enc_tiles.size());
-    if (!P.carry_tiles.empty())
-        std::memcpy(img + P.carry_tiles_at, P.carry_tiles.data(), sizeof(SurvTile) * P.carry_tiles.size());
     if (!P.off_tiles.empty())
         std::memcpy(img + P.off_tiles_at, P.off_tiles.data(), sizeof(OffTile) * P.off_tiles.size());
 

@@ -321,11 +321,11 @@ struct SelArgs {
 };
 
 // This generation's lists of occupied tiles (plan_tiles_kernel), in device
-// memory: counts[0] survival tiles, [1] encounter tiles, [2] carry tiles,
-// [3 + c] offspring tiles of kernel class c, whose list starts at off +
-// the class's first tile index (the class's share of the plan's tiles).
+// memory: counts[0] survival tiles, [1] encounter tiles, [2 + c] offspring
+// tiles of kernel class c, whose list starts at off + the class's first
+// tile index (the class's share of the plan's tiles).
 struct TileLists {
-    SurvTile *surv, *enc, *carry;
+    SurvTile *surv, *enc;
     OffTile *off;
     uint32_t *counts;
     uint32_t n_classes;
@@ -373,17 +373,13 @@ hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const 
 // the consumer whose key it kept (survival tiles of every deme, or a list).
 hipError_t launch_credit(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
                          const uint32_t *list_n, uint32_t grid, hipStream_t s);
-// Consumer-resource and physiology regimes: survivors into the next census
-// (one block per survival tile of the regime's demes, or a list as above).
-hipError_t launch_carry(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
-                        const uint32_t *list_n, uint32_t grid, hipStream_t s);
 // The lists of occupied tiles of phase 0 (before encounter and survive) or
 // phase 1 (after compact), one block per deme.
 hipError_t launch_plan_tiles(const RepDesc *descs, const RepState *states, uint32_t n_demes, const TileLists &lists,
                              int phase, hipStream_t s);
 // Blocks per compute unit of the list-walking kernels (HIP's occupancy
 // calculation): kind 0 survive, 1 compact (items adults per thread), 2
-// encounter, 3 carry.
+// encounter.
 hipError_t list_blocks_per_cu(int kind, int items, int *blocks);
 // Fill n words of a uint64 array with ~0 (capture keys before the first
 // generation) and n bytes with 0 (ages).
