@@ -1234,10 +1234,9 @@ __device__ __forceinline__ void compact_tile(const RepDesc *__restrict__ descs, 
     uint32_t spos = aoff + block_excl_scan(a_loc, sh_a, &atot, tid);
     uint64_t slot = koff + block_excl_scan(k_loc, sh_k, &ktot, tid);
     // consumer-resource and physiology survivors lead the next census: the
-    // thread moves its survivors' small values; genomes are copied by the
-    // whole block below, its survivors' sources listed in LDS
+    // tile's survivors are listed in LDS, then moved by the whole block,
+    // consecutive threads on consecutive survivors (and genome words)
     const bool carries = d.regime == SPEGG_CONSUMER_RESOURCE || d.regime == SPEGG_PHYSIOLOGY;
-    const bool copy_genomes = carries && !d.gfree;  // uniform over the block
     __shared__ uint32_t sh_from[kBlock * IT];
     const uint32_t tile_pos0 = aoff;  // the tile's first survivor position
 #pragma unroll
@@ -1245,8 +1244,7 @@ __device__ __forceinline__ void compact_tile(const RepDesc *__restrict__ descs, 
         if (fate[q] >> 15) {
             if (spos < d.cap) {
                 gstore(d.S + spos, i0 + q);
-                if (carries) carry_one(d, t & 1u, i0 + q, spos);
-                if (copy_genomes) sh_from[spos - tile_pos0] = i0 + q;
+                if (carries) sh_from[spos - tile_pos0] = i0 + q;
             }
             ++spos;
         } else if (d.gfree && i0 + q < n) {
@@ -1262,11 +1260,14 @@ __device__ __forceinline__ void compact_tile(const RepDesc *__restrict__ descs, 
                 if (slot < d.cap) gstore(d.owner + slot, i0 + q);
         }
     }
-    if (copy_genomes) {
+    if (carries) {  // uniform over the block
         __syncthreads();
         const uint32_t cnt = tile_pos0 + atot <= d.cap ? atot : (tile_pos0 < d.cap ? d.cap - tile_pos0 : 0u);
         const uint32_t cur = t & 1u, per = 2u * d.W;
-        if ((per & 3u) == 0) {  // 16-byte copies, consecutive threads on consecutive words
+        for (uint32_t kk = tid; kk < cnt; kk += kBlock) carry_one(d, cur, sh_from[kk], tile_pos0 + kk);
+        if (d.gfree) {
+            // the allelic values stay in their slots
+        } else if ((per & 3u) == 0) {  // 16-byte copies, consecutive threads on consecutive words
             const uint32_t per4 = per / 4u;
             const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(d.genome[cur]);
             uint4 *__restrict__ dst = reinterpret_cast<uint4 *>(d.genome[cur ^ 1u]);

@@ -452,11 +452,16 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         }
     // survival tiles, deme by deme: four adults per thread where the
     // population has several demes and no consumer-resource replicate (fewer,
-    // longer blocks; measured faster on the batched table), else one (more
-    // blocks in flight for one deme; the consumer-resource kernels assume it)
-    bool any_cr = false;  // consumer-resource or physiology: one adult per thread, carried survivors
-    for (const RepPlan &p : P.reps) any_cr |= p.cr || p.phys;
+    // longer blocks, the per-tile sums shared by more adults; measured faster
+    // on the batched table and the physiology batch), else one (more blocks
+    // in flight for one deme; the consumer-resource kernels assume it)
+    bool any_cr = false;  // consumer-resource: one adult per thread (its encounter tiles assume it)
+    for (const RepPlan &p : P.reps) any_cr |= p.cr;
     P.surv_items = (!any_cr && P.demes.size() > 1) ? (uint32_t)kSurvItemsMax : 1u;
+    // SPEGG_SURV_ITEMS=1 forces one adult per thread (an experiment knob: no
+    // result depends on it)
+    const char *items = std::getenv("SPEGG_SURV_ITEMS");
+    if (items && items[0] == '1' && items[1] == 0) P.surv_items = 1u;
     const uint32_t surv_tile = kBlock * P.surv_items;
     for (uint32_t u = 0; u < P.demes.size(); ++u) {
         DemePlan &q = P.demes[u];
