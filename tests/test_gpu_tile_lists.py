@@ -4,7 +4,8 @@ walking lists of the tiles each generation occupies (the default for
 populations of several demes whose censuses can fall below their
 capacities).  SPEGG_TILE_LISTS forces either way at creation; every output
 -- census, genomes or allelic values, phenotypes, masses, sexes, ages,
-survivors and traced parents -- is compared after every generation."""
+survivors and traced parents -- is compared after every generation.  So do
+four adults per thread in survive and compact and one (SPEGG_SURV_ITEMS)."""
 import os
 
 import numpy as np
@@ -141,3 +142,36 @@ def test_lists_equal_capacity_grids(name, reps, gens):
     same(dense, listed, reps, f"{name} after a change of shapes")
     dense.close()
     listed.close()
+
+
+def build_env(reps, **env):
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        pop = spegg.Population(reps)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
+    pop.set_trace(True)
+    return pop
+
+
+@pytest.mark.parametrize("name,reps", [
+    ("physiology", [phys(1, 1500, 12000), phys(2, 300, 9000), phys(3, 2500, 2600, L=40)]),
+    ("poisson_wf", [poisson(4), wf(5, n_patches=3, migration=0.05, n0=300, capacity=900), wf(6, sexes=1)]),
+], ids=["physiology", "poisson_wf"])
+def test_adults_per_thread_equal(name, reps):
+    """Four adults per thread (the default for several demes without a
+    consumer-resource replicate) and one give the same populations."""
+    say("adults per thread", name)
+    four, one = build_env(reps), build_env(reps, SPEGG_SURV_ITEMS="1")
+    same(four, one, reps, f"{name} start")
+    for g in range(12):
+        four.step(1)
+        one.step(1)
+        same(four, one, reps, f"{name} generation {g + 1}")
+    four.close()
+    one.close()
