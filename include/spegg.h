@@ -216,7 +216,7 @@ enum { SPEGG_BIALLELIC = 0, SPEGG_CONTINUOUS = 1 };
  * the bit-serial comparison of its uniform U against R_b = floor(r_b 2^32)
  * finds U < R_b, U's bits from the top taken from bit b % 32 of words
  * 1 + 8 (b / 32) + ... of the RECOMB stream, as for a uniform r of at least
- * 0.17.  NULL: r at every boundary.
+ * 0.10.  NULL: r at every boundary.
  *
  * sexes = 1: each individual is female or male by bit 0 of word 0 of stream
  * 16 (block 0 for newborn j, block 1 for a founder); mothers are females,
@@ -601,7 +601,7 @@ int spegg_threshold_table(int kind, double a, uint32_t b, uint64_t *out, int cap
 int spegg_geometric_gap(double r, uint32_t n_loci, uint32_t x, uint32_t guess, uint32_t *gap);
 
 /* Host-only: crossover-sampling mode for r (0 raw bits, r = 1/2; 1 none,
- * r = 0; 2 geometric skips, 0 < r < 0.17; 3 bit-serial comparison). */
+ * r = 0; 2 geometric skips, 0 < r < 0.10; 3 bit-serial comparison). */
 int spegg_recomb_mode(double r);
 
 /* Device Philox4x32-10 for testing: for i < n, out[4i..4i+3] =

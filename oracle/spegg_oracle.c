@@ -377,7 +377,7 @@ int oracle_recomb_mode(double r)
         return MODE_RAW;
     if (r == 0.0)
         return MODE_ZERO;
-    if (r < 0.17)
+    if (r < 0.10)
         return MODE_SKIP;
     return MODE_LAZY;
 }

@@ -71,7 +71,7 @@ constexpr uint32_t geometric_gap_fix(const uint32_t *T, uint32_t len, uint32_t g
     return g;
 }
 
-constexpr double kSkipBelow = 0.17;  // r < 0.17: geometric gaps; above: bit-serial Bernoulli
+constexpr double kSkipBelow = 0.10;  // r < 0.10: geometric gaps; above: bit-serial Bernoulli
 
 constexpr int kBlock = 256;          // threads per block in every kernel
 // Consecutive adults per thread in survive and compact, chosen per

@@ -3,8 +3,9 @@ consumes the word 0xFFFFFFFF while a crossover is still to follow.
 
 Crossovers at independent boundaries (Supplementary S2, "Genetics") are
 drawn as geometric gaps by inversion, gap = min{k : x < T_k} with
-T_k = floor((1 - (1-r)^(k+1)) 2^32).  For r = 0.1 and L = 1024 the table
-reaches 2^32 at k = 427, so a word of 0xFFFFFFFF must give the gap 427.
+T_k = floor((1 - (1-r)^(k+1)) 2^32).  For r = 0.09 and L = 1024 the table
+reaches 2^32 inside the genome, so a word of 0xFFFFFFFF must give the index
+of that entry.
 The search uses only the oracle: its Philox words and its table.  Run from
 the repository root: python tests/golden/make_skip_gap_edge.py
 """
@@ -17,7 +18,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
 
-SEED, C3, R, L, SLOTS = 7, 0, 0.1, 1024, 4096
+SEED, C3, R, L, SLOTS = 7, 0, 0.09, 1024, 4096
 CHUNK = 32  # generations per search task
 X = 0xFFFFFFFF
 

@@ -57,7 +57,7 @@ def test_geometric_tables_match_oracle(r, n):
     assert np.array_equal(spegg.threshold_table(2, r, n, cap=max(n, 1)), oracle.geometric_thresholds(r, n))
 
 
-@pytest.mark.parametrize("r", [0.0, 1e-9, 0.001, 0.01, 0.1699999, 0.17, 0.25, 0.4999999, 0.5])
+@pytest.mark.parametrize("r", [0.0, 1e-9, 0.001, 0.01, 0.0999999, 0.1, 0.17, 0.25, 0.4999999, 0.5])
 def test_recomb_mode_matches_oracle(r):
     assert spegg.recomb_mode(r) == oracle.recomb_mode(r)
 

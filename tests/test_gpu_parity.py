@@ -74,15 +74,15 @@ CASES = [
     ("wf-raw-L64", dict(regime=0, n_loci=64, r=0.5, mu=1e-3, omega=4.0), 3),
     ("wf-zero-L100", dict(regime=0, n_loci=100, r=0.0, mu=0.01, omega=6.0), 3),
     ("wf-skip-L1024", dict(regime=0, n_loci=1024, r=0.01, mu=1e-3, omega=20.0), 3),
-    ("wf-skip-L257", dict(regime=0, n_loci=257, r=0.1, mu=0.02, omega=9.0), 3),
+    ("wf-skip-L257", dict(regime=0, n_loci=257, r=0.09, mu=0.02, omega=9.0), 3),
     ("wf-lazy-L200", dict(regime=0, n_loci=200, r=0.3, mu=1e-2, omega=8.0), 3),
-    ("wf-lazy-boundary-r", dict(regime=0, n_loci=96, r=0.17, mu=0.0, omega=0.0), 2),
+    ("wf-lazy-boundary-r", dict(regime=0, n_loci=96, r=0.10, mu=0.0, omega=0.0), 2),
     ("wf-lazy-L2048", dict(regime=0, n_loci=2048, r=0.45, mu=1e-4, omega=30.0), 2),
     ("wf-L1", dict(regime=0, n_loci=1, r=0.01, mu=0.1, omega=0.5), 3),
     # the gap table's edges: one threshold (L = 2), and r just below the bit-serial cut, where gaps of 0 and
     # gaps past the table's end are both common
-    ("wf-skip-L2", dict(regime=0, n_loci=2, r=0.12, mu=0.05, omega=1.0), 3),
-    ("wf-skip-L33-r016", dict(regime=0, n_loci=33, r=0.16, mu=0.01, omega=3.0), 3),
+    ("wf-skip-L2", dict(regime=0, n_loci=2, r=0.08, mu=0.05, omega=1.0), 3),
+    ("wf-skip-L33-r0095", dict(regime=0, n_loci=33, r=0.095, mu=0.01, omega=3.0), 3),
     ("wf-L31-high-mu", dict(regime=0, n_loci=31, r=0.5, mu=0.4, omega=3.0), 3),
     ("wf-effects", dict(regime=0, n_loci=300, r=0.05, mu=1e-3, omega=15.0, effects="grid"), 3),
     ("pois-bh-L1024", dict(regime=1, n_loci=1024, r=0.01, mu=1e-4, omega=64.0, K=800.0, fecundity=2.2,

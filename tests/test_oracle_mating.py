@@ -40,10 +40,11 @@ def crossovers(gametes):
 
 # ---------------------------------------------------------------- linkage map
 
-def test_uniform_map_is_the_bit_serial_rule():
+@pytest.mark.parametrize("r", [0.1, 0.3])
+def test_uniform_map_is_the_bit_serial_rule(r):
     L = 150
-    plain = oracle.OraclePop(seed=4, n0=10, n_loci=L, r=0.3)
-    mapped = oracle.OraclePop(seed=4, n0=10, n_loci=L, r=0.3, linkage=np.full(L - 1, 0.3))
+    plain = oracle.OraclePop(seed=4, n0=10, n_loci=L, r=r)
+    mapped = oracle.OraclePop(seed=4, n0=10, n_loci=L, r=r, linkage=np.full(L - 1, r))
     for pat in (False, True):
         a = plain.sample_gametes(het_parent(L), 0, 400, gen=2, paternal=pat)
         b = mapped.sample_gametes(het_parent(L), 0, 400, gen=2, paternal=pat)

@@ -99,6 +99,7 @@ def test_recomb_mode_rule():
     assert oracle.recomb_mode(0.5) == "raw"
     assert oracle.recomb_mode(0.0) == "zero"
     assert oracle.recomb_mode(0.01) == "skip"
-    assert oracle.recomb_mode(0.169) == "skip"
+    assert oracle.recomb_mode(0.0999) == "skip"
+    assert oracle.recomb_mode(0.10) == "lazy"
     assert oracle.recomb_mode(0.17) == "lazy"
     assert oracle.recomb_mode(0.4999) == "lazy"

@@ -13,7 +13,7 @@ import oracle
 from paper_1603_09255_amd import spegg
 
 ALWAYS = 1 << 32
-CASES = [(r, L) for r in (0.044, 0.05, 0.1, 0.163, 0.169) for L in (256, 1024)] + [(0.01, 16384)]
+CASES = [(r, L) for r in (0.044, 0.05, 0.09, 0.0999, 0.163, 0.169) for L in (256, 1024)] + [(0.01, 16384)]
 
 
 def words_at_edges(T):
