@@ -6,10 +6,14 @@ holds, against the oracle's gap for every word that can reach a table edge.
 The full table T_k = floor((1 - (1-r)^(k+1)) 2^32) reaches 2^32 for long
 genomes; a word x always lies below that entry, so the kernel keeps the
 entries before it, all of which fit the 32-bit words it stores in LDS."""
+import math
+import os
+
 import numpy as np
 import pytest
 
 import oracle
+from conftest import GOLDEN
 from paper_1603_09255_amd import spegg
 
 ALWAYS = 1 << 32
@@ -48,11 +52,35 @@ def test_kernel_table_fits_32_bits(r, L):
         assert int(full[n]) == ALWAYS  # the table stops at its first 2^32 entry
 
 
-def test_reaching_case_exists():
-    # the edge the narrowing once broke: for L = 1024 and r = 0.1 the table
-    # reaches 2^32 inside the genome, so the top word must give that index
-    full = oracle.geometric_thresholds(0.1, 1023)
+@pytest.mark.parametrize("r,k_edge", [(0.1, 427), (0.09, 477)])
+def test_reaching_case_exists(r, k_edge):
+    # the edge the narrowing once broke: for L = 1024 the table reaches 2^32
+    # inside the genome, so the top word must give that index.  The sum of
+    # the terms rounds to 1 once (1-r)^(k+1) falls below about 2^-64 (the
+    # 64-bit significand of the extended-precision accumulator), so the edge
+    # sits near 64 ln 2 / -ln(1-r).
+    full = oracle.geometric_thresholds(r, 1023)
     k = next(k for k, t in enumerate(full) if int(t) >= ALWAYS)
-    assert k == 427
-    assert oracle.skip_gap(0.1, 1024, ALWAYS - 1) == 427
-    assert spegg.geometric_gap(0.1, 1024, ALWAYS - 1, 0)[0] == 427
+    assert abs(k - 64 * math.log(2) / -math.log1p(-r)) < 0.03 * k
+    assert k == k_edge
+    assert oracle.skip_gap(r, 1024, ALWAYS - 1) == k_edge
+    assert spegg.geometric_gap(r, 1024, ALWAYS - 1, 0)[0] == k_edge
+
+
+def test_gap_edge_fixture_is_what_it_says():
+    # the stored gamete of tests/golden/skip_gap_edge.txt: its counter gives
+    # the word 0xFFFFFFFF (Philox pinned to the published answers elsewhere),
+    # the word's gap is the table's 2^32 index, and a crossover still follows
+    with open(os.path.join(GOLDEN, "skip_gap_edge.txt")) as f:
+        row = next(ln.split() for ln in f if ln.strip() and not ln.startswith("#"))
+    seed, c3, r, L, slots, t, j, stream, word, b, gap = row
+    seed, c3, L, t, j, stream, word, b, gap = map(int, (seed, c3, L, t, j, stream, word, b, gap))
+    r = float(r)
+    assert oracle.recomb_mode(r) == "skip"
+    assert j < int(slots) and word >= 4  # gaps are read from word 4 on
+    blk = oracle.philox4x32_10([j, (stream << 24) | (word >> 2), t, c3], [seed & 0xFFFFFFFF, seed >> 32])
+    assert int(blk[word & 3]) == ALWAYS - 1
+    full = oracle.geometric_thresholds(r, L - 1)
+    assert gap == next(k for k, v in enumerate(full) if int(v) >= ALWAYS)
+    assert oracle.skip_gap(r, L, ALWAYS - 1) == gap
+    assert b + 1 + gap <= L - 1
