@@ -2287,27 +2287,31 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
 
 // ---------------------------------------------------------------- consumer-resource
 
-// One block per survival tile (kBlock consumers: this regime runs one adult
-// per thread), one consumer per thread: every capture offers its key (consumer, encounter) to the
-// captured resource, which keeps the lowest.  The keys were reset to ~0
-// when the resource census was written.
+// One block per survival tile of a consumer deme, a consumer per thread at
+// a time (kBlock consecutive consumers per pass over the tile): every
+// capture offers its key (consumer, encounter) to the captured resource,
+// which keeps the lowest.  The keys were reset to ~0 when the resource
+// census was written.
 __device__ __forceinline__ void encounter_tile(const RepDesc *__restrict__ descs, const RepState *__restrict__ states,
                                                const SurvTile tile) {
-    const uint32_t i = tile.start + threadIdx.x;  // tiles of kBlock adults in this regime
     const RepDesc &c = descs[tile.rep];
     const RepState &cs = states[tile.rep];
     const uint32_t par = current_pair(cs);
     const uint32_t t = cs.t[par], n = cs.n[par];
-    if (i >= n) return;
-    gstore(c.intake + i, 0u);  // credit_kernel counts this generation's credited captures
     const RepDesc &r = descs[c.partner];
     const RepState &rs = states[c.partner];
     const uint32_t NR = rs.n[current_pair(rs)];
     const int32_t *zr = r.z[t & 1u];
     const int32_t *zc = c.z[t & 1u];
     unsigned long long *won = reinterpret_cast<unsigned long long *>(r.won);
-    consumer_captures(c, i, t, zc[i], zr, NR,
-                      [&](uint32_t e, uint32_t tgt) { atomicMin(won + tgt, (unsigned long long)capture_key(i, e)); });
+    for (uint32_t k = threadIdx.x; k < c.surv_tile; k += kBlock) {
+        const uint32_t i = tile.start + k;
+        if (i >= n) break;
+        gstore(c.intake + i, 0u);  // credit_kernel counts this generation's credited captures
+        consumer_captures(c, i, t, zc[i], zr, NR, [&](uint32_t e, uint32_t tgt) {
+            atomicMin(won + tgt, (unsigned long long)capture_key(i, e));
+        });
+    }
 }
 
 // A captured resource credits the consumer whose key it kept (the lowest

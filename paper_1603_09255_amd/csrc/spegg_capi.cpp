@@ -451,13 +451,11 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
             q.cap = consumer ? reps[i].ecology->capacity_consumer : reps[i].capacity;
         }
     // survival tiles, deme by deme: four adults per thread where the
-    // population has several demes and no consumer-resource replicate (fewer,
-    // longer blocks, the per-tile sums shared by more adults; measured faster
-    // on the batched table and the physiology batch), else one (more blocks
-    // in flight for one deme; the consumer-resource kernels assume it)
-    bool any_cr = false;  // consumer-resource: one adult per thread (its encounter tiles assume it)
-    for (const RepPlan &p : P.reps) any_cr |= p.cr;
-    P.surv_items = (!any_cr && P.demes.size() > 1) ? (uint32_t)kSurvItemsMax : 1u;
+    // population has several demes (fewer, longer blocks, the per-tile sums
+    // shared by more adults; measured faster on the batched table, the
+    // physiology batch and the consumer-resource replicates), else one (more
+    // blocks in flight for one deme)
+    P.surv_items = P.demes.size() > 1 ? (uint32_t)kSurvItemsMax : 1u;
     // SPEGG_SURV_ITEMS=1 forces one adult per thread (an experiment knob: no
     // result depends on it)
     const char *items = std::getenv("SPEGG_SURV_ITEMS");

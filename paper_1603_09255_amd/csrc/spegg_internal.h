@@ -75,8 +75,8 @@ constexpr double kSkipBelow = 0.10;  // r < 0.10: geometric gaps; above: bit-ser
 
 constexpr int kBlock = 256;          // threads per block in every kernel
 // Consecutive adults per thread in survive and compact, chosen per
-// population: 1 (one deme, or any consumer-resource replicate) or 4 (several
-// demes); a survival tile holds kBlock times that many adults.  Per-adult
+// population: 1 (one deme) or 4 (several demes); a survival tile holds
+// kBlock times that many adults.  Per-adult
 // buffers are padded to whole tiles of the largest size.
 constexpr int kSurvItemsMax = 4;
 constexpr int kSurvTileMax = kBlock * kSurvItemsMax;
@@ -363,8 +363,8 @@ hipError_t launch_offspring(OffShape shape, const OffArgs &a);
 // Blocks of the shape's offspring kernel one compute unit holds at once with
 // lds bytes of dynamic LDS (HIP's occupancy calculation).
 hipError_t offspring_blocks_per_cu(OffShape shape, size_t lds, int *blocks);
-// Consumer-resource regime (one adult per thread in the survival tiles):
-// encounters and captures of the consumers, one block per tile; with
+// Consumer-resource regime: encounters and captures of the consumers, one
+// block per survival tile of a consumer deme; with
 // list_n non-null, tiles is a list of list_n tiles on the device walked by
 // grid blocks.
 hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,

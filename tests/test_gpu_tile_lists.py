@@ -162,10 +162,11 @@ def build_env(reps, **env):
 @pytest.mark.parametrize("name,reps", [
     ("physiology", [phys(1, 1500, 12000), phys(2, 300, 9000), phys(3, 2500, 2600, L=40)]),
     ("poisson_wf", [poisson(4), wf(5, n_patches=3, migration=0.05, n0=300, capacity=900), wf(6, sexes=1)]),
-], ids=["physiology", "poisson_wf"])
+    ("consumer_resource", [cr(7), cr(8, n0_consumer=200, capacity_consumer=800, encounters=10.0)]),
+], ids=["physiology", "poisson_wf", "consumer_resource"])
 def test_adults_per_thread_equal(name, reps):
-    """Four adults per thread (the default for several demes without a
-    consumer-resource replicate) and one give the same populations."""
+    """Four adults per thread (the default for several demes) and one give
+    the same populations."""
     say("adults per thread", name)
     four, one = build_env(reps), build_env(reps, SPEGG_SURV_ITEMS="1")
     same(four, one, reps, f"{name} start")
