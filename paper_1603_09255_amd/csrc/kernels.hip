@@ -2178,16 +2178,17 @@ __global__ void __launch_bounds__(kBlock) plan_tiles_kernel(const RepDesc *__res
         // a census beyond the capacity is an impossible state (the kernels
         // that find one report it): never write past the deme's share
         uint32_t ms = n == 0 ? 1u : (n + T - 1u) / T, me = 0;
-        if (d.regime == SPEGG_CONSUMER_RESOURCE && d.species == 1) me = (n + T - 1u) / T;
+        const uint32_t enc_ntiles = (d.cap + kBlock - 1u) / kBlock;  // encounter tiles: kBlock consumers each
+        if (d.regime == SPEGG_CONSUMER_RESOURCE && d.species == 1) me = (n + kBlock - 1u) / kBlock;
         ms = ms < d.surv_ntiles ? ms : d.surv_ntiles;
-        me = me < d.surv_ntiles ? me : d.surv_ntiles;
+        me = me < enc_ntiles ? me : enc_ntiles;
         if (threadIdx.x == 0) {
             base[0] = atomicAdd(lists.counts, ms);
             base[1] = me ? atomicAdd(lists.counts + 1, me) : 0u;
         }
         __syncthreads();
         for (uint32_t k = threadIdx.x; k < ms; k += kBlock) lists.surv[base[0] + k] = SurvTile{u, k * T};
-        for (uint32_t k = threadIdx.x; k < me; k += kBlock) lists.enc[base[1] + k] = SurvTile{u, k * T};
+        for (uint32_t k = threadIdx.x; k < me; k += kBlock) lists.enc[base[1] + k] = SurvTile{u, k * (uint32_t)kBlock};
     } else {
         if (u == 0 && threadIdx.x < 2) lists.counts[threadIdx.x] = 0;
         const uint32_t nn = st.n[current_pair(st)] - st.n_carry;
@@ -2287,31 +2288,28 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
 
 // ---------------------------------------------------------------- consumer-resource
 
-// One block per survival tile of a consumer deme, a consumer per thread at
-// a time (kBlock consecutive consumers per pass over the tile): every
-// capture offers its key (consumer, encounter) to the captured resource,
-// which keeps the lowest.  The keys were reset to ~0 when the resource
-// census was written.
+// One block per encounter tile of a consumer deme (kBlock consumers,
+// whatever the survival tiles hold), one consumer per thread: every capture
+// offers its key (consumer, encounter) to the captured resource, which
+// keeps the lowest.  The keys were reset to ~0 when the resource census was
+// written.
 __device__ __forceinline__ void encounter_tile(const RepDesc *__restrict__ descs, const RepState *__restrict__ states,
                                                const SurvTile tile) {
+    const uint32_t i = tile.start + threadIdx.x;
     const RepDesc &c = descs[tile.rep];
     const RepState &cs = states[tile.rep];
     const uint32_t par = current_pair(cs);
     const uint32_t t = cs.t[par], n = cs.n[par];
+    if (i >= n) return;
+    gstore(c.intake + i, 0u);  // credit_kernel counts this generation's credited captures
     const RepDesc &r = descs[c.partner];
     const RepState &rs = states[c.partner];
     const uint32_t NR = rs.n[current_pair(rs)];
     const int32_t *zr = r.z[t & 1u];
     const int32_t *zc = c.z[t & 1u];
     unsigned long long *won = reinterpret_cast<unsigned long long *>(r.won);
-    for (uint32_t k = threadIdx.x; k < c.surv_tile; k += kBlock) {
-        const uint32_t i = tile.start + k;
-        if (i >= n) break;
-        gstore(c.intake + i, 0u);  // credit_kernel counts this generation's credited captures
-        consumer_captures(c, i, t, zc[i], zr, NR, [&](uint32_t e, uint32_t tgt) {
-            atomicMin(won + tgt, (unsigned long long)capture_key(i, e));
-        });
-    }
+    consumer_captures(c, i, t, zc[i], zr, NR,
+                      [&](uint32_t e, uint32_t tgt) { atomicMin(won + tgt, (unsigned long long)capture_key(i, e)); });
 }
 
 // A captured resource credits the consumer whose key it kept (the lowest

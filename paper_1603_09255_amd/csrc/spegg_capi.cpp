@@ -121,7 +121,7 @@ struct Plan {
     std::vector<DemePlan> demes;
     std::vector<OffClass> classes;
     std::vector<SurvTile> surv_tiles;
-    std::vector<SurvTile> enc_tiles;    // survival tiles of consumer demes
+    std::vector<SurvTile> enc_tiles;    // encounter tiles of consumer demes (kBlock consumers each)
     std::vector<OffTile> off_tiles;
     size_t descs = 0, states = 0, surv_tiles_at = 0, off_tiles_at = 0, enc_tiles_at = 0;
     size_t static_end = 0;  // [0, static_end) is uploaded at create
@@ -468,11 +468,11 @@ spegg_status make_plan(const spegg_rep_desc *reps, uint32_t n, Plan &P, const Gc
         q.grp0 = P.n_groups;
         q.grp_n = q.surv_ntiles > kGroupTiles ? (q.surv_ntiles + kGroupTiles - 1) / kGroupTiles : 0u;
         P.n_groups += 2u * q.grp_n;
-        for (uint32_t k = 0; k < q.surv_ntiles; ++k) {
-            const SurvTile tile{u, k * surv_tile};
-            P.surv_tiles.push_back(tile);
-            if (P.reps[q.rep].cr && q.species == 1) P.enc_tiles.push_back(tile);
-        }
+        for (uint32_t k = 0; k < q.surv_ntiles; ++k) P.surv_tiles.push_back(SurvTile{u, k * surv_tile});
+        // consumers: encounter tiles of kBlock consumers, one per thread
+        if (P.reps[q.rep].cr && q.species == 1)
+            for (uint32_t k = 0; k < (q.cap + kBlock - 1u) / kBlock; ++k)
+                P.enc_tiles.push_back(SurvTile{u, k * (uint32_t)kBlock});
     }
     // offspring tiles grouped by kernel shape
     std::vector<OffShape> shapes;

@@ -364,7 +364,7 @@ hipError_t launch_offspring(OffShape shape, const OffArgs &a);
 // lds bytes of dynamic LDS (HIP's occupancy calculation).
 hipError_t offspring_blocks_per_cu(OffShape shape, size_t lds, int *blocks);
 // Consumer-resource regime: encounters and captures of the consumers, one
-// block per survival tile of a consumer deme; with
+// block per encounter tile (kBlock consumers) of a consumer deme; with
 // list_n non-null, tiles is a list of list_n tiles on the device walked by
 // grid blocks.
 hipError_t launch_encounter(const RepDesc *descs, const RepState *states, const SurvTile *tiles, uint32_t ntiles,
