@@ -2315,22 +2315,28 @@ __device__ __forceinline__ void encounter_tile(const RepDesc *__restrict__ descs
 // A captured resource credits the consumer whose key it kept (the lowest
 // (consumer, encounter) key of its captures): one atomic add to that
 // consumer's intake.  Survival tiles of every deme; only the resources'
-// act.
+// act.  A thread's keys (one per kBlock resources of the tile) are all
+// loaded before its first add.
 __device__ __forceinline__ void credit_tile(const RepDesc *__restrict__ descs, const RepState *__restrict__ states,
                                             const SurvTile tile) {
     const RepDesc &r = descs[tile.rep];
     if (r.regime != SPEGG_CONSUMER_RESOURCE || r.species != 0) return;  // uniform over the block
     const RepState &rs = states[tile.rep];
     const uint32_t NR = rs.n[current_pair(rs)];
-    for (uint32_t k = threadIdx.x; k < r.surv_tile; k += kBlock) {
-        const uint32_t j = tile.start + k;
-        if (j >= NR) break;
-        const uint64_t key = gload(r.won + j);
-        if (key == ~0ull) continue;
-        const RepDesc &c = descs[r.partner];
-        const uint32_t i = (uint32_t)(key >> 32);
-        const RepState &cs = states[r.partner];
-        if (i < cs.n[current_pair(cs)]) atomicAdd(c.intake + i, 1u);
+    uint64_t key[kSurvItemsMax];
+#pragma unroll
+    for (int q = 0; q < kSurvItemsMax; ++q) {
+        const uint32_t k = threadIdx.x + (uint32_t)q * kBlock, j = tile.start + k;
+        key[q] = (k < r.surv_tile && j < NR) ? gload(r.won + j) : ~0ull;
+    }
+    const RepDesc &c = descs[r.partner];
+    const RepState &cs = states[r.partner];
+    const uint32_t NC = cs.n[current_pair(cs)];
+#pragma unroll
+    for (int q = 0; q < kSurvItemsMax; ++q) {
+        if (key[q] == ~0ull) continue;
+        const uint32_t i = (uint32_t)(key[q] >> 32);
+        if (i < NC) atomicAdd(c.intake + i, 1u);
         else atomicOr(const_cast<uint32_t *>(&rs.error), 1u);  // a key of no consumer: impossible
     }
 }
