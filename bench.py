@@ -40,14 +40,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # taken with (lanes-per-gamete cap by genome words W); otherwise the
 # traffic figure is null until re-measured.
 MEASURED_TRAFFIC = {
-    # offspring L = 1024 class of the 4096-replicate table: FETCH 7114537 KiB x 2.00 + WRITE 11668074 KiB x 1.00
+    # offspring L = 1024 class of the 4096-replicate table: FETCH 7114387 KiB x 2.00 + WRITE 11668344 KiB x 1.00
     # per launch over 33832793 newborns (profiles/offspring_batched_table_kernel_trace.md)
-    "batched": {"device_sources_sha256_16": "120938665573a32f", "lanes_per_gamete_by_W": {2: 1, 8: 1, 32: 4},
+    "batched": {"device_sources_sha256_16": "11927a85c16dea1e", "lanes_per_gamete_by_W": {2: 1, 8: 1, 32: 4},
                 "bytes_per_newborn": 783.8},
-    # continuous alleles, N = 1e5, L = 256: FETCH 202952 KiB x 2.00 + WRITE 200439 KiB x 1.00 per launch
+    # continuous alleles, N = 1e5, L = 256: FETCH 202936 KiB x 2.00 + WRITE 200439 KiB x 1.00 per launch
     # (profiles/offspring_continuous_kernel_trace.md)
-    "continuous": {"device_sources_sha256_16": "120938665573a32f", "lanes_per_gamete_by_W": {0x80000100: 8},
-                   "bytes_per_newborn": 6209.0},
+    "continuous": {"device_sources_sha256_16": "11927a85c16dea1e", "lanes_per_gamete_by_W": {0x80000100: 8},
+                   "bytes_per_newborn": 6208.6},
 }
 # the device code and the compiler flags it is built with
 DEVICE_SOURCES = ("csrc/kernels.hip", "csrc/philox.h", "csrc/spegg_internal.h", "build.py")
