@@ -44,6 +44,10 @@ MEASURED_TRAFFIC = {
     # per launch over 33832793 newborns (profiles/offspring_batched_table_kernel_trace.md)
     "batched": {"device_sources_sha256_16": "11927a85c16dea1e", "lanes_per_gamete_by_W": {2: 1, 8: 1, 32: 4},
                 "bytes_per_newborn": 783.8},
+    # plain method at scale, L = 1024, census about 63.2k: FETCH 10205 KiB x 2.00 + WRITE 22935 KiB x 1.00 per
+    # launch (profiles/offspring_plain_scale_hbm_traffic.md)
+    "scale": {"device_sources_sha256_16": "11927a85c16dea1e", "lanes_per_gamete_by_W": {32: 4},
+              "bytes_per_newborn": 702.4},
     # continuous alleles, N = 1e5, L = 256: FETCH 202936 KiB x 2.00 + WRITE 200439 KiB x 1.00 per launch
     # (profiles/offspring_continuous_kernel_trace.md)
     "continuous": {"device_sources_sha256_16": "11927a85c16dea1e", "lanes_per_gamete_by_W": {0x80000100: 8},
