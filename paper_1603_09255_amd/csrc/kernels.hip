@@ -529,22 +529,40 @@ struct SeqWords {
 // uniform slot of the habitat (at least the resource census NR) and meets
 // the resource of that index if there is one; it captures it when its
 // CAPTURE word is below the matching threshold.  f(e, target) is called
-// for every capture.
+// for every capture.  Encounters go four at a time, so that their resource
+// gathers are in flight together; capT is the capture table (in LDS where
+// it fits).
+constexpr uint32_t kEncounterBatch = 4;
 template <typename F>
 __device__ __forceinline__ void consumer_captures(const RepDesc &c, uint32_t i, uint32_t t, int32_t zc,
-                                                  const int32_t *__restrict__ zr, uint32_t NR, F &&f) {
+                                                  const int32_t *__restrict__ zr, uint32_t NR,
+                                                  const uint64_t *capT, F &&f) {
     if (NR == 0) return;
     const Rng rng{c.key0, c.key1, c.c3};
     SeqWords enc(rng, i, kStEncounter, t), cap(rng, i, kStCapture, t);
     const uint32_t ne = table_draw_global(c.enc, c.enc_len, enc(0));
     const uint32_t span = c.habitat > NR ? c.habitat : NR;
-    for (uint32_t e = 0; e < ne; ++e) {
-        const uint32_t lo = enc(1u + 2u * e), hi = enc(2u + 2u * e);
-        const uint32_t tgt = uniform_index(lo, hi, span);
-        if (tgt >= NR) continue;
-        const int32_t dz = zc - gload(zr + tgt);
-        const uint32_t d = (uint32_t)(dz < 0 ? -dz : dz);
-        if ((uint64_t)cap(e) < gload(c.capT + d)) f(e, tgt);
+    for (uint32_t e0 = 0; e0 < ne; e0 += kEncounterBatch) {
+        uint32_t tgt[kEncounterBatch];
+        int32_t z[kEncounterBatch];
+#pragma unroll
+        for (uint32_t q = 0; q < kEncounterBatch; ++q) {
+            const uint32_t e = e0 + q;
+            tgt[q] = ~0u;
+            if (e < ne) {
+                const uint32_t lo = enc(1u + 2u * e), hi = enc(2u + 2u * e);
+                tgt[q] = uniform_index(lo, hi, span);
+            }
+            z[q] = tgt[q] < NR ? gload(zr + tgt[q]) : 0;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kEncounterBatch; ++q) {
+            const uint32_t e = e0 + q;
+            if (e >= ne || tgt[q] >= NR) continue;
+            const int32_t dz = zc - z[q];
+            const uint32_t d = (uint32_t)(dz < 0 ? -dz : dz);
+            if ((uint64_t)cap(e) < capT[d]) f(e, tgt[q]);
+        }
     }
 }
 
@@ -2293,13 +2311,23 @@ __global__ void __launch_bounds__(kBlock) census_kernel(const RepDesc *__restric
 // offers its key (consumer, encounter) to the captured resource, which
 // keeps the lowest.  The keys were reset to ~0 when the resource census was
 // written.
+// The tile's capture thresholds (one table per consumer deme) are staged in
+// LDS when they fit.
+constexpr uint32_t kCaptureLds = 1024;
 __device__ __forceinline__ void encounter_tile(const RepDesc *__restrict__ descs, const RepState *__restrict__ states,
                                                const SurvTile tile) {
+    __shared__ uint64_t sh_cap[kCaptureLds];
     const uint32_t i = tile.start + threadIdx.x;
     const RepDesc &c = descs[tile.rep];
     const RepState &cs = states[tile.rep];
     const uint32_t par = current_pair(cs);
     const uint32_t t = cs.t[par], n = cs.n[par];
+    const bool staged = c.cap_len <= kCaptureLds;  // uniform over the block
+    if (staged) {
+        __syncthreads();  // the block's previous tile has finished reading the table
+        for (uint32_t q = threadIdx.x; q < c.cap_len; q += kBlock) sh_cap[q] = gload(c.capT + q);
+        __syncthreads();
+    }
     if (i >= n) return;
     gstore(c.intake + i, 0u);  // credit_kernel counts this generation's credited captures
     const RepDesc &r = descs[c.partner];
@@ -2308,7 +2336,7 @@ __device__ __forceinline__ void encounter_tile(const RepDesc *__restrict__ descs
     const int32_t *zr = r.z[t & 1u];
     const int32_t *zc = c.z[t & 1u];
     unsigned long long *won = reinterpret_cast<unsigned long long *>(r.won);
-    consumer_captures(c, i, t, zc[i], zr, NR,
+    consumer_captures(c, i, t, zc[i], zr, NR, staged ? sh_cap : c.capT,
                       [&](uint32_t e, uint32_t tgt) { atomicMin(won + tgt, (unsigned long long)capture_key(i, e)); });
 }
 
