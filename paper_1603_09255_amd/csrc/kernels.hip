@@ -529,10 +529,10 @@ struct SeqWords {
 // uniform slot of the habitat (at least the resource census NR) and meets
 // the resource of that index if there is one; it captures it when its
 // CAPTURE word is below the matching threshold.  f(e, target) is called
-// for every capture.  Encounters go four at a time, so that their resource
+// for every capture.  Encounters go eight at a time, so that their resource
 // gathers are in flight together; capT is the capture table (in LDS where
 // it fits).
-constexpr uint32_t kEncounterBatch = 4;
+constexpr uint32_t kEncounterBatch = 8;
 template <typename F>
 __device__ __forceinline__ void consumer_captures(const RepDesc &c, uint32_t i, uint32_t t, int32_t zc,
                                                   const int32_t *__restrict__ zr, uint32_t NR,
