@@ -40,18 +40,18 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # taken with (lanes-per-gamete cap by genome words W); otherwise the
 # traffic figure is null until re-measured.
 MEASURED_TRAFFIC = {
-    # offspring L = 1024 class of the 4096-replicate table: FETCH 7114387 KiB x 2.00 + WRITE 11668344 KiB x 1.00
+    # offspring L = 1024 class of the 4096-replicate table: FETCH 7114392 KiB x 2.00 + WRITE 11669357 KiB x 1.00
     # per launch over 33832793 newborns (profiles/offspring_batched_table_kernel_trace.md)
-    "batched": {"device_sources_sha256_16": "11927a85c16dea1e", "lanes_per_gamete_by_W": {2: 1, 8: 1, 32: 4},
+    "batched": {"device_sources_sha256_16": "cd66b0e8ac59217a", "lanes_per_gamete_by_W": {2: 1, 8: 1, 32: 4},
                 "bytes_per_newborn": 783.8},
-    # plain method at scale, L = 1024, census about 63.2k: FETCH 10205 KiB x 2.00 + WRITE 22935 KiB x 1.00 per
+    # plain method at scale, L = 1024, census about 63.2k: FETCH 10209 KiB x 2.00 + WRITE 22940 KiB x 1.00 per
     # launch (profiles/offspring_plain_scale_hbm_traffic.md)
-    "scale": {"device_sources_sha256_16": "11927a85c16dea1e", "lanes_per_gamete_by_W": {32: 4},
-              "bytes_per_newborn": 702.4},
-    # continuous alleles, N = 1e5, L = 256: FETCH 202936 KiB x 2.00 + WRITE 200439 KiB x 1.00 per launch
+    "scale": {"device_sources_sha256_16": "cd66b0e8ac59217a", "lanes_per_gamete_by_W": {32: 4},
+              "bytes_per_newborn": 702.6},
+    # continuous alleles, N = 1e5, L = 256: FETCH 202945 KiB x 2.00 + WRITE 200441 KiB x 1.00 per launch
     # (profiles/offspring_continuous_kernel_trace.md)
-    "continuous": {"device_sources_sha256_16": "11927a85c16dea1e", "lanes_per_gamete_by_W": {0x80000100: 8},
-                   "bytes_per_newborn": 6208.6},
+    "continuous": {"device_sources_sha256_16": "cd66b0e8ac59217a", "lanes_per_gamete_by_W": {0x80000100: 8},
+                   "bytes_per_newborn": 6208.8},
 }
 # the device code and the compiler flags it is built with
 DEVICE_SOURCES = ("csrc/kernels.hip", "csrc/philox.h", "csrc/spegg_internal.h", "build.py")
